@@ -1,0 +1,191 @@
+"""Benchmark: per-frame FEWHA reconstruction on one MI355X.
+
+One step = one tomographic frame of the hot path on the ELT MCAO configuration (9 guide
+stars with 84x84 subapertures, 9 layers, J = 6, 3 DMs) in FP32: right-hand side, warm-restart
+residual update, 4 PCG iterations (Alg. 2) and DM fitting with gain (Alg. 1), with slopes
+already resident in HBM.  Slopes are synthetic: seeded von Karman layers (frozen flow over 16
+frames) through the library's own forward operator plus white noise.
+
+Prints one JSON line: ms per frame (median over the timed frames is reported beside the mean),
+effective bandwidth of the algorithmic byte model against the 8 TB/s HBM peak, the roofline
+object of the dominant launch, and the FP64 CPU oracle timed on a bounded sample of the same
+frames on the host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "ms per tomographic frame (fixed PCG iters) + effective HBM GB/s vs peak"
+
+
+def footprint(cfg):
+    """(sum_U, U_fit): layer nodes touched by any WFS interpolation stencil / by any fitting stencil."""
+    sum_u, u_fit = 0, 0
+    D = cfg["D"]
+    heights = [d["height"] for d in cfg["dms"]]
+    for li, lay in enumerate(cfg["layers"]):
+        n, dl, h = lay["n"], lay["spacing"], lay["height"]
+        mark = np.zeros((n, n), bool)
+        for w in cfg["wfs"]:
+            ns = w["n_sub"]
+            x = -D / 2 + (D / ns) * np.arange(ns + 1)
+            sig = 1 - h / w["gs_height"] if w["gs_height"] > 0 else 1.0
+            u = (sig * x + w["theta_x"] * h) / dl + n / 2
+            v = (sig * x + w["theta_y"] * h) / dl + n / 2
+            l0 = np.minimum(np.floor(u).astype(int), n - 2)
+            k0 = np.minimum(np.floor(v).astype(int), n - 2)
+            for dk in (0, 1):
+                for dj in (0, 1):
+                    mark[np.ix_(k0 + dk, l0 + dj)] = True
+        sum_u += int(mark.sum())
+        m = int(np.argmin([abs(h - hd) + 1e-9 * hd for hd in heights]))
+        dm = cfg["dms"][m]
+        xa = (np.arange(dm["n_act"]) - (dm["n_act"] - 1) / 2) * dm["pitch"] / dl + n / 2
+        a0 = np.minimum(np.floor(xa).astype(int), n - 2)
+        fm = np.zeros((n, n), bool)
+        for dk in (0, 1):
+            for dj in (0, 1):
+                fm[np.ix_(a0 + dk, a0 + dj)] = True
+        u_fit += int(fm.sum())
+    return sum_u, u_fit
+
+
+def byte_model(cfg, elem_bytes, n_iter):
+    """Algorithmic bytes per frame with stage-materialised intermediates (elements x size)."""
+    n_c = sum(l["n"] ** 2 for l in cfg["layers"])
+    sum_v = sum((w["n_sub"] + 1) ** 2 for w in cfg["wfs"])
+    sum_s = sum(2 * w["n_sub"] ** 2 for w in cfg["wfs"])
+    n_act = sum(d["n_act"] ** 2 for d in cfg["dms"])
+    sum_u, u_fit = footprint(cfg)
+    per_iter = 18 * n_c + sum_u + 4 * sum_v
+    rhs = sum_s + 2 * sum_v + 7 * n_c
+    fit = 2 * n_c + u_fit + n_act
+    return {"per_iter": per_iter * elem_bytes, "rhs": rhs * elem_bytes, "fit": fit * elem_bytes,
+            "frame": (n_iter * per_iter + rhs + fit) * elem_bytes,
+            "n_coef": n_c, "sum_V": sum_v, "sum_S": sum_s, "sum_U": sum_u, "U_fit": u_fit}
+
+
+def cpu_baseline(cfg, frames_s, n_iter, budget_s):
+    """The FP64 oracle (single-threaded C) on host cores: ms per frame on a bounded sample."""
+    from oracle import Oracle
+    O = Oracle(cfg)
+    N = O.n_coef
+    c, bp, rp = np.zeros(N), np.zeros(N), np.zeros(N)
+    times = []
+    t_all = time.perf_counter()
+    f = 0
+    while True:
+        t0 = time.perf_counter()
+        c, bp, rp, _, _ = O.frame(frames_s[f % len(frames_s)], c, bp, rp, n_iter, cold=(f == 0))
+        O.fit(c, None, cfg["gain"])
+        times.append(time.perf_counter() - t0)
+        f += 1
+        if time.perf_counter() - t_all > budget_s or f >= 64:
+            break
+    return {"value": 1e3 * float(np.median(times)), "unit": "ms/frame", "cores": 1, "kind": "oracle",
+            "sample": "%d frames of the same configuration (RHS + %d PCG iterations + fit), FP64, "
+                      "median per frame" % (len(times), n_iter)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--config", default="c1_elt_mcao")
+    ap.add_argument("--frames", type=int, default=16, help="distinct synthetic slope frames (cycled)")
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle CPU time")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs the single-GPU hot path only; multi-GPU runs are not provided "
+              "(frames would shard across GPUs with no exchange)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2009_00946_amd import fewha, synth
+
+    torch.cuda.set_device(0)
+    cfg = synth.load_config(args.config)
+    n_iter, gain = cfg["n_iter"], cfg["gain"]
+    P = fewha.Plan(cfg)
+    stream = torch.cuda.current_stream()
+
+    # synthetic frames, resident on the device before timing
+    S, S_host = [], []
+    for f in range(args.frames):
+        phi = torch.as_tensor(synth.layer_screens_flat(cfg, f), dtype=P.dtype, device=P.device)
+        s = P.apply_A(P.dwt_forward(phi))
+        s += torch.as_tensor(synth.slope_noise(cfg, f), dtype=P.dtype, device=P.device)
+        S.append(s)
+    torch.cuda.synchronize()
+    if not args.no_cpu_baseline:
+        S_host = [s.double().cpu().numpy() for s in S]
+
+    c = P.zeros(P.n_coef)
+    a = P.zeros(P.n_act)
+
+    def frame(k, warm=True):
+        P.pcg_solve(S[k % len(S)], c, n_iter, warm=warm)
+        P.fit_dm(c, a, gain, out=a)
+
+    frame(0, warm=False)
+    for k in range(1, args.warmup):
+        frame(k)
+    torch.cuda.synchronize()
+    assert P.last_status() == 0, fewha.STATUS.get(P.last_status())
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for k in range(args.steps):
+        frame(args.warmup + k)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    per = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
+    total_ms = ev[0].elapsed_time(ev[-1])
+    assert P.last_status() == 0
+    ms_mean = total_ms / args.steps
+
+    model = byte_model(cfg, 4 if P.precision == "fp32" else 8, n_iter)
+    eff_gbps = model["frame"] / (ms_mean * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": round(ms_mean, 5),
+        "unit": "ms/frame",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_mean, 5),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if P.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "%s: %s" % (cfg["name"], cfg["description"]), "n_iter": n_iter, "warm": True,
+                   "gain": gain, "n_coef": model["n_coef"], "n_slopes": P.n_slopes, "n_act": P.n_act},
+        "ms_median": round(float(np.median(per)), 5),
+        "ms_p99": round(float(np.percentile(per, 99)), 5),
+        "frames_per_s": round(1e3 / ms_mean, 1),
+        "effective_GBps": round(eff_gbps, 1),
+        "frac_hbm_peak": round(eff_gbps / HBM_PEAK_GBPS, 4),
+        "bytes_per_frame": model["frame"],
+        "roofline": {"bound": "hbm", "achieved": round(eff_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(eff_gbps / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "kernel": "whole frame (RHS + %d PCG iterations + fit)" % n_iter},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, S_host, n_iter, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,179 @@
+/*
+ * fewha.h -- C ABI of the MI355X (gfx950) implementation of the FEWHA tomography hot path:
+ * the matrix-free Jacobi-PCG solve of the wavelet-domain MAP normal equations
+ *
+ *     (W Ahat^T C_eta^-1 Ahat W^T + alpha D) c = W Ahat^T C_eta^-1 s        (Eq. (fewha))
+ *
+ * followed by deformable-mirror fitting (Alg. 1), after Stadler, Biasi, Manetti, Ramlau,
+ * "Real-time implementation of an iterative solver for atmospheric tomography" (arXiv 2009.00946).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Pointers named d_* are DEVICE pointers (HIP global memory on the plan's GPU) holding
+ * contiguous arrays of the plan's precision (float for FEWHA_FP32, double for FEWHA_FP64)
+ * unless stated otherwise.  Pointers named h_* are host pointers.  `stream` is a hipStream_t
+ * passed as void* (NULL = the default stream).  The caller owns every buffer it passes; the
+ * library never keeps a pointer to a caller buffer after a call returns.
+ *
+ * Vector layouts (sizes from fewha_sizes):
+ *   coefficient vector c (n_coef): layers concatenated in configuration order, each n x n
+ *     row-major (row = y, column = x) in the Mallat in-place pyramid: top-left LL, top-right
+ *     x-high/y-low, bottom-left x-low/y-high, bottom-right HH, recursing J times into LL.
+ *   layer vector (n_coef): the same concatenation of n x n row-major nodal values (finite
+ *     element domain; node (k, l) of layer i at ((l - n/2) spacing, (k - n/2) spacing)).
+ *   slope vector s (n_slopes): per guide star the s^x plane then the s^y plane, each
+ *     n_sub x n_sub row-major; entries of inactive subapertures are ignored on input and
+ *     written as 0 on output.
+ *   actuator vector a (n_act): DMs concatenated, each n_act x n_act row-major; actuator (i, j)
+ *     at ((j - (n_act-1)/2) pitch, (i - (n_act-1)/2) pitch).
+ *
+ * Execution: fewha_plan_create and fewha_plan_bind are synchronous.  Every other call that
+ * takes a stream only enqueues kernels on it and returns (no host synchronisation, no device
+ * allocation), so a sequence of calls can be captured into a HIP graph.  A plan may be used by
+ * one stream at a time; calls on one plan from two streams at once race on its workspace.
+ *
+ * Errors: every call returns FEWHA_OK (0) or a negative fewha_status; nothing is thrown across
+ * the ABI.  Numerical failures inside a solve (PCG breakdown, non-finite reductions) are
+ * recorded in a device status word that fewha_last_status reads after the caller synchronises.
+ */
+#ifndef FEWHA_H
+#define FEWHA_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fewha_plan fewha_plan;
+
+typedef enum {
+    FEWHA_OK = 0,
+    FEWHA_ERR_INVALID_ARG = -1, /* null pointer, bad size, not a power of two, sigma <= 0, ... */
+    FEWHA_ERR_GEOMETRY = -2,    /* a projected node or actuator leaves its layer grid, LGS below a layer */
+    FEWHA_ERR_UNSUPPORTED = -3, /* configuration outside the implemented limits (see fewha_plan_create) */
+    FEWHA_ERR_HIP = -4,         /* a HIP runtime call or kernel launch failed */
+    FEWHA_ERR_WORKSPACE = -5,   /* plan not bound, or workspace too small / misaligned */
+    FEWHA_ERR_BREAKDOWN = -6,   /* PCG denominator mu - rho beta / alpha_old <= 0 (device status) */
+    FEWHA_ERR_NONFINITE = -7    /* NaN or Inf in a PCG reduction (device status) */
+} fewha_status;
+
+typedef enum { FEWHA_FP32 = 0, FEWHA_FP64 = 1 } fewha_precision;
+
+/* PCG start flags for fewha_pcg_solve */
+#define FEWHA_COLD 0 /* c = b_prev = r_prev = 0 before the frame */
+#define FEWHA_WARM 1 /* warm restart from the caller's c and the plan's b_prev, r_prev */
+
+/* One Shack-Hartmann wavefront sensor / guide star (Sec. 2.1). */
+typedef struct {
+    int n_sub;        /* subapertures per side (>= 1); subaperture size d = D / n_sub */
+    double theta_x;   /* guide-star direction, rad */
+    double theta_y;
+    double gs_height; /* m; 0 = natural guide star at infinity, > 0 = laser guide star height H */
+    double sigma;     /* noise standard deviation per slope (rad); C_eta^-1 = sigma^-2 on active slopes */
+} fewha_wfs;
+
+/* One turbulent layer, discretised on an n x n node grid (Table 1, Table 2). */
+typedef struct {
+    double height;     /* m */
+    double cn2_weight; /* fractional Cn2 weight gamma (> 0) */
+    double spacing;    /* node spacing delta, m */
+    int n;             /* power of two, n >= max(2, 2^J) */
+} fewha_layer;
+
+/* One deformable mirror (Alg. 1 fitting target). */
+typedef struct {
+    double height; /* conjugation height, m */
+    double pitch;  /* actuator pitch, m */
+    int n_act;     /* actuators per side (>= 2) */
+} fewha_dm;
+
+typedef struct {
+    double D;           /* telescope diameter, m */
+    double obstruction; /* central obstruction as a fraction of D, in [0, 1) */
+    int n_wfs, n_layers, n_dms;
+    int J;              /* wavelet decomposition levels (>= 1) */
+    const fewha_wfs *wfs;
+    const fewha_layer *layers;
+    const fewha_dm *dms;
+    double alpha_reg;   /* regularisation weight alpha of Eq. (fewha), > 0 */
+    int precision;      /* fewha_precision */
+} fewha_config;
+
+/* Validate a configuration and size a plan (host only; touches no GPU).  The configuration is
+ * copied.  Geometry rules (Sec. 2.1): WFS node x_j = -D/2 + j d; a ray from node (x, y) towards
+ * guide star g meets layer l at (sigma x + theta_x h, sigma y + theta_y h) with sigma = 1 - h/H
+ * (LGS) or 1 (NGS); every such point and every fitting actuator must lie inside its layer grid.
+ * Limits: n_layers <= 64, n_wfs <= 64, n_dms <= 16, J <= 12, layer n <= 4096, n_sub <= 4096.
+ * Returns FEWHA_ERR_INVALID_ARG, FEWHA_ERR_GEOMETRY or FEWHA_ERR_UNSUPPORTED on rejection. */
+int fewha_plan_create(const fewha_config *cfg, fewha_plan **out);
+
+/* Bytes of device workspace the plan needs (tables, intermediates, b_prev, r_prev, PCG vectors). */
+size_t fewha_workspace_bytes(const fewha_plan *p);
+
+/* Attach a caller-allocated device workspace (>= fewha_workspace_bytes, 256-byte aligned, owned
+ * by the caller and kept alive until fewha_plan_destroy) on the current HIP device, upload the
+ * geometry tables, zero the warm-restart state and build the preconditioner of Sec. 3.4 by
+ * probing the data term (one application of A per (layer, level, orientation) band).
+ * Synchronous.  May be called again with another workspace (the state is reset). */
+int fewha_plan_bind(fewha_plan *p, void *d_workspace, size_t bytes, void *stream);
+
+/* Free the host side of the plan (the workspace stays the caller's). */
+int fewha_plan_destroy(fewha_plan *p);
+
+/* Vector lengths: wavelet coefficients (= layer nodes), dense slopes, actuators. Any output may be NULL. */
+int fewha_sizes(const fewha_plan *p, size_t *n_coef, size_t *n_slopes, size_t *n_act);
+
+/* s = mask Gamma P W^T c: wavelet coefficients to slopes (Eq. (atmo) in the wavelet domain). */
+int fewha_apply_A(const fewha_plan *p, const void *d_c, void *d_s, void *stream);
+
+/* c = W P^T Gamma^T mask s: the exact adjoint of fewha_apply_A. */
+int fewha_apply_At(const fewha_plan *p, const void *d_s, void *d_c, void *stream);
+
+/* y = M c = W P^T Gamma^T C_eta^-1 Gamma P W^T c + alpha D c (left-hand side of Eq. (fewha)). */
+int fewha_apply_M(const fewha_plan *p, const void *d_c, void *d_y, void *stream);
+
+/* c = W x: layer nodal values to wavelet coefficients (periodic Daubechies-3, J levels). */
+int fewha_dwt_forward(const fewha_plan *p, const void *d_layers, void *d_c, void *stream);
+
+/* x = W^T c = W^-1 c: wavelet coefficients to layer nodal values (the reconstructed layers). */
+int fewha_dwt_inverse(const fewha_plan *p, const void *d_c, void *d_layers, void *stream);
+
+/* One reconstruction frame of Alg. 1 up to the PCG: b = W Ahat^T C_eta^-1 s; residual update
+ * r = (b - b_prev) + r_prev; n_iter passes of Alg. 2 with the Jacobi preconditioner; then
+ * b_prev = b, r_prev = r (kept in the workspace).  d_c holds c^(0) on entry (ignored for
+ * FEWHA_COLD, which starts from c = b_prev = r_prev = 0) and c^(1) on return.  d_resnorm
+ * (optional, n_iter doubles on the device) receives sqrt((r, J^-1 r)) at the start of every pass
+ * that ran.  A zero residual ends the passes early (not an error); breakdown or non-finite
+ * reductions stop the passes and set the device status word (fewha_last_status). */
+int fewha_pcg_solve(fewha_plan *p, const void *d_s, void *d_c, int n_iter, int flags, double *d_resnorm,
+                    void *stream);
+
+/* Fitting and open-loop gain of Alg. 1: a = (1 - gain) a_prev + gain F W^T c, where F samples each
+ * layer on-axis at the actuators of the DM nearest in altitude (ties to the lower DM) by bilinear
+ * interpolation and sums the layers sharing a DM.  d_a_prev may be NULL (taken as 0).  d_a must
+ * not alias d_c; it may alias d_a_prev. */
+int fewha_fit_dm(const fewha_plan *p, const void *d_c, const void *d_a_prev, double gain, void *d_a,
+                 void *stream);
+
+/* Copy the warm-restart state (b_prev, r_prev; n_coef each) out of / into the workspace. */
+int fewha_state_get(const fewha_plan *p, void *d_b_prev, void *d_r_prev, void *stream);
+int fewha_state_set(fewha_plan *p, const void *d_b_prev, const void *d_r_prev, void *stream);
+
+/* Host copy of the preconditioner: h_jdiag[(l * (J + 1) + s) * 4 + o] = alpha D + tau for layer l,
+ * level s in 1..J (1 finest) and orientation o (0 LL, only at s = J; 1 x-high; 2 y-high; 3 HH);
+ * unused entries are 0.  h_jdiag holds n_layers * (J + 1) * 4 doubles.  Requires a bound plan. */
+int fewha_precond_table(const fewha_plan *p, double *h_jdiag);
+
+/* Read the device status word of the last solve (synchronises the device): FEWHA_OK,
+ * FEWHA_ERR_BREAKDOWN or FEWHA_ERR_NONFINITE; FEWHA_ERR_WORKSPACE if unbound. */
+int fewha_last_status(const fewha_plan *p);
+
+/* Static description of a status code. */
+const char *fewha_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FEWHA_H */

@@ -1,0 +1,342 @@
+// C ABI of the FEWHA library (include/fewha.h): argument checks, workspace binding and the
+// sequences of kernel launches behind each call.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "kernels.h"
+
+using namespace fewha;
+
+namespace {
+
+template <typename T>
+Bufs<T> bufs(const Plan &P) {
+    Bufs<T> b{};
+    char *w = P.ws;
+    b.wfs = reinterpret_cast<const DevWfs *>(w + P.o_wfs);
+    b.lay = reinterpret_cast<const DevLayer *>(w + P.o_lay);
+    b.proj = reinterpret_cast<const DevProj *>(w + P.o_proj);
+    b.dm = reinterpret_cast<const DevDm *>(w + P.o_dm);
+    b.idwt_tiles = reinterpret_cast<const Tile *>(w + P.o_idwt);
+    b.node_tiles = reinterpret_cast<const Tile *>(w + P.o_node);
+    b.sub_tiles = reinterpret_cast<const Tile *>(w + P.o_sub);
+    b.lay_tiles = reinterpret_cast<const Tile *>(w + P.o_laytile);
+    b.jinv = reinterpret_cast<const T *>(w + P.o_jinv);
+    b.ad = reinterpret_cast<const T *>(w + P.o_ad);
+    b.b_prev = reinterpret_cast<T *>(w + P.o_bprev);
+    b.r = reinterpret_cast<T *>(w + P.o_r);
+    b.p = reinterpret_cast<T *>(w + P.o_p);
+    b.q = reinterpret_cast<T *>(w + P.o_q);
+    b.y = reinterpret_cast<T *>(w + P.o_y);
+    b.u = reinterpret_cast<T *>(w + P.o_u);
+    b.x = reinterpret_cast<T *>(w + P.o_x);
+    b.v = reinterpret_cast<T *>(w + P.o_v);
+    b.tmpA = reinterpret_cast<T *>(w + P.o_tmpA);
+    b.tmpB = reinterpret_cast<T *>(w + P.o_tmpB);
+    b.b = reinterpret_cast<T *>(w + P.o_b);
+    b.probe_c = reinterpret_cast<T *>(w + P.o_probe_c);
+    b.probe_s = reinterpret_cast<T *>(w + P.o_probe_s);
+    b.partials = reinterpret_cast<double *>(w + P.o_partials);
+    b.sc = reinterpret_cast<Scalars *>(w + P.o_scalars);
+    return b;
+}
+
+template <typename T>
+Ops<T> ops(const Plan &P, void *stream) {
+    return Ops<T>{P, bufs<T>(P), static_cast<hipStream_t>(stream)};
+}
+
+#define TRY(x)                          \
+    do {                                \
+        int _e = (x);                   \
+        if (_e != FEWHA_OK) return _e;  \
+    } while (0)
+
+#define HIPTRY(x)                                          \
+    do {                                                   \
+        if ((x) != hipSuccess) return FEWHA_ERR_HIP;       \
+    } while (0)
+
+int ready(const fewha_plan *p) {
+    if (!p) return FEWHA_ERR_INVALID_ARG;
+    if (!p->p.bound) return FEWHA_ERR_WORKSPACE;
+    return FEWHA_OK;
+}
+
+template <typename T>
+int apply_A(const Plan &P, const void *c, void *s, void *stream) {
+    auto o = ops<T>(P, stream);
+    TRY(o.idwt(static_cast<const T *>(c), o.B.u, false));
+    return o.slopes(o.B.u, static_cast<T *>(s));
+}
+
+template <typename T>
+int apply_At(const Plan &P, const void *s, void *c, void *stream) {
+    auto o = ops<T>(P, stream);
+    TRY(o.nodes(static_cast<const T *>(s), o.B.v, kModeAdj));
+    TRY(o.pt(o.B.v, o.B.x));
+    return o.fdwt(o.B.x, static_cast<T *>(c));
+}
+
+template <typename T>
+int apply_M(const Plan &P, const void *c, void *y, void *stream) {
+    auto o = ops<T>(P, stream);
+    TRY(o.idwt(static_cast<const T *>(c), o.B.u, false));
+    TRY(o.nodes(o.B.u, o.B.v, kModeM));
+    TRY(o.pt(o.B.v, o.B.x));
+    TRY(o.fdwt(o.B.x, static_cast<T *>(y)));
+    return o.add_prior(static_cast<T *>(y), static_cast<const T *>(c));
+}
+
+template <typename T>
+int pcg_solve(const Plan &P, const void *s, void *c, int n_iter, int flags, double *resnorm, void *stream) {
+    auto o = ops<T>(P, stream);
+    T *cc = static_cast<T *>(c);
+    // right-hand side b = W P^T Gamma^T C s, then the warm-restart residual update
+    TRY(o.nodes(static_cast<const T *>(s), o.B.v, kModeRhs));
+    TRY(o.pt(o.B.v, o.B.x));
+    TRY(o.fdwt(o.B.x, o.B.b));
+    TRY(o.residual(cc, flags == FEWHA_COLD));
+    for (int k = 0; k < n_iter; ++k) {
+        // y = M z with z = J^-1 r folded into the inverse transform's loads
+        TRY(o.idwt(o.B.r, o.B.u, true));
+        TRY(o.nodes(o.B.u, o.B.v, kModeM));
+        TRY(o.pt(o.B.v, o.B.x));
+        TRY(o.fdwt(o.B.x, o.B.y));
+        TRY(o.dots(k, resnorm));
+        TRY(o.update(cc, k));
+    }
+    return FEWHA_OK;
+}
+
+template <typename T>
+int fit_dm(const Plan &P, const void *c, const void *a_prev, double gain, void *a, void *stream) {
+    auto o = ops<T>(P, stream);
+    TRY(o.idwt(static_cast<const T *>(c), o.B.u, false));
+    return o.fit(o.B.u, static_cast<const T *>(a_prev), static_cast<T *>(a), gain);
+}
+
+template <typename T>
+int bind_tables(Plan &P, hipStream_t st) {
+    auto o = ops<T>(P, st);
+    char *w = P.ws;
+    HIPTRY(hipMemcpy(w + P.o_wfs, P.dwfs.data(), sizeof(DevWfs) * P.dwfs.size(), hipMemcpyHostToDevice));
+    HIPTRY(hipMemcpy(w + P.o_lay, P.dlay.data(), sizeof(DevLayer) * P.dlay.size(), hipMemcpyHostToDevice));
+    HIPTRY(hipMemcpy(w + P.o_proj, P.dproj.data(), sizeof(DevProj) * P.dproj.size(), hipMemcpyHostToDevice));
+    HIPTRY(hipMemcpy(w + P.o_dm, P.ddm.data(), sizeof(DevDm) * P.ddm.size(), hipMemcpyHostToDevice));
+    HIPTRY(hipMemcpy(w + P.o_idwt, P.idwt_tiles.data(), sizeof(Tile) * P.idwt_tiles.size(), hipMemcpyHostToDevice));
+    HIPTRY(hipMemcpy(w + P.o_node, P.node_tiles.data(), sizeof(Tile) * P.node_tiles.size(), hipMemcpyHostToDevice));
+    HIPTRY(hipMemcpy(w + P.o_sub, P.sub_tiles.data(), sizeof(Tile) * P.sub_tiles.size(), hipMemcpyHostToDevice));
+    HIPTRY(hipMemcpy(w + P.o_laytile, P.lay_tiles.data(), sizeof(Tile) * P.lay_tiles.size(), hipMemcpyHostToDevice));
+    const int nb = P.nl * (P.J + 1);
+    std::vector<T> ad(nb);
+    for (int k = 0; k < nb; ++k) ad[k] = (T)P.ad[k];
+    HIPTRY(hipMemcpy(w + P.o_ad, ad.data(), sizeof(T) * nb, hipMemcpyHostToDevice));
+    const long N = (long)P.n_coef;
+    TRY(o.init_scalars());
+    TRY(o.fill(o.B.b_prev, N, 0));
+    TRY(o.fill(o.B.r, N, 0));
+    TRY(o.fill(o.B.probe_c, N, 0));
+
+    // Preconditioner of Sec. 3.4: J = alpha D + tau per (layer, level, orientation), with tau the
+    // data-term diagonal ||C^1/2 A e_k||^2 at the band's representative coefficient
+    // (block-local position (m/2, m/2)).
+    P.jtab.assign(size_t(nb) * 4, 0.0);
+    for (int l = 0; l < P.nl; ++l) {
+        const int n = P.lay[l].n;
+        for (int s = 1; s <= P.J; ++s)
+            for (int ori = 0; ori < 4; ++ori) {
+                if (ori == 0 && s != P.J) continue;
+                const int m = n >> s;
+                const int r0 = (ori == 2 || ori == 3) ? m : 0, c0 = (ori == 1 || ori == 3) ? m : 0;
+                const long k = P.dlay[l].c_off + (long)(r0 + m / 2) * n + (c0 + m / 2);
+                TRY(o.fill(o.B.probe_c + k, 1, (T)1));
+                TRY(apply_A<T>(P, o.B.probe_c, o.B.probe_s, st));
+                TRY(o.wnorm(o.B.probe_s));
+                TRY(o.fill(o.B.probe_c + k, 1, (T)0));
+                double tau = 0;
+                HIPTRY(hipMemcpyAsync(&tau, &o.B.sc->rho, sizeof(double), hipMemcpyDeviceToHost, st));
+                HIPTRY(hipStreamSynchronize(st));
+                P.jtab[size_t(l * (P.J + 1) + s) * 4 + ori] = P.ad[size_t(l) * (P.J + 1) + s] + tau;
+            }
+    }
+    std::vector<T> jinv(size_t(nb) * 4, (T)0);
+    for (size_t k = 0; k < jinv.size(); ++k)
+        if (P.jtab[k] > 0) jinv[k] = (T)(1.0 / P.jtab[k]);
+    HIPTRY(hipMemcpy(w + P.o_jinv, jinv.data(), sizeof(T) * jinv.size(), hipMemcpyHostToDevice));
+    TRY(o.init_scalars());
+    HIPTRY(hipStreamSynchronize(st));
+    return FEWHA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fewha_plan_create(const fewha_config *cfg, fewha_plan **out) {
+    if (!out) return FEWHA_ERR_INVALID_ARG;
+    *out = nullptr;
+    Plan *P = nullptr;
+    int st = plan_create(cfg, &P);
+    if (st != FEWHA_OK) return st;
+    fewha_plan *h = new (std::nothrow) fewha_plan;
+    if (!h) {
+        delete P;
+        return FEWHA_ERR_INVALID_ARG;
+    }
+    h->p = std::move(*P);
+    delete P;
+    *out = h;
+    return FEWHA_OK;
+}
+
+size_t fewha_workspace_bytes(const fewha_plan *p) { return p ? p->p.ws_bytes : 0; }
+
+int fewha_plan_bind(fewha_plan *p, void *d_workspace, size_t bytes, void *stream) {
+    if (!p || !d_workspace) return FEWHA_ERR_INVALID_ARG;
+    Plan &P = p->p;
+    if (bytes < P.ws_bytes || (reinterpret_cast<uintptr_t>(d_workspace) & 255)) return FEWHA_ERR_WORKSPACE;
+    int dev = -1;
+    HIPTRY(hipGetDevice(&dev));
+    P.ws = static_cast<char *>(d_workspace);
+    P.device = dev;
+    P.bound = false;
+    int st = P.prec == FEWHA_FP64 ? bind_tables<double>(P, static_cast<hipStream_t>(stream))
+                                  : bind_tables<float>(P, static_cast<hipStream_t>(stream));
+    if (st != FEWHA_OK) return st;
+    P.bound = true;
+    return FEWHA_OK;
+}
+
+int fewha_plan_destroy(fewha_plan *p) {
+    delete p;
+    return FEWHA_OK;
+}
+
+int fewha_sizes(const fewha_plan *p, size_t *n_coef, size_t *n_slopes, size_t *n_act) {
+    if (!p) return FEWHA_ERR_INVALID_ARG;
+    if (n_coef) *n_coef = p->p.n_coef;
+    if (n_slopes) *n_slopes = p->p.n_slopes;
+    if (n_act) *n_act = p->p.n_act;
+    return FEWHA_OK;
+}
+
+int fewha_apply_A(const fewha_plan *p, const void *d_c, void *d_s, void *stream) {
+    TRY(ready(p));
+    if (!d_c || !d_s) return FEWHA_ERR_INVALID_ARG;
+    return p->p.prec == FEWHA_FP64 ? apply_A<double>(p->p, d_c, d_s, stream) : apply_A<float>(p->p, d_c, d_s, stream);
+}
+
+int fewha_apply_At(const fewha_plan *p, const void *d_s, void *d_c, void *stream) {
+    TRY(ready(p));
+    if (!d_c || !d_s) return FEWHA_ERR_INVALID_ARG;
+    return p->p.prec == FEWHA_FP64 ? apply_At<double>(p->p, d_s, d_c, stream)
+                                   : apply_At<float>(p->p, d_s, d_c, stream);
+}
+
+int fewha_apply_M(const fewha_plan *p, const void *d_c, void *d_y, void *stream) {
+    TRY(ready(p));
+    if (!d_c || !d_y || d_c == d_y) return FEWHA_ERR_INVALID_ARG;
+    return p->p.prec == FEWHA_FP64 ? apply_M<double>(p->p, d_c, d_y, stream) : apply_M<float>(p->p, d_c, d_y, stream);
+}
+
+int fewha_dwt_forward(const fewha_plan *p, const void *d_layers, void *d_c, void *stream) {
+    TRY(ready(p));
+    if (!d_layers || !d_c || d_layers == d_c) return FEWHA_ERR_INVALID_ARG;
+    if (p->p.prec == FEWHA_FP64) {
+        auto o = ops<double>(p->p, stream);
+        return o.fdwt(static_cast<const double *>(d_layers), static_cast<double *>(d_c));
+    }
+    auto o = ops<float>(p->p, stream);
+    return o.fdwt(static_cast<const float *>(d_layers), static_cast<float *>(d_c));
+}
+
+int fewha_dwt_inverse(const fewha_plan *p, const void *d_c, void *d_layers, void *stream) {
+    TRY(ready(p));
+    if (!d_layers || !d_c || d_layers == d_c) return FEWHA_ERR_INVALID_ARG;
+    if (p->p.prec == FEWHA_FP64) {
+        auto o = ops<double>(p->p, stream);
+        return o.idwt(static_cast<const double *>(d_c), static_cast<double *>(d_layers), false);
+    }
+    auto o = ops<float>(p->p, stream);
+    return o.idwt(static_cast<const float *>(d_c), static_cast<float *>(d_layers), false);
+}
+
+int fewha_pcg_solve(fewha_plan *p, const void *d_s, void *d_c, int n_iter, int flags, double *d_resnorm,
+                    void *stream) {
+    TRY(ready(p));
+    if (!d_s || !d_c || n_iter < 0 || (flags != FEWHA_COLD && flags != FEWHA_WARM)) return FEWHA_ERR_INVALID_ARG;
+    return p->p.prec == FEWHA_FP64 ? pcg_solve<double>(p->p, d_s, d_c, n_iter, flags, d_resnorm, stream)
+                                   : pcg_solve<float>(p->p, d_s, d_c, n_iter, flags, d_resnorm, stream);
+}
+
+int fewha_fit_dm(const fewha_plan *p, const void *d_c, const void *d_a_prev, double gain, void *d_a, void *stream) {
+    TRY(ready(p));
+    if (!d_c || !d_a || d_a == d_c || !std::isfinite(gain)) return FEWHA_ERR_INVALID_ARG;
+    return p->p.prec == FEWHA_FP64 ? fit_dm<double>(p->p, d_c, d_a_prev, gain, d_a, stream)
+                                   : fit_dm<float>(p->p, d_c, d_a_prev, gain, d_a, stream);
+}
+
+int fewha_state_get(const fewha_plan *p, void *d_b_prev, void *d_r_prev, void *stream) {
+    TRY(ready(p));
+    if (!d_b_prev || !d_r_prev) return FEWHA_ERR_INVALID_ARG;
+    const long N = (long)p->p.n_coef;
+    if (p->p.prec == FEWHA_FP64) {
+        auto o = ops<double>(p->p, stream);
+        TRY(o.copy(static_cast<double *>(d_b_prev), o.B.b_prev, N));
+        return o.copy(static_cast<double *>(d_r_prev), o.B.r, N);
+    }
+    auto o = ops<float>(p->p, stream);
+    TRY(o.copy(static_cast<float *>(d_b_prev), o.B.b_prev, N));
+    return o.copy(static_cast<float *>(d_r_prev), o.B.r, N);
+}
+
+int fewha_state_set(fewha_plan *p, const void *d_b_prev, const void *d_r_prev, void *stream) {
+    TRY(ready(p));
+    if (!d_b_prev || !d_r_prev) return FEWHA_ERR_INVALID_ARG;
+    const long N = (long)p->p.n_coef;
+    if (p->p.prec == FEWHA_FP64) {
+        auto o = ops<double>(p->p, stream);
+        TRY(o.copy(o.B.b_prev, static_cast<const double *>(d_b_prev), N));
+        return o.copy(o.B.r, static_cast<const double *>(d_r_prev), N);
+    }
+    auto o = ops<float>(p->p, stream);
+    TRY(o.copy(o.B.b_prev, static_cast<const float *>(d_b_prev), N));
+    return o.copy(o.B.r, static_cast<const float *>(d_r_prev), N);
+}
+
+int fewha_precond_table(const fewha_plan *p, double *h_jdiag) {
+    TRY(ready(p));
+    if (!h_jdiag) return FEWHA_ERR_INVALID_ARG;
+    std::memcpy(h_jdiag, p->p.jtab.data(), sizeof(double) * p->p.jtab.size());
+    return FEWHA_OK;
+}
+
+int fewha_last_status(const fewha_plan *p) {
+    TRY(ready(p));
+    int st = 0;
+    const Scalars *sc = reinterpret_cast<const Scalars *>(p->p.ws + p->p.o_scalars);
+    if (hipMemcpy(&st, &sc->status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return FEWHA_ERR_HIP;
+    return st;
+}
+
+const char *fewha_strerror(int status) {
+    switch (status) {
+        case FEWHA_OK: return "ok";
+        case FEWHA_ERR_INVALID_ARG: return "invalid argument";
+        case FEWHA_ERR_GEOMETRY: return "geometry: a projected point or actuator leaves its layer grid";
+        case FEWHA_ERR_UNSUPPORTED: return "configuration outside the implemented limits";
+        case FEWHA_ERR_HIP: return "HIP runtime error";
+        case FEWHA_ERR_WORKSPACE: return "plan not bound or workspace too small";
+        case FEWHA_ERR_BREAKDOWN: return "PCG breakdown (non-positive curvature)";
+        case FEWHA_ERR_NONFINITE: return "non-finite value in a PCG reduction";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

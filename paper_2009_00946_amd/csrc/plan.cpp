@@ -1,0 +1,249 @@
+// Host side of the FEWHA plan: configuration checks, ray geometry, vector layouts, tile tables
+// and the workspace map.  Touches no GPU, so configuration validation is testable anywhere.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "fewha_internal.h"
+
+namespace fewha {
+
+namespace {
+
+bool pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+int ilog2(int n) {
+    int k = 0;
+    while ((1 << k) < n) ++k;
+    return k;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Grid coordinate of a metric position on a layer (node k at (k - n/2) spacing).
+double grid_coord(const fewha_layer &l, double X) { return X / l.spacing + l.n / 2; }
+
+bool inside(double u, int n) { return u >= 0.0 && u <= double(n - 1); }
+
+}  // namespace
+
+// Level s (1 finest .. J) and orientation o (0 LL, 1 x-high/y-low, 2 x-low/y-high, 3 HH) of
+// Mallat position (row, col) in an n x n pyramid of J levels.
+int level_band(int n, int J, int row, int col, int *s, int *o) {
+    int v = row > col ? row : col;
+    int mJ = n >> J;
+    if (v < mJ) {
+        *s = J;
+        *o = 0;
+        return 0;
+    }
+    int lv = 0;
+    while ((2 << lv) <= v) ++lv;  // 2^lv <= v < 2^(lv+1): band size m = 2^lv
+    int m = 1 << lv;
+    *s = ilog2(n) - lv;
+    *o = (row < m) ? 1 : ((col < m) ? 2 : 3);
+    return 0;
+}
+
+int plan_create(const fewha_config *cfg, Plan **out) {
+    if (!cfg || !out) return FEWHA_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (cfg->n_wfs < 1 || cfg->n_layers < 1 || cfg->n_dms < 1 || cfg->J < 1 || !cfg->wfs || !cfg->layers ||
+        !cfg->dms)
+        return FEWHA_ERR_INVALID_ARG;
+    if (cfg->n_wfs > kMaxWfs || cfg->n_layers > kMaxLayers || cfg->n_dms > kMaxDms || cfg->J > kMaxJ)
+        return FEWHA_ERR_UNSUPPORTED;
+    if (!(cfg->D > 0) || !(cfg->obstruction >= 0 && cfg->obstruction < 1) || !(cfg->alpha_reg > 0) ||
+        !std::isfinite(cfg->D) || !std::isfinite(cfg->alpha_reg))
+        return FEWHA_ERR_INVALID_ARG;
+    if (cfg->precision != FEWHA_FP32 && cfg->precision != FEWHA_FP64) return FEWHA_ERR_INVALID_ARG;
+    for (int l = 0; l < cfg->n_layers; ++l) {
+        const fewha_layer &L = cfg->layers[l];
+        if (!pow2(L.n) || L.n < 2 || (L.n >> cfg->J) < 1 || !(L.spacing > 0) || !(L.cn2_weight > 0) ||
+            !(L.height >= 0) || !std::isfinite(L.spacing) || !std::isfinite(L.height))
+            return FEWHA_ERR_INVALID_ARG;
+        if (L.n > kMaxGrid) return FEWHA_ERR_UNSUPPORTED;
+    }
+    for (int g = 0; g < cfg->n_wfs; ++g) {
+        const fewha_wfs &W = cfg->wfs[g];
+        if (W.n_sub < 1 || !(W.sigma > 0) || !(W.gs_height >= 0) || !std::isfinite(W.theta_x) ||
+            !std::isfinite(W.theta_y) || !std::isfinite(W.gs_height))
+            return FEWHA_ERR_INVALID_ARG;
+        if (W.n_sub > kMaxGrid) return FEWHA_ERR_UNSUPPORTED;
+    }
+    for (int m = 0; m < cfg->n_dms; ++m)
+        if (cfg->dms[m].n_act < 2 || !(cfg->dms[m].pitch > 0) || !std::isfinite(cfg->dms[m].height))
+            return FEWHA_ERR_INVALID_ARG;
+
+    Plan *P = new (std::nothrow) Plan();
+    if (!P) return FEWHA_ERR_INVALID_ARG;
+    P->wfs.assign(cfg->wfs, cfg->wfs + cfg->n_wfs);
+    P->lay.assign(cfg->layers, cfg->layers + cfg->n_layers);
+    P->dm.assign(cfg->dms, cfg->dms + cfg->n_dms);
+    P->D = cfg->D;
+    P->obstruction = cfg->obstruction;
+    P->alpha_reg = cfg->alpha_reg;
+    P->J = cfg->J;
+    P->nl = cfg->n_layers;
+    P->nw = cfg->n_wfs;
+    P->nd = cfg->n_dms;
+    P->prec = cfg->precision;
+    P->elem = P->prec == FEWHA_FP64 ? 8 : 4;
+
+    // layers
+    for (int l = 0; l < P->nl; ++l) {
+        const fewha_layer &L = P->lay[l];
+        DevLayer d{};
+        d.c_off = long(P->n_coef);
+        d.spacing = L.spacing;
+        d.half = L.n / 2;
+        d.n = L.n;
+        d.log2n = ilog2(L.n);
+        // fitting: nearest DM in altitude, ties to the lower one
+        int best = 0;
+        for (int m = 1; m < P->nd; ++m) {
+            double dn = std::fabs(L.height - P->dm[m].height), db = std::fabs(L.height - P->dm[best].height);
+            if (dn < db || (dn == db && P->dm[m].height < P->dm[best].height)) best = m;
+        }
+        d.dm = best;
+        P->dlay.push_back(d);
+        P->n_coef += size_t(L.n) * L.n;
+    }
+    // guide stars
+    for (int g = 0; g < P->nw; ++g) {
+        const fewha_wfs &W = P->wfs[g];
+        DevWfs d{};
+        d.d = P->D / W.n_sub;
+        d.x0 = -P->D / 2;
+        d.inv_var = 1.0 / (W.sigma * W.sigma);
+        d.r_out2 = (P->D / 2) * (P->D / 2);
+        d.r_in2 = (P->obstruction * P->D / 2) * (P->obstruction * P->D / 2);
+        d.s_off = long(P->n_slopes);
+        d.v_off = long(P->n_nodes);
+        d.n_sub = W.n_sub;
+        d.nv = W.n_sub + 1;
+        P->dwfs.push_back(d);
+        P->n_slopes += 2 * size_t(W.n_sub) * W.n_sub;
+        P->n_nodes += size_t(W.n_sub + 1) * (W.n_sub + 1);
+    }
+    // DMs
+    for (int m = 0; m < P->nd; ++m) {
+        DevDm d{};
+        d.a_off = long(P->n_act);
+        d.pitch = P->dm[m].pitch;
+        d.centre = (P->dm[m].n_act - 1) / 2.0;
+        d.n_act = P->dm[m].n_act;
+        P->ddm.push_back(d);
+        P->n_act += size_t(P->dm[m].n_act) * P->dm[m].n_act;
+    }
+    // ray geometry and the grid checks of Sec. 2.1
+    int status = FEWHA_OK;
+    for (int g = 0; g < P->nw && status == FEWHA_OK; ++g) {
+        const fewha_wfs &W = P->wfs[g];
+        const DevWfs &dw = P->dwfs[g];
+        for (int l = 0; l < P->nl; ++l) {
+            const fewha_layer &L = P->lay[l];
+            if (W.gs_height > 0 && !(L.height < W.gs_height)) {
+                status = FEWHA_ERR_GEOMETRY;
+                break;
+            }
+            DevProj pr{};
+            pr.sig = W.gs_height > 0 ? 1.0 - L.height / W.gs_height : 1.0;
+            pr.hx = W.theta_x * L.height;
+            pr.hy = W.theta_y * L.height;
+            pr.slope = pr.sig * dw.d / L.spacing;
+            pr.bx = grid_coord(L, pr.sig * dw.x0 + pr.hx);
+            pr.by = grid_coord(L, pr.sig * dw.x0 + pr.hy);
+            // the map is affine and increasing in the node index: checking both ends suffices
+            double u0 = grid_coord(L, pr.sig * (dw.x0 + 0 * dw.d) + pr.hx);
+            double u1 = grid_coord(L, pr.sig * (dw.x0 + W.n_sub * dw.d) + pr.hx);
+            double v0 = grid_coord(L, pr.sig * (dw.x0 + 0 * dw.d) + pr.hy);
+            double v1 = grid_coord(L, pr.sig * (dw.x0 + W.n_sub * dw.d) + pr.hy);
+            if (!inside(u0, L.n) || !inside(u1, L.n) || !inside(v0, L.n) || !inside(v1, L.n)) {
+                status = FEWHA_ERR_GEOMETRY;
+                break;
+            }
+            // the transpose gather keeps at most 24 sensor nodes per layer node and axis
+            if (pr.slope < 0.1) {
+                status = FEWHA_ERR_UNSUPPORTED;
+                break;
+            }
+            P->dproj.push_back(pr);
+        }
+    }
+    for (int l = 0; l < P->nl && status == FEWHA_OK; ++l) {
+        const fewha_layer &L = P->lay[l];
+        const DevDm &d = P->ddm[P->dlay[l].dm];
+        double lo = grid_coord(L, (0 - d.centre) * d.pitch), hi = grid_coord(L, ((d.n_act - 1) - d.centre) * d.pitch);
+        if (!inside(lo, L.n) || !inside(hi, L.n)) status = FEWHA_ERR_GEOMETRY;
+    }
+    if (status != FEWHA_OK) {
+        delete P;
+        return status;
+    }
+
+    // alpha D per (layer, level): prior read as the Kolmogorov scale law
+    // gamma^-1 (spacing / d_1)^(-5/3) 2^(-(11/3)(s-1)), d_1 = subaperture size of the first sensor
+    P->ad.assign(size_t(P->nl) * (P->J + 1), 0.0);
+    for (int l = 0; l < P->nl; ++l)
+        for (int s = 1; s <= P->J; ++s)
+            P->ad[size_t(l) * (P->J + 1) + s] = P->alpha_reg / P->lay[l].cn2_weight *
+                                                std::pow(P->lay[l].spacing / P->dwfs[0].d, -5.0 / 3.0) *
+                                                std::pow(2.0, -(11.0 / 3.0) * (s - 1));
+
+    // tile tables
+    for (int l = 0; l < P->nl; ++l) {
+        int n = P->lay[l].n, t = n < kIdwtTile ? n : kIdwtTile;
+        for (int ty = 0; ty < n; ty += t)
+            for (int tx = 0; tx < n; tx += t) P->idwt_tiles.push_back({l, ty, tx, t});
+        for (int ty = 0; ty < n; ty += kNodeTile)
+            for (int tx = 0; tx < n; tx += kNodeTile) P->lay_tiles.push_back({l, ty, tx, 0});
+    }
+    for (int g = 0; g < P->nw; ++g) {
+        int nv = P->wfs[g].n_sub + 1, ns = P->wfs[g].n_sub;
+        for (int i = 0; i < nv; i += kNodeTile)
+            for (int j = 0; j < nv; j += kNodeTile) P->node_tiles.push_back({g, i, j, 0});
+        for (int i = 0; i < ns; i += kNodeTile)
+            for (int j = 0; j < ns; j += kNodeTile) P->sub_tiles.push_back({g, i, j, 0});
+    }
+
+    // workspace map
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    const size_t E = P->elem, N = P->n_coef;
+    P->o_wfs = take(sizeof(DevWfs) * P->nw);
+    P->o_lay = take(sizeof(DevLayer) * P->nl);
+    P->o_proj = take(sizeof(DevProj) * P->nw * P->nl);
+    P->o_dm = take(sizeof(DevDm) * P->nd);
+    P->o_idwt = take(sizeof(Tile) * P->idwt_tiles.size());
+    P->o_node = take(sizeof(Tile) * P->node_tiles.size());
+    P->o_sub = take(sizeof(Tile) * P->sub_tiles.size());
+    P->o_laytile = take(sizeof(Tile) * P->lay_tiles.size());
+    P->o_jinv = take(E * P->nl * (P->J + 1) * 4);
+    P->o_ad = take(E * P->nl * (P->J + 1));
+    P->o_bprev = take(E * N);
+    P->o_r = take(E * N);
+    P->o_p = take(E * N);
+    P->o_q = take(E * N);
+    P->o_y = take(E * N);
+    P->o_u = take(E * N);
+    P->o_x = take(E * N);
+    P->o_v = take(E * P->n_nodes);
+    P->o_tmpA = take(E * (N / 4 + 1));
+    P->o_tmpB = take(E * (N / 4 + 1));
+    P->o_b = take(E * N);
+    P->o_probe_c = take(E * N);
+    P->o_probe_s = take(E * P->n_slopes);
+    P->n_partials = 1024;
+    P->o_partials = take(sizeof(double) * 2 * P->n_partials);
+    P->o_scalars = take(sizeof(Scalars));
+    P->ws_bytes = o;
+    *out = P;
+    return FEWHA_OK;
+}
+
+}  // namespace fewha

@@ -1,0 +1,236 @@
+"""Python binding of the FEWHA MI355X library (``libfewha.so``, C ABI in include/fewha.h).
+
+Argument marshalling only: every operation runs in the library's HIP kernels.  PyTorch
+provides device memory (the plan workspace and all vectors are torch CUDA tensors) and the
+stream (``torch.cuda.current_stream()``).  There is no CPU fallback: without the built
+library every entry point raises.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfewha.so")
+
+FEWHA_FP32, FEWHA_FP64 = 0, 1
+FEWHA_COLD, FEWHA_WARM = 0, 1
+STATUS = {0: "FEWHA_OK", -1: "FEWHA_ERR_INVALID_ARG", -2: "FEWHA_ERR_GEOMETRY", -3: "FEWHA_ERR_UNSUPPORTED",
+          -4: "FEWHA_ERR_HIP", -5: "FEWHA_ERR_WORKSPACE", -6: "FEWHA_ERR_BREAKDOWN", -7: "FEWHA_ERR_NONFINITE"}
+
+EXPORTS = ["fewha_plan_create", "fewha_workspace_bytes", "fewha_plan_bind", "fewha_plan_destroy", "fewha_sizes",
+           "fewha_apply_A", "fewha_apply_At", "fewha_apply_M", "fewha_dwt_forward", "fewha_dwt_inverse",
+           "fewha_pcg_solve", "fewha_fit_dm", "fewha_state_get", "fewha_state_set", "fewha_precond_table",
+           "fewha_last_status", "fewha_strerror"]
+
+
+class FewhaError(RuntimeError):
+    def __init__(self, status, what=""):
+        super().__init__("%s: %s (%d)" % (what, STATUS.get(status, "unknown"), status))
+        self.status = status
+
+
+class _Wfs(ctypes.Structure):
+    _fields_ = [("n_sub", ctypes.c_int), ("theta_x", ctypes.c_double), ("theta_y", ctypes.c_double),
+                ("gs_height", ctypes.c_double), ("sigma", ctypes.c_double)]
+
+
+class _Layer(ctypes.Structure):
+    _fields_ = [("height", ctypes.c_double), ("cn2_weight", ctypes.c_double), ("spacing", ctypes.c_double),
+                ("n", ctypes.c_int)]
+
+
+class _Dm(ctypes.Structure):
+    _fields_ = [("height", ctypes.c_double), ("pitch", ctypes.c_double), ("n_act", ctypes.c_int)]
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_double), ("obstruction", ctypes.c_double), ("n_wfs", ctypes.c_int),
+                ("n_layers", ctypes.c_int), ("n_dms", ctypes.c_int), ("J", ctypes.c_int),
+                ("wfs", ctypes.POINTER(_Wfs)), ("layers", ctypes.POINTER(_Layer)), ("dms", ctypes.POINTER(_Dm)),
+                ("alpha_reg", ctypes.c_double), ("precision", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libfewha.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libfewha.so is not built (run python -m paper_2009_00946_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    L.fewha_plan_create.argtypes = [ctypes.POINTER(_Config), ctypes.POINTER(vp)]
+    L.fewha_workspace_bytes.argtypes = [vp]
+    L.fewha_workspace_bytes.restype = sz
+    L.fewha_plan_bind.argtypes = [vp, vp, sz, vp]
+    L.fewha_plan_destroy.argtypes = [vp]
+    L.fewha_sizes.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz), ctypes.POINTER(sz)]
+    for name in ("fewha_apply_A", "fewha_apply_At", "fewha_apply_M", "fewha_dwt_forward", "fewha_dwt_inverse",
+                 "fewha_state_get", "fewha_state_set"):
+        getattr(L, name).argtypes = [vp, vp, vp, vp]
+    L.fewha_pcg_solve.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, vp]
+    L.fewha_fit_dm.argtypes = [vp, vp, vp, ctypes.c_double, vp, vp]
+    L.fewha_precond_table.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.fewha_last_status.argtypes = [vp]
+    L.fewha_strerror.argtypes = [ctypes.c_int]
+    L.fewha_strerror.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(st, what):
+    if st != 0:
+        raise FewhaError(st, what)
+
+
+def make_config(cfg, precision=None):
+    """ctypes fewha_config from a configuration dictionary; returns (struct, keepalive)."""
+    prec = cfg.get("precision", "fp32") if precision is None else precision
+    prec = FEWHA_FP64 if prec in ("fp64", FEWHA_FP64) else FEWHA_FP32
+    wfs = (_Wfs * len(cfg["wfs"]))(*[_Wfs(int(w["n_sub"]), float(w["theta_x"]), float(w["theta_y"]),
+                                          float(w["gs_height"]), float(w["sigma"])) for w in cfg["wfs"]])
+    lay = (_Layer * len(cfg["layers"]))(*[_Layer(float(l["height"]), float(l["cn2_weight"]), float(l["spacing"]),
+                                                 int(l["n"])) for l in cfg["layers"]])
+    dms = (_Dm * len(cfg["dms"]))(*[_Dm(float(d["height"]), float(d["pitch"]), int(d["n_act"])) for d in cfg["dms"]])
+    c = _Config(float(cfg["D"]), float(cfg.get("obstruction", 0.0)), len(cfg["wfs"]), len(cfg["layers"]),
+                len(cfg["dms"]), int(cfg["J"]), wfs, lay, dms, float(cfg["alpha_reg"]), prec)
+    return c, (wfs, lay, dms)
+
+
+def create_host_plan(cfg, precision=None):
+    """Validate and size a plan without touching a GPU; returns (handle, status)."""
+    L = load_library()
+    c, keep = make_config(cfg, precision)
+    h = ctypes.c_void_p()
+    st = L.fewha_plan_create(ctypes.byref(c), ctypes.byref(h))
+    return (h if st == 0 else None), st
+
+
+class Plan:
+    """A bound FEWHA plan on the current CUDA (HIP) device.
+
+    ``precision`` overrides the configuration's ("fp32" or "fp64").  All tensors must be
+    contiguous CUDA tensors of ``self.dtype`` with the lengths of ``fewha_sizes``.
+    """
+
+    def __init__(self, cfg, precision=None, device=None):
+        import torch
+        self._torch = torch
+        L = load_library()
+        self.cfg = cfg
+        c, keep = make_config(cfg, precision)
+        self.precision = "fp64" if c.precision == FEWHA_FP64 else "fp32"
+        self.dtype = torch.float64 if c.precision == FEWHA_FP64 else torch.float32
+        h = ctypes.c_void_p()
+        _check(L.fewha_plan_create(ctypes.byref(c), ctypes.byref(h)), "fewha_plan_create")
+        self._h = h
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        nc, ns, na = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        L.fewha_sizes(h, ctypes.byref(nc), ctypes.byref(ns), ctypes.byref(na))
+        self.n_coef, self.n_slopes, self.n_act = nc.value, ns.value, na.value
+        nbytes = L.fewha_workspace_bytes(h)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            base = self.workspace.data_ptr()
+            self._ws_ptr = (base + 255) & ~255
+            _check(L.fewha_plan_bind(h, self._ws_ptr, nbytes, self._stream()), "fewha_plan_bind")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.fewha_plan_destroy(h)
+            self._h = None
+
+    # -- helpers -------------------------------------------------------------------------------
+    def _stream(self):
+        return self._torch.cuda.current_stream(self.device).cuda_stream
+
+    def _arg(self, t, n, name):
+        if not t.is_cuda or t.dtype != self.dtype or not t.is_contiguous() or t.numel() != n:
+            raise ValueError("%s: expected a contiguous %s CUDA tensor of %d elements, got %s %s %s"
+                             % (name, self.dtype, n, tuple(t.shape), t.dtype, t.device))
+        return t.data_ptr()
+
+    def _out(self, out, n):
+        if out is None:
+            return self._torch.empty(n, dtype=self.dtype, device=self.device)
+        return out
+
+    def empty(self, n):
+        return self._torch.empty(n, dtype=self.dtype, device=self.device)
+
+    def zeros(self, n):
+        return self._torch.zeros(n, dtype=self.dtype, device=self.device)
+
+    # -- operators -----------------------------------------------------------------------------
+    def apply_A(self, c, out=None):
+        s = self._out(out, self.n_slopes)
+        _check(_lib.fewha_apply_A(self._h, self._arg(c, self.n_coef, "c"), self._arg(s, self.n_slopes, "s"),
+                                  self._stream()), "fewha_apply_A")
+        return s
+
+    def apply_At(self, s, out=None):
+        c = self._out(out, self.n_coef)
+        _check(_lib.fewha_apply_At(self._h, self._arg(s, self.n_slopes, "s"), self._arg(c, self.n_coef, "c"),
+                                   self._stream()), "fewha_apply_At")
+        return c
+
+    def apply_M(self, c, out=None):
+        y = self._out(out, self.n_coef)
+        _check(_lib.fewha_apply_M(self._h, self._arg(c, self.n_coef, "c"), self._arg(y, self.n_coef, "y"),
+                                  self._stream()), "fewha_apply_M")
+        return y
+
+    def dwt_forward(self, layers, out=None):
+        c = self._out(out, self.n_coef)
+        _check(_lib.fewha_dwt_forward(self._h, self._arg(layers, self.n_coef, "layers"),
+                                      self._arg(c, self.n_coef, "c"), self._stream()), "fewha_dwt_forward")
+        return c
+
+    def dwt_inverse(self, c, out=None):
+        x = self._out(out, self.n_coef)
+        _check(_lib.fewha_dwt_inverse(self._h, self._arg(c, self.n_coef, "c"),
+                                      self._arg(x, self.n_coef, "layers"), self._stream()), "fewha_dwt_inverse")
+        return x
+
+    # -- solver --------------------------------------------------------------------------------
+    def pcg_solve(self, s, c, n_iter, warm=True, resnorm=None):
+        """One frame (RHS, residual update, n_iter PCG passes); c is updated in place and returned."""
+        rp = None
+        if resnorm is not None:
+            if not resnorm.is_cuda or resnorm.dtype != self._torch.float64 or resnorm.numel() < n_iter:
+                raise ValueError("resnorm: float64 CUDA tensor of n_iter elements expected")
+            rp = resnorm.data_ptr()
+        _check(_lib.fewha_pcg_solve(self._h, self._arg(s, self.n_slopes, "s"), self._arg(c, self.n_coef, "c"),
+                                    int(n_iter), FEWHA_WARM if warm else FEWHA_COLD, rp, self._stream()),
+               "fewha_pcg_solve")
+        return c
+
+    def fit_dm(self, c, a_prev=None, gain=1.0, out=None):
+        a = self._out(out, self.n_act)
+        ap = None if a_prev is None else self._arg(a_prev, self.n_act, "a_prev")
+        _check(_lib.fewha_fit_dm(self._h, self._arg(c, self.n_coef, "c"), ap, float(gain),
+                                 self._arg(a, self.n_act, "a"), self._stream()), "fewha_fit_dm")
+        return a
+
+    def state_get(self):
+        b, r = self.empty(self.n_coef), self.empty(self.n_coef)
+        _check(_lib.fewha_state_get(self._h, b.data_ptr(), r.data_ptr(), self._stream()), "fewha_state_get")
+        return b, r
+
+    def state_set(self, b_prev, r_prev):
+        _check(_lib.fewha_state_set(self._h, self._arg(b_prev, self.n_coef, "b_prev"),
+                                    self._arg(r_prev, self.n_coef, "r_prev"), self._stream()), "fewha_state_set")
+
+    def precond_table(self):
+        import numpy as np
+        J, nl = int(self.cfg["J"]), len(self.cfg["layers"])
+        out = np.zeros(nl * (J + 1) * 4)
+        _check(_lib.fewha_precond_table(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+               "fewha_precond_table")
+        return out.reshape(nl, J + 1, 4)
+
+    def last_status(self):
+        return _lib.fewha_last_status(self._h)

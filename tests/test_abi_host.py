@@ -1,0 +1,105 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every function the
+public header declares, sizes vectors like the configuration says, and rejects invalid
+configurations with the documented status codes before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2009_00946_amd import fewha, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "fewha.h")).read()
+    return sorted(set(re.findall(r"\b(fewha_[A-Za-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    L = fewha.load_library()
+    names = _declared()
+    assert len(names) >= 17
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(fewha.EXPORTS) == names
+
+
+@pytest.mark.parametrize("name", ["c0_tiny", "c1_elt_mcao", "c3_mid_lgs", "c4_stress", "t1_mixed"])
+def test_sizes_match_configuration(name):
+    cfg = synth.load_config(name)
+    h, st = fewha.create_host_plan(cfg)
+    assert st == 0
+    L = fewha.load_library()
+    nc, ns, na = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.fewha_sizes(h, ctypes.byref(nc), ctypes.byref(ns), ctypes.byref(na)) == 0
+    assert (nc.value, ns.value, na.value) == synth.sizes(cfg)
+    assert L.fewha_workspace_bytes(h) > 4 * 8 * nc.value
+    L.fewha_plan_destroy(h)
+
+
+def _mut(cfg, part, idx, key, val):
+    c = dict(cfg)
+    c[part] = [dict(x) for x in cfg[part]]
+    c[part][idx][key] = val
+    return c
+
+
+@pytest.mark.parametrize("mutation,status", [
+    (("layers", 0, "n", 24), -1),                 # not a power of two
+    (("layers", 0, "n", 8), -1),                  # fewer than 2^J nodes
+    (("layers", 1, "spacing", 0.0), -1),
+    (("layers", 1, "cn2_weight", -0.1), -1),
+    (("wfs", 0, "sigma", 0.0), -1),
+    (("wfs", 0, "n_sub", 0), -1),
+    (("dms", 0, "n_act", 1), -1),
+    (("layers", 1, "spacing", 0.2), -2),          # 8 km footprint leaves the grid
+    (("wfs", 1, "gs_height", 5000.0), -2),        # LGS below a layer
+    (("dms", 0, "pitch", 5.0), -2),               # actuators outside the layer grids
+    (("layers", 0, "n", 8192), -1),               # 8192 > 2^J fine but above the limit -> unsupported? (n>4096)
+])
+def test_invalid_configurations_rejected(mutation, status, cfg_c0):
+    bad = _mut(cfg_c0, *mutation)
+    h, st = fewha.create_host_plan(bad)
+    if mutation[3] == 8192:
+        assert st == -3
+    else:
+        assert st == status
+
+
+def test_global_limits(cfg_c0):
+    L = fewha.load_library()
+    c, keep = fewha.make_config(cfg_c0)
+    c.J = 0
+    h = ctypes.c_void_p()
+    assert L.fewha_plan_create(ctypes.byref(c), ctypes.byref(h)) == -1
+    c, keep = fewha.make_config(cfg_c0)
+    c.alpha_reg = 0.0
+    assert L.fewha_plan_create(ctypes.byref(c), ctypes.byref(h)) == -1
+    c, keep = fewha.make_config(cfg_c0)
+    c.obstruction = 1.0
+    assert L.fewha_plan_create(ctypes.byref(c), ctypes.byref(h)) == -1
+    c, keep = fewha.make_config(cfg_c0)
+    c.precision = 7
+    assert L.fewha_plan_create(ctypes.byref(c), ctypes.byref(h)) == -1
+    assert L.fewha_plan_create(None, ctypes.byref(h)) == -1
+
+
+def test_unbound_plan_refuses_work(cfg_c0):
+    L = fewha.load_library()
+    h, st = fewha.create_host_plan(cfg_c0)
+    assert st == 0
+    assert L.fewha_apply_A(h, 1, 1, None) == -5
+    assert L.fewha_pcg_solve(h, 1, 1, 4, 1, None, None) == -5
+    assert L.fewha_fit_dm(h, 1, None, 1.0, 2, None) == -5
+    assert L.fewha_last_status(h) == -5
+    assert L.fewha_strerror(-6) == b"PCG breakdown (non-positive curvature)"
+    L.fewha_plan_destroy(h)
+
+
+def test_no_cpu_fallback_in_binding():
+    """The binding has no compute path of its own: every operator is a library call."""
+    src = open(os.path.join(ROOT, "paper_2009_00946_amd", "fewha.py")).read()
+    assert "oracle" not in src
+    assert "numpy" not in src.split("def precond_table")[0]

@@ -1,0 +1,229 @@
+"""GPU parity: every C-ABI call against the FP64 oracle on identical seeded inputs.
+
+Tolerances (relative to the reference vector's largest magnitude, checked element by element,
+plus the norm-wise relative error):
+  FP64 plans: operators 1e-12, solver iterates 1e-9;
+  FP32 plans: operators 1e-5, reconstructed layers W^T c 1e-4 per frame (FP32 storage, FP64
+  reductions), the bound the method's spec target states.
+Inputs: seeded von Karman layers / noise from ``synth`` and N(0,1) vectors; slopes are made by
+the oracle (s = Ahat(phi) + mask * noise), never by the GPU.
+"""
+import numpy as np
+import pytest
+
+from paper_2009_00946_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+_plans, _oracles = {}, {}
+
+
+def plan(name, prec):
+    _need_gpu()
+    from paper_2009_00946_amd import fewha
+    key = (name, prec)
+    if key not in _plans:
+        print("\n[bind] %s %s" % key, flush=True)
+        _plans[key] = fewha.Plan(synth.load_config(name), precision=prec)
+    return _plans[key]
+
+
+def oracle(name):
+    from oracle import Oracle
+    if name not in _oracles:
+        _oracles[name] = Oracle(synth.load_config(name))
+    return _oracles[name]
+
+
+def dev(P, x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=P.dtype, device=P.device)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().double().cpu().numpy()
+
+
+def check(got, ref, tol, what=""):
+    got, ref = np.asarray(got, dtype=np.float64), np.asarray(ref, dtype=np.float64)
+    assert got.shape == ref.shape, what
+    assert np.all(np.isfinite(got)), what + ": non-finite output"
+    scale = max(np.abs(ref).max(), 1e-300)
+    err = np.abs(got - ref).max() / scale
+    nrm = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300)
+    assert err <= tol and nrm <= tol, "%s: max-rel %.3e norm-rel %.3e > %.1e" % (what, err, nrm, tol)
+    return err
+
+
+OPS_CASES = [("t1_mixed", "fp64", 1e-12), ("c0_tiny", "fp64", 1e-12), ("t1_mixed", "fp32", 1e-5),
+             ("c1_elt_mcao", "fp32", 1e-5), ("c3_mid_lgs", "fp32", 1e-5)]
+
+
+@pytest.mark.parametrize("name,prec,tol", OPS_CASES)
+def test_dwt_parity(name, prec, tol):
+    P, O = plan(name, prec), oracle(name)
+    x = synth.normal_vector(O.n_coef, 11)
+    c_ref = O.W(x)
+    c = P.dwt_forward(dev(P, x))
+    check(host(c), c_ref, tol, "W")
+    xr = P.dwt_inverse(dev(P, c_ref))
+    check(host(xr), O.Wt(c_ref), tol, "W^T")
+    check(host(P.dwt_inverse(c)), x, 4 * tol, "W^T W")
+
+
+@pytest.mark.parametrize("name,prec,tol", OPS_CASES)
+def test_operator_parity(name, prec, tol):
+    P, O = plan(name, prec), oracle(name)
+    c = synth.normal_vector(O.n_coef, 21)
+    s = synth.normal_vector(O.n_slopes, 22)
+    check(host(P.apply_A(dev(P, c))), O.A(c), tol, "A")
+    check(host(P.apply_At(dev(P, s))), O.At(s), tol, "A^T")
+    check(host(P.apply_M(dev(P, c))), O.M(c), tol, "M")
+
+
+@pytest.mark.parametrize("name,prec,tol", [("t1_mixed", "fp64", 1e-12), ("c0_tiny", "fp64", 1e-12),
+                                           ("c1_elt_mcao", "fp32", 2e-5)])
+def test_precond_table_parity(name, prec, tol):
+    P, O = plan(name, prec), oracle(name)
+    tab = P.precond_table()
+    jd = O.precond()
+    cfg = synth.load_config(name)
+    from oracle.oracle import level_of
+    off = 0
+    for l, lay in enumerate(cfg["layers"]):
+        n, J = lay["n"], cfg["J"]
+        for s in range(1, J + 1):
+            for o in range(4):
+                if o == 0 and s != J:
+                    continue
+                m = n >> s
+                r = (m if o in (2, 3) else 0) + m // 2
+                q = (m if o in (1, 3) else 0) + m // 2
+                assert level_of(n, J, r, q) == (s, o)
+                ref = jd[off + r * n + q]
+                assert abs(tab[l, s, o] - ref) <= tol * ref, (l, s, o, tab[l, s, o], ref)
+        off += n * n
+
+
+def test_gpu_adjointness_fp64():
+    P = plan("t1_mixed", "fp64")
+    rng = np.random.default_rng(3)
+    c, s = rng.standard_normal(P.n_coef), rng.standard_normal(P.n_slopes)
+    lhs = float(np.dot(host(P.apply_A(dev(P, c))), s))
+    rhs = float(np.dot(c, host(P.apply_At(dev(P, s)))))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    y = rng.standard_normal(P.n_coef)
+    lhs = float(np.dot(host(P.apply_M(dev(P, c))), y))
+    rhs = float(np.dot(c, host(P.apply_M(dev(P, y)))))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def _slopes(O, cfg, frame):
+    return O.Ahat(synth.layer_screens_flat(cfg, frame)) + O.slope_mask() * synth.slope_noise(cfg, frame)
+
+
+@pytest.mark.parametrize("name,prec,frames,tol_c,tol_layers", [
+    ("c0_tiny", "fp64", 2, 1e-9, 1e-9),
+    ("t1_mixed", "fp64", 4, 1e-9, 1e-9),
+    ("t1_mixed", "fp32", 4, 1e-3, 1e-4),
+    ("c3_mid_lgs", "fp32", 4, 1e-3, 1e-4),
+    ("c1_elt_mcao", "fp32", 8, 1e-3, 1e-4),
+])
+def test_frame_chain_parity(name, prec, frames, tol_c, tol_layers):
+    """Alg. 1 frames chained by warm restart (cold first frame), GPU vs oracle after every frame."""
+    P, O = plan(name, prec), oracle(name)
+    cfg = synth.load_config(name)
+    n_iter, warm = cfg["n_iter"], cfg["warm"]
+    N = O.n_coef
+    c_ref, bp, rp = np.zeros(N), np.zeros(N), np.zeros(N)
+    c_gpu = P.zeros(N)
+    res = torch.zeros(n_iter, dtype=torch.float64, device=P.device)
+    for f in range(frames):
+        print("[frame] %s %s %d" % (name, prec, f), flush=True)
+        s = _slopes(O, cfg, f)
+        cold = (f == 0) or not warm
+        c_ref, bp, rp, res_ref, st = O.frame(s, c_ref, bp, rp, n_iter, cold)
+        assert st == 0
+        P.pcg_solve(dev(P, s), c_gpu, n_iter, warm=not cold, resnorm=res)
+        assert P.last_status() == 0
+        check(host(c_gpu), c_ref, tol_c, "c frame %d" % f)
+        check(host(P.dwt_inverse(c_gpu)), O.Wt(c_ref), tol_layers, "layers frame %d" % f)
+        check(host(res), res_ref, max(tol_c, 1e-6) if prec == "fp32" else 1e-9, "resnorm frame %d" % f)
+        b_g, r_g = P.state_get()
+        check(host(b_g), bp, 1e-5 if prec == "fp32" else 1e-12, "b_prev frame %d" % f)
+
+
+@pytest.mark.parametrize("name,prec,tol", [("t1_mixed", "fp64", 1e-12), ("c1_elt_mcao", "fp32", 1e-5),
+                                           ("c0_tiny", "fp64", 1e-12)])
+def test_fit_parity(name, prec, tol):
+    P, O = plan(name, prec), oracle(name)
+    c = synth.normal_vector(O.n_coef, 31)
+    a_prev = synth.normal_vector(O.n_act, 32)
+    check(host(P.fit_dm(dev(P, c))), O.fit(c, None, 1.0), tol, "fit gain 1")
+    check(host(P.fit_dm(dev(P, c), dev(P, a_prev), 0.5)), O.fit(c, a_prev, 0.5), tol, "fit gain 0.5")
+
+
+def test_outputs_fully_overwritten():
+    """NaN-poisoned outputs must come back finite: every element is written."""
+    P = plan("t1_mixed", "fp32")
+    c = dev(P, synth.normal_vector(P.n_coef, 41))
+    s = dev(P, synth.normal_vector(P.n_slopes, 42))
+    for fn, arg, n in ((P.apply_A, c, P.n_slopes), (P.apply_At, s, P.n_coef), (P.apply_M, c, P.n_coef),
+                       (P.dwt_forward, c, P.n_coef), (P.dwt_inverse, c, P.n_coef), (P.fit_dm, c, P.n_act)):
+        out = torch.full((n,), float("nan"), dtype=P.dtype, device=P.device)
+        fn(arg, out=out)
+        assert torch.isfinite(out).all().item(), fn.__name__
+
+
+def test_bitwise_deterministic():
+    P = plan("c1_elt_mcao", "fp32")
+    O = oracle("c1_elt_mcao")
+    s = dev(P, _slopes(O, synth.load_config("c1_elt_mcao"), 0))
+    outs = []
+    for _ in range(2):
+        c = P.zeros(P.n_coef)
+        P.pcg_solve(s, c, 4, warm=False)
+        outs.append(host(c))
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_state_roundtrip_split_chain():
+    """A warm chain split after frame 2 and resumed from saved state is bitwise identical."""
+    P = plan("t1_mixed", "fp32")
+    O = oracle("t1_mixed")
+    cfg = synth.load_config("t1_mixed")
+    S = [dev(P, _slopes(O, cfg, f)) for f in range(4)]
+    c = P.zeros(P.n_coef)
+    saved = None
+    for f in range(4):
+        P.pcg_solve(S[f], c, 6, warm=f > 0)
+        if f == 1:
+            saved = (c.clone(),) + P.state_get()
+    full = host(c)
+    c2 = saved[0].clone()
+    P.pcg_solve(S[0], P.zeros(P.n_coef), 3, warm=False)   # clobber the state
+    P.state_set(saved[1], saved[2])
+    for f in (2, 3):
+        P.pcg_solve(S[f], c2, 6, warm=True)
+    assert np.array_equal(host(c2), full)
+
+
+def test_zero_slopes_and_nonfinite_status():
+    P = plan("t1_mixed", "fp64")
+    c = P.zeros(P.n_coef)
+    res = torch.full((5,), -1.0, dtype=torch.float64, device=P.device)
+    P.pcg_solve(P.zeros(P.n_slopes), c, 5, warm=False, resnorm=res)
+    assert P.last_status() == 0
+    assert torch.count_nonzero(c).item() == 0 and host(res)[0] == 0.0
+    bad = P.zeros(P.n_slopes)
+    bad[3 * 20 + 10] = float("nan")     # an active subaperture of the first sensor
+    P.pcg_solve(bad, c, 3, warm=False)
+    assert P.last_status() == -7
+    assert torch.count_nonzero(c).item() == 0
