@@ -26,6 +26,15 @@ Bufs<T> bufs(const Plan &P) {
     b.node_tiles = reinterpret_cast<const Tile *>(w + P.o_node);
     b.sub_tiles = reinterpret_cast<const Tile *>(w + P.o_sub);
     b.lay_tiles = reinterpret_cast<const Tile *>(w + P.o_laytile);
+    b.fine_tiles = reinterpret_cast<const Tile *>(w + P.o_fine);
+    b.coef_tiles = reinterpret_cast<const Tile *>(w + P.o_coef);
+    b.xtab = reinterpret_cast<const Ent<T> *>(w + P.o_xtab);
+    b.ytab = reinterpret_cast<const Ent<T> *>(w + P.o_ytab);
+    b.xrng = reinterpret_cast<const Range *>(w + P.o_xrng);
+    b.yrng = reinterpret_cast<const Range *>(w + P.o_yrng);
+    b.maxnv = P.maxnv;
+    b.sum_n = P.sum_n;
+    b.kf = P.kf;
     b.jinv = reinterpret_cast<const T *>(w + P.o_jinv);
     b.ad = reinterpret_cast<const T *>(w + P.o_ad);
     b.b_prev = reinterpret_cast<T *>(w + P.o_bprev);
@@ -89,8 +98,7 @@ int apply_M(const Plan &P, const void *c, void *y, void *stream) {
     TRY(o.idwt(static_cast<const T *>(c), o.B.u, false));
     TRY(o.nodes(o.B.u, o.B.v, kModeM));
     TRY(o.pt(o.B.v, o.B.x));
-    TRY(o.fdwt(o.B.x, static_cast<T *>(y)));
-    return o.add_prior(static_cast<T *>(y), static_cast<const T *>(c));
+    return o.fdwt_prior(o.B.x, static_cast<const T *>(c), static_cast<T *>(y));
 }
 
 template <typename T>
@@ -100,15 +108,14 @@ int pcg_solve(const Plan &P, const void *s, void *c, int n_iter, int flags, doub
     // right-hand side b = W P^T Gamma^T C s, then the warm-restart residual update
     TRY(o.nodes(static_cast<const T *>(s), o.B.v, kModeRhs));
     TRY(o.pt(o.B.v, o.B.x));
-    TRY(o.fdwt(o.B.x, o.B.b));
-    TRY(o.residual(cc, flags == FEWHA_COLD));
+    TRY(o.fdwt_rhs(o.B.x, cc, flags == FEWHA_COLD));
     for (int k = 0; k < n_iter; ++k) {
-        // y = M z with z = J^-1 r folded into the inverse transform's loads
+        // y = M z with z = J^-1 r folded into the inverse transform's loads; alpha D z and the
+        // reductions (r, z), (y, z) in the forward transform's epilogue
         TRY(o.idwt(o.B.r, o.B.u, true));
         TRY(o.nodes(o.B.u, o.B.v, kModeM));
         TRY(o.pt(o.B.v, o.B.x));
-        TRY(o.fdwt(o.B.x, o.B.y));
-        TRY(o.dots(k, resnorm));
+        TRY(o.fdwt_pcg(o.B.x, k, resnorm));
         TRY(o.update(cc, k));
     }
     return FEWHA_OK;
@@ -133,11 +140,14 @@ int bind_tables(Plan &P, hipStream_t st) {
     HIPTRY(hipMemcpy(w + P.o_node, P.node_tiles.data(), sizeof(Tile) * P.node_tiles.size(), hipMemcpyHostToDevice));
     HIPTRY(hipMemcpy(w + P.o_sub, P.sub_tiles.data(), sizeof(Tile) * P.sub_tiles.size(), hipMemcpyHostToDevice));
     HIPTRY(hipMemcpy(w + P.o_laytile, P.lay_tiles.data(), sizeof(Tile) * P.lay_tiles.size(), hipMemcpyHostToDevice));
+    HIPTRY(hipMemcpy(w + P.o_fine, P.fine_tiles.data(), sizeof(Tile) * P.fine_tiles.size(), hipMemcpyHostToDevice));
+    HIPTRY(hipMemcpy(w + P.o_coef, P.coef_tiles.data(), sizeof(Tile) * P.coef_tiles.size(), hipMemcpyHostToDevice));
     const int nb = P.nl * (P.J + 1);
     std::vector<T> ad(nb);
     for (int k = 0; k < nb; ++k) ad[k] = (T)P.ad[k];
     HIPTRY(hipMemcpy(w + P.o_ad, ad.data(), sizeof(T) * nb, hipMemcpyHostToDevice));
     const long N = (long)P.n_coef;
+    TRY(o.build_tables());
     TRY(o.init_scalars());
     TRY(o.fill(o.B.b_prev, N, 0));
     TRY(o.fill(o.B.r, N, 0));

@@ -14,12 +14,17 @@ constexpr int kMaxLayers = 64;
 constexpr int kMaxWfs = 64;
 constexpr int kMaxDms = 16;
 constexpr int kMaxJ = 12;
-constexpr int kMaxGrid = 4096;
+constexpr int kMaxGrid = 4096;    // sensor subapertures per side
+constexpr int kMaxLayerGrid = 512; // layer nodes per side
 
 // Inverse-DWT output tile edge (nodes); layers smaller than this form a single tile.
 constexpr int kIdwtTile = 32;
 // Node / subaperture / layer-node tile edge of the projection kernels.
 constexpr int kNodeTile = 16;
+// Coefficients per workgroup of the element-wise PCG kernels (4 per lane, 256 lanes).
+constexpr int kCoefTile = 1024;
+// Slots per row of the FP64 partial-sum buffer (one per workgroup of a reduction chain).
+constexpr int kPartialPitch = 4096;
 
 // Per guide star, as the kernels read it.
 struct DevWfs {
@@ -42,7 +47,17 @@ struct DevLayer {
     int n;
     int log2n;
     int dm;          // fitting DM index
+    int r_off;       // offset of this layer's n grid lines in the per-axis range tables
+};
+
+// One node of a sensor grid seen on one layer along one axis: bilinear cell k0 and the
+// weights (1 - t, t) of grid lines k0 and k0 + 1.  Built once per plan on the device by the
+// same arithmetic for every consumer, so P and P^T use identical matrix entries.
+template <typename T>
+struct Ent {
+    int k0;
     int pad;
+    T w0, w1;
 };
 
 // Per (guide star, layer): ray geometry of Sec. 2.1.  Node (i, j) lands at grid coordinates
@@ -67,6 +82,11 @@ struct Tile {
     int a, b, c, d;
 };
 
+// Inclusive range [lo, hi] of sensor node indices (empty when lo > hi).
+struct Range {
+    int lo, hi;
+};
+
 // PCG scalars of Alg. 2 in FP64, kept on the device so no pass needs a host round trip.
 struct Scalars {
     double rho, mu, rho_old, alpha, alpha_old, beta;
@@ -83,7 +103,10 @@ struct Bufs {
     const DevLayer *lay;
     const DevProj *proj;
     const DevDm *dm;
-    const Tile *idwt_tiles, *node_tiles, *sub_tiles, *lay_tiles;
+    const Tile *idwt_tiles, *node_tiles, *sub_tiles, *lay_tiles, *fine_tiles, *coef_tiles;
+    const Ent<T> *xtab, *ytab;  // [nw][nl][maxnv]
+    const Range *xrng, *yrng;   // [nw][sum_n]: sensor nodes touching each layer grid line
+    int maxnv, sum_n, kf;       // table pitch, total grid lines, levels done by the tiled forward DWT
     const T *jinv;   // [nl][J+1][4] inverse preconditioner per band
     const T *ad;     // [nl][J+1] alpha D per level
     T *b_prev, *r, *p, *q, *y, *u, *x, *v, *tmpA, *tmpB, *b, *probe_c, *probe_s;
@@ -104,12 +127,17 @@ struct Plan {
     std::vector<DevLayer> dlay;
     std::vector<DevProj> dproj;
     std::vector<DevDm> ddm;
-    std::vector<Tile> idwt_tiles, node_tiles, sub_tiles, lay_tiles;
+    std::vector<Tile> idwt_tiles, node_tiles, sub_tiles, lay_tiles, fine_tiles, coef_tiles;
+    int maxnv = 0, sum_n = 0;
+    int kf = 1;        // forward-DWT levels done by the tiled kernel; the rest per layer in one workgroup
+    int tq = 8;        // level-kf quads per tile edge of the tiled forward DWT
+    size_t coarse_lds = 0;
     std::vector<double> ad;     // alpha D per (layer, level)
     std::vector<double> jtab;   // alpha D + tau per (layer, level, orientation), after bind
 
     // workspace layout (byte offsets)
     size_t o_wfs = 0, o_lay = 0, o_proj = 0, o_dm = 0, o_idwt = 0, o_node = 0, o_sub = 0, o_laytile = 0;
+    size_t o_fine = 0, o_coef = 0, o_xtab = 0, o_ytab = 0, o_xrng = 0, o_yrng = 0;
     size_t o_jinv = 0, o_ad = 0, o_bprev = 0, o_r = 0, o_p = 0, o_q = 0, o_y = 0, o_u = 0, o_x = 0, o_v = 0;
     size_t o_tmpA = 0, o_tmpB = 0, o_b = 0, o_probe_c = 0, o_probe_s = 0, o_partials = 0, o_scalars = 0;
     size_t ws_bytes = 0;

@@ -5,21 +5,23 @@
 // atomics except the last-block-done counter of the reductions, and results are bitwise
 // reproducible run to run.
 //
-//   k_idwt       W^T (= W^-1) of every layer, all J levels in one launch: each workgroup owns a
-//                square output tile and rebuilds, level by level from the coarsest, only the
-//                cone of approximation coefficients that tile depends on (LDS resident);
-//                optionally scales coefficients by the Jacobi preconditioner on load (z = J^-1 r).
-//   k_nodes      per WFS node tile: P (bilinear ray gather from all layers, LGS cone), Gamma,
-//                C_eta^-1 and Gamma^T fused through LDS (the Kernel-2 stage of the paper), or
-//                Gamma^T C s / Gamma^T mask s for right-hand sides and adjoints.
-//   k_slopes     mask Gamma P u on subaperture tiles (forward operator A).
-//   k_pt         P^T as a gather per layer node: recomputes, with the same code as the forward,
-//                the cell and weights of every candidate WFS node and keeps the ones that touch
-//                this node, so P^T is the exact transpose of the implemented P without atomics.
-//   k_fdwt_level one level of the forward periodic db3 transform for all layers.
-//   k_dots       alpha D z epilogue of M z plus the two PCG reductions (r, z), (Mz, z) in FP64;
-//                the last block to finish forms the Alg. 2 scalars on the device.
-//   k_update     fused p, q, c, r update of Alg. 2.
+//   k_idwt         W^T (= W^-1) of every layer, all J levels in one launch: each workgroup owns a
+//                  square output tile and rebuilds, level by level from the coarsest, only the
+//                  cone of approximation coefficients that tile depends on (LDS resident);
+//                  optionally scales coefficients by the Jacobi preconditioner on load (z = J^-1 r).
+//   k_nodes        per WFS node tile: P (bilinear ray gather from all layers through per-axis
+//                  cell tables, LGS cone included), Gamma, C_eta^-1 and Gamma^T fused through LDS
+//                  (the paper's Kernel-2 stage), or Gamma^T C s / Gamma^T mask s.
+//   k_slopes       mask Gamma P u on subaperture tiles (forward operator A).
+//   k_pt           P^T as a gather per layer node over the contiguous ranges of sensor nodes whose
+//                  cells touch it, with the very table entries the forward uses: the exact
+//                  transpose of P without atomics.
+//   k_fdwt_fine    the first kf levels of the forward transform W for every layer, on tiles of
+//                  level-kf quads with their halo staged in LDS; fused epilogues (alpha D z and the
+//                  PCG dot products, or the right-hand side's warm-restart residual update).
+//   k_fdwt_coarse  the remaining levels, one workgroup per layer, LDS resident; same epilogues; its
+//                  last workgroup forms the Alg. 2 scalars on the device.
+//   k_update       fused p, q, c, r update of Alg. 2.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -33,7 +35,7 @@ namespace {
 constexpr int kBlock = 256;
 
 // ---------------------------------------------------------------------------------------------
-// Geometry helpers shared by the forward projection and its transpose (identical arithmetic).
+// Geometry helpers
 // ---------------------------------------------------------------------------------------------
 struct Cell {
     int k0;      // lower grid index
@@ -46,7 +48,7 @@ __device__ __forceinline__ Cell cell_of(double u, int n) {
     return {k, u - (double)k};
 }
 
-// Grid coordinate on layer l of node index j of WFS g along one axis (h = theta h_l of that axis).
+// Grid coordinate on layer L of node index j of a sensor along one axis (h = theta h_l there).
 __device__ __forceinline__ double ray_coord(const DevProj &pr, const DevWfs &W, const DevLayer &L, int j, double h) {
     double X = pr.sig * (W.x0 + (double)j * W.d) + h;
     return X / L.spacing + L.half;
@@ -58,19 +60,17 @@ __device__ __forceinline__ bool subap_active(const DevWfs &W, int i, int j) {
     return r2 <= W.r_out2 && r2 >= W.r_in2;
 }
 
-// phi_g(i, j) = sum_l bilinear(u_l at the ray point)  (P of Sec. 2.1)
+// phi_g(i, j) = sum_l bilinear(u_l at the ray point)  (P of Sec. 2.1), via the cell tables.
 template <typename T>
-__device__ __forceinline__ T project_node(const T *__restrict__ u, const DevWfs &W, const DevProj *__restrict__ proj,
-                                          const DevLayer *__restrict__ lays, int nl, int i, int j) {
+__device__ __forceinline__ T project_node(const T *__restrict__ u, const Bufs<T> &B, int g, int nl, int i, int j) {
     T acc = 0;
+    const Ent<T> *xt = B.xtab + (long)g * nl * B.maxnv;
+    const Ent<T> *yt = B.ytab + (long)g * nl * B.maxnv;
     for (int l = 0; l < nl; ++l) {
-        const DevProj pr = proj[l];
-        const DevLayer L = lays[l];
-        Cell cx = cell_of(ray_coord(pr, W, L, j, pr.hx), L.n);
-        Cell cy = cell_of(ray_coord(pr, W, L, i, pr.hy), L.n);
-        T wx1 = (T)cx.t, wx0 = (T)(1.0 - cx.t), wy1 = (T)cy.t, wy0 = (T)(1.0 - cy.t);
-        const T *U = u + L.c_off + (long)cy.k0 * L.n + cx.k0;
-        acc += (wy0 * wx0) * U[0] + (wy0 * wx1) * U[1] + (wy1 * wx0) * U[L.n] + (wy1 * wx1) * U[L.n + 1];
+        const Ent<T> ex = xt[l * B.maxnv + j], ey = yt[l * B.maxnv + i];
+        const int n = B.lay[l].n;
+        const T *U = u + B.lay[l].c_off + (long)ey.k0 * n + ex.k0;
+        acc += (ey.w0 * ex.w0) * U[0] + (ey.w0 * ex.w1) * U[1] + (ey.w1 * ex.w0) * U[n] + (ey.w1 * ex.w1) * U[n + 1];
     }
     return acc;
 }
@@ -96,13 +96,15 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
     return t;
 }
 
-// Publish this block's partials; return true in the one block that finishes last (all
-// partials are then visible to it).  The counter returns to zero for the next use.
-__device__ __forceinline__ bool publish_last(double *partials, int nparts, const double *vals, unsigned *counter) {
+// Publish this block's partials at slot `slot` of each of `nrows` rows (row pitch `pitch`);
+// return true in the one block of the grid that finishes last, when every earlier write of
+// this and of previous kernels on the stream is visible.  The counter returns to zero.
+__device__ __forceinline__ bool publish_last(double *partials, int pitch, int nrows, int slot, const double *vals,
+                                             unsigned *counter) {
     __shared__ bool last;
     if (threadIdx.x == 0) {
-        for (int k = 0; k < nparts; ++k)
-            __hip_atomic_store(partials + (size_t)k * gridDim.x + blockIdx.x, vals[k], __ATOMIC_RELAXED,
+        for (int k = 0; k < nrows; ++k)
+            __hip_atomic_store(partials + (size_t)k * pitch + slot, vals[k], __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         __threadfence();
         unsigned prev = atomicAdd(counter, 1u);
@@ -116,44 +118,64 @@ __device__ __forceinline__ bool publish_last(double *partials, int nparts, const
     return last;
 }
 
-// Sum one partial row in fixed (block index) order, cooperatively by the last block.
-__device__ __forceinline__ double gather_partials(const double *partials, int row, double *sh) {
+// Sum slots [0, count) of one partial row in fixed order, cooperatively by one block.
+__device__ __forceinline__ double gather_partials(const double *partials, int pitch, int row, int count, double *sh) {
     double v = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x)
-        v += __hip_atomic_load(partials + (size_t)row * gridDim.x + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int b = threadIdx.x; b < count; b += blockDim.x)
+        v += __hip_atomic_load(partials + (size_t)row * pitch + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return block_sum(v, sh);
 }
 
-// Layer, level and orientation of coefficient index i.
-struct Band {
-    int l, s, o;
-    long off;
-};
+// Alg. 2 scalars from the reduced (rho, mu) of pass k (thread 0 of the last block only).
+__device__ void pcg_scalars(Scalars *sc, double R, double Mu, int k, double *resnorm) {
+    sc->rho = R;
+    sc->mu = Mu;
+    if (sc->stopped) return;
+    if (!isfinite(R) || !isfinite(Mu)) {
+        sc->status = FEWHA_ERR_NONFINITE;
+        sc->stopped = 1;
+        return;
+    }
+    if (resnorm) resnorm[k] = sqrt(R);
+    if (R == 0.0) {
+        sc->stopped = 1;
+        return;
+    }
+    double beta = 0.0, den = Mu;
+    if (k > 0) {
+        beta = R / sc->rho_old;
+        den = Mu - R * beta / sc->alpha_old;
+    }
+    if (!(den > 0.0)) {
+        sc->status = FEWHA_ERR_BREAKDOWN;
+        sc->stopped = 1;
+        return;
+    }
+    const double alpha = R / den;
+    sc->alpha = alpha;
+    sc->beta = beta;
+    sc->rho_old = R;
+    sc->alpha_old = alpha;
+}
 
-__device__ __forceinline__ Band band_of(long i, const DevLayer *__restrict__ lays, int nl, int J) {
-    int lo = 0, hi = nl - 1;
-    while (lo < hi) {  // last layer with c_off <= i
-        int mid = (lo + hi + 1) >> 1;
-        if (lays[mid].c_off <= i) lo = mid;
-        else hi = mid - 1;
-    }
-    const DevLayer L = lays[lo];
-    long loc = i - L.c_off;
-    int row = (int)(loc >> L.log2n), col = (int)(loc & (L.n - 1));
-    int v = row > col ? row : col;
-    Band b;
-    b.l = lo;
-    b.off = L.c_off;
-    if (v < (L.n >> J)) {
-        b.s = J;
-        b.o = 0;
+__device__ __forceinline__ void reset_scalars(Scalars *sc) {
+    sc->rho = sc->mu = sc->rho_old = sc->alpha = sc->alpha_old = sc->beta = 0.0;
+    sc->stopped = 0;
+    sc->status = FEWHA_OK;
+}
+
+// Level and orientation of Mallat position (row, col) of an n x n pyramid with J levels.
+__device__ __forceinline__ void band_at(int row, int col, int n, int log2n, int J, int &s, int &o) {
+    const int v = row > col ? row : col;
+    if (v < (n >> J)) {
+        s = J;
+        o = 0;
     } else {
-        int lv = 31 - __clz(v);
-        int m = 1 << lv;
-        b.s = L.log2n - lv;
-        b.o = (row < m) ? 1 : ((col < m) ? 2 : 3);
+        const int lv = 31 - __clz(v);
+        const int m = 1 << lv;
+        s = log2n - lv;
+        o = (row < m) ? 1 : ((col < m) ? 2 : 3);
     }
-    return b;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -277,11 +299,10 @@ __global__ __launch_bounds__(kBlock) void k_nodes(const T *__restrict__ in, T *_
     const int ns = W.n_sub, nv = W.nv, i0 = t.b, j0 = t.c;
 
     if constexpr (MODE == kModeM) {
-        const DevProj *proj = B.proj + (long)t.a * nl;
         for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) {
             int a = idx / NP, b = idx - a * NP, i = i0 - 1 + a, j = j0 - 1 + b;
             T val = 0;
-            if (i >= 0 && i <= ns && j >= 0 && j <= ns) val = project_node(in, W, proj, B.lay, nl, i, j);
+            if (i >= 0 && i <= ns && j >= 0 && j <= ns) val = project_node(in, B, t.a, nl, i, j);
             sPhi[idx] = val;
         }
         __syncthreads();
@@ -323,11 +344,10 @@ __global__ __launch_bounds__(kBlock) void k_slopes(const T *__restrict__ u, T *_
     const Tile t = B.sub_tiles[blockIdx.x];
     const DevWfs W = B.wfs[t.a];
     const int ns = W.n_sub, i0 = t.b, j0 = t.c;
-    const DevProj *proj = B.proj + (long)t.a * nl;
     for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) {
         int a = idx / NP, b = idx - a * NP, i = i0 + a, j = j0 + b;
         T val = 0;
-        if (i <= ns && j <= ns) val = project_node(u, W, proj, B.lay, nl, i, j);
+        if (i <= ns && j <= ns) val = project_node(u, B, t.a, nl, i, j);
         sPhi[idx] = val;
     }
     __syncthreads();
@@ -347,214 +367,256 @@ __global__ __launch_bounds__(kBlock) void k_slopes(const T *__restrict__ u, T *_
 }
 
 // ---------------------------------------------------------------------------------------------
-// P^T as a gather over layer-node tiles.
+// P^T as a gather over layer-node tiles, through the transpose ranges of the cell tables.
 // ---------------------------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pt(const T *__restrict__ v, T *__restrict__ x, Bufs<T> B, int nl,
                                                int nw) {
-    constexpr int NT = kNodeTile, MAXC = 24;
+    constexpr int NT = kNodeTile;
     const Tile t = B.lay_tiles[blockIdx.x];
     const DevLayer L = B.lay[t.a];
     const int k = t.b + (int)(threadIdx.x / NT), q = t.c + (int)(threadIdx.x % NT);
     if (k >= L.n || q >= L.n) return;
     T acc = 0;
     for (int g = 0; g < nw; ++g) {
+        const Range rx = B.xrng[(long)g * B.sum_n + L.r_off + q];
+        const Range ry = B.yrng[(long)g * B.sum_n + L.r_off + k];
+        if (rx.lo > rx.hi || ry.lo > ry.hi) continue;
+        const Ent<T> *xt = B.xtab + ((long)g * nl + t.a) * B.maxnv;
+        const Ent<T> *yt = B.ytab + ((long)g * nl + t.a) * B.maxnv;
         const DevWfs W = B.wfs[g];
-        const DevProj pr = B.proj[(long)g * nl + t.a];
-        const int ns = W.n_sub;
-        // candidate nodes: those whose affine coordinate is within one cell (+1 node of slack)
-        int jlo = (int)floor((q - 1 - pr.bx) / pr.slope) - 1, jhi = (int)ceil((q + 1 - pr.bx) / pr.slope) + 1;
-        int ilo = (int)floor((k - 1 - pr.by) / pr.slope) - 1, ihi = (int)ceil((k + 1 - pr.by) / pr.slope) + 1;
-        jlo = jlo < 0 ? 0 : jlo;
-        ilo = ilo < 0 ? 0 : ilo;
-        jhi = jhi > ns ? ns : jhi;
-        ihi = ihi > ns ? ns : ihi;
-        if (jlo > jhi || ilo > ihi) continue;
-        int jn[MAXC];
-        T jw[MAXC];
-        int cnt = 0;
-        for (int j = jlo; j <= jhi && cnt < MAXC; ++j) {
-            Cell cx = cell_of(ray_coord(pr, W, L, j, pr.hx), L.n);
-            if (cx.k0 == q) {
-                jn[cnt] = j;
-                jw[cnt++] = (T)(1.0 - cx.t);
-            } else if (cx.k0 + 1 == q) {
-                jn[cnt] = j;
-                jw[cnt++] = (T)cx.t;
-            }
-        }
-        if (cnt == 0) continue;
         const T *vg = v + W.v_off;
-        for (int i = ilo; i <= ihi; ++i) {
-            Cell cy = cell_of(ray_coord(pr, W, L, i, pr.hy), L.n);
-            T wy;
-            if (cy.k0 == k) wy = (T)(1.0 - cy.t);
-            else if (cy.k0 + 1 == k) wy = (T)cy.t;
-            else continue;
-            for (int c = 0; c < cnt; ++c) acc += (wy * jw[c]) * vg[(long)i * W.nv + jn[c]];
+        for (int i = ry.lo; i <= ry.hi; ++i) {
+            const Ent<T> ey = yt[i];
+            const T wy = (ey.k0 == k) ? ey.w0 : ey.w1;
+            const T *row = vg + (long)i * W.nv;
+            for (int j = rx.lo; j <= rx.hi; ++j) {
+                const Ent<T> ex = xt[j];
+                const T wx = (ex.k0 == q) ? ex.w0 : ex.w1;
+                acc += (wy * wx) * row[j];
+            }
         }
     }
     x[L.c_off + (long)k * L.n + q] = acc;
 }
 
 // ---------------------------------------------------------------------------------------------
-// W: one level of the forward transform for every layer (thread per output quad).
+// Forward transform W with fused epilogues.
 // ---------------------------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fdwt_level(const T *__restrict__ src, T *__restrict__ dst,
-                                                       T *__restrict__ ll_out, const DevLayer *__restrict__ lays,
-                                                       int nl, int lev, int J, long nquads, Taps<T> tp) {
-    long qi = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (qi >= nquads) return;
-    const int sh = 2 * (lev + 1);
-    int lo = 0, hi = nl - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if ((lays[mid].c_off >> sh) <= qi) lo = mid;
-        else hi = mid - 1;
-    }
-    const DevLayer L = lays[lo];
-    const int n = L.n, m = n >> lev, h2 = m >> 1, msk = m - 1;
-    const long loc = qi - (L.c_off >> sh);
-    const int kr = (int)(loc / h2), kc = (int)(loc - (long)kr * h2);
-    const T *S;
-    int pitch;
-    if (lev == 0) {
-        S = src + L.c_off;
-        pitch = n;
-    } else {
-        S = src + (L.c_off >> (2 * lev));
-        pitch = m;
-    }
-    int cols[6];
-#pragma unroll
-    for (int b = 0; b < 6; ++b) cols[b] = (2 * kc + b) & msk;
-    T ll = 0, lh = 0, hl = 0, hh = 0;
-#pragma unroll
-    for (int a = 0; a < 6; ++a) {
-        const T *row = S + (long)((2 * kr + a) & msk) * pitch;
-        T ax = 0, dx = 0;
-#pragma unroll
-        for (int b = 0; b < 6; ++b) {
-            const T xv = row[cols[b]];
-            ax += tp.h[b] * xv;
-            dx += tp.g[b] * xv;
-        }
-        ll += tp.h[a] * ax;
-        lh += tp.g[a] * ax;
-        hl += tp.h[a] * dx;
-        hh += tp.g[a] * dx;
-    }
-    T *D = dst + L.c_off;
-    D[(long)kr * n + h2 + kc] = hl;
-    D[(long)(h2 + kr) * n + kc] = lh;
-    D[(long)(h2 + kr) * n + h2 + kc] = hh;
-    if (lev == J - 1) D[(long)kr * n + kc] = ll;
-    else ll_out[(L.c_off >> sh) + (long)kr * h2 + kc] = ll;
-}
+struct EpiArgs {
+    const void *cin;   // kEpiPrior: c of y = W x + alpha D c
+    void *out;         // destination coefficient vector (y, or b for kEpiRhs)
+    void *c;           // kEpiRhs + cold: caller's c, zeroed
+    int cold;          // kEpiRhs
+    int k;             // kEpiPcg: pass index
+    double *resnorm;   // kEpiPcg
+    int nfine;         // partial slots used by the tiled kernel
+};
 
-// ---------------------------------------------------------------------------------------------
-// PCG pieces (Alg. 2)
-// ---------------------------------------------------------------------------------------------
-
-// y += alpha D z with z = J^-1 r; partial (r, z), (y, z); the last block forms the scalars.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_dots(T *__restrict__ y, const T *__restrict__ r, Bufs<T> B, int nl, int J,
-                                                 long N, int k, double *resnorm) {
-    __shared__ double sh[kBlock / 64];
-    double rho = 0.0, mu = 0.0;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x) {
-        Band b = band_of(i, B.lay, nl, J);
-        const T z = r[i] * B.jinv[(b.l * (J + 1) + b.s) * 4 + b.o];
-        const T yi = y[i] + B.ad[b.l * (J + 1) + b.s] * z;
-        y[i] = yi;
-        rho += (double)r[i] * (double)z;
+// Deliver one coefficient of W x to its destination; accumulate the PCG dot partials.
+template <typename T, int EPI>
+__device__ __forceinline__ void epilogue(const Bufs<T> &B, const EpiArgs &E, long i, int l, int s, int o, int J, T w,
+                                         double &rho, double &mu) {
+    T *out = static_cast<T *>(E.out);
+    if constexpr (EPI == kEpiPlain) {
+        out[i] = w;
+    } else if constexpr (EPI == kEpiPrior) {
+        out[i] = w + B.ad[l * (J + 1) + s] * static_cast<const T *>(E.cin)[i];
+    } else if constexpr (EPI == kEpiPcg) {
+        const T ri = B.r[i];
+        const T z = ri * B.jinv[(l * (J + 1) + s) * 4 + o];
+        const T yi = w + B.ad[l * (J + 1) + s] * z;
+        out[i] = yi;
+        rho += (double)ri * (double)z;
         mu += (double)yi * (double)z;
+    } else {  // kEpiRhs: b = W x; r = (b - b_prev) + r (cold: r = b, c = 0); b_prev = b
+        out[i] = w;
+        if (E.cold) {
+            B.r[i] = w;
+            static_cast<T *>(E.c)[i] = 0;
+        } else {
+            B.r[i] = (w - B.b_prev[i]) + B.r[i];
+        }
+        B.b_prev[i] = w;
     }
-    double vals[2];
-    vals[0] = block_sum(rho, sh);
-    vals[1] = block_sum(mu, sh);
-    if (!publish_last(B.partials, 2, vals, &B.sc->counter)) return;
-    const double R = gather_partials(B.partials, 0, sh);
-    const double Mu = gather_partials(B.partials, 1, sh);
-    if (threadIdx.x != 0) return;
-    Scalars *sc = B.sc;
-    sc->rho = R;
-    sc->mu = Mu;
-    if (sc->stopped) return;
-    if (!isfinite(R) || !isfinite(Mu)) {
-        sc->status = FEWHA_ERR_NONFINITE;
-        sc->stopped = 1;
-        return;
-    }
-    if (resnorm) resnorm[k] = sqrt(R);
-    if (R == 0.0) {
-        sc->stopped = 1;
-        return;
-    }
-    double beta = 0.0, den = Mu;
-    if (k > 0) {
-        beta = R / sc->rho_old;
-        den = Mu - R * beta / sc->alpha_old;
-    }
-    if (!(den > 0.0)) {
-        sc->status = FEWHA_ERR_BREAKDOWN;
-        sc->stopped = 1;
-        return;
-    }
-    const double alpha = R / den;
-    sc->alpha = alpha;
-    sc->beta = beta;
-    sc->rho_old = R;
-    sc->alpha_old = alpha;
 }
 
+// Region geometry of the tiled forward DWT: a tile of TQ x TQ level-KF approximation
+// coefficients needs LL_{s} on a run of len(s) = TQ 2^(KF-s) + 4 (2^(KF-s) - 1) indices.
+template <int KF, int TQ>
+struct FineGeom {
+    static constexpr int len(int s) { return TQ * (1 << (KF - s)) + 4 * ((1 << (KF - s)) - 1); }
+};
+
+template <typename T, int KF, int TQ, int EPI>
+__global__ __launch_bounds__(kBlock) void k_fdwt_fine(const T *__restrict__ x, T *__restrict__ ll_out, Bufs<T> B,
+                                                      int J, EpiArgs E, Taps<T> tp, int last) {
+    using G = FineGeom<KF, TQ>;
+    constexpr int L0 = G::len(0), L1 = G::len(1);
+    __shared__ T sA[L0 * L0];
+    __shared__ T sB[(KF >= 2 ? L1 * L1 : 1)];
+    __shared__ double sh[kBlock / 64];
+    if constexpr (EPI == kEpiRhs) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) reset_scalars(B.sc);
+    }
+
+    const Tile t = B.fine_tiles[blockIdx.x];
+    const DevLayer L = B.lay[t.a];
+    const int n = L.n, tq = t.d, shift = KF;
+    // run lengths and origins for this tile (tq <= TQ; small layers use smaller tiles)
+    int len[KF + 1];
+#pragma unroll
+    for (int s = 0; s <= KF; ++s) len[s] = tq * (1 << (KF - s)) + 4 * ((1 << (KF - s)) - 1);
+    const int oy = t.b << shift, ox = t.c << shift, nmask = n - 1;
+
+    // stage the input region (periodic wrap) in LDS
+    for (int idx = threadIdx.x; idx < len[0] * len[0]; idx += blockDim.x) {
+        const int r = idx / len[0], q = idx - r * len[0];
+        sA[r * L0 + q] = x[L.c_off + (long)((oy + r) & nmask) * n + ((ox + q) & nmask)];
+    }
+    __syncthreads();
+
+    double rho = 0.0, mu = 0.0;
+#pragma unroll
+    for (int s = 1; s <= KF; ++s) {
+        const T *src = (s & 1) ? sA : sB;
+        T *dst = (s & 1) ? sB : sA;
+        const int sp = (s & 1) ? L0 : L1, dp = (s & 1) ? L1 : L0;
+        const int ln = len[s], own = tq << (KF - s), m = n >> s;  // output run, owned run, band size
+        const int by = t.b << (KF - s), bx = t.c << (KF - s);      // owned origin at level s
+        for (int idx = threadIdx.x; idx < ln * ln; idx += blockDim.x) {
+            const int r = idx / ln, q = idx - r * ln;
+            T ll = 0, lh = 0, hl = 0, hh = 0;
+#pragma unroll
+            for (int a = 0; a < 6; ++a) {
+                const T *row = src + (2 * r + a) * sp + 2 * q;
+                T ax = 0, dx = 0;
+#pragma unroll
+                for (int b = 0; b < 6; ++b) {
+                    ax += tp.h[b] * row[b];
+                    dx += tp.g[b] * row[b];
+                }
+                ll += tp.h[a] * ax;
+                lh += tp.g[a] * ax;
+                hl += tp.h[a] * dx;
+                hh += tp.g[a] * dx;
+            }
+            if (s < KF) dst[r * dp + q] = ll;
+            if (r < own && q < own) {
+                const int gr = by + r, gc = bx + q;
+                const long base = L.c_off;
+                epilogue<T, EPI>(B, E, base + (long)gr * n + m + gc, t.a, s, 1, J, hl, rho, mu);
+                epilogue<T, EPI>(B, E, base + (long)(m + gr) * n + gc, t.a, s, 2, J, lh, rho, mu);
+                epilogue<T, EPI>(B, E, base + (long)(m + gr) * n + m + gc, t.a, s, 3, J, hh, rho, mu);
+                if (s == KF) {
+                    if (KF == J) epilogue<T, EPI>(B, E, base + (long)gr * n + gc, t.a, s, 0, J, ll, rho, mu);
+                    else ll_out[(L.c_off >> (2 * KF)) + (long)gr * m + gc] = ll;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if constexpr (EPI == kEpiPcg) {
+        double vals[2];
+        vals[0] = block_sum(rho, sh);
+        vals[1] = block_sum(mu, sh);
+        const int pitch = kPartialPitch;
+        const bool am_last = publish_last(B.partials, pitch, 2, blockIdx.x, vals, &B.sc->counter);
+        if (!last || !am_last) return;
+        const double R = gather_partials(B.partials, pitch, 0, gridDim.x, sh);
+        const double Mu = gather_partials(B.partials, pitch, 1, gridDim.x, sh);
+        if (threadIdx.x == 0) pcg_scalars(B.sc, R, Mu, E.k, E.resnorm);
+    }
+}
+
+// Levels KF+1..J of one layer per workgroup; the level-KF approximation comes from ll_in.
+template <typename T, int EPI>
+__global__ __launch_bounds__(kBlock) void k_fdwt_coarse(const T *__restrict__ ll_in, Bufs<T> B, int J, int KF,
+                                                        EpiArgs E, Taps<T> tp) {
+    extern __shared__ char smem_raw[];
+    T *sA = reinterpret_cast<T *>(smem_raw);
+    __shared__ double sh[kBlock / 64];
+    const int l = blockIdx.x;
+    const DevLayer L = B.lay[l];
+    const int n = L.n, m0 = n >> KF;
+    T *sB = sA + m0 * m0;
+    for (int idx = threadIdx.x; idx < m0 * m0; idx += blockDim.x) sA[idx] = ll_in[(L.c_off >> (2 * KF)) + idx];
+    __syncthreads();
+    double rho = 0.0, mu = 0.0;
+    T *src = sA, *dst = sB;
+    for (int s = KF + 1; s <= J; ++s) {
+        const int mi = n >> (s - 1), h = mi >> 1, msk = mi - 1;
+        for (int idx = threadIdx.x; idx < h * h; idx += blockDim.x) {
+            const int r = idx / h, q = idx - r * h;
+            int cols[6];
+#pragma unroll
+            for (int b = 0; b < 6; ++b) cols[b] = (2 * q + b) & msk;
+            T ll = 0, lh = 0, hl = 0, hh = 0;
+#pragma unroll
+            for (int a = 0; a < 6; ++a) {
+                const T *row = src + ((2 * r + a) & msk) * mi;
+                T ax = 0, dx = 0;
+#pragma unroll
+                for (int b = 0; b < 6; ++b) {
+                    const T xv = row[cols[b]];
+                    ax += tp.h[b] * xv;
+                    dx += tp.g[b] * xv;
+                }
+                ll += tp.h[a] * ax;
+                lh += tp.g[a] * ax;
+                hl += tp.h[a] * dx;
+                hh += tp.g[a] * dx;
+            }
+            const long base = L.c_off;
+            epilogue<T, EPI>(B, E, base + (long)r * n + h + q, l, s, 1, J, hl, rho, mu);
+            epilogue<T, EPI>(B, E, base + (long)(h + r) * n + q, l, s, 2, J, lh, rho, mu);
+            epilogue<T, EPI>(B, E, base + (long)(h + r) * n + h + q, l, s, 3, J, hh, rho, mu);
+            if (s == J) epilogue<T, EPI>(B, E, base + (long)r * n + q, l, s, 0, J, ll, rho, mu);
+            else dst[r * h + q] = ll;
+        }
+        __syncthreads();
+        // the next level reads what was just written; the old input becomes the next output
+        T *tmp = src;
+        src = dst;
+        dst = tmp;
+    }
+    if constexpr (EPI == kEpiPcg) {
+        double vals[2];
+        vals[0] = block_sum(rho, sh);
+        vals[1] = block_sum(mu, sh);
+        const int pitch = kPartialPitch;
+        if (!publish_last(B.partials, pitch, 2, E.nfine + blockIdx.x, vals, &B.sc->counter)) return;
+        const double R = gather_partials(B.partials, pitch, 0, E.nfine + gridDim.x, sh);
+        const double Mu = gather_partials(B.partials, pitch, 1, E.nfine + gridDim.x, sh);
+        if (threadIdx.x == 0) pcg_scalars(B.sc, R, Mu, E.k, E.resnorm);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Element-wise PCG update on coefficient tiles (layer known per tile, band from the index).
+// ---------------------------------------------------------------------------------------------
 // p = z + beta p; q = y + beta q; c += alpha p; r -= alpha q   (first pass: p = z, q = y)
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_update(T *__restrict__ c, Bufs<T> B, int nl, int J, long N, int k) {
+__global__ __launch_bounds__(kBlock) void k_update(T *__restrict__ c, Bufs<T> B, int J, int k) {
     if (B.sc->stopped) return;
     const T alpha = (T)B.sc->alpha, beta = (T)B.sc->beta;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x) {
-        Band b = band_of(i, B.lay, nl, J);
+    const Tile t = B.coef_tiles[blockIdx.x];
+    const DevLayer L = B.lay[t.a];
+#pragma unroll
+    for (int e = 0; e < kCoefTile / kBlock; ++e) {
+        const int loc = t.b + e * kBlock + (int)threadIdx.x;
+        if (loc >= t.b + t.c) break;
+        const long i = L.c_off + loc;
+        int s, o;
+        band_at(loc >> L.log2n, loc & (L.n - 1), L.n, L.log2n, J, s, o);
         const T ri = B.r[i];
-        const T z = ri * B.jinv[(b.l * (J + 1) + b.s) * 4 + b.o];
+        const T z = ri * B.jinv[(t.a * (J + 1) + s) * 4 + o];
         const T p = (k == 0) ? z : z + beta * B.p[i];
         const T q = (k == 0) ? B.y[i] : B.y[i] + beta * B.q[i];
         B.p[i] = p;
         B.q[i] = q;
         c[i] += alpha * p;
         B.r[i] = ri - alpha * q;
-    }
-}
-
-// y += alpha D c  (tail of apply_M)
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_add_prior(T *__restrict__ y, const T *__restrict__ c, Bufs<T> B, int nl,
-                                                      int J, long N) {
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x) {
-        Band b = band_of(i, B.lay, nl, J);
-        y[i] += B.ad[b.l * (J + 1) + b.s] * c[i];
-    }
-}
-
-// Residual update of Alg. 1 and reset of the PCG scalars.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_residual(T *__restrict__ c, Bufs<T> B, long N, int cold) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        Scalars *sc = B.sc;
-        sc->rho = sc->mu = sc->rho_old = sc->alpha = sc->alpha_old = sc->beta = 0.0;
-        sc->stopped = 0;
-        sc->status = FEWHA_OK;
-    }
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x) {
-        const T b = B.b[i];
-        if (cold) {
-            c[i] = 0;
-            B.r[i] = b;
-        } else {
-            B.r[i] = (b - B.b_prev[i]) + B.r[i];
-        }
-        B.b_prev[i] = b;
     }
 }
 
@@ -574,8 +636,8 @@ __global__ __launch_bounds__(kBlock) void k_wnorm(const T *__restrict__ s, Bufs<
         }
     }
     double v = block_sum(acc, sh);
-    if (!publish_last(B.partials, 1, &v, &B.sc->counter)) return;
-    const double tot = gather_partials(B.partials, 0, sh);
+    if (!publish_last(B.partials, kPartialPitch, 1, blockIdx.x, &v, &B.sc->counter)) return;
+    const double tot = gather_partials(B.partials, kPartialPitch, 0, gridDim.x, sh);
     if (threadIdx.x == 0) B.sc->rho = tot;
 }
 
@@ -604,6 +666,58 @@ __global__ __launch_bounds__(kBlock) void k_fit(const T *__restrict__ u, const T
     a[i] = (T)(1.0 - gain) * prev + (T)gain * acc;
 }
 
+// Cell tables: entry (g, l, j) of each axis from the ray geometry (setup, once per bind).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_build_tabs(Ent<T> *xtab, Ent<T> *ytab, const DevWfs *__restrict__ wfs,
+                                                       const DevProj *__restrict__ proj,
+                                                       const DevLayer *__restrict__ lays, int nw, int nl, int maxnv) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)nw * nl * maxnv) return;
+    const int j = (int)(idx % maxnv), gl = (int)(idx / maxnv), l = gl % nl, g = gl / nl;
+    const DevWfs W = wfs[g];
+    Ent<T> ex{0, 0, (T)0, (T)0}, ey{0, 0, (T)0, (T)0};
+    if (j < W.nv) {
+        const DevProj pr = proj[(long)g * nl + l];
+        const DevLayer L = lays[l];
+        const Cell cx = cell_of(ray_coord(pr, W, L, j, pr.hx), L.n);
+        const Cell cy = cell_of(ray_coord(pr, W, L, j, pr.hy), L.n);
+        ex = Ent<T>{cx.k0, 0, (T)(1.0 - cx.t), (T)cx.t};
+        ey = Ent<T>{cy.k0, 0, (T)(1.0 - cy.t), (T)cy.t};
+    }
+    xtab[idx] = ex;
+    ytab[idx] = ey;
+}
+
+// Transpose ranges: for grid line q of layer l, the sensor nodes j with cell k0_j in {q-1, q}
+// (k0_j is non-decreasing in j, so they are contiguous).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_build_ranges(Range *xrng, Range *yrng, const Ent<T> *__restrict__ xtab,
+                                                         const Ent<T> *__restrict__ ytab,
+                                                         const DevWfs *__restrict__ wfs,
+                                                         const DevLayer *__restrict__ lays, int nw, int nl, int maxnv,
+                                                         int sum_n) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)nw * sum_n) return;
+    const int g = (int)(idx / sum_n), line = (int)(idx % sum_n);
+    int l = 0;
+    while (l + 1 < nl && lays[l + 1].r_off <= line) ++l;
+    const int q = line - lays[l].r_off, nv = wfs[g].nv;
+    for (int axis = 0; axis < 2; ++axis) {
+        const Ent<T> *tab = (axis == 0 ? xtab : ytab) + ((long)g * nl + l) * maxnv;
+        int lo = nv, hi = -1;
+        for (int j = 0; j < nv; ++j) {
+            const int k0 = tab[j].k0;
+            if (k0 == q || k0 + 1 == q) {
+                lo = j < lo ? j : lo;
+                hi = j;
+            }
+        }
+        Range r{lo, hi};
+        if (hi < 0) r = Range{1, 0};
+        (axis == 0 ? xrng : yrng)[idx] = r;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fill(T *__restrict__ x, long n, T val) {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) x[i] = val;
@@ -616,9 +730,7 @@ __global__ __launch_bounds__(kBlock) void k_copy(T *__restrict__ dst, const T *_
 
 __global__ void k_init_scalars(Scalars *sc) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        sc->rho = sc->mu = sc->rho_old = sc->alpha = sc->alpha_old = sc->beta = 0.0;
-        sc->stopped = 0;
-        sc->status = FEWHA_OK;
+        reset_scalars(sc);
         sc->counter = 0u;
     }
 }
@@ -631,6 +743,26 @@ int grid_for(long n) {
 }
 
 int check() { return hipGetLastError() == hipSuccess ? FEWHA_OK : FEWHA_ERR_HIP; }
+
+template <typename T, int EPI>
+int launch_fdwt(const Plan &P, const Bufs<T> &B, hipStream_t st, const T *x, const EpiArgs &E0) {
+    const Taps<T> tp = make_taps<T>();
+    EpiArgs E = E0;
+    const int nfine = (int)P.fine_tiles.size();
+    E.nfine = nfine;
+    const int last = (P.kf == P.J) ? 1 : 0;
+    switch (P.kf) {
+        case 1: k_fdwt_fine<T, 1, 16, EPI><<<nfine, kBlock, 0, st>>>(x, B.tmpA, B, P.J, E, tp, last); break;
+        case 2: k_fdwt_fine<T, 2, 8, EPI><<<nfine, kBlock, 0, st>>>(x, B.tmpA, B, P.J, E, tp, last); break;
+        default: k_fdwt_fine<T, 3, 4, EPI><<<nfine, kBlock, 0, st>>>(x, B.tmpA, B, P.J, E, tp, last); break;
+    }
+    if (int e = check()) return e;
+    if (P.kf < P.J) {
+        k_fdwt_coarse<T, EPI><<<P.nl, kBlock, P.coarse_lds, st>>>(B.tmpA, B, P.J, P.kf, E, tp);
+        if (int e = check()) return e;
+    }
+    return FEWHA_OK;
+}
 
 }  // namespace
 
@@ -662,17 +794,35 @@ int Ops<T>::idwt(const T *c, T *out, bool scale) const {
 
 template <typename T>
 int Ops<T>::fdwt(const T *x, T *out) const {
-    const Taps<T> tp = make_taps<T>();
-    const T *src = x;
-    for (int lev = 0; lev < P.J; ++lev) {
-        T *ll = (lev & 1) ? B.tmpB : B.tmpA;
-        const long nq = (long)(P.n_coef >> (2 * (lev + 1)));
-        k_fdwt_level<T><<<(int)((nq + kBlock - 1) / kBlock), kBlock, 0, st>>>(src, out, ll, B.lay, P.nl, lev, P.J, nq,
-                                                                              tp);
-        if (int e = check()) return e;
-        src = ll;
-    }
-    return FEWHA_OK;
+    EpiArgs E{};
+    E.out = out;
+    return launch_fdwt<T, kEpiPlain>(P, B, st, x, E);
+}
+
+template <typename T>
+int Ops<T>::fdwt_prior(const T *x, const T *cin, T *out) const {
+    EpiArgs E{};
+    E.out = out;
+    E.cin = cin;
+    return launch_fdwt<T, kEpiPrior>(P, B, st, x, E);
+}
+
+template <typename T>
+int Ops<T>::fdwt_pcg(const T *x, int k, double *resnorm) const {
+    EpiArgs E{};
+    E.out = B.y;
+    E.k = k;
+    E.resnorm = resnorm;
+    return launch_fdwt<T, kEpiPcg>(P, B, st, x, E);
+}
+
+template <typename T>
+int Ops<T>::fdwt_rhs(const T *x, T *c, bool cold) const {
+    EpiArgs E{};
+    E.out = B.b;
+    E.c = c;
+    E.cold = cold ? 1 : 0;
+    return launch_fdwt<T, kEpiRhs>(P, B, st, x, E);
 }
 
 template <typename T>
@@ -697,28 +847,8 @@ int Ops<T>::pt(const T *v, T *x) const {
 }
 
 template <typename T>
-int Ops<T>::add_prior(T *y, const T *c) const {
-    k_add_prior<T><<<grid_for((long)P.n_coef), kBlock, 0, st>>>(y, c, B, P.nl, P.J, (long)P.n_coef);
-    return check();
-}
-
-template <typename T>
-int Ops<T>::residual(T *c, bool cold) const {
-    k_residual<T><<<grid_for((long)P.n_coef), kBlock, 0, st>>>(c, B, (long)P.n_coef, cold ? 1 : 0);
-    return check();
-}
-
-template <typename T>
-int Ops<T>::dots(int k, double *resnorm) const {
-    int g = grid_for((long)P.n_coef);
-    if (g > P.n_partials) g = P.n_partials;
-    k_dots<T><<<g, kBlock, 0, st>>>(B.y, B.r, B, P.nl, P.J, (long)P.n_coef, k, resnorm);
-    return check();
-}
-
-template <typename T>
 int Ops<T>::update(T *c, int k) const {
-    k_update<T><<<grid_for((long)P.n_coef), kBlock, 0, st>>>(c, B, P.nl, P.J, (long)P.n_coef, k);
+    k_update<T><<<(int)P.coef_tiles.size(), kBlock, 0, st>>>(c, B, P.J, k);
     return check();
 }
 
@@ -735,6 +865,19 @@ int Ops<T>::wnorm(const T *s) const {
 template <typename T>
 int Ops<T>::fit(const T *u, const T *a_prev, T *a, double gain) const {
     k_fit<T><<<grid_for((long)P.n_act), kBlock, 0, st>>>(u, a_prev, a, B, P.nl, P.nd, (long)P.n_act, gain);
+    return check();
+}
+
+template <typename T>
+int Ops<T>::build_tables() const {
+    const long ne = (long)P.nw * P.nl * P.maxnv;
+    k_build_tabs<T><<<(int)((ne + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+        const_cast<Ent<T> *>(B.xtab), const_cast<Ent<T> *>(B.ytab), B.wfs, B.proj, B.lay, P.nw, P.nl, P.maxnv);
+    if (int e = check()) return e;
+    const long nr = (long)P.nw * P.sum_n;
+    k_build_ranges<T><<<(int)((nr + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+        const_cast<Range *>(B.xrng), const_cast<Range *>(B.yrng), B.xtab, B.ytab, B.wfs, B.lay, P.nw, P.nl, P.maxnv,
+        P.sum_n);
     return check();
 }
 

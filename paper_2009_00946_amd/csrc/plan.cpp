@@ -62,7 +62,7 @@ int plan_create(const fewha_config *cfg, Plan **out) {
         if (!pow2(L.n) || L.n < 2 || (L.n >> cfg->J) < 1 || !(L.spacing > 0) || !(L.cn2_weight > 0) ||
             !(L.height >= 0) || !std::isfinite(L.spacing) || !std::isfinite(L.height))
             return FEWHA_ERR_INVALID_ARG;
-        if (L.n > kMaxGrid) return FEWHA_ERR_UNSUPPORTED;
+        if (L.n > kMaxLayerGrid) return FEWHA_ERR_UNSUPPORTED;
     }
     for (int g = 0; g < cfg->n_wfs; ++g) {
         const fewha_wfs &W = cfg->wfs[g];
@@ -106,6 +106,8 @@ int plan_create(const fewha_config *cfg, Plan **out) {
             if (dn < db || (dn == db && P->dm[m].height < P->dm[best].height)) best = m;
         }
         d.dm = best;
+        d.r_off = P->sum_n;
+        P->sum_n += L.n;
         P->dlay.push_back(d);
         P->n_coef += size_t(L.n) * L.n;
     }
@@ -122,6 +124,7 @@ int plan_create(const fewha_config *cfg, Plan **out) {
         d.v_off = long(P->n_nodes);
         d.n_sub = W.n_sub;
         d.nv = W.n_sub + 1;
+        if (d.nv > P->maxnv) P->maxnv = d.nv;
         P->dwfs.push_back(d);
         P->n_slopes += 2 * size_t(W.n_sub) * W.n_sub;
         P->n_nodes += size_t(W.n_sub + 1) * (W.n_sub + 1);
@@ -191,6 +194,28 @@ int plan_create(const fewha_config *cfg, Plan **out) {
                                                 std::pow(P->lay[l].spacing / P->dwfs[0].d, -5.0 / 3.0) *
                                                 std::pow(2.0, -(11.0 / 3.0) * (s - 1));
 
+    // forward DWT split: the first kf levels in tiles over the whole GPU, the remaining ones per
+    // layer inside one workgroup whose LDS holds the level-kf approximation (1.25 m^2 values)
+    int max_n = 0;
+    for (auto &L : P->lay) max_n = L.n > max_n ? L.n : max_n;
+    P->kf = 0;
+    for (int k = (P->J < 2 ? P->J : 2); k <= (P->J < 3 ? P->J : 3); ++k) {
+        size_t m = size_t(max_n >> k);
+        if (m * m * P->elem * 5 / 4 <= 48 * 1024) {
+            P->kf = k;
+            break;
+        }
+    }
+    if (P->kf == 0) {
+        delete P;
+        return FEWHA_ERR_UNSUPPORTED;
+    }
+    P->tq = P->kf == 1 ? 16 : (P->kf == 2 ? 8 : 4);
+    {
+        size_t m = size_t(max_n >> P->kf);
+        P->coarse_lds = (m * m + (m * m) / 4 + 4) * P->elem;
+    }
+
     // tile tables
     for (int l = 0; l < P->nl; ++l) {
         int n = P->lay[l].n, t = n < kIdwtTile ? n : kIdwtTile;
@@ -198,6 +223,11 @@ int plan_create(const fewha_config *cfg, Plan **out) {
             for (int tx = 0; tx < n; tx += t) P->idwt_tiles.push_back({l, ty, tx, t});
         for (int ty = 0; ty < n; ty += kNodeTile)
             for (int tx = 0; tx < n; tx += kNodeTile) P->lay_tiles.push_back({l, ty, tx, 0});
+        int m = n >> P->kf, tq = m < P->tq ? m : P->tq;
+        for (int qy = 0; qy < m; qy += tq)
+            for (int qx = 0; qx < m; qx += tq) P->fine_tiles.push_back({l, qy, qx, tq});
+        for (int st = 0; st < n * n; st += kCoefTile)
+            P->coef_tiles.push_back({l, st, (n * n - st) < kCoefTile ? (n * n - st) : kCoefTile, 0});
     }
     for (int g = 0; g < P->nw; ++g) {
         int nv = P->wfs[g].n_sub + 1, ns = P->wfs[g].n_sub;
@@ -223,6 +253,13 @@ int plan_create(const fewha_config *cfg, Plan **out) {
     P->o_node = take(sizeof(Tile) * P->node_tiles.size());
     P->o_sub = take(sizeof(Tile) * P->sub_tiles.size());
     P->o_laytile = take(sizeof(Tile) * P->lay_tiles.size());
+    P->o_fine = take(sizeof(Tile) * P->fine_tiles.size());
+    P->o_coef = take(sizeof(Tile) * P->coef_tiles.size());
+    const size_t ent = P->prec == FEWHA_FP64 ? 24 : 16;
+    P->o_xtab = take(ent * P->nw * P->nl * P->maxnv);
+    P->o_ytab = take(ent * P->nw * P->nl * P->maxnv);
+    P->o_xrng = take(sizeof(Range) * P->nw * P->sum_n);
+    P->o_yrng = take(sizeof(Range) * P->nw * P->sum_n);
     P->o_jinv = take(E * P->nl * (P->J + 1) * 4);
     P->o_ad = take(E * P->nl * (P->J + 1));
     P->o_bprev = take(E * N);
@@ -238,7 +275,11 @@ int plan_create(const fewha_config *cfg, Plan **out) {
     P->o_b = take(E * N);
     P->o_probe_c = take(E * N);
     P->o_probe_s = take(E * P->n_slopes);
-    P->n_partials = 1024;
+    P->n_partials = kPartialPitch;
+    if (P->fine_tiles.size() + size_t(P->nl) > size_t(kPartialPitch)) {
+        delete P;
+        return FEWHA_ERR_UNSUPPORTED;
+    }
     P->o_partials = take(sizeof(double) * 2 * P->n_partials);
     P->o_scalars = take(sizeof(Scalars));
     P->ws_bytes = o;
