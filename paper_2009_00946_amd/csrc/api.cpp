@@ -51,6 +51,9 @@ Bufs<T> bufs(const Plan &P) {
     b.probe_c = reinterpret_cast<T *>(w + P.o_probe_c);
     b.probe_s = reinterpret_cast<T *>(w + P.o_probe_s);
     b.partials = reinterpret_cast<double *>(w + P.o_partials);
+    b.r2 = reinterpret_cast<T *>(w + P.o_r2);
+    b.q2 = reinterpret_cast<T *>(w + P.o_q2);
+    b.lcount = reinterpret_cast<unsigned *>(w + P.o_lcount);
     b.sc = reinterpret_cast<Scalars *>(w + P.o_scalars);
     return b;
 }
@@ -80,7 +83,7 @@ int ready(const fewha_plan *p) {
 template <typename T>
 int apply_A(const Plan &P, const void *c, void *s, void *stream) {
     auto o = ops<T>(P, stream);
-    TRY(o.idwt(static_cast<const T *>(c), o.B.u, false));
+    TRY(o.idwt(static_cast<const T *>(c), o.B.u));
     return o.slopes(o.B.u, static_cast<T *>(s));
 }
 
@@ -95,7 +98,7 @@ int apply_At(const Plan &P, const void *s, void *c, void *stream) {
 template <typename T>
 int apply_M(const Plan &P, const void *c, void *y, void *stream) {
     auto o = ops<T>(P, stream);
-    TRY(o.idwt(static_cast<const T *>(c), o.B.u, false));
+    TRY(o.idwt(static_cast<const T *>(c), o.B.u));
     TRY(o.nodes(o.B.u, o.B.v, kModeM));
     TRY(o.pt(o.B.v, o.B.x));
     return o.fdwt_prior(o.B.x, static_cast<const T *>(c), static_cast<T *>(y));
@@ -109,22 +112,26 @@ int pcg_solve(const Plan &P, const void *s, void *c, int n_iter, int flags, doub
     TRY(o.nodes(static_cast<const T *>(s), o.B.v, kModeRhs));
     TRY(o.pt(o.B.v, o.B.x));
     TRY(o.fdwt_rhs(o.B.x, cc, flags == FEWHA_COLD));
+    // Residual r_k and search-direction image q_k alternate between two buffers so that the
+    // fused update can read the previous values anywhere while owners write the new ones.
+    T *R[2] = {o.B.r, o.B.r2}, *Q[2] = {o.B.q, o.B.q2};
     for (int k = 0; k < n_iter; ++k) {
-        // y = M z with z = J^-1 r folded into the inverse transform's loads; alpha D z and the
-        // reductions (r, z), (y, z) in the forward transform's epilogue
-        TRY(o.idwt(o.B.r, o.B.u, true));
+        // u = W^T J^-1 r_k (pass k >= 1 first completes the update of pass k-1)
+        if (k == 0) TRY(o.idwt_first(R[0], o.B.u));
+        else TRY(o.idwt_update(R[(k - 1) & 1], Q[k & 1], Q[(k - 1) & 1], R[k & 1], cc, k == 1, o.B.u));
         TRY(o.nodes(o.B.u, o.B.v, kModeM));
         TRY(o.pt(o.B.v, o.B.x));
-        TRY(o.fdwt_pcg(o.B.x, k, resnorm));
-        TRY(o.update(cc, k));
+        // y = W x + alpha D z, (r_k, z), (y, z) and the Alg. 2 scalars of pass k
+        TRY(o.fdwt_pcg(o.B.x, R[k & 1], k, resnorm));
     }
+    if (n_iter > 0) TRY(o.update_last(cc, R[(n_iter - 1) & 1], Q[n_iter & 1], Q[(n_iter - 1) & 1], n_iter == 1));
     return FEWHA_OK;
 }
 
 template <typename T>
 int fit_dm(const Plan &P, const void *c, const void *a_prev, double gain, void *a, void *stream) {
     auto o = ops<T>(P, stream);
-    TRY(o.idwt(static_cast<const T *>(c), o.B.u, false));
+    TRY(o.idwt(static_cast<const T *>(c), o.B.u));
     return o.fit(o.B.u, static_cast<const T *>(a_prev), static_cast<T *>(a), gain);
 }
 
@@ -152,6 +159,7 @@ int bind_tables(Plan &P, hipStream_t st) {
     TRY(o.fill(o.B.b_prev, N, 0));
     TRY(o.fill(o.B.r, N, 0));
     TRY(o.fill(o.B.probe_c, N, 0));
+    HIPTRY(hipMemsetAsync(o.B.lcount, 0, sizeof(unsigned) * P.nl, st));
 
     // Preconditioner of Sec. 3.4: J = alpha D + tau per (layer, level, orientation), with tau the
     // data-term diagonal ||C^1/2 A e_k||^2 at the band's representative coefficient
@@ -271,10 +279,10 @@ int fewha_dwt_inverse(const fewha_plan *p, const void *d_c, void *d_layers, void
     if (!d_layers || !d_c || d_layers == d_c) return FEWHA_ERR_INVALID_ARG;
     if (p->p.prec == FEWHA_FP64) {
         auto o = ops<double>(p->p, stream);
-        return o.idwt(static_cast<const double *>(d_c), static_cast<double *>(d_layers), false);
+        return o.idwt(static_cast<const double *>(d_c), static_cast<double *>(d_layers));
     }
     auto o = ops<float>(p->p, stream);
-    return o.idwt(static_cast<const float *>(d_c), static_cast<float *>(d_layers), false);
+    return o.idwt(static_cast<const float *>(d_c), static_cast<float *>(d_layers));
 }
 
 int fewha_pcg_solve(fewha_plan *p, const void *d_s, void *d_c, int n_iter, int flags, double *d_resnorm,

@@ -78,8 +78,10 @@ struct DevDm {
     int pad;
 };
 
+// Work-item record of a tiled kernel: a = layer or sensor, b, c = tile origin, d = tile size,
+// e = coefficient offset of the layer, f = its grid size n, g = log2 n, h = tiles of that layer.
 struct Tile {
-    int a, b, c, d;
+    int a, b, c, d, e, f, g, h;
 };
 
 // Inclusive range [lo, hi] of sensor node indices (empty when lo > hi).
@@ -110,6 +112,8 @@ struct Bufs {
     const T *jinv;   // [nl][J+1][4] inverse preconditioner per band
     const T *ad;     // [nl][J+1] alpha D per level
     T *b_prev, *r, *p, *q, *y, *u, *x, *v, *tmpA, *tmpB, *b, *probe_c, *probe_s;
+    T *r2, *q2;           // second residual / search-direction image buffers (PCG ping-pong)
+    unsigned *lcount;     // per-layer tile completion counters of the forward transform
     double *partials;
     Scalars *sc;
 };
@@ -140,6 +144,7 @@ struct Plan {
     size_t o_fine = 0, o_coef = 0, o_xtab = 0, o_ytab = 0, o_xrng = 0, o_yrng = 0;
     size_t o_jinv = 0, o_ad = 0, o_bprev = 0, o_r = 0, o_p = 0, o_q = 0, o_y = 0, o_u = 0, o_x = 0, o_v = 0;
     size_t o_tmpA = 0, o_tmpB = 0, o_b = 0, o_probe_c = 0, o_probe_s = 0, o_partials = 0, o_scalars = 0;
+    size_t o_r2 = 0, o_q2 = 0, o_lcount = 0;
     size_t ws_bytes = 0;
     int n_partials = 0;
 

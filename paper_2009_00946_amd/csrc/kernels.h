@@ -7,6 +7,29 @@
 
 namespace fewha {
 
+// Operands of the forward transform's epilogues.
+struct FwdArgs {
+    void *out;          // destination coefficients (plain / prior / pcg)
+    const void *cin;    // prior: c of y = W x + alpha D c
+    const void *rk;     // pcg: r_k
+    void *c;            // rhs: caller's c (zeroed on a cold start)
+    int cold;           // rhs
+    int k;              // pcg: pass index
+    double *resnorm;    // pcg
+};
+
+// Operands of the inverse transform (with the fused Alg. 2 update in kInvUpdate mode).
+struct InvArgs {
+    const void *src;   // plain: c; first / update: r_{k-1} (update) or r_0 (first)
+    void *out;         // layer nodal values
+    const void *yv;    // update: y_{k-1}
+    const void *qold;  // update: q_{k-2} (unused when k-1 is the first pass)
+    void *qnew;        // update: q_{k-1}
+    void *rnew;        // update: r_k
+    void *c;           // update: iterate c (owned entries updated)
+    int first_pass;    // update: pass k-1 was the first (p = z, q = y)
+};
+
 // Daubechies-3 analysis taps h and high-pass partner g_n = (-1)^n h_{5-n}.
 template <typename T>
 struct Taps {
@@ -23,6 +46,9 @@ enum { kModeM = 0, kModeRhs = 1, kModeAdj = 2 };
 // the PCG dot products | b = W x with the warm-restart residual update of Alg. 1.
 enum { kEpiPlain = 0, kEpiPrior = 1, kEpiPcg = 2, kEpiRhs = 3 };
 
+// Inverse-transform input modes: c as given | z = J^-1 r | Alg. 2 update, then z = J^-1 r_new.
+enum { kInvPlain = 0, kInvFirst = 1, kInvUpdate = 2 };
+
 // Enqueues the kernels of one plan on one stream; every call returns FEWHA_OK or FEWHA_ERR_HIP.
 template <typename T>
 struct Ops {
@@ -30,15 +56,21 @@ struct Ops {
     Bufs<T> B;
     hipStream_t st;
 
-    int idwt(const T *c, T *out, bool scale) const;          // out = W^T (J^-1 c if scale)
+    int idwt(const T *c, T *out) const;                      // out = W^T c
+    int idwt_first(const T *r, T *out) const;                // out = W^T J^-1 r
+    // Alg. 2 update of pass k-1 (owned entries of p, q_new, c, r_new written), then out = W^T J^-1 r_new
+    int idwt_update(const T *r_old, const T *q_old, T *q_new, T *r_new, T *c, bool first_pass, T *out) const;
+    template <int EPI>
+    int fwd(const T *x, const FwdArgs &E) const;
     int fdwt(const T *x, T *out) const;                      // out = W x
     int fdwt_prior(const T *x, const T *cin, T *out) const;  // out = W x + alpha D cin
-    int fdwt_pcg(const T *x, int k, double *resnorm) const;  // y = W x + alpha D J^-1 r; Alg. 2 scalars
+    int fdwt_pcg(const T *x, const T *rk, int k, double *resnorm) const;  // y = W x + alpha D J^-1 r_k; scalars
     int fdwt_rhs(const T *x, T *c, bool cold) const;         // b = W x; r = (b - b_prev) + r; b_prev = b
+    // final Alg. 2 update of a solve; the residual lands in the state buffer
+    int update_last(T *c, const T *r_in, const T *q_old, T *q_new, bool first_pass) const;
     int nodes(const T *in, T *v, int mode) const;            // Gamma^T C Gamma P u | Gamma^T C s | Gamma^T mask s
     int slopes(const T *u, T *s) const;                      // s = mask Gamma P u
     int pt(const T *v, T *x) const;                          // x = P^T v
-    int update(T *c, int k) const;                           // p, q, c, r
     int wnorm(const T *s) const;                             // sc->rho = sum C^-1 s^2
     int fit(const T *u, const T *a_prev, T *a, double gain) const;
     int build_tables() const;                                // projection cell tables and ranges

@@ -179,31 +179,46 @@ __device__ __forceinline__ void band_at(int row, int col, int n, int log2n, int 
 }
 
 // ---------------------------------------------------------------------------------------------
-// W^T: multi-level inverse DWT, one launch, cone recomputation per output tile.
+// W^T: multi-level inverse DWT in one launch, with the PCG update fused in front of it.
+//
+// Each workgroup owns a square output tile and rebuilds, from the coarsest level down, only the
+// cone of coefficients that tile depends on.  The whole cone (every level, every band) is
+// fetched from global memory in one batch of independent loads into LDS, so the J levels of
+// synthesis then run from LDS.  In the update mode the loads bring r_{k-1}, y_{k-1}, q_{k-2},
+// the Alg. 2 update is evaluated for every cone coefficient, the coefficients this tile owns are
+// written back (p, q, c and the new residual), and the transform runs on z = J^-1 r_k.
+// Ownership: at level s a tile owns the indices [y0 >> s, (y0 + T0) >> s) when T0 >= 2^s, else
+// index y0 >> s if y0 is a multiple of 2^s (likewise in x), a partition of every band.
 // ---------------------------------------------------------------------------------------------
-template <typename T, bool SCALE>
-__global__ __launch_bounds__(kBlock) void k_idwt(const T *__restrict__ c, T *__restrict__ out,
-                                                 const Tile *__restrict__ tiles, const DevLayer *__restrict__ lays,
-                                                 int J, const T *__restrict__ jinv, Taps<T> tp) {
+
+constexpr int kInvSegMax = 3072;  // cone coefficients of a 32 x 32 tile over up to 12 levels
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_inv(Bufs<T> B, int J, InvArgs A, Taps<T> tp) {
     constexpr int TILE = kIdwtTile;
-    constexpr int R = TILE / 2 + 2;  // longest coefficient run any level needs
-    __shared__ T sA[R * R], sB[R * R], sHL[R * R], sLH[R * R], sHH[R * R];
+    constexpr int R = TILE / 2 + 2;
+    constexpr int MAXI = (kInvSegMax + kBlock - 1) / kBlock;
+    __shared__ T sSeg[kInvSegMax];
+    __shared__ T sL0[R * R], sL1[R * R];
     __shared__ T sAX[TILE * R], sDX[TILE * R];
+    __shared__ int shLoY[kMaxJ + 1], shLoX[kMaxJ + 1], shLnY[kMaxJ + 1], shLnX[kMaxJ + 1], shSeg[kMaxJ + 2];
+    __shared__ T sJinv[(kMaxJ + 1) * 4];
 
-    const Tile t = tiles[blockIdx.x];
-    const DevLayer L = lays[t.a];
-    const int n = L.n, T0 = t.d;
-    const T *cl = c + L.c_off;
-
-    // cone bounds per level (unwrapped indices; periodic wrap happens only on loads)
-    __shared__ int loY[kMaxJ + 1], loX[kMaxJ + 1], lnY[kMaxJ + 1], lnX[kMaxJ + 1];
-    if (threadIdx.x == 0) {
-        int ly = t.b, hy = t.b + T0 - 1, lx = t.c, hx = t.c + T0 - 1;
+    const Tile t = B.idwt_tiles[blockIdx.x];
+    const int l = t.a, y0 = t.b, x0 = t.c, T0 = t.d, n = t.f;
+    const long coff = t.e;
+    // Cone bounds per level, computed by every lane in registers (uniform values): the item
+    // decode below then needs no LDS round trips.
+    int loY[kMaxJ + 1], loX[kMaxJ + 1], lnY[kMaxJ + 1], lnX[kMaxJ + 1], seg[kMaxJ + 2];
+    {
+        int ly = y0, hy = y0 + T0 - 1, lx = x0, hx = x0 + T0 - 1, off = 0;
         loY[0] = ly;
         loX[0] = lx;
         lnY[0] = T0;
         lnX[0] = T0;
-        for (int s = 1; s <= J; ++s) {
+        seg[0] = 0;
+#pragma unroll
+        for (int s = 1; s <= kMaxJ; ++s) {
             ly = (ly >> 1) - 2;
             hy >>= 1;
             lx = (lx >> 1) - 2;
@@ -212,43 +227,142 @@ __global__ __launch_bounds__(kBlock) void k_idwt(const T *__restrict__ c, T *__r
             loX[s] = lx;
             lnY[s] = hy - ly + 1;
             lnX[s] = hx - lx + 1;
+            seg[s] = off;
+            if (s <= J) off += 3 * lnY[s] * lnX[s];
+        }
+        seg[kMaxJ + 1] = off;  // the coarsest LL starts here
+    }
+    int lnYJ = 0, lnXJ = 0, loYJ = 0, loXJ = 0;
+#pragma unroll
+    for (int s = 1; s <= kMaxJ; ++s)
+        if (s == J) {
+            lnYJ = lnY[s];
+            lnXJ = lnX[s];
+            loYJ = loY[s];
+            loXJ = loX[s];
+        }
+    const int llOff = seg[kMaxJ + 1], total = llOff + lnYJ * lnXJ;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int s = 0; s <= kMaxJ; ++s) {
+            shLoY[s] = loY[s];
+            shLoX[s] = loX[s];
+            shLnY[s] = lnY[s];
+            shLnX[s] = lnX[s];
+            shSeg[s] = seg[s];
+        }
+        shSeg[kMaxJ + 1] = llOff;
+    }
+    if (MODE != kInvPlain && threadIdx.x < (J + 1) * 4) sJinv[threadIdx.x] = B.jinv[l * (J + 1) * 4 + threadIdx.x];
+
+    double alpha = 0.0, beta = 0.0;
+    int stopped = 0;
+    if constexpr (MODE == kInvUpdate) {
+        alpha = B.sc->alpha;
+        beta = B.sc->beta;
+        stopped = B.sc->stopped;
+    }
+    const T *src = static_cast<const T *>(A.src);
+    __syncthreads();
+    // ---- one batch of independent loads: the whole cone (plus owned-only operands) ----
+    for (int base = 0; base < total; base += MAXI * kBlock) {
+        long gi[MAXI];
+        int li[MAXI], bnd[MAXI];
+        bool own[MAXI];
+        T rv[MAXI], yv[MAXI], qv[MAXI], pv[MAXI], cv[MAXI];
+#pragma unroll
+        for (int c = 0; c < MAXI; ++c) {
+            const int k = base + c * kBlock + (int)threadIdx.x;
+            gi[c] = -1;
+            own[c] = false;
+            if (k >= total) continue;
+            // segment of item k: a detail band of level s, or the coarsest LL
+            int s = J, o = 0, ly = loYJ, lx = loXJ, nxs = lnXJ, rem = k - llOff;
+#pragma unroll
+            for (int ss = 1; ss <= kMaxJ; ++ss) {
+                const int sz = lnY[ss] * lnX[ss];
+                if (ss <= J && k >= seg[ss] && k < seg[ss] + 3 * sz) {
+                    s = ss;
+                    ly = loY[ss];
+                    lx = loX[ss];
+                    nxs = lnX[ss];
+                    rem = k - seg[ss];
+                    o = 1 + rem / sz;
+                    rem -= (o - 1) * sz;
+                }
+            }
+            const int r = rem / nxs, q = rem - r * nxs;
+            const int m = n >> s, msk = m - 1;
+            const int uy = ly + r, ux = lx + q;
+            const int gr = uy & msk, gc = ux & msk;
+            const int row = gr + ((o == 2 || o == 3) ? m : 0), col = gc + ((o == 1 || o == 3) ? m : 0);
+            gi[c] = coff + (long)row * n + col;
+            li[c] = k;
+            bnd[c] = s * 4 + o;
+            if constexpr (MODE == kInvUpdate) {
+                const int ts = T0 >> s, msk2 = (1 << s) - 1;
+                const bool oy = ts >= 1 ? (uy >= (y0 >> s) && uy < (y0 >> s) + ts) : ((y0 & msk2) == 0 && uy == (y0 >> s));
+                const bool ox = ts >= 1 ? (ux >= (x0 >> s) && ux < (x0 >> s) + ts) : ((x0 & msk2) == 0 && ux == (x0 >> s));
+                own[c] = oy && ox;
+            }
+            rv[c] = src[gi[c]];
+            if constexpr (MODE == kInvUpdate) {
+                yv[c] = static_cast<const T *>(A.yv)[gi[c]];
+                qv[c] = A.first_pass ? (T)0 : static_cast<const T *>(A.qold)[gi[c]];
+                if (own[c]) {
+                    pv[c] = A.first_pass ? (T)0 : B.p[gi[c]];
+                    cv[c] = static_cast<T *>(A.c)[gi[c]];
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < MAXI; ++c) {
+            if (gi[c] < 0) continue;
+            T val = rv[c];
+            if constexpr (MODE == kInvFirst) {
+                val = rv[c] * sJinv[bnd[c]];
+            } else if constexpr (MODE == kInvUpdate) {
+                const T ji = sJinv[bnd[c]];
+                T rn = rv[c];
+                if (!stopped) {
+                    const T zo = rv[c] * ji;
+                    const T qn = A.first_pass ? yv[c] : yv[c] + (T)beta * qv[c];
+                    rn = rv[c] - (T)alpha * qn;
+                    if (own[c]) {
+                        const T pn = A.first_pass ? zo : zo + (T)beta * pv[c];
+                        B.p[gi[c]] = pn;
+                        static_cast<T *>(A.qnew)[gi[c]] = qn;
+                        static_cast<T *>(A.c)[gi[c]] = cv[c] + (T)alpha * pn;
+                    }
+                }
+                if (own[c]) static_cast<T *>(A.rnew)[gi[c]] = rn;
+                val = rn * ji;
+            }
+            sSeg[li[c]] = val;
         }
     }
     __syncthreads();
-    auto scale = [&](int s, int o) -> T {
-        if constexpr (SCALE) return jinv[(t.a * (J + 1) + s) * 4 + o];
-        else return (T)1;
-    };
 
-    // coarsest level: LL and the three detail bands of the cone region
-    {
-        const int m = n >> J, msk = m - 1, ny = lnY[J], nx = lnX[J];
-        const T s0 = scale(J, 0), s1 = scale(J, 1), s2 = scale(J, 2), s3 = scale(J, 3);
-        for (int idx = threadIdx.x; idx < ny * nx; idx += blockDim.x) {
-            int r = idx / nx, q = idx - r * nx;
-            int gr = (loY[J] + r) & msk, gc = (loX[J] + q) & msk;
-            sA[r * R + q] = cl[(long)gr * n + gc] * s0;
-            sHL[r * R + q] = cl[(long)gr * n + m + gc] * s1;
-            sLH[r * R + q] = cl[(long)(m + gr) * n + gc] * s2;
-            sHH[r * R + q] = cl[(long)(m + gr) * n + m + gc] * s3;
-        }
-    }
-    __syncthreads();
-
-    T *LL = sA, *NX = sB;
+    // ---- synthesis from the coarsest level, all in LDS ----
+    const T *LL = sSeg + llOff;
+    int llp = lnXJ;
+    T *NX = sL0;
+    T *outp = static_cast<T *>(A.out);
     for (int s = J; s >= 1; --s) {
-        const int ny = lnY[s - 1], nxk = lnX[s], nx = lnX[s - 1];
-        const int oy = loY[s - 1], ky = loY[s], ox = loX[s - 1], kx = loX[s];
+        const int ny = shLnY[s - 1], nxk = shLnX[s], nx = shLnX[s - 1];
+        const int oy = shLoY[s - 1], ky = shLoY[s], ox = shLoX[s - 1], kx = shLoX[s];
+        const int bsz = shLnY[s] * shLnX[s], bp = shLnX[s];
+        const T *HL = sSeg + shSeg[s], *LH = HL + bsz, *HH = LH + bsz;
         // undo the y analysis: (LL, x-low/y-high) -> x-low rows, (x-high/y-low, HH) -> x-high rows
         for (int idx = threadIdx.x; idx < ny * nxk; idx += blockDim.x) {
-            int r = idx / nxk, q = idx - r * nxk;
-            int y = oy + r, p = y & 1, kb = (y >> 1) - ky;
+            const int r = idx / nxk, q = idx - r * nxk;
+            const int y = oy + r, p = y & 1, kb = (y >> 1) - ky;
             T a = 0, d = 0;
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                const int at = (kb - j) * R + q;
-                a += tp.h[p + 2 * j] * LL[at] + tp.g[p + 2 * j] * sLH[at];
-                d += tp.h[p + 2 * j] * sHL[at] + tp.g[p + 2 * j] * sHH[at];
+                const int rr = kb - j;
+                a += tp.h[p + 2 * j] * LL[rr * llp + q] + tp.g[p + 2 * j] * LH[rr * bp + q];
+                d += tp.h[p + 2 * j] * HL[rr * bp + q] + tp.g[p + 2 * j] * HH[rr * bp + q];
             }
             sAX[r * R + q] = a;
             sDX[r * R + q] = d;
@@ -256,8 +370,8 @@ __global__ __launch_bounds__(kBlock) void k_idwt(const T *__restrict__ c, T *__r
         __syncthreads();
         // undo the x analysis
         for (int idx = threadIdx.x; idx < ny * nx; idx += blockDim.x) {
-            int r = idx / nx, q = idx - r * nx;
-            int x = ox + q, p = x & 1, kb = (x >> 1) - kx;
+            const int r = idx / nx, q = idx - r * nx;
+            const int x = ox + q, p = x & 1, kb = (x >> 1) - kx;
             T v = 0;
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
@@ -265,24 +379,41 @@ __global__ __launch_bounds__(kBlock) void k_idwt(const T *__restrict__ c, T *__r
                 v += tp.h[p + 2 * j] * sAX[at] + tp.g[p + 2 * j] * sDX[at];
             }
             if (s > 1) NX[r * R + q] = v;
-            else out[L.c_off + (long)(oy + r) * n + ox + q] = v;
-        }
-        if (s > 1) {
-            // detail bands of level s-1 over the region just synthesised
-            const int m = n >> (s - 1), msk = m - 1;
-            const T s1 = scale(s - 1, 1), s2 = scale(s - 1, 2), s3 = scale(s - 1, 3);
-            for (int idx = threadIdx.x; idx < ny * nx; idx += blockDim.x) {
-                int r = idx / nx, q = idx - r * nx;
-                int gr = (oy + r) & msk, gc = (ox + q) & msk;
-                sHL[r * R + q] = cl[(long)gr * n + m + gc] * s1;
-                sLH[r * R + q] = cl[(long)(m + gr) * n + gc] * s2;
-                sHH[r * R + q] = cl[(long)(m + gr) * n + m + gc] * s3;
-            }
-            T *tmp = LL;
-            LL = NX;
-            NX = tmp;
+            else outp[coff + (long)(oy + r) * n + ox + q] = v;
         }
         __syncthreads();
+        LL = NX;
+        llp = R;
+        NX = (NX == sL0) ? sL1 : sL0;
+    }
+}
+
+// Final Alg. 2 update of a solve (elementwise; the residual ends in the state buffer B.r).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_update_last(T *__restrict__ c, Bufs<T> B, int J, const T *__restrict__ rin,
+                                                        const T *__restrict__ qold, T *__restrict__ qnew, int first) {
+    const Tile t = B.coef_tiles[blockIdx.x];
+    const double alpha = B.sc->alpha, beta = B.sc->beta;
+    const int stopped = B.sc->stopped;
+#pragma unroll
+    for (int e = 0; e < kCoefTile / kBlock; ++e) {
+        const int loc = t.b + e * kBlock + (int)threadIdx.x;
+        if (loc >= t.b + t.c) break;
+        const long i = t.e + loc;
+        const T ri = rin[i];
+        if (stopped) {
+            B.r[i] = ri;
+            continue;
+        }
+        int s, o;
+        band_at(loc >> t.g, loc & (t.f - 1), t.f, t.g, J, s, o);
+        const T z = ri * B.jinv[(t.a * (J + 1) + s) * 4 + o];
+        const T p = first ? z : z + (T)beta * B.p[i];
+        const T q = first ? B.y[i] : B.y[i] + (T)beta * qold[i];
+        B.p[i] = p;
+        qnew[i] = q;
+        c[i] += (T)alpha * p;
+        B.r[i] = ri - (T)alpha * q;
     }
 }
 
@@ -336,6 +467,97 @@ __global__ __launch_bounds__(kBlock) void k_nodes(const T *__restrict__ in, T *_
     }
 }
 
+// P + Gamma + C_eta^-1 + Gamma^T on one node tile (the paper's Kernel-2 stage, y-part of M).
+// phi is needed on the tile plus a one-node halo.  Layers are processed in chunks: the cell
+// table entries of the chunk's rows and columns are staged in LDS, then every (node, layer)
+// bilinear gather of the chunk is issued as one batch of independent loads; the per-layer
+// contributions are summed in layer order (deterministic), then slopes, weights and Gamma^T
+// run from LDS.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_nodes_m(const T *__restrict__ u, T *__restrict__ v, Bufs<T> B, int nl) {
+    constexpr int NT = kNodeTile, NP = NT + 2, NS = NT + 1, NN = NP * NP;
+    constexpr int LMAX = 12;
+    constexpr int MAXI = (NN * LMAX + kBlock - 1) / kBlock;
+    __shared__ Ent<T> sX[LMAX * NP], sY[LMAX * NP];
+    __shared__ T sPart[LMAX * NN];
+    __shared__ T sPhi[NN];
+    __shared__ T sSx[NS * NS], sSy[NS * NS];
+    __shared__ long sOff[LMAX];
+    __shared__ int sN[LMAX];
+    const Tile t = B.node_tiles[blockIdx.x];
+    const int g = t.a, i0 = t.b, j0 = t.c;
+    const DevWfs W = B.wfs[g];
+    const int ns = W.n_sub, nv = W.nv;
+    for (int idx = threadIdx.x; idx < NN; idx += blockDim.x) sPhi[idx] = 0;
+    for (int l0 = 0; l0 < nl; l0 += LMAX) {
+        const int nc = (nl - l0) < LMAX ? (nl - l0) : LMAX;
+        for (int idx = threadIdx.x; idx < 2 * nc * NP; idx += blockDim.x) {
+            const int axis = idx / (nc * NP), rem = idx - axis * nc * NP, l = rem / NP, b = rem - l * NP;
+            int node = (axis ? i0 : j0) - 1 + b;
+            node = node < 0 ? 0 : (node > ns ? ns : node);
+            const long at = ((long)g * nl + l0 + l) * B.maxnv + node;
+            if (axis) sY[l * NP + b] = B.ytab[at];
+            else sX[l * NP + b] = B.xtab[at];
+        }
+        if (threadIdx.x < nc) {
+            sOff[threadIdx.x] = B.lay[l0 + threadIdx.x].c_off;
+            sN[threadIdx.x] = B.lay[l0 + threadIdx.x].n;
+        }
+        __syncthreads();
+        T val[MAXI];
+#pragma unroll
+        for (int c = 0; c < MAXI; ++c) {
+            const int k = c * kBlock + (int)threadIdx.x;
+            val[c] = 0;
+            if (k < nc * NN) {
+                const int l = k / NN, nd = k - l * NN, a = nd / NP, b = nd - a * NP;
+                const int i = i0 - 1 + a, j = j0 - 1 + b;
+                if (i >= 0 && i <= ns && j >= 0 && j <= ns) {
+                    const Ent<T> ex = sX[l * NP + b], ey = sY[l * NP + a];
+                    const int n = sN[l];
+                    const T *U = u + sOff[l] + (long)ey.k0 * n + ex.k0;
+                    val[c] = (ey.w0 * ex.w0) * U[0] + (ey.w0 * ex.w1) * U[1] + (ey.w1 * ex.w0) * U[n] +
+                             (ey.w1 * ex.w1) * U[n + 1];
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < MAXI; ++c) {
+            const int k = c * kBlock + (int)threadIdx.x;
+            if (k < nc * NN) sPart[k] = val[c];
+        }
+        __syncthreads();
+        for (int nd = threadIdx.x; nd < NN; nd += blockDim.x) {
+            T acc = sPhi[nd];
+            for (int l = 0; l < nc; ++l) acc += sPart[l * NN + nd];
+            sPhi[nd] = acc;
+        }
+        __syncthreads();
+    }
+    for (int idx = threadIdx.x; idx < NS * NS; idx += blockDim.x) {
+        const int a = idx / NS, b = idx - a * NS, i = i0 - 1 + a, j = j0 - 1 + b;
+        T sx = 0, sy = 0;
+        if (i >= 0 && i < ns && j >= 0 && j < ns && subap_active(W, i, j)) {
+            const T w = (T)W.inv_var;
+            const T p00 = sPhi[a * NP + b], p01 = sPhi[a * NP + b + 1];
+            const T p10 = sPhi[(a + 1) * NP + b], p11 = sPhi[(a + 1) * NP + b + 1];
+            sx = w * ((T)0.5 * ((p01 - p00) + (p11 - p10)));
+            sy = w * ((T)0.5 * ((p10 - p00) + (p11 - p01)));
+        }
+        sSx[idx] = sx;
+        sSy[idx] = sy;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < NT * NT; idx += blockDim.x) {
+        const int a = idx / NT, b = idx - a * NT, i = i0 + a, j = j0 + b;
+        if (i > ns || j > ns) continue;
+        const int s11 = (a + 1) * NS + (b + 1), s10 = (a + 1) * NS + b, s01 = a * NS + (b + 1), s00 = a * NS + b;
+        const T val = (T)0.5 * ((-sSx[s11] - sSy[s11]) + (sSx[s10] - sSy[s10]) + (-sSx[s01] + sSy[s01]) +
+                                (sSx[s00] + sSy[s00]));
+        v[W.v_off + (long)i * nv + j] = val;
+    }
+}
+
 // s = mask Gamma P u on subaperture tiles.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_slopes(const T *__restrict__ u, T *__restrict__ s, Bufs<T> B, int nl) {
@@ -367,112 +589,326 @@ __global__ __launch_bounds__(kBlock) void k_slopes(const T *__restrict__ u, T *_
 }
 
 // ---------------------------------------------------------------------------------------------
-// P^T as a gather over layer-node tiles, through the transpose ranges of the cell tables.
+// P^T on a tile of layer nodes, as a gather through the transpose ranges of the cell tables.
+// For each sensor the node ranges of the tile's rows and columns are staged in LDS, then the
+// sub-block of v_g they span and its table entries arrive in one batch of independent loads;
+// each lane sums its node's contributions (sensor, then row, then column order) from LDS.  A
+// sensor whose sub-block does not fit the LDS budget is gathered straight from global memory.
 // ---------------------------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pt(const T *__restrict__ v, T *__restrict__ x, Bufs<T> B, int nl,
                                                int nw) {
-    constexpr int NT = kNodeTile;
+    constexpr int NT = kNodeTile, GMAX = kBlock / NT, VMAX = sizeof(T) == 4 ? 4096 : 2048, EMAX = 512, MAXI = 16;
+    static_assert(GMAX == 16, "16 lanes per sensor");
+    __shared__ Range sRy[GMAX * NT], sRx[GMAX * NT];
+    __shared__ T sV[VMAX];
+    __shared__ Ent<T> sEy[EMAX], sEx[EMAX];
+    __shared__ int sGeo[GMAX][4];  // i0, ni, j0, nj of each sensor's sub-block (ni = 0: empty)
     const Tile t = B.lay_tiles[blockIdx.x];
-    const DevLayer L = B.lay[t.a];
-    const int k = t.b + (int)(threadIdx.x / NT), q = t.c + (int)(threadIdx.x % NT);
-    if (k >= L.n || q >= L.n) return;
+    const int l = t.a, k0 = t.b, q0 = t.c, n = t.f, roff = t.h;
+    const int k = k0 + (int)(threadIdx.x / NT), q = q0 + (int)(threadIdx.x % NT);
+    const bool valid = k < n && q < n;
+    const int lane = threadIdx.x & (NT - 1), grp = threadIdx.x / NT;
     T acc = 0;
-    for (int g = 0; g < nw; ++g) {
-        const Range rx = B.xrng[(long)g * B.sum_n + L.r_off + q];
-        const Range ry = B.yrng[(long)g * B.sum_n + L.r_off + k];
-        if (rx.lo > rx.hi || ry.lo > ry.hi) continue;
-        const Ent<T> *xt = B.xtab + ((long)g * nl + t.a) * B.maxnv;
-        const Ent<T> *yt = B.ytab + ((long)g * nl + t.a) * B.maxnv;
-        const DevWfs W = B.wfs[g];
-        const T *vg = v + W.v_off;
-        for (int i = ry.lo; i <= ry.hi; ++i) {
-            const Ent<T> ey = yt[i];
-            const T wy = (ey.k0 == k) ? ey.w0 : ey.w1;
-            const T *row = vg + (long)i * W.nv;
-            for (int j = rx.lo; j <= rx.hi; ++j) {
-                const Ent<T> ex = xt[j];
-                const T wx = (ex.k0 == q) ? ex.w0 : ex.w1;
-                acc += (wy * wx) * row[j];
+    for (int gb = 0; gb < nw; gb += GMAX) {
+        const int gc = (nw - gb) < GMAX ? (nw - gb) : GMAX;
+        // 16 lanes per sensor: each loads the range of one tile row and one tile column, then the
+        // group reduces them to the sub-block of sensor nodes the whole tile needs
+        {
+            Range ry{1, 0}, rx{1, 0};
+            if (grp < gc) {
+                const long base = (long)(gb + grp) * B.sum_n + roff;
+                if (k0 + lane < n) ry = B.yrng[base + k0 + lane];
+                if (q0 + lane < n) rx = B.xrng[base + q0 + lane];
+            }
+            sRy[grp * NT + lane] = ry;
+            sRx[grp * NT + lane] = rx;
+            int i0 = ry.lo <= ry.hi ? ry.lo : (1 << 30), i1 = ry.lo <= ry.hi ? ry.hi : -1;
+            int j0 = rx.lo <= rx.hi ? rx.lo : (1 << 30), j1 = rx.lo <= rx.hi ? rx.hi : -1;
+#pragma unroll
+            for (int m = 1; m < NT; m <<= 1) {
+                i0 = min(i0, __shfl_xor(i0, m, NT));
+                i1 = max(i1, __shfl_xor(i1, m, NT));
+                j0 = min(j0, __shfl_xor(j0, m, NT));
+                j1 = max(j1, __shfl_xor(j1, m, NT));
+            }
+            if (lane == 0) {
+                const bool ne = i1 >= i0 && j1 >= j0;
+                sGeo[grp][0] = i0;
+                sGeo[grp][1] = ne ? i1 - i0 + 1 : 0;
+                sGeo[grp][2] = j0;
+                sGeo[grp][3] = ne ? j1 - j0 + 1 : 0;
             }
         }
-    }
-    x[L.c_off + (long)k * L.n + q] = acc;
-}
-
-// ---------------------------------------------------------------------------------------------
-// Forward transform W with fused epilogues.
-// ---------------------------------------------------------------------------------------------
-struct EpiArgs {
-    const void *cin;   // kEpiPrior: c of y = W x + alpha D c
-    void *out;         // destination coefficient vector (y, or b for kEpiRhs)
-    void *c;           // kEpiRhs + cold: caller's c, zeroed
-    int cold;          // kEpiRhs
-    int k;             // kEpiPcg: pass index
-    double *resnorm;   // kEpiPcg
-    int nfine;         // partial slots used by the tiled kernel
-};
-
-// Deliver one coefficient of W x to its destination; accumulate the PCG dot partials.
-template <typename T, int EPI>
-__device__ __forceinline__ void epilogue(const Bufs<T> &B, const EpiArgs &E, long i, int l, int s, int o, int J, T w,
-                                         double &rho, double &mu) {
-    T *out = static_cast<T *>(E.out);
-    if constexpr (EPI == kEpiPlain) {
-        out[i] = w;
-    } else if constexpr (EPI == kEpiPrior) {
-        out[i] = w + B.ad[l * (J + 1) + s] * static_cast<const T *>(E.cin)[i];
-    } else if constexpr (EPI == kEpiPcg) {
-        const T ri = B.r[i];
-        const T z = ri * B.jinv[(l * (J + 1) + s) * 4 + o];
-        const T yi = w + B.ad[l * (J + 1) + s] * z;
-        out[i] = yi;
-        rho += (double)ri * (double)z;
-        mu += (double)yi * (double)z;
-    } else {  // kEpiRhs: b = W x; r = (b - b_prev) + r (cold: r = b, c = 0); b_prev = b
-        out[i] = w;
-        if (E.cold) {
-            B.r[i] = w;
-            static_cast<T *>(E.c)[i] = 0;
-        } else {
-            B.r[i] = (w - B.b_prev[i]) + B.r[i];
+        __syncthreads();
+        // staging plan (uniform, in registers): sensors in order while the LDS budget lasts
+        int I0[GMAX], NI[GMAX], J0[GMAX], NJ[GMAX], VO[GMAX], EYO[GMAX], EXO[GMAX], CUM[GMAX + 1];
+        {
+            int vo = 0, eyo = 0, exo = 0, cum = 0;
+#pragma unroll
+            for (int g = 0; g < GMAX; ++g) {
+                I0[g] = sGeo[g][0];
+                J0[g] = sGeo[g][2];
+                const int ni = g < gc ? sGeo[g][1] : 0, nj = g < gc ? sGeo[g][3] : 0;
+                const bool ok = ni > 0 && vo + ni * nj <= VMAX && eyo + ni <= EMAX && exo + nj <= EMAX;
+                NI[g] = ok ? ni : (ni > 0 ? -1 : 0);  // -1: not staged, gather from global memory
+                NJ[g] = ok ? nj : 0;
+                VO[g] = vo;
+                EYO[g] = eyo;
+                EXO[g] = exo;
+                CUM[g] = cum;
+                if (ok) {
+                    vo += ni * nj;
+                    eyo += ni;
+                    exo += nj;
+                    cum += ni * nj + ni + nj;
+                }
+            }
+            CUM[GMAX] = cum;
         }
-        B.b_prev[i] = w;
+        const int total = CUM[GMAX];
+        for (int base = 0; base < total; base += MAXI * kBlock) {
+            T vv[MAXI], w0[MAXI], w1[MAXI];
+            int k0e[MAXI], dst[MAXI], kind[MAXI];
+#pragma unroll
+            for (int c = 0; c < MAXI; ++c) {
+                const int kk = base + c * kBlock + (int)threadIdx.x;
+                kind[c] = -1;
+                if (kk >= total) continue;
+                int g = 0;
+#pragma unroll
+                for (int gg = 1; gg < GMAX; ++gg)
+                    if (kk >= CUM[gg]) g = gg;
+                int i0 = 0, j0 = 0, ni = 0, nj = 0, vo = 0, eyo = 0, exo = 0, cm = 0;
+#pragma unroll
+                for (int gg = 0; gg < GMAX; ++gg)
+                    if (gg == g) {
+                        i0 = I0[gg];
+                        j0 = J0[gg];
+                        ni = NI[gg];
+                        nj = NJ[gg];
+                        vo = VO[gg];
+                        eyo = EYO[gg];
+                        exo = EXO[gg];
+                        cm = CUM[gg];
+                    }
+                int rem = kk - cm;
+                const int sg = gb + g;
+                const long tb = ((long)sg * nl + l) * B.maxnv;
+                if (rem < ni * nj) {
+                    const int a = rem / nj, b = rem - a * nj;
+                    const DevWfs &W = B.wfs[sg];
+                    vv[c] = v[W.v_off + (long)(i0 + a) * W.nv + j0 + b];
+                    dst[c] = vo + rem;
+                    kind[c] = 0;
+                } else {
+                    rem -= ni * nj;
+                    const bool isy = rem < ni;
+                    if (!isy) rem -= ni;
+                    const Ent<T> e = isy ? B.ytab[tb + i0 + rem] : B.xtab[tb + j0 + rem];
+                    k0e[c] = e.k0;
+                    w0[c] = e.w0;
+                    w1[c] = e.w1;
+                    dst[c] = (isy ? eyo : exo) + rem;
+                    kind[c] = isy ? 1 : 2;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < MAXI; ++c) {
+                if (kind[c] == 0) sV[dst[c]] = vv[c];
+                else if (kind[c] > 0) {
+                    Ent<T> &e = (kind[c] == 1) ? sEy[dst[c]] : sEx[dst[c]];
+                    e.k0 = k0e[c];
+                    e.w0 = w0[c];
+                    e.w1 = w1[c];
+                }
+            }
+        }
+        __syncthreads();
+        if (valid) {
+#pragma unroll
+            for (int g = 0; g < GMAX; ++g) {
+                const Range ry = sRy[g * NT + (k - k0)], rx = sRx[g * NT + (q - q0)];
+                if (g >= gc || ry.lo > ry.hi || rx.lo > rx.hi) continue;
+                if (NI[g] > 0) {
+                    const T *V = sV + VO[g];
+                    for (int i = ry.lo; i <= ry.hi; ++i) {
+                        const Ent<T> ey = sEy[EYO[g] + i - I0[g]];
+                        const T wy = (ey.k0 == k) ? ey.w0 : ey.w1;
+                        for (int j = rx.lo; j <= rx.hi; ++j) {
+                            const Ent<T> ex = sEx[EXO[g] + j - J0[g]];
+                            const T wx = (ex.k0 == q) ? ex.w0 : ex.w1;
+                            acc += (wy * wx) * V[(i - I0[g]) * NJ[g] + (j - J0[g])];
+                        }
+                    }
+                } else {  // did not fit the LDS budget: straight from global memory
+                    const int sg = gb + g;
+                    const DevWfs W = B.wfs[sg];
+                    const Ent<T> *xt = B.xtab + ((long)sg * nl + l) * B.maxnv;
+                    const Ent<T> *yt = B.ytab + ((long)sg * nl + l) * B.maxnv;
+                    for (int i = ry.lo; i <= ry.hi; ++i) {
+                        const Ent<T> ey = yt[i];
+                        const T wy = (ey.k0 == k) ? ey.w0 : ey.w1;
+                        for (int j = rx.lo; j <= rx.hi; ++j) {
+                            const Ent<T> ex = xt[j];
+                            const T wx = (ex.k0 == q) ? ex.w0 : ex.w1;
+                            acc += (wy * wx) * v[W.v_off + (long)i * W.nv + j];
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
     }
+    if (valid) x[(long)t.e + (long)k * n + q] = acc;
 }
 
-// Region geometry of the tiled forward DWT: a tile of TQ x TQ level-KF approximation
-// coefficients needs LL_{s} on a run of len(s) = TQ 2^(KF-s) + 4 (2^(KF-s) - 1) indices.
+// ---------------------------------------------------------------------------------------------
+// Forward transform W in one launch, with fused epilogues.
+//
+// Fine part: a workgroup owns a TQ x TQ tile of level-KF approximation coefficients; it stages
+// the input region with its halo (periodic wrap) and the epilogue operands of every coefficient
+// it owns in one batch of independent loads, then runs levels 1..KF from LDS.  Coarse part: the
+// last tile of a layer to finish (per-layer counter) runs levels KF+1..J of that layer in LDS.
+// The last layer to finish combines the FP64 partial sums of every workgroup, in a fixed order,
+// into the Alg. 2 scalars.
+// ---------------------------------------------------------------------------------------------
+
+// Region geometry of the fine part: a tile of TQ x TQ level-KF approximation coefficients needs
+// LL_s on a run of len(s) = TQ 2^(KF-s) + 4 (2^(KF-s) - 1) indices (s = 0 is the input).
 template <int KF, int TQ>
 struct FineGeom {
     static constexpr int len(int s) { return TQ * (1 << (KF - s)) + 4 * ((1 << (KF - s)) - 1); }
 };
 
+// Deliver one coefficient w of W x (operands e0, e1 prefetched); accumulate PCG dot partials.
+template <typename T, int EPI>
+__device__ __forceinline__ void deliver(const Bufs<T> &B, const FwdArgs &E, long i, T w, T ad, T ji, T e0, T e1,
+                                        double &rho, double &mu) {
+    if constexpr (EPI == kEpiPlain) {
+        static_cast<T *>(E.out)[i] = w;
+    } else if constexpr (EPI == kEpiPrior) {
+        static_cast<T *>(E.out)[i] = w + ad * e0;
+    } else if constexpr (EPI == kEpiPcg) {
+        const T z = e0 * ji;
+        const T yi = w + ad * z;
+        static_cast<T *>(E.out)[i] = yi;
+        rho += (double)e0 * (double)z;
+        mu += (double)yi * (double)z;
+    } else {  // b = W x:  r = (b - b_prev) + r  (cold: r = b, c = 0);  b_prev = b
+        if (E.cold) {
+            B.r[i] = w;
+            static_cast<T *>(E.c)[i] = 0;
+        } else {
+            B.r[i] = (w - e0) + e1;
+        }
+        B.b_prev[i] = w;
+    }
+}
+
+template <typename T, int EPI>
+__device__ __forceinline__ void prefetch(const Bufs<T> &B, const FwdArgs &E, long i, T &e0, T &e1) {
+    if constexpr (EPI == kEpiPrior) e0 = static_cast<const T *>(E.cin)[i];
+    else if constexpr (EPI == kEpiPcg) e0 = static_cast<const T *>(E.rk)[i];
+    else if constexpr (EPI == kEpiRhs) {
+        e0 = B.b_prev[i];
+        e1 = B.r[i];
+    }
+}
+
+// Global index of coefficient (r, q) of band o (0 LL, 1 x-high, 2 y-high, 3 HH) at level s.
+__device__ __forceinline__ long band_index(long coff, int n, int s, int o, int r, int q) {
+    const int m = n >> s;
+    return coff + (long)(r + ((o == 2 || o == 3) ? m : 0)) * n + q + ((o == 1 || o == 3) ? m : 0);
+}
+
 template <typename T, int KF, int TQ, int EPI>
-__global__ __launch_bounds__(kBlock) void k_fdwt_fine(const T *__restrict__ x, T *__restrict__ ll_out, Bufs<T> B,
-                                                      int J, EpiArgs E, Taps<T> tp, int last) {
+__global__ __launch_bounds__(kBlock) void k_fwd(const T *__restrict__ x, Bufs<T> B, int J, int nl, FwdArgs E,
+                                                Taps<T> tp) {
     using G = FineGeom<KF, TQ>;
-    constexpr int L0 = G::len(0), L1 = G::len(1);
-    __shared__ T sA[L0 * L0];
-    __shared__ T sB[(KF >= 2 ? L1 * L1 : 1)];
+    constexpr int L0 = G::len(0), L1 = G::len(1), EMAX = 1024;
+    constexpr int NE = (EPI == kEpiRhs) ? 2 : ((EPI == kEpiPlain) ? 0 : 1);
+    constexpr int FINE = L0 * L0 + (KF >= 2 ? L1 * L1 : 0) + NE * EMAX;
+    constexpr int COARSE = 64 * 64 + 32 * 32;
+    constexpr int SMEM = FINE > COARSE ? FINE : COARSE;
+    constexpr int MAXI = 8;
+    __shared__ T sm[SMEM];
+    __shared__ T sAd[kMaxJ + 1], sJi[(kMaxJ + 1) * 4];
     __shared__ double sh[kBlock / 64];
+    __shared__ int sLast;
+    T *sA = sm, *sB = sm + L0 * L0, *sE0 = sB + (KF >= 2 ? L1 * L1 : 0), *sE1 = sE0 + EMAX;
+
     if constexpr (EPI == kEpiRhs) {
         if (blockIdx.x == 0 && threadIdx.x == 0) reset_scalars(B.sc);
     }
-
     const Tile t = B.fine_tiles[blockIdx.x];
-    const DevLayer L = B.lay[t.a];
-    const int n = L.n, tq = t.d, shift = KF;
-    // run lengths and origins for this tile (tq <= TQ; small layers use smaller tiles)
-    int len[KF + 1];
-#pragma unroll
-    for (int s = 0; s <= KF; ++s) len[s] = tq * (1 << (KF - s)) + 4 * ((1 << (KF - s)) - 1);
-    const int oy = t.b << shift, ox = t.c << shift, nmask = n - 1;
+    const int l = t.a, qy = t.b, qx = t.c, tq = t.d, n = t.f, ntiles = t.h;
+    const long coff = t.e;
+    if (threadIdx.x <= J) sAd[threadIdx.x] = (EPI == kEpiPrior || EPI == kEpiPcg) ? B.ad[l * (J + 1) + threadIdx.x] : (T)0;
+    if (EPI == kEpiPcg && threadIdx.x < (J + 1) * 4) sJi[threadIdx.x] = B.jinv[l * (J + 1) * 4 + threadIdx.x];
 
-    // stage the input region (periodic wrap) in LDS
-    for (int idx = threadIdx.x; idx < len[0] * len[0]; idx += blockDim.x) {
-        const int r = idx / len[0], q = idx - r * len[0];
-        sA[r * L0 + q] = x[L.c_off + (long)((oy + r) & nmask) * n + ((ox + q) & nmask)];
+    int len[KF + 1], own[KF + 1], eoff[KF + 2];
+    eoff[1] = 0;
+#pragma unroll
+    for (int s = 0; s <= KF; ++s) {
+        len[s] = tq * (1 << (KF - s)) + 4 * ((1 << (KF - s)) - 1);
+        own[s] = tq << (KF - s);
+        if (s >= 1) eoff[s + 1] = eoff[s] + 3 * own[s] * own[s];
+    }
+    const int ne = eoff[KF + 1] + (KF == J ? own[KF] * own[KF] : 0);
+    const int oy = qy << KF, ox = qx << KF, nmask = n - 1;
+
+    // ---- one batch of loads: input region + epilogue operands of the owned coefficients ----
+    {
+        const int nreg = len[0] * len[0], tot = nreg + (NE ? ne : 0);
+        for (int base = 0; base < tot; base += MAXI * kBlock) {
+            T v0[MAXI], v1[MAXI];
+            int d[MAXI];
+#pragma unroll
+            for (int c = 0; c < MAXI; ++c) {
+                const int k = base + c * kBlock + (int)threadIdx.x;
+                d[c] = -1;
+                if (k >= tot) continue;
+                if (k < nreg) {
+                    const int r = k / len[0], q = k - r * len[0];
+                    v0[c] = x[coff + (long)((oy + r) & nmask) * n + ((ox + q) & nmask)];
+                    d[c] = r * L0 + q;
+                } else {
+                    const int e = k - nreg;
+                    int s = 1;
+                    while (s < KF && e >= eoff[s + 1]) ++s;
+                    int o, r, q;
+                    if (e >= eoff[KF + 1]) {  // LL at level KF == J
+                        s = KF;
+                        o = 0;
+                        const int rem = e - eoff[KF + 1];
+                        r = rem / own[KF];
+                        q = rem - r * own[KF];
+                    } else {
+                        const int rem = e - eoff[s], b2 = own[s] * own[s];
+                        o = 1 + rem / b2;
+                        const int rr = rem - (o - 1) * b2;
+                        r = rr / own[s];
+                        q = rr - r * own[s];
+                    }
+                    const long gi = band_index(coff, n, s, o, (qy << (KF - s)) + r, (qx << (KF - s)) + q);
+                    T a0 = 0, a1 = 0;
+                    prefetch<T, EPI>(B, E, gi, a0, a1);
+                    v0[c] = a0;
+                    v1[c] = a1;
+                    d[c] = SMEM + e;  // marks an epilogue slot
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < MAXI; ++c) {
+                if (d[c] < 0) continue;
+                if (d[c] < SMEM) sA[d[c]] = v0[c];
+                else {
+                    sE0[d[c] - SMEM] = v0[c];
+                    if (NE == 2) sE1[d[c] - SMEM] = v1[c];
+                }
+            }
+        }
     }
     __syncthreads();
 
@@ -482,8 +918,9 @@ __global__ __launch_bounds__(kBlock) void k_fdwt_fine(const T *__restrict__ x, T
         const T *src = (s & 1) ? sA : sB;
         T *dst = (s & 1) ? sB : sA;
         const int sp = (s & 1) ? L0 : L1, dp = (s & 1) ? L1 : L0;
-        const int ln = len[s], own = tq << (KF - s), m = n >> s;  // output run, owned run, band size
-        const int by = t.b << (KF - s), bx = t.c << (KF - s);      // owned origin at level s
+        const int ln = len[s], ow = own[s];
+        const int by = qy << (KF - s), bx = qx << (KF - s);
+        const T ad = sAd[s];
         for (int idx = threadIdx.x; idx < ln * ln; idx += blockDim.x) {
             const int r = idx / ln, q = idx - r * ln;
             T ll = 0, lh = 0, hl = 0, hh = 0;
@@ -502,121 +939,146 @@ __global__ __launch_bounds__(kBlock) void k_fdwt_fine(const T *__restrict__ x, T
                 hh += tp.g[a] * dx;
             }
             if (s < KF) dst[r * dp + q] = ll;
-            if (r < own && q < own) {
-                const int gr = by + r, gc = bx + q;
-                const long base = L.c_off;
-                epilogue<T, EPI>(B, E, base + (long)gr * n + m + gc, t.a, s, 1, J, hl, rho, mu);
-                epilogue<T, EPI>(B, E, base + (long)(m + gr) * n + gc, t.a, s, 2, J, lh, rho, mu);
-                epilogue<T, EPI>(B, E, base + (long)(m + gr) * n + m + gc, t.a, s, 3, J, hh, rho, mu);
+            if (r < ow && q < ow) {
+                const int e = eoff[s] + r * ow + q, b2 = ow * ow;
+                const T w[3] = {hl, lh, hh};
+#pragma unroll
+                for (int o = 1; o <= 3; ++o) {
+                    const int ei = e + (o - 1) * b2;
+                    const T e0 = NE ? sE0[ei] : (T)0, e1 = NE == 2 ? sE1[ei] : (T)0;
+                    deliver<T, EPI>(B, E, band_index(coff, n, s, o, by + r, bx + q), w[o - 1], ad,
+                                    EPI == kEpiPcg ? sJi[s * 4 + o] : (T)0, e0, e1, rho, mu);
+                }
                 if (s == KF) {
-                    if (KF == J) epilogue<T, EPI>(B, E, base + (long)gr * n + gc, t.a, s, 0, J, ll, rho, mu);
-                    else ll_out[(L.c_off >> (2 * KF)) + (long)gr * m + gc] = ll;
+                    if (KF == J) {
+                        const int ei = eoff[KF + 1] + r * ow + q;
+                        const T e0 = NE ? sE0[ei] : (T)0, e1 = NE == 2 ? sE1[ei] : (T)0;
+                        deliver<T, EPI>(B, E, band_index(coff, n, s, 0, by + r, bx + q), ll, ad,
+                                        EPI == kEpiPcg ? sJi[s * 4] : (T)0, e0, e1, rho, mu);
+                    } else {
+                        B.tmpA[(coff >> (2 * KF)) + (long)(by + r) * (n >> KF) + bx + q] = ll;
+                    }
                 }
             }
         }
         __syncthreads();
     }
+
+    double vals[2];
     if constexpr (EPI == kEpiPcg) {
-        double vals[2];
         vals[0] = block_sum(rho, sh);
         vals[1] = block_sum(mu, sh);
-        const int pitch = kPartialPitch;
-        const bool am_last = publish_last(B.partials, pitch, 2, blockIdx.x, vals, &B.sc->counter);
-        if (!last || !am_last) return;
-        const double R = gather_partials(B.partials, pitch, 0, gridDim.x, sh);
-        const double Mu = gather_partials(B.partials, pitch, 1, gridDim.x, sh);
-        if (threadIdx.x == 0) pcg_scalars(B.sc, R, Mu, E.k, E.resnorm);
     }
-}
-
-// Levels KF+1..J of one layer per workgroup; the level-KF approximation comes from ll_in.
-template <typename T, int EPI>
-__global__ __launch_bounds__(kBlock) void k_fdwt_coarse(const T *__restrict__ ll_in, Bufs<T> B, int J, int KF,
-                                                        EpiArgs E, Taps<T> tp) {
-    extern __shared__ char smem_raw[];
-    T *sA = reinterpret_cast<T *>(smem_raw);
-    __shared__ double sh[kBlock / 64];
-    const int l = blockIdx.x;
-    const DevLayer L = B.lay[l];
-    const int n = L.n, m0 = n >> KF;
-    T *sB = sA + m0 * m0;
-    for (int idx = threadIdx.x; idx < m0 * m0; idx += blockDim.x) sA[idx] = ll_in[(L.c_off >> (2 * KF)) + idx];
+    const int nfine = gridDim.x;
+    if (KF == J) {
+        if constexpr (EPI == kEpiPcg) {
+            if (!publish_last(B.partials, kPartialPitch, 2, blockIdx.x, vals, &B.sc->counter)) return;
+            const double R = gather_partials(B.partials, kPartialPitch, 0, nfine, sh);
+            const double Mu = gather_partials(B.partials, kPartialPitch, 1, nfine, sh);
+            if (threadIdx.x == 0) pcg_scalars(B.sc, R, Mu, E.k, E.resnorm);
+        }
+        return;
+    }
+    // ---- hand the layer's remaining levels to its last tile ----
+    if (threadIdx.x == 0) {
+        if constexpr (EPI == kEpiPcg) {
+            __hip_atomic_store(B.partials + blockIdx.x, vals[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(B.partials + kPartialPitch + blockIdx.x, vals[1], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __threadfence();
+        const unsigned prev = atomicAdd(B.lcount + l, 1u);
+        sLast = (prev == (unsigned)(ntiles - 1));
+        if (sLast) __hip_atomic_store(B.lcount + l, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     __syncthreads();
-    double rho = 0.0, mu = 0.0;
-    T *src = sA, *dst = sB;
+    if (!sLast) return;
+    __threadfence();
+
+    const int m0 = n >> KF;
+    T *cs = sm, *cd = sm + m0 * m0;
+    for (int idx = threadIdx.x; idx < m0 * m0; idx += blockDim.x) cs[idx] = B.tmpA[(coff >> (2 * KF)) + idx];
+    __syncthreads();
+    rho = 0.0;
+    mu = 0.0;
     for (int s = KF + 1; s <= J; ++s) {
-        const int mi = n >> (s - 1), h = mi >> 1, msk = mi - 1;
-        for (int idx = threadIdx.x; idx < h * h; idx += blockDim.x) {
-            const int r = idx / h, q = idx - r * h;
-            int cols[6];
+        const int mi = n >> (s - 1), h = mi >> 1, msk = mi - 1, nq = h * h;
+        const T ad = sAd[s];
+        for (int base = 0; base < nq; base += 4 * kBlock) {
+            T e0[4][4], e1[4][4];
 #pragma unroll
-            for (int b = 0; b < 6; ++b) cols[b] = (2 * q + b) & msk;
-            T ll = 0, lh = 0, hl = 0, hh = 0;
+            for (int c = 0; c < 4; ++c) {
+                const int qi = base + c * kBlock + (int)threadIdx.x;
+                if (qi >= nq || NE == 0) continue;
+                const int r = qi / h, q = qi - r * h;
 #pragma unroll
-            for (int a = 0; a < 6; ++a) {
-                const T *row = src + ((2 * r + a) & msk) * mi;
-                T ax = 0, dx = 0;
-#pragma unroll
-                for (int b = 0; b < 6; ++b) {
-                    const T xv = row[cols[b]];
-                    ax += tp.h[b] * xv;
-                    dx += tp.g[b] * xv;
+                for (int o = 0; o < 4; ++o) {
+                    if (o == 0 && s != J) continue;
+                    prefetch<T, EPI>(B, E, band_index(coff, n, s, o, r, q), e0[c][o], e1[c][o]);
                 }
-                ll += tp.h[a] * ax;
-                lh += tp.g[a] * ax;
-                hl += tp.h[a] * dx;
-                hh += tp.g[a] * dx;
             }
-            const long base = L.c_off;
-            epilogue<T, EPI>(B, E, base + (long)r * n + h + q, l, s, 1, J, hl, rho, mu);
-            epilogue<T, EPI>(B, E, base + (long)(h + r) * n + q, l, s, 2, J, lh, rho, mu);
-            epilogue<T, EPI>(B, E, base + (long)(h + r) * n + h + q, l, s, 3, J, hh, rho, mu);
-            if (s == J) epilogue<T, EPI>(B, E, base + (long)r * n + q, l, s, 0, J, ll, rho, mu);
-            else dst[r * h + q] = ll;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int qi = base + c * kBlock + (int)threadIdx.x;
+                if (qi >= nq) continue;
+                const int r = qi / h, q = qi - r * h;
+                int cols[6];
+#pragma unroll
+                for (int b = 0; b < 6; ++b) cols[b] = (2 * q + b) & msk;
+                T ll = 0, lh = 0, hl = 0, hh = 0;
+#pragma unroll
+                for (int a = 0; a < 6; ++a) {
+                    const T *row = cs + ((2 * r + a) & msk) * mi;
+                    T ax = 0, dx = 0;
+#pragma unroll
+                    for (int b = 0; b < 6; ++b) {
+                        const T xv = row[cols[b]];
+                        ax += tp.h[b] * xv;
+                        dx += tp.g[b] * xv;
+                    }
+                    ll += tp.h[a] * ax;
+                    lh += tp.g[a] * ax;
+                    hl += tp.h[a] * dx;
+                    hh += tp.g[a] * dx;
+                }
+                const T w[4] = {ll, hl, lh, hh};
+#pragma unroll
+                for (int o = 1; o <= 3; ++o)
+                    deliver<T, EPI>(B, E, band_index(coff, n, s, o, r, q), w[o], ad,
+                                    EPI == kEpiPcg ? sJi[s * 4 + o] : (T)0, NE ? e0[c][o] : (T)0,
+                                    NE == 2 ? e1[c][o] : (T)0, rho, mu);
+                if (s == J)
+                    deliver<T, EPI>(B, E, band_index(coff, n, s, 0, r, q), ll, ad, EPI == kEpiPcg ? sJi[s * 4] : (T)0,
+                                    NE ? e0[c][0] : (T)0, NE == 2 ? e1[c][0] : (T)0, rho, mu);
+                else
+                    cd[r * h + q] = ll;
+            }
         }
         __syncthreads();
-        // the next level reads what was just written; the old input becomes the next output
-        T *tmp = src;
-        src = dst;
-        dst = tmp;
+        T *tmp = cs;
+        cs = cd;
+        cd = tmp;
     }
     if constexpr (EPI == kEpiPcg) {
-        double vals[2];
         vals[0] = block_sum(rho, sh);
         vals[1] = block_sum(mu, sh);
-        const int pitch = kPartialPitch;
-        if (!publish_last(B.partials, pitch, 2, E.nfine + blockIdx.x, vals, &B.sc->counter)) return;
-        const double R = gather_partials(B.partials, pitch, 0, E.nfine + gridDim.x, sh);
-        const double Mu = gather_partials(B.partials, pitch, 1, E.nfine + gridDim.x, sh);
+        if (threadIdx.x == 0) {
+            __hip_atomic_store(B.partials + nfine + l, vals[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(B.partials + kPartialPitch + nfine + l, vals[1], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence();
+            const unsigned prev = atomicAdd(&B.sc->counter, 1u);
+            sLast = (prev == (unsigned)(nl - 1));
+            if (sLast) {
+                __threadfence();
+                __hip_atomic_store(&B.sc->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        __syncthreads();
+        if (!sLast) return;
+        const double R = gather_partials(B.partials, kPartialPitch, 0, nfine + nl, sh);
+        const double Mu = gather_partials(B.partials, kPartialPitch, 1, nfine + nl, sh);
         if (threadIdx.x == 0) pcg_scalars(B.sc, R, Mu, E.k, E.resnorm);
-    }
-}
-
-// ---------------------------------------------------------------------------------------------
-// Element-wise PCG update on coefficient tiles (layer known per tile, band from the index).
-// ---------------------------------------------------------------------------------------------
-// p = z + beta p; q = y + beta q; c += alpha p; r -= alpha q   (first pass: p = z, q = y)
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_update(T *__restrict__ c, Bufs<T> B, int J, int k) {
-    if (B.sc->stopped) return;
-    const T alpha = (T)B.sc->alpha, beta = (T)B.sc->beta;
-    const Tile t = B.coef_tiles[blockIdx.x];
-    const DevLayer L = B.lay[t.a];
-#pragma unroll
-    for (int e = 0; e < kCoefTile / kBlock; ++e) {
-        const int loc = t.b + e * kBlock + (int)threadIdx.x;
-        if (loc >= t.b + t.c) break;
-        const long i = L.c_off + loc;
-        int s, o;
-        band_at(loc >> L.log2n, loc & (L.n - 1), L.n, L.log2n, J, s, o);
-        const T ri = B.r[i];
-        const T z = ri * B.jinv[(t.a * (J + 1) + s) * 4 + o];
-        const T p = (k == 0) ? z : z + beta * B.p[i];
-        const T q = (k == 0) ? B.y[i] : B.y[i] + beta * B.q[i];
-        B.p[i] = p;
-        B.q[i] = q;
-        c[i] += alpha * p;
-        B.r[i] = ri - alpha * q;
     }
 }
 
@@ -744,26 +1206,6 @@ int grid_for(long n) {
 
 int check() { return hipGetLastError() == hipSuccess ? FEWHA_OK : FEWHA_ERR_HIP; }
 
-template <typename T, int EPI>
-int launch_fdwt(const Plan &P, const Bufs<T> &B, hipStream_t st, const T *x, const EpiArgs &E0) {
-    const Taps<T> tp = make_taps<T>();
-    EpiArgs E = E0;
-    const int nfine = (int)P.fine_tiles.size();
-    E.nfine = nfine;
-    const int last = (P.kf == P.J) ? 1 : 0;
-    switch (P.kf) {
-        case 1: k_fdwt_fine<T, 1, 16, EPI><<<nfine, kBlock, 0, st>>>(x, B.tmpA, B, P.J, E, tp, last); break;
-        case 2: k_fdwt_fine<T, 2, 8, EPI><<<nfine, kBlock, 0, st>>>(x, B.tmpA, B, P.J, E, tp, last); break;
-        default: k_fdwt_fine<T, 3, 4, EPI><<<nfine, kBlock, 0, st>>>(x, B.tmpA, B, P.J, E, tp, last); break;
-    }
-    if (int e = check()) return e;
-    if (P.kf < P.J) {
-        k_fdwt_coarse<T, EPI><<<P.nl, kBlock, P.coarse_lds, st>>>(B.tmpA, B, P.J, P.kf, E, tp);
-        if (int e = check()) return e;
-    }
-    return FEWHA_OK;
-}
-
 }  // namespace
 
 // ---------------------------------------------------------------------------------------------
@@ -783,52 +1225,88 @@ Taps<T> make_taps() {
 }
 
 template <typename T>
-int Ops<T>::idwt(const T *c, T *out, bool scale) const {
-    const int tiles = (int)P.idwt_tiles.size();
-    if (scale)
-        k_idwt<T, true><<<tiles, kBlock, 0, st>>>(c, out, B.idwt_tiles, B.lay, P.J, B.jinv, make_taps<T>());
-    else
-        k_idwt<T, false><<<tiles, kBlock, 0, st>>>(c, out, B.idwt_tiles, B.lay, P.J, B.jinv, make_taps<T>());
+int Ops<T>::idwt(const T *c, T *out) const {
+    InvArgs A{};
+    A.src = c;
+    A.out = out;
+    k_inv<T, kInvPlain><<<(int)P.idwt_tiles.size(), kBlock, 0, st>>>(B, P.J, A, make_taps<T>());
+    return check();
+}
+
+template <typename T>
+int Ops<T>::idwt_first(const T *r, T *out) const {
+    InvArgs A{};
+    A.src = r;
+    A.out = out;
+    k_inv<T, kInvFirst><<<(int)P.idwt_tiles.size(), kBlock, 0, st>>>(B, P.J, A, make_taps<T>());
+    return check();
+}
+
+template <typename T>
+int Ops<T>::idwt_update(const T *r_old, const T *q_old, T *q_new, T *r_new, T *c, bool first_pass, T *out) const {
+    InvArgs A{};
+    A.src = r_old;
+    A.out = out;
+    A.yv = B.y;
+    A.qold = first_pass ? B.y : q_old;  // never read on the first pass
+    A.qnew = q_new;
+    A.rnew = r_new;
+    A.c = c;
+    A.first_pass = first_pass ? 1 : 0;
+    k_inv<T, kInvUpdate><<<(int)P.idwt_tiles.size(), kBlock, 0, st>>>(B, P.J, A, make_taps<T>());
+    return check();
+}
+
+template <typename T>
+template <int EPI>
+int Ops<T>::fwd(const T *x, const FwdArgs &E) const {
+    const int nf = (int)P.fine_tiles.size();
+    const Taps<T> tp = make_taps<T>();
+    switch (P.kf) {
+        case 1: k_fwd<T, 1, 16, EPI><<<nf, kBlock, 0, st>>>(x, B, P.J, P.nl, E, tp); break;
+        case 2: k_fwd<T, 2, 8, EPI><<<nf, kBlock, 0, st>>>(x, B, P.J, P.nl, E, tp); break;
+        default: k_fwd<T, 3, 4, EPI><<<nf, kBlock, 0, st>>>(x, B, P.J, P.nl, E, tp); break;
+    }
     return check();
 }
 
 template <typename T>
 int Ops<T>::fdwt(const T *x, T *out) const {
-    EpiArgs E{};
+    FwdArgs E{};
     E.out = out;
-    return launch_fdwt<T, kEpiPlain>(P, B, st, x, E);
+    return fwd<kEpiPlain>(x, E);
 }
 
 template <typename T>
 int Ops<T>::fdwt_prior(const T *x, const T *cin, T *out) const {
-    EpiArgs E{};
+    FwdArgs E{};
     E.out = out;
     E.cin = cin;
-    return launch_fdwt<T, kEpiPrior>(P, B, st, x, E);
+    return fwd<kEpiPrior>(x, E);
 }
 
 template <typename T>
-int Ops<T>::fdwt_pcg(const T *x, int k, double *resnorm) const {
-    EpiArgs E{};
+int Ops<T>::fdwt_pcg(const T *x, const T *rk, int k, double *resnorm) const {
+    FwdArgs E{};
     E.out = B.y;
+    E.rk = rk;
     E.k = k;
     E.resnorm = resnorm;
-    return launch_fdwt<T, kEpiPcg>(P, B, st, x, E);
+    return fwd<kEpiPcg>(x, E);
 }
 
 template <typename T>
 int Ops<T>::fdwt_rhs(const T *x, T *c, bool cold) const {
-    EpiArgs E{};
-    E.out = B.b;
+    FwdArgs E{};
     E.c = c;
     E.cold = cold ? 1 : 0;
-    return launch_fdwt<T, kEpiRhs>(P, B, st, x, E);
+    return fwd<kEpiRhs>(x, E);
 }
 
 template <typename T>
 int Ops<T>::nodes(const T *in, T *v, int mode) const {
     const int tiles = (int)P.node_tiles.size();
-    if (mode == kModeM) k_nodes<T, kModeM><<<tiles, kBlock, 0, st>>>(in, v, B, P.nl);
+    if (mode == kModeM) k_nodes_m<T><<<tiles, kBlock, 0, st>>>(in, v, B, P.nl);
     else if (mode == kModeRhs) k_nodes<T, kModeRhs><<<tiles, kBlock, 0, st>>>(in, v, B, P.nl);
     else k_nodes<T, kModeAdj><<<tiles, kBlock, 0, st>>>(in, v, B, P.nl);
     return check();
@@ -847,8 +1325,9 @@ int Ops<T>::pt(const T *v, T *x) const {
 }
 
 template <typename T>
-int Ops<T>::update(T *c, int k) const {
-    k_update<T><<<(int)P.coef_tiles.size(), kBlock, 0, st>>>(c, B, P.J, k);
+int Ops<T>::update_last(T *c, const T *r_in, const T *q_old, T *q_new, bool first_pass) const {
+    k_update_last<T><<<(int)P.coef_tiles.size(), kBlock, 0, st>>>(c, B, P.J, r_in, first_pass ? B.y : q_old, q_new,
+                                                                    first_pass ? 1 : 0);
     return check();
 }
 

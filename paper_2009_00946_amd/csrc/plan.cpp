@@ -206,7 +206,7 @@ int plan_create(const fewha_config *cfg, Plan **out) {
             break;
         }
     }
-    if (P->kf == 0) {
+    if (P->kf == 0 || P->n_coef >= (size_t(1) << 31)) {
         delete P;
         return FEWHA_ERR_UNSUPPORTED;
     }
@@ -218,23 +218,24 @@ int plan_create(const fewha_config *cfg, Plan **out) {
 
     // tile tables
     for (int l = 0; l < P->nl; ++l) {
-        int n = P->lay[l].n, t = n < kIdwtTile ? n : kIdwtTile;
+        const int n = P->lay[l].n, t = n < kIdwtTile ? n : kIdwtTile, off = int(P->dlay[l].c_off);
+        const int lg = P->dlay[l].log2n;
         for (int ty = 0; ty < n; ty += t)
-            for (int tx = 0; tx < n; tx += t) P->idwt_tiles.push_back({l, ty, tx, t});
+            for (int tx = 0; tx < n; tx += t) P->idwt_tiles.push_back({l, ty, tx, t, off, n, lg, 0});
         for (int ty = 0; ty < n; ty += kNodeTile)
-            for (int tx = 0; tx < n; tx += kNodeTile) P->lay_tiles.push_back({l, ty, tx, 0});
-        int m = n >> P->kf, tq = m < P->tq ? m : P->tq;
+            for (int tx = 0; tx < n; tx += kNodeTile) P->lay_tiles.push_back({l, ty, tx, kNodeTile, off, n, lg, P->dlay[l].r_off});
+        const int m = n >> P->kf, tq = m < P->tq ? m : P->tq, nt = (m / tq) * (m / tq);
         for (int qy = 0; qy < m; qy += tq)
-            for (int qx = 0; qx < m; qx += tq) P->fine_tiles.push_back({l, qy, qx, tq});
+            for (int qx = 0; qx < m; qx += tq) P->fine_tiles.push_back({l, qy, qx, tq, off, n, lg, nt});
         for (int st = 0; st < n * n; st += kCoefTile)
-            P->coef_tiles.push_back({l, st, (n * n - st) < kCoefTile ? (n * n - st) : kCoefTile, 0});
+            P->coef_tiles.push_back({l, st, (n * n - st) < kCoefTile ? (n * n - st) : kCoefTile, 0, off, n, lg, 0});
     }
     for (int g = 0; g < P->nw; ++g) {
         int nv = P->wfs[g].n_sub + 1, ns = P->wfs[g].n_sub;
         for (int i = 0; i < nv; i += kNodeTile)
-            for (int j = 0; j < nv; j += kNodeTile) P->node_tiles.push_back({g, i, j, 0});
+            for (int j = 0; j < nv; j += kNodeTile) P->node_tiles.push_back({g, i, j, kNodeTile, 0, 0, 0, 0});
         for (int i = 0; i < ns; i += kNodeTile)
-            for (int j = 0; j < ns; j += kNodeTile) P->sub_tiles.push_back({g, i, j, 0});
+            for (int j = 0; j < ns; j += kNodeTile) P->sub_tiles.push_back({g, i, j, kNodeTile, 0, 0, 0, 0});
     }
 
     // workspace map
@@ -275,6 +276,9 @@ int plan_create(const fewha_config *cfg, Plan **out) {
     P->o_b = take(E * N);
     P->o_probe_c = take(E * N);
     P->o_probe_s = take(E * P->n_slopes);
+    P->o_r2 = take(E * N);
+    P->o_q2 = take(E * N);
+    P->o_lcount = take(sizeof(unsigned) * P->nl);
     P->n_partials = kPartialPitch;
     if (P->fine_tiles.size() + size_t(P->nl) > size_t(kPartialPitch)) {
         delete P;
