@@ -104,6 +104,7 @@ def main():
     ap.add_argument("--frames", type=int, default=16, help="distinct synthetic slope frames (cycled)")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle CPU time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--eager", action="store_true", help="launch kernels one by one instead of replaying HIP graphs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs the single-GPU hot path only; multi-GPU runs are not provided "
@@ -142,12 +143,34 @@ def main():
         frame(k)
     torch.cuda.synchronize()
     assert P.last_status() == 0, fewha.STATUS.get(P.last_status())
+    run = frame
+    if not args.eager:
+        # one HIP graph per synthetic frame (same launches, its own slope buffer): a replay is
+        # one whole frame, RHS + PCG + fitting, with no host work between kernels
+        graphs = []
+        cap = torch.cuda.Stream()
+        cap.wait_stream(torch.cuda.current_stream())
+        for f in range(len(S)):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=cap):
+                frame(f)
+            graphs.append(g)
+        torch.cuda.current_stream().wait_stream(cap)
+        torch.cuda.synchronize()
+
+        def run(k, warm=True):
+            graphs[k % len(graphs)].replay()
+
+        for k in range(len(S)):
+            run(k)
+        torch.cuda.synchronize()
+        assert P.last_status() == 0, fewha.STATUS.get(P.last_status())
 
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     ev[0].record(stream)
     for k in range(args.steps):
-        frame(args.warmup + k)
+        run(args.warmup + k)
         ev[k + 1].record(stream)
     torch.cuda.synchronize()
     per = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
@@ -171,7 +194,8 @@ def main():
         "dtype": "f32" if P.precision == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": "%s: %s" % (cfg["name"], cfg["description"]), "n_iter": n_iter, "warm": True,
-                   "gain": gain, "n_coef": model["n_coef"], "n_slopes": P.n_slopes, "n_act": P.n_act},
+                   "gain": gain, "n_coef": model["n_coef"], "n_slopes": P.n_slopes, "n_act": P.n_act,
+                   "launch": "eager" if args.eager else "hip_graph_per_frame"},
         "ms_median": round(float(np.median(per)), 5),
         "ms_p99": round(float(np.percentile(per, 99)), 5),
         "frames_per_s": round(1e3 / ms_mean, 1),

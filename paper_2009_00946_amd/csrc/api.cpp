@@ -53,7 +53,9 @@ Bufs<T> bufs(const Plan &P) {
     b.partials = reinterpret_cast<double *>(w + P.o_partials);
     b.r2 = reinterpret_cast<T *>(w + P.o_r2);
     b.q2 = reinterpret_cast<T *>(w + P.o_q2);
-    b.lcount = reinterpret_cast<unsigned *>(w + P.o_lcount);
+    b.over = reinterpret_cast<int *>(w + P.o_lcount);
+    b.xrtab = reinterpret_cast<const RtabEnt<T> *>(w + P.o_xrtab);
+    b.yrtab = reinterpret_cast<const RtabEnt<T> *>(w + P.o_yrtab);
     b.sc = reinterpret_cast<Scalars *>(w + P.o_scalars);
     return b;
 }
@@ -116,15 +118,17 @@ int pcg_solve(const Plan &P, const void *s, void *c, int n_iter, int flags, doub
     // fused update can read the previous values anywhere while owners write the new ones.
     T *R[2] = {o.B.r, o.B.r2}, *Q[2] = {o.B.q, o.B.q2};
     for (int k = 0; k < n_iter; ++k) {
-        // u = W^T J^-1 r_k (pass k >= 1 first completes the update of pass k-1)
+        // u = W^T J^-1 r_k; from pass 1 on, this launch first reduces pass k-1, forms its Alg. 2
+        // scalars and applies its update
         if (k == 0) TRY(o.idwt_first(R[0], o.B.u));
-        else TRY(o.idwt_update(R[(k - 1) & 1], Q[k & 1], Q[(k - 1) & 1], R[k & 1], cc, k == 1, o.B.u));
+        else TRY(o.idwt_update(R[(k - 1) & 1], Q[k & 1], Q[(k - 1) & 1], R[k & 1], cc, k - 1, resnorm, o.B.u));
         TRY(o.nodes(o.B.u, o.B.v, kModeM));
         TRY(o.pt(o.B.v, o.B.x));
-        // y = W x + alpha D z, (r_k, z), (y, z) and the Alg. 2 scalars of pass k
-        TRY(o.fdwt_pcg(o.B.x, R[k & 1], k, resnorm));
+        // y = W x + alpha D z with the (r_k, z), (y, z) partials of pass k
+        TRY(o.fdwt_pcg(o.B.x, R[k & 1]));
     }
-    if (n_iter > 0) TRY(o.update_last(cc, R[(n_iter - 1) & 1], Q[n_iter & 1], Q[(n_iter - 1) & 1], n_iter == 1));
+    if (n_iter > 0) TRY(o.update_last(cc, R[(n_iter - 1) & 1], Q[n_iter & 1], Q[(n_iter - 1) & 1], n_iter - 1, resnorm));
+    const_cast<Plan &>(P).last_slot = n_iter > 0 ? ((n_iter - 1) & 1) : 1;
     return FEWHA_OK;
 }
 
@@ -154,12 +158,13 @@ int bind_tables(Plan &P, hipStream_t st) {
     for (int k = 0; k < nb; ++k) ad[k] = (T)P.ad[k];
     HIPTRY(hipMemcpy(w + P.o_ad, ad.data(), sizeof(T) * nb, hipMemcpyHostToDevice));
     const long N = (long)P.n_coef;
-    TRY(o.build_tables());
+    TRY(o.prepare());
+    HIPTRY(hipMemset(o.B.over, 0, sizeof(int) * P.nw));
+    TRY(o.build_tables(o.B.over));
     TRY(o.init_scalars());
     TRY(o.fill(o.B.b_prev, N, 0));
     TRY(o.fill(o.B.r, N, 0));
     TRY(o.fill(o.B.probe_c, N, 0));
-    HIPTRY(hipMemsetAsync(o.B.lcount, 0, sizeof(unsigned) * P.nl, st));
 
     // Preconditioner of Sec. 3.4: J = alpha D + tau per (layer, level, orientation), with tau the
     // data-term diagonal ||C^1/2 A e_k||^2 at the band's representative coefficient
@@ -178,10 +183,17 @@ int bind_tables(Plan &P, hipStream_t st) {
                 TRY(o.wnorm(o.B.probe_s));
                 TRY(o.fill(o.B.probe_c + k, 1, (T)0));
                 double tau = 0;
-                HIPTRY(hipMemcpyAsync(&tau, &o.B.sc->rho, sizeof(double), hipMemcpyDeviceToHost, st));
+                HIPTRY(hipMemcpyAsync(&tau, &o.B.sc[2].rho, sizeof(double), hipMemcpyDeviceToHost, st));
                 HIPTRY(hipStreamSynchronize(st));
                 P.jtab[size_t(l * (P.J + 1) + s) * 4 + ori] = P.ad[size_t(l) * (P.J + 1) + s] + tau;
             }
+    }
+    {
+        std::vector<int> over(P.nw, 0);
+        HIPTRY(hipMemcpy(over.data(), o.B.over, sizeof(int) * P.nw, hipMemcpyDeviceToHost));
+        P.rtab_ok = true;
+        for (int g = 0; g < P.nw; ++g)
+            if (over[g]) P.rtab_ok = false;
     }
     std::vector<T> jinv(size_t(nb) * 4, (T)0);
     for (size_t k = 0; k < jinv.size(); ++k)
@@ -338,7 +350,7 @@ int fewha_precond_table(const fewha_plan *p, double *h_jdiag) {
 int fewha_last_status(const fewha_plan *p) {
     TRY(ready(p));
     int st = 0;
-    const Scalars *sc = reinterpret_cast<const Scalars *>(p->p.ws + p->p.o_scalars);
+    const Scalars *sc = reinterpret_cast<const Scalars *>(p->p.ws + p->p.o_scalars) + p->p.last_slot;
     if (hipMemcpy(&st, &sc->status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return FEWHA_ERR_HIP;
     return st;
 }

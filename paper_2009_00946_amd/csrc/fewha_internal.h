@@ -60,6 +60,15 @@ struct Ent {
     T w0, w1;
 };
 
+// One (sensor node, weight) pair of a transpose-table row: the nodes of a sensor grid line whose
+// bilinear cells touch a given layer grid line, zero-padded to kRtabWidth pairs.
+constexpr int kRtabWidth = 4;
+template <typename T>
+struct RtabEnt {
+    int idx;
+    T w;
+};
+
 // Per (guide star, layer): ray geometry of Sec. 2.1.  Node (i, j) lands at grid coordinates
 // u = (sig (x0 + j d) + hx) / spacing + n/2, v = (sig (x0 + i d) + hy) / spacing + n/2;
 // slope / intercept give the same map in affine form, used only to bound candidate searches.
@@ -89,7 +98,10 @@ struct Range {
     int lo, hi;
 };
 
-// PCG scalars of Alg. 2 in FP64, kept on the device so no pass needs a host round trip.
+// PCG scalars of Alg. 2 in FP64, kept on the device so no pass needs a host round trip.  The
+// workspace holds three: the states after even and odd passes (written by workgroup 0 of the
+// kernel that consumes a pass's reduction while the others still read the previous state) and
+// one for setup-time reductions.
 struct Scalars {
     double rho, mu, rho_old, alpha, alpha_old, beta;
     int stopped;     // zero residual, breakdown or non-finite: later passes are no-ops
@@ -108,12 +120,13 @@ struct Bufs {
     const Tile *idwt_tiles, *node_tiles, *sub_tiles, *lay_tiles, *fine_tiles, *coef_tiles;
     const Ent<T> *xtab, *ytab;  // [nw][nl][maxnv]
     const Range *xrng, *yrng;   // [nw][sum_n]: sensor nodes touching each layer grid line
+    const RtabEnt<T> *xrtab, *yrtab;  // [nw][sum_n][kRtabWidth]: the same as (node, weight) lists
     int maxnv, sum_n, kf;       // table pitch, total grid lines, levels done by the tiled forward DWT
     const T *jinv;   // [nl][J+1][4] inverse preconditioner per band
     const T *ad;     // [nl][J+1] alpha D per level
     T *b_prev, *r, *p, *q, *y, *u, *x, *v, *tmpA, *tmpB, *b, *probe_c, *probe_s;
     T *r2, *q2;           // second residual / search-direction image buffers (PCG ping-pong)
-    unsigned *lcount;     // per-layer tile completion counters of the forward transform
+    int *over;            // per-sensor flags: a transpose row exceeded kRtabWidth (setup only)
     double *partials;
     Scalars *sc;
 };
@@ -134,6 +147,8 @@ struct Plan {
     std::vector<Tile> idwt_tiles, node_tiles, sub_tiles, lay_tiles, fine_tiles, coef_tiles;
     int maxnv = 0, sum_n = 0;
     int kf = 1;        // forward-DWT levels done by the tiled kernel; the rest per layer in one workgroup
+    bool rtab_ok = true;  // every transpose row fits kRtabWidth pairs (else the scanning P^T)
+    int last_slot = 1;    // scalar slot holding the state after the last enqueued solve
     int tq = 8;        // level-kf quads per tile edge of the tiled forward DWT
     size_t coarse_lds = 0;
     std::vector<double> ad;     // alpha D per (layer, level)
@@ -144,7 +159,7 @@ struct Plan {
     size_t o_fine = 0, o_coef = 0, o_xtab = 0, o_ytab = 0, o_xrng = 0, o_yrng = 0;
     size_t o_jinv = 0, o_ad = 0, o_bprev = 0, o_r = 0, o_p = 0, o_q = 0, o_y = 0, o_u = 0, o_x = 0, o_v = 0;
     size_t o_tmpA = 0, o_tmpB = 0, o_b = 0, o_probe_c = 0, o_probe_s = 0, o_partials = 0, o_scalars = 0;
-    size_t o_r2 = 0, o_q2 = 0, o_lcount = 0;
+    size_t o_r2 = 0, o_q2 = 0, o_lcount = 0, o_xrtab = 0, o_yrtab = 0;
     size_t ws_bytes = 0;
     int n_partials = 0;
 

@@ -1,27 +1,29 @@
 // HIP kernels of the FEWHA hot path for gfx950 (CDNA4, wave64).
 //
 // Every stage is bandwidth/latency bound (no dense contraction anywhere), so the kernels are
-// gather-only stencils: each output element is written by exactly one lane, nothing uses
-// atomics except the last-block-done counter of the reductions, and results are bitwise
-// reproducible run to run.
+// gather-only stencils: each output element is written by exactly one lane and results are
+// bitwise reproducible run to run.  Device-scope atomics on a shared address serialise on this
+// chip (tens of ns each), so the per-frame path uses none: reductions leave one FP64 partial
+// per workgroup and the next kernel, which needs the Alg. 2 scalars anyway, sums them itself
+// (every workgroup redundantly, in a fixed order, so all agree bit for bit).
 //
-//   k_idwt         W^T (= W^-1) of every layer, all J levels in one launch: each workgroup owns a
-//                  square output tile and rebuilds, level by level from the coarsest, only the
-//                  cone of approximation coefficients that tile depends on (LDS resident);
-//                  optionally scales coefficients by the Jacobi preconditioner on load (z = J^-1 r).
-//   k_nodes        per WFS node tile: P (bilinear ray gather from all layers through per-axis
-//                  cell tables, LGS cone included), Gamma, C_eta^-1 and Gamma^T fused through LDS
-//                  (the paper's Kernel-2 stage), or Gamma^T C s / Gamma^T mask s.
+//   k_inv          W^T (= W^-1) of every layer, all J levels in one launch: each workgroup owns
+//                  a square output tile and rebuilds, from the coarsest level down, only the cone
+//                  of coefficients that tile depends on, loaded in one batch into LDS.  Modes:
+//                  plain c | z = J^-1 r | the Alg. 2 update of the previous pass fused in front.
+//   k_nodes_m      per WFS node tile: P (bilinear ray gather from all layers through per-axis
+//                  cell tables, LGS cone included), Gamma, C_eta^-1 and Gamma^T through LDS
+//                  (the paper's Kernel-2 stage).  k_nodes: Gamma^T C s / Gamma^T mask s.
 //   k_slopes       mask Gamma P u on subaperture tiles (forward operator A).
-//   k_pt           P^T as a gather per layer node over the contiguous ranges of sensor nodes whose
-//                  cells touch it, with the very table entries the forward uses: the exact
-//                  transpose of P without atomics.
-//   k_fdwt_fine    the first kf levels of the forward transform W for every layer, on tiles of
-//                  level-kf quads with their halo staged in LDS; fused epilogues (alpha D z and the
-//                  PCG dot products, or the right-hand side's warm-restart residual update).
-//   k_fdwt_coarse  the remaining levels, one workgroup per layer, LDS resident; same epilogues; its
-//                  last workgroup forms the Alg. 2 scalars on the device.
-//   k_update       fused p, q, c, r update of Alg. 2.
+//   k_pt_tab       P^T as a gather per layer node through the transpose tables (the sensor nodes
+//                  and weights that touch each layer grid line, the very entries P uses): the
+//                  exact transpose of P without atomics.  k_pt_scan: same result by scanning
+//                  the cell tables, for geometries whose transpose rows exceed the table width.
+//   k_fwd_fine     the first kf levels of W for every layer, on tiles of level-kf quads with
+//                  their halo in LDS; epilogues: alpha D z and the PCG dot-product partials, or
+//                  the right-hand side's warm-restart residual update, or alpha D c.
+//   k_fwd_coarse   the remaining levels, one workgroup per layer, LDS resident; same epilogues.
+//   k_update_last  the last Alg. 2 update of a solve.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -75,8 +77,22 @@ __device__ __forceinline__ T project_node(const T *__restrict__ u, const Bufs<T>
     return acc;
 }
 
+// Level and orientation of Mallat position (row, col) of an n x n pyramid with J levels.
+__device__ __forceinline__ void band_at(int row, int col, int n, int log2n, int J, int &s, int &o) {
+    const int v = row > col ? row : col;
+    if (v < (n >> J)) {
+        s = J;
+        o = 0;
+    } else {
+        const int lv = 31 - __clz(v);
+        const int m = 1 << lv;
+        s = log2n - lv;
+        o = (row < m) ? 1 : ((col < m) ? 2 : 3);
+    }
+}
+
 // ---------------------------------------------------------------------------------------------
-// Reductions
+// Reductions and the Alg. 2 scalars
 // ---------------------------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -96,101 +112,91 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
     return t;
 }
 
-// Publish this block's partials at slot `slot` of each of `nrows` rows (row pitch `pitch`);
-// return true in the one block of the grid that finishes last, when every earlier write of
-// this and of previous kernels on the stream is visible.  The counter returns to zero.
-__device__ __forceinline__ bool publish_last(double *partials, int pitch, int nrows, int slot, const double *vals,
-                                             unsigned *counter) {
-    __shared__ bool last;
-    if (threadIdx.x == 0) {
-        for (int k = 0; k < nrows; ++k)
-            __hip_atomic_store(partials + (size_t)k * pitch + slot, vals[k], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        unsigned prev = atomicAdd(counter, 1u);
-        last = (prev == gridDim.x - 1);
-        if (last) {
-            __threadfence();
-            __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
-    __syncthreads();
-    return last;
-}
-
-// Sum slots [0, count) of one partial row in fixed order, cooperatively by one block.
-__device__ __forceinline__ double gather_partials(const double *partials, int pitch, int row, int count, double *sh) {
-    double v = 0.0;
-    for (int b = threadIdx.x; b < count; b += blockDim.x)
-        v += __hip_atomic_load(partials + (size_t)row * pitch + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return block_sum(v, sh);
-}
-
-// Alg. 2 scalars from the reduced (rho, mu) of pass k (thread 0 of the last block only).
-__device__ void pcg_scalars(Scalars *sc, double R, double Mu, int k, double *resnorm) {
-    sc->rho = R;
-    sc->mu = Mu;
-    if (sc->stopped) return;
-    if (!isfinite(R) || !isfinite(Mu)) {
-        sc->status = FEWHA_ERR_NONFINITE;
-        sc->stopped = 1;
-        return;
-    }
-    if (resnorm) resnorm[k] = sqrt(R);
-    if (R == 0.0) {
-        sc->stopped = 1;
-        return;
-    }
-    double beta = 0.0, den = Mu;
-    if (k > 0) {
-        beta = R / sc->rho_old;
-        den = Mu - R * beta / sc->alpha_old;
-    }
-    if (!(den > 0.0)) {
-        sc->status = FEWHA_ERR_BREAKDOWN;
-        sc->stopped = 1;
-        return;
-    }
-    const double alpha = R / den;
-    sc->alpha = alpha;
-    sc->beta = beta;
-    sc->rho_old = R;
-    sc->alpha_old = alpha;
-}
-
 __device__ __forceinline__ void reset_scalars(Scalars *sc) {
     sc->rho = sc->mu = sc->rho_old = sc->alpha = sc->alpha_old = sc->beta = 0.0;
     sc->stopped = 0;
     sc->status = FEWHA_OK;
 }
 
-// Level and orientation of Mallat position (row, col) of an n x n pyramid with J levels.
-__device__ __forceinline__ void band_at(int row, int col, int n, int log2n, int J, int &s, int &o) {
-    const int v = row > col ? row : col;
-    if (v < (n >> J)) {
-        s = J;
-        o = 0;
-    } else {
-        const int lv = 31 - __clz(v);
-        const int m = 1 << lv;
-        s = log2n - lv;
-        o = (row < m) ? 1 : ((col < m) ? 2 : 3);
+// One step of the Alg. 2 scalar recurrence for pass k from the reduced (rho, mu) and the state
+// after pass k-1:  beta = rho / rho_old, alpha = rho / (mu - rho beta / alpha_old)  (first pass:
+// beta = 0, alpha = rho / mu).  rho = 0 stops (exact solution); non-finite sums or a
+// non-positive denominator stop with a status.  Returns the state after pass k.
+__device__ Scalars alg2_step(const Scalars &prev, double R, double Mu, int k) {
+    Scalars nx = prev;
+    nx.rho = R;
+    nx.mu = Mu;
+    nx.alpha = 0.0;
+    nx.beta = 0.0;
+    if (prev.stopped) return nx;
+    if (!isfinite(R) || !isfinite(Mu)) {
+        nx.status = FEWHA_ERR_NONFINITE;
+        nx.stopped = 1;
+        return nx;
     }
+    if (R == 0.0) {
+        nx.stopped = 1;
+        return nx;
+    }
+    double beta = 0.0, den = Mu;
+    if (k > 0) {
+        beta = R / prev.rho_old;
+        den = Mu - R * beta / prev.alpha_old;
+    }
+    if (!(den > 0.0)) {
+        nx.status = FEWHA_ERR_BREAKDOWN;
+        nx.stopped = 1;
+        return nx;
+    }
+    nx.alpha = R / den;
+    nx.beta = beta;
+    nx.rho_old = R;
+    nx.alpha_old = nx.alpha;
+    return nx;
+}
+
+// Every workgroup of a consumer kernel: sum the partials of pass k in fixed order, step the
+// scalar recurrence from sc[(k-1)&1], and (workgroup 0) publish the new state to sc[k&1] and
+// sqrt(rho) to resnorm[k].  Returns (alpha, beta, stopped) to all lanes.
+struct StepOut {
+    double alpha, beta;
+    int stopped;
+};
+
+__device__ StepOut consume_pass(const double *__restrict__ partials, int nparts, Scalars *sc, int k, double *resnorm) {
+    __shared__ double sh[16];
+    __shared__ StepOut so;
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+        a += partials[i];
+        b += partials[kPartialPitch + i];
+    }
+    const double R = block_sum(a, sh);
+    const double Mu = block_sum(b, sh);
+    if (threadIdx.x == 0) {
+        const Scalars prev = sc[(k - 1) & 1];
+        const Scalars nx = alg2_step(prev, R, Mu, k);
+        so = StepOut{nx.alpha, nx.beta, nx.stopped};
+        if (blockIdx.x == 0) {
+            sc[k & 1] = nx;
+            if (resnorm && !prev.stopped && isfinite(R)) resnorm[k] = sqrt(R);
+        }
+    }
+    __syncthreads();
+    return so;
 }
 
 // ---------------------------------------------------------------------------------------------
 // W^T: multi-level inverse DWT in one launch, with the PCG update fused in front of it.
 //
-// Each workgroup owns a square output tile and rebuilds, from the coarsest level down, only the
-// cone of coefficients that tile depends on.  The whole cone (every level, every band) is
-// fetched from global memory in one batch of independent loads into LDS, so the J levels of
-// synthesis then run from LDS.  In the update mode the loads bring r_{k-1}, y_{k-1}, q_{k-2},
-// the Alg. 2 update is evaluated for every cone coefficient, the coefficients this tile owns are
-// written back (p, q, c and the new residual), and the transform runs on z = J^-1 r_k.
-// Ownership: at level s a tile owns the indices [y0 >> s, (y0 + T0) >> s) when T0 >= 2^s, else
-// index y0 >> s if y0 is a multiple of 2^s (likewise in x), a partition of every band.
+// The whole cone of a tile (every level, every band) is fetched in one batch of independent
+// loads into LDS, then the J levels of synthesis run from LDS.  In the update mode the loads
+// bring r_{k-1}, y_{k-1}, q_{k-2}; the Alg. 2 update of pass k-1 is evaluated for every cone
+// coefficient, the coefficients this tile owns are written back (p, q, c and the new residual),
+// and the transform runs on z = J^-1 r_k.  Ownership: at level s a tile owns the indices
+// [y0 >> s, (y0 + T0) >> s) when T0 >= 2^s, else index y0 >> s if y0 is a multiple of 2^s
+// (likewise in x), which partitions every band.
 // ---------------------------------------------------------------------------------------------
-
 constexpr int kInvSegMax = 3072;  // cone coefficients of a 32 x 32 tile over up to 12 levels
 
 template <typename T, int MODE>
@@ -258,9 +264,10 @@ __global__ __launch_bounds__(kBlock) void k_inv(Bufs<T> B, int J, InvArgs A, Tap
     double alpha = 0.0, beta = 0.0;
     int stopped = 0;
     if constexpr (MODE == kInvUpdate) {
-        alpha = B.sc->alpha;
-        beta = B.sc->beta;
-        stopped = B.sc->stopped;
+        const StepOut so = consume_pass(B.partials, A.nparts, B.sc, A.kprev, A.resnorm);
+        alpha = so.alpha;
+        beta = so.beta;
+        stopped = so.stopped;
     }
     const T *src = static_cast<const T *>(A.src);
     __syncthreads();
@@ -388,154 +395,60 @@ __global__ __launch_bounds__(kBlock) void k_inv(Bufs<T> B, int J, InvArgs A, Tap
     }
 }
 
-// Final Alg. 2 update of a solve (elementwise; the residual ends in the state buffer B.r).
+// Last Alg. 2 update of a solve (elementwise); the residual lands in the state buffer B.r.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_update_last(T *__restrict__ c, Bufs<T> B, int J, const T *__restrict__ rin,
-                                                        const T *__restrict__ qold, T *__restrict__ qnew, int first) {
+                                                        const T *__restrict__ qold, T *__restrict__ qnew, int first,
+                                                        int nparts, int kprev, double *resnorm) {
+    const StepOut so = consume_pass(B.partials, nparts, B.sc, kprev, resnorm);
     const Tile t = B.coef_tiles[blockIdx.x];
-    const double alpha = B.sc->alpha, beta = B.sc->beta;
-    const int stopped = B.sc->stopped;
 #pragma unroll
     for (int e = 0; e < kCoefTile / kBlock; ++e) {
         const int loc = t.b + e * kBlock + (int)threadIdx.x;
         if (loc >= t.b + t.c) break;
         const long i = t.e + loc;
         const T ri = rin[i];
-        if (stopped) {
+        if (so.stopped) {
             B.r[i] = ri;
             continue;
         }
         int s, o;
         band_at(loc >> t.g, loc & (t.f - 1), t.f, t.g, J, s, o);
         const T z = ri * B.jinv[(t.a * (J + 1) + s) * 4 + o];
-        const T p = first ? z : z + (T)beta * B.p[i];
-        const T q = first ? B.y[i] : B.y[i] + (T)beta * qold[i];
+        const T p = first ? z : z + (T)so.beta * B.p[i];
+        const T q = first ? B.y[i] : B.y[i] + (T)so.beta * qold[i];
         B.p[i] = p;
         qnew[i] = q;
-        c[i] += (T)alpha * p;
-        B.r[i] = ri - (T)alpha * q;
+        c[i] += (T)so.alpha * p;
+        B.r[i] = ri - (T)so.alpha * q;
     }
 }
 
 // ---------------------------------------------------------------------------------------------
 // Node-tile kernels (Kernel-2 stage): P, Gamma, C_eta^-1, Gamma^T.
 // ---------------------------------------------------------------------------------------------
-template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void k_nodes(const T *__restrict__ in, T *__restrict__ v, Bufs<T> B, int nl) {
+constexpr int kNodeBlock = 512;
+
+// y-part of M on one node tile: phi on the tile plus a one-node halo (one node per lane), then
+// weighted Fried slopes and Gamma^T from LDS.
+template <typename T>
+__global__ __launch_bounds__(kNodeBlock) void k_nodes_m(const T *__restrict__ u, T *__restrict__ v, Bufs<T> B,
+                                                        int nl) {
     constexpr int NT = kNodeTile, NP = NT + 2, NS = NT + 1;
     __shared__ T sPhi[NP * NP];
     __shared__ T sSx[NS * NS], sSy[NS * NS];
     const Tile t = B.node_tiles[blockIdx.x];
     const DevWfs W = B.wfs[t.a];
     const int ns = W.n_sub, nv = W.nv, i0 = t.b, j0 = t.c;
-
-    if constexpr (MODE == kModeM) {
-        for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) {
-            int a = idx / NP, b = idx - a * NP, i = i0 - 1 + a, j = j0 - 1 + b;
-            T val = 0;
-            if (i >= 0 && i <= ns && j >= 0 && j <= ns) val = project_node(in, B, t.a, nl, i, j);
-            sPhi[idx] = val;
-        }
-        __syncthreads();
-    }
-    for (int idx = threadIdx.x; idx < NS * NS; idx += blockDim.x) {
-        int a = idx / NS, b = idx - a * NS, i = i0 - 1 + a, j = j0 - 1 + b;
-        T sx = 0, sy = 0;
-        if (i >= 0 && i < ns && j >= 0 && j < ns && subap_active(W, i, j)) {
-            const T w = (MODE == kModeAdj) ? (T)1 : (T)W.inv_var;
-            if constexpr (MODE == kModeM) {
-                const T p00 = sPhi[a * NP + b], p01 = sPhi[a * NP + b + 1];
-                const T p10 = sPhi[(a + 1) * NP + b], p11 = sPhi[(a + 1) * NP + b + 1];
-                sx = w * ((T)0.5 * ((p01 - p00) + (p11 - p10)));
-                sy = w * ((T)0.5 * ((p10 - p00) + (p11 - p01)));
-            } else {
-                sx = w * in[W.s_off + (long)i * ns + j];
-                sy = w * in[W.s_off + (long)ns * ns + (long)i * ns + j];
-            }
-        }
-        sSx[idx] = sx;
-        sSy[idx] = sy;
+    if (threadIdx.x < NP * NP) {
+        const int a = threadIdx.x / NP, b = threadIdx.x - a * NP, i = i0 - 1 + a, j = j0 - 1 + b;
+        T val = 0;
+        if (i >= 0 && i <= ns && j >= 0 && j <= ns) val = project_node(u, B, t.a, nl, i, j);
+        sPhi[threadIdx.x] = val;
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < NT * NT; idx += blockDim.x) {
-        int a = idx / NT, b = idx - a * NT, i = i0 + a, j = j0 + b;
-        if (i > ns || j > ns) continue;
-        // node (i, j) is a corner of subapertures (i, j), (i, j-1), (i-1, j), (i-1, j-1)
-        const int s11 = (a + 1) * NS + (b + 1), s10 = (a + 1) * NS + b, s01 = a * NS + (b + 1), s00 = a * NS + b;
-        T val = (T)0.5 * ((-sSx[s11] - sSy[s11]) + (sSx[s10] - sSy[s10]) + (-sSx[s01] + sSy[s01]) + (sSx[s00] + sSy[s00]));
-        v[W.v_off + (long)i * nv + j] = val;
-    }
-}
-
-// P + Gamma + C_eta^-1 + Gamma^T on one node tile (the paper's Kernel-2 stage, y-part of M).
-// phi is needed on the tile plus a one-node halo.  Layers are processed in chunks: the cell
-// table entries of the chunk's rows and columns are staged in LDS, then every (node, layer)
-// bilinear gather of the chunk is issued as one batch of independent loads; the per-layer
-// contributions are summed in layer order (deterministic), then slopes, weights and Gamma^T
-// run from LDS.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_nodes_m(const T *__restrict__ u, T *__restrict__ v, Bufs<T> B, int nl) {
-    constexpr int NT = kNodeTile, NP = NT + 2, NS = NT + 1, NN = NP * NP;
-    constexpr int LMAX = 12;
-    constexpr int MAXI = (NN * LMAX + kBlock - 1) / kBlock;
-    __shared__ Ent<T> sX[LMAX * NP], sY[LMAX * NP];
-    __shared__ T sPart[LMAX * NN];
-    __shared__ T sPhi[NN];
-    __shared__ T sSx[NS * NS], sSy[NS * NS];
-    __shared__ long sOff[LMAX];
-    __shared__ int sN[LMAX];
-    const Tile t = B.node_tiles[blockIdx.x];
-    const int g = t.a, i0 = t.b, j0 = t.c;
-    const DevWfs W = B.wfs[g];
-    const int ns = W.n_sub, nv = W.nv;
-    for (int idx = threadIdx.x; idx < NN; idx += blockDim.x) sPhi[idx] = 0;
-    for (int l0 = 0; l0 < nl; l0 += LMAX) {
-        const int nc = (nl - l0) < LMAX ? (nl - l0) : LMAX;
-        for (int idx = threadIdx.x; idx < 2 * nc * NP; idx += blockDim.x) {
-            const int axis = idx / (nc * NP), rem = idx - axis * nc * NP, l = rem / NP, b = rem - l * NP;
-            int node = (axis ? i0 : j0) - 1 + b;
-            node = node < 0 ? 0 : (node > ns ? ns : node);
-            const long at = ((long)g * nl + l0 + l) * B.maxnv + node;
-            if (axis) sY[l * NP + b] = B.ytab[at];
-            else sX[l * NP + b] = B.xtab[at];
-        }
-        if (threadIdx.x < nc) {
-            sOff[threadIdx.x] = B.lay[l0 + threadIdx.x].c_off;
-            sN[threadIdx.x] = B.lay[l0 + threadIdx.x].n;
-        }
-        __syncthreads();
-        T val[MAXI];
-#pragma unroll
-        for (int c = 0; c < MAXI; ++c) {
-            const int k = c * kBlock + (int)threadIdx.x;
-            val[c] = 0;
-            if (k < nc * NN) {
-                const int l = k / NN, nd = k - l * NN, a = nd / NP, b = nd - a * NP;
-                const int i = i0 - 1 + a, j = j0 - 1 + b;
-                if (i >= 0 && i <= ns && j >= 0 && j <= ns) {
-                    const Ent<T> ex = sX[l * NP + b], ey = sY[l * NP + a];
-                    const int n = sN[l];
-                    const T *U = u + sOff[l] + (long)ey.k0 * n + ex.k0;
-                    val[c] = (ey.w0 * ex.w0) * U[0] + (ey.w0 * ex.w1) * U[1] + (ey.w1 * ex.w0) * U[n] +
-                             (ey.w1 * ex.w1) * U[n + 1];
-                }
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < MAXI; ++c) {
-            const int k = c * kBlock + (int)threadIdx.x;
-            if (k < nc * NN) sPart[k] = val[c];
-        }
-        __syncthreads();
-        for (int nd = threadIdx.x; nd < NN; nd += blockDim.x) {
-            T acc = sPhi[nd];
-            for (int l = 0; l < nc; ++l) acc += sPart[l * NN + nd];
-            sPhi[nd] = acc;
-        }
-        __syncthreads();
-    }
-    for (int idx = threadIdx.x; idx < NS * NS; idx += blockDim.x) {
-        const int a = idx / NS, b = idx - a * NS, i = i0 - 1 + a, j = j0 - 1 + b;
+    if (threadIdx.x < NS * NS) {
+        const int a = threadIdx.x / NS, b = threadIdx.x - a * NS, i = i0 - 1 + a, j = j0 - 1 + b;
         T sx = 0, sy = 0;
         if (i >= 0 && i < ns && j >= 0 && j < ns && subap_active(W, i, j)) {
             const T w = (T)W.inv_var;
@@ -543,6 +456,37 @@ __global__ __launch_bounds__(kBlock) void k_nodes_m(const T *__restrict__ u, T *
             const T p10 = sPhi[(a + 1) * NP + b], p11 = sPhi[(a + 1) * NP + b + 1];
             sx = w * ((T)0.5 * ((p01 - p00) + (p11 - p10)));
             sy = w * ((T)0.5 * ((p10 - p00) + (p11 - p01)));
+        }
+        sSx[threadIdx.x] = sx;
+        sSy[threadIdx.x] = sy;
+    }
+    __syncthreads();
+    if (threadIdx.x < NT * NT) {
+        const int a = threadIdx.x / NT, b = threadIdx.x - a * NT, i = i0 + a, j = j0 + b;
+        if (i <= ns && j <= ns) {
+            // node (i, j) is a corner of subapertures (i, j), (i, j-1), (i-1, j), (i-1, j-1)
+            const int s11 = (a + 1) * NS + (b + 1), s10 = (a + 1) * NS + b, s01 = a * NS + (b + 1), s00 = a * NS + b;
+            v[W.v_off + (long)i * nv + j] = (T)0.5 * ((-sSx[s11] - sSy[s11]) + (sSx[s10] - sSy[s10]) +
+                                                      (-sSx[s01] + sSy[s01]) + (sSx[s00] + sSy[s00]));
+        }
+    }
+}
+
+// Gamma^T C s (MODE kModeRhs) or Gamma^T mask s (kModeAdj) on one node tile.
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_nodes(const T *__restrict__ in, T *__restrict__ v, Bufs<T> B) {
+    constexpr int NT = kNodeTile, NS = NT + 1;
+    __shared__ T sSx[NS * NS], sSy[NS * NS];
+    const Tile t = B.node_tiles[blockIdx.x];
+    const DevWfs W = B.wfs[t.a];
+    const int ns = W.n_sub, nv = W.nv, i0 = t.b, j0 = t.c;
+    for (int idx = threadIdx.x; idx < NS * NS; idx += blockDim.x) {
+        const int a = idx / NS, b = idx - a * NS, i = i0 - 1 + a, j = j0 - 1 + b;
+        T sx = 0, sy = 0;
+        if (i >= 0 && i < ns && j >= 0 && j < ns && subap_active(W, i, j)) {
+            const T w = (MODE == kModeAdj) ? (T)1 : (T)W.inv_var;
+            sx = w * in[W.s_off + (long)i * ns + j];
+            sy = w * in[W.s_off + (long)ns * ns + (long)i * ns + j];
         }
         sSx[idx] = sx;
         sSy[idx] = sy;
@@ -552,235 +496,138 @@ __global__ __launch_bounds__(kBlock) void k_nodes_m(const T *__restrict__ u, T *
         const int a = idx / NT, b = idx - a * NT, i = i0 + a, j = j0 + b;
         if (i > ns || j > ns) continue;
         const int s11 = (a + 1) * NS + (b + 1), s10 = (a + 1) * NS + b, s01 = a * NS + (b + 1), s00 = a * NS + b;
-        const T val = (T)0.5 * ((-sSx[s11] - sSy[s11]) + (sSx[s10] - sSy[s10]) + (-sSx[s01] + sSy[s01]) +
-                                (sSx[s00] + sSy[s00]));
-        v[W.v_off + (long)i * nv + j] = val;
+        v[W.v_off + (long)i * nv + j] = (T)0.5 * ((-sSx[s11] - sSy[s11]) + (sSx[s10] - sSy[s10]) +
+                                                  (-sSx[s01] + sSy[s01]) + (sSx[s00] + sSy[s00]));
     }
 }
 
 // s = mask Gamma P u on subaperture tiles.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_slopes(const T *__restrict__ u, T *__restrict__ s, Bufs<T> B, int nl) {
+__global__ __launch_bounds__(kNodeBlock) void k_slopes(const T *__restrict__ u, T *__restrict__ s, Bufs<T> B, int nl) {
     constexpr int NT = kNodeTile, NP = NT + 1;
     __shared__ T sPhi[NP * NP];
     const Tile t = B.sub_tiles[blockIdx.x];
     const DevWfs W = B.wfs[t.a];
     const int ns = W.n_sub, i0 = t.b, j0 = t.c;
-    for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) {
-        int a = idx / NP, b = idx - a * NP, i = i0 + a, j = j0 + b;
+    if (threadIdx.x < NP * NP) {
+        const int a = threadIdx.x / NP, b = threadIdx.x - a * NP, i = i0 + a, j = j0 + b;
         T val = 0;
         if (i <= ns && j <= ns) val = project_node(u, B, t.a, nl, i, j);
-        sPhi[idx] = val;
+        sPhi[threadIdx.x] = val;
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < NT * NT; idx += blockDim.x) {
-        int a = idx / NT, b = idx - a * NT, i = i0 + a, j = j0 + b;
-        if (i >= ns || j >= ns) continue;
-        T sx = 0, sy = 0;
-        if (subap_active(W, i, j)) {
-            const T p00 = sPhi[a * NP + b], p01 = sPhi[a * NP + b + 1];
-            const T p10 = sPhi[(a + 1) * NP + b], p11 = sPhi[(a + 1) * NP + b + 1];
-            sx = (T)0.5 * ((p01 - p00) + (p11 - p10));
-            sy = (T)0.5 * ((p10 - p00) + (p11 - p01));
+    if (threadIdx.x < NT * NT) {
+        const int a = threadIdx.x / NT, b = threadIdx.x - a * NT, i = i0 + a, j = j0 + b;
+        if (i < ns && j < ns) {
+            T sx = 0, sy = 0;
+            if (subap_active(W, i, j)) {
+                const T p00 = sPhi[a * NP + b], p01 = sPhi[a * NP + b + 1];
+                const T p10 = sPhi[(a + 1) * NP + b], p11 = sPhi[(a + 1) * NP + b + 1];
+                sx = (T)0.5 * ((p01 - p00) + (p11 - p10));
+                sy = (T)0.5 * ((p10 - p00) + (p11 - p01));
+            }
+            s[W.s_off + (long)i * ns + j] = sx;
+            s[W.s_off + (long)ns * ns + (long)i * ns + j] = sy;
         }
-        s[W.s_off + (long)i * ns + j] = sx;
-        s[W.s_off + (long)ns * ns + (long)i * ns + j] = sy;
     }
 }
 
 // ---------------------------------------------------------------------------------------------
-// P^T on a tile of layer nodes, as a gather through the transpose ranges of the cell tables.
-// For each sensor the node ranges of the tile's rows and columns are staged in LDS, then the
-// sub-block of v_g they span and its table entries arrive in one batch of independent loads;
-// each lane sums its node's contributions (sensor, then row, then column order) from LDS.  A
-// sensor whose sub-block does not fit the LDS budget is gathered straight from global memory.
+// P^T
 // ---------------------------------------------------------------------------------------------
+// Through the transpose tables: for each sensor, the tile rows' and columns' (node, weight)
+// lists are staged in LDS; each lane then gathers the v values of its node's non-zero pairs,
+// four sensors' loads in flight at a time.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pt(const T *__restrict__ v, T *__restrict__ x, Bufs<T> B, int nl,
-                                               int nw) {
-    constexpr int NT = kNodeTile, GMAX = kBlock / NT, VMAX = sizeof(T) == 4 ? 4096 : 2048, EMAX = 512, MAXI = 16;
-    static_assert(GMAX == 16, "16 lanes per sensor");
-    __shared__ Range sRy[GMAX * NT], sRx[GMAX * NT];
-    __shared__ T sV[VMAX];
-    __shared__ Ent<T> sEy[EMAX], sEx[EMAX];
-    __shared__ int sGeo[GMAX][4];  // i0, ni, j0, nj of each sensor's sub-block (ni = 0: empty)
+__global__ __launch_bounds__(kBlock) void k_pt_tab(const T *__restrict__ v, T *__restrict__ x, Bufs<T> B, int nl,
+                                                   int nw) {
+    constexpr int NT = kNodeTile, RW = kRtabWidth, GMAX = 16;
+    __shared__ RtabEnt<T> sRy[GMAX * NT * RW], sRx[GMAX * NT * RW];
+    __shared__ long sVoff[GMAX];
+    __shared__ int sNv[GMAX];
     const Tile t = B.lay_tiles[blockIdx.x];
-    const int l = t.a, k0 = t.b, q0 = t.c, n = t.f, roff = t.h;
-    const int k = k0 + (int)(threadIdx.x / NT), q = q0 + (int)(threadIdx.x % NT);
-    const bool valid = k < n && q < n;
-    const int lane = threadIdx.x & (NT - 1), grp = threadIdx.x / NT;
+    const int k0 = t.b, q0 = t.c, n = t.f, roff = t.h;
+    const int rk = (int)(threadIdx.x / NT), rq = (int)(threadIdx.x % NT);
+    const bool valid = k0 + rk < n && q0 + rq < n;
     T acc = 0;
     for (int gb = 0; gb < nw; gb += GMAX) {
         const int gc = (nw - gb) < GMAX ? (nw - gb) : GMAX;
-        // 16 lanes per sensor: each loads the range of one tile row and one tile column, then the
-        // group reduces them to the sub-block of sensor nodes the whole tile needs
-        {
-            Range ry{1, 0}, rx{1, 0};
-            if (grp < gc) {
-                const long base = (long)(gb + grp) * B.sum_n + roff;
-                if (k0 + lane < n) ry = B.yrng[base + k0 + lane];
-                if (q0 + lane < n) rx = B.xrng[base + q0 + lane];
-            }
-            sRy[grp * NT + lane] = ry;
-            sRx[grp * NT + lane] = rx;
-            int i0 = ry.lo <= ry.hi ? ry.lo : (1 << 30), i1 = ry.lo <= ry.hi ? ry.hi : -1;
-            int j0 = rx.lo <= rx.hi ? rx.lo : (1 << 30), j1 = rx.lo <= rx.hi ? rx.hi : -1;
-#pragma unroll
-            for (int m = 1; m < NT; m <<= 1) {
-                i0 = min(i0, __shfl_xor(i0, m, NT));
-                i1 = max(i1, __shfl_xor(i1, m, NT));
-                j0 = min(j0, __shfl_xor(j0, m, NT));
-                j1 = max(j1, __shfl_xor(j1, m, NT));
-            }
-            if (lane == 0) {
-                const bool ne = i1 >= i0 && j1 >= j0;
-                sGeo[grp][0] = i0;
-                sGeo[grp][1] = ne ? i1 - i0 + 1 : 0;
-                sGeo[grp][2] = j0;
-                sGeo[grp][3] = ne ? j1 - j0 + 1 : 0;
-            }
+        for (int idx = threadIdx.x; idx < 2 * gc * NT * RW; idx += blockDim.x) {
+            const int axis = idx / (gc * NT * RW), rem = idx - axis * gc * NT * RW;
+            const int g = rem / (NT * RW), rr = rem - g * NT * RW, line = rr / RW, e = rr - line * RW;
+            const int gl = (axis ? k0 : q0) + line;
+            RtabEnt<T> en{0, (T)0};
+            if (gl < n) en = (axis ? B.yrtab : B.xrtab)[((long)(gb + g) * B.sum_n + roff + gl) * RW + e];
+            (axis ? sRy : sRx)[rem] = en;
         }
-        __syncthreads();
-        // staging plan (uniform, in registers): sensors in order while the LDS budget lasts
-        int I0[GMAX], NI[GMAX], J0[GMAX], NJ[GMAX], VO[GMAX], EYO[GMAX], EXO[GMAX], CUM[GMAX + 1];
-        {
-            int vo = 0, eyo = 0, exo = 0, cum = 0;
-#pragma unroll
-            for (int g = 0; g < GMAX; ++g) {
-                I0[g] = sGeo[g][0];
-                J0[g] = sGeo[g][2];
-                const int ni = g < gc ? sGeo[g][1] : 0, nj = g < gc ? sGeo[g][3] : 0;
-                const bool ok = ni > 0 && vo + ni * nj <= VMAX && eyo + ni <= EMAX && exo + nj <= EMAX;
-                NI[g] = ok ? ni : (ni > 0 ? -1 : 0);  // -1: not staged, gather from global memory
-                NJ[g] = ok ? nj : 0;
-                VO[g] = vo;
-                EYO[g] = eyo;
-                EXO[g] = exo;
-                CUM[g] = cum;
-                if (ok) {
-                    vo += ni * nj;
-                    eyo += ni;
-                    exo += nj;
-                    cum += ni * nj + ni + nj;
-                }
-            }
-            CUM[GMAX] = cum;
-        }
-        const int total = CUM[GMAX];
-        for (int base = 0; base < total; base += MAXI * kBlock) {
-            T vv[MAXI], w0[MAXI], w1[MAXI];
-            int k0e[MAXI], dst[MAXI], kind[MAXI];
-#pragma unroll
-            for (int c = 0; c < MAXI; ++c) {
-                const int kk = base + c * kBlock + (int)threadIdx.x;
-                kind[c] = -1;
-                if (kk >= total) continue;
-                int g = 0;
-#pragma unroll
-                for (int gg = 1; gg < GMAX; ++gg)
-                    if (kk >= CUM[gg]) g = gg;
-                int i0 = 0, j0 = 0, ni = 0, nj = 0, vo = 0, eyo = 0, exo = 0, cm = 0;
-#pragma unroll
-                for (int gg = 0; gg < GMAX; ++gg)
-                    if (gg == g) {
-                        i0 = I0[gg];
-                        j0 = J0[gg];
-                        ni = NI[gg];
-                        nj = NJ[gg];
-                        vo = VO[gg];
-                        eyo = EYO[gg];
-                        exo = EXO[gg];
-                        cm = CUM[gg];
-                    }
-                int rem = kk - cm;
-                const int sg = gb + g;
-                const long tb = ((long)sg * nl + l) * B.maxnv;
-                if (rem < ni * nj) {
-                    const int a = rem / nj, b = rem - a * nj;
-                    const DevWfs &W = B.wfs[sg];
-                    vv[c] = v[W.v_off + (long)(i0 + a) * W.nv + j0 + b];
-                    dst[c] = vo + rem;
-                    kind[c] = 0;
-                } else {
-                    rem -= ni * nj;
-                    const bool isy = rem < ni;
-                    if (!isy) rem -= ni;
-                    const Ent<T> e = isy ? B.ytab[tb + i0 + rem] : B.xtab[tb + j0 + rem];
-                    k0e[c] = e.k0;
-                    w0[c] = e.w0;
-                    w1[c] = e.w1;
-                    dst[c] = (isy ? eyo : exo) + rem;
-                    kind[c] = isy ? 1 : 2;
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < MAXI; ++c) {
-                if (kind[c] == 0) sV[dst[c]] = vv[c];
-                else if (kind[c] > 0) {
-                    Ent<T> &e = (kind[c] == 1) ? sEy[dst[c]] : sEx[dst[c]];
-                    e.k0 = k0e[c];
-                    e.w0 = w0[c];
-                    e.w1 = w1[c];
-                }
-            }
+        if (threadIdx.x < gc) {
+            sVoff[threadIdx.x] = B.wfs[gb + threadIdx.x].v_off;
+            sNv[threadIdx.x] = B.wfs[gb + threadIdx.x].nv;
         }
         __syncthreads();
         if (valid) {
+            for (int g4 = 0; g4 < gc; g4 += 4) {
+                T part[4][RW * RW];
 #pragma unroll
-            for (int g = 0; g < GMAX; ++g) {
-                const Range ry = sRy[g * NT + (k - k0)], rx = sRx[g * NT + (q - q0)];
-                if (g >= gc || ry.lo > ry.hi || rx.lo > rx.hi) continue;
-                if (NI[g] > 0) {
-                    const T *V = sV + VO[g];
-                    for (int i = ry.lo; i <= ry.hi; ++i) {
-                        const Ent<T> ey = sEy[EYO[g] + i - I0[g]];
-                        const T wy = (ey.k0 == k) ? ey.w0 : ey.w1;
-                        for (int j = rx.lo; j <= rx.hi; ++j) {
-                            const Ent<T> ex = sEx[EXO[g] + j - J0[g]];
-                            const T wx = (ex.k0 == q) ? ex.w0 : ex.w1;
-                            acc += (wy * wx) * V[(i - I0[g]) * NJ[g] + (j - J0[g])];
+                for (int gg = 0; gg < 4; ++gg) {
+                    const int g = g4 + gg;
+#pragma unroll
+                    for (int a = 0; a < RW; ++a)
+#pragma unroll
+                        for (int b = 0; b < RW; ++b) {
+                            part[gg][a * RW + b] = 0;
+                            if (g < gc) {
+                                const RtabEnt<T> ey = sRy[(g * NT + rk) * RW + a], ex = sRx[(g * NT + rq) * RW + b];
+                                if (ey.w != (T)0 && ex.w != (T)0)
+                                    part[gg][a * RW + b] = (ey.w * ex.w) * v[sVoff[g] + (long)ey.idx * sNv[g] + ex.idx];
+                            }
                         }
-                    }
-                } else {  // did not fit the LDS budget: straight from global memory
-                    const int sg = gb + g;
-                    const DevWfs W = B.wfs[sg];
-                    const Ent<T> *xt = B.xtab + ((long)sg * nl + l) * B.maxnv;
-                    const Ent<T> *yt = B.ytab + ((long)sg * nl + l) * B.maxnv;
-                    for (int i = ry.lo; i <= ry.hi; ++i) {
-                        const Ent<T> ey = yt[i];
-                        const T wy = (ey.k0 == k) ? ey.w0 : ey.w1;
-                        for (int j = rx.lo; j <= rx.hi; ++j) {
-                            const Ent<T> ex = xt[j];
-                            const T wx = (ex.k0 == q) ? ex.w0 : ex.w1;
-                            acc += (wy * wx) * v[W.v_off + (long)i * W.nv + j];
-                        }
-                    }
                 }
+#pragma unroll
+                for (int gg = 0; gg < 4; ++gg)
+#pragma unroll
+                    for (int e = 0; e < RW * RW; ++e) acc += part[gg][e];
             }
         }
         __syncthreads();
     }
-    if (valid) x[(long)t.e + (long)k * n + q] = acc;
+    if (valid) x[(long)t.e + (long)(k0 + rk) * n + q0 + rq] = acc;
+}
+
+// By scanning the cell tables over each layer node's contiguous node ranges (any geometry).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pt_scan(const T *__restrict__ v, T *__restrict__ x, Bufs<T> B, int nl,
+                                                    int nw) {
+    constexpr int NT = kNodeTile;
+    const Tile t = B.lay_tiles[blockIdx.x];
+    const int l = t.a, k = t.b + (int)(threadIdx.x / NT), q = t.c + (int)(threadIdx.x % NT), n = t.f;
+    if (k >= n || q >= n) return;
+    T acc = 0;
+    for (int g = 0; g < nw; ++g) {
+        const Range rx = B.xrng[(long)g * B.sum_n + t.h + q];
+        const Range ry = B.yrng[(long)g * B.sum_n + t.h + k];
+        if (rx.lo > rx.hi || ry.lo > ry.hi) continue;
+        const Ent<T> *xt = B.xtab + ((long)g * nl + l) * B.maxnv;
+        const Ent<T> *yt = B.ytab + ((long)g * nl + l) * B.maxnv;
+        const DevWfs W = B.wfs[g];
+        const T *vg = v + W.v_off;
+        for (int i = ry.lo; i <= ry.hi; ++i) {
+            const Ent<T> ey = yt[i];
+            const T wy = (ey.k0 == k) ? ey.w0 : ey.w1;
+            const T *row = vg + (long)i * W.nv;
+            for (int j = rx.lo; j <= rx.hi; ++j) {
+                const Ent<T> ex = xt[j];
+                const T wx = (ex.k0 == q) ? ex.w0 : ex.w1;
+                acc += (wy * wx) * row[j];
+            }
+        }
+    }
+    x[(long)t.e + (long)k * n + q] = acc;
 }
 
 // ---------------------------------------------------------------------------------------------
-// Forward transform W in one launch, with fused epilogues.
-//
-// Fine part: a workgroup owns a TQ x TQ tile of level-KF approximation coefficients; it stages
-// the input region with its halo (periodic wrap) and the epilogue operands of every coefficient
-// it owns in one batch of independent loads, then runs levels 1..KF from LDS.  Coarse part: the
-// last tile of a layer to finish (per-layer counter) runs levels KF+1..J of that layer in LDS.
-// The last layer to finish combines the FP64 partial sums of every workgroup, in a fixed order,
-// into the Alg. 2 scalars.
+// Forward transform W with fused epilogues.
 // ---------------------------------------------------------------------------------------------
-
-// Region geometry of the fine part: a tile of TQ x TQ level-KF approximation coefficients needs
-// LL_s on a run of len(s) = TQ 2^(KF-s) + 4 (2^(KF-s) - 1) indices (s = 0 is the input).
-template <int KF, int TQ>
-struct FineGeom {
-    static constexpr int len(int s) { return TQ * (1 << (KF - s)) + 4 * ((1 << (KF - s)) - 1); }
-};
-
 // Deliver one coefficient w of W x (operands e0, e1 prefetched); accumulate PCG dot partials.
 template <typename T, int EPI>
 __device__ __forceinline__ void deliver(const Bufs<T> &B, const FwdArgs &E, long i, T w, T ad, T ji, T e0, T e1,
@@ -822,29 +669,36 @@ __device__ __forceinline__ long band_index(long coff, int n, int s, int o, int r
     return coff + (long)(r + ((o == 2 || o == 3) ? m : 0)) * n + q + ((o == 1 || o == 3) ? m : 0);
 }
 
+// Region geometry of the fine part: a tile of TQ x TQ level-KF approximation coefficients needs
+// LL_s on a run of len(s) = TQ 2^(KF-s) + 4 (2^(KF-s) - 1) indices (s = 0 is the input).
+template <int KF, int TQ>
+struct FineGeom {
+    static constexpr int len(int s) { return TQ * (1 << (KF - s)) + 4 * ((1 << (KF - s)) - 1); }
+};
+
+// Levels 1..KF on a tile of TQ x TQ level-KF approximation coefficients: the input region with
+// its halo (periodic wrap) and the epilogue operands of every owned coefficient arrive in one
+// batch of independent loads, then the levels run from LDS.
 template <typename T, int KF, int TQ, int EPI>
-__global__ __launch_bounds__(kBlock) void k_fwd(const T *__restrict__ x, Bufs<T> B, int J, int nl, FwdArgs E,
-                                                Taps<T> tp) {
+__global__ __launch_bounds__(kBlock) void k_fwd_fine(const T *__restrict__ x, Bufs<T> B, int J, FwdArgs E,
+                                                     Taps<T> tp) {
     using G = FineGeom<KF, TQ>;
     constexpr int L0 = G::len(0), L1 = G::len(1), EMAX = 1024;
     constexpr int NE = (EPI == kEpiRhs) ? 2 : ((EPI == kEpiPlain) ? 0 : 1);
-    constexpr int FINE = L0 * L0 + (KF >= 2 ? L1 * L1 : 0) + NE * EMAX;
-    constexpr int COARSE = 64 * 64 + 32 * 32;
-    constexpr int SMEM = FINE > COARSE ? FINE : COARSE;
     constexpr int MAXI = 8;
-    __shared__ T sm[SMEM];
+    __shared__ T sA[L0 * L0];
+    __shared__ T sB[KF >= 2 ? L1 * L1 : 1];
+    __shared__ T sE0[NE >= 1 ? EMAX : 1], sE1[NE >= 2 ? EMAX : 1];
     __shared__ T sAd[kMaxJ + 1], sJi[(kMaxJ + 1) * 4];
     __shared__ double sh[kBlock / 64];
-    __shared__ int sLast;
-    T *sA = sm, *sB = sm + L0 * L0, *sE0 = sB + (KF >= 2 ? L1 * L1 : 0), *sE1 = sE0 + EMAX;
 
     if constexpr (EPI == kEpiRhs) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) reset_scalars(B.sc);
+        if (blockIdx.x == 0 && threadIdx.x == 0) reset_scalars(B.sc + 1);  // state "before pass 0"
     }
     const Tile t = B.fine_tiles[blockIdx.x];
-    const int l = t.a, qy = t.b, qx = t.c, tq = t.d, n = t.f, ntiles = t.h;
+    const int l = t.a, qy = t.b, qx = t.c, tq = t.d, n = t.f;
     const long coff = t.e;
-    if (threadIdx.x <= J) sAd[threadIdx.x] = (EPI == kEpiPrior || EPI == kEpiPcg) ? B.ad[l * (J + 1) + threadIdx.x] : (T)0;
+    if ((EPI == kEpiPrior || EPI == kEpiPcg) && threadIdx.x <= J) sAd[threadIdx.x] = B.ad[l * (J + 1) + threadIdx.x];
     if (EPI == kEpiPcg && threadIdx.x < (J + 1) * 4) sJi[threadIdx.x] = B.jinv[l * (J + 1) * 4 + threadIdx.x];
 
     int len[KF + 1], own[KF + 1], eoff[KF + 2];
@@ -857,8 +711,6 @@ __global__ __launch_bounds__(kBlock) void k_fwd(const T *__restrict__ x, Bufs<T>
     }
     const int ne = eoff[KF + 1] + (KF == J ? own[KF] * own[KF] : 0);
     const int oy = qy << KF, ox = qx << KF, nmask = n - 1;
-
-    // ---- one batch of loads: input region + epilogue operands of the owned coefficients ----
     {
         const int nreg = len[0] * len[0], tot = nreg + (NE ? ne : 0);
         for (int base = 0; base < tot; base += MAXI * kBlock) {
@@ -876,7 +728,9 @@ __global__ __launch_bounds__(kBlock) void k_fwd(const T *__restrict__ x, Bufs<T>
                 } else {
                     const int e = k - nreg;
                     int s = 1;
-                    while (s < KF && e >= eoff[s + 1]) ++s;
+#pragma unroll
+                    for (int ss = 2; ss <= KF; ++ss)
+                        if (e >= eoff[ss]) s = ss;
                     int o, r, q;
                     if (e >= eoff[KF + 1]) {  // LL at level KF == J
                         s = KF;
@@ -891,21 +745,21 @@ __global__ __launch_bounds__(kBlock) void k_fwd(const T *__restrict__ x, Bufs<T>
                         r = rr / own[s];
                         q = rr - r * own[s];
                     }
-                    const long gi = band_index(coff, n, s, o, (qy << (KF - s)) + r, (qx << (KF - s)) + q);
                     T a0 = 0, a1 = 0;
-                    prefetch<T, EPI>(B, E, gi, a0, a1);
+                    prefetch<T, EPI>(B, E, band_index(coff, n, s, o, (qy << (KF - s)) + r, (qx << (KF - s)) + q), a0,
+                                     a1);
                     v0[c] = a0;
                     v1[c] = a1;
-                    d[c] = SMEM + e;  // marks an epilogue slot
+                    d[c] = L0 * L0 + e;
                 }
             }
 #pragma unroll
             for (int c = 0; c < MAXI; ++c) {
                 if (d[c] < 0) continue;
-                if (d[c] < SMEM) sA[d[c]] = v0[c];
+                if (d[c] < L0 * L0) sA[d[c]] = v0[c];
                 else {
-                    sE0[d[c] - SMEM] = v0[c];
-                    if (NE == 2) sE1[d[c] - SMEM] = v1[c];
+                    if constexpr (NE >= 1) sE0[d[c] - L0 * L0] = v0[c];
+                    if constexpr (NE >= 2) sE1[d[c] - L0 * L0] = v1[c];
                 }
             }
         }
@@ -920,7 +774,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd(const T *__restrict__ x, Bufs<T>
         const int sp = (s & 1) ? L0 : L1, dp = (s & 1) ? L1 : L0;
         const int ln = len[s], ow = own[s];
         const int by = qy << (KF - s), bx = qx << (KF - s);
-        const T ad = sAd[s];
+        const T ad = (EPI == kEpiPrior || EPI == kEpiPcg) ? sAd[s] : (T)0;
         for (int idx = threadIdx.x; idx < ln * ln; idx += blockDim.x) {
             const int r = idx / ln, q = idx - r * ln;
             T ll = 0, lh = 0, hl = 0, hh = 0;
@@ -945,14 +799,18 @@ __global__ __launch_bounds__(kBlock) void k_fwd(const T *__restrict__ x, Bufs<T>
 #pragma unroll
                 for (int o = 1; o <= 3; ++o) {
                     const int ei = e + (o - 1) * b2;
-                    const T e0 = NE ? sE0[ei] : (T)0, e1 = NE == 2 ? sE1[ei] : (T)0;
+                    T e0 = 0, e1 = 0;
+                    if constexpr (NE >= 1) e0 = sE0[ei];
+                    if constexpr (NE >= 2) e1 = sE1[ei];
                     deliver<T, EPI>(B, E, band_index(coff, n, s, o, by + r, bx + q), w[o - 1], ad,
                                     EPI == kEpiPcg ? sJi[s * 4 + o] : (T)0, e0, e1, rho, mu);
                 }
                 if (s == KF) {
                     if (KF == J) {
                         const int ei = eoff[KF + 1] + r * ow + q;
-                        const T e0 = NE ? sE0[ei] : (T)0, e1 = NE == 2 ? sE1[ei] : (T)0;
+                        T e0 = 0, e1 = 0;
+                        if constexpr (NE >= 1) e0 = sE0[ei];
+                        if constexpr (NE >= 2) e1 = sE1[ei];
                         deliver<T, EPI>(B, E, band_index(coff, n, s, 0, by + r, bx + q), ll, ad,
                                         EPI == kEpiPcg ? sJi[s * 4] : (T)0, e0, e1, rho, mu);
                     } else {
@@ -963,96 +821,79 @@ __global__ __launch_bounds__(kBlock) void k_fwd(const T *__restrict__ x, Bufs<T>
         }
         __syncthreads();
     }
-
-    double vals[2];
     if constexpr (EPI == kEpiPcg) {
-        vals[0] = block_sum(rho, sh);
-        vals[1] = block_sum(mu, sh);
-    }
-    const int nfine = gridDim.x;
-    if (KF == J) {
-        if constexpr (EPI == kEpiPcg) {
-            if (!publish_last(B.partials, kPartialPitch, 2, blockIdx.x, vals, &B.sc->counter)) return;
-            const double R = gather_partials(B.partials, kPartialPitch, 0, nfine, sh);
-            const double Mu = gather_partials(B.partials, kPartialPitch, 1, nfine, sh);
-            if (threadIdx.x == 0) pcg_scalars(B.sc, R, Mu, E.k, E.resnorm);
+        const double a = block_sum(rho, sh), b = block_sum(mu, sh);
+        if (threadIdx.x == 0) {
+            B.partials[blockIdx.x] = a;
+            B.partials[kPartialPitch + blockIdx.x] = b;
         }
-        return;
     }
-    // ---- hand the layer's remaining levels to its last tile ----
-    if (threadIdx.x == 0) {
-        if constexpr (EPI == kEpiPcg) {
-            __hip_atomic_store(B.partials + blockIdx.x, vals[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(B.partials + kPartialPitch + blockIdx.x, vals[1], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __threadfence();
-        const unsigned prev = atomicAdd(B.lcount + l, 1u);
-        sLast = (prev == (unsigned)(ntiles - 1));
-        if (sLast) __hip_atomic_store(B.lcount + l, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    if (!sLast) return;
-    __threadfence();
+}
 
-    const int m0 = n >> KF;
-    T *cs = sm, *cd = sm + m0 * m0;
-    for (int idx = threadIdx.x; idx < m0 * m0; idx += blockDim.x) cs[idx] = B.tmpA[(coff >> (2 * KF)) + idx];
+// Levels KF+1..J of one layer per workgroup: the level-KF approximation (from tmpA) and the
+// epilogue operands of the layer's top-left m0 x m0 block (exactly the coefficients of these
+// levels) arrive in one batch of loads, then the levels run from LDS (dynamic shared memory:
+// (1 + 1/4 + NE) m0^2 values).
+template <typename T, int EPI>
+__global__ __launch_bounds__(512) void k_fwd_coarse(Bufs<T> B, int J, int KF, FwdArgs E, Taps<T> tp, int nfine) {
+    extern __shared__ char smem_raw[];
+    constexpr int NE = (EPI == kEpiRhs) ? 2 : ((EPI == kEpiPlain) ? 0 : 1);
+    __shared__ T sAd[kMaxJ + 1], sJi[(kMaxJ + 1) * 4];
+    __shared__ double sh[512 / 64];
+    const int l = blockIdx.x;
+    const DevLayer L = B.lay[l];
+    const int n = L.n, m0 = n >> KF;
+    const long coff = L.c_off;
+    T *cs = reinterpret_cast<T *>(smem_raw), *cd = cs + m0 * m0, *e0s = cd + (m0 * m0) / 4 + 1, *e1s = e0s + m0 * m0;
+    if ((EPI == kEpiPrior || EPI == kEpiPcg) && threadIdx.x <= J) sAd[threadIdx.x] = B.ad[l * (J + 1) + threadIdx.x];
+    if (EPI == kEpiPcg && threadIdx.x < (J + 1) * 4) sJi[threadIdx.x] = B.jinv[l * (J + 1) * 4 + threadIdx.x];
+    for (int idx = threadIdx.x; idx < m0 * m0; idx += blockDim.x) {
+        const int r = idx / m0, q = idx - r * m0;
+        T a0 = 0, a1 = 0;
+        prefetch<T, EPI>(B, E, coff + (long)r * n + q, a0, a1);
+        cs[idx] = B.tmpA[(coff >> (2 * KF)) + idx];
+        if constexpr (NE >= 1) e0s[idx] = a0;
+        if constexpr (NE >= 2) e1s[idx] = a1;
+    }
     __syncthreads();
-    rho = 0.0;
-    mu = 0.0;
+    double rho = 0.0, mu = 0.0;
     for (int s = KF + 1; s <= J; ++s) {
         const int mi = n >> (s - 1), h = mi >> 1, msk = mi - 1, nq = h * h;
-        const T ad = sAd[s];
-        for (int base = 0; base < nq; base += 4 * kBlock) {
-            T e0[4][4], e1[4][4];
+        const T ad = (EPI == kEpiPrior || EPI == kEpiPcg) ? sAd[s] : (T)0;
+        for (int qi = threadIdx.x; qi < nq; qi += blockDim.x) {
+            const int r = qi / h, q = qi - r * h;
+            int cols[6];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int qi = base + c * kBlock + (int)threadIdx.x;
-                if (qi >= nq || NE == 0) continue;
-                const int r = qi / h, q = qi - r * h;
+            for (int b = 0; b < 6; ++b) cols[b] = (2 * q + b) & msk;
+            T ll = 0, lh = 0, hl = 0, hh = 0;
 #pragma unroll
-                for (int o = 0; o < 4; ++o) {
-                    if (o == 0 && s != J) continue;
-                    prefetch<T, EPI>(B, E, band_index(coff, n, s, o, r, q), e0[c][o], e1[c][o]);
+            for (int a = 0; a < 6; ++a) {
+                const T *row = cs + ((2 * r + a) & msk) * mi;
+                T ax = 0, dx = 0;
+#pragma unroll
+                for (int b = 0; b < 6; ++b) {
+                    const T xv = row[cols[b]];
+                    ax += tp.h[b] * xv;
+                    dx += tp.g[b] * xv;
                 }
+                ll += tp.h[a] * ax;
+                lh += tp.g[a] * ax;
+                hl += tp.h[a] * dx;
+                hh += tp.g[a] * dx;
             }
+            const T w[4] = {ll, hl, lh, hh};
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int qi = base + c * kBlock + (int)threadIdx.x;
-                if (qi >= nq) continue;
-                const int r = qi / h, q = qi - r * h;
-                int cols[6];
-#pragma unroll
-                for (int b = 0; b < 6; ++b) cols[b] = (2 * q + b) & msk;
-                T ll = 0, lh = 0, hl = 0, hh = 0;
-#pragma unroll
-                for (int a = 0; a < 6; ++a) {
-                    const T *row = cs + ((2 * r + a) & msk) * mi;
-                    T ax = 0, dx = 0;
-#pragma unroll
-                    for (int b = 0; b < 6; ++b) {
-                        const T xv = row[cols[b]];
-                        ax += tp.h[b] * xv;
-                        dx += tp.g[b] * xv;
-                    }
-                    ll += tp.h[a] * ax;
-                    lh += tp.g[a] * ax;
-                    hl += tp.h[a] * dx;
-                    hh += tp.g[a] * dx;
-                }
-                const T w[4] = {ll, hl, lh, hh};
-#pragma unroll
-                for (int o = 1; o <= 3; ++o)
-                    deliver<T, EPI>(B, E, band_index(coff, n, s, o, r, q), w[o], ad,
-                                    EPI == kEpiPcg ? sJi[s * 4 + o] : (T)0, NE ? e0[c][o] : (T)0,
-                                    NE == 2 ? e1[c][o] : (T)0, rho, mu);
-                if (s == J)
-                    deliver<T, EPI>(B, E, band_index(coff, n, s, 0, r, q), ll, ad, EPI == kEpiPcg ? sJi[s * 4] : (T)0,
-                                    NE ? e0[c][0] : (T)0, NE == 2 ? e1[c][0] : (T)0, rho, mu);
-                else
-                    cd[r * h + q] = ll;
+            for (int o = 0; o <= 3; ++o) {
+                if (o == 0 && s != J) continue;
+                const int lr = r + ((o == 2 || o == 3) ? h : 0), lc = q + ((o == 1 || o == 3) ? h : 0);
+                const int li = lr * m0 + lc;
+                T e0 = 0, e1 = 0;
+                if constexpr (NE >= 1) e0 = e0s[li];
+                if constexpr (NE >= 2) e1 = e1s[li];
+                deliver<T, EPI>(B, E, coff + (long)lr * n + lc, w[o], ad, EPI == kEpiPcg ? sJi[s * 4 + o] : (T)0, e0,
+                                e1, rho, mu);
             }
+            if (s != J) cd[r * h + q] = ll;
         }
         __syncthreads();
         T *tmp = cs;
@@ -1060,29 +901,18 @@ __global__ __launch_bounds__(kBlock) void k_fwd(const T *__restrict__ x, Bufs<T>
         cd = tmp;
     }
     if constexpr (EPI == kEpiPcg) {
-        vals[0] = block_sum(rho, sh);
-        vals[1] = block_sum(mu, sh);
+        const double a = block_sum(rho, sh), b = block_sum(mu, sh);
         if (threadIdx.x == 0) {
-            __hip_atomic_store(B.partials + nfine + l, vals[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(B.partials + kPartialPitch + nfine + l, vals[1], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            __threadfence();
-            const unsigned prev = atomicAdd(&B.sc->counter, 1u);
-            sLast = (prev == (unsigned)(nl - 1));
-            if (sLast) {
-                __threadfence();
-                __hip_atomic_store(&B.sc->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
+            B.partials[nfine + l] = a;
+            B.partials[kPartialPitch + nfine + l] = b;
         }
-        __syncthreads();
-        if (!sLast) return;
-        const double R = gather_partials(B.partials, kPartialPitch, 0, nfine + nl, sh);
-        const double Mu = gather_partials(B.partials, kPartialPitch, 1, nfine + nl, sh);
-        if (threadIdx.x == 0) pcg_scalars(B.sc, R, Mu, E.k, E.resnorm);
     }
 }
 
-// Weighted squared norm sum_k C_eta^-1_k s_k^2 (preconditioner probes); result -> sc->rho.
+// ---------------------------------------------------------------------------------------------
+// Setup and small kernels
+// ---------------------------------------------------------------------------------------------
+// Weighted squared norm sum_k C_eta^-1_k s_k^2 (preconditioner probes): one partial per block.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_wnorm(const T *__restrict__ s, Bufs<T> B, int nw) {
     __shared__ double sh[kBlock / 64];
@@ -1097,10 +927,17 @@ __global__ __launch_bounds__(kBlock) void k_wnorm(const T *__restrict__ s, Bufs<
             acc += W.inv_var * (sx * sx + sy * sy);
         }
     }
-    double v = block_sum(acc, sh);
-    if (!publish_last(B.partials, kPartialPitch, 1, blockIdx.x, &v, &B.sc->counter)) return;
-    const double tot = gather_partials(B.partials, kPartialPitch, 0, gridDim.x, sh);
-    if (threadIdx.x == 0) B.sc->rho = tot;
+    const double v = block_sum(acc, sh);
+    if (threadIdx.x == 0) B.partials[blockIdx.x] = v;
+}
+
+// Sum of n partials in fixed order -> sc[2].rho (single workgroup).
+__global__ __launch_bounds__(kBlock) void k_sum_partials(const double *__restrict__ partials, int n, Scalars *sc) {
+    __shared__ double sh[kBlock / 64];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) a += partials[i];
+    const double t = block_sum(a, sh);
+    if (threadIdx.x == 0) sc[2].rho = t;
 }
 
 // Fitting (bilinear on-axis sampling of the layers at the actuators of their DM) + gain.
@@ -1150,14 +987,17 @@ __global__ __launch_bounds__(kBlock) void k_build_tabs(Ent<T> *xtab, Ent<T> *yta
     ytab[idx] = ey;
 }
 
-// Transpose ranges: for grid line q of layer l, the sensor nodes j with cell k0_j in {q-1, q}
-// (k0_j is non-decreasing in j, so they are contiguous).
+// Transpose of the cell tables: for grid line q of layer l, the sensor nodes j whose cell
+// touches it (k0_j in {q-1, q}; contiguous since k0_j is non-decreasing in j) as a range, and as
+// a zero-padded list of (j, weight) pairs of width kRtabWidth; lines with more pairs than that
+// set over[g] (the plan then uses the scanning transpose).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_build_ranges(Range *xrng, Range *yrng, const Ent<T> *__restrict__ xtab,
+__global__ __launch_bounds__(kBlock) void k_build_ranges(Range *xrng, Range *yrng, RtabEnt<T> *xrt, RtabEnt<T> *yrt,
+                                                         const Ent<T> *__restrict__ xtab,
                                                          const Ent<T> *__restrict__ ytab,
                                                          const DevWfs *__restrict__ wfs,
                                                          const DevLayer *__restrict__ lays, int nw, int nl, int maxnv,
-                                                         int sum_n) {
+                                                         int sum_n, int *over) {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)nw * sum_n) return;
     const int g = (int)(idx / sum_n), line = (int)(idx % sum_n);
@@ -1166,14 +1006,19 @@ __global__ __launch_bounds__(kBlock) void k_build_ranges(Range *xrng, Range *yrn
     const int q = line - lays[l].r_off, nv = wfs[g].nv;
     for (int axis = 0; axis < 2; ++axis) {
         const Ent<T> *tab = (axis == 0 ? xtab : ytab) + ((long)g * nl + l) * maxnv;
-        int lo = nv, hi = -1;
+        RtabEnt<T> *rt = (axis == 0 ? xrt : yrt) + idx * kRtabWidth;
+        int lo = nv, hi = -1, cnt = 0;
         for (int j = 0; j < nv; ++j) {
-            const int k0 = tab[j].k0;
-            if (k0 == q || k0 + 1 == q) {
+            const Ent<T> e = tab[j];
+            if (e.k0 == q || e.k0 + 1 == q) {
                 lo = j < lo ? j : lo;
                 hi = j;
+                if (cnt < kRtabWidth) rt[cnt] = RtabEnt<T>{j, e.k0 == q ? e.w0 : e.w1};
+                ++cnt;
             }
         }
+        for (int c = cnt; c < kRtabWidth; ++c) rt[c] = RtabEnt<T>{0, (T)0};
+        if (cnt > kRtabWidth) over[g] = 1;  // idempotent flag, no read-modify-write needed
         Range r{lo, hi};
         if (hi < 0) r = Range{1, 0};
         (axis == 0 ? xrng : yrng)[idx] = r;
@@ -1191,9 +1036,9 @@ __global__ __launch_bounds__(kBlock) void k_copy(T *__restrict__ dst, const T *_
 }
 
 __global__ void k_init_scalars(Scalars *sc) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        reset_scalars(sc);
-        sc->counter = 0u;
+    if (threadIdx.x < 3 && blockIdx.x == 0) {
+        reset_scalars(sc + threadIdx.x);
+        sc[threadIdx.x].counter = 0u;
     }
 }
 
@@ -1225,6 +1070,11 @@ Taps<T> make_taps() {
 }
 
 template <typename T>
+int Ops<T>::nparts() const {
+    return (int)P.fine_tiles.size() + (P.kf < P.J ? P.nl : 0);
+}
+
+template <typename T>
 int Ops<T>::idwt(const T *c, T *out) const {
     InvArgs A{};
     A.src = c;
@@ -1243,18 +1093,31 @@ int Ops<T>::idwt_first(const T *r, T *out) const {
 }
 
 template <typename T>
-int Ops<T>::idwt_update(const T *r_old, const T *q_old, T *q_new, T *r_new, T *c, bool first_pass, T *out) const {
+int Ops<T>::idwt_update(const T *r_old, const T *q_old, T *q_new, T *r_new, T *c, int kprev, double *resnorm,
+                        T *out) const {
     InvArgs A{};
     A.src = r_old;
     A.out = out;
     A.yv = B.y;
-    A.qold = first_pass ? B.y : q_old;  // never read on the first pass
+    A.qold = kprev == 0 ? B.y : q_old;  // never read after the first pass
     A.qnew = q_new;
     A.rnew = r_new;
     A.c = c;
-    A.first_pass = first_pass ? 1 : 0;
+    A.first_pass = kprev == 0 ? 1 : 0;
+    A.kprev = kprev;
+    A.nparts = nparts();
+    A.resnorm = resnorm;
     k_inv<T, kInvUpdate><<<(int)P.idwt_tiles.size(), kBlock, 0, st>>>(B, P.J, A, make_taps<T>());
     return check();
+}
+
+template <typename T>
+template <int EPI>
+size_t Ops<T>::coarse_lds() const {
+    constexpr int NE = (EPI == kEpiRhs) ? 2 : ((EPI == kEpiPlain) ? 0 : 1);
+    size_t m0 = 0;
+    for (auto &L : P.lay) m0 = (size_t)(L.n >> P.kf) > m0 ? (size_t)(L.n >> P.kf) : m0;
+    return (m0 * m0 + m0 * m0 / 4 + 1 + NE * m0 * m0) * sizeof(T);
 }
 
 template <typename T>
@@ -1263,11 +1126,30 @@ int Ops<T>::fwd(const T *x, const FwdArgs &E) const {
     const int nf = (int)P.fine_tiles.size();
     const Taps<T> tp = make_taps<T>();
     switch (P.kf) {
-        case 1: k_fwd<T, 1, 16, EPI><<<nf, kBlock, 0, st>>>(x, B, P.J, P.nl, E, tp); break;
-        case 2: k_fwd<T, 2, 8, EPI><<<nf, kBlock, 0, st>>>(x, B, P.J, P.nl, E, tp); break;
-        default: k_fwd<T, 3, 4, EPI><<<nf, kBlock, 0, st>>>(x, B, P.J, P.nl, E, tp); break;
+        case 1: k_fwd_fine<T, 1, 16, EPI><<<nf, kBlock, 0, st>>>(x, B, P.J, E, tp); break;
+        case 2: k_fwd_fine<T, 2, 8, EPI><<<nf, kBlock, 0, st>>>(x, B, P.J, E, tp); break;
+        default: k_fwd_fine<T, 3, 4, EPI><<<nf, kBlock, 0, st>>>(x, B, P.J, E, tp); break;
     }
-    return check();
+    if (int e = check()) return e;
+    if (P.kf < P.J) {
+        k_fwd_coarse<T, EPI><<<P.nl, 512, coarse_lds<EPI>(), st>>>(B, P.J, P.kf, E, tp, nf);
+        if (int e = check()) return e;
+    }
+    return FEWHA_OK;
+}
+
+template <typename T>
+int Ops<T>::prepare() const {
+    // the per-layer coarse transform may need more than the default 64 KiB of dynamic LDS
+    const void *fns[4] = {(const void *)k_fwd_coarse<T, kEpiPlain>, (const void *)k_fwd_coarse<T, kEpiPrior>,
+                          (const void *)k_fwd_coarse<T, kEpiPcg>, (const void *)k_fwd_coarse<T, kEpiRhs>};
+    const size_t need[4] = {coarse_lds<kEpiPlain>(), coarse_lds<kEpiPrior>(), coarse_lds<kEpiPcg>(),
+                            coarse_lds<kEpiRhs>()};
+    for (int i = 0; i < 4; ++i)
+        if (need[i] > 48 * 1024 &&
+            hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)need[i]) != hipSuccess)
+            return FEWHA_ERR_UNSUPPORTED;
+    return FEWHA_OK;
 }
 
 template <typename T>
@@ -1286,12 +1168,10 @@ int Ops<T>::fdwt_prior(const T *x, const T *cin, T *out) const {
 }
 
 template <typename T>
-int Ops<T>::fdwt_pcg(const T *x, const T *rk, int k, double *resnorm) const {
+int Ops<T>::fdwt_pcg(const T *x, const T *rk) const {
     FwdArgs E{};
     E.out = B.y;
     E.rk = rk;
-    E.k = k;
-    E.resnorm = resnorm;
     return fwd<kEpiPcg>(x, E);
 }
 
@@ -1306,28 +1186,29 @@ int Ops<T>::fdwt_rhs(const T *x, T *c, bool cold) const {
 template <typename T>
 int Ops<T>::nodes(const T *in, T *v, int mode) const {
     const int tiles = (int)P.node_tiles.size();
-    if (mode == kModeM) k_nodes_m<T><<<tiles, kBlock, 0, st>>>(in, v, B, P.nl);
-    else if (mode == kModeRhs) k_nodes<T, kModeRhs><<<tiles, kBlock, 0, st>>>(in, v, B, P.nl);
-    else k_nodes<T, kModeAdj><<<tiles, kBlock, 0, st>>>(in, v, B, P.nl);
+    if (mode == kModeM) k_nodes_m<T><<<tiles, kNodeBlock, 0, st>>>(in, v, B, P.nl);
+    else if (mode == kModeRhs) k_nodes<T, kModeRhs><<<tiles, kBlock, 0, st>>>(in, v, B);
+    else k_nodes<T, kModeAdj><<<tiles, kBlock, 0, st>>>(in, v, B);
     return check();
 }
 
 template <typename T>
 int Ops<T>::slopes(const T *u, T *s) const {
-    k_slopes<T><<<(int)P.sub_tiles.size(), kBlock, 0, st>>>(u, s, B, P.nl);
+    k_slopes<T><<<(int)P.sub_tiles.size(), kNodeBlock, 0, st>>>(u, s, B, P.nl);
     return check();
 }
 
 template <typename T>
 int Ops<T>::pt(const T *v, T *x) const {
-    k_pt<T><<<(int)P.lay_tiles.size(), kBlock, 0, st>>>(v, x, B, P.nl, P.nw);
+    if (P.rtab_ok) k_pt_tab<T><<<(int)P.lay_tiles.size(), kBlock, 0, st>>>(v, x, B, P.nl, P.nw);
+    else k_pt_scan<T><<<(int)P.lay_tiles.size(), kBlock, 0, st>>>(v, x, B, P.nl, P.nw);
     return check();
 }
 
 template <typename T>
-int Ops<T>::update_last(T *c, const T *r_in, const T *q_old, T *q_new, bool first_pass) const {
-    k_update_last<T><<<(int)P.coef_tiles.size(), kBlock, 0, st>>>(c, B, P.J, r_in, first_pass ? B.y : q_old, q_new,
-                                                                    first_pass ? 1 : 0);
+int Ops<T>::update_last(T *c, const T *r_in, const T *q_old, T *q_new, int kprev, double *resnorm) const {
+    k_update_last<T><<<(int)P.coef_tiles.size(), kBlock, 0, st>>>(c, B, P.J, r_in, kprev == 0 ? B.y : q_old, q_new,
+                                                                    kprev == 0 ? 1 : 0, nparts(), kprev, resnorm);
     return check();
 }
 
@@ -1336,8 +1217,10 @@ int Ops<T>::wnorm(const T *s) const {
     long mx = 0;
     for (auto &w : P.dwfs) mx = mx > (long)w.n_sub * w.n_sub ? mx : (long)w.n_sub * w.n_sub;
     int g = grid_for(mx);
-    if (g > P.n_partials) g = P.n_partials;
+    if (g > kPartialPitch) g = kPartialPitch;
     k_wnorm<T><<<g, kBlock, 0, st>>>(s, B, P.nw);
+    if (int e = check()) return e;
+    k_sum_partials<<<1, kBlock, 0, st>>>(B.partials, g, B.sc);
     return check();
 }
 
@@ -1348,15 +1231,15 @@ int Ops<T>::fit(const T *u, const T *a_prev, T *a, double gain) const {
 }
 
 template <typename T>
-int Ops<T>::build_tables() const {
+int Ops<T>::build_tables(int *over) const {
     const long ne = (long)P.nw * P.nl * P.maxnv;
     k_build_tabs<T><<<(int)((ne + kBlock - 1) / kBlock), kBlock, 0, st>>>(
         const_cast<Ent<T> *>(B.xtab), const_cast<Ent<T> *>(B.ytab), B.wfs, B.proj, B.lay, P.nw, P.nl, P.maxnv);
     if (int e = check()) return e;
     const long nr = (long)P.nw * P.sum_n;
     k_build_ranges<T><<<(int)((nr + kBlock - 1) / kBlock), kBlock, 0, st>>>(
-        const_cast<Range *>(B.xrng), const_cast<Range *>(B.yrng), B.xtab, B.ytab, B.wfs, B.lay, P.nw, P.nl, P.maxnv,
-        P.sum_n);
+        const_cast<Range *>(B.xrng), const_cast<Range *>(B.yrng), const_cast<RtabEnt<T> *>(B.xrtab),
+        const_cast<RtabEnt<T> *>(B.yrtab), B.xtab, B.ytab, B.wfs, B.lay, P.nw, P.nl, P.maxnv, P.sum_n, over);
     return check();
 }
 

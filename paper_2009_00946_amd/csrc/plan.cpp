@@ -278,14 +278,16 @@ int plan_create(const fewha_config *cfg, Plan **out) {
     P->o_probe_s = take(E * P->n_slopes);
     P->o_r2 = take(E * N);
     P->o_q2 = take(E * N);
-    P->o_lcount = take(sizeof(unsigned) * P->nl);
+    P->o_lcount = take(sizeof(int) * P->nw);
+    P->o_xrtab = take((P->prec == FEWHA_FP64 ? 16 : 8) * size_t(kRtabWidth) * P->nw * P->sum_n);
+    P->o_yrtab = take((P->prec == FEWHA_FP64 ? 16 : 8) * size_t(kRtabWidth) * P->nw * P->sum_n);
     P->n_partials = kPartialPitch;
     if (P->fine_tiles.size() + size_t(P->nl) > size_t(kPartialPitch)) {
         delete P;
         return FEWHA_ERR_UNSUPPORTED;
     }
     P->o_partials = take(sizeof(double) * 2 * P->n_partials);
-    P->o_scalars = take(sizeof(Scalars));
+    P->o_scalars = take(3 * sizeof(Scalars));
     P->ws_bytes = o;
     *out = P;
     return FEWHA_OK;

@@ -227,3 +227,50 @@ def test_zero_slopes_and_nonfinite_status():
     P.pcg_solve(bad, c, 3, warm=False)
     assert P.last_status() == -7
     assert torch.count_nonzero(c).item() == 0
+
+
+def test_graph_replay_matches_eager():
+    """A frame captured in a HIP graph and replayed gives bitwise the eager chain's result,
+    replay after replay (host synchronisation between replays)."""
+    P = plan("t1_mixed", "fp32")
+    O = oracle("t1_mixed")
+    cfg = synth.load_config("t1_mixed")
+    S = [dev(P, _slopes(O, cfg, f)) for f in range(4)]
+    n_iter = cfg["n_iter"]
+    # eager reference chain
+    c_e = P.zeros(P.n_coef)
+    a_e = P.zeros(P.n_act)
+    P.pcg_solve(S[0], c_e, n_iter, warm=False)
+    ref = []
+    for f in range(1, 4):
+        P.pcg_solve(S[f], c_e, n_iter, warm=True)
+        P.fit_dm(c_e, a_e, 0.5, out=a_e)
+        ref.append((host(c_e).copy(), host(a_e).copy()))
+    # graph chain from the same start
+    c_g = P.zeros(P.n_coef)
+    a_g = P.zeros(P.n_act)
+    P.pcg_solve(S[0], c_g, n_iter, warm=False)
+    torch.cuda.synchronize()
+    graphs = []
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    saved = (c_g.clone(), a_g.clone()) + P.state_get()
+    torch.cuda.synchronize()
+    for f in range(1, 4):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            P.pcg_solve(S[f], c_g, n_iter, warm=True)
+            P.fit_dm(c_g, a_g, 0.5, out=a_g)
+        graphs.append(g)
+    torch.cuda.synchronize()
+    # capture does not execute: restore the start state, then replay
+    c_g.copy_(saved[0])
+    a_g.copy_(saved[1])
+    P.state_set(saved[2], saved[3])
+    torch.cuda.synchronize()
+    for f in range(3):
+        graphs[f].replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(c_g), ref[f][0]), f
+        assert np.array_equal(host(a_g), ref[f][1]), f
+    assert P.last_status() == 0
