@@ -197,31 +197,37 @@ __device__ StepOut consume_pass(const double *__restrict__ partials, int nparts,
 // [y0 >> s, (y0 + T0) >> s) when T0 >= 2^s, else index y0 >> s if y0 is a multiple of 2^s
 // (likewise in x), which partitions every band.
 // ---------------------------------------------------------------------------------------------
-constexpr int kInvSegMax = 3072;  // cone coefficients of a 32 x 32 tile over up to 12 levels
+constexpr int kInvBlock = 512;
+constexpr int kInvSegMax = 4096;  // cone of a 32 x 32 tile, rows padded to power-of-two pitches
+
+// ceil(log2(v)) for 1 <= v <= 2^30
+__device__ __forceinline__ int clog2(int v) { return v <= 1 ? 0 : 32 - __clz(v - 1); }
 
 template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void k_inv(Bufs<T> B, int J, InvArgs A, Taps<T> tp) {
+__global__ __launch_bounds__(kInvBlock) void k_inv(Bufs<T> B, int J, InvArgs A, Taps<T> tp) {
     constexpr int TILE = kIdwtTile;
-    constexpr int R = TILE / 2 + 2;
-    constexpr int MAXI = (kInvSegMax + kBlock - 1) / kBlock;
+    constexpr int MAXI = kInvSegMax / kInvBlock;
     __shared__ T sSeg[kInvSegMax];
-    __shared__ T sL0[R * R], sL1[R * R];
-    __shared__ T sAX[TILE * R], sDX[TILE * R];
-    __shared__ int shLoY[kMaxJ + 1], shLoX[kMaxJ + 1], shLnY[kMaxJ + 1], shLnX[kMaxJ + 1], shSeg[kMaxJ + 2];
+    __shared__ T sL0[(TILE / 2 + 2) * TILE], sL1[(TILE / 2 + 2) * TILE];  // level-1 rows x pitch 32
+    __shared__ T sAX[TILE * TILE], sDX[TILE * TILE];
+    __shared__ int shLoY[kMaxJ + 1], shLoX[kMaxJ + 1], shLnY[kMaxJ + 1], shLnX[kMaxJ + 1], shLp[kMaxJ + 1];
+    __shared__ int shSeg[kMaxJ + 2];
     __shared__ T sJinv[(kMaxJ + 1) * 4];
 
     const Tile t = B.idwt_tiles[blockIdx.x];
     const int l = t.a, y0 = t.b, x0 = t.c, T0 = t.d, n = t.f;
     const long coff = t.e;
-    // Cone bounds per level, computed by every lane in registers (uniform values): the item
-    // decode below then needs no LDS round trips.
-    int loY[kMaxJ + 1], loX[kMaxJ + 1], lnY[kMaxJ + 1], lnX[kMaxJ + 1], seg[kMaxJ + 2];
+    // Cone bounds per level, computed by every lane in registers (uniform values).  Each band
+    // region is stored with rows padded to a power-of-two pitch, so decoding an item needs only
+    // compares and shifts.
+    int loY[kMaxJ + 1], loX[kMaxJ + 1], lnY[kMaxJ + 1], lnX[kMaxJ + 1], lp[kMaxJ + 1], seg[kMaxJ + 2];
     {
         int ly = y0, hy = y0 + T0 - 1, lx = x0, hx = x0 + T0 - 1, off = 0;
         loY[0] = ly;
         loX[0] = lx;
         lnY[0] = T0;
         lnX[0] = T0;
+        lp[0] = clog2(T0);
         seg[0] = 0;
 #pragma unroll
         for (int s = 1; s <= kMaxJ; ++s) {
@@ -233,21 +239,20 @@ __global__ __launch_bounds__(kBlock) void k_inv(Bufs<T> B, int J, InvArgs A, Tap
             loX[s] = lx;
             lnY[s] = hy - ly + 1;
             lnX[s] = hx - lx + 1;
+            lp[s] = clog2(lnX[s]);
             seg[s] = off;
-            if (s <= J) off += 3 * lnY[s] * lnX[s];
+            if (s <= J) off += 3 * (lnY[s] << lp[s]);
         }
         seg[kMaxJ + 1] = off;  // the coarsest LL starts here
     }
-    int lnYJ = 0, lnXJ = 0, loYJ = 0, loXJ = 0;
+    int lnYJ = 0, lpJ = 0;
 #pragma unroll
     for (int s = 1; s <= kMaxJ; ++s)
         if (s == J) {
             lnYJ = lnY[s];
-            lnXJ = lnX[s];
-            loYJ = loY[s];
-            loXJ = loX[s];
+            lpJ = lp[s];
         }
-    const int llOff = seg[kMaxJ + 1], total = llOff + lnYJ * lnXJ;
+    const int llOff = seg[kMaxJ + 1], total = llOff + (lnYJ << lpJ);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int s = 0; s <= kMaxJ; ++s) {
@@ -255,6 +260,7 @@ __global__ __launch_bounds__(kBlock) void k_inv(Bufs<T> B, int J, InvArgs A, Tap
             shLoX[s] = loX[s];
             shLnY[s] = lnY[s];
             shLnX[s] = lnX[s];
+            shLp[s] = lp[s];
             shSeg[s] = seg[s];
         }
         shSeg[kMaxJ + 1] = llOff;
@@ -269,42 +275,57 @@ __global__ __launch_bounds__(kBlock) void k_inv(Bufs<T> B, int J, InvArgs A, Tap
         beta = so.beta;
         stopped = so.stopped;
     }
-    const T *src = static_cast<const T *>(A.src);
+    const T *__restrict__ src = static_cast<const T *>(A.src);
+    const T *__restrict__ yin = static_cast<const T *>(A.yv);
+    const T *__restrict__ qin = static_cast<const T *>(A.qold);
+    T *__restrict__ pio = B.p;
+    T *__restrict__ cio = static_cast<T *>(A.c);
     __syncthreads();
     // ---- one batch of independent loads: the whole cone (plus owned-only operands) ----
-    for (int base = 0; base < total; base += MAXI * kBlock) {
+    for (int base = 0; base < total; base += MAXI * kInvBlock) {
         long gi[MAXI];
-        int li[MAXI], bnd[MAXI];
+        int bnd[MAXI];
         bool own[MAXI];
         T rv[MAXI], yv[MAXI], qv[MAXI], pv[MAXI], cv[MAXI];
 #pragma unroll
         for (int c = 0; c < MAXI; ++c) {
-            const int k = base + c * kBlock + (int)threadIdx.x;
+            const int k = base + c * kInvBlock + (int)threadIdx.x;
             gi[c] = -1;
             own[c] = false;
             if (k >= total) continue;
-            // segment of item k: a detail band of level s, or the coarsest LL
-            int s = J, o = 0, ly = loYJ, lx = loXJ, nxs = lnXJ, rem = k - llOff;
+            // level (compare chain over uniform offsets), band, row, column (shifts)
+            int s = J, o = 0, ly = 0, lx = 0, nxs = 1, lps = 0, rem = k - llOff;
 #pragma unroll
             for (int ss = 1; ss <= kMaxJ; ++ss) {
-                const int sz = lnY[ss] * lnX[ss];
-                if (ss <= J && k >= seg[ss] && k < seg[ss] + 3 * sz) {
-                    s = ss;
+                if (ss <= J && k >= seg[ss] && k < seg[ss + 1 <= kMaxJ ? ss + 1 : kMaxJ + 1]) s = ss;
+            }
+#pragma unroll
+            for (int ss = 1; ss <= kMaxJ; ++ss)
+                if (ss == s) {
                     ly = loY[ss];
                     lx = loX[ss];
                     nxs = lnX[ss];
-                    rem = k - seg[ss];
-                    o = 1 + rem / sz;
-                    rem -= (o - 1) * sz;
+                    lps = lp[ss];
                 }
+            if (k < llOff) {
+                int lny = 0, sg = 0;
+#pragma unroll
+                for (int ss = 1; ss <= kMaxJ; ++ss)
+                    if (ss == s) {
+                        lny = lnY[ss];
+                        sg = seg[ss];
+                    }
+                const int bsz = lny << lps, kk = k - sg;
+                o = 1 + (kk >= bsz) + (kk >= 2 * bsz);
+                rem = kk - (o - 1) * bsz;
             }
-            const int r = rem / nxs, q = rem - r * nxs;
+            const int r = rem >> lps, q = rem & ((1 << lps) - 1);
+            if (q >= nxs) continue;  // row padding
             const int m = n >> s, msk = m - 1;
             const int uy = ly + r, ux = lx + q;
             const int gr = uy & msk, gc = ux & msk;
             const int row = gr + ((o == 2 || o == 3) ? m : 0), col = gc + ((o == 1 || o == 3) ? m : 0);
             gi[c] = coff + (long)row * n + col;
-            li[c] = k;
             bnd[c] = s * 4 + o;
             if constexpr (MODE == kInvUpdate) {
                 const int ts = T0 >> s, msk2 = (1 << s) - 1;
@@ -314,11 +335,11 @@ __global__ __launch_bounds__(kBlock) void k_inv(Bufs<T> B, int J, InvArgs A, Tap
             }
             rv[c] = src[gi[c]];
             if constexpr (MODE == kInvUpdate) {
-                yv[c] = static_cast<const T *>(A.yv)[gi[c]];
-                qv[c] = A.first_pass ? (T)0 : static_cast<const T *>(A.qold)[gi[c]];
+                yv[c] = yin[gi[c]];
+                qv[c] = A.first_pass ? (T)0 : qin[gi[c]];
                 if (own[c]) {
-                    pv[c] = A.first_pass ? (T)0 : B.p[gi[c]];
-                    cv[c] = static_cast<T *>(A.c)[gi[c]];
+                    pv[c] = A.first_pass ? (T)0 : pio[gi[c]];
+                    cv[c] = cio[gi[c]];
                 }
             }
         }
@@ -337,60 +358,63 @@ __global__ __launch_bounds__(kBlock) void k_inv(Bufs<T> B, int J, InvArgs A, Tap
                     rn = rv[c] - (T)alpha * qn;
                     if (own[c]) {
                         const T pn = A.first_pass ? zo : zo + (T)beta * pv[c];
-                        B.p[gi[c]] = pn;
+                        pio[gi[c]] = pn;
                         static_cast<T *>(A.qnew)[gi[c]] = qn;
-                        static_cast<T *>(A.c)[gi[c]] = cv[c] + (T)alpha * pn;
+                        cio[gi[c]] = cv[c] + (T)alpha * pn;
                     }
                 }
                 if (own[c]) static_cast<T *>(A.rnew)[gi[c]] = rn;
                 val = rn * ji;
             }
-            sSeg[li[c]] = val;
+            sSeg[base + c * kInvBlock + (int)threadIdx.x] = val;
         }
     }
     __syncthreads();
 
-    // ---- synthesis from the coarsest level, all in LDS ----
+    // ---- synthesis from the coarsest level, all in LDS (power-of-two row pitches) ----
     const T *LL = sSeg + llOff;
-    int llp = lnXJ;
+    int llp = lpJ;
     T *NX = sL0;
-    T *outp = static_cast<T *>(A.out);
+    T *__restrict__ outp = static_cast<T *>(A.out);
     for (int s = J; s >= 1; --s) {
         const int ny = shLnY[s - 1], nxk = shLnX[s], nx = shLnX[s - 1];
         const int oy = shLoY[s - 1], ky = shLoY[s], ox = shLoX[s - 1], kx = shLoX[s];
-        const int bsz = shLnY[s] * shLnX[s], bp = shLnX[s];
+        const int bp = shLp[s], op = shLp[s - 1];
+        const int bsz = shLnY[s] << bp;
         const T *HL = sSeg + shSeg[s], *LH = HL + bsz, *HH = LH + bsz;
         // undo the y analysis: (LL, x-low/y-high) -> x-low rows, (x-high/y-low, HH) -> x-high rows
-        for (int idx = threadIdx.x; idx < ny * nxk; idx += blockDim.x) {
-            const int r = idx / nxk, q = idx - r * nxk;
+        for (int idx = threadIdx.x; idx < (ny << bp); idx += blockDim.x) {
+            const int r = idx >> bp, q = idx & ((1 << bp) - 1);
+            if (q >= nxk) continue;
             const int y = oy + r, p = y & 1, kb = (y >> 1) - ky;
             T a = 0, d = 0;
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 const int rr = kb - j;
-                a += tp.h[p + 2 * j] * LL[rr * llp + q] + tp.g[p + 2 * j] * LH[rr * bp + q];
-                d += tp.h[p + 2 * j] * HL[rr * bp + q] + tp.g[p + 2 * j] * HH[rr * bp + q];
+                a += tp.h[p + 2 * j] * LL[(rr << llp) + q] + tp.g[p + 2 * j] * LH[(rr << bp) + q];
+                d += tp.h[p + 2 * j] * HL[(rr << bp) + q] + tp.g[p + 2 * j] * HH[(rr << bp) + q];
             }
-            sAX[r * R + q] = a;
-            sDX[r * R + q] = d;
+            sAX[idx] = a;
+            sDX[idx] = d;
         }
         __syncthreads();
         // undo the x analysis
-        for (int idx = threadIdx.x; idx < ny * nx; idx += blockDim.x) {
-            const int r = idx / nx, q = idx - r * nx;
+        for (int idx = threadIdx.x; idx < (ny << op); idx += blockDim.x) {
+            const int r = idx >> op, q = idx & ((1 << op) - 1);
+            if (q >= nx) continue;
             const int x = ox + q, p = x & 1, kb = (x >> 1) - kx;
             T v = 0;
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                const int at = r * R + kb - j;
+                const int at = (r << bp) + kb - j;
                 v += tp.h[p + 2 * j] * sAX[at] + tp.g[p + 2 * j] * sDX[at];
             }
-            if (s > 1) NX[r * R + q] = v;
+            if (s > 1) NX[idx] = v;
             else outp[coff + (long)(oy + r) * n + ox + q] = v;
         }
         __syncthreads();
         LL = NX;
-        llp = R;
+        llp = op;
         NX = (NX == sL0) ? sL1 : sL0;
     }
 }
@@ -400,27 +424,44 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_update_last(T *__restrict__ c, Bufs<T> B, int J, const T *__restrict__ rin,
                                                         const T *__restrict__ qold, T *__restrict__ qnew, int first,
                                                         int nparts, int kprev, double *resnorm) {
-    const StepOut so = consume_pass(B.partials, nparts, B.sc, kprev, resnorm);
+    constexpr int E = kCoefTile / kBlock;
+    __shared__ T sJ[(kMaxJ + 1) * 4];
     const Tile t = B.coef_tiles[blockIdx.x];
+    if (threadIdx.x < (J + 1) * 4) sJ[threadIdx.x] = B.jinv[t.a * (J + 1) * 4 + threadIdx.x];
+    const StepOut so = consume_pass(B.partials, nparts, B.sc, kprev, resnorm);
+    T *__restrict__ pp = B.p;
+    T *__restrict__ rr = B.r;
+    const T *__restrict__ yy = B.y;
+    T rv[E], pv[E], yv[E], qv[E], cv[E];
 #pragma unroll
-    for (int e = 0; e < kCoefTile / kBlock; ++e) {
+    for (int e = 0; e < E; ++e) {
         const int loc = t.b + e * kBlock + (int)threadIdx.x;
-        if (loc >= t.b + t.c) break;
+        if (loc >= t.b + t.c) continue;
         const long i = t.e + loc;
-        const T ri = rin[i];
+        rv[e] = rin[i];
+        yv[e] = yy[i];
+        cv[e] = c[i];
+        pv[e] = first ? (T)0 : pp[i];
+        qv[e] = first ? (T)0 : qold[i];
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int loc = t.b + e * kBlock + (int)threadIdx.x;
+        if (loc >= t.b + t.c) continue;
+        const long i = t.e + loc;
         if (so.stopped) {
-            B.r[i] = ri;
+            rr[i] = rv[e];
             continue;
         }
         int s, o;
         band_at(loc >> t.g, loc & (t.f - 1), t.f, t.g, J, s, o);
-        const T z = ri * B.jinv[(t.a * (J + 1) + s) * 4 + o];
-        const T p = first ? z : z + (T)so.beta * B.p[i];
-        const T q = first ? B.y[i] : B.y[i] + (T)so.beta * qold[i];
-        B.p[i] = p;
+        const T z = rv[e] * sJ[s * 4 + o];
+        const T p = first ? z : z + (T)so.beta * pv[e];
+        const T q = first ? yv[e] : yv[e] + (T)so.beta * qv[e];
+        pp[i] = p;
         qnew[i] = q;
-        c[i] += (T)so.alpha * p;
-        B.r[i] = ri - (T)so.alpha * q;
+        c[i] = cv[e] + (T)so.alpha * p;
+        rr[i] = rv[e] - (T)so.alpha * q;
     }
 }
 
@@ -430,30 +471,85 @@ __global__ __launch_bounds__(kBlock) void k_update_last(T *__restrict__ c, Bufs<
 constexpr int kNodeBlock = 512;
 
 // y-part of M on one node tile: phi on the tile plus a one-node halo (one node per lane), then
-// weighted Fried slopes and Gamma^T from LDS.
+// weighted Fried slopes and Gamma^T from LDS.  The cell-table entries of the tile's rows and
+// columns are staged in LDS per chunk of layers; each lane then issues the bilinear loads of
+// eight layers at a time before accumulating them in layer order.
 template <typename T>
 __global__ __launch_bounds__(kNodeBlock) void k_nodes_m(const T *__restrict__ u, T *__restrict__ v, Bufs<T> B,
                                                         int nl) {
-    constexpr int NT = kNodeTile, NP = NT + 2, NS = NT + 1;
+    constexpr int NT = kNodeTile, NP = NT + 2, NS = NT + 1, LMAX = 16, LCH = 8;
+    __shared__ int sXk[LMAX * NP], sYk[LMAX * NP];
+    __shared__ T sXw0[LMAX * NP], sXw1[LMAX * NP], sYw0[LMAX * NP], sYw1[LMAX * NP];
+    __shared__ long sOff[LMAX];
+    __shared__ int sN[LMAX];
     __shared__ T sPhi[NP * NP];
     __shared__ T sSx[NS * NS], sSy[NS * NS];
     const Tile t = B.node_tiles[blockIdx.x];
     const DevWfs W = B.wfs[t.a];
-    const int ns = W.n_sub, nv = W.nv, i0 = t.b, j0 = t.c;
-    if (threadIdx.x < NP * NP) {
-        const int a = threadIdx.x / NP, b = threadIdx.x - a * NP, i = i0 - 1 + a, j = j0 - 1 + b;
-        T val = 0;
-        if (i >= 0 && i <= ns && j >= 0 && j <= ns) val = project_node(u, B, t.a, nl, i, j);
-        sPhi[threadIdx.x] = val;
+    const int g = t.a, ns = W.n_sub, nv = W.nv, i0 = t.b, j0 = t.c;
+    const int a = (int)threadIdx.x / NP, b = (int)threadIdx.x - a * NP, i = i0 - 1 + a, j = j0 - 1 + b;
+    const bool node = threadIdx.x < NP * NP && i >= 0 && i <= ns && j >= 0 && j <= ns;
+    const Ent<T> *__restrict__ xt = B.xtab + (long)g * nl * B.maxnv;
+    const Ent<T> *__restrict__ yt = B.ytab + (long)g * nl * B.maxnv;
+    T phi = 0;
+    for (int l0 = 0; l0 < nl; l0 += LMAX) {
+        const int nc = (nl - l0) < LMAX ? (nl - l0) : LMAX;
+        for (int idx = threadIdx.x; idx < 2 * nc * NP; idx += blockDim.x) {
+            const int axis = idx / (nc * NP), rem = idx - axis * nc * NP, l = rem / NP, bb = rem - l * NP;
+            int nd = (axis ? i0 : j0) - 1 + bb;
+            nd = nd < 0 ? 0 : (nd > ns ? ns : nd);
+            const Ent<T> e = (axis ? yt : xt)[(long)(l0 + l) * B.maxnv + nd];
+            if (axis) {
+                sYk[rem] = e.k0;
+                sYw0[rem] = e.w0;
+                sYw1[rem] = e.w1;
+            } else {
+                sXk[rem] = e.k0;
+                sXw0[rem] = e.w0;
+                sXw1[rem] = e.w1;
+            }
+        }
+        if (threadIdx.x < nc) {
+            sOff[threadIdx.x] = B.lay[l0 + threadIdx.x].c_off;
+            sN[threadIdx.x] = B.lay[l0 + threadIdx.x].n;
+        }
+        __syncthreads();
+        if (node) {
+            for (int lc = 0; lc < nc; lc += LCH) {
+                T uv[LCH][4], wy0[LCH], wy1[LCH], wx0[LCH], wx1[LCH];
+#pragma unroll
+                for (int c = 0; c < LCH; ++c) {
+                    const int l = lc + c;
+                    const bool ok = l < nc;
+                    const int xs = ok ? l * NP + b : 0, ys = ok ? l * NP + a : 0;
+                    const int n = ok ? sN[l] : 0;
+                    wx0[c] = ok ? sXw0[xs] : (T)0;
+                    wx1[c] = ok ? sXw1[xs] : (T)0;
+                    wy0[c] = ok ? sYw0[ys] : (T)0;
+                    wy1[c] = ok ? sYw1[ys] : (T)0;
+                    const T *U = u + (ok ? sOff[l] + (long)sYk[ys] * n + sXk[xs] : 0);
+                    uv[c][0] = U[0];
+                    uv[c][1] = ok ? U[1] : (T)0;
+                    uv[c][2] = ok ? U[n] : (T)0;
+                    uv[c][3] = ok ? U[n + 1] : (T)0;
+                }
+#pragma unroll
+                for (int c = 0; c < LCH; ++c)
+                    phi += (wy0[c] * wx0[c]) * uv[c][0] + (wy0[c] * wx1[c]) * uv[c][1] + (wy1[c] * wx0[c]) * uv[c][2] +
+                           (wy1[c] * wx1[c]) * uv[c][3];
+            }
+        }
+        __syncthreads();
     }
+    if (threadIdx.x < NP * NP) sPhi[threadIdx.x] = node ? phi : (T)0;
     __syncthreads();
     if (threadIdx.x < NS * NS) {
-        const int a = threadIdx.x / NS, b = threadIdx.x - a * NS, i = i0 - 1 + a, j = j0 - 1 + b;
+        const int aa = threadIdx.x / NS, bb = threadIdx.x - aa * NS, ii = i0 - 1 + aa, jj = j0 - 1 + bb;
         T sx = 0, sy = 0;
-        if (i >= 0 && i < ns && j >= 0 && j < ns && subap_active(W, i, j)) {
+        if (ii >= 0 && ii < ns && jj >= 0 && jj < ns && subap_active(W, ii, jj)) {
             const T w = (T)W.inv_var;
-            const T p00 = sPhi[a * NP + b], p01 = sPhi[a * NP + b + 1];
-            const T p10 = sPhi[(a + 1) * NP + b], p11 = sPhi[(a + 1) * NP + b + 1];
+            const T p00 = sPhi[aa * NP + bb], p01 = sPhi[aa * NP + bb + 1];
+            const T p10 = sPhi[(aa + 1) * NP + bb], p11 = sPhi[(aa + 1) * NP + bb + 1];
             sx = w * ((T)0.5 * ((p01 - p00) + (p11 - p10)));
             sy = w * ((T)0.5 * ((p10 - p00) + (p11 - p01)));
         }
@@ -462,12 +558,12 @@ __global__ __launch_bounds__(kNodeBlock) void k_nodes_m(const T *__restrict__ u,
     }
     __syncthreads();
     if (threadIdx.x < NT * NT) {
-        const int a = threadIdx.x / NT, b = threadIdx.x - a * NT, i = i0 + a, j = j0 + b;
-        if (i <= ns && j <= ns) {
+        const int aa = threadIdx.x / NT, bb = threadIdx.x - aa * NT, ii = i0 + aa, jj = j0 + bb;
+        if (ii <= ns && jj <= ns) {
             // node (i, j) is a corner of subapertures (i, j), (i, j-1), (i-1, j), (i-1, j-1)
-            const int s11 = (a + 1) * NS + (b + 1), s10 = (a + 1) * NS + b, s01 = a * NS + (b + 1), s00 = a * NS + b;
-            v[W.v_off + (long)i * nv + j] = (T)0.5 * ((-sSx[s11] - sSy[s11]) + (sSx[s10] - sSy[s10]) +
-                                                      (-sSx[s01] + sSy[s01]) + (sSx[s00] + sSy[s00]));
+            const int s11 = (aa + 1) * NS + (bb + 1), s10 = (aa + 1) * NS + bb, s01 = aa * NS + (bb + 1), s00 = aa * NS + bb;
+            v[W.v_off + (long)ii * nv + jj] = (T)0.5 * ((-sSx[s11] - sSy[s11]) + (sSx[s10] - sSy[s10]) +
+                                                        (-sSx[s01] + sSy[s01]) + (sSx[s00] + sSy[s00]));
         }
     }
 }
@@ -536,29 +632,51 @@ __global__ __launch_bounds__(kNodeBlock) void k_slopes(const T *__restrict__ u, 
 // P^T
 // ---------------------------------------------------------------------------------------------
 // Through the transpose tables: for each sensor, the tile rows' and columns' (node, weight)
-// lists are staged in LDS; each lane then gathers the v values of its node's non-zero pairs,
-// four sensors' loads in flight at a time.
+// lists are staged in LDS (structure of arrays, entry-major, so the 16 lanes of a tile row read
+// consecutive words); each lane then gathers the v values of its node's non-zero pairs, two
+// sensors' loads in flight at a time.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pt_tab(const T *__restrict__ v, T *__restrict__ x, Bufs<T> B, int nl,
                                                    int nw) {
-    constexpr int NT = kNodeTile, RW = kRtabWidth, GMAX = 16;
-    __shared__ RtabEnt<T> sRy[GMAX * NT * RW], sRx[GMAX * NT * RW];
+    constexpr int NT = kNodeTile, RW = kRtabWidth, GMAX = 16, GCH = 2;
+    constexpr int NSTAGE = 2 * GMAX * NT * RW, MAXI = NSTAGE / kBlock;
+    static_assert(NT == 16 && RW == 4 && kBlock == 256, "index arithmetic below assumes these sizes");
+    __shared__ int sIdx[NSTAGE];  // [axis][g][entry][line]
+    __shared__ T sW[NSTAGE];
     __shared__ long sVoff[GMAX];
     __shared__ int sNv[GMAX];
     const Tile t = B.lay_tiles[blockIdx.x];
     const int k0 = t.b, q0 = t.c, n = t.f, roff = t.h;
-    const int rk = (int)(threadIdx.x / NT), rq = (int)(threadIdx.x % NT);
+    const int rk = (int)(threadIdx.x >> 4), rq = (int)(threadIdx.x & 15);
     const bool valid = k0 + rk < n && q0 + rq < n;
+    const RtabEnt<T> *__restrict__ xrt = B.xrtab;
+    const RtabEnt<T> *__restrict__ yrt = B.yrtab;
     T acc = 0;
     for (int gb = 0; gb < nw; gb += GMAX) {
         const int gc = (nw - gb) < GMAX ? (nw - gb) : GMAX;
-        for (int idx = threadIdx.x; idx < 2 * gc * NT * RW; idx += blockDim.x) {
-            const int axis = idx / (gc * NT * RW), rem = idx - axis * gc * NT * RW;
-            const int g = rem / (NT * RW), rr = rem - g * NT * RW, line = rr / RW, e = rr - line * RW;
-            const int gl = (axis ? k0 : q0) + line;
-            RtabEnt<T> en{0, (T)0};
-            if (gl < n) en = (axis ? B.yrtab : B.xrtab)[((long)(gb + g) * B.sum_n + roff + gl) * RW + e];
-            (axis ? sRy : sRx)[rem] = en;
+        {
+            int id[MAXI];
+            T w[MAXI];
+#pragma unroll
+            for (int c = 0; c < MAXI; ++c) {
+                // staged slot e = (((axis * 16 + g) * 4 + entry) * 16 + line); loads are read in
+                // (line, entry) order for coalescing
+                const int e = c * kBlock + (int)threadIdx.x;
+                const int axis = e >> 10, g = (e >> 6) & 15, line = (e >> 2) & 15, entry = e & 3;
+                const int gl = (axis ? k0 : q0) + line;
+                RtabEnt<T> en{0, (T)0};
+                if (g < gc && gl < n) en = (axis ? yrt : xrt)[((long)(gb + g) * B.sum_n + roff + gl) * RW + entry];
+                id[c] = en.idx;
+                w[c] = en.w;
+            }
+#pragma unroll
+            for (int c = 0; c < MAXI; ++c) {
+                const int e = c * kBlock + (int)threadIdx.x;
+                const int axis = e >> 10, g = (e >> 6) & 15, line = (e >> 2) & 15, entry = e & 3;
+                const int slot = (((axis * GMAX + g) * RW + entry) * NT) + line;
+                sIdx[slot] = id[c];
+                sW[slot] = w[c];
+            }
         }
         if (threadIdx.x < gc) {
             sVoff[threadIdx.x] = B.wfs[gb + threadIdx.x].v_off;
@@ -566,27 +684,34 @@ __global__ __launch_bounds__(kBlock) void k_pt_tab(const T *__restrict__ v, T *_
         }
         __syncthreads();
         if (valid) {
-            for (int g4 = 0; g4 < gc; g4 += 4) {
-                T part[4][RW * RW];
+            for (int g0 = 0; g0 < gc; g0 += GCH) {
+                T val[GCH][RW][RW], wy[GCH][RW], wx[GCH][RW];
 #pragma unroll
-                for (int gg = 0; gg < 4; ++gg) {
-                    const int g = g4 + gg;
+                for (int gg = 0; gg < GCH; ++gg) {
+                    const int g = g0 + gg;
+                    int iy[RW], ix[RW];
+#pragma unroll
+                    for (int a = 0; a < RW; ++a) {
+                        const int sy = ((GMAX + g) * RW + a) * NT + rk, sx = (g * RW + a) * NT + rq;
+                        iy[a] = g < gc ? sIdx[sy] : 0;
+                        wy[gg][a] = g < gc ? sW[sy] : (T)0;
+                        ix[a] = g < gc ? sIdx[sx] : 0;
+                        wx[gg][a] = g < gc ? sW[sx] : (T)0;
+                    }
+                    const T *vg = v + (g < gc ? sVoff[g] : 0);
+                    const int nv = g < gc ? sNv[g] : 0;
 #pragma unroll
                     for (int a = 0; a < RW; ++a)
 #pragma unroll
-                        for (int b = 0; b < RW; ++b) {
-                            part[gg][a * RW + b] = 0;
-                            if (g < gc) {
-                                const RtabEnt<T> ey = sRy[(g * NT + rk) * RW + a], ex = sRx[(g * NT + rq) * RW + b];
-                                if (ey.w != (T)0 && ex.w != (T)0)
-                                    part[gg][a * RW + b] = (ey.w * ex.w) * v[sVoff[g] + (long)ey.idx * sNv[g] + ex.idx];
-                            }
-                        }
+                        for (int b = 0; b < RW; ++b)
+                            val[gg][a][b] = (wy[gg][a] != (T)0 && wx[gg][b] != (T)0) ? vg[(long)iy[a] * nv + ix[b]] : (T)0;
                 }
 #pragma unroll
-                for (int gg = 0; gg < 4; ++gg)
+                for (int gg = 0; gg < GCH; ++gg)
 #pragma unroll
-                    for (int e = 0; e < RW * RW; ++e) acc += part[gg][e];
+                    for (int a = 0; a < RW; ++a)
+#pragma unroll
+                        for (int b = 0; b < RW; ++b) acc += (wy[gg][a] * wx[gg][b]) * val[gg][a][b];
             }
         }
         __syncthreads();
@@ -679,18 +804,20 @@ struct FineGeom {
 // Levels 1..KF on a tile of TQ x TQ level-KF approximation coefficients: the input region with
 // its halo (periodic wrap) and the epilogue operands of every owned coefficient arrive in one
 // batch of independent loads, then the levels run from LDS.
+constexpr int kFwdBlock = 512;
+
 template <typename T, int KF, int TQ, int EPI>
-__global__ __launch_bounds__(kBlock) void k_fwd_fine(const T *__restrict__ x, Bufs<T> B, int J, FwdArgs E,
+__global__ __launch_bounds__(kFwdBlock) void k_fwd_fine(const T *__restrict__ x, Bufs<T> B, int J, FwdArgs E,
                                                      Taps<T> tp) {
     using G = FineGeom<KF, TQ>;
     constexpr int L0 = G::len(0), L1 = G::len(1), EMAX = 1024;
     constexpr int NE = (EPI == kEpiRhs) ? 2 : ((EPI == kEpiPlain) ? 0 : 1);
-    constexpr int MAXI = 8;
+    constexpr int MAXI = 6;
     __shared__ T sA[L0 * L0];
     __shared__ T sB[KF >= 2 ? L1 * L1 : 1];
     __shared__ T sE0[NE >= 1 ? EMAX : 1], sE1[NE >= 2 ? EMAX : 1];
     __shared__ T sAd[kMaxJ + 1], sJi[(kMaxJ + 1) * 4];
-    __shared__ double sh[kBlock / 64];
+    __shared__ double sh[kFwdBlock / 64];
 
     if constexpr (EPI == kEpiRhs) {
         if (blockIdx.x == 0 && threadIdx.x == 0) reset_scalars(B.sc + 1);  // state "before pass 0"
@@ -713,12 +840,12 @@ __global__ __launch_bounds__(kBlock) void k_fwd_fine(const T *__restrict__ x, Bu
     const int oy = qy << KF, ox = qx << KF, nmask = n - 1;
     {
         const int nreg = len[0] * len[0], tot = nreg + (NE ? ne : 0);
-        for (int base = 0; base < tot; base += MAXI * kBlock) {
+        for (int base = 0; base < tot; base += MAXI * kFwdBlock) {
             T v0[MAXI], v1[MAXI];
             int d[MAXI];
 #pragma unroll
             for (int c = 0; c < MAXI; ++c) {
-                const int k = base + c * kBlock + (int)threadIdx.x;
+                const int k = base + c * kFwdBlock + (int)threadIdx.x;
                 d[c] = -1;
                 if (k >= tot) continue;
                 if (k < nreg) {
@@ -847,21 +974,35 @@ __global__ __launch_bounds__(512) void k_fwd_coarse(Bufs<T> B, int J, int KF, Fw
     T *cs = reinterpret_cast<T *>(smem_raw), *cd = cs + m0 * m0, *e0s = cd + (m0 * m0) / 4 + 1, *e1s = e0s + m0 * m0;
     if ((EPI == kEpiPrior || EPI == kEpiPcg) && threadIdx.x <= J) sAd[threadIdx.x] = B.ad[l * (J + 1) + threadIdx.x];
     if (EPI == kEpiPcg && threadIdx.x < (J + 1) * 4) sJi[threadIdx.x] = B.jinv[l * (J + 1) * 4 + threadIdx.x];
-    for (int idx = threadIdx.x; idx < m0 * m0; idx += blockDim.x) {
-        const int r = idx / m0, q = idx - r * m0;
-        T a0 = 0, a1 = 0;
-        prefetch<T, EPI>(B, E, coff + (long)r * n + q, a0, a1);
-        cs[idx] = B.tmpA[(coff >> (2 * KF)) + idx];
-        if constexpr (NE >= 1) e0s[idx] = a0;
-        if constexpr (NE >= 2) e1s[idx] = a1;
+    const int lm = L.log2n - KF;
+    const T *__restrict__ llin = B.tmpA + (coff >> (2 * KF));
+    for (int base = 0; base < m0 * m0; base += 8 * 512) {
+        T cv[8], a0v[8], a1v[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int idx = base + c * 512 + (int)threadIdx.x;
+            a0v[c] = 0;
+            a1v[c] = 0;
+            if (idx >= m0 * m0) continue;
+            prefetch<T, EPI>(B, E, coff + (long)(idx >> lm) * n + (idx & (m0 - 1)), a0v[c], a1v[c]);
+            cv[c] = llin[idx];
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int idx = base + c * 512 + (int)threadIdx.x;
+            if (idx >= m0 * m0) continue;
+            cs[idx] = cv[c];
+            if constexpr (NE >= 1) e0s[idx] = a0v[c];
+            if constexpr (NE >= 2) e1s[idx] = a1v[c];
+        }
     }
     __syncthreads();
     double rho = 0.0, mu = 0.0;
     for (int s = KF + 1; s <= J; ++s) {
-        const int mi = n >> (s - 1), h = mi >> 1, msk = mi - 1, nq = h * h;
+        const int mi = n >> (s - 1), h = mi >> 1, msk = mi - 1, nq = h * h, lh = L.log2n - s;
         const T ad = (EPI == kEpiPrior || EPI == kEpiPcg) ? sAd[s] : (T)0;
         for (int qi = threadIdx.x; qi < nq; qi += blockDim.x) {
-            const int r = qi / h, q = qi - r * h;
+            const int r = qi >> lh, q = qi & (h - 1);
             int cols[6];
 #pragma unroll
             for (int b = 0; b < 6; ++b) cols[b] = (2 * q + b) & msk;
@@ -886,7 +1027,7 @@ __global__ __launch_bounds__(512) void k_fwd_coarse(Bufs<T> B, int J, int KF, Fw
             for (int o = 0; o <= 3; ++o) {
                 if (o == 0 && s != J) continue;
                 const int lr = r + ((o == 2 || o == 3) ? h : 0), lc = q + ((o == 1 || o == 3) ? h : 0);
-                const int li = lr * m0 + lc;
+                const int li = (lr << lm) + lc;
                 T e0 = 0, e1 = 0;
                 if constexpr (NE >= 1) e0 = e0s[li];
                 if constexpr (NE >= 2) e1 = e1s[li];
@@ -1079,7 +1220,7 @@ int Ops<T>::idwt(const T *c, T *out) const {
     InvArgs A{};
     A.src = c;
     A.out = out;
-    k_inv<T, kInvPlain><<<(int)P.idwt_tiles.size(), kBlock, 0, st>>>(B, P.J, A, make_taps<T>());
+    k_inv<T, kInvPlain><<<(int)P.idwt_tiles.size(), kInvBlock, 0, st>>>(B, P.J, A, make_taps<T>());
     return check();
 }
 
@@ -1088,7 +1229,7 @@ int Ops<T>::idwt_first(const T *r, T *out) const {
     InvArgs A{};
     A.src = r;
     A.out = out;
-    k_inv<T, kInvFirst><<<(int)P.idwt_tiles.size(), kBlock, 0, st>>>(B, P.J, A, make_taps<T>());
+    k_inv<T, kInvFirst><<<(int)P.idwt_tiles.size(), kInvBlock, 0, st>>>(B, P.J, A, make_taps<T>());
     return check();
 }
 
@@ -1107,7 +1248,7 @@ int Ops<T>::idwt_update(const T *r_old, const T *q_old, T *q_new, T *r_new, T *c
     A.kprev = kprev;
     A.nparts = nparts();
     A.resnorm = resnorm;
-    k_inv<T, kInvUpdate><<<(int)P.idwt_tiles.size(), kBlock, 0, st>>>(B, P.J, A, make_taps<T>());
+    k_inv<T, kInvUpdate><<<(int)P.idwt_tiles.size(), kInvBlock, 0, st>>>(B, P.J, A, make_taps<T>());
     return check();
 }
 
@@ -1126,9 +1267,9 @@ int Ops<T>::fwd(const T *x, const FwdArgs &E) const {
     const int nf = (int)P.fine_tiles.size();
     const Taps<T> tp = make_taps<T>();
     switch (P.kf) {
-        case 1: k_fwd_fine<T, 1, 16, EPI><<<nf, kBlock, 0, st>>>(x, B, P.J, E, tp); break;
-        case 2: k_fwd_fine<T, 2, 8, EPI><<<nf, kBlock, 0, st>>>(x, B, P.J, E, tp); break;
-        default: k_fwd_fine<T, 3, 4, EPI><<<nf, kBlock, 0, st>>>(x, B, P.J, E, tp); break;
+        case 1: k_fwd_fine<T, 1, 16, EPI><<<nf, kFwdBlock, 0, st>>>(x, B, P.J, E, tp); break;
+        case 2: k_fwd_fine<T, 2, 8, EPI><<<nf, kFwdBlock, 0, st>>>(x, B, P.J, E, tp); break;
+        default: k_fwd_fine<T, 3, 4, EPI><<<nf, kFwdBlock, 0, st>>>(x, B, P.J, E, tp); break;
     }
     if (int e = check()) return e;
     if (P.kf < P.J) {
