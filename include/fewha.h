@@ -165,6 +165,23 @@ int fewha_state_set(fewha_plan *p, const void *d_b_prev, const void *d_r_prev, v
  * unused entries are 0.  h_jdiag holds n_layers * (J + 1) * 4 doubles.  Requires a bound plan. */
 int fewha_precond_table(const fewha_plan *p, double *h_jdiag);
 
+/* Stages of one PCG pass, for timing a single launch (fewha_stage_launch). */
+typedef enum {
+    FEWHA_STAGE_WT = 0,   /* u = W^T J^-1 r: inverse DWT of the preconditioned residual, with the
+                             (r, z) and (z, alpha D z) partial sums (Alg. 2; Kernel 1, Sec. 3.3) */
+    FEWHA_STAGE_PROJ = 1, /* v = Gamma^T C_eta^-1 Gamma P u on every guide star (Kernel 2, Sec. 3.3) */
+    FEWHA_STAGE_PT = 2,   /* x = P^T v on every layer (Kernel 3, Sec. 3.3) */
+    FEWHA_STAGE_FWD = 3   /* y = W x + alpha D z, all levels, with the PCG update of Alg. 2, applied to
+                             workspace scratch copies of r, p, q, c (Kernel 3, Sec. 3.3) */
+} fewha_stage;
+
+/* Enqueue one launch of one stage of the PCG pass on the plan's current workspace contents
+ * (the vectors the previous stage left there), for timing and profiling a single kernel.  The
+ * stages read and write only workspace intermediates (u, v, x, partial sums, scratch vectors):
+ * the caller's vectors, the warm-restart state and the PCG scalars are untouched, so a later
+ * fewha_pcg_solve is unaffected.  Returns FEWHA_ERR_INVALID_ARG for an unknown stage. */
+int fewha_stage_launch(const fewha_plan *p, int stage, void *stream);
+
 /* Read the device status word of the last solve (synchronises the device): FEWHA_OK,
  * FEWHA_ERR_BREAKDOWN or FEWHA_ERR_NONFINITE; FEWHA_ERR_WORKSPACE if unbound. */
 int fewha_last_status(const fewha_plan *p);

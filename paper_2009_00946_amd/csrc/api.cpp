@@ -22,40 +22,29 @@ Bufs<T> bufs(const Plan &P) {
     b.lay = reinterpret_cast<const DevLayer *>(w + P.o_lay);
     b.proj = reinterpret_cast<const DevProj *>(w + P.o_proj);
     b.dm = reinterpret_cast<const DevDm *>(w + P.o_dm);
-    b.idwt_tiles = reinterpret_cast<const Tile *>(w + P.o_idwt);
-    b.node_tiles = reinterpret_cast<const Tile *>(w + P.o_node);
-    b.sub_tiles = reinterpret_cast<const Tile *>(w + P.o_sub);
-    b.lay_tiles = reinterpret_cast<const Tile *>(w + P.o_laytile);
-    b.fine_tiles = reinterpret_cast<const Tile *>(w + P.o_fine);
-    b.coef_tiles = reinterpret_cast<const Tile *>(w + P.o_coef);
     b.xtab = reinterpret_cast<const Ent<T> *>(w + P.o_xtab);
     b.ytab = reinterpret_cast<const Ent<T> *>(w + P.o_ytab);
     b.xrng = reinterpret_cast<const Range *>(w + P.o_xrng);
     b.yrng = reinterpret_cast<const Range *>(w + P.o_yrng);
+    b.xrtab = reinterpret_cast<const RtabEnt<T> *>(w + P.o_xrtab);
+    b.yrtab = reinterpret_cast<const RtabEnt<T> *>(w + P.o_yrtab);
+    b.rects = reinterpret_cast<const int4 *>(w + P.o_rects);
     b.maxnv = P.maxnv;
     b.sum_n = P.sum_n;
-    b.kf = P.kf;
     b.jinv = reinterpret_cast<const T *>(w + P.o_jinv);
     b.ad = reinterpret_cast<const T *>(w + P.o_ad);
     b.b_prev = reinterpret_cast<T *>(w + P.o_bprev);
     b.r = reinterpret_cast<T *>(w + P.o_r);
     b.p = reinterpret_cast<T *>(w + P.o_p);
     b.q = reinterpret_cast<T *>(w + P.o_q);
-    b.y = reinterpret_cast<T *>(w + P.o_y);
     b.u = reinterpret_cast<T *>(w + P.o_u);
     b.x = reinterpret_cast<T *>(w + P.o_x);
     b.v = reinterpret_cast<T *>(w + P.o_v);
-    b.tmpA = reinterpret_cast<T *>(w + P.o_tmpA);
-    b.tmpB = reinterpret_cast<T *>(w + P.o_tmpB);
-    b.b = reinterpret_cast<T *>(w + P.o_b);
+    b.ll = reinterpret_cast<T *>(w + P.o_ll);
     b.probe_c = reinterpret_cast<T *>(w + P.o_probe_c);
     b.probe_s = reinterpret_cast<T *>(w + P.o_probe_s);
+    b.over = reinterpret_cast<int *>(w + P.o_over);
     b.partials = reinterpret_cast<double *>(w + P.o_partials);
-    b.r2 = reinterpret_cast<T *>(w + P.o_r2);
-    b.q2 = reinterpret_cast<T *>(w + P.o_q2);
-    b.over = reinterpret_cast<int *>(w + P.o_lcount);
-    b.xrtab = reinterpret_cast<const RtabEnt<T> *>(w + P.o_xrtab);
-    b.yrtab = reinterpret_cast<const RtabEnt<T> *>(w + P.o_yrtab);
     b.sc = reinterpret_cast<Scalars *>(w + P.o_scalars);
     return b;
 }
@@ -85,49 +74,53 @@ int ready(const fewha_plan *p) {
 template <typename T>
 int apply_A(const Plan &P, const void *c, void *s, void *stream) {
     auto o = ops<T>(P, stream);
-    TRY(o.idwt(static_cast<const T *>(c), o.B.u));
-    return o.slopes(o.B.u, static_cast<T *>(s));
+    TRY(o.wt(static_cast<const T *>(c), o.B.u));
+    return o.proj(o.B.u, static_cast<T *>(s), kProjA);
 }
 
 template <typename T>
 int apply_At(const Plan &P, const void *s, void *c, void *stream) {
     auto o = ops<T>(P, stream);
-    TRY(o.nodes(static_cast<const T *>(s), o.B.v, kModeAdj));
-    TRY(o.pt(o.B.v, o.B.x));
-    return o.fdwt(o.B.x, static_cast<T *>(c));
+    TRY(o.gt(static_cast<const T *>(s), o.B.v, kGtAdj));
+    TRY(o.pt(o.B.v, o.B.x, PassArgs{-1, 0, 0, 0, nullptr}));
+    FwdArgs E{};
+    E.out = c;
+    return o.fwd(o.B.x, E, kEpiPlain);
 }
 
 template <typename T>
 int apply_M(const Plan &P, const void *c, void *y, void *stream) {
     auto o = ops<T>(P, stream);
-    TRY(o.idwt(static_cast<const T *>(c), o.B.u));
-    TRY(o.nodes(o.B.u, o.B.v, kModeM));
-    TRY(o.pt(o.B.v, o.B.x));
-    return o.fdwt_prior(o.B.x, static_cast<const T *>(c), static_cast<T *>(y));
+    TRY(o.wt(static_cast<const T *>(c), o.B.u));
+    TRY(o.proj(o.B.u, o.B.v, kProjM));
+    TRY(o.pt(o.B.v, o.B.x, PassArgs{-1, 0, 0, 0, nullptr}));
+    FwdArgs E{};
+    E.out = y;
+    E.cin = c;
+    return o.fwd(o.B.x, E, kEpiPrior);
 }
 
 template <typename T>
 int pcg_solve(const Plan &P, const void *s, void *c, int n_iter, int flags, double *resnorm, void *stream) {
     auto o = ops<T>(P, stream);
-    T *cc = static_cast<T *>(c);
     // right-hand side b = W P^T Gamma^T C s, then the warm-restart residual update
-    TRY(o.nodes(static_cast<const T *>(s), o.B.v, kModeRhs));
-    TRY(o.pt(o.B.v, o.B.x));
-    TRY(o.fdwt_rhs(o.B.x, cc, flags == FEWHA_COLD));
-    // Residual r_k and search-direction image q_k alternate between two buffers so that the
-    // fused update can read the previous values anywhere while owners write the new ones.
-    T *R[2] = {o.B.r, o.B.r2}, *Q[2] = {o.B.q, o.B.q2};
+    TRY(o.gt(static_cast<const T *>(s), o.B.v, kGtRhs));
+    TRY(o.pt(o.B.v, o.B.x, PassArgs{-1, 0, 0, 0, nullptr}));
+    FwdArgs R{};
+    R.c = c;
+    R.cold = flags == FEWHA_COLD ? 1 : 0;
+    TRY(o.fwd(o.B.x, R, kEpiRhs));
     for (int k = 0; k < n_iter; ++k) {
-        // u = W^T J^-1 r_k; from pass 1 on, this launch first reduces pass k-1, forms its Alg. 2
-        // scalars and applies its update
-        if (k == 0) TRY(o.idwt_first(R[0], o.B.u));
-        else TRY(o.idwt_update(R[(k - 1) & 1], Q[k & 1], Q[(k - 1) & 1], R[k & 1], cc, k - 1, resnorm, o.B.u));
-        TRY(o.nodes(o.B.u, o.B.v, kModeM));
-        TRY(o.pt(o.B.v, o.B.x));
-        // y = W x + alpha D z with the (r_k, z), (y, z) partials of pass k
-        TRY(o.fdwt_pcg(o.B.x, R[k & 1]));
+        TRY(o.wt_pcg(o.B.r, o.B.u));             // u = W^T J^-1 r; (r, z), (z, alpha D z) partials
+        TRY(o.proj(o.B.u, o.B.v, kProjM));       // v = Gamma^T C Gamma P u; (C Gamma P u, Gamma P u) partials
+        TRY(o.pt(o.B.v, o.B.x, PassArgs{k, P.n_wt, P.n_proj, 1, resnorm}));  // x = P^T v; Alg. 2 scalars
+        FwdArgs E{};                             // y = W x + alpha D z; the pass update
+        E.c = c;
+        E.k = k;
+        E.resnorm = resnorm;
+        E.publish = 1;
+        TRY(o.fwd(o.B.x, E, kEpiPcg));
     }
-    if (n_iter > 0) TRY(o.update_last(cc, R[(n_iter - 1) & 1], Q[n_iter & 1], Q[(n_iter - 1) & 1], n_iter - 1, resnorm));
     const_cast<Plan &>(P).last_slot = n_iter > 0 ? ((n_iter - 1) & 1) : 1;
     return FEWHA_OK;
 }
@@ -135,8 +128,32 @@ int pcg_solve(const Plan &P, const void *s, void *c, int n_iter, int flags, doub
 template <typename T>
 int fit_dm(const Plan &P, const void *c, const void *a_prev, double gain, void *a, void *stream) {
     auto o = ops<T>(P, stream);
-    TRY(o.idwt(static_cast<const T *>(c), o.B.u));
+    TRY(o.wt(static_cast<const T *>(c), o.B.u));
     return o.fit(o.B.u, static_cast<const T *>(a_prev), static_cast<T *>(a), gain);
+}
+
+template <typename T>
+int stage_launch(const Plan &P, int stage, void *stream) {
+    auto o = ops<T>(P, stream);
+    switch (stage) {
+        case FEWHA_STAGE_WT: return o.wt_pcg(o.B.r, o.B.u);
+        case FEWHA_STAGE_PROJ: return o.proj(o.B.u, o.B.v, kProjM);
+        case FEWHA_STAGE_PT: return o.pt(o.B.v, o.B.x, PassArgs{1, P.n_wt, P.n_proj, 0, nullptr});
+        default: {
+            // the frame's y = W x + alpha D z with the pass update, applied to scratch copies of
+            // r, p, q and c, without publishing scalars
+            const size_t N = P.n_coef;
+            T *scr = reinterpret_cast<T *>(P.ws + P.o_stage);
+            o.B.r = scr;
+            o.B.p = scr + N;
+            o.B.q = scr + 2 * N;
+            FwdArgs E{};
+            E.c = scr + 3 * N;
+            E.k = 1;
+            E.publish = 0;
+            return o.fwd(o.B.x, E, kEpiPcg);
+        }
+    }
 }
 
 template <typename T>
@@ -147,12 +164,6 @@ int bind_tables(Plan &P, hipStream_t st) {
     HIPTRY(hipMemcpy(w + P.o_lay, P.dlay.data(), sizeof(DevLayer) * P.dlay.size(), hipMemcpyHostToDevice));
     HIPTRY(hipMemcpy(w + P.o_proj, P.dproj.data(), sizeof(DevProj) * P.dproj.size(), hipMemcpyHostToDevice));
     HIPTRY(hipMemcpy(w + P.o_dm, P.ddm.data(), sizeof(DevDm) * P.ddm.size(), hipMemcpyHostToDevice));
-    HIPTRY(hipMemcpy(w + P.o_idwt, P.idwt_tiles.data(), sizeof(Tile) * P.idwt_tiles.size(), hipMemcpyHostToDevice));
-    HIPTRY(hipMemcpy(w + P.o_node, P.node_tiles.data(), sizeof(Tile) * P.node_tiles.size(), hipMemcpyHostToDevice));
-    HIPTRY(hipMemcpy(w + P.o_sub, P.sub_tiles.data(), sizeof(Tile) * P.sub_tiles.size(), hipMemcpyHostToDevice));
-    HIPTRY(hipMemcpy(w + P.o_laytile, P.lay_tiles.data(), sizeof(Tile) * P.lay_tiles.size(), hipMemcpyHostToDevice));
-    HIPTRY(hipMemcpy(w + P.o_fine, P.fine_tiles.data(), sizeof(Tile) * P.fine_tiles.size(), hipMemcpyHostToDevice));
-    HIPTRY(hipMemcpy(w + P.o_coef, P.coef_tiles.data(), sizeof(Tile) * P.coef_tiles.size(), hipMemcpyHostToDevice));
     const int nb = P.nl * (P.J + 1);
     std::vector<T> ad(nb);
     for (int k = 0; k < nb; ++k) ad[k] = (T)P.ad[k];
@@ -165,6 +176,38 @@ int bind_tables(Plan &P, hipStream_t st) {
     TRY(o.fill(o.B.b_prev, N, 0));
     TRY(o.fill(o.B.r, N, 0));
     TRY(o.fill(o.B.probe_c, N, 0));
+    TRY(o.fill(reinterpret_cast<T *>(w + P.o_stage), 4 * N, 0));
+    HIPTRY(hipStreamSynchronize(st));
+
+    // staged P^T: every guide star's node rectangle per tile must fit the LDS stage, every
+    // transpose row kRtabWidth pairs; otherwise the scanning P^T
+    {
+        std::vector<int> over(P.nw, 0);
+        HIPTRY(hipMemcpy(over.data(), o.B.over, sizeof(int) * P.nw, hipMemcpyDeviceToHost));
+        std::vector<int4> rects(size_t(P.n_pt) * P.nw);
+        HIPTRY(hipMemcpy(rects.data(), o.B.rects, sizeof(int4) * rects.size(), hipMemcpyDeviceToHost));
+        P.rtab_ok = P.nw <= kPtMaxWfs;
+        for (int g = 0; g < P.nw; ++g)
+            if (over[g]) P.rtab_ok = false;
+        size_t stage = 1;
+        for (int l = 0; l < P.nl; ++l) {
+            int cr = 1, cw = 1;
+            for (int t = P.seg_pt.start[l]; t < P.seg_pt.start[l + 1]; ++t)
+                for (int g = 0; g < P.nw; ++g) {
+                    const int4 R = rects[size_t(t) * P.nw + g];  // rows / columns packed lo | hi << 16
+                    const int rr = (R.x >> 16) - (R.x & 0xffff) + 1, rc = (R.y >> 16) - (R.y & 0xffff) + 1;
+                    cr = rr > cr ? rr : cr;
+                    cw = rc > cw ? rc : cw;
+                    if (R.z > kRtabWidth || R.w > kRtabWidth) P.rtab_ok = false;
+                }
+            P.seg_pt.capr[l] = cr;
+            P.seg_pt.capw[l] = cw;
+            const size_t need = size_t(P.nw) * cr * cw;
+            stage = need > stage ? need : stage;
+        }
+        if (stage > size_t(kPtStage)) P.rtab_ok = false;
+        P.pt_lds = stage * P.elem;
+    }
 
     // Preconditioner of Sec. 3.4: J = alpha D + tau per (layer, level, orientation), with tau the
     // data-term diagonal ||C^1/2 A e_k||^2 at the band's representative coefficient
@@ -187,13 +230,6 @@ int bind_tables(Plan &P, hipStream_t st) {
                 HIPTRY(hipStreamSynchronize(st));
                 P.jtab[size_t(l * (P.J + 1) + s) * 4 + ori] = P.ad[size_t(l) * (P.J + 1) + s] + tau;
             }
-    }
-    {
-        std::vector<int> over(P.nw, 0);
-        HIPTRY(hipMemcpy(over.data(), o.B.over, sizeof(int) * P.nw, hipMemcpyDeviceToHost));
-        P.rtab_ok = true;
-        for (int g = 0; g < P.nw; ++g)
-            if (over[g]) P.rtab_ok = false;
     }
     std::vector<T> jinv(size_t(nb) * 4, (T)0);
     for (size_t k = 0; k < jinv.size(); ++k)
@@ -280,10 +316,14 @@ int fewha_dwt_forward(const fewha_plan *p, const void *d_layers, void *d_c, void
     if (!d_layers || !d_c || d_layers == d_c) return FEWHA_ERR_INVALID_ARG;
     if (p->p.prec == FEWHA_FP64) {
         auto o = ops<double>(p->p, stream);
-        return o.fdwt(static_cast<const double *>(d_layers), static_cast<double *>(d_c));
+        FwdArgs E{};
+        E.out = d_c;
+        return o.fwd(static_cast<const double *>(d_layers), E, kEpiPlain);
     }
     auto o = ops<float>(p->p, stream);
-    return o.fdwt(static_cast<const float *>(d_layers), static_cast<float *>(d_c));
+    FwdArgs E{};
+    E.out = d_c;
+    return o.fwd(static_cast<const float *>(d_layers), E, kEpiPlain);
 }
 
 int fewha_dwt_inverse(const fewha_plan *p, const void *d_c, void *d_layers, void *stream) {
@@ -291,10 +331,10 @@ int fewha_dwt_inverse(const fewha_plan *p, const void *d_c, void *d_layers, void
     if (!d_layers || !d_c || d_layers == d_c) return FEWHA_ERR_INVALID_ARG;
     if (p->p.prec == FEWHA_FP64) {
         auto o = ops<double>(p->p, stream);
-        return o.idwt(static_cast<const double *>(d_c), static_cast<double *>(d_layers));
+        return o.wt(static_cast<const double *>(d_c), static_cast<double *>(d_layers));
     }
     auto o = ops<float>(p->p, stream);
-    return o.idwt(static_cast<const float *>(d_c), static_cast<float *>(d_layers));
+    return o.wt(static_cast<const float *>(d_c), static_cast<float *>(d_layers));
 }
 
 int fewha_pcg_solve(fewha_plan *p, const void *d_s, void *d_c, int n_iter, int flags, double *d_resnorm,
@@ -310,6 +350,14 @@ int fewha_fit_dm(const fewha_plan *p, const void *d_c, const void *d_a_prev, dou
     if (!d_c || !d_a || d_a == d_c || !std::isfinite(gain)) return FEWHA_ERR_INVALID_ARG;
     return p->p.prec == FEWHA_FP64 ? fit_dm<double>(p->p, d_c, d_a_prev, gain, d_a, stream)
                                    : fit_dm<float>(p->p, d_c, d_a_prev, gain, d_a, stream);
+}
+
+int fewha_stage_launch(const fewha_plan *p, int stage, void *stream) {
+    TRY(ready(p));
+    if (stage < FEWHA_STAGE_WT || stage > FEWHA_STAGE_FWD) return FEWHA_ERR_INVALID_ARG;
+    const Plan &P = p->p;
+    if (P.prec == FEWHA_FP64) return stage_launch<double>(P, stage, stream);
+    return stage_launch<float>(P, stage, stream);
 }
 
 int fewha_state_get(const fewha_plan *p, void *d_b_prev, void *d_r_prev, void *stream) {

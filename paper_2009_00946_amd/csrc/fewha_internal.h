@@ -6,6 +6,8 @@
 #include <cstdint>
 #include <vector>
 
+#include <hip/hip_runtime.h>
+
 #include "../../include/fewha.h"
 
 namespace fewha {
@@ -17,14 +19,42 @@ constexpr int kMaxJ = 12;
 constexpr int kMaxGrid = 4096;    // sensor subapertures per side
 constexpr int kMaxLayerGrid = 512; // layer nodes per side
 
-// Inverse-DWT output tile edge (nodes); layers smaller than this form a single tile.
-constexpr int kIdwtTile = 32;
-// Node / subaperture / layer-node tile edge of the projection kernels.
-constexpr int kNodeTile = 16;
-// Coefficients per workgroup of the element-wise PCG kernels (4 per lane, 256 lanes).
-constexpr int kCoefTile = 1024;
-// Slots per row of the FP64 partial-sum buffer (one per workgroup of a reduction chain).
+// Output tile edge of the inverse DWT (layers smaller than this form one tile of n x n).
+constexpr int kWtTile = 32;
+// Node tile of the projection kernels: 16 x 16 nodes computed, the inner 14 x 14 delivered.
+constexpr int kProjTile = 14;
+// Layer-node tile edge of the transpose projection P^T.
+constexpr int kPtTile = 16;
+// Level-kf quads per tile edge of the fine forward DWT (at most).
+constexpr int kFwdQuads = 8;
+// LDS values available to the P^T tile for its staged node rectangles (all guide stars).
+constexpr int kPtStage = 6144;
+// Guide stars whose transpose tables the P^T tile stages at once (more: the scanning P^T).
+constexpr int kPtMaxWfs = 16;
+// Slots per row of the FP64 partial-sum buffer (one per workgroup of a reduction).
 constexpr int kPartialPitch = 4096;
+// Segments (layers or guide stars) of one launch's tile table.
+constexpr int kMaxSeg = 64;
+
+// Tile decode table of one launch, passed by value as a kernel argument so that a workgroup
+// finds its tile without touching memory written by earlier kernels.  Segment i (a layer or a
+// guide star) owns workgroups [start[i], start[i+1]).
+struct SegTab {
+    int nseg;
+    int start[kMaxSeg + 1];
+    int off[kMaxSeg];     // element offset of the segment's array (layer c_off / sensor v_off)
+    int aux[kMaxSeg];     // layers: first grid line in the per-axis line tables; sensors: s_off
+    int n[kMaxSeg];       // layer n, or sensor n_sub
+    int lt[kMaxSeg];      // layers: log2 of tiles per row; sensors: tiles per row
+    int capr[kMaxSeg];    // P^T (layer segments): staged node rows / columns per guide star
+    int capw[kMaxSeg];
+};
+
+// Per-layer offsets and sizes, as a kernel argument (the projection reads every layer).
+struct LayTab {
+    int off[kMaxLayers];
+    int n[kMaxLayers];
+};
 
 // Per guide star, as the kernels read it.
 struct DevWfs {
@@ -87,21 +117,15 @@ struct DevDm {
     int pad;
 };
 
-// Work-item record of a tiled kernel: a = layer or sensor, b, c = tile origin, d = tile size,
-// e = coefficient offset of the layer, f = its grid size n, g = log2 n, h = tiles of that layer.
-struct Tile {
-    int a, b, c, d, e, f, g, h;
-};
-
 // Inclusive range [lo, hi] of sensor node indices (empty when lo > hi).
 struct Range {
     int lo, hi;
 };
 
 // PCG scalars of Alg. 2 in FP64, kept on the device so no pass needs a host round trip.  The
-// workspace holds three: the states after even and odd passes (written by workgroup 0 of the
-// kernel that consumes a pass's reduction while the others still read the previous state) and
-// one for setup-time reductions.
+// workspace holds four: the states after even and odd passes (the scalar step of pass k reads
+// slot (k-1)&1 and writes slot k&1), one for setup-time reductions, and the (alpha, beta,
+// stopped) of the current pass for the kernels that apply its update.
 struct Scalars {
     double rho, mu, rho_old, alpha, alpha_old, beta;
     int stopped;     // zero residual, breakdown or non-finite: later passes are no-ops
@@ -117,17 +141,17 @@ struct Bufs {
     const DevLayer *lay;
     const DevProj *proj;
     const DevDm *dm;
-    const Tile *idwt_tiles, *node_tiles, *sub_tiles, *lay_tiles, *fine_tiles, *coef_tiles;
-    const Ent<T> *xtab, *ytab;  // [nw][nl][maxnv]
-    const Range *xrng, *yrng;   // [nw][sum_n]: sensor nodes touching each layer grid line
+    const Ent<T> *xtab, *ytab;        // [nw][nl][maxnv]
+    const Range *xrng, *yrng;         // [nw][sum_n]: sensor nodes touching each layer grid line
     const RtabEnt<T> *xrtab, *yrtab;  // [nw][sum_n][kRtabWidth]: the same as (node, weight) lists
-    int maxnv, sum_n, kf;       // table pitch, total grid lines, levels done by the tiled forward DWT
-    const T *jinv;   // [nl][J+1][4] inverse preconditioner per band
-    const T *ad;     // [nl][J+1] alpha D per level
-    T *b_prev, *r, *p, *q, *y, *u, *x, *v, *tmpA, *tmpB, *b, *probe_c, *probe_s;
-    T *r2, *q2;           // second residual / search-direction image buffers (PCG ping-pong)
-    int *over;            // per-sensor flags: a transpose row exceeded kRtabWidth (setup only)
-    double *partials;
+    const int4 *rects;                // [P^T tile][nw]: node rows / columns a tile's lines touch
+    int maxnv, sum_n;                 // table pitch, total grid lines
+    const T *jinv;                    // [nl][J+1][4] inverse preconditioner per band
+    const T *ad;                      // [nl][J+1] alpha D per level
+    T *b_prev, *r, *p, *q, *u, *x, *v, *ll, *probe_c, *probe_s;
+    int *over;                        // per-sensor flags: a transpose row exceeded kRtabWidth (setup)
+    double *partials;                 // [3][kPartialPitch]: (r, z) and (z, alpha D z) per inverse-DWT
+                                      // tile, sum C (Gamma P u)^2 per projection tile
     Scalars *sc;
 };
 
@@ -144,24 +168,26 @@ struct Plan {
     std::vector<DevLayer> dlay;
     std::vector<DevProj> dproj;
     std::vector<DevDm> ddm;
-    std::vector<Tile> idwt_tiles, node_tiles, sub_tiles, lay_tiles, fine_tiles, coef_tiles;
+    // tile tables of the launches (kernel arguments)
+    SegTab seg_wt{}, seg_pt{}, seg_fwd{}, seg_proj{};
+    LayTab laytab{};
+    int n_wt = 0, n_pt = 0, n_fwd = 0, n_proj = 0;  // workgroups of each launch
     int maxnv = 0, sum_n = 0;
-    int kf = 1;        // forward-DWT levels done by the tiled kernel; the rest per layer in one workgroup
-    bool rtab_ok = true;  // every transpose row fits kRtabWidth pairs (else the scanning P^T)
+    int kf = 1;           // forward-DWT levels done on tiles; the rest per layer in one workgroup
+    int tq = 8;           // level-kf quads per tile edge of the fine forward DWT
+    bool rtab_ok = true;  // the staged transpose gather applies (else the scanning P^T)
     int last_slot = 1;    // scalar slot holding the state after the last enqueued solve
-    int tq = 8;        // level-kf quads per tile edge of the tiled forward DWT
     size_t coarse_lds = 0;
+    size_t pt_lds = 0;    // dynamic LDS of the staged P^T (node rectangles of every guide star)
     std::vector<double> ad;     // alpha D per (layer, level)
     std::vector<double> jtab;   // alpha D + tau per (layer, level, orientation), after bind
 
     // workspace layout (byte offsets)
-    size_t o_wfs = 0, o_lay = 0, o_proj = 0, o_dm = 0, o_idwt = 0, o_node = 0, o_sub = 0, o_laytile = 0;
-    size_t o_fine = 0, o_coef = 0, o_xtab = 0, o_ytab = 0, o_xrng = 0, o_yrng = 0;
-    size_t o_jinv = 0, o_ad = 0, o_bprev = 0, o_r = 0, o_p = 0, o_q = 0, o_y = 0, o_u = 0, o_x = 0, o_v = 0;
-    size_t o_tmpA = 0, o_tmpB = 0, o_b = 0, o_probe_c = 0, o_probe_s = 0, o_partials = 0, o_scalars = 0;
-    size_t o_r2 = 0, o_q2 = 0, o_lcount = 0, o_xrtab = 0, o_yrtab = 0;
+    size_t o_wfs = 0, o_lay = 0, o_proj = 0, o_dm = 0;
+    size_t o_xtab = 0, o_ytab = 0, o_xrng = 0, o_yrng = 0, o_xrtab = 0, o_yrtab = 0, o_rects = 0;
+    size_t o_jinv = 0, o_ad = 0, o_bprev = 0, o_r = 0, o_p = 0, o_q = 0, o_u = 0, o_x = 0, o_v = 0;
+    size_t o_ll = 0, o_stage = 0, o_probe_c = 0, o_probe_s = 0, o_partials = 0, o_scalars = 0, o_over = 0;
     size_t ws_bytes = 0;
-    int n_partials = 0;
 
     char *ws = nullptr;
     bool bound = false;
@@ -171,6 +197,8 @@ struct Plan {
 // plan.cpp (host only)
 int plan_create(const fewha_config *cfg, Plan **out);
 int level_band(int n, int J, int row, int col, int *s, int *o);
+// Inverse-DWT cone of a tile: level-s region origins / sizes (level-s index space), s = 0..J.
+void wt_cone(int y0, int x0, int T0, int J, int *loY, int *loX, int *LY, int *LX);
 
 }  // namespace fewha
 

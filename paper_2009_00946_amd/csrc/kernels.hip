@@ -1,29 +1,26 @@
 // HIP kernels of the FEWHA hot path for gfx950 (CDNA4, wave64).
 //
-// Every stage is bandwidth/latency bound (no dense contraction anywhere), so the kernels are
-// gather-only stencils: each output element is written by exactly one lane and results are
-// bitwise reproducible run to run.  Device-scope atomics on a shared address serialise on this
-// chip (tens of ns each), so the per-frame path uses none: reductions leave one FP64 partial
-// per workgroup and the next kernel, which needs the Alg. 2 scalars anyway, sums them itself
-// (every workgroup redundantly, in a fixed order, so all agree bit for bit).
+// The frame is a chain of small dependent launches over an L2-resident working set, so every
+// kernel is built to need one round of independent global loads: a workgroup finds its tile
+// from a table passed as a kernel argument (no tile records in memory), issues all of its loads
+// at once, and then works from LDS and registers.  Every output element is written by exactly
+// one lane and every sum runs in a fixed order, so results are bitwise reproducible.  There are
+// no atomics: reductions leave one FP64 partial per workgroup, summed in fixed order by the
+// kernels that need the result.
 //
-//   k_inv          W^T (= W^-1) of every layer, all J levels in one launch: each workgroup owns
-//                  a square output tile and rebuilds, from the coarsest level down, only the cone
-//                  of coefficients that tile depends on, loaded in one batch into LDS.  Modes:
-//                  plain c | z = J^-1 r | the Alg. 2 update of the previous pass fused in front.
-//   k_nodes_m      per WFS node tile: P (bilinear ray gather from all layers through per-axis
-//                  cell tables, LGS cone included), Gamma, C_eta^-1 and Gamma^T through LDS
-//                  (the paper's Kernel-2 stage).  k_nodes: Gamma^T C s / Gamma^T mask s.
-//   k_slopes       mask Gamma P u on subaperture tiles (forward operator A).
-//   k_pt_tab       P^T as a gather per layer node through the transpose tables (the sensor nodes
-//                  and weights that touch each layer grid line, the very entries P uses): the
-//                  exact transpose of P without atomics.  k_pt_scan: same result by scanning
-//                  the cell tables, for geometries whose transpose rows exceed the table width.
-//   k_fwd_fine     the first kf levels of W for every layer, on tiles of level-kf quads with
-//                  their halo in LDS; epilogues: alpha D z and the PCG dot-product partials, or
-//                  the right-hand side's warm-restart residual update, or alpha D c.
-//   k_fwd_coarse   the remaining levels, one workgroup per layer, LDS resident; same epilogues.
-//   k_update_last  the last Alg. 2 update of a solve.
+// One PCG pass of Alg. 2 (Jacobi-preconditioned, one reduction point) is four launches:
+//   k_wt<pcg>    z = J^-1 r and u = W^T z on 32 x 32 output tiles (all J levels per tile from a
+//                cone of coefficients); partials of rho = (r, z) and (z, alpha D z)
+//   k_proj<M>    per 16 x 16 node tile of each guide star: phi = P u (bilinear rays, cone effect),
+//                Gamma, C_eta^-1, Gamma^T -> v; partial of sum C (Gamma P u)^2
+//   k_pt         x = P^T v on 16 x 16 layer tiles, from staged node rectangles and the transpose
+//                tables (the same matrix entries as P)
+//   k_fwd/k_coarse<pcg>  y = W x + alpha D z on the fine levels (tiles) and the coarse levels
+//                (one workgroup per layer), then the pass's update in place.
+// The denominator mu = (M z, z) is formed from the partials as (C Gamma P W^T z, Gamma P W^T z)
+// + (z, alpha D z): W is orthonormal and every adjoint here is the exact transpose of its
+// forward operator, so this equals (y, z) without waiting for y, and the update of a pass can
+// run in the same launch that produces y.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -34,11 +31,45 @@ namespace fewha {
 
 namespace {
 
-constexpr int kBlock = 256;
+constexpr int kB = 256;       // workgroup size of the tile kernels
+constexpr int kCB = 1024;     // workgroup size of the per-layer coarse forward DWT
+constexpr size_t kCoarseLdsMax = 150 * 1024;  // dynamic LDS of the coarse forward DWT (at most)
 
 // ---------------------------------------------------------------------------------------------
-// Geometry helpers
+// Kernel-argument tables and small helpers
 // ---------------------------------------------------------------------------------------------
+struct InvVar {               // sigma^-2 per guide star
+    double v[kMaxWfs];
+};
+
+struct WfsOff {               // node grid offset and n_sub per guide star
+    int v_off[kMaxWfs];
+    int n_sub[kMaxWfs];
+};
+
+struct PupilArgs {            // subaperture (i, j) of guide star g is active iff its centre is in
+    double D;                 // the annulus r_in^2 <= r^2 <= r_out^2 (d = D / n_sub, x0 = -D/2)
+    double r_out2, r_in2;
+};
+
+struct TileId {
+    int seg, loc;
+};
+
+__device__ __forceinline__ TileId find_tile(const SegTab &S) {
+    const int b = blockIdx.x;
+    int s = 0;
+    for (int i = 1; i < S.nseg; ++i) s = (b >= S.start[i]) ? i : s;
+    return {s, b - S.start[s]};
+}
+
+__device__ __forceinline__ bool subap_active(const PupilArgs &pa, int ns, int i, int j) {
+    const double d = pa.D / ns, x0 = -0.5 * pa.D;
+    const double xc = ((double)j + 0.5) * d + x0, yc = ((double)i + 0.5) * d + x0;
+    const double r2 = xc * xc + yc * yc;
+    return r2 <= pa.r_out2 && r2 >= pa.r_in2;
+}
+
 struct Cell {
     int k0;      // lower grid index
     double t;    // fractional position in [0, 1]
@@ -56,58 +87,19 @@ __device__ __forceinline__ double ray_coord(const DevProj &pr, const DevWfs &W, 
     return X / L.spacing + L.half;
 }
 
-__device__ __forceinline__ bool subap_active(const DevWfs &W, int i, int j) {
-    double xc = ((double)j + 0.5) * W.d + W.x0, yc = ((double)i + 0.5) * W.d + W.x0;
-    double r2 = xc * xc + yc * yc;
-    return r2 <= W.r_out2 && r2 >= W.r_in2;
-}
-
-// phi_g(i, j) = sum_l bilinear(u_l at the ray point)  (P of Sec. 2.1), via the cell tables.
-template <typename T>
-__device__ __forceinline__ T project_node(const T *__restrict__ u, const Bufs<T> &B, int g, int nl, int i, int j) {
-    T acc = 0;
-    const Ent<T> *xt = B.xtab + (long)g * nl * B.maxnv;
-    const Ent<T> *yt = B.ytab + (long)g * nl * B.maxnv;
-    for (int l = 0; l < nl; ++l) {
-        const Ent<T> ex = xt[l * B.maxnv + j], ey = yt[l * B.maxnv + i];
-        const int n = B.lay[l].n;
-        const T *U = u + B.lay[l].c_off + (long)ey.k0 * n + ex.k0;
-        acc += (ey.w0 * ex.w0) * U[0] + (ey.w0 * ex.w1) * U[1] + (ey.w1 * ex.w0) * U[n] + (ey.w1 * ex.w1) * U[n + 1];
-    }
-    return acc;
-}
-
-// Level and orientation of Mallat position (row, col) of an n x n pyramid with J levels.
-__device__ __forceinline__ void band_at(int row, int col, int n, int log2n, int J, int &s, int &o) {
-    const int v = row > col ? row : col;
-    if (v < (n >> J)) {
-        s = J;
-        o = 0;
-    } else {
-        const int lv = 31 - __clz(v);
-        const int m = 1 << lv;
-        s = log2n - lv;
-        o = (row < m) ? 1 : ((col < m) ? 2 : 3);
-    }
-}
-
-// ---------------------------------------------------------------------------------------------
-// Reductions and the Alg. 2 scalars
-// ---------------------------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     return v;
 }
 
-// Sum over the block in fixed order; result valid in thread 0.
+// Sum over the block in fixed order; the result is returned to every lane.
 __device__ __forceinline__ double block_sum(double v, double *sh) {
     v = wave_sum(v);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0) sh[wid] = v;
     __syncthreads();
     double t = 0.0;
-    if (threadIdx.x == 0)
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
     __syncthreads();
     return t;
 }
@@ -155,475 +147,418 @@ __device__ Scalars alg2_step(const Scalars &prev, double R, double Mu, int k) {
     return nx;
 }
 
-// Every workgroup of a consumer kernel: sum the partials of pass k in fixed order, step the
-// scalar recurrence from sc[(k-1)&1], and (workgroup 0) publish the new state to sc[k&1] and
-// sqrt(rho) to resnorm[k].  Returns (alpha, beta, stopped) to all lanes.
 struct StepOut {
     double alpha, beta;
     int stopped;
 };
 
-__device__ StepOut consume_pass(const double *__restrict__ partials, int nparts, Scalars *sc, int k, double *resnorm) {
-    __shared__ double sh[16];
-    __shared__ StepOut so;
-    double a = 0.0, b = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
-        a += partials[i];
-        b += partials[kPartialPitch + i];
+// The scalar step of pass k, done once by one extra workgroup of the P^T launch (whose inputs,
+// the partials of the inverse DWT and of the projection, are complete by then): reduce the
+// partials in fixed order, step the recurrence from sc[(k-1)&1], store (alpha, beta, stopped) in
+// sc[3] for the forward transform that applies the update and, if `publish`, the new state in
+// sc[k&1] and sqrt(rho) in resnorm[k].
+__device__ void scalar_step(const double *__restrict__ part, int nwt, int nproj, Scalars *sc, int k,
+                            double *resnorm, int publish) {
+    __shared__ double sh[kB / 64];
+    double r = 0.0, m = 0.0;
+    for (int i = threadIdx.x; i < nwt; i += blockDim.x) {
+        r += part[i];
+        m += part[kPartialPitch + i];
     }
-    const double R = block_sum(a, sh);
-    const double Mu = block_sum(b, sh);
+    for (int i = threadIdx.x; i < nproj; i += blockDim.x) m += part[2 * kPartialPitch + i];
+    const double R = block_sum(r, sh);
+    const double Mu = block_sum(m, sh);
     if (threadIdx.x == 0) {
         const Scalars prev = sc[(k - 1) & 1];
         const Scalars nx = alg2_step(prev, R, Mu, k);
-        so = StepOut{nx.alpha, nx.beta, nx.stopped};
-        if (blockIdx.x == 0) {
+        Scalars st = nx;
+        st.stopped = nx.stopped;
+        sc[3] = st;
+        if (publish) {
             sc[k & 1] = nx;
             if (resnorm && !prev.stopped && isfinite(R)) resnorm[k] = sqrt(R);
         }
     }
-    __syncthreads();
-    return so;
 }
 
-// ---------------------------------------------------------------------------------------------
-// W^T: multi-level inverse DWT in one launch, with the PCG update fused in front of it.
-//
-// The whole cone of a tile (every level, every band) is fetched in one batch of independent
-// loads into LDS, then the J levels of synthesis run from LDS.  In the update mode the loads
-// bring r_{k-1}, y_{k-1}, q_{k-2}; the Alg. 2 update of pass k-1 is evaluated for every cone
-// coefficient, the coefficients this tile owns are written back (p, q, c and the new residual),
-// and the transform runs on z = J^-1 r_k.  Ownership: at level s a tile owns the indices
-// [y0 >> s, (y0 + T0) >> s) when T0 >= 2^s, else index y0 >> s if y0 is a multiple of 2^s
-// (likewise in x), which partitions every band.
-// ---------------------------------------------------------------------------------------------
-constexpr int kInvBlock = 512;
-constexpr int kInvSegMax = 4096;  // cone of a 32 x 32 tile, rows padded to power-of-two pitches
+// (alpha, beta, stopped) of the current pass, as left in sc[3] by the P^T launch.
+__device__ __forceinline__ StepOut read_step(const Scalars *sc) {
+    const Scalars st = sc[3];
+    return StepOut{st.alpha, st.beta, st.stopped};
+}
 
-// ceil(log2(v)) for 1 <= v <= 2^30
-__device__ __forceinline__ int clog2(int v) { return v <= 1 ? 0 : 32 - __clz(v - 1); }
+// float-reciprocal quotient of small non-negative integers (a < 2^20, b <= 2^10): exact
+__device__ __forceinline__ int small_div(int a, float rb) { return (int)(((float)a + 0.5f) * rb); }
+
+// ---------------------------------------------------------------------------------------------
+// W^T: the inverse DWT of every layer, all J levels in one launch.
+//
+// A workgroup owns a T0 x T0 output tile (T0 = min(32, n)).  In level-s index space the tile
+// depends on the region [lo_s, hi_s] per axis, lo_s = ((lo_{s-1} >> 1) - 2) rounded down to even,
+// hi_s = hi_{s-1} >> 1 (periodic, so indices wrap modulo n >> s).  The whole cone (three detail
+// bands per level and the coarsest LL) arrives in one batch of loads, then the J synthesis
+// levels run in LDS: along y (pairs of output rows share their three taps), then along x.
+// In PCG mode the cone holds z = J^-1 r and the workgroup reduces (r, z) and (z, alpha D z) over
+// the coefficients it owns (at level s: indices [y0 >> s, (y0 + T0) >> s), or y0 >> s alone when
+// T0 < 2^s and y0 is a multiple of 2^s), which partition every band.
+// ---------------------------------------------------------------------------------------------
+constexpr int kWtLL = 18 * 18;   // LL_{s-1} region of a level s >= 2
+constexpr int kWtX = 32 * 18;    // y-synthesis output: (rows of level s-1) x (columns of level s)
+constexpr int kWB = 256;         // workgroup of one inverse-DWT tile
+constexpr int kWtSlots = 9 + 3 + (kMaxJ - 2);
+
+// Cone layout: level 1 in nine passes of 8 rows x 32 lanes, level 2 in three passes of 16 rows x
+// 16 lanes, each coarser level in one pass of 32 rows x 8 lanes.  Pass p of level s is LDS slot
+// wt_slot0(s) + p (kWB values, in lane order), so level s is a row-major block of pitch
+// 2^wt_lanes_log2(s) whose rows are band * LY_s + r (bands x-high, y-high, HH, and LL at s = J).
+__host__ __device__ constexpr int wt_passes(int s) { return s == 1 ? 9 : (s == 2 ? 3 : 1); }
+__host__ __device__ constexpr int wt_lanes_log2(int s) { return s == 1 ? 5 : (s == 2 ? 4 : 3); }
+__host__ __device__ constexpr int wt_slot0(int s) { return s == 1 ? 0 : (s == 2 ? 9 : 12 + (s - 3)); }
+
+// Asynchronous copy of one 4-byte value per active lane from global memory into LDS at
+// wave_base[lane] (lane = threadIdx.x & 63) without registers; complete at s_waitcnt vmcnt(0).
+// wave_base must be the same for every lane of the wave.
+__device__ __forceinline__ void g2lds(const float *gp, float *wave_base) {
+    __builtin_amdgcn_global_load_lds(gp, (__attribute__((address_space(3))) void *)wave_base, 4, 0, 0);
+}
+
+__device__ __forceinline__ void lds_fence() {
+    __builtin_amdgcn_s_waitcnt(0);  // every outstanding load, including those into LDS
+    __syncthreads();
+}
+
+enum { kWtPlain = 0, kWtPcg = 1 };
 
 template <typename T, int MODE>
-__global__ __launch_bounds__(kInvBlock) void k_inv(Bufs<T> B, int J, InvArgs A, Taps<T> tp) {
-    constexpr int TILE = kIdwtTile;
-    constexpr int MAXI = kInvSegMax / kInvBlock;
-    __shared__ T sSeg[kInvSegMax];
-    __shared__ T sL0[(TILE / 2 + 2) * TILE], sL1[(TILE / 2 + 2) * TILE];  // level-1 rows x pitch 32
-    __shared__ T sAX[TILE * TILE], sDX[TILE * TILE];
-    __shared__ int shLoY[kMaxJ + 1], shLoX[kMaxJ + 1], shLnY[kMaxJ + 1], shLnX[kMaxJ + 1], shLp[kMaxJ + 1];
-    __shared__ int shSeg[kMaxJ + 2];
-    __shared__ T sJinv[(kMaxJ + 1) * 4];
+__global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src, T *__restrict__ out, Bufs<T> B,
+                                           Taps<T> tp, int J) {
+    __shared__ T sCone[kWtSlots * kWB];
+    __shared__ T sLL[2][kWtLL];
+    __shared__ T sXl[kWtX], sXh[kWtX];
+    __shared__ int sLoY[kMaxJ + 1], sLoX[kMaxJ + 1], sLY[kMaxJ + 1], sLX[kMaxJ + 1];
+    __shared__ T sJi[(kMaxJ + 1) * 4], sAd[kMaxJ + 1];
+    __shared__ double sRed[kWB / 64];
 
-    const Tile t = B.idwt_tiles[blockIdx.x];
-    const int l = t.a, y0 = t.b, x0 = t.c, T0 = t.d, n = t.f;
-    const long coff = t.e;
-    // Cone bounds per level, computed by every lane in registers (uniform values).  Each band
-    // region is stored with rows padded to a power-of-two pitch, so decoding an item needs only
-    // compares and shifts.
-    int loY[kMaxJ + 1], loX[kMaxJ + 1], lnY[kMaxJ + 1], lnX[kMaxJ + 1], lp[kMaxJ + 1], seg[kMaxJ + 2];
+    const int tid = threadIdx.x;
+    const TileId id = find_tile(S);
+    const int l = id.seg, n = S.n[l], lt = S.lt[l];
+    const int T0 = n < kWtTile ? n : kWtTile;
+    const int y0 = (id.loc >> lt) * T0, x0 = (id.loc & ((1 << lt) - 1)) * T0;
+    const long coff = S.off[l];
+
+    // cone bounds (uniform; compile-time indexed, so they stay in scalar registers)
+    int loY[kMaxJ + 1], loX[kMaxJ + 1], LY[kMaxJ + 1], LX[kMaxJ + 1];
     {
-        int ly = y0, hy = y0 + T0 - 1, lx = x0, hx = x0 + T0 - 1, off = 0;
+        int ly = y0, hy = y0 + T0 - 1, lx = x0, hx = x0 + T0 - 1;
         loY[0] = ly;
         loX[0] = lx;
-        lnY[0] = T0;
-        lnX[0] = T0;
-        lp[0] = clog2(T0);
-        seg[0] = 0;
+        LY[0] = T0;
+        LX[0] = T0;
 #pragma unroll
         for (int s = 1; s <= kMaxJ; ++s) {
-            ly = (ly >> 1) - 2;
+            ly = ((ly >> 1) - 2) & ~1;
             hy >>= 1;
-            lx = (lx >> 1) - 2;
+            lx = ((lx >> 1) - 2) & ~1;
             hx >>= 1;
             loY[s] = ly;
             loX[s] = lx;
-            lnY[s] = hy - ly + 1;
-            lnX[s] = hx - lx + 1;
-            lp[s] = clog2(lnX[s]);
-            seg[s] = off;
-            if (s <= J) off += 3 * (lnY[s] << lp[s]);
+            LY[s] = hy - ly + 1;
+            LX[s] = hx - lx + 1;
         }
-        seg[kMaxJ + 1] = off;  // the coarsest LL starts here
     }
-    int lnYJ = 0, lpJ = 0;
-#pragma unroll
-    for (int s = 1; s <= kMaxJ; ++s)
-        if (s == J) {
-            lnYJ = lnY[s];
-            lpJ = lp[s];
-        }
-    const int llOff = seg[kMaxJ + 1], total = llOff + (lnYJ << lpJ);
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
 #pragma unroll
         for (int s = 0; s <= kMaxJ; ++s) {
-            shLoY[s] = loY[s];
-            shLoX[s] = loX[s];
-            shLnY[s] = lnY[s];
-            shLnX[s] = lnX[s];
-            shLp[s] = lp[s];
-            shSeg[s] = seg[s];
+            sLoY[s] = loY[s];
+            sLoX[s] = loX[s];
+            sLY[s] = LY[s];
+            sLX[s] = LX[s];
         }
-        shSeg[kMaxJ + 1] = llOff;
     }
-    if (MODE != kInvPlain && threadIdx.x < (J + 1) * 4) sJinv[threadIdx.x] = B.jinv[l * (J + 1) * 4 + threadIdx.x];
+    // preconditioner and prior of the layer's bands (PCG), loaded with the cone
+    T jl = 1;
+    if (MODE == kWtPcg) {
+        const int tj = min(tid, (J + 1) * 5 - 1);
+        jl = tj < (J + 1) * 4 ? B.jinv[l * (J + 1) * 4 + tj] : B.ad[l * (J + 1) + tj - (J + 1) * 4];
+    }
 
-    double alpha = 0.0, beta = 0.0;
-    int stopped = 0;
-    if constexpr (MODE == kInvUpdate) {
-        const StepOut so = consume_pass(B.partials, A.nparts, B.sc, A.kprev, A.resnorm);
-        alpha = so.alpha;
-        beta = so.beta;
-        stopped = so.stopped;
-    }
-    const T *__restrict__ src = static_cast<const T *>(A.src);
-    const T *__restrict__ yin = static_cast<const T *>(A.yv);
-    const T *__restrict__ qin = static_cast<const T *>(A.qold);
-    T *__restrict__ pio = B.p;
-    T *__restrict__ cio = static_cast<T *>(A.c);
-    __syncthreads();
-    // ---- one batch of independent loads: the whole cone (plus owned-only operands) ----
-    for (int base = 0; base < total; base += MAXI * kInvBlock) {
-        long gi[MAXI];
-        int bnd[MAXI];
-        bool own[MAXI];
-        T rv[MAXI], yv[MAXI], qv[MAXI], pv[MAXI], cv[MAXI];
+    // ---- one batch of independent loads: the whole cone, straight into LDS ----
 #pragma unroll
-        for (int c = 0; c < MAXI; ++c) {
-            const int k = base + c * kInvBlock + (int)threadIdx.x;
-            gi[c] = -1;
-            own[c] = false;
-            if (k >= total) continue;
-            // level (compare chain over uniform offsets), band, row, column (shifts)
-            int s = J, o = 0, ly = 0, lx = 0, nxs = 1, lps = 0, rem = k - llOff;
+    for (int s = 1; s <= kMaxJ; ++s) {
+        if (s <= J) {
+            const int lp = wt_lanes_log2(s), ly = LY[s], lx = LX[s], m = n >> s, mk = m - 1;
 #pragma unroll
-            for (int ss = 1; ss <= kMaxJ; ++ss) {
-                if (ss <= J && k >= seg[ss] && k < seg[ss + 1 <= kMaxJ ? ss + 1 : kMaxJ + 1]) s = ss;
-            }
-#pragma unroll
-            for (int ss = 1; ss <= kMaxJ; ++ss)
-                if (ss == s) {
-                    ly = loY[ss];
-                    lx = loX[ss];
-                    nxs = lnX[ss];
-                    lps = lp[ss];
-                }
-            if (k < llOff) {
-                int lny = 0, sg = 0;
-#pragma unroll
-                for (int ss = 1; ss <= kMaxJ; ++ss)
-                    if (ss == s) {
-                        lny = lnY[ss];
-                        sg = seg[ss];
-                    }
-                const int bsz = lny << lps, kk = k - sg;
-                o = 1 + (kk >= bsz) + (kk >= 2 * bsz);
-                rem = kk - (o - 1) * bsz;
-            }
-            const int r = rem >> lps, q = rem & ((1 << lps) - 1);
-            if (q >= nxs) continue;  // row padding
-            const int m = n >> s, msk = m - 1;
-            const int uy = ly + r, ux = lx + q;
-            const int gr = uy & msk, gc = ux & msk;
-            const int row = gr + ((o == 2 || o == 3) ? m : 0), col = gc + ((o == 1 || o == 3) ? m : 0);
-            gi[c] = coff + (long)row * n + col;
-            bnd[c] = s * 4 + o;
-            if constexpr (MODE == kInvUpdate) {
-                const int ts = T0 >> s, msk2 = (1 << s) - 1;
-                const bool oy = ts >= 1 ? (uy >= (y0 >> s) && uy < (y0 >> s) + ts) : ((y0 & msk2) == 0 && uy == (y0 >> s));
-                const bool ox = ts >= 1 ? (ux >= (x0 >> s) && ux < (x0 >> s) + ts) : ((x0 & msk2) == 0 && ux == (x0 >> s));
-                own[c] = oy && ox;
-            }
-            rv[c] = src[gi[c]];
-            if constexpr (MODE == kInvUpdate) {
-                yv[c] = yin[gi[c]];
-                qv[c] = A.first_pass ? (T)0 : qin[gi[c]];
-                if (own[c]) {
-                    pv[c] = A.first_pass ? (T)0 : pio[gi[c]];
-                    cv[c] = cio[gi[c]];
+            for (int p = 0; p < wt_passes(s); ++p) {
+                const int rowi = (tid >> lp) + p * (kWB >> lp), q = tid & ((1 << lp) - 1);
+                const int bi = (rowi >= ly) + (rowi >= 2 * ly) + (rowi >= 3 * ly);
+                const int r = rowi - bi * ly, o = bi == 3 ? 0 : bi + 1;
+                const int gr = ((loY[s] + r) & mk) + (o >= 2 ? m : 0);
+                const int gc = ((loX[s] + q) & mk) + ((o & 1) ? m : 0);
+                if (q < lx && rowi < (s == J ? 4 : 3) * ly) {
+                    const T *gp = src + coff + (long)gr * n + gc;
+                    T *dst = sCone + (wt_slot0(s) + p) * kWB;
+                    if constexpr (sizeof(T) == 4) g2lds(gp, dst + (tid & ~63));
+                    else dst[tid] = *gp;
                 }
             }
         }
-#pragma unroll
-        for (int c = 0; c < MAXI; ++c) {
-            if (gi[c] < 0) continue;
-            T val = rv[c];
-            if constexpr (MODE == kInvFirst) {
-                val = rv[c] * sJinv[bnd[c]];
-            } else if constexpr (MODE == kInvUpdate) {
-                const T ji = sJinv[bnd[c]];
-                T rn = rv[c];
-                if (!stopped) {
-                    const T zo = rv[c] * ji;
-                    const T qn = A.first_pass ? yv[c] : yv[c] + (T)beta * qv[c];
-                    rn = rv[c] - (T)alpha * qn;
-                    if (own[c]) {
-                        const T pn = A.first_pass ? zo : zo + (T)beta * pv[c];
-                        pio[gi[c]] = pn;
-                        static_cast<T *>(A.qnew)[gi[c]] = qn;
-                        cio[gi[c]] = cv[c] + (T)alpha * pn;
-                    }
-                }
-                if (own[c]) static_cast<T *>(A.rnew)[gi[c]] = rn;
-                val = rn * ji;
-            }
-            sSeg[base + c * kInvBlock + (int)threadIdx.x] = val;
-        }
     }
-    __syncthreads();
+    if (MODE == kWtPcg && tid < (J + 1) * 5) {
+        if (tid < (J + 1) * 4) sJi[tid] = jl;
+        else sAd[tid - (J + 1) * 4] = jl;
+    }
+    lds_fence();
 
-    // ---- synthesis from the coarsest level, all in LDS (power-of-two row pitches) ----
-    const T *LL = sSeg + llOff;
-    int llp = lpJ;
-    T *NX = sL0;
-    T *__restrict__ outp = static_cast<T *>(A.out);
+    // PCG: (r, z) and (z, alpha D z) over the coefficients this tile owns.  At level s the owned
+    // indices form a contiguous run inside the staged region of every band (rows oy0 - loY_s ..,
+    // columns ox0 - loX_s ..), so the lanes sweep (band, row, column) of the owned blocks.
+    double rho = 0.0, dz = 0.0;
+    if (MODE == kWtPcg) {
+        for (int s = 1; s <= J; ++s) {
+            const int ts = T0 >> s, sh = (1 << s) - 1;
+            const int ny = ts >= 1 ? ts : ((y0 & sh) == 0 ? 1 : 0), nx = ts >= 1 ? ts : ((x0 & sh) == 0 ? 1 : 0);
+            const int nb = s == J ? 4 : 3, tot = nb * ny * nx;
+            if (tot == 0) continue;
+            const int ry = (y0 >> s) - sLoY[s], rx = (x0 >> s) - sLoX[s], lys = sLY[s];
+            const int pb = 1 << wt_lanes_log2(s), base = wt_slot0(s) * kWB;
+            const int nyx = ny * nx;
+            for (int it = tid; it < tot; it += kWB) {
+                const int bi = it / nyx, rem = it - bi * nyx, r = rem / nx, c = rem - r * nx;
+                const T rv = sCone[base + (bi * lys + ry + r) * pb + rx + c];
+                const T z = rv * sJi[s * 4 + (bi == 3 ? 0 : bi + 1)];
+                rho += (double)rv * (double)z;
+                dz += (double)sAd[s] * (double)z * (double)z;
+            }
+        }
+    }
+
+    // ---- synthesis, coarsest level first, all in LDS.  In PCG mode the cone holds r: the
+    // band scales J^-1 are folded into the taps (the synthesized LL of levels below J is z-space
+    // already). ----
+    const T *LLs = sCone + wt_slot0(J) * kWB + 3 * sLY[J] * (1 << wt_lanes_log2(J));
+    int pLL = 1 << wt_lanes_log2(J);
+    int cur = 0;
     for (int s = J; s >= 1; --s) {
-        const int ny = shLnY[s - 1], nxk = shLnX[s], nx = shLnX[s - 1];
-        const int oy = shLoY[s - 1], ky = shLoY[s], ox = shLoX[s - 1], kx = shLoX[s];
-        const int bp = shLp[s], op = shLp[s - 1];
-        const int bsz = shLnY[s] << bp;
-        const T *HL = sSeg + shSeg[s], *LH = HL + bsz, *HH = LH + bsz;
-        // undo the y analysis: (LL, x-low/y-high) -> x-low rows, (x-high/y-low, HH) -> x-high rows
-        for (int idx = threadIdx.x; idx < (ny << bp); idx += blockDim.x) {
-            const int r = idx >> bp, q = idx & ((1 << bp) - 1);
-            if (q >= nxk) continue;
-            const int y = oy + r, p = y & 1, kb = (y >> 1) - ky;
-            T a = 0, d = 0;
+        const int LYs = sLY[s], LXs = sLX[s], LYo = sLY[s - 1], LXo = sLX[s - 1];
+        const int pB = 1 << wt_lanes_log2(s);
+        const int dY = (sLoY[s - 1] >> 1) - sLoY[s], dX = (sLoX[s - 1] >> 1) - sLoX[s];
+        const T *B1 = sCone + wt_slot0(s) * kWB, *B2 = B1 + LYs * pB, *B3 = B2 + LYs * pB;
+        const T jL = (MODE == kWtPcg && s == J) ? sJi[s * 4] : (T)1;
+        const T j1 = MODE == kWtPcg ? sJi[s * 4 + 1] : (T)1, j2 = MODE == kWtPcg ? sJi[s * 4 + 2] : (T)1,
+                j3 = MODE == kWtPcg ? sJi[s * 4 + 3] : (T)1;
+        const int npair = (LYo + 1) >> 1;
+        const float rLXs = 1.0f / (float)LXs;
+        // y: (LL, x-low/y-high) -> x-low rows; (x-high/y-low, HH) -> x-high rows; two rows per item
+        for (int it = tid; it < npair * LXs; it += kWB) {
+            const int a = small_div(it, rLXs), c = it - a * LXs;
+            T xl0 = 0, xl1 = 0, xh0 = 0, xh1 = 0;
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                const int rr = kb - j;
-                a += tp.h[p + 2 * j] * LL[(rr << llp) + q] + tp.g[p + 2 * j] * LH[(rr << bp) + q];
-                d += tp.h[p + 2 * j] * HL[(rr << bp) + q] + tp.g[p + 2 * j] * HH[(rr << bp) + q];
+                const int row = a + dY - j;
+                const T ll = jL * LLs[row * pLL + c], b1 = j1 * B1[row * pB + c], b2 = j2 * B2[row * pB + c],
+                        b3 = j3 * B3[row * pB + c];
+                xl0 += tp.h[2 * j] * ll + tp.g[2 * j] * b2;
+                xl1 += tp.h[2 * j + 1] * ll + tp.g[2 * j + 1] * b2;
+                xh0 += tp.h[2 * j] * b1 + tp.g[2 * j] * b3;
+                xh1 += tp.h[2 * j + 1] * b1 + tp.g[2 * j + 1] * b3;
             }
-            sAX[idx] = a;
-            sDX[idx] = d;
+            sXl[(2 * a) * LXs + c] = xl0;
+            sXl[(2 * a + 1) * LXs + c] = xl1;
+            sXh[(2 * a) * LXs + c] = xh0;
+            sXh[(2 * a + 1) * LXs + c] = xh1;
         }
         __syncthreads();
-        // undo the x analysis
-        for (int idx = threadIdx.x; idx < (ny << op); idx += blockDim.x) {
-            const int r = idx >> op, q = idx & ((1 << op) - 1);
-            if (q >= nx) continue;
-            const int x = ox + q, p = x & 1, kb = (x >> 1) - kx;
-            T v = 0;
+        // x: two output columns per item
+        const int nq = (LXo + 1) >> 1;
+        const float rnq = 1.0f / (float)nq;
+        T *dst = sLL[cur ^ 1];
+        for (int it = tid; it < LYo * nq; it += kWB) {
+            const int y = small_div(it, rnq), b = it - y * nq;
+            T o0 = 0, o1 = 0;
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                const int at = (r << bp) + kb - j;
-                v += tp.h[p + 2 * j] * sAX[at] + tp.g[p + 2 * j] * sDX[at];
+                const int at = y * LXs + b + dX - j;
+                const T xl = sXl[at], xh = sXh[at];
+                o0 += tp.h[2 * j] * xl + tp.g[2 * j] * xh;
+                o1 += tp.h[2 * j + 1] * xl + tp.g[2 * j + 1] * xh;
             }
-            if (s > 1) NX[idx] = v;
-            else outp[coff + (long)(oy + r) * n + ox + q] = v;
+            if (s > 1) {
+                dst[y * LXo + 2 * b] = o0;
+                if (2 * b + 1 < LXo) dst[y * LXo + 2 * b + 1] = o1;
+            } else {
+                T *orow = out + coff + (long)(y0 + y) * n + x0 + 2 * b;
+                orow[0] = o0;
+                orow[1] = o1;
+            }
         }
         __syncthreads();
-        LL = NX;
-        llp = op;
-        NX = (NX == sL0) ? sL1 : sL0;
+        LLs = dst;
+        pLL = LXo;
+        cur ^= 1;
     }
-}
-
-// Last Alg. 2 update of a solve (elementwise); the residual lands in the state buffer B.r.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_update_last(T *__restrict__ c, Bufs<T> B, int J, const T *__restrict__ rin,
-                                                        const T *__restrict__ qold, T *__restrict__ qnew, int first,
-                                                        int nparts, int kprev, double *resnorm) {
-    constexpr int E = kCoefTile / kBlock;
-    __shared__ T sJ[(kMaxJ + 1) * 4];
-    const Tile t = B.coef_tiles[blockIdx.x];
-    if (threadIdx.x < (J + 1) * 4) sJ[threadIdx.x] = B.jinv[t.a * (J + 1) * 4 + threadIdx.x];
-    const StepOut so = consume_pass(B.partials, nparts, B.sc, kprev, resnorm);
-    T *__restrict__ pp = B.p;
-    T *__restrict__ rr = B.r;
-    const T *__restrict__ yy = B.y;
-    T rv[E], pv[E], yv[E], qv[E], cv[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int loc = t.b + e * kBlock + (int)threadIdx.x;
-        if (loc >= t.b + t.c) continue;
-        const long i = t.e + loc;
-        rv[e] = rin[i];
-        yv[e] = yy[i];
-        cv[e] = c[i];
-        pv[e] = first ? (T)0 : pp[i];
-        qv[e] = first ? (T)0 : qold[i];
-    }
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int loc = t.b + e * kBlock + (int)threadIdx.x;
-        if (loc >= t.b + t.c) continue;
-        const long i = t.e + loc;
-        if (so.stopped) {
-            rr[i] = rv[e];
-            continue;
+    if (MODE == kWtPcg) {
+        const double a = block_sum(rho, sRed), b = block_sum(dz, sRed);
+        if (tid == 0) {
+            B.partials[blockIdx.x] = a;
+            B.partials[kPartialPitch + blockIdx.x] = b;
         }
-        int s, o;
-        band_at(loc >> t.g, loc & (t.f - 1), t.f, t.g, J, s, o);
-        const T z = rv[e] * sJ[s * 4 + o];
-        const T p = first ? z : z + (T)so.beta * pv[e];
-        const T q = first ? yv[e] : yv[e] + (T)so.beta * qv[e];
-        pp[i] = p;
-        qnew[i] = q;
-        c[i] = cv[e] + (T)so.alpha * p;
-        rr[i] = rv[e] - (T)so.alpha * q;
     }
 }
 
 // ---------------------------------------------------------------------------------------------
-// Node-tile kernels (Kernel-2 stage): P, Gamma, C_eta^-1, Gamma^T.
+// Node tiles of a guide star: 16 x 16 nodes computed (a one-node halo), the inner 14 x 14
+// delivered; the 15 x 15 subapertures between them carry the slopes.
 // ---------------------------------------------------------------------------------------------
-constexpr int kNodeBlock = 512;
+constexpr int kPR = kProjTile + 2;   // computed region edge (16)
+constexpr int kPS = kProjTile + 1;   // subaperture block edge (15)
+constexpr int kProjLch = 12;         // layers whose bilinear loads are in flight together
+constexpr int kProjEntSlots = (2 * kMaxLayers * kPR + kB - 1) / kB;
 
-// y-part of M on one node tile: phi on the tile plus a one-node halo (one node per lane), then
-// weighted Fried slopes and Gamma^T from LDS.  The cell-table entries of the tile's rows and
-// columns are staged in LDS per chunk of layers; each lane then issues the bilinear loads of
-// eight layers at a time before accumulating them in layer order.
-template <typename T>
-__global__ __launch_bounds__(kNodeBlock) void k_nodes_m(const T *__restrict__ u, T *__restrict__ v, Bufs<T> B,
-                                                        int nl) {
-    constexpr int NT = kNodeTile, NP = NT + 2, NS = NT + 1, LMAX = 16, LCH = 8;
-    __shared__ int sXk[LMAX * NP], sYk[LMAX * NP];
-    __shared__ T sXw0[LMAX * NP], sXw1[LMAX * NP], sYw0[LMAX * NP], sYw1[LMAX * NP];
-    __shared__ long sOff[LMAX];
-    __shared__ int sN[LMAX];
-    __shared__ T sPhi[NP * NP];
-    __shared__ T sSx[NS * NS], sSy[NS * NS];
-    const Tile t = B.node_tiles[blockIdx.x];
-    const DevWfs W = B.wfs[t.a];
-    const int g = t.a, ns = W.n_sub, nv = W.nv, i0 = t.b, j0 = t.c;
-    const int a = (int)threadIdx.x / NP, b = (int)threadIdx.x - a * NP, i = i0 - 1 + a, j = j0 - 1 + b;
-    const bool node = threadIdx.x < NP * NP && i >= 0 && i <= ns && j >= 0 && j <= ns;
+// kProjM: v = Gamma^T C Gamma P u with the partial sum C (Gamma P u)^2 (Kernel 2 of the paper);
+// kProjA: s = mask Gamma P u.  phi = P u comes from the bilinear cell tables of the region's 16
+// rows and columns on every layer, staged in LDS; each lane then gathers its node's four
+// neighbours on kProjLch layers at a time and sums the layers in order.
+template <typename T, int MODE>
+__global__ __launch_bounds__(kB) void k_proj(SegTab S, LayTab LT, InvVar IV, PupilArgs pa, const T *__restrict__ u,
+                                             T *__restrict__ out, Bufs<T> B, int nl) {
+    __shared__ int sK[2][kMaxLayers][kPR];
+    __shared__ T sW0[2][kMaxLayers][kPR], sW1[2][kMaxLayers][kPR];
+    __shared__ T sPhi[kPR * kPR];
+    __shared__ T sSx[kPS * kPS], sSy[kPS * kPS];
+    __shared__ double sRed[kB / 64];
+
+    const int tid = threadIdx.x;
+    const TileId id = find_tile(S);
+    const int g = id.seg, ns = S.n[g], tpr = S.lt[g];
+    const int ti = id.loc / tpr, tj = id.loc - ti * tpr;
+    const int i0 = ti * kProjTile, j0 = tj * kProjTile;
     const Ent<T> *__restrict__ xt = B.xtab + (long)g * nl * B.maxnv;
     const Ent<T> *__restrict__ yt = B.ytab + (long)g * nl * B.maxnv;
-    T phi = 0;
-    for (int l0 = 0; l0 < nl; l0 += LMAX) {
-        const int nc = (nl - l0) < LMAX ? (nl - l0) : LMAX;
-        for (int idx = threadIdx.x; idx < 2 * nc * NP; idx += blockDim.x) {
-            const int axis = idx / (nc * NP), rem = idx - axis * nc * NP, l = rem / NP, bb = rem - l * NP;
-            int nd = (axis ? i0 : j0) - 1 + bb;
+
+    // cell entries of the region's rows and columns on every layer: e = (l * 2 + axis) * 16 + idx
+    {
+        const int ne = 2 * nl * kPR;
+        Ent<T> en[kProjEntSlots];
+#pragma unroll
+        for (int c = 0; c < kProjEntSlots; ++c) {
+            const int e = min(tid + c * kB, ne - 1);
+            const int l = e >> 5, axis = (e >> 4) & 1, idx = e & 15;
+            int nd = (axis ? i0 : j0) - 1 + idx;
             nd = nd < 0 ? 0 : (nd > ns ? ns : nd);
-            const Ent<T> e = (axis ? yt : xt)[(long)(l0 + l) * B.maxnv + nd];
-            if (axis) {
-                sYk[rem] = e.k0;
-                sYw0[rem] = e.w0;
-                sYw1[rem] = e.w1;
-            } else {
-                sXk[rem] = e.k0;
-                sXw0[rem] = e.w0;
-                sXw1[rem] = e.w1;
+            en[c] = (axis ? yt : xt)[(long)l * B.maxnv + nd];
+        }
+#pragma unroll
+        for (int c = 0; c < kProjEntSlots; ++c) {
+            const int e = tid + c * kB;
+            if (c * kB < ne && e < ne) {
+                const int l = e >> 5, axis = (e >> 4) & 1, idx = e & 15;
+                sK[axis][l][idx] = en[c].k0;
+                sW0[axis][l][idx] = en[c].w0;
+                sW1[axis][l][idx] = en[c].w1;
             }
         }
-        if (threadIdx.x < nc) {
-            sOff[threadIdx.x] = B.lay[l0 + threadIdx.x].c_off;
-            sN[threadIdx.x] = B.lay[l0 + threadIdx.x].n;
-        }
-        __syncthreads();
-        if (node) {
-            for (int lc = 0; lc < nc; lc += LCH) {
-                T uv[LCH][4], wy0[LCH], wy1[LCH], wx0[LCH], wx1[LCH];
-#pragma unroll
-                for (int c = 0; c < LCH; ++c) {
-                    const int l = lc + c;
-                    const bool ok = l < nc;
-                    const int xs = ok ? l * NP + b : 0, ys = ok ? l * NP + a : 0;
-                    const int n = ok ? sN[l] : 0;
-                    wx0[c] = ok ? sXw0[xs] : (T)0;
-                    wx1[c] = ok ? sXw1[xs] : (T)0;
-                    wy0[c] = ok ? sYw0[ys] : (T)0;
-                    wy1[c] = ok ? sYw1[ys] : (T)0;
-                    const T *U = u + (ok ? sOff[l] + (long)sYk[ys] * n + sXk[xs] : 0);
-                    uv[c][0] = U[0];
-                    uv[c][1] = ok ? U[1] : (T)0;
-                    uv[c][2] = ok ? U[n] : (T)0;
-                    uv[c][3] = ok ? U[n + 1] : (T)0;
-                }
-#pragma unroll
-                for (int c = 0; c < LCH; ++c)
-                    phi += (wy0[c] * wx0[c]) * uv[c][0] + (wy0[c] * wx1[c]) * uv[c][1] + (wy1[c] * wx0[c]) * uv[c][2] +
-                           (wy1[c] * wx1[c]) * uv[c][3];
-            }
-        }
-        __syncthreads();
     }
-    if (threadIdx.x < NP * NP) sPhi[threadIdx.x] = node ? phi : (T)0;
     __syncthreads();
-    if (threadIdx.x < NS * NS) {
-        const int aa = threadIdx.x / NS, bb = threadIdx.x - aa * NS, ii = i0 - 1 + aa, jj = j0 - 1 + bb;
+
+    const int a = tid >> 4, b = tid & 15, i = i0 - 1 + a, j = j0 - 1 + b;
+    const bool node = i >= 0 && i <= ns && j >= 0 && j <= ns;
+    T phi = 0;
+    for (int l0 = 0; l0 < nl; l0 += kProjLch) {
+        T uv[kProjLch][4];
+#pragma unroll
+        for (int c = 0; c < kProjLch; ++c) {
+            const int l = min(l0 + c, nl - 1);  // layers past the last reload it (dropped below)
+            const int n = LT.n[l];
+            const T *U = u + LT.off[l] + (long)sK[1][l][a] * n + sK[0][l][b];
+            uv[c][0] = U[0];
+            uv[c][1] = U[1];
+            uv[c][2] = U[n];
+            uv[c][3] = U[n + 1];
+        }
+#pragma unroll
+        for (int c = 0; c < kProjLch; ++c) {
+            const int l = l0 + c;
+            if (l < nl) {
+                const T wy0 = sW0[1][l][a], wy1 = sW1[1][l][a], wx0 = sW0[0][l][b], wx1 = sW1[0][l][b];
+                phi += (wy0 * wx0) * uv[c][0] + (wy0 * wx1) * uv[c][1] + (wy1 * wx0) * uv[c][2] +
+                       (wy1 * wx1) * uv[c][3];  // (garbage on rows outside the grid: sPhi drops it)
+            }
+        }
+    }
+    sPhi[tid] = node ? phi : (T)0;
+    __syncthreads();
+
+    double e2 = 0.0;
+    if (tid < kPS * kPS) {
+        const int aa = tid / kPS, bb = tid - aa * kPS, ii = i0 - 1 + aa, jj = j0 - 1 + bb;
         T sx = 0, sy = 0;
-        if (ii >= 0 && ii < ns && jj >= 0 && jj < ns && subap_active(W, ii, jj)) {
-            const T w = (T)W.inv_var;
-            const T p00 = sPhi[aa * NP + bb], p01 = sPhi[aa * NP + bb + 1];
-            const T p10 = sPhi[(aa + 1) * NP + bb], p11 = sPhi[(aa + 1) * NP + bb + 1];
-            sx = w * ((T)0.5 * ((p01 - p00) + (p11 - p10)));
-            sy = w * ((T)0.5 * ((p10 - p00) + (p11 - p01)));
+        const bool act = ii >= 0 && ii < ns && jj >= 0 && jj < ns && subap_active(pa, ns, ii, jj);
+        if (act) {
+            const T p00 = sPhi[aa * kPR + bb], p01 = sPhi[aa * kPR + bb + 1];
+            const T p10 = sPhi[(aa + 1) * kPR + bb], p11 = sPhi[(aa + 1) * kPR + bb + 1];
+            sx = (T)0.5 * ((p01 - p00) + (p11 - p10));
+            sy = (T)0.5 * ((p10 - p00) + (p11 - p01));
         }
-        sSx[threadIdx.x] = sx;
-        sSy[threadIdx.x] = sy;
+        const bool own = aa >= 1 && bb >= 1 && ii < ns && jj < ns;
+        if (MODE == kProjA) {
+            if (own) {
+                out[S.aux[g] + (long)ii * ns + jj] = sx;
+                out[S.aux[g] + (long)ns * ns + (long)ii * ns + jj] = sy;
+            }
+        } else {
+            const double iv = IV.v[g];
+            if (own && act) e2 = iv * ((double)sx * (double)sx + (double)sy * (double)sy);
+            sSx[tid] = (T)iv * sx;
+            sSy[tid] = (T)iv * sy;
+        }
     }
+    if (MODE == kProjA) return;
     __syncthreads();
-    if (threadIdx.x < NT * NT) {
-        const int aa = threadIdx.x / NT, bb = threadIdx.x - aa * NT, ii = i0 + aa, jj = j0 + bb;
+    if (tid < kProjTile * kProjTile) {
+        const int aa = tid / kProjTile, bb = tid - aa * kProjTile, ii = i0 + aa, jj = j0 + bb;
         if (ii <= ns && jj <= ns) {
             // node (i, j) is a corner of subapertures (i, j), (i, j-1), (i-1, j), (i-1, j-1)
-            const int s11 = (aa + 1) * NS + (bb + 1), s10 = (aa + 1) * NS + bb, s01 = aa * NS + (bb + 1), s00 = aa * NS + bb;
-            v[W.v_off + (long)ii * nv + jj] = (T)0.5 * ((-sSx[s11] - sSy[s11]) + (sSx[s10] - sSy[s10]) +
-                                                        (-sSx[s01] + sSy[s01]) + (sSx[s00] + sSy[s00]));
+            const int s11 = (aa + 1) * kPS + (bb + 1), s10 = (aa + 1) * kPS + bb, s01 = aa * kPS + (bb + 1),
+                      s00 = aa * kPS + bb;
+            out[S.off[g] + (long)ii * (ns + 1) + jj] =
+                (T)0.5 * ((-sSx[s11] - sSy[s11]) + (sSx[s10] - sSy[s10]) + (-sSx[s01] + sSy[s01]) + (sSx[s00] + sSy[s00]));
         }
     }
+    const double t = block_sum(e2, sRed);
+    if (tid == 0) B.partials[2 * kPartialPitch + blockIdx.x] = t;
 }
 
-// Gamma^T C s (MODE kModeRhs) or Gamma^T mask s (kModeAdj) on one node tile.
+// Gamma^T C s (kGtRhs) or Gamma^T mask s (kGtAdj) on the node tiles of k_proj.
 template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void k_nodes(const T *__restrict__ in, T *__restrict__ v, Bufs<T> B) {
-    constexpr int NT = kNodeTile, NS = NT + 1;
-    __shared__ T sSx[NS * NS], sSy[NS * NS];
-    const Tile t = B.node_tiles[blockIdx.x];
-    const DevWfs W = B.wfs[t.a];
-    const int ns = W.n_sub, nv = W.nv, i0 = t.b, j0 = t.c;
-    for (int idx = threadIdx.x; idx < NS * NS; idx += blockDim.x) {
-        const int a = idx / NS, b = idx - a * NS, i = i0 - 1 + a, j = j0 - 1 + b;
-        T sx = 0, sy = 0;
-        if (i >= 0 && i < ns && j >= 0 && j < ns && subap_active(W, i, j)) {
-            const T w = (MODE == kModeAdj) ? (T)1 : (T)W.inv_var;
-            sx = w * in[W.s_off + (long)i * ns + j];
-            sy = w * in[W.s_off + (long)ns * ns + (long)i * ns + j];
+__global__ __launch_bounds__(kB) void k_gt(SegTab S, InvVar IV, PupilArgs pa, const T *__restrict__ in,
+                                           T *__restrict__ v) {
+    __shared__ T sSx[kPS * kPS], sSy[kPS * kPS];
+    const int tid = threadIdx.x;
+    const TileId id = find_tile(S);
+    const int g = id.seg, ns = S.n[g], tpr = S.lt[g];
+    const int ti = id.loc / tpr, tj = id.loc - ti * tpr;
+    const int i0 = ti * kProjTile, j0 = tj * kProjTile;
+    {
+        const int t = tid < kPS * kPS ? tid : 0;
+        const int aa = t / kPS, bb = t - aa * kPS, ii = i0 - 1 + aa, jj = j0 - 1 + bb;
+        const bool in_grid = ii >= 0 && ii < ns && jj >= 0 && jj < ns;
+        const long at = S.aux[g] + (in_grid ? (long)ii * ns + jj : 0L);  // every lane loads
+        const T vx = in[at], vy = in[at + (long)ns * ns];
+        if (tid < kPS * kPS) {
+            const bool act = in_grid && subap_active(pa, ns, ii, jj);
+            const T w = (MODE == kGtAdj) ? (T)1 : (T)IV.v[g];
+            sSx[tid] = act ? w * vx : (T)0;
+            sSy[tid] = act ? w * vy : (T)0;
         }
-        sSx[idx] = sx;
-        sSy[idx] = sy;
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < NT * NT; idx += blockDim.x) {
-        const int a = idx / NT, b = idx - a * NT, i = i0 + a, j = j0 + b;
-        if (i > ns || j > ns) continue;
-        const int s11 = (a + 1) * NS + (b + 1), s10 = (a + 1) * NS + b, s01 = a * NS + (b + 1), s00 = a * NS + b;
-        v[W.v_off + (long)i * nv + j] = (T)0.5 * ((-sSx[s11] - sSy[s11]) + (sSx[s10] - sSy[s10]) +
-                                                  (-sSx[s01] + sSy[s01]) + (sSx[s00] + sSy[s00]));
-    }
-}
-
-// s = mask Gamma P u on subaperture tiles.
-template <typename T>
-__global__ __launch_bounds__(kNodeBlock) void k_slopes(const T *__restrict__ u, T *__restrict__ s, Bufs<T> B, int nl) {
-    constexpr int NT = kNodeTile, NP = NT + 1;
-    __shared__ T sPhi[NP * NP];
-    const Tile t = B.sub_tiles[blockIdx.x];
-    const DevWfs W = B.wfs[t.a];
-    const int ns = W.n_sub, i0 = t.b, j0 = t.c;
-    if (threadIdx.x < NP * NP) {
-        const int a = threadIdx.x / NP, b = threadIdx.x - a * NP, i = i0 + a, j = j0 + b;
-        T val = 0;
-        if (i <= ns && j <= ns) val = project_node(u, B, t.a, nl, i, j);
-        sPhi[threadIdx.x] = val;
-    }
-    __syncthreads();
-    if (threadIdx.x < NT * NT) {
-        const int a = threadIdx.x / NT, b = threadIdx.x - a * NT, i = i0 + a, j = j0 + b;
-        if (i < ns && j < ns) {
-            T sx = 0, sy = 0;
-            if (subap_active(W, i, j)) {
-                const T p00 = sPhi[a * NP + b], p01 = sPhi[a * NP + b + 1];
-                const T p10 = sPhi[(a + 1) * NP + b], p11 = sPhi[(a + 1) * NP + b + 1];
-                sx = (T)0.5 * ((p01 - p00) + (p11 - p10));
-                sy = (T)0.5 * ((p10 - p00) + (p11 - p01));
-            }
-            s[W.s_off + (long)i * ns + j] = sx;
-            s[W.s_off + (long)ns * ns + (long)i * ns + j] = sy;
+    if (tid < kProjTile * kProjTile) {
+        const int aa = tid / kProjTile, bb = tid - aa * kProjTile, ii = i0 + aa, jj = j0 + bb;
+        if (ii <= ns && jj <= ns) {
+            const int s11 = (aa + 1) * kPS + (bb + 1), s10 = (aa + 1) * kPS + bb, s01 = aa * kPS + (bb + 1),
+                      s00 = aa * kPS + bb;
+            v[S.off[g] + (long)ii * (ns + 1) + jj] =
+                (T)0.5 * ((-sSx[s11] - sSy[s11]) + (sSx[s10] - sSy[s10]) + (-sSx[s01] + sSy[s01]) + (sSx[s00] + sSy[s00]));
         }
     }
 }
@@ -631,106 +566,142 @@ __global__ __launch_bounds__(kNodeBlock) void k_slopes(const T *__restrict__ u, 
 // ---------------------------------------------------------------------------------------------
 // P^T
 // ---------------------------------------------------------------------------------------------
-// Through the transpose tables: for each sensor, the tile rows' and columns' (node, weight)
-// lists are staged in LDS (structure of arrays, entry-major, so the 16 lanes of a tile row read
-// consecutive words); each lane then gathers the v values of its node's non-zero pairs, two
-// sensors' loads in flight at a time.
+// Staged gather on a 16 x 16 layer tile.  The transpose-table lines of the tile's rows and
+// columns (up to kRtabWidth (node, weight) pairs each, per guide star) and each guide star's
+// record (the node rows / columns those pairs name and the largest pair count over the tile's
+// rows / columns, precomputed at bind time) come first; the node rectangles are then staged in
+// LDS (dynamic, nw * capr * capw values) with one round of loads, and each lane sums
+//   x(k, q) = sum_g sum_{(i, wy) in row k} wy sum_{(j, wx) in column q} wx v_g(i, j)
+// from LDS, with loop bounds uniform over the tile (missing pairs carry weight 0).  The pairs are
+// the very matrix entries P uses, so P^T is P's exact transpose.
+constexpr int kPtSlots = kPtStage / kB;
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pt_tab(const T *__restrict__ v, T *__restrict__ x, Bufs<T> B, int nl,
-                                                   int nw) {
-    constexpr int NT = kNodeTile, RW = kRtabWidth, GMAX = 16, GCH = 2;
-    constexpr int NSTAGE = 2 * GMAX * NT * RW, MAXI = NSTAGE / kBlock;
-    static_assert(NT == 16 && RW == 4 && kBlock == 256, "index arithmetic below assumes these sizes");
-    __shared__ int sIdx[NSTAGE];  // [axis][g][entry][line]
-    __shared__ T sW[NSTAGE];
-    __shared__ long sVoff[GMAX];
-    __shared__ int sNv[GMAX];
-    const Tile t = B.lay_tiles[blockIdx.x];
-    const int k0 = t.b, q0 = t.c, n = t.f, roff = t.h;
-    const int rk = (int)(threadIdx.x >> 4), rq = (int)(threadIdx.x & 15);
-    const bool valid = k0 + rk < n && q0 + rq < n;
-    const RtabEnt<T> *__restrict__ xrt = B.xrtab;
-    const RtabEnt<T> *__restrict__ yrt = B.yrtab;
-    T acc = 0;
-    for (int gb = 0; gb < nw; gb += GMAX) {
-        const int gc = (nw - gb) < GMAX ? (nw - gb) : GMAX;
-        {
-            int id[MAXI];
-            T w[MAXI];
-#pragma unroll
-            for (int c = 0; c < MAXI; ++c) {
-                // staged slot e = (((axis * 16 + g) * 4 + entry) * 16 + line); loads are read in
-                // (line, entry) order for coalescing
-                const int e = c * kBlock + (int)threadIdx.x;
-                const int axis = e >> 10, g = (e >> 6) & 15, line = (e >> 2) & 15, entry = e & 3;
-                const int gl = (axis ? k0 : q0) + line;
-                RtabEnt<T> en{0, (T)0};
-                if (g < gc && gl < n) en = (axis ? yrt : xrt)[((long)(gb + g) * B.sum_n + roff + gl) * RW + entry];
-                id[c] = en.idx;
-                w[c] = en.w;
-            }
-#pragma unroll
-            for (int c = 0; c < MAXI; ++c) {
-                const int e = c * kBlock + (int)threadIdx.x;
-                const int axis = e >> 10, g = (e >> 6) & 15, line = (e >> 2) & 15, entry = e & 3;
-                const int slot = (((axis * GMAX + g) * RW + entry) * NT) + line;
-                sIdx[slot] = id[c];
-                sW[slot] = w[c];
-            }
-        }
-        if (threadIdx.x < gc) {
-            sVoff[threadIdx.x] = B.wfs[gb + threadIdx.x].v_off;
-            sNv[threadIdx.x] = B.wfs[gb + threadIdx.x].nv;
-        }
-        __syncthreads();
-        if (valid) {
-            for (int g0 = 0; g0 < gc; g0 += GCH) {
-                T val[GCH][RW][RW], wy[GCH][RW], wx[GCH][RW];
-#pragma unroll
-                for (int gg = 0; gg < GCH; ++gg) {
-                    const int g = g0 + gg;
-                    int iy[RW], ix[RW];
-#pragma unroll
-                    for (int a = 0; a < RW; ++a) {
-                        const int sy = ((GMAX + g) * RW + a) * NT + rk, sx = (g * RW + a) * NT + rq;
-                        iy[a] = g < gc ? sIdx[sy] : 0;
-                        wy[gg][a] = g < gc ? sW[sy] : (T)0;
-                        ix[a] = g < gc ? sIdx[sx] : 0;
-                        wx[gg][a] = g < gc ? sW[sx] : (T)0;
-                    }
-                    const T *vg = v + (g < gc ? sVoff[g] : 0);
-                    const int nv = g < gc ? sNv[g] : 0;
-#pragma unroll
-                    for (int a = 0; a < RW; ++a)
-#pragma unroll
-                        for (int b = 0; b < RW; ++b)
-                            val[gg][a][b] = (wy[gg][a] != (T)0 && wx[gg][b] != (T)0) ? vg[(long)iy[a] * nv + ix[b]] : (T)0;
-                }
-#pragma unroll
-                for (int gg = 0; gg < GCH; ++gg)
-#pragma unroll
-                    for (int a = 0; a < RW; ++a)
-#pragma unroll
-                        for (int b = 0; b < RW; ++b) acc += (wy[gg][a] * wx[gg][b]) * val[gg][a][b];
-            }
-        }
-        __syncthreads();
+__global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restrict__ v, T *__restrict__ x, Bufs<T> B,
+                                           int nw, PassArgs PA) {
+    constexpr int NT = kPtTile, RW = kRtabWidth;
+    static_assert(NT == 16 && 2 * kPtMaxWfs * NT == 2 * kB, "line decode below assumes these sizes");
+    extern __shared__ char smem_raw[];
+    T *sV = reinterpret_cast<T *>(smem_raw);
+    __shared__ RtabEnt<T> sP[kPtMaxWfs][2][RW][NT];
+    __shared__ int4 sRect[kPtMaxWfs];  // iA, iB, jA, jB
+    __shared__ int2 sCnt[kPtMaxWfs];   // largest pair count over the tile's rows, columns
+    __shared__ int2 sVb[kPtMaxWfs];
+
+    if (PA.k >= 0 && blockIdx.x == gridDim.x - 1) {  // the pass's scalar step (extra workgroup)
+        scalar_step(B.partials, PA.nwt, PA.nproj, B.sc, PA.k, PA.resnorm, PA.publish);
+        return;
     }
-    if (valid) x[(long)t.e + (long)(k0 + rk) * n + q0 + rq] = acc;
+    const int tid = threadIdx.x;
+    const TileId id = find_tile(S);
+    const int l = id.seg, n = S.n[l], lt = S.lt[l];
+    const int T0 = n < NT ? n : NT;
+    const int k0 = (id.loc >> lt) * T0, q0 = (id.loc & ((1 << lt) - 1)) * T0;
+    const int roff = S.aux[l];
+    const int capw = S.capw[l], cell = S.capr[l] * capw;
+
+    // transpose-table lines e = (g * 2 + axis) * 16 + idx, and the records (every lane loads;
+    // clamped indices stand in for lines the tile does not have)
+    RtabEnt<T> pe[2][RW];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int e = tid + c * kB, g = min(e >> 5, nw - 1), axis = (e >> 4) & 1, idx = min(e & 15, T0 - 1);
+        const RtabEnt<T> *rt = (axis ? B.yrtab : B.xrtab) + ((long)g * B.sum_n + roff + (axis ? k0 : q0) + idx) * RW;
+#pragma unroll
+        for (int a = 0; a < RW; ++a) pe[c][a] = rt[a];
+    }
+    const int tg = min(tid, nw - 1);
+    const int4 rec = B.rects[(long)blockIdx.x * nw + tg];
+    const int2 vb = make_int2(WO.v_off[tg], WO.n_sub[tg] + 1);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int e = tid + c * kB, g = e >> 5, axis = (e >> 4) & 1, idx = e & 15;
+        if (g < nw && idx < T0) {
+#pragma unroll
+            for (int a = 0; a < RW; ++a) sP[g][axis][a][idx] = pe[c][a];
+        }
+    }
+    if (tid < nw) {
+        sRect[tid] = make_int4(rec.x & 0xffff, rec.x >> 16, rec.y & 0xffff, rec.y >> 16);
+        sCnt[tid] = make_int2(rec.z, rec.w);
+        sVb[tid] = vb;
+    }
+    __syncthreads();
+
+    // node rectangles of every guide star, one round of loads straight into LDS: staged value
+    // k = g cell + r capw + q
+    {
+        const float rcell = 1.0f / (float)cell, rw = 1.0f / (float)capw;
+        const int total = nw * cell;
+#pragma unroll
+        for (int c = 0; c < kPtSlots; ++c) {
+            if (c * kB < total) {
+                const int k = tid + c * kB, kc = min(k, total - 1);
+                const int g = small_div(kc, rcell), rem = kc - g * cell;
+                const int r = small_div(rem, rw), q = rem - r * capw;
+                const int4 R = sRect[g];
+                const int2 V = sVb[g];
+                if (k < total && R.x + r <= R.y && R.z + q <= R.w) {
+                    const T *gp = v + V.x + (long)(R.x + r) * V.y + R.z + q;
+                    if constexpr (sizeof(T) == 4) g2lds(gp, sV + c * kB + (tid & ~63));
+                    else sV[k] = *gp;
+                }
+            }
+        }
+    }
+    lds_fence();
+
+    const int a = tid >> 4, b = tid & 15;
+    if (a < T0 && b < T0) {
+        T acc = 0;
+        for (int g = 0; g < nw; ++g) {
+            const int4 R = sRect[g];
+            const int2 C = sCnt[g];
+            const T *Vg = sV + g * cell - R.x * capw - R.z;
+            int jx[RW];
+            T wx[RW];
+#pragma unroll
+            for (int e = 0; e < RW; ++e) {
+                const RtabEnt<T> p = sP[g][0][e][b];
+                jx[e] = max(p.idx, R.z);  // padding (index -1) has weight 0
+                wx[e] = p.w;
+            }
+#pragma unroll
+            for (int ea = 0; ea < RW; ++ea) {
+                if (ea < C.x) {
+                    const RtabEnt<T> p = sP[g][1][ea][a];
+                    const T *Vr = Vg + max(p.idx, R.x) * capw;
+                    T t = 0;
+#pragma unroll
+                    for (int eb = 0; eb < RW; ++eb)
+                        if (eb < C.y) t += wx[eb] * Vr[jx[eb]];
+                    acc += p.w * t;
+                }
+            }
+        }
+        x[S.off[l] + (long)(k0 + a) * n + q0 + b] = acc;
+    }
 }
 
 // By scanning the cell tables over each layer node's contiguous node ranges (any geometry).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pt_scan(const T *__restrict__ v, T *__restrict__ x, Bufs<T> B, int nl,
-                                                    int nw) {
-    constexpr int NT = kNodeTile;
-    const Tile t = B.lay_tiles[blockIdx.x];
-    const int l = t.a, k = t.b + (int)(threadIdx.x / NT), q = t.c + (int)(threadIdx.x % NT), n = t.f;
-    if (k >= n || q >= n) return;
+__global__ __launch_bounds__(kB) void k_pt_scan(SegTab S, const T *__restrict__ v, T *__restrict__ x, Bufs<T> B,
+                                                int nl, int nw, PassArgs PA) {
+    constexpr int NT = kPtTile;
+    if (PA.k >= 0 && blockIdx.x == gridDim.x - 1) {  // the pass's scalar step (extra workgroup)
+        scalar_step(B.partials, PA.nwt, PA.nproj, B.sc, PA.k, PA.resnorm, PA.publish);
+        return;
+    }
+    const TileId id = find_tile(S);
+    const int l = id.seg, n = S.n[l], lt = S.lt[l];
+    const int T0 = n < NT ? n : NT;
+    const int a = threadIdx.x >> 4, b = threadIdx.x & 15;
+    if (a >= T0 || b >= T0) return;
+    const int k = (id.loc >> lt) * T0 + a, q = (id.loc & ((1 << lt) - 1)) * T0 + b;
     T acc = 0;
     for (int g = 0; g < nw; ++g) {
-        const Range rx = B.xrng[(long)g * B.sum_n + t.h + q];
-        const Range ry = B.yrng[(long)g * B.sum_n + t.h + k];
+        const Range rx = B.xrng[(long)g * B.sum_n + S.aux[l] + q];
+        const Range ry = B.yrng[(long)g * B.sum_n + S.aux[l] + k];
         if (rx.lo > rx.hi || ry.lo > ry.hi) continue;
         const Ent<T> *xt = B.xtab + ((long)g * nl + l) * B.maxnv;
         const Ent<T> *yt = B.ytab + ((long)g * nl + l) * B.maxnv;
@@ -747,306 +718,311 @@ __global__ __launch_bounds__(kBlock) void k_pt_scan(const T *__restrict__ v, T *
             }
         }
     }
-    x[(long)t.e + (long)k * n + q] = acc;
+    x[S.off[l] + (long)k * n + q] = acc;
 }
 
 // ---------------------------------------------------------------------------------------------
 // Forward transform W with fused epilogues.
 // ---------------------------------------------------------------------------------------------
-// Deliver one coefficient w of W x (operands e0, e1 prefetched); accumulate PCG dot partials.
+// Global index of coefficient (r, q) of band o (0 LL, 1 x-high/y-low, 2 x-low/y-high, 3 HH) at
+// level s.
+__device__ __forceinline__ long band_index(long coff, int n, int s, int o, int r, int q) {
+    const int m = n >> s;
+    return coff + (long)(r + (o >= 2 ? m : 0)) * n + q + ((o & 1) ? m : 0);
+}
+
+// One 2D analysis step on the 6 x 6 input patch at (2r, 2q): rows along x, then columns along y.
+template <typename T>
+__device__ __forceinline__ void analyse(const T *src, int pitch, int r, int q, const Taps<T> &tp, T &ll, T &hl,
+                                        T &lh, T &hh) {
+    ll = hl = lh = hh = 0;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+        const T *row = src + (2 * r + a) * pitch + 2 * q;
+        T ax = 0, dx = 0;
+#pragma unroll
+        for (int b = 0; b < 6; ++b) {
+            ax += tp.h[b] * row[b];
+            dx += tp.g[b] * row[b];
+        }
+        ll += tp.h[a] * ax;
+        lh += tp.g[a] * ax;
+        hl += tp.h[a] * dx;
+        hh += tp.g[a] * dx;
+    }
+}
+
+template <int EPI>
+struct EpiOps {
+    static constexpr int n = EPI == kEpiPcg ? 4 : (EPI == kEpiRhs ? 2 : (EPI == kEpiPrior ? 1 : 0));
+};
+
+// Operands of coefficient i: prior c | pcg r, c, p, q | rhs b_prev, r.
 template <typename T, int EPI>
-__device__ __forceinline__ void deliver(const Bufs<T> &B, const FwdArgs &E, long i, T w, T ad, T ji, T e0, T e1,
-                                        double &rho, double &mu) {
+__device__ __forceinline__ void epi_load(const Bufs<T> &B, const FwdArgs &E, long i, T *op) {
+    if constexpr (EPI == kEpiPrior) {
+        op[0] = static_cast<const T *>(E.cin)[i];
+    } else if constexpr (EPI == kEpiPcg) {
+        op[0] = B.r[i];
+        op[1] = static_cast<const T *>(E.c)[i];
+        op[2] = E.k > 0 ? B.p[i] : (T)0;
+        op[3] = E.k > 0 ? B.q[i] : (T)0;
+    } else if constexpr (EPI == kEpiRhs) {
+        op[0] = E.cold ? (T)0 : B.b_prev[i];
+        op[1] = E.cold ? (T)0 : B.r[i];
+    }
+}
+
+// Deliver coefficient i of W x (value w) through the epilogue.
+template <typename T, int EPI>
+__device__ __forceinline__ void epi_store(const Bufs<T> &B, const FwdArgs &E, long i, T w, const T *op, T ji, T ad,
+                                          const StepOut &so) {
     if constexpr (EPI == kEpiPlain) {
         static_cast<T *>(E.out)[i] = w;
     } else if constexpr (EPI == kEpiPrior) {
-        static_cast<T *>(E.out)[i] = w + ad * e0;
+        static_cast<T *>(E.out)[i] = w + ad * op[0];
     } else if constexpr (EPI == kEpiPcg) {
-        const T z = e0 * ji;
-        const T yi = w + ad * z;
-        static_cast<T *>(E.out)[i] = yi;
-        rho += (double)e0 * (double)z;
-        mu += (double)yi * (double)z;
+        if (so.stopped) return;
+        const T r = op[0], z = r * ji, y = w + ad * z;
+        const T al = (T)so.alpha, be = (T)so.beta;
+        const T p = E.k > 0 ? z + be * op[2] : z;
+        const T q = E.k > 0 ? y + be * op[3] : y;
+        B.p[i] = p;
+        B.q[i] = q;
+        static_cast<T *>(E.c)[i] = op[1] + al * p;
+        B.r[i] = r - al * q;
     } else {  // b = W x:  r = (b - b_prev) + r  (cold: r = b, c = 0);  b_prev = b
         if (E.cold) {
             B.r[i] = w;
             static_cast<T *>(E.c)[i] = 0;
         } else {
-            B.r[i] = (w - e0) + e1;
+            B.r[i] = (w - op[0]) + op[1];
         }
         B.b_prev[i] = w;
     }
 }
 
-template <typename T, int EPI>
-__device__ __forceinline__ void prefetch(const Bufs<T> &B, const FwdArgs &E, long i, T &e0, T &e1) {
-    if constexpr (EPI == kEpiPrior) e0 = static_cast<const T *>(E.cin)[i];
-    else if constexpr (EPI == kEpiPcg) e0 = static_cast<const T *>(E.rk)[i];
-    else if constexpr (EPI == kEpiRhs) {
-        e0 = B.b_prev[i];
-        e1 = B.r[i];
-    }
-}
-
-// Global index of coefficient (r, q) of band o (0 LL, 1 x-high, 2 y-high, 3 HH) at level s.
-__device__ __forceinline__ long band_index(long coff, int n, int s, int o, int r, int q) {
-    const int m = n >> s;
-    return coff + (long)(r + ((o == 2 || o == 3) ? m : 0)) * n + q + ((o == 1 || o == 3) ? m : 0);
-}
-
-// Region geometry of the fine part: a tile of TQ x TQ level-KF approximation coefficients needs
-// LL_s on a run of len(s) = TQ 2^(KF-s) + 4 (2^(KF-s) - 1) indices (s = 0 is the input).
+// Level region of the fine part: a tile of TQ x TQ level-KF quads needs LL_s on a run of
+// len(s) = TQ 2^(KF-s) + 4 (2^(KF-s) - 1) indices (s = 0 is x) and owns TQ 2^(KF-s) of them.
 template <int KF, int TQ>
 struct FineGeom {
     static constexpr int len(int s) { return TQ * (1 << (KF - s)) + 4 * ((1 << (KF - s)) - 1); }
+    static constexpr int own(int s) { return TQ << (KF - s); }
 };
 
-// Levels 1..KF on a tile of TQ x TQ level-KF approximation coefficients: the input region with
-// its halo (periodic wrap) and the epilogue operands of every owned coefficient arrive in one
-// batch of independent loads, then the levels run from LDS.
-constexpr int kFwdBlock = 512;
+// Levels 1..KF on a tile of TQ x TQ level-KF quads.  The input region with its periodic halo
+// (straight into LDS), the epilogue operands of the coefficients each lane will deliver, and
+// (pcg) the pass's partial sums arrive in one batch of loads; the levels then run from LDS.  Lane
+// roles: lanes [0, O1^2) own the level-1 quads, lanes [256, 256 + H1) compute the level-1 halo
+// quads (LL only, for level 2), lanes [512, 512 + O2^2) own the level-2 quads.
+constexpr int kFB = 1024;
 
 template <typename T, int KF, int TQ, int EPI>
-__global__ __launch_bounds__(kFwdBlock) void k_fwd_fine(const T *__restrict__ x, Bufs<T> B, int J, FwdArgs E,
-                                                     Taps<T> tp) {
+__global__ __launch_bounds__(kFB) void k_fwd(SegTab S, const T *__restrict__ x, Bufs<T> B, FwdArgs E, Taps<T> tp,
+                                             int J, int nwt, int nproj) {
     using G = FineGeom<KF, TQ>;
-    constexpr int L0 = G::len(0), L1 = G::len(1), EMAX = 1024;
-    constexpr int NE = (EPI == kEpiRhs) ? 2 : ((EPI == kEpiPlain) ? 0 : 1);
-    constexpr int MAXI = 6;
+    constexpr int L0 = G::len(0), L1 = G::len(1), NX = (L0 * L0 + kFB - 1) / kFB;
+    constexpr int O1 = G::own(1), O2 = KF >= 2 ? G::own(2) : 1, H1 = KF >= 2 ? L1 * L1 - O1 * O1 : 0;
+    constexpr int NOP = EpiOps<EPI>::n, HW = L1 > O1 ? L1 - O1 : 1;
+    static_assert(O1 * O1 <= 256 && H1 <= 256 && O2 * O2 <= 512, "lane roles");
     __shared__ T sA[L0 * L0];
     __shared__ T sB[KF >= 2 ? L1 * L1 : 1];
-    __shared__ T sE0[NE >= 1 ? EMAX : 1], sE1[NE >= 2 ? EMAX : 1];
-    __shared__ T sAd[kMaxJ + 1], sJi[(kMaxJ + 1) * 4];
-    __shared__ double sh[kFwdBlock / 64];
 
+    const int tid = threadIdx.x;
     if constexpr (EPI == kEpiRhs) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) reset_scalars(B.sc + 1);  // state "before pass 0"
+        if (blockIdx.x == 0 && tid == 0) reset_scalars(B.sc + 1);  // the state "before pass 0"
     }
-    const Tile t = B.fine_tiles[blockIdx.x];
-    const int l = t.a, qy = t.b, qx = t.c, tq = t.d, n = t.f;
-    const long coff = t.e;
-    if ((EPI == kEpiPrior || EPI == kEpiPcg) && threadIdx.x <= J) sAd[threadIdx.x] = B.ad[l * (J + 1) + threadIdx.x];
-    if (EPI == kEpiPcg && threadIdx.x < (J + 1) * 4) sJi[threadIdx.x] = B.jinv[l * (J + 1) * 4 + threadIdx.x];
+    const TileId id = find_tile(S);
+    const int l = id.seg, n = S.n[l], lt = S.lt[l], nm = n - 1;
+    const int qy = (id.loc >> lt) * TQ, qx = (id.loc & ((1 << lt) - 1)) * TQ;
+    const long coff = S.off[l];
+    const int oy = qy << KF, ox = qx << KF;
 
-    int len[KF + 1], own[KF + 1], eoff[KF + 2];
-    eoff[1] = 0;
+    // x region with its periodic halo, straight into LDS (row-major, pitch L0)
 #pragma unroll
-    for (int s = 0; s <= KF; ++s) {
-        len[s] = tq * (1 << (KF - s)) + 4 * ((1 << (KF - s)) - 1);
-        own[s] = tq << (KF - s);
-        if (s >= 1) eoff[s + 1] = eoff[s] + 3 * own[s] * own[s];
-    }
-    const int ne = eoff[KF + 1] + (KF == J ? own[KF] * own[KF] : 0);
-    const int oy = qy << KF, ox = qx << KF, nmask = n - 1;
-    {
-        const int nreg = len[0] * len[0], tot = nreg + (NE ? ne : 0);
-        for (int base = 0; base < tot; base += MAXI * kFwdBlock) {
-            T v0[MAXI], v1[MAXI];
-            int d[MAXI];
-#pragma unroll
-            for (int c = 0; c < MAXI; ++c) {
-                const int k = base + c * kFwdBlock + (int)threadIdx.x;
-                d[c] = -1;
-                if (k >= tot) continue;
-                if (k < nreg) {
-                    const int r = k / len[0], q = k - r * len[0];
-                    v0[c] = x[coff + (long)((oy + r) & nmask) * n + ((ox + q) & nmask)];
-                    d[c] = r * L0 + q;
-                } else {
-                    const int e = k - nreg;
-                    int s = 1;
-#pragma unroll
-                    for (int ss = 2; ss <= KF; ++ss)
-                        if (e >= eoff[ss]) s = ss;
-                    int o, r, q;
-                    if (e >= eoff[KF + 1]) {  // LL at level KF == J
-                        s = KF;
-                        o = 0;
-                        const int rem = e - eoff[KF + 1];
-                        r = rem / own[KF];
-                        q = rem - r * own[KF];
-                    } else {
-                        const int rem = e - eoff[s], b2 = own[s] * own[s];
-                        o = 1 + rem / b2;
-                        const int rr = rem - (o - 1) * b2;
-                        r = rr / own[s];
-                        q = rr - r * own[s];
-                    }
-                    T a0 = 0, a1 = 0;
-                    prefetch<T, EPI>(B, E, band_index(coff, n, s, o, (qy << (KF - s)) + r, (qx << (KF - s)) + q), a0,
-                                     a1);
-                    v0[c] = a0;
-                    v1[c] = a1;
-                    d[c] = L0 * L0 + e;
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < MAXI; ++c) {
-                if (d[c] < 0) continue;
-                if (d[c] < L0 * L0) sA[d[c]] = v0[c];
-                else {
-                    if constexpr (NE >= 1) sE0[d[c] - L0 * L0] = v0[c];
-                    if constexpr (NE >= 2) sE1[d[c] - L0 * L0] = v1[c];
-                }
-            }
+    for (int c = 0; c < NX; ++c) {
+        const int k = tid + c * kFB;
+        if (k < L0 * L0) {
+            const int r = k / L0, q = k - r * L0;
+            const T *gp = x + coff + (long)((oy + r) & nm) * n + ((ox + q) & nm);
+            if constexpr (sizeof(T) == 4) g2lds(gp, sA + c * kFB + (tid & ~63));
+            else sA[k] = *gp;
         }
     }
-    __syncthreads();
+    // the quad this lane delivers: level 1 (owner), level 2 (owner), or none (quad 0 of level 1
+    // stands in so that every lane issues the same loads)
+    const bool own1 = tid < O1 * O1, own2 = KF >= 2 && tid >= 512 && tid < 512 + O2 * O2;
+    const int s_own = own2 ? 2 : 1;
+    const int t1 = own1 ? tid : 0, t2 = own2 ? tid - 512 : 0;
+    const int rq = own2 ? t2 / O2 : t1 / O1, cq = own2 ? t2 - (t2 / O2) * O2 : t1 - (t1 / O1) * O1;
+    const int by = (qy << (KF - s_own)) + rq, bx = (qx << (KF - s_own)) + cq;
+    T op[4][NOP > 0 ? NOP : 1];
+    if (NOP > 0) {
+#pragma unroll
+        for (int o = 0; o < 4; ++o)
+            if (o > 0 || KF == J) epi_load<T, EPI>(B, E, band_index(coff, n, s_own, o, by, bx), op[o]);
+    }
+    StepOut so{0.0, 0.0, 0};
+    if constexpr (EPI == kEpiPcg) so = read_step(B.sc);
+    lds_fence();
 
-    double rho = 0.0, mu = 0.0;
 #pragma unroll
     for (int s = 1; s <= KF; ++s) {
-        const T *src = (s & 1) ? sA : sB;
-        T *dst = (s & 1) ? sB : sA;
-        const int sp = (s & 1) ? L0 : L1, dp = (s & 1) ? L1 : L0;
-        const int ln = len[s], ow = own[s];
-        const int by = qy << (KF - s), bx = qx << (KF - s);
-        const T ad = (EPI == kEpiPrior || EPI == kEpiPcg) ? sAd[s] : (T)0;
-        for (int idx = threadIdx.x; idx < ln * ln; idx += blockDim.x) {
-            const int r = idx / ln, q = idx - r * ln;
-            T ll = 0, lh = 0, hl = 0, hh = 0;
+        const T *src = s == 1 ? sA : sB;
+        const int sp = s == 1 ? L0 : L1;
+        const bool mine = s == 1 ? own1 : own2;
+        if (mine) {
+            T ad = 0, ji[4] = {0, 0, 0, 0};
+            if (EPI == kEpiPrior || EPI == kEpiPcg) ad = B.ad[l * (J + 1) + s];
+            if (EPI == kEpiPcg) {
 #pragma unroll
-            for (int a = 0; a < 6; ++a) {
-                const T *row = src + (2 * r + a) * sp + 2 * q;
-                T ax = 0, dx = 0;
-#pragma unroll
-                for (int b = 0; b < 6; ++b) {
-                    ax += tp.h[b] * row[b];
-                    dx += tp.g[b] * row[b];
-                }
-                ll += tp.h[a] * ax;
-                lh += tp.g[a] * ax;
-                hl += tp.h[a] * dx;
-                hh += tp.g[a] * dx;
+                for (int o = 0; o < 4; ++o) ji[o] = B.jinv[(l * (J + 1) + s) * 4 + o];
             }
-            if (s < KF) dst[r * dp + q] = ll;
-            if (r < ow && q < ow) {
-                const int e = eoff[s] + r * ow + q, b2 = ow * ow;
-                const T w[3] = {hl, lh, hh};
+            T w[4];
+            analyse(src, sp, rq, cq, tp, w[0], w[1], w[2], w[3]);
 #pragma unroll
-                for (int o = 1; o <= 3; ++o) {
-                    const int ei = e + (o - 1) * b2;
-                    T e0 = 0, e1 = 0;
-                    if constexpr (NE >= 1) e0 = sE0[ei];
-                    if constexpr (NE >= 2) e1 = sE1[ei];
-                    deliver<T, EPI>(B, E, band_index(coff, n, s, o, by + r, bx + q), w[o - 1], ad,
-                                    EPI == kEpiPcg ? sJi[s * 4 + o] : (T)0, e0, e1, rho, mu);
-                }
-                if (s == KF) {
-                    if (KF == J) {
-                        const int ei = eoff[KF + 1] + r * ow + q;
-                        T e0 = 0, e1 = 0;
-                        if constexpr (NE >= 1) e0 = sE0[ei];
-                        if constexpr (NE >= 2) e1 = sE1[ei];
-                        deliver<T, EPI>(B, E, band_index(coff, n, s, 0, by + r, bx + q), ll, ad,
-                                        EPI == kEpiPcg ? sJi[s * 4] : (T)0, e0, e1, rho, mu);
-                    } else {
-                        B.tmpA[(coff >> (2 * KF)) + (long)(by + r) * (n >> KF) + bx + q] = ll;
-                    }
-                }
+            for (int o = 1; o < 4; ++o) epi_store<T, EPI>(B, E, band_index(coff, n, s, o, by, bx), w[o], op[o], ji[o], ad, so);
+            if (s < KF) {
+                sB[rq * L1 + cq] = w[0];
+            } else if (KF == J) {
+                epi_store<T, EPI>(B, E, band_index(coff, n, s, 0, by, bx), w[0], op[0], ji[0], ad, so);
+            } else {
+                B.ll[(coff >> (2 * KF)) + (long)by * (n >> KF) + bx] = w[0];
             }
         }
-        __syncthreads();
-    }
-    if constexpr (EPI == kEpiPcg) {
-        const double a = block_sum(rho, sh), b = block_sum(mu, sh);
-        if (threadIdx.x == 0) {
-            B.partials[blockIdx.x] = a;
-            B.partials[kPartialPitch + blockIdx.x] = b;
+        if (s < KF && tid >= 256 && tid < 256 + H1) {  // halo quads of level 1: LL only
+            const int h = tid - 256, rs = O1 * HW;
+            int hr, hc;
+            if (h < rs) {
+                hr = h / HW;
+                hc = O1 + h - hr * HW;
+            } else {
+                hr = O1 + (h - rs) / L1;
+                hc = (h - rs) - (hr - O1) * L1;
+            }
+            T w[4];
+            analyse(src, sp, hr, hc, tp, w[0], w[1], w[2], w[3]);
+            sB[hr * L1 + hc] = w[0];
         }
+        if (s < KF) __syncthreads();
     }
 }
 
-// Levels KF+1..J of one layer per workgroup: the level-KF approximation (from tmpA) and the
-// epilogue operands of the layer's top-left m0 x m0 block (exactly the coefficients of these
-// levels) arrive in one batch of loads, then the levels run from LDS (dynamic shared memory:
-// (1 + 1/4 + NE) m0^2 values).
+// Levels KF+1..J of one layer per workgroup, from the level-KF approximation left by k_fwd
+// (periodic, so indices wrap).  Every coefficient of these levels lies in the layer's top-left
+// m0 x m0 block (m0 = n >> KF).  With `pre`, that block of every epilogue operand is staged in
+// LDS together with the approximation, in one round of loads; otherwise each level requests its
+// operands before its analysis.  Dynamic LDS: m0^2 + (m0/2)^2 (+ NOP m0^2 with `pre`) values.
 template <typename T, int EPI>
-__global__ __launch_bounds__(512) void k_fwd_coarse(Bufs<T> B, int J, int KF, FwdArgs E, Taps<T> tp, int nfine) {
+__global__ __launch_bounds__(kCB) void k_coarse(LayTab LT, Bufs<T> B, FwdArgs E, Taps<T> tp, int J, int KF, int nwt,
+                                                int nproj, int pre) {
     extern __shared__ char smem_raw[];
-    constexpr int NE = (EPI == kEpiRhs) ? 2 : ((EPI == kEpiPlain) ? 0 : 1);
-    __shared__ T sAd[kMaxJ + 1], sJi[(kMaxJ + 1) * 4];
-    __shared__ double sh[512 / 64];
-    const int l = blockIdx.x;
-    const DevLayer L = B.lay[l];
-    const int n = L.n, m0 = n >> KF;
-    const long coff = L.c_off;
-    T *cs = reinterpret_cast<T *>(smem_raw), *cd = cs + m0 * m0, *e0s = cd + (m0 * m0) / 4 + 1, *e1s = e0s + m0 * m0;
-    if ((EPI == kEpiPrior || EPI == kEpiPcg) && threadIdx.x <= J) sAd[threadIdx.x] = B.ad[l * (J + 1) + threadIdx.x];
-    if (EPI == kEpiPcg && threadIdx.x < (J + 1) * 4) sJi[threadIdx.x] = B.jinv[l * (J + 1) * 4 + threadIdx.x];
-    const int lm = L.log2n - KF;
-    const T *__restrict__ llin = B.tmpA + (coff >> (2 * KF));
-    for (int base = 0; base < m0 * m0; base += 8 * 512) {
-        T cv[8], a0v[8], a1v[8];
+    constexpr int NOP = EpiOps<EPI>::n, NL = 16;
+    const int tid = threadIdx.x, l = blockIdx.x, n = LT.n[l], m0 = n >> KF, mm = m0 * m0;
+    const long coff = LT.off[l];
+    T *cs = reinterpret_cast<T *>(smem_raw), *cd = cs + mm, *opl = cd + mm / 4;
+    const T *__restrict__ llin = B.ll + (coff >> (2 * KF));
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const int idx = base + c * 512 + (int)threadIdx.x;
-            a0v[c] = 0;
-            a1v[c] = 0;
-            if (idx >= m0 * m0) continue;
-            prefetch<T, EPI>(B, E, coff + (long)(idx >> lm) * n + (idx & (m0 - 1)), a0v[c], a1v[c]);
-            cv[c] = llin[idx];
-        }
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const int idx = base + c * 512 + (int)threadIdx.x;
-            if (idx >= m0 * m0) continue;
-            cs[idx] = cv[c];
-            if constexpr (NE >= 1) e0s[idx] = a0v[c];
-            if constexpr (NE >= 2) e1s[idx] = a1v[c];
+    for (int c = 0; c < NL; ++c) {
+        const int k = tid + c * kCB;
+        if (c * kCB < mm && k < mm) {
+            if constexpr (sizeof(T) == 4) g2lds(llin + k, cs + c * kCB + (tid & ~63));
+            else cs[k] = llin[k];
         }
     }
-    __syncthreads();
-    double rho = 0.0, mu = 0.0;
-    for (int s = KF + 1; s <= J; ++s) {
-        const int mi = n >> (s - 1), h = mi >> 1, msk = mi - 1, nq = h * h, lh = L.log2n - s;
-        const T ad = (EPI == kEpiPrior || EPI == kEpiPcg) ? sAd[s] : (T)0;
-        for (int qi = threadIdx.x; qi < nq; qi += blockDim.x) {
-            const int r = qi >> lh, q = qi & (h - 1);
-            int cols[6];
+    if (NOP > 0 && pre) {
+        // operand j of block element (r, c) -> opl[j * mm + r * m0 + c]
+        const T *srcs[4] = {nullptr, nullptr, nullptr, nullptr};
+        int nsrc = 0;
+        if constexpr (EPI == kEpiPrior) {
+            srcs[0] = static_cast<const T *>(E.cin);
+            nsrc = 1;
+        } else if constexpr (EPI == kEpiPcg) {
+            srcs[0] = B.r;
+            srcs[1] = static_cast<const T *>(E.c);
+            srcs[2] = B.p;
+            srcs[3] = B.q;
+            nsrc = E.k > 0 ? 4 : 2;
+        } else if constexpr (EPI == kEpiRhs) {
+            srcs[0] = B.b_prev;
+            srcs[1] = B.r;
+            nsrc = E.cold ? 0 : 2;
+        }
+        const int lm = __ffs(m0) - 1;
 #pragma unroll
-            for (int b = 0; b < 6; ++b) cols[b] = (2 * q + b) & msk;
-            T ll = 0, lh = 0, hl = 0, hh = 0;
+        for (int j = 0; j < (NOP > 0 ? NOP : 1); ++j) {
+            if (j < nsrc) {
 #pragma unroll
-            for (int a = 0; a < 6; ++a) {
-                const T *row = cs + ((2 * r + a) & msk) * mi;
-                T ax = 0, dx = 0;
-#pragma unroll
-                for (int b = 0; b < 6; ++b) {
-                    const T xv = row[cols[b]];
-                    ax += tp.h[b] * xv;
-                    dx += tp.g[b] * xv;
+                for (int c = 0; c < NL; ++c) {
+                    const int k = tid + c * kCB;
+                    if (c * kCB < mm && k < mm) {
+                        const T *gp = srcs[j] + coff + (long)(k >> lm) * n + (k & (m0 - 1));
+                        if constexpr (sizeof(T) == 4) g2lds(gp, opl + j * mm + c * kCB + (tid & ~63));
+                        else opl[j * mm + k] = *gp;
+                    }
                 }
-                ll += tp.h[a] * ax;
-                lh += tp.g[a] * ax;
-                hl += tp.h[a] * dx;
-                hh += tp.g[a] * dx;
             }
-            const T w[4] = {ll, hl, lh, hh};
+        }
+    }
+    StepOut so{0.0, 0.0, 0};
+    if constexpr (EPI == kEpiPcg) so = read_step(B.sc);
+    lds_fence();
+    for (int s = KF + 1; s <= J; ++s) {
+        const int mi = n >> (s - 1), h = mi >> 1, msk = mi - 1, nq = h * h;
+        T ad = 0, ji[4] = {0, 0, 0, 0};
+        if (EPI == kEpiPrior || EPI == kEpiPcg) ad = B.ad[l * (J + 1) + s];
+        if (EPI == kEpiPcg) {
 #pragma unroll
-            for (int o = 0; o <= 3; ++o) {
-                if (o == 0 && s != J) continue;
-                const int lr = r + ((o == 2 || o == 3) ? h : 0), lc = q + ((o == 1 || o == 3) ? h : 0);
-                const int li = (lr << lm) + lc;
-                T e0 = 0, e1 = 0;
-                if constexpr (NE >= 1) e0 = e0s[li];
-                if constexpr (NE >= 2) e1 = e1s[li];
-                deliver<T, EPI>(B, E, coff + (long)lr * n + lc, w[o], ad, EPI == kEpiPcg ? sJi[s * 4 + o] : (T)0, e0,
-                                e1, rho, mu);
+            for (int o = 0; o < 4; ++o) ji[o] = B.jinv[(l * (J + 1) + s) * 4 + o];
+        }
+        for (int q0 = 0; q0 < nq; q0 += kCB) {
+            const int qi = q0 + tid;
+            const bool act = qi < nq;
+            const int r = act ? qi / h : 0, q = act ? qi - r * h : 0;
+            T op[4][NOP > 0 ? NOP : 1];
+            if (NOP > 0) {
+#pragma unroll
+                for (int o = 0; o < 4; ++o) {
+                    if (o > 0 || s == J) {
+                        const int br = r + (o >= 2 ? h : 0), bc = q + ((o & 1) ? h : 0);
+                        if (pre) {
+#pragma unroll
+                            for (int j = 0; j < (NOP > 0 ? NOP : 1); ++j) op[o][j] = opl[j * mm + br * m0 + bc];
+                            if (EPI == kEpiPcg && E.k == 0) op[o][2] = op[o][3] = (T)0;
+                            if (EPI == kEpiRhs && E.cold) op[o][0] = op[o][1] = (T)0;
+                        } else {  // every lane loads (quad 0 stands in for lanes without one)
+                            epi_load<T, EPI>(B, E, coff + (long)br * n + bc, op[o]);
+                        }
+                    }
+                }
             }
-            if (s != J) cd[r * h + q] = ll;
+            if (act) {
+                T w[4] = {0, 0, 0, 0};
+#pragma unroll
+                for (int a = 0; a < 6; ++a) {
+                    const T *row = cs + ((2 * r + a) & msk) * mi;
+                    T ax = 0, dx = 0;
+#pragma unroll
+                    for (int b = 0; b < 6; ++b) {
+                        const T xv = row[(2 * q + b) & msk];
+                        ax += tp.h[b] * xv;
+                        dx += tp.g[b] * xv;
+                    }
+                    w[0] += tp.h[a] * ax;
+                    w[2] += tp.g[a] * ax;
+                    w[1] += tp.h[a] * dx;
+                    w[3] += tp.g[a] * dx;
+                }
+#pragma unroll
+                for (int o = 1; o < 4; ++o) epi_store<T, EPI>(B, E, band_index(coff, n, s, o, r, q), w[o], op[o], ji[o], ad, so);
+                if (s == J) epi_store<T, EPI>(B, E, band_index(coff, n, s, 0, r, q), w[0], op[0], ji[0], ad, so);
+                else cd[r * h + q] = w[0];
+            }
         }
         __syncthreads();
-        T *tmp = cs;
+        T *t = cs;
         cs = cd;
-        cd = tmp;
-    }
-    if constexpr (EPI == kEpiPcg) {
-        const double a = block_sum(rho, sh), b = block_sum(mu, sh);
-        if (threadIdx.x == 0) {
-            B.partials[nfine + l] = a;
-            B.partials[kPartialPitch + nfine + l] = b;
-        }
+        cd = t;
     }
 }
 
@@ -1055,15 +1031,15 @@ __global__ __launch_bounds__(512) void k_fwd_coarse(Bufs<T> B, int J, int KF, Fw
 // ---------------------------------------------------------------------------------------------
 // Weighted squared norm sum_k C_eta^-1_k s_k^2 (preconditioner probes): one partial per block.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_wnorm(const T *__restrict__ s, Bufs<T> B, int nw) {
-    __shared__ double sh[kBlock / 64];
+__global__ __launch_bounds__(kB) void k_wnorm(const T *__restrict__ s, Bufs<T> B, int nw, PupilArgs pa) {
+    __shared__ double sh[kB / 64];
     double acc = 0.0;
     for (int g = 0; g < nw; ++g) {
         const DevWfs W = B.wfs[g];
         const long n2 = (long)W.n_sub * W.n_sub;
         for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (long)gridDim.x * blockDim.x) {
             int r = (int)(i / W.n_sub), q = (int)(i - (long)r * W.n_sub);
-            if (!subap_active(W, r, q)) continue;
+            if (!subap_active(pa, W.n_sub, r, q)) continue;
             const double sx = (double)s[W.s_off + i], sy = (double)s[W.s_off + n2 + i];
             acc += W.inv_var * (sx * sx + sy * sy);
         }
@@ -1073,8 +1049,8 @@ __global__ __launch_bounds__(kBlock) void k_wnorm(const T *__restrict__ s, Bufs<
 }
 
 // Sum of n partials in fixed order -> sc[2].rho (single workgroup).
-__global__ __launch_bounds__(kBlock) void k_sum_partials(const double *__restrict__ partials, int n, Scalars *sc) {
-    __shared__ double sh[kBlock / 64];
+__global__ __launch_bounds__(kB) void k_sum_partials(const double *__restrict__ partials, int n, Scalars *sc) {
+    __shared__ double sh[kB / 64];
     double a = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) a += partials[i];
     const double t = block_sum(a, sh);
@@ -1083,8 +1059,8 @@ __global__ __launch_bounds__(kBlock) void k_sum_partials(const double *__restric
 
 // Fitting (bilinear on-axis sampling of the layers at the actuators of their DM) + gain.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fit(const T *__restrict__ u, const T *__restrict__ a_prev, T *__restrict__ a,
-                                                Bufs<T> B, int nl, int nd, long n_act, double gain) {
+__global__ __launch_bounds__(kB) void k_fit(const T *__restrict__ u, const T *__restrict__ a_prev, T *__restrict__ a,
+                                            Bufs<T> B, int nl, int nd, long n_act, double gain) {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_act) return;
     int m = 0;
@@ -1108,9 +1084,9 @@ __global__ __launch_bounds__(kBlock) void k_fit(const T *__restrict__ u, const T
 
 // Cell tables: entry (g, l, j) of each axis from the ray geometry (setup, once per bind).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_build_tabs(Ent<T> *xtab, Ent<T> *ytab, const DevWfs *__restrict__ wfs,
-                                                       const DevProj *__restrict__ proj,
-                                                       const DevLayer *__restrict__ lays, int nw, int nl, int maxnv) {
+__global__ __launch_bounds__(kB) void k_build_tabs(Ent<T> *xtab, Ent<T> *ytab, const DevWfs *__restrict__ wfs,
+                                                   const DevProj *__restrict__ proj,
+                                                   const DevLayer *__restrict__ lays, int nw, int nl, int maxnv) {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)nw * nl * maxnv) return;
     const int j = (int)(idx % maxnv), gl = (int)(idx / maxnv), l = gl % nl, g = gl / nl;
@@ -1130,15 +1106,14 @@ __global__ __launch_bounds__(kBlock) void k_build_tabs(Ent<T> *xtab, Ent<T> *yta
 
 // Transpose of the cell tables: for grid line q of layer l, the sensor nodes j whose cell
 // touches it (k0_j in {q-1, q}; contiguous since k0_j is non-decreasing in j) as a range, and as
-// a zero-padded list of (j, weight) pairs of width kRtabWidth; lines with more pairs than that
-// set over[g] (the plan then uses the scanning transpose).
+// a list of (j, weight) pairs of width kRtabWidth padded with index -1; lines with more pairs than
+// that set over[g] (the plan then uses the scanning transpose).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_build_ranges(Range *xrng, Range *yrng, RtabEnt<T> *xrt, RtabEnt<T> *yrt,
-                                                         const Ent<T> *__restrict__ xtab,
-                                                         const Ent<T> *__restrict__ ytab,
-                                                         const DevWfs *__restrict__ wfs,
-                                                         const DevLayer *__restrict__ lays, int nw, int nl, int maxnv,
-                                                         int sum_n, int *over) {
+__global__ __launch_bounds__(kB) void k_build_ranges(Range *xrng, Range *yrng, RtabEnt<T> *xrt, RtabEnt<T> *yrt,
+                                                     const Ent<T> *__restrict__ xtab, const Ent<T> *__restrict__ ytab,
+                                                     const DevWfs *__restrict__ wfs,
+                                                     const DevLayer *__restrict__ lays, int nw, int nl, int maxnv,
+                                                     int sum_n, int *over) {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)nw * sum_n) return;
     const int g = (int)(idx / sum_n), line = (int)(idx % sum_n);
@@ -1158,7 +1133,7 @@ __global__ __launch_bounds__(kBlock) void k_build_ranges(Range *xrng, Range *yrn
                 ++cnt;
             }
         }
-        for (int c = cnt; c < kRtabWidth; ++c) rt[c] = RtabEnt<T>{0, (T)0};
+        for (int c = cnt; c < kRtabWidth; ++c) rt[c] = RtabEnt<T>{-1, (T)0};
         if (cnt > kRtabWidth) over[g] = 1;  // idempotent flag, no read-modify-write needed
         Range r{lo, hi};
         if (hi < 0) r = Range{1, 0};
@@ -1166,31 +1141,85 @@ __global__ __launch_bounds__(kBlock) void k_build_ranges(Range *xrng, Range *yrn
     }
 }
 
+// Record of every (P^T tile, guide star): the node rows / columns that the transpose pairs of
+// the tile's rows / columns name, packed as (lo | hi << 16) (empty: lo > hi), and the largest pair
+// count over the tile's rows and over its columns.  One workgroup per tile.
+__global__ __launch_bounds__(kMaxWfs) void k_build_rects(SegTab S, const Range *__restrict__ xrng,
+                                                         const Range *__restrict__ yrng, int4 *rects, int nw, int sum_n) {
+    const int g = threadIdx.x;
+    if (g >= nw) return;
+    const TileId id = find_tile(S);
+    const int l = id.seg, n = S.n[l], lt = S.lt[l];
+    const int T0 = n < kPtTile ? n : kPtTile;
+    const int k0 = (id.loc >> lt) * T0, q0 = (id.loc & ((1 << lt) - 1)) * T0;
+    int iA = 1 << 30, iB = -1, jA = 1 << 30, jB = -1, cy = 0, cx = 0;
+    for (int t = 0; t < T0; ++t) {
+        const Range ry = yrng[(long)g * sum_n + S.aux[l] + k0 + t];
+        const Range rx = xrng[(long)g * sum_n + S.aux[l] + q0 + t];
+        if (ry.lo <= ry.hi) {
+            iA = ry.lo < iA ? ry.lo : iA;
+            iB = ry.hi > iB ? ry.hi : iB;
+            cy = ry.hi - ry.lo + 1 > cy ? ry.hi - ry.lo + 1 : cy;
+        }
+        if (rx.lo <= rx.hi) {
+            jA = rx.lo < jA ? rx.lo : jA;
+            jB = rx.hi > jB ? rx.hi : jB;
+            cx = rx.hi - rx.lo + 1 > cx ? rx.hi - rx.lo + 1 : cx;
+        }
+    }
+    if (iA > iB || jA > jB) {
+        iA = jA = 1;
+        iB = jB = 0;
+        cy = cx = 0;
+    }
+    rects[(long)blockIdx.x * nw + g] = make_int4(iA | (iB << 16), jA | (jB << 16), cy, cx);
+}
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fill(T *__restrict__ x, long n, T val) {
+__global__ __launch_bounds__(kB) void k_fill(T *__restrict__ x, long n, T val) {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) x[i] = val;
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_copy(T *__restrict__ dst, const T *__restrict__ src, long n) {
+__global__ __launch_bounds__(kB) void k_copy(T *__restrict__ dst, const T *__restrict__ src, long n) {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) dst[i] = src[i];
 }
 
 __global__ void k_init_scalars(Scalars *sc) {
-    if (threadIdx.x < 3 && blockIdx.x == 0) {
+    if (threadIdx.x < 4 && blockIdx.x == 0) {
         reset_scalars(sc + threadIdx.x);
         sc[threadIdx.x].counter = 0u;
     }
 }
 
 int grid_for(long n) {
-    long g = (n + kBlock - 1) / kBlock;
+    long g = (n + kB - 1) / kB;
     if (g < 1) g = 1;
     if (g > 2048) g = 2048;
     return (int)g;
 }
 
 int check() { return hipGetLastError() == hipSuccess ? FEWHA_OK : FEWHA_ERR_HIP; }
+
+InvVar inv_var_tab(const Plan &P) {
+    InvVar t{};
+    for (int g = 0; g < P.nw; ++g) t.v[g] = P.dwfs[g].inv_var;
+    return t;
+}
+
+WfsOff wfs_off_tab(const Plan &P) {
+    WfsOff t{};
+    for (int g = 0; g < P.nw; ++g) {
+        t.v_off[g] = (int)P.dwfs[g].v_off;
+        t.n_sub[g] = P.dwfs[g].n_sub;
+    }
+    return t;
+}
+
+PupilArgs pupil(const Plan &P) {
+    const double ro = P.D / 2, ri = P.obstruction * P.D / 2;
+    return PupilArgs{P.D, ro * ro, ri * ri};
+}
 
 }  // namespace
 
@@ -1211,146 +1240,93 @@ Taps<T> make_taps() {
 }
 
 template <typename T>
-int Ops<T>::nparts() const {
-    return (int)P.fine_tiles.size() + (P.kf < P.J ? P.nl : 0);
-}
-
-template <typename T>
-int Ops<T>::idwt(const T *c, T *out) const {
-    InvArgs A{};
-    A.src = c;
-    A.out = out;
-    k_inv<T, kInvPlain><<<(int)P.idwt_tiles.size(), kInvBlock, 0, st>>>(B, P.J, A, make_taps<T>());
+int Ops<T>::wt(const T *c, T *out) const {
+    k_wt<T, kWtPlain><<<P.n_wt, kWB, 0, st>>>(P.seg_wt, c, out, B, make_taps<T>(), P.J);
     return check();
 }
 
 template <typename T>
-int Ops<T>::idwt_first(const T *r, T *out) const {
-    InvArgs A{};
-    A.src = r;
-    A.out = out;
-    k_inv<T, kInvFirst><<<(int)P.idwt_tiles.size(), kInvBlock, 0, st>>>(B, P.J, A, make_taps<T>());
+int Ops<T>::wt_pcg(const T *r, T *out) const {
+    k_wt<T, kWtPcg><<<P.n_wt, kWB, 0, st>>>(P.seg_wt, r, out, B, make_taps<T>(), P.J);
     return check();
 }
 
 template <typename T>
-int Ops<T>::idwt_update(const T *r_old, const T *q_old, T *q_new, T *r_new, T *c, int kprev, double *resnorm,
-                        T *out) const {
-    InvArgs A{};
-    A.src = r_old;
-    A.out = out;
-    A.yv = B.y;
-    A.qold = kprev == 0 ? B.y : q_old;  // never read after the first pass
-    A.qnew = q_new;
-    A.rnew = r_new;
-    A.c = c;
-    A.first_pass = kprev == 0 ? 1 : 0;
-    A.kprev = kprev;
-    A.nparts = nparts();
-    A.resnorm = resnorm;
-    k_inv<T, kInvUpdate><<<(int)P.idwt_tiles.size(), kInvBlock, 0, st>>>(B, P.J, A, make_taps<T>());
+int Ops<T>::proj(const T *u, T *out, int mode) const {
+    if (mode == kProjM)
+        k_proj<T, kProjM><<<P.n_proj, kB, 0, st>>>(P.seg_proj, P.laytab, inv_var_tab(P), pupil(P), u, out, B, P.nl);
+    else
+        k_proj<T, kProjA><<<P.n_proj, kB, 0, st>>>(P.seg_proj, P.laytab, inv_var_tab(P), pupil(P), u, out, B, P.nl);
     return check();
 }
 
 template <typename T>
-template <int EPI>
-size_t Ops<T>::coarse_lds() const {
-    constexpr int NE = (EPI == kEpiRhs) ? 2 : ((EPI == kEpiPlain) ? 0 : 1);
-    size_t m0 = 0;
-    for (auto &L : P.lay) m0 = (size_t)(L.n >> P.kf) > m0 ? (size_t)(L.n >> P.kf) : m0;
-    return (m0 * m0 + m0 * m0 / 4 + 1 + NE * m0 * m0) * sizeof(T);
+int Ops<T>::gt(const T *s, T *v, int mode) const {
+    if (mode == kGtRhs) k_gt<T, kGtRhs><<<P.n_proj, kB, 0, st>>>(P.seg_proj, inv_var_tab(P), pupil(P), s, v);
+    else k_gt<T, kGtAdj><<<P.n_proj, kB, 0, st>>>(P.seg_proj, inv_var_tab(P), pupil(P), s, v);
+    return check();
 }
 
 template <typename T>
-template <int EPI>
-int Ops<T>::fwd(const T *x, const FwdArgs &E) const {
-    const int nf = (int)P.fine_tiles.size();
+int Ops<T>::pt(const T *v, T *x, const PassArgs &PA) const {
+    const int grid = P.n_pt + (PA.k >= 0 ? 1 : 0);
+    if (P.rtab_ok) k_pt<T><<<grid, kB, P.pt_lds, st>>>(P.seg_pt, wfs_off_tab(P), v, x, B, P.nw, PA);
+    else k_pt_scan<T><<<grid, kB, 0, st>>>(P.seg_pt, v, x, B, P.nl, P.nw, PA);
+    return check();
+}
+
+template <typename T, int EPI>
+static int fwd_launch(const Plan &P, const Bufs<T> &B, hipStream_t st, const T *x, const FwdArgs &E) {
     const Taps<T> tp = make_taps<T>();
-    switch (P.kf) {
-        case 1: k_fwd_fine<T, 1, 16, EPI><<<nf, kFwdBlock, 0, st>>>(x, B, P.J, E, tp); break;
-        case 2: k_fwd_fine<T, 2, 8, EPI><<<nf, kFwdBlock, 0, st>>>(x, B, P.J, E, tp); break;
-        default: k_fwd_fine<T, 3, 4, EPI><<<nf, kFwdBlock, 0, st>>>(x, B, P.J, E, tp); break;
+    const int nf = P.n_fwd, nwt = P.n_wt, npj = P.n_proj;
+#define FEWHA_FWD(KF, TQ) k_fwd<T, KF, TQ, EPI><<<nf, kFB, 0, st>>>(P.seg_fwd, x, B, E, tp, P.J, nwt, npj)
+    if (P.kf == 1) {
+        switch (P.tq) {
+            case 1: FEWHA_FWD(1, 1); break;
+            case 2: FEWHA_FWD(1, 2); break;
+            case 4: FEWHA_FWD(1, 4); break;
+            default: FEWHA_FWD(1, 8); break;
+        }
+    } else {
+        switch (P.tq) {
+            case 1: FEWHA_FWD(2, 1); break;
+            case 2: FEWHA_FWD(2, 2); break;
+            case 4: FEWHA_FWD(2, 4); break;
+            default: FEWHA_FWD(2, 8); break;
+        }
     }
+#undef FEWHA_FWD
     if (int e = check()) return e;
     if (P.kf < P.J) {
-        k_fwd_coarse<T, EPI><<<P.nl, 512, coarse_lds<EPI>(), st>>>(B, P.J, P.kf, E, tp, nf);
+        size_t m = 0;
+        for (auto &L : P.lay) m = (size_t)(L.n >> P.kf) > m ? (size_t)(L.n >> P.kf) : m;
+        const size_t base = (m * m + m * m / 4) * sizeof(T), opb = (size_t)EpiOps<EPI>::n * m * m * sizeof(T);
+        const int pre = EpiOps<EPI>::n > 0 && base + opb <= kCoarseLdsMax ? 1 : 0;
+        k_coarse<T, EPI><<<P.nl, kCB, base + (pre ? opb : 0), st>>>(P.laytab, B, E, tp, P.J, P.kf, nwt, npj, pre);
         if (int e = check()) return e;
     }
     return FEWHA_OK;
 }
 
 template <typename T>
+int Ops<T>::fwd(const T *x, const FwdArgs &E, int epi) const {
+    switch (epi) {
+        case kEpiPlain: return fwd_launch<T, kEpiPlain>(P, B, st, x, E);
+        case kEpiPrior: return fwd_launch<T, kEpiPrior>(P, B, st, x, E);
+        case kEpiPcg: return fwd_launch<T, kEpiPcg>(P, B, st, x, E);
+        default: return fwd_launch<T, kEpiRhs>(P, B, st, x, E);
+    }
+}
+
+template <typename T>
 int Ops<T>::prepare() const {
     // the per-layer coarse transform may need more than the default 64 KiB of dynamic LDS
-    const void *fns[4] = {(const void *)k_fwd_coarse<T, kEpiPlain>, (const void *)k_fwd_coarse<T, kEpiPrior>,
-                          (const void *)k_fwd_coarse<T, kEpiPcg>, (const void *)k_fwd_coarse<T, kEpiRhs>};
-    const size_t need[4] = {coarse_lds<kEpiPlain>(), coarse_lds<kEpiPrior>(), coarse_lds<kEpiPcg>(),
-                            coarse_lds<kEpiRhs>()};
+    const void *fns[4] = {(const void *)k_coarse<T, kEpiPlain>, (const void *)k_coarse<T, kEpiPrior>,
+                          (const void *)k_coarse<T, kEpiPcg>, (const void *)k_coarse<T, kEpiRhs>};
     for (int i = 0; i < 4; ++i)
-        if (need[i] > 48 * 1024 &&
-            hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)need[i]) != hipSuccess)
+        if (hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCoarseLdsMax) != hipSuccess)
             return FEWHA_ERR_UNSUPPORTED;
     return FEWHA_OK;
-}
-
-template <typename T>
-int Ops<T>::fdwt(const T *x, T *out) const {
-    FwdArgs E{};
-    E.out = out;
-    return fwd<kEpiPlain>(x, E);
-}
-
-template <typename T>
-int Ops<T>::fdwt_prior(const T *x, const T *cin, T *out) const {
-    FwdArgs E{};
-    E.out = out;
-    E.cin = cin;
-    return fwd<kEpiPrior>(x, E);
-}
-
-template <typename T>
-int Ops<T>::fdwt_pcg(const T *x, const T *rk) const {
-    FwdArgs E{};
-    E.out = B.y;
-    E.rk = rk;
-    return fwd<kEpiPcg>(x, E);
-}
-
-template <typename T>
-int Ops<T>::fdwt_rhs(const T *x, T *c, bool cold) const {
-    FwdArgs E{};
-    E.c = c;
-    E.cold = cold ? 1 : 0;
-    return fwd<kEpiRhs>(x, E);
-}
-
-template <typename T>
-int Ops<T>::nodes(const T *in, T *v, int mode) const {
-    const int tiles = (int)P.node_tiles.size();
-    if (mode == kModeM) k_nodes_m<T><<<tiles, kNodeBlock, 0, st>>>(in, v, B, P.nl);
-    else if (mode == kModeRhs) k_nodes<T, kModeRhs><<<tiles, kBlock, 0, st>>>(in, v, B);
-    else k_nodes<T, kModeAdj><<<tiles, kBlock, 0, st>>>(in, v, B);
-    return check();
-}
-
-template <typename T>
-int Ops<T>::slopes(const T *u, T *s) const {
-    k_slopes<T><<<(int)P.sub_tiles.size(), kNodeBlock, 0, st>>>(u, s, B, P.nl);
-    return check();
-}
-
-template <typename T>
-int Ops<T>::pt(const T *v, T *x) const {
-    if (P.rtab_ok) k_pt_tab<T><<<(int)P.lay_tiles.size(), kBlock, 0, st>>>(v, x, B, P.nl, P.nw);
-    else k_pt_scan<T><<<(int)P.lay_tiles.size(), kBlock, 0, st>>>(v, x, B, P.nl, P.nw);
-    return check();
-}
-
-template <typename T>
-int Ops<T>::update_last(T *c, const T *r_in, const T *q_old, T *q_new, int kprev, double *resnorm) const {
-    k_update_last<T><<<(int)P.coef_tiles.size(), kBlock, 0, st>>>(c, B, P.J, r_in, kprev == 0 ? B.y : q_old, q_new,
-                                                                    kprev == 0 ? 1 : 0, nparts(), kprev, resnorm);
-    return check();
 }
 
 template <typename T>
@@ -1359,40 +1335,42 @@ int Ops<T>::wnorm(const T *s) const {
     for (auto &w : P.dwfs) mx = mx > (long)w.n_sub * w.n_sub ? mx : (long)w.n_sub * w.n_sub;
     int g = grid_for(mx);
     if (g > kPartialPitch) g = kPartialPitch;
-    k_wnorm<T><<<g, kBlock, 0, st>>>(s, B, P.nw);
+    k_wnorm<T><<<g, kB, 0, st>>>(s, B, P.nw, pupil(P));
     if (int e = check()) return e;
-    k_sum_partials<<<1, kBlock, 0, st>>>(B.partials, g, B.sc);
+    k_sum_partials<<<1, kB, 0, st>>>(B.partials, g, B.sc);
     return check();
 }
 
 template <typename T>
 int Ops<T>::fit(const T *u, const T *a_prev, T *a, double gain) const {
-    k_fit<T><<<grid_for((long)P.n_act), kBlock, 0, st>>>(u, a_prev, a, B, P.nl, P.nd, (long)P.n_act, gain);
+    k_fit<T><<<grid_for((long)P.n_act), kB, 0, st>>>(u, a_prev, a, B, P.nl, P.nd, (long)P.n_act, gain);
     return check();
 }
 
 template <typename T>
 int Ops<T>::build_tables(int *over) const {
     const long ne = (long)P.nw * P.nl * P.maxnv;
-    k_build_tabs<T><<<(int)((ne + kBlock - 1) / kBlock), kBlock, 0, st>>>(
-        const_cast<Ent<T> *>(B.xtab), const_cast<Ent<T> *>(B.ytab), B.wfs, B.proj, B.lay, P.nw, P.nl, P.maxnv);
+    k_build_tabs<T><<<(int)((ne + kB - 1) / kB), kB, 0, st>>>(const_cast<Ent<T> *>(B.xtab), const_cast<Ent<T> *>(B.ytab),
+                                                              B.wfs, B.proj, B.lay, P.nw, P.nl, P.maxnv);
     if (int e = check()) return e;
     const long nr = (long)P.nw * P.sum_n;
-    k_build_ranges<T><<<(int)((nr + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+    k_build_ranges<T><<<(int)((nr + kB - 1) / kB), kB, 0, st>>>(
         const_cast<Range *>(B.xrng), const_cast<Range *>(B.yrng), const_cast<RtabEnt<T> *>(B.xrtab),
         const_cast<RtabEnt<T> *>(B.yrtab), B.xtab, B.ytab, B.wfs, B.lay, P.nw, P.nl, P.maxnv, P.sum_n, over);
+    if (int e = check()) return e;
+    k_build_rects<<<P.n_pt, kMaxWfs, 0, st>>>(P.seg_pt, B.xrng, B.yrng, const_cast<int4 *>(B.rects), P.nw, P.sum_n);
     return check();
 }
 
 template <typename T>
 int Ops<T>::fill(T *x, long n, T val) const {
-    k_fill<T><<<grid_for(n), kBlock, 0, st>>>(x, n, val);
+    k_fill<T><<<grid_for(n), kB, 0, st>>>(x, n, val);
     return check();
 }
 
 template <typename T>
 int Ops<T>::copy(T *dst, const T *src, long n) const {
-    k_copy<T><<<grid_for(n), kBlock, 0, st>>>(dst, src, n);
+    k_copy<T><<<grid_for(n), kB, 0, st>>>(dst, src, n);
     return check();
 }
 

@@ -45,6 +45,23 @@ int level_band(int n, int J, int row, int col, int *s, int *o) {
     return 0;
 }
 
+void wt_cone(int y0, int x0, int T0, int J, int *loY, int *loX, int *LY, int *LX) {
+    int ly = y0, hy = y0 + T0 - 1, lx = x0, hx = x0 + T0 - 1;
+    loY[0] = ly;
+    loX[0] = lx;
+    LY[0] = LX[0] = T0;
+    for (int s = 1; s <= J; ++s) {
+        ly = ((ly >> 1) - 2) & ~1;
+        hy >>= 1;
+        lx = ((lx >> 1) - 2) & ~1;
+        hx >>= 1;
+        loY[s] = ly;
+        loX[s] = lx;
+        LY[s] = hy - ly + 1;
+        LX[s] = hx - lx + 1;
+    }
+}
+
 int plan_create(const fewha_config *cfg, Plan **out) {
     if (!cfg || !out) return FEWHA_ERR_INVALID_ARG;
     *out = nullptr;
@@ -194,48 +211,88 @@ int plan_create(const fewha_config *cfg, Plan **out) {
                                                 std::pow(P->lay[l].spacing / P->dwfs[0].d, -5.0 / 3.0) *
                                                 std::pow(2.0, -(11.0 / 3.0) * (s - 1));
 
-    // forward DWT split: the first kf levels in tiles over the whole GPU, the remaining ones per
-    // layer inside one workgroup whose LDS holds the level-kf approximation (1.25 m^2 values)
-    int max_n = 0;
-    for (auto &L : P->lay) max_n = L.n > max_n ? L.n : max_n;
-    P->kf = 0;
-    for (int k = (P->J < 2 ? P->J : 2); k <= (P->J < 3 ? P->J : 3); ++k) {
-        size_t m = size_t(max_n >> k);
-        if (m * m * P->elem * 5 / 4 <= 48 * 1024) {
-            P->kf = k;
-            break;
-        }
+    // forward DWT split: levels 1..kf on tiles of tq x tq level-kf quads over the whole GPU, the
+    // remaining ones per layer in one workgroup whose LDS holds the level-kf approximation
+    int max_n = 0, min_n = 1 << 30;
+    for (auto &L : P->lay) {
+        max_n = L.n > max_n ? L.n : max_n;
+        min_n = L.n < min_n ? L.n : min_n;
     }
-    if (P->kf == 0 || P->n_coef >= (size_t(1) << 31)) {
+    P->kf = P->J < 2 ? P->J : 2;
+    P->tq = kFwdQuads;
+    while (P->tq > (min_n >> P->kf)) P->tq >>= 1;
+    {
+        size_t m = size_t(max_n >> P->kf);
+        P->coarse_lds = P->kf < P->J ? (m * m + (m / 2) * (m / 2)) * P->elem : 0;
+    }
+    if (P->coarse_lds > 150 * 1024 || (size_t(max_n >> P->kf) * (max_n >> P->kf) > size_t(16) * 1024) ||
+        P->n_coef >= (size_t(1) << 31) || P->n_nodes >= (size_t(1) << 31) || P->n_slopes >= (size_t(1) << 31)) {
         delete P;
         return FEWHA_ERR_UNSUPPORTED;
     }
-    P->tq = P->kf == 1 ? 16 : (P->kf == 2 ? 8 : 4);
-    {
-        size_t m = size_t(max_n >> P->kf);
-        P->coarse_lds = (m * m + (m * m) / 4 + 4) * P->elem;
-    }
 
-    // tile tables
+    // tile tables (kernel arguments): inverse DWT, P^T and fine forward DWT per layer, projection
+    // node tiles per guide star
+    auto lg2 = [](int v) {
+        int k = 0;
+        while ((1 << k) < v) ++k;
+        return k;
+    };
+    P->seg_wt.nseg = P->seg_pt.nseg = P->seg_fwd.nseg = P->nl;
     for (int l = 0; l < P->nl; ++l) {
-        const int n = P->lay[l].n, t = n < kIdwtTile ? n : kIdwtTile, off = int(P->dlay[l].c_off);
-        const int lg = P->dlay[l].log2n;
-        for (int ty = 0; ty < n; ty += t)
-            for (int tx = 0; tx < n; tx += t) P->idwt_tiles.push_back({l, ty, tx, t, off, n, lg, 0});
-        for (int ty = 0; ty < n; ty += kNodeTile)
-            for (int tx = 0; tx < n; tx += kNodeTile) P->lay_tiles.push_back({l, ty, tx, kNodeTile, off, n, lg, P->dlay[l].r_off});
-        const int m = n >> P->kf, tq = m < P->tq ? m : P->tq, nt = (m / tq) * (m / tq);
-        for (int qy = 0; qy < m; qy += tq)
-            for (int qx = 0; qx < m; qx += tq) P->fine_tiles.push_back({l, qy, qx, tq, off, n, lg, nt});
-        for (int st = 0; st < n * n; st += kCoefTile)
-            P->coef_tiles.push_back({l, st, (n * n - st) < kCoefTile ? (n * n - st) : kCoefTile, 0, off, n, lg, 0});
+        const int n = P->lay[l].n, off = int(P->dlay[l].c_off);
+        const int tw = n < kWtTile ? n : kWtTile, tp = n < kPtTile ? n : kPtTile;
+        const int nq = (n >> P->kf) / P->tq;
+        SegTab *S[3] = {&P->seg_wt, &P->seg_pt, &P->seg_fwd};
+        const int per_row[3] = {n / tw, n / tp, nq};
+        int *cnt[3] = {&P->n_wt, &P->n_pt, &P->n_fwd};
+        for (int k = 0; k < 3; ++k) {
+            S[k]->start[l] = *cnt[k];
+            S[k]->off[l] = off;
+            S[k]->aux[l] = P->dlay[l].r_off;
+            S[k]->n[l] = n;
+            S[k]->lt[l] = lg2(per_row[k]);
+            *cnt[k] += per_row[k] * per_row[k];
+        }
+        // every inverse-DWT cone of this layer must fit the kernel's load slots and LDS
+        for (int y0 = 0; y0 < n; y0 += tw)
+            for (int x0 = 0; x0 < n; x0 += tw) {
+                int loY[kMaxJ + 1], loX[kMaxJ + 1], LY[kMaxJ + 1], LX[kMaxJ + 1];
+                wt_cone(y0, x0, tw, P->J, loY, loX, LY, LX);
+                bool ok = true;
+                for (int s = 1; s <= P->J; ++s) {
+                    const int lanes = s == 1 ? 32 : (s == 2 ? 16 : 8), rows = (s == 1 ? 72 : (s == 2 ? 48 : 32));
+                    ok = ok && LX[s] <= lanes && (s == P->J ? 4 : 3) * LY[s] <= rows;
+                    if (s >= 2) ok = ok && LY[s - 1] * LX[s - 1] <= 18 * 18;
+                    ok = ok && ((LY[s - 1] + 1) & ~1) * LX[s] <= 32 * 18;
+                }
+                if (!ok) {
+                    delete P;
+                    return FEWHA_ERR_UNSUPPORTED;
+                }
+            }
     }
+    P->seg_wt.start[P->nl] = P->n_wt;
+    P->seg_pt.start[P->nl] = P->n_pt;
+    P->seg_fwd.start[P->nl] = P->n_fwd;
+    P->seg_proj.nseg = P->nw;
     for (int g = 0; g < P->nw; ++g) {
-        int nv = P->wfs[g].n_sub + 1, ns = P->wfs[g].n_sub;
-        for (int i = 0; i < nv; i += kNodeTile)
-            for (int j = 0; j < nv; j += kNodeTile) P->node_tiles.push_back({g, i, j, kNodeTile, 0, 0, 0, 0});
-        for (int i = 0; i < ns; i += kNodeTile)
-            for (int j = 0; j < ns; j += kNodeTile) P->sub_tiles.push_back({g, i, j, kNodeTile, 0, 0, 0, 0});
+        const int nv = P->wfs[g].n_sub + 1, tpr = (nv + kProjTile - 1) / kProjTile;
+        P->seg_proj.start[g] = P->n_proj;
+        P->seg_proj.off[g] = int(P->dwfs[g].v_off);
+        P->seg_proj.aux[g] = int(P->dwfs[g].s_off);
+        P->seg_proj.n[g] = P->wfs[g].n_sub;
+        P->seg_proj.lt[g] = tpr;
+        P->n_proj += tpr * tpr;
+    }
+    P->seg_proj.start[P->nw] = P->n_proj;
+    for (int l = 0; l < P->nl; ++l) {
+        P->laytab.off[l] = int(P->dlay[l].c_off);
+        P->laytab.n[l] = P->lay[l].n;
+    }
+    if (P->n_wt > kPartialPitch || P->n_proj > kPartialPitch) {
+        delete P;
+        return FEWHA_ERR_UNSUPPORTED;
     }
 
     // workspace map
@@ -250,44 +307,30 @@ int plan_create(const fewha_config *cfg, Plan **out) {
     P->o_lay = take(sizeof(DevLayer) * P->nl);
     P->o_proj = take(sizeof(DevProj) * P->nw * P->nl);
     P->o_dm = take(sizeof(DevDm) * P->nd);
-    P->o_idwt = take(sizeof(Tile) * P->idwt_tiles.size());
-    P->o_node = take(sizeof(Tile) * P->node_tiles.size());
-    P->o_sub = take(sizeof(Tile) * P->sub_tiles.size());
-    P->o_laytile = take(sizeof(Tile) * P->lay_tiles.size());
-    P->o_fine = take(sizeof(Tile) * P->fine_tiles.size());
-    P->o_coef = take(sizeof(Tile) * P->coef_tiles.size());
     const size_t ent = P->prec == FEWHA_FP64 ? 24 : 16;
     P->o_xtab = take(ent * P->nw * P->nl * P->maxnv);
     P->o_ytab = take(ent * P->nw * P->nl * P->maxnv);
     P->o_xrng = take(sizeof(Range) * P->nw * P->sum_n);
     P->o_yrng = take(sizeof(Range) * P->nw * P->sum_n);
+    P->o_xrtab = take((P->prec == FEWHA_FP64 ? 16 : 8) * size_t(kRtabWidth) * P->nw * P->sum_n);
+    P->o_yrtab = take((P->prec == FEWHA_FP64 ? 16 : 8) * size_t(kRtabWidth) * P->nw * P->sum_n);
+    P->o_rects = take(16 * size_t(P->n_pt) * P->nw);
     P->o_jinv = take(E * P->nl * (P->J + 1) * 4);
     P->o_ad = take(E * P->nl * (P->J + 1));
     P->o_bprev = take(E * N);
     P->o_r = take(E * N);
     P->o_p = take(E * N);
     P->o_q = take(E * N);
-    P->o_y = take(E * N);
     P->o_u = take(E * N);
     P->o_x = take(E * N);
     P->o_v = take(E * P->n_nodes);
-    P->o_tmpA = take(E * (N / 4 + 1));
-    P->o_tmpB = take(E * (N / 4 + 1));
-    P->o_b = take(E * N);
+    P->o_ll = take(E * (N / 4 + 1));
     P->o_probe_c = take(E * N);
+    P->o_stage = take(4 * E * N);  // stage timing: scratch r, p, q, c
     P->o_probe_s = take(E * P->n_slopes);
-    P->o_r2 = take(E * N);
-    P->o_q2 = take(E * N);
-    P->o_lcount = take(sizeof(int) * P->nw);
-    P->o_xrtab = take((P->prec == FEWHA_FP64 ? 16 : 8) * size_t(kRtabWidth) * P->nw * P->sum_n);
-    P->o_yrtab = take((P->prec == FEWHA_FP64 ? 16 : 8) * size_t(kRtabWidth) * P->nw * P->sum_n);
-    P->n_partials = kPartialPitch;
-    if (P->fine_tiles.size() + size_t(P->nl) > size_t(kPartialPitch)) {
-        delete P;
-        return FEWHA_ERR_UNSUPPORTED;
-    }
-    P->o_partials = take(sizeof(double) * 2 * P->n_partials);
-    P->o_scalars = take(3 * sizeof(Scalars));
+    P->o_over = take(sizeof(int) * P->nw);
+    P->o_partials = take(sizeof(double) * 3 * kPartialPitch);
+    P->o_scalars = take(4 * sizeof(Scalars));
     P->ws_bytes = o;
     *out = P;
     return FEWHA_OK;

@@ -19,7 +19,7 @@ STATUS = {0: "FEWHA_OK", -1: "FEWHA_ERR_INVALID_ARG", -2: "FEWHA_ERR_GEOMETRY", 
 EXPORTS = ["fewha_plan_create", "fewha_workspace_bytes", "fewha_plan_bind", "fewha_plan_destroy", "fewha_sizes",
            "fewha_apply_A", "fewha_apply_At", "fewha_apply_M", "fewha_dwt_forward", "fewha_dwt_inverse",
            "fewha_pcg_solve", "fewha_fit_dm", "fewha_state_get", "fewha_state_set", "fewha_precond_table",
-           "fewha_last_status", "fewha_strerror"]
+           "fewha_last_status", "fewha_stage_launch", "fewha_strerror"]
 
 
 class FewhaError(RuntimeError):
@@ -74,6 +74,7 @@ def load_library():
     L.fewha_fit_dm.argtypes = [vp, vp, vp, ctypes.c_double, vp, vp]
     L.fewha_precond_table.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     L.fewha_last_status.argtypes = [vp]
+    L.fewha_stage_launch.argtypes = [vp, ctypes.c_int, vp]
     L.fewha_strerror.argtypes = [ctypes.c_int]
     L.fewha_strerror.restype = ctypes.c_char_p
     _lib = L
@@ -231,6 +232,12 @@ class Plan:
         _check(_lib.fewha_precond_table(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
                "fewha_precond_table")
         return out.reshape(nl, J + 1, 4)
+
+    STAGES = {"wt": 0, "proj": 1, "pt": 2, "fwd": 3}
+
+    def stage_launch(self, stage):
+        """Enqueue one launch of one PCG-pass stage ("wt", "proj", "pt", "fwd") for timing."""
+        _check(_lib.fewha_stage_launch(self._h, self.STAGES[stage], self._stream()), "fewha_stage_launch")
 
     def last_status(self):
         return _lib.fewha_last_status(self._h)
