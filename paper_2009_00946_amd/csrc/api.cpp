@@ -110,10 +110,12 @@ int pcg_solve(const Plan &P, const void *s, void *c, int n_iter, int flags, doub
     R.c = c;
     R.cold = flags == FEWHA_COLD ? 1 : 0;
     TRY(o.fwd(o.B.x, R, kEpiRhs));
+    // partial sums of (r, z) and (z, alpha D z) come from the forward transforms that write r
+    const int nres = P.n_fwd + (P.kf < P.J ? P.nl : 0);
     for (int k = 0; k < n_iter; ++k) {
-        TRY(o.wt_pcg(o.B.r, o.B.u));             // u = W^T J^-1 r; (r, z), (z, alpha D z) partials
+        TRY(o.wt_pcg(o.B.r, o.B.u));             // u = W^T J^-1 r
         TRY(o.proj(o.B.u, o.B.v, kProjM));       // v = Gamma^T C Gamma P u; (C Gamma P u, Gamma P u) partials
-        TRY(o.pt(o.B.v, o.B.x, PassArgs{k, P.n_wt, P.n_proj, 1, resnorm}));  // x = P^T v; Alg. 2 scalars
+        TRY(o.pt(o.B.v, o.B.x, PassArgs{k, nres, P.n_proj, 1, resnorm}));  // x = P^T v; Alg. 2 scalars
         FwdArgs E{};                             // y = W x + alpha D z; the pass update
         E.c = c;
         E.k = k;
@@ -138,7 +140,8 @@ int stage_launch(const Plan &P, int stage, void *stream) {
     switch (stage) {
         case FEWHA_STAGE_WT: return o.wt_pcg(o.B.r, o.B.u);
         case FEWHA_STAGE_PROJ: return o.proj(o.B.u, o.B.v, kProjM);
-        case FEWHA_STAGE_PT: return o.pt(o.B.v, o.B.x, PassArgs{1, P.n_wt, P.n_proj, 0, nullptr});
+        case FEWHA_STAGE_PT:
+            return o.pt(o.B.v, o.B.x, PassArgs{1, P.n_fwd + (P.kf < P.J ? P.nl : 0), P.n_proj, 0, nullptr});
         default: {
             // the frame's y = W x + alpha D z with the pass update, applied to scratch copies of
             // r, p, q and c, without publishing scalars
@@ -190,23 +193,22 @@ int bind_tables(Plan &P, hipStream_t st) {
         for (int g = 0; g < P.nw; ++g)
             if (over[g]) P.rtab_ok = false;
         size_t stage = 1;
+        const int ch = P.prec == FEWHA_FP64 ? 2 : 4;  // values per 16-byte chunk
         for (int l = 0; l < P.nl; ++l) {
-            int cr = 1, cw = 1;
-            for (int t = P.seg_pt.start[l]; t < P.seg_pt.start[l + 1]; ++t)
+            for (int t = P.seg_pt.start[l]; t < P.seg_pt.start[l + 1]; ++t) {
+                size_t need = 0;
                 for (int g = 0; g < P.nw; ++g) {
                     const int4 R = rects[size_t(t) * P.nw + g];  // rows / columns packed lo | hi << 16
-                    const int rr = (R.x >> 16) - (R.x & 0xffff) + 1, rc = (R.y >> 16) - (R.y & 0xffff) + 1;
-                    cr = rr > cr ? rr : cr;
-                    cw = rc > cw ? rc : cw;
+                    const int iA = R.x & 0xffff, iB = R.x >> 16, jA = R.y & 0xffff, jB = R.y >> 16;
+                    if (iA <= iB) need += size_t(iB - iA + 1) * (((jB - (jA & ~(ch - 1))) / ch + 1) * ch);
                     if (R.z > kRtabWidth || R.w > kRtabWidth) P.rtab_ok = false;
                 }
-            P.seg_pt.capr[l] = cr;
-            P.seg_pt.capw[l] = cw;
-            const size_t need = size_t(P.nw) * cr * cw;
-            stage = need > stage ? need : stage;
+                stage = need > stage ? need : stage;
+            }
         }
         if (stage > size_t(kPtStage)) P.rtab_ok = false;
-        P.pt_lds = stage * P.elem;
+        // the tile's transpose pairs (index, weight) of every guide star, then the stage
+        P.pt_lds = size_t(P.nw) * 2 * kRtabWidth * kPtTile * (P.prec == FEWHA_FP64 ? 16 : 8) + stage * P.elem;
     }
 
     // Preconditioner of Sec. 3.4: J = alpha D + tau per (layer, level, orientation), with tau the

@@ -48,6 +48,7 @@ struct SegTab {
     int lt[kMaxSeg];      // layers: log2 of tiles per row; sensors: tiles per row
     int capr[kMaxSeg];    // P^T (layer segments): staged node rows / columns per guide star
     int capw[kMaxSeg];
+    int pitch[kMaxSeg];   // sensors: row pitch of the node grid (n_sub + 1 rounded up to 4)
 };
 
 // Per-layer offsets and sizes, as a kernel argument (the projection reads every layer).
@@ -64,9 +65,10 @@ struct DevWfs {
     double r_out2;   // (D/2)^2: active iff r^2 <= r_out2 and r^2 >= r_in2
     double r_in2;    // (obstruction D/2)^2
     long s_off;      // offset of the s^x plane in the slope vector
-    long v_off;      // offset of the (n_sub+1)^2 node grid in the node vector
+    long v_off;      // offset of the (n_sub+1) x vp node grid in the node vector
     int n_sub;
     int nv;          // n_sub + 1
+    int vp;          // node grid row pitch: nv rounded up to a multiple of 4 (16-byte rows)
 };
 
 // Per layer.

@@ -42,9 +42,9 @@ struct InvVar {               // sigma^-2 per guide star
     double v[kMaxWfs];
 };
 
-struct WfsOff {               // node grid offset and n_sub per guide star
+struct WfsOff {               // node grid offset and row pitch per guide star
     int v_off[kMaxWfs];
-    int n_sub[kMaxWfs];
+    int vp[kMaxWfs];
 };
 
 struct PupilArgs {            // subaperture (i, j) of guide star g is active iff its centre is in
@@ -52,15 +52,32 @@ struct PupilArgs {            // subaperture (i, j) of guide star g is active if
     double r_out2, r_in2;
 };
 
+// The tile of this workgroup and its segment's entries.  Every lane of the wave reads one
+// segment's entries in a single round of loads (entries past the last segment start at INT_MAX);
+// a ballot then picks the last segment starting at or before this workgroup and its entries are
+// broadcast from that lane.
 struct TileId {
     int seg, loc;
+    int off, n, lt, aux, capr, capw, pitch;
 };
 
 __device__ __forceinline__ TileId find_tile(const SegTab &S) {
-    const int b = blockIdx.x;
-    int s = 0;
-    for (int i = 1; i < S.nseg; ++i) s = (b >= S.start[i]) ? i : s;
-    return {s, b - S.start[s]};
+    const int lane = threadIdx.x & 63;
+    const int st = S.start[lane], of = S.off[lane], nn = S.n[lane], l2 = S.lt[lane], ax = S.aux[lane];
+    const int cr = S.capr[lane], cw = S.capw[lane], pi = S.pitch[lane];
+    const unsigned long long m = __ballot((int)blockIdx.x >= st);
+    const int s = 63 - __clzll(m);
+    TileId t;
+    t.seg = s;
+    t.loc = (int)blockIdx.x - __builtin_amdgcn_readlane(st, s);
+    t.off = __builtin_amdgcn_readlane(of, s);
+    t.n = __builtin_amdgcn_readlane(nn, s);
+    t.lt = __builtin_amdgcn_readlane(l2, s);
+    t.aux = __builtin_amdgcn_readlane(ax, s);
+    t.capr = __builtin_amdgcn_readlane(cr, s);
+    t.capw = __builtin_amdgcn_readlane(cw, s);
+    t.pitch = __builtin_amdgcn_readlane(pi, s);
+    return t;
 }
 
 __device__ __forceinline__ bool subap_active(const PupilArgs &pa, int ns, int i, int j) {
@@ -202,8 +219,8 @@ __device__ __forceinline__ int small_div(int a, float rb) { return (int)(((float
 // the coefficients it owns (at level s: indices [y0 >> s, (y0 + T0) >> s), or y0 >> s alone when
 // T0 < 2^s and y0 is a multiple of 2^s), which partition every band.
 // ---------------------------------------------------------------------------------------------
-constexpr int kWtLL = 18 * 18;   // LL_{s-1} region of a level s >= 2
-constexpr int kWtX = 32 * 18;    // y-synthesis output: (rows of level s-1) x (columns of level s)
+constexpr int kWtLL = 18 * 32;   // LL_{s-1} region of a level s >= 2 (rows x the level's pitch)
+constexpr int kWtX = 32 * 32;    // y-synthesis output: (rows of level s-1) x (pitch of level s)
 constexpr int kWB = 256;         // workgroup of one inverse-DWT tile
 constexpr int kWtSlots = 9 + 3 + (kMaxJ - 2);
 
@@ -235,16 +252,14 @@ __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src,
     __shared__ T sCone[kWtSlots * kWB];
     __shared__ T sLL[2][kWtLL];
     __shared__ T sXl[kWtX], sXh[kWtX];
-    __shared__ int sLoY[kMaxJ + 1], sLoX[kMaxJ + 1], sLY[kMaxJ + 1], sLX[kMaxJ + 1];
-    __shared__ T sJi[(kMaxJ + 1) * 4], sAd[kMaxJ + 1];
-    __shared__ double sRed[kWB / 64];
+    __shared__ T sJi[(kMaxJ + 1) * 4];
 
     const int tid = threadIdx.x;
     const TileId id = find_tile(S);
-    const int l = id.seg, n = S.n[l], lt = S.lt[l];
+    const int l = id.seg, n = id.n, lt = id.lt;
     const int T0 = n < kWtTile ? n : kWtTile;
     const int y0 = (id.loc >> lt) * T0, x0 = (id.loc & ((1 << lt) - 1)) * T0;
-    const long coff = S.off[l];
+    const long coff = id.off;
 
     // cone bounds (uniform; compile-time indexed, so they stay in scalar registers)
     int loY[kMaxJ + 1], loX[kMaxJ + 1], LY[kMaxJ + 1], LX[kMaxJ + 1];
@@ -266,21 +281,9 @@ __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src,
             LX[s] = hx - lx + 1;
         }
     }
-    if (tid == 0) {
-#pragma unroll
-        for (int s = 0; s <= kMaxJ; ++s) {
-            sLoY[s] = loY[s];
-            sLoX[s] = loX[s];
-            sLY[s] = LY[s];
-            sLX[s] = LX[s];
-        }
-    }
-    // preconditioner and prior of the layer's bands (PCG), loaded with the cone
+    // preconditioner of the layer's bands (PCG), loaded with the cone
     T jl = 1;
-    if (MODE == kWtPcg) {
-        const int tj = min(tid, (J + 1) * 5 - 1);
-        jl = tj < (J + 1) * 4 ? B.jinv[l * (J + 1) * 4 + tj] : B.ad[l * (J + 1) + tj - (J + 1) * 4];
-    }
+    if (MODE == kWtPcg) jl = B.jinv[l * (J + 1) * 4 + min(tid, (J + 1) * 4 - 1)];
 
     // ---- one batch of independent loads: the whole cone, straight into LDS ----
 #pragma unroll
@@ -303,104 +306,106 @@ __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src,
             }
         }
     }
-    if (MODE == kWtPcg && tid < (J + 1) * 5) {
-        if (tid < (J + 1) * 4) sJi[tid] = jl;
-        else sAd[tid - (J + 1) * 4] = jl;
-    }
+    if (MODE == kWtPcg && tid < (J + 1) * 4) sJi[tid] = jl;
     lds_fence();
 
     // PCG: (r, z) and (z, alpha D z) over the coefficients this tile owns.  At level s the owned
     // indices form a contiguous run inside the staged region of every band (rows oy0 - loY_s ..,
     // columns ox0 - loX_s ..), so the lanes sweep (band, row, column) of the owned blocks.
-    double rho = 0.0, dz = 0.0;
-    if (MODE == kWtPcg) {
-        for (int s = 1; s <= J; ++s) {
-            const int ts = T0 >> s, sh = (1 << s) - 1;
-            const int ny = ts >= 1 ? ts : ((y0 & sh) == 0 ? 1 : 0), nx = ts >= 1 ? ts : ((x0 & sh) == 0 ? 1 : 0);
-            const int nb = s == J ? 4 : 3, tot = nb * ny * nx;
-            if (tot == 0) continue;
-            const int ry = (y0 >> s) - sLoY[s], rx = (x0 >> s) - sLoX[s], lys = sLY[s];
-            const int pb = 1 << wt_lanes_log2(s), base = wt_slot0(s) * kWB;
-            const int nyx = ny * nx;
-            for (int it = tid; it < tot; it += kWB) {
-                const int bi = it / nyx, rem = it - bi * nyx, r = rem / nx, c = rem - r * nx;
-                const T rv = sCone[base + (bi * lys + ry + r) * pb + rx + c];
-                const T z = rv * sJi[s * 4 + (bi == 3 ? 0 : bi + 1)];
-                rho += (double)rv * (double)z;
-                dz += (double)sAd[s] * (double)z * (double)z;
-            }
-        }
-    }
-
-    // ---- synthesis, coarsest level first, all in LDS.  In PCG mode the cone holds r: the
-    // band scales J^-1 are folded into the taps (the synthesized LL of levels below J is z-space
-    // already). ----
-    const T *LLs = sCone + wt_slot0(J) * kWB + 3 * sLY[J] * (1 << wt_lanes_log2(J));
-    int pLL = 1 << wt_lanes_log2(J);
+    // ---- synthesis, coarsest level first, all in LDS.  Levels are unrolled so that every
+    // region pitch is the compile-time power of two of its level (LL_s below J and the y-pass
+    // outputs use the level's pitch too).  In PCG mode the cone holds r: the band scales J^-1
+    // are applied as the values are read (the synthesized LL below J is z-space already). ----
     int cur = 0;
-    for (int s = J; s >= 1; --s) {
-        const int LYs = sLY[s], LXs = sLX[s], LYo = sLY[s - 1], LXo = sLX[s - 1];
-        const int pB = 1 << wt_lanes_log2(s);
-        const int dY = (sLoY[s - 1] >> 1) - sLoY[s], dX = (sLoX[s - 1] >> 1) - sLoX[s];
-        const T *B1 = sCone + wt_slot0(s) * kWB, *B2 = B1 + LYs * pB, *B3 = B2 + LYs * pB;
-        const T jL = (MODE == kWtPcg && s == J) ? sJi[s * 4] : (T)1;
-        const T j1 = MODE == kWtPcg ? sJi[s * 4 + 1] : (T)1, j2 = MODE == kWtPcg ? sJi[s * 4 + 2] : (T)1,
-                j3 = MODE == kWtPcg ? sJi[s * 4 + 3] : (T)1;
-        const int npair = (LYo + 1) >> 1;
-        const float rLXs = 1.0f / (float)LXs;
-        // y: (LL, x-low/y-high) -> x-low rows; (x-high/y-low, HH) -> x-high rows; two rows per item
-        for (int it = tid; it < npair * LXs; it += kWB) {
-            const int a = small_div(it, rLXs), c = it - a * LXs;
-            T xl0 = 0, xl1 = 0, xh0 = 0, xh1 = 0;
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const int row = a + dY - j;
-                const T ll = jL * LLs[row * pLL + c], b1 = j1 * B1[row * pB + c], b2 = j2 * B2[row * pB + c],
-                        b3 = j3 * B3[row * pB + c];
-                xl0 += tp.h[2 * j] * ll + tp.g[2 * j] * b2;
-                xl1 += tp.h[2 * j + 1] * ll + tp.g[2 * j + 1] * b2;
-                xh0 += tp.h[2 * j] * b1 + tp.g[2 * j] * b3;
-                xh1 += tp.h[2 * j + 1] * b1 + tp.g[2 * j + 1] * b3;
-            }
-            sXl[(2 * a) * LXs + c] = xl0;
-            sXl[(2 * a + 1) * LXs + c] = xl1;
-            sXh[(2 * a) * LXs + c] = xh0;
-            sXh[(2 * a + 1) * LXs + c] = xh1;
-        }
-        __syncthreads();
-        // x: two output columns per item
-        const int nq = (LXo + 1) >> 1;
-        const float rnq = 1.0f / (float)nq;
-        T *dst = sLL[cur ^ 1];
-        for (int it = tid; it < LYo * nq; it += kWB) {
-            const int y = small_div(it, rnq), b = it - y * nq;
-            T o0 = 0, o1 = 0;
+    for (int s = kMaxJ; s >= 1; --s) {
+        if (s <= J) {
+            const int lp = wt_lanes_log2(s), PB = 1 << lp;
+            const int lpo = s > 1 ? wt_lanes_log2(s - 1) : 5, PO = 1 << lpo;  // level 0: tiles <= 32 wide
+            const int LYs = LY[s], LXs = LX[s], LYo = LY[s - 1], LXo = LX[s - 1];
+            const int dY = (loY[s - 1] >> 1) - loY[s], dX = (loX[s - 1] >> 1) - loX[s];
+            const T *B1 = sCone + wt_slot0(s) * kWB, *B2 = B1 + LYs * PB, *B3 = B2 + LYs * PB;
+            const T *LLs = s == J ? B3 + LYs * PB : sLL[cur];
+            const T jL = (MODE == kWtPcg && s == J) ? sJi[s * 4] : (T)1;
+            const T j1 = MODE == kWtPcg ? sJi[s * 4 + 1] : (T)1, j2 = MODE == kWtPcg ? sJi[s * 4 + 2] : (T)1,
+                    j3 = MODE == kWtPcg ? sJi[s * 4 + 3] : (T)1;
+            if (s >= 3) {
+                // small coarse regions: both directions at once, one output per item (no barrier
+                // between the y and x passes)
+                T *dst = sLL[cur ^ 1];
+                for (int it = tid; it < (LYo << lpo); it += kWB) {
+                    const int y = it >> lpo, xq = it & (PO - 1);
+                    if (xq < LXo) {
+                        const int py = y & 1, px = xq & 1, ky = (y >> 1) + dY, kx = (xq >> 1) + dX;
+                        T acc = 0;
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const int at = y * LXs + b + dX - j;
-                const T xl = sXl[at], xh = sXh[at];
-                o0 += tp.h[2 * j] * xl + tp.g[2 * j] * xh;
-                o1 += tp.h[2 * j + 1] * xl + tp.g[2 * j + 1] * xh;
+                        for (int jy = 0; jy < 3; ++jy) {
+                            const T hy = py ? tp.h[2 * jy + 1] : tp.h[2 * jy], gy = py ? tp.g[2 * jy + 1] : tp.g[2 * jy];
+                            const T cL = hy * jL, c1 = hy * j1, c2 = gy * j2, c3 = gy * j3;
+                            const int row = (ky - jy) * PB;
+#pragma unroll
+                            for (int jx = 0; jx < 3; ++jx) {
+                                const T hx = px ? tp.h[2 * jx + 1] : tp.h[2 * jx], gx = px ? tp.g[2 * jx + 1] : tp.g[2 * jx];
+                                const int o = row + kx - jx;
+                                acc += (cL * hx) * LLs[o] + (c1 * gx) * B1[o] + (c2 * hx) * B2[o] + (c3 * gx) * B3[o];
+                            }
+                        }
+                        dst[y * PO + xq] = acc;
+                    }
+                }
+                __syncthreads();
+                cur ^= 1;
+                continue;
             }
-            if (s > 1) {
-                dst[y * LXo + 2 * b] = o0;
-                if (2 * b + 1 < LXo) dst[y * LXo + 2 * b + 1] = o1;
-            } else {
-                T *orow = out + coff + (long)(y0 + y) * n + x0 + 2 * b;
-                orow[0] = o0;
-                orow[1] = o1;
+            const int npair = (LYo + 1) >> 1;
+            // y: (LL, x-low/y-high) -> x-low rows; (x-high/y-low, HH) -> x-high rows; two rows per item
+            for (int it = tid; it < (npair << lp); it += kWB) {
+                const int a = it >> lp, c = it & (PB - 1);
+                if (c < LXs) {
+                    const int at = (a + dY) * PB + c;
+                    T xl0 = 0, xl1 = 0, xh0 = 0, xh1 = 0;
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        const int o = at - j * PB;
+                        const T ll = jL * LLs[o], b1 = j1 * B1[o], b2 = j2 * B2[o], b3 = j3 * B3[o];
+                        xl0 += tp.h[2 * j] * ll + tp.g[2 * j] * b2;
+                        xl1 += tp.h[2 * j + 1] * ll + tp.g[2 * j + 1] * b2;
+                        xh0 += tp.h[2 * j] * b1 + tp.g[2 * j] * b3;
+                        xh1 += tp.h[2 * j + 1] * b1 + tp.g[2 * j + 1] * b3;
+                    }
+                    sXl[(2 * a) * PB + c] = xl0;
+                    sXl[(2 * a + 1) * PB + c] = xl1;
+                    sXh[(2 * a) * PB + c] = xh0;
+                    sXh[(2 * a + 1) * PB + c] = xh1;
+                }
             }
-        }
-        __syncthreads();
-        LLs = dst;
-        pLL = LXo;
-        cur ^= 1;
-    }
-    if (MODE == kWtPcg) {
-        const double a = block_sum(rho, sRed), b = block_sum(dz, sRed);
-        if (tid == 0) {
-            B.partials[blockIdx.x] = a;
-            B.partials[kPartialPitch + blockIdx.x] = b;
+            __syncthreads();
+            // x: two output columns per item
+            T *dst = sLL[cur ^ 1];
+            const int lq = lpo - 1, PQ = 1 << lq;  // output pairs per row, padded
+            for (int it = tid; it < (LYo << lq); it += kWB) {
+                const int y = it >> lq, bq = it & (PQ - 1);
+                if (2 * bq < LXo) {
+                    const int at = y * PB + bq + dX;
+                    T o0 = 0, o1 = 0;
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        const T xl = sXl[at - j], xh = sXh[at - j];
+                        o0 += tp.h[2 * j] * xl + tp.g[2 * j] * xh;
+                        o1 += tp.h[2 * j + 1] * xl + tp.g[2 * j + 1] * xh;
+                    }
+                    if (s > 1) {
+                        dst[y * PO + 2 * bq] = o0;
+                        if (2 * bq + 1 < LXo) dst[y * PO + 2 * bq + 1] = o1;
+                    } else {
+                        T *orow = out + coff + (long)(y0 + y) * n + x0 + 2 * bq;
+                        orow[0] = o0;
+                        orow[1] = o1;
+                    }
+                }
+            }
+            __syncthreads();
+            cur ^= 1;
         }
     }
 }
@@ -429,7 +434,7 @@ __global__ __launch_bounds__(kB) void k_proj(SegTab S, LayTab LT, InvVar IV, Pup
 
     const int tid = threadIdx.x;
     const TileId id = find_tile(S);
-    const int g = id.seg, ns = S.n[g], tpr = S.lt[g];
+    const int g = id.seg, ns = id.n, tpr = id.lt;
     const int ti = id.loc / tpr, tj = id.loc - ti * tpr;
     const int i0 = ti * kProjTile, j0 = tj * kProjTile;
     const Ent<T> *__restrict__ xt = B.xtab + (long)g * nl * B.maxnv;
@@ -462,14 +467,15 @@ __global__ __launch_bounds__(kB) void k_proj(SegTab S, LayTab LT, InvVar IV, Pup
 
     const int a = tid >> 4, b = tid & 15, i = i0 - 1 + a, j = j0 - 1 + b;
     const bool node = i >= 0 && i <= ns && j >= 0 && j <= ns;
+    const int lay_off = LT.off[tid & 63], lay_n = LT.n[tid & 63];  // lane l holds layer l
     T phi = 0;
     for (int l0 = 0; l0 < nl; l0 += kProjLch) {
         T uv[kProjLch][4];
 #pragma unroll
         for (int c = 0; c < kProjLch; ++c) {
             const int l = min(l0 + c, nl - 1);  // layers past the last reload it (dropped below)
-            const int n = LT.n[l];
-            const T *U = u + LT.off[l] + (long)sK[1][l][a] * n + sK[0][l][b];
+            const int n = __builtin_amdgcn_readlane(lay_n, l);
+            const T *U = u + __builtin_amdgcn_readlane(lay_off, l) + (long)sK[1][l][a] * n + sK[0][l][b];
             uv[c][0] = U[0];
             uv[c][1] = U[1];
             uv[c][2] = U[n];
@@ -502,8 +508,8 @@ __global__ __launch_bounds__(kB) void k_proj(SegTab S, LayTab LT, InvVar IV, Pup
         const bool own = aa >= 1 && bb >= 1 && ii < ns && jj < ns;
         if (MODE == kProjA) {
             if (own) {
-                out[S.aux[g] + (long)ii * ns + jj] = sx;
-                out[S.aux[g] + (long)ns * ns + (long)ii * ns + jj] = sy;
+                out[id.aux + (long)ii * ns + jj] = sx;
+                out[id.aux + (long)ns * ns + (long)ii * ns + jj] = sy;
             }
         } else {
             const double iv = IV.v[g];
@@ -520,7 +526,7 @@ __global__ __launch_bounds__(kB) void k_proj(SegTab S, LayTab LT, InvVar IV, Pup
             // node (i, j) is a corner of subapertures (i, j), (i, j-1), (i-1, j), (i-1, j-1)
             const int s11 = (aa + 1) * kPS + (bb + 1), s10 = (aa + 1) * kPS + bb, s01 = aa * kPS + (bb + 1),
                       s00 = aa * kPS + bb;
-            out[S.off[g] + (long)ii * (ns + 1) + jj] =
+            out[id.off + (long)ii * id.pitch + jj] =
                 (T)0.5 * ((-sSx[s11] - sSy[s11]) + (sSx[s10] - sSy[s10]) + (-sSx[s01] + sSy[s01]) + (sSx[s00] + sSy[s00]));
         }
     }
@@ -535,14 +541,14 @@ __global__ __launch_bounds__(kB) void k_gt(SegTab S, InvVar IV, PupilArgs pa, co
     __shared__ T sSx[kPS * kPS], sSy[kPS * kPS];
     const int tid = threadIdx.x;
     const TileId id = find_tile(S);
-    const int g = id.seg, ns = S.n[g], tpr = S.lt[g];
+    const int g = id.seg, ns = id.n, tpr = id.lt;
     const int ti = id.loc / tpr, tj = id.loc - ti * tpr;
     const int i0 = ti * kProjTile, j0 = tj * kProjTile;
     {
         const int t = tid < kPS * kPS ? tid : 0;
         const int aa = t / kPS, bb = t - aa * kPS, ii = i0 - 1 + aa, jj = j0 - 1 + bb;
         const bool in_grid = ii >= 0 && ii < ns && jj >= 0 && jj < ns;
-        const long at = S.aux[g] + (in_grid ? (long)ii * ns + jj : 0L);  // every lane loads
+        const long at = id.aux + (in_grid ? (long)ii * ns + jj : 0L);  // every lane loads
         const T vx = in[at], vy = in[at + (long)ns * ns];
         if (tid < kPS * kPS) {
             const bool act = in_grid && subap_active(pa, ns, ii, jj);
@@ -557,7 +563,7 @@ __global__ __launch_bounds__(kB) void k_gt(SegTab S, InvVar IV, PupilArgs pa, co
         if (ii <= ns && jj <= ns) {
             const int s11 = (aa + 1) * kPS + (bb + 1), s10 = (aa + 1) * kPS + bb, s01 = aa * kPS + (bb + 1),
                       s00 = aa * kPS + bb;
-            v[S.off[g] + (long)ii * (ns + 1) + jj] =
+            v[id.off + (long)ii * id.pitch + jj] =
                 (T)0.5 * ((-sSx[s11] - sSy[s11]) + (sSx[s10] - sSy[s10]) + (-sSx[s01] + sSy[s01]) + (sSx[s00] + sSy[s00]));
         }
     }
@@ -569,36 +575,37 @@ __global__ __launch_bounds__(kB) void k_gt(SegTab S, InvVar IV, PupilArgs pa, co
 // Staged gather on a 16 x 16 layer tile.  The transpose-table lines of the tile's rows and
 // columns (up to kRtabWidth (node, weight) pairs each, per guide star) and each guide star's
 // record (the node rows / columns those pairs name and the largest pair count over the tile's
-// rows / columns, precomputed at bind time) come first; the node rectangles are then staged in
-// LDS (dynamic, nw * capr * capw values) with one round of loads, and each lane sums
+// rows / columns, precomputed at bind time) come first.  Each guide star's node rectangle is then
+// staged in LDS, widened to 16-byte column chunks (node grid rows are 16-byte aligned), one
+// guide star after the other with one 16-byte copy per lane and chunk, and each lane sums
 //   x(k, q) = sum_g sum_{(i, wy) in row k} wy sum_{(j, wx) in column q} wx v_g(i, j)
 // from LDS, with loop bounds uniform over the tile (missing pairs carry weight 0).  The pairs are
 // the very matrix entries P uses, so P^T is P's exact transpose.
-constexpr int kPtSlots = kPtStage / kB;
+__device__ __forceinline__ void g2lds16(const float *gp, float *wave_base) {
+    __builtin_amdgcn_global_load_lds(gp, (__attribute__((address_space(3))) void *)wave_base, 16, 0, 0);
+}
 
 template <typename T>
 __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restrict__ v, T *__restrict__ x, Bufs<T> B,
                                            int nw, PassArgs PA) {
-    constexpr int NT = kPtTile, RW = kRtabWidth;
+    constexpr int NT = kPtTile, RW = kRtabWidth, CH = 16 / sizeof(T);  // values per 16-byte chunk
     static_assert(NT == 16 && 2 * kPtMaxWfs * NT == 2 * kB, "line decode below assumes these sizes");
+    // dynamic LDS: the tile's (node, weight) pairs [g][axis][entry][line], then the staged node
+    // rectangles
     extern __shared__ char smem_raw[];
-    T *sV = reinterpret_cast<T *>(smem_raw);
-    __shared__ RtabEnt<T> sP[kPtMaxWfs][2][RW][NT];
-    __shared__ int4 sRect[kPtMaxWfs];  // iA, iB, jA, jB
-    __shared__ int2 sCnt[kPtMaxWfs];   // largest pair count over the tile's rows, columns
-    __shared__ int2 sVb[kPtMaxWfs];
+    RtabEnt<T>(*sP)[2][RW][NT] = reinterpret_cast<RtabEnt<T>(*)[2][RW][NT]>(smem_raw);
+    T *sV = reinterpret_cast<T *>(smem_raw + sizeof(RtabEnt<T>) * 2 * RW * NT * nw);
 
     if (PA.k >= 0 && blockIdx.x == gridDim.x - 1) {  // the pass's scalar step (extra workgroup)
         scalar_step(B.partials, PA.nwt, PA.nproj, B.sc, PA.k, PA.resnorm, PA.publish);
         return;
     }
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
     const TileId id = find_tile(S);
-    const int l = id.seg, n = S.n[l], lt = S.lt[l];
+    const int n = id.n, lt = id.lt;
     const int T0 = n < NT ? n : NT;
     const int k0 = (id.loc >> lt) * T0, q0 = (id.loc & ((1 << lt) - 1)) * T0;
-    const int roff = S.aux[l];
-    const int capw = S.capw[l], cell = S.capr[l] * capw;
+    const int roff = id.aux;
 
     // transpose-table lines e = (g * 2 + axis) * 16 + idx, and the records (every lane loads;
     // clamped indices stand in for lines the tile does not have)
@@ -610,9 +617,21 @@ __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restr
 #pragma unroll
         for (int a = 0; a < RW; ++a) pe[c][a] = rt[a];
     }
-    const int tg = min(tid, nw - 1);
+    // lane g of every wave holds guide star g's record: node rows iA..iB, first staged column c0
+    // (16-byte aligned), last column jB, pair counts, node grid offset / pitch, and the LDS
+    // offset / pitch of its staged rectangle
+    const int tg = min(lane, nw - 1);
     const int4 rec = B.rects[(long)blockIdx.x * nw + tg];
-    const int2 vb = make_int2(WO.v_off[tg], WO.n_sub[tg] + 1);
+    const int gv = WO.v_off[tg], gp = WO.vp[tg];
+    const int iA = rec.x & 0xffff, iB = rec.x >> 16, c0 = (rec.y & 0xffff) & ~(CH - 1), jB = rec.y >> 16;
+    const int pitch = lane < nw && iA <= iB ? ((jB - c0) / CH + 1) * CH : 0;
+    const int sz = pitch ? (iB - iA + 1) * pitch : 0;
+    int incl = sz;  // inclusive prefix sum over the lanes
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    const int sbase = incl - sz;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const int e = tid + c * kB, g = e >> 5, axis = (e >> 4) & 1, idx = e & 15;
@@ -621,30 +640,26 @@ __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restr
             for (int a = 0; a < RW; ++a) sP[g][axis][a][idx] = pe[c][a];
         }
     }
-    if (tid < nw) {
-        sRect[tid] = make_int4(rec.x & 0xffff, rec.x >> 16, rec.y & 0xffff, rec.y >> 16);
-        sCnt[tid] = make_int2(rec.z, rec.w);
-        sVb[tid] = vb;
-    }
-    __syncthreads();
 
-    // node rectangles of every guide star, one round of loads straight into LDS: staged value
-    // k = g cell + r capw + q
-    {
-        const float rcell = 1.0f / (float)cell, rw = 1.0f / (float)capw;
-        const int total = nw * cell;
+    // node rectangles, one guide star after the other (the copies of all of them in flight)
+    for (int g = 0; g < nw; ++g) {
+        const int pg = __builtin_amdgcn_readlane(pitch, g);
+        if (pg == 0) continue;
+        const int ra = __builtin_amdgcn_readlane(iA, g), rb = __builtin_amdgcn_readlane(iB, g);
+        const int cg = __builtin_amdgcn_readlane(c0, g), bg = __builtin_amdgcn_readlane(sbase, g);
+        const int vg = __builtin_amdgcn_readlane(gv, g), vpg = __builtin_amdgcn_readlane(gp, g);
+        const int chunks = pg / CH, items = (rb - ra + 1) * chunks;
+        const float rch = 1.0f / (float)chunks;
+        for (int i0 = 0; i0 < items; i0 += kB) {
+            const int it = i0 + tid;
+            if (it < items) {
+                const int r = small_div(it, rch), c4 = it - r * chunks;
+                const T *src = v + vg + (long)(ra + r) * vpg + cg + c4 * CH;
+                if constexpr (sizeof(T) == 4) {
+                    g2lds16(src, sV + bg + (i0 + (tid & ~63)) * CH);
+                } else {
 #pragma unroll
-        for (int c = 0; c < kPtSlots; ++c) {
-            if (c * kB < total) {
-                const int k = tid + c * kB, kc = min(k, total - 1);
-                const int g = small_div(kc, rcell), rem = kc - g * cell;
-                const int r = small_div(rem, rw), q = rem - r * capw;
-                const int4 R = sRect[g];
-                const int2 V = sVb[g];
-                if (k < total && R.x + r <= R.y && R.z + q <= R.w) {
-                    const T *gp = v + V.x + (long)(R.x + r) * V.y + R.z + q;
-                    if constexpr (sizeof(T) == 4) g2lds(gp, sV + c * kB + (tid & ~63));
-                    else sV[k] = *gp;
+                    for (int e = 0; e < CH; ++e) sV[bg + it * CH + e] = src[e];
                 }
             }
         }
@@ -655,31 +670,34 @@ __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restr
     if (a < T0 && b < T0) {
         T acc = 0;
         for (int g = 0; g < nw; ++g) {
-            const int4 R = sRect[g];
-            const int2 C = sCnt[g];
-            const T *Vg = sV + g * cell - R.x * capw - R.z;
+            const int pg = __builtin_amdgcn_readlane(pitch, g);
+            const int cy = __builtin_amdgcn_readlane(rec.z, g), cx = __builtin_amdgcn_readlane(rec.w, g);
+            const int ra = __builtin_amdgcn_readlane(iA, g), cg = __builtin_amdgcn_readlane(c0, g);
+            const T *Vg = sV + __builtin_amdgcn_readlane(sbase, g) - ra * pg - cg;
             int jx[RW];
             T wx[RW];
 #pragma unroll
             for (int e = 0; e < RW; ++e) {
-                const RtabEnt<T> p = sP[g][0][e][b];
-                jx[e] = max(p.idx, R.z);  // padding (index -1) has weight 0
-                wx[e] = p.w;
+                if (e < cx) {
+                    const RtabEnt<T> p = sP[g][0][e][b];
+                    jx[e] = max(p.idx, cg);  // padding (index -1) has weight 0
+                    wx[e] = p.w;
+                }
             }
 #pragma unroll
             for (int ea = 0; ea < RW; ++ea) {
-                if (ea < C.x) {
+                if (ea < cy) {
                     const RtabEnt<T> p = sP[g][1][ea][a];
-                    const T *Vr = Vg + max(p.idx, R.x) * capw;
+                    const T *Vr = Vg + max(p.idx, ra) * pg;
                     T t = 0;
 #pragma unroll
                     for (int eb = 0; eb < RW; ++eb)
-                        if (eb < C.y) t += wx[eb] * Vr[jx[eb]];
+                        if (eb < cx) t += wx[eb] * Vr[jx[eb]];
                     acc += p.w * t;
                 }
             }
         }
-        x[S.off[l] + (long)(k0 + a) * n + q0 + b] = acc;
+        x[id.off + (long)(k0 + a) * n + q0 + b] = acc;
     }
 }
 
@@ -693,15 +711,15 @@ __global__ __launch_bounds__(kB) void k_pt_scan(SegTab S, const T *__restrict__ 
         return;
     }
     const TileId id = find_tile(S);
-    const int l = id.seg, n = S.n[l], lt = S.lt[l];
+    const int l = id.seg, n = id.n, lt = id.lt;
     const int T0 = n < NT ? n : NT;
     const int a = threadIdx.x >> 4, b = threadIdx.x & 15;
     if (a >= T0 || b >= T0) return;
     const int k = (id.loc >> lt) * T0 + a, q = (id.loc & ((1 << lt) - 1)) * T0 + b;
     T acc = 0;
     for (int g = 0; g < nw; ++g) {
-        const Range rx = B.xrng[(long)g * B.sum_n + S.aux[l] + q];
-        const Range ry = B.yrng[(long)g * B.sum_n + S.aux[l] + k];
+        const Range rx = B.xrng[(long)g * B.sum_n + id.aux + q];
+        const Range ry = B.yrng[(long)g * B.sum_n + id.aux + k];
         if (rx.lo > rx.hi || ry.lo > ry.hi) continue;
         const Ent<T> *xt = B.xtab + ((long)g * nl + l) * B.maxnv;
         const Ent<T> *yt = B.ytab + ((long)g * nl + l) * B.maxnv;
@@ -710,7 +728,7 @@ __global__ __launch_bounds__(kB) void k_pt_scan(SegTab S, const T *__restrict__ 
         for (int i = ry.lo; i <= ry.hi; ++i) {
             const Ent<T> ey = yt[i];
             const T wy = (ey.k0 == k) ? ey.w0 : ey.w1;
-            const T *row = vg + (long)i * W.nv;
+            const T *row = vg + (long)i * W.vp;
             for (int j = rx.lo; j <= rx.hi; ++j) {
                 const Ent<T> ex = xt[j];
                 const T wx = (ex.k0 == q) ? ex.w0 : ex.w1;
@@ -718,7 +736,7 @@ __global__ __launch_bounds__(kB) void k_pt_scan(SegTab S, const T *__restrict__ 
             }
         }
     }
-    x[S.off[l] + (long)k * n + q] = acc;
+    x[id.off + (long)k * n + q] = acc;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -773,32 +791,44 @@ __device__ __forceinline__ void epi_load(const Bufs<T> &B, const FwdArgs &E, lon
     }
 }
 
-// Deliver coefficient i of W x (value w) through the epilogue.
+// Deliver coefficient i of W x (value w) through the epilogue.  pcg and rhs also accumulate the
+// next pass's (r, z) and (z, alpha D z) over the residual they write (z = J^-1 r).
 template <typename T, int EPI>
 __device__ __forceinline__ void epi_store(const Bufs<T> &B, const FwdArgs &E, long i, T w, const T *op, T ji, T ad,
-                                          const StepOut &so) {
+                                          const StepOut &so, double &rho, double &dz) {
     if constexpr (EPI == kEpiPlain) {
         static_cast<T *>(E.out)[i] = w;
     } else if constexpr (EPI == kEpiPrior) {
         static_cast<T *>(E.out)[i] = w + ad * op[0];
     } else if constexpr (EPI == kEpiPcg) {
-        if (so.stopped) return;
-        const T r = op[0], z = r * ji, y = w + ad * z;
-        const T al = (T)so.alpha, be = (T)so.beta;
-        const T p = E.k > 0 ? z + be * op[2] : z;
-        const T q = E.k > 0 ? y + be * op[3] : y;
-        B.p[i] = p;
-        B.q[i] = q;
-        static_cast<T *>(E.c)[i] = op[1] + al * p;
-        B.r[i] = r - al * q;
+        T rn = op[0];
+        if (!so.stopped) {
+            const T r = op[0], z = r * ji, y = w + ad * z;
+            const T al = (T)so.alpha, be = (T)so.beta;
+            const T p = E.k > 0 ? z + be * op[2] : z;
+            const T q = E.k > 0 ? y + be * op[3] : y;
+            B.p[i] = p;
+            B.q[i] = q;
+            static_cast<T *>(E.c)[i] = op[1] + al * p;
+            rn = r - al * q;
+            B.r[i] = rn;
+        }
+        const T zn = rn * ji;
+        rho += (double)rn * (double)zn;
+        dz += (double)ad * (double)zn * (double)zn;
     } else {  // b = W x:  r = (b - b_prev) + r  (cold: r = b, c = 0);  b_prev = b
+        T rn;
         if (E.cold) {
-            B.r[i] = w;
+            rn = w;
             static_cast<T *>(E.c)[i] = 0;
         } else {
-            B.r[i] = (w - op[0]) + op[1];
+            rn = (w - op[0]) + op[1];
         }
+        B.r[i] = rn;
         B.b_prev[i] = w;
+        const T zn = rn * ji;
+        rho += (double)rn * (double)zn;
+        dz += (double)ad * (double)zn * (double)zn;
     }
 }
 
@@ -812,19 +842,26 @@ struct FineGeom {
 
 // Levels 1..KF on a tile of TQ x TQ level-KF quads.  The input region with its periodic halo
 // (straight into LDS), the epilogue operands of the coefficients each lane will deliver, and
-// (pcg) the pass's partial sums arrive in one batch of loads; the levels then run from LDS.  Lane
-// roles: lanes [0, O1^2) own the level-1 quads, lanes [256, 256 + H1) compute the level-1 halo
-// quads (LL only, for level 2), lanes [512, 512 + O2^2) own the level-2 quads.
-constexpr int kFB = 1024;
+// (pcg) the pass's scalar step arrive in one round of loads; the levels then run from LDS.  Lane
+// roles: lanes [0, O1^2) own the level-1 quads, the next H1 lanes compute the level-1 halo quads
+// (LL only, for level 2), and the O2^2 lanes from fwd_l2<KF, TQ>() own the level-2 quads.
+template <int KF, int TQ>
+struct FwdLanes {
+    static constexpr int O1 = TQ << (KF - 1), L1 = TQ * (1 << (KF - 1)) + 4 * ((1 << (KF - 1)) - 1);
+    static constexpr int H1 = KF >= 2 ? L1 * L1 - O1 * O1 : 0;
+    static constexpr int O2 = KF >= 2 ? TQ : 1;
+    static constexpr int l2 = ((O1 * O1 + H1 + 63) / 64) * 64;  // first level-2 lane (wave aligned)
+    static constexpr int block = ((KF >= 2 ? l2 + O2 * O2 : O1 * O1) + 255) / 256 * 256;
+};
 
 template <typename T, int KF, int TQ, int EPI>
-__global__ __launch_bounds__(kFB) void k_fwd(SegTab S, const T *__restrict__ x, Bufs<T> B, FwdArgs E, Taps<T> tp,
-                                             int J, int nwt, int nproj) {
+__global__ __launch_bounds__((FwdLanes<KF, TQ>::block)) void k_fwd(SegTab S, const T *__restrict__ x, Bufs<T> B, FwdArgs E,
+                                                                    Taps<T> tp, int J) {
     using G = FineGeom<KF, TQ>;
-    constexpr int L0 = G::len(0), L1 = G::len(1), NX = (L0 * L0 + kFB - 1) / kFB;
-    constexpr int O1 = G::own(1), O2 = KF >= 2 ? G::own(2) : 1, H1 = KF >= 2 ? L1 * L1 - O1 * O1 : 0;
+    using R = FwdLanes<KF, TQ>;
+    constexpr int FB = R::block, L0 = G::len(0), L1 = G::len(1), NX = (L0 * L0 + FB - 1) / FB;
+    constexpr int O1 = R::O1, O2 = R::O2, H1 = R::H1, L2 = R::l2;
     constexpr int NOP = EpiOps<EPI>::n, HW = L1 > O1 ? L1 - O1 : 1;
-    static_assert(O1 * O1 <= 256 && H1 <= 256 && O2 * O2 <= 512, "lane roles");
     __shared__ T sA[L0 * L0];
     __shared__ T sB[KF >= 2 ? L1 * L1 : 1];
 
@@ -833,27 +870,27 @@ __global__ __launch_bounds__(kFB) void k_fwd(SegTab S, const T *__restrict__ x, 
         if (blockIdx.x == 0 && tid == 0) reset_scalars(B.sc + 1);  // the state "before pass 0"
     }
     const TileId id = find_tile(S);
-    const int l = id.seg, n = S.n[l], lt = S.lt[l], nm = n - 1;
+    const int l = id.seg, n = id.n, lt = id.lt, nm = n - 1;
     const int qy = (id.loc >> lt) * TQ, qx = (id.loc & ((1 << lt) - 1)) * TQ;
-    const long coff = S.off[l];
+    const long coff = id.off;
     const int oy = qy << KF, ox = qx << KF;
 
     // x region with its periodic halo, straight into LDS (row-major, pitch L0)
 #pragma unroll
     for (int c = 0; c < NX; ++c) {
-        const int k = tid + c * kFB;
+        const int k = tid + c * FB;
         if (k < L0 * L0) {
             const int r = k / L0, q = k - r * L0;
             const T *gp = x + coff + (long)((oy + r) & nm) * n + ((ox + q) & nm);
-            if constexpr (sizeof(T) == 4) g2lds(gp, sA + c * kFB + (tid & ~63));
+            if constexpr (sizeof(T) == 4) g2lds(gp, sA + c * FB + (tid & ~63));
             else sA[k] = *gp;
         }
     }
     // the quad this lane delivers: level 1 (owner), level 2 (owner), or none (quad 0 of level 1
     // stands in so that every lane issues the same loads)
-    const bool own1 = tid < O1 * O1, own2 = KF >= 2 && tid >= 512 && tid < 512 + O2 * O2;
+    const bool own1 = tid < O1 * O1, own2 = KF >= 2 && tid >= L2 && tid < L2 + O2 * O2;
     const int s_own = own2 ? 2 : 1;
-    const int t1 = own1 ? tid : 0, t2 = own2 ? tid - 512 : 0;
+    const int t1 = own1 ? tid : 0, t2 = own2 ? tid - L2 : 0;
     const int rq = own2 ? t2 / O2 : t1 / O1, cq = own2 ? t2 - (t2 / O2) * O2 : t1 - (t1 / O1) * O1;
     const int by = (qy << (KF - s_own)) + rq, bx = (qx << (KF - s_own)) + cq;
     T op[4][NOP > 0 ? NOP : 1];
@@ -866,6 +903,7 @@ __global__ __launch_bounds__(kFB) void k_fwd(SegTab S, const T *__restrict__ x, 
     if constexpr (EPI == kEpiPcg) so = read_step(B.sc);
     lds_fence();
 
+    double rho = 0.0, dz = 0.0;  // (r, z), (z, alpha D z) of the residual written (pcg, rhs)
 #pragma unroll
     for (int s = 1; s <= KF; ++s) {
         const T *src = s == 1 ? sA : sB;
@@ -873,25 +911,25 @@ __global__ __launch_bounds__(kFB) void k_fwd(SegTab S, const T *__restrict__ x, 
         const bool mine = s == 1 ? own1 : own2;
         if (mine) {
             T ad = 0, ji[4] = {0, 0, 0, 0};
-            if (EPI == kEpiPrior || EPI == kEpiPcg) ad = B.ad[l * (J + 1) + s];
-            if (EPI == kEpiPcg) {
+            if (EPI != kEpiPlain) ad = B.ad[l * (J + 1) + s];
+            if (EPI == kEpiPcg || EPI == kEpiRhs) {
 #pragma unroll
                 for (int o = 0; o < 4; ++o) ji[o] = B.jinv[(l * (J + 1) + s) * 4 + o];
             }
             T w[4];
             analyse(src, sp, rq, cq, tp, w[0], w[1], w[2], w[3]);
 #pragma unroll
-            for (int o = 1; o < 4; ++o) epi_store<T, EPI>(B, E, band_index(coff, n, s, o, by, bx), w[o], op[o], ji[o], ad, so);
+            for (int o = 1; o < 4; ++o) epi_store<T, EPI>(B, E, band_index(coff, n, s, o, by, bx), w[o], op[o], ji[o], ad, so, rho, dz);
             if (s < KF) {
                 sB[rq * L1 + cq] = w[0];
             } else if (KF == J) {
-                epi_store<T, EPI>(B, E, band_index(coff, n, s, 0, by, bx), w[0], op[0], ji[0], ad, so);
+                epi_store<T, EPI>(B, E, band_index(coff, n, s, 0, by, bx), w[0], op[0], ji[0], ad, so, rho, dz);
             } else {
                 B.ll[(coff >> (2 * KF)) + (long)by * (n >> KF) + bx] = w[0];
             }
         }
-        if (s < KF && tid >= 256 && tid < 256 + H1) {  // halo quads of level 1: LL only
-            const int h = tid - 256, rs = O1 * HW;
+        if (s < KF && tid >= O1 * O1 && tid < O1 * O1 + H1) {  // halo quads of level 1: LL only
+            const int h = tid - O1 * O1, rs = O1 * HW;
             int hr, hc;
             if (h < rs) {
                 hr = h / HW;
@@ -906,6 +944,14 @@ __global__ __launch_bounds__(kFB) void k_fwd(SegTab S, const T *__restrict__ x, 
         }
         if (s < KF) __syncthreads();
     }
+    if constexpr (EPI == kEpiPcg || EPI == kEpiRhs) {
+        __shared__ double sRed[16];
+        const double a = block_sum(rho, sRed), b = block_sum(dz, sRed);
+        if (tid == 0) {
+            B.partials[blockIdx.x] = a;
+            B.partials[kPartialPitch + blockIdx.x] = b;
+        }
+    }
 }
 
 // Levels KF+1..J of one layer per workgroup, from the level-KF approximation left by k_fwd
@@ -914,8 +960,8 @@ __global__ __launch_bounds__(kFB) void k_fwd(SegTab S, const T *__restrict__ x, 
 // LDS together with the approximation, in one round of loads; otherwise each level requests its
 // operands before its analysis.  Dynamic LDS: m0^2 + (m0/2)^2 (+ NOP m0^2 with `pre`) values.
 template <typename T, int EPI>
-__global__ __launch_bounds__(kCB) void k_coarse(LayTab LT, Bufs<T> B, FwdArgs E, Taps<T> tp, int J, int KF, int nwt,
-                                                int nproj, int pre) {
+__global__ __launch_bounds__(kCB) void k_coarse(LayTab LT, Bufs<T> B, FwdArgs E, Taps<T> tp, int J, int KF, int nfine,
+                                                int pre) {
     extern __shared__ char smem_raw[];
     constexpr int NOP = EpiOps<EPI>::n, NL = 16;
     const int tid = threadIdx.x, l = blockIdx.x, n = LT.n[l], m0 = n >> KF, mm = m0 * m0;
@@ -967,11 +1013,12 @@ __global__ __launch_bounds__(kCB) void k_coarse(LayTab LT, Bufs<T> B, FwdArgs E,
     StepOut so{0.0, 0.0, 0};
     if constexpr (EPI == kEpiPcg) so = read_step(B.sc);
     lds_fence();
+    double rho = 0.0, dz = 0.0;  // (r, z), (z, alpha D z) of the residual written (pcg, rhs)
     for (int s = KF + 1; s <= J; ++s) {
         const int mi = n >> (s - 1), h = mi >> 1, msk = mi - 1, nq = h * h;
         T ad = 0, ji[4] = {0, 0, 0, 0};
-        if (EPI == kEpiPrior || EPI == kEpiPcg) ad = B.ad[l * (J + 1) + s];
-        if (EPI == kEpiPcg) {
+        if (EPI != kEpiPlain) ad = B.ad[l * (J + 1) + s];
+        if (EPI == kEpiPcg || EPI == kEpiRhs) {
 #pragma unroll
             for (int o = 0; o < 4; ++o) ji[o] = B.jinv[(l * (J + 1) + s) * 4 + o];
         }
@@ -1014,8 +1061,8 @@ __global__ __launch_bounds__(kCB) void k_coarse(LayTab LT, Bufs<T> B, FwdArgs E,
                     w[3] += tp.g[a] * dx;
                 }
 #pragma unroll
-                for (int o = 1; o < 4; ++o) epi_store<T, EPI>(B, E, band_index(coff, n, s, o, r, q), w[o], op[o], ji[o], ad, so);
-                if (s == J) epi_store<T, EPI>(B, E, band_index(coff, n, s, 0, r, q), w[0], op[0], ji[0], ad, so);
+                for (int o = 1; o < 4; ++o) epi_store<T, EPI>(B, E, band_index(coff, n, s, o, r, q), w[o], op[o], ji[o], ad, so, rho, dz);
+                if (s == J) epi_store<T, EPI>(B, E, band_index(coff, n, s, 0, r, q), w[0], op[0], ji[0], ad, so, rho, dz);
                 else cd[r * h + q] = w[0];
             }
         }
@@ -1023,6 +1070,14 @@ __global__ __launch_bounds__(kCB) void k_coarse(LayTab LT, Bufs<T> B, FwdArgs E,
         T *t = cs;
         cs = cd;
         cd = t;
+    }
+    if constexpr (EPI == kEpiPcg || EPI == kEpiRhs) {
+        __shared__ double sRed[kCB / 64];
+        const double a = block_sum(rho, sRed), b = block_sum(dz, sRed);
+        if (tid == 0) {  // slots after the fine tiles' partials
+            B.partials[nfine + l] = a;
+            B.partials[kPartialPitch + nfine + l] = b;
+        }
     }
 }
 
@@ -1149,13 +1204,13 @@ __global__ __launch_bounds__(kMaxWfs) void k_build_rects(SegTab S, const Range *
     const int g = threadIdx.x;
     if (g >= nw) return;
     const TileId id = find_tile(S);
-    const int l = id.seg, n = S.n[l], lt = S.lt[l];
+    const int n = id.n, lt = id.lt;
     const int T0 = n < kPtTile ? n : kPtTile;
     const int k0 = (id.loc >> lt) * T0, q0 = (id.loc & ((1 << lt) - 1)) * T0;
     int iA = 1 << 30, iB = -1, jA = 1 << 30, jB = -1, cy = 0, cx = 0;
     for (int t = 0; t < T0; ++t) {
-        const Range ry = yrng[(long)g * sum_n + S.aux[l] + k0 + t];
-        const Range rx = xrng[(long)g * sum_n + S.aux[l] + q0 + t];
+        const Range ry = yrng[(long)g * sum_n + id.aux + k0 + t];
+        const Range rx = xrng[(long)g * sum_n + id.aux + q0 + t];
         if (ry.lo <= ry.hi) {
             iA = ry.lo < iA ? ry.lo : iA;
             iB = ry.hi > iB ? ry.hi : iB;
@@ -1211,7 +1266,7 @@ WfsOff wfs_off_tab(const Plan &P) {
     WfsOff t{};
     for (int g = 0; g < P.nw; ++g) {
         t.v_off[g] = (int)P.dwfs[g].v_off;
-        t.n_sub[g] = P.dwfs[g].n_sub;
+        t.vp[g] = P.dwfs[g].vp;
     }
     return t;
 }
@@ -1278,8 +1333,8 @@ int Ops<T>::pt(const T *v, T *x, const PassArgs &PA) const {
 template <typename T, int EPI>
 static int fwd_launch(const Plan &P, const Bufs<T> &B, hipStream_t st, const T *x, const FwdArgs &E) {
     const Taps<T> tp = make_taps<T>();
-    const int nf = P.n_fwd, nwt = P.n_wt, npj = P.n_proj;
-#define FEWHA_FWD(KF, TQ) k_fwd<T, KF, TQ, EPI><<<nf, kFB, 0, st>>>(P.seg_fwd, x, B, E, tp, P.J, nwt, npj)
+    const int nf = P.n_fwd;
+#define FEWHA_FWD(KF, TQ) k_fwd<T, KF, TQ, EPI><<<nf, (FwdLanes<KF, TQ>::block), 0, st>>>(P.seg_fwd, x, B, E, tp, P.J)
     if (P.kf == 1) {
         switch (P.tq) {
             case 1: FEWHA_FWD(1, 1); break;
@@ -1302,7 +1357,7 @@ static int fwd_launch(const Plan &P, const Bufs<T> &B, hipStream_t st, const T *
         for (auto &L : P.lay) m = (size_t)(L.n >> P.kf) > m ? (size_t)(L.n >> P.kf) : m;
         const size_t base = (m * m + m * m / 4) * sizeof(T), opb = (size_t)EpiOps<EPI>::n * m * m * sizeof(T);
         const int pre = EpiOps<EPI>::n > 0 && base + opb <= kCoarseLdsMax ? 1 : 0;
-        k_coarse<T, EPI><<<P.nl, kCB, base + (pre ? opb : 0), st>>>(P.laytab, B, E, tp, P.J, P.kf, nwt, npj, pre);
+        k_coarse<T, EPI><<<P.nl, kCB, base + (pre ? opb : 0), st>>>(P.laytab, B, E, tp, P.J, P.kf, nf, pre);
         if (int e = check()) return e;
     }
     return FEWHA_OK;
@@ -1326,6 +1381,10 @@ int Ops<T>::prepare() const {
     for (int i = 0; i < 4; ++i)
         if (hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCoarseLdsMax) != hipSuccess)
             return FEWHA_ERR_UNSUPPORTED;
+    // staged P^T: the tile's transpose pairs and node rectangles
+    const int pt_max = (int)(kPtMaxWfs * 2 * kRtabWidth * kPtTile * sizeof(RtabEnt<T>) + kPtStage * sizeof(T));
+    if (hipFuncSetAttribute((const void *)k_pt<T>, hipFuncAttributeMaxDynamicSharedMemorySize, pt_max) != hipSuccess)
+        return FEWHA_ERR_UNSUPPORTED;
     return FEWHA_OK;
 }
 

@@ -141,10 +141,11 @@ int plan_create(const fewha_config *cfg, Plan **out) {
         d.v_off = long(P->n_nodes);
         d.n_sub = W.n_sub;
         d.nv = W.n_sub + 1;
+        d.vp = (d.nv + 3) & ~3;
         if (d.nv > P->maxnv) P->maxnv = d.nv;
         P->dwfs.push_back(d);
         P->n_slopes += 2 * size_t(W.n_sub) * W.n_sub;
-        P->n_nodes += size_t(W.n_sub + 1) * (W.n_sub + 1);
+        P->n_nodes += size_t(d.nv) * d.vp;
     }
     // DMs
     for (int m = 0; m < P->nd; ++m) {
@@ -239,6 +240,8 @@ int plan_create(const fewha_config *cfg, Plan **out) {
         return k;
     };
     P->seg_wt.nseg = P->seg_pt.nseg = P->seg_fwd.nseg = P->nl;
+    for (int i = 0; i <= kMaxSeg; ++i)  // entries past the last segment never match a workgroup
+        P->seg_wt.start[i] = P->seg_pt.start[i] = P->seg_fwd.start[i] = P->seg_proj.start[i] = 0x7fffffff;
     for (int l = 0; l < P->nl; ++l) {
         const int n = P->lay[l].n, off = int(P->dlay[l].c_off);
         const int tw = n < kWtTile ? n : kWtTile, tp = n < kPtTile ? n : kPtTile;
@@ -261,10 +264,14 @@ int plan_create(const fewha_config *cfg, Plan **out) {
                 wt_cone(y0, x0, tw, P->J, loY, loX, LY, LX);
                 bool ok = true;
                 for (int s = 1; s <= P->J; ++s) {
+                    // load slots of the inverse DWT (lanes per row, rows per level) and the LDS
+                    // regions of its synthesis (rows x the level's power-of-two pitch)
                     const int lanes = s == 1 ? 32 : (s == 2 ? 16 : 8), rows = (s == 1 ? 72 : (s == 2 ? 48 : 32));
+                    const int lanes_o = s - 1 == 0 ? 32 : (s - 1 == 1 ? 32 : (s - 1 == 2 ? 16 : 8));
                     ok = ok && LX[s] <= lanes && (s == P->J ? 4 : 3) * LY[s] <= rows;
-                    if (s >= 2) ok = ok && LY[s - 1] * LX[s - 1] <= 18 * 18;
-                    ok = ok && ((LY[s - 1] + 1) & ~1) * LX[s] <= 32 * 18;
+                    ok = ok && LX[s - 1] <= lanes_o;
+                    if (s >= 2) ok = ok && LY[s - 1] * lanes_o <= 18 * 32;
+                    ok = ok && ((LY[s - 1] + 1) & ~1) * lanes <= 32 * 32;
                 }
                 if (!ok) {
                     delete P;
@@ -280,6 +287,7 @@ int plan_create(const fewha_config *cfg, Plan **out) {
         const int nv = P->wfs[g].n_sub + 1, tpr = (nv + kProjTile - 1) / kProjTile;
         P->seg_proj.start[g] = P->n_proj;
         P->seg_proj.off[g] = int(P->dwfs[g].v_off);
+        P->seg_proj.pitch[g] = P->dwfs[g].vp;
         P->seg_proj.aux[g] = int(P->dwfs[g].s_off);
         P->seg_proj.n[g] = P->wfs[g].n_sub;
         P->seg_proj.lt[g] = tpr;
@@ -290,7 +298,7 @@ int plan_create(const fewha_config *cfg, Plan **out) {
         P->laytab.off[l] = int(P->dlay[l].c_off);
         P->laytab.n[l] = P->lay[l].n;
     }
-    if (P->n_wt > kPartialPitch || P->n_proj > kPartialPitch) {
+    if (P->n_fwd + P->nl > kPartialPitch || P->n_proj > kPartialPitch) {
         delete P;
         return FEWHA_ERR_UNSUPPORTED;
     }
