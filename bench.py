@@ -8,8 +8,9 @@ frames) through the library's own forward operator plus white noise.
 
 Prints one JSON line: ms per frame (median over the timed frames is reported beside the mean),
 effective bandwidth of the algorithmic byte model against the 8 TB/s HBM peak, the roofline
-object of the dominant launch, and the FP64 CPU oracle timed on a bounded sample of the same
-frames on the host.
+object of the dominant kernel of a PCG pass (its algorithmic bytes per launch over its average
+launch duration, timed live with HIP events on the launch stream), per-stage timings, and the
+FP64 CPU oracle timed on a bounded sample of the same frames on the host.
 """
 import argparse
 import json
@@ -73,6 +74,81 @@ def byte_model(cfg, elem_bytes, n_iter):
             "n_coef": n_c, "sum_V": sum_v, "sum_S": sum_s, "sum_U": sum_u, "U_fit": u_fit}
 
 
+# Kernels of one PCG pass that fewha_stage_launch enqueues on their own (stage "fwd" is the pair
+# of forward-DWT launches, fine levels then coarse levels), with their algorithmic bytes per
+# launch in elements: W^T J^-1 r (read r, write u) | P then Gamma^T C Gamma (read the layer
+# footprints, the node grids through the slope stencil and back) | P^T (read v, write x) |
+# W + alpha D z + dots + fused update.
+STAGES = ("wt", "proj", "pt", "fwd")
+STAGE_KERNELS = {"wt": "k_wt<pcg>", "proj": "k_proj<M>", "pt": "k_pt", "fwd": "k_fwd<pcg> + k_coarse<pcg>"}
+SINGLE_KERNEL = ("wt", "proj", "pt")
+
+
+def stage_elements(model):
+    n_c, sv, su = model["n_coef"], model["sum_V"], model["sum_U"]
+    return {"wt": 2 * n_c, "proj": su + 3 * sv, "pt": sv + n_c, "fwd": 15 * n_c}
+
+
+def time_stages(P, stream, reps, replays=4):
+    """Average device duration (us) of each stage launch: `reps` back-to-back launches captured in
+    one HIP graph, replayed `replays` times between HIP events on the stream the plan launches on
+    (each per-launch figure therefore includes the launch's share of the dispatch gaps)."""
+    import torch
+    out = {}
+    cap = torch.cuda.Stream()
+    for st in STAGES:
+        for _ in range(5):
+            P.stage_launch(st)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        cap.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.graph(g, stream=cap):
+            for _ in range(reps):
+                P.stage_launch(st)
+        torch.cuda.current_stream().wait_stream(cap)
+        g.replay()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(replays + 1)]
+        ev[0].record(stream)
+        for i in range(replays):
+            g.replay()
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        out[st] = 1e3 * ev[0].elapsed_time(ev[-1]) / (replays * reps)
+        del g
+    return out
+
+
+def source_digest():
+    """SHA-256 over the kernel sources; recorded traffic is valid only for this digest."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "kernels.h", "fewha_internal.h"):
+        with open(os.path.join(ROOT, "paper_2009_00946_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel_stage, config):
+    """HBM bytes per launch from the committed counter summary of this kernel and workload
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when absent or taken on other sources."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_hbm_traffic.md" % (kernel_stage, config))
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- `") and "`: " in line:
+                key, val = line[3:].split("`: ", 1)
+                rec[key] = val.strip()
+    if rec.get("source_sha256") != source_digest():
+        return None
+    try:
+        return float(rec["fetch_bytes_per_launch"]) + float(rec["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(cfg, frames_s, n_iter, budget_s):
     """The FP64 oracle (single-threaded C) on host cores: ms per frame on a bounded sample."""
     from oracle import Oracle
@@ -105,6 +181,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle CPU time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eager", action="store_true", help="launch kernels one by one instead of replaying HIP graphs")
+    ap.add_argument("--stage-reps", type=int, default=50, help="launches per PCG-pass stage in its timing graph")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run plain 256 MiB device copies (reference dispatches for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs the single-GPU hot path only; multi-GPU runs are not provided "
@@ -178,8 +257,28 @@ def main():
     assert P.last_status() == 0
     ms_mean = total_ms / args.steps
 
-    model = byte_model(cfg, 4 if P.precision == "fp32" else 8, n_iter)
+    elem = 4 if P.precision == "fp32" else 8
+    model = byte_model(cfg, elem, n_iter)
     eff_gbps = model["frame"] / (ms_mean * 1e-3) / 1e9
+
+    # the dominant single kernel of a PCG pass, timed live (launches per frame x duration)
+    us = time_stages(P, stream, args.stage_reps)
+    sel = stage_elements(model)
+    per_frame = {"wt": n_iter, "proj": n_iter, "pt": n_iter + 1, "fwd": n_iter}
+    stages = {st: {"kernel": STAGE_KERNELS[st], "us_per_launch": round(us[st], 3),
+                   "bytes_per_launch": sel[st] * elem, "launches_per_frame": per_frame[st],
+                   "GBps": round(sel[st] * elem / (us[st] * 1e-6) / 1e9, 1)} for st in STAGES}
+    dom = max(SINGLE_KERNEL, key=lambda st: per_frame[st] * us[st])
+    achieved = sel[dom] * elem / (us[dom] * 1e-6) / 1e9
+    traffic = recorded_traffic(dom, cfg["name"])
+    if args.copy_calibration:
+        import torch
+        src = torch.empty(64 << 20, dtype=torch.float32, device=P.device).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     out = {
         "metric": METRIC,
         "value": round(ms_mean, 5),
@@ -202,9 +301,11 @@ def main():
         "effective_GBps": round(eff_gbps, 1),
         "frac_hbm_peak": round(eff_gbps / HBM_PEAK_GBPS, 4),
         "bytes_per_frame": model["frame"],
-        "roofline": {"bound": "hbm", "achieved": round(eff_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(eff_gbps / HBM_PEAK_GBPS, 4), "traffic": None,
-                     "kernel": "whole frame (RHS + %d PCG iterations + fit)" % n_iter},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                     "kernel": STAGE_KERNELS[dom], "us_per_launch": round(us[dom], 3),
+                     "bytes_per_launch": sel[dom] * elem},
+        "stages": stages,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, S_host, n_iter, args.cpu_budget)

@@ -61,15 +61,28 @@ struct TileId {
     int off, n, lt, aux, capr, capw, pitch;
 };
 
-__device__ __forceinline__ TileId find_tile(const SegTab &S) {
+// Workgroups are dealt to the chip's 8 XCDs round-robin (workgroup b runs on XCD b mod 8), and
+// every XCD has its own L2.  Tile kernels renumber their ntiles workgroups so that each XCD
+// receives one contiguous run of tiles: neighbouring tiles share halos and table lines, which then
+// meet in one L2 instead of being fetched into all eight.
+constexpr bool kXcdRuns = true;
+
+__device__ __forceinline__ int xcd_tile(int ntiles) {
+    const int b = (int)blockIdx.x;
+    if (!kXcdRuns) return b;
+    const int q = ntiles >> 3, rem = ntiles & 7, x = b & 7;
+    return x * q + min(x, rem) + (b >> 3);
+}
+
+__device__ __forceinline__ TileId find_tile(const SegTab &S, int b) {
     const int lane = threadIdx.x & 63;
     const int st = S.start[lane], of = S.off[lane], nn = S.n[lane], l2 = S.lt[lane], ax = S.aux[lane];
     const int cr = S.capr[lane], cw = S.capw[lane], pi = S.pitch[lane];
-    const unsigned long long m = __ballot((int)blockIdx.x >= st);
+    const unsigned long long m = __ballot(b >= st);
     const int s = 63 - __clzll(m);
     TileId t;
     t.seg = s;
-    t.loc = (int)blockIdx.x - __builtin_amdgcn_readlane(st, s);
+    t.loc = b - __builtin_amdgcn_readlane(st, s);
     t.off = __builtin_amdgcn_readlane(of, s);
     t.n = __builtin_amdgcn_readlane(nn, s);
     t.lt = __builtin_amdgcn_readlane(l2, s);
@@ -255,7 +268,7 @@ __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src,
     __shared__ T sJi[(kMaxJ + 1) * 4];
 
     const int tid = threadIdx.x;
-    const TileId id = find_tile(S);
+    const TileId id = find_tile(S, xcd_tile(gridDim.x));
     const int l = id.seg, n = id.n, lt = id.lt;
     const int T0 = n < kWtTile ? n : kWtTile;
     const int y0 = (id.loc >> lt) * T0, x0 = (id.loc & ((1 << lt) - 1)) * T0;
@@ -433,7 +446,7 @@ __global__ __launch_bounds__(kB) void k_proj(SegTab S, LayTab LT, InvVar IV, Pup
     __shared__ double sRed[kB / 64];
 
     const int tid = threadIdx.x;
-    const TileId id = find_tile(S);
+    const TileId id = find_tile(S, xcd_tile(gridDim.x));
     const int g = id.seg, ns = id.n, tpr = id.lt;
     const int ti = id.loc / tpr, tj = id.loc - ti * tpr;
     const int i0 = ti * kProjTile, j0 = tj * kProjTile;
@@ -540,7 +553,7 @@ __global__ __launch_bounds__(kB) void k_gt(SegTab S, InvVar IV, PupilArgs pa, co
                                            T *__restrict__ v) {
     __shared__ T sSx[kPS * kPS], sSy[kPS * kPS];
     const int tid = threadIdx.x;
-    const TileId id = find_tile(S);
+    const TileId id = find_tile(S, xcd_tile(gridDim.x));
     const int g = id.seg, ns = id.n, tpr = id.lt;
     const int ti = id.loc / tpr, tj = id.loc - ti * tpr;
     const int i0 = ti * kProjTile, j0 = tj * kProjTile;
@@ -601,7 +614,8 @@ __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restr
         return;
     }
     const int tid = threadIdx.x, lane = tid & 63;
-    const TileId id = find_tile(S);
+    const int vt = xcd_tile(PA.k >= 0 ? (int)gridDim.x - 1 : (int)gridDim.x);
+    const TileId id = find_tile(S, vt);
     const int n = id.n, lt = id.lt;
     const int T0 = n < NT ? n : NT;
     const int k0 = (id.loc >> lt) * T0, q0 = (id.loc & ((1 << lt) - 1)) * T0;
@@ -621,7 +635,7 @@ __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restr
     // (16-byte aligned), last column jB, pair counts, node grid offset / pitch, and the LDS
     // offset / pitch of its staged rectangle
     const int tg = min(lane, nw - 1);
-    const int4 rec = B.rects[(long)blockIdx.x * nw + tg];
+    const int4 rec = B.rects[(long)vt * nw + tg];
     const int gv = WO.v_off[tg], gp = WO.vp[tg];
     const int iA = rec.x & 0xffff, iB = rec.x >> 16, c0 = (rec.y & 0xffff) & ~(CH - 1), jB = rec.y >> 16;
     const int pitch = lane < nw && iA <= iB ? ((jB - c0) / CH + 1) * CH : 0;
@@ -710,7 +724,8 @@ __global__ __launch_bounds__(kB) void k_pt_scan(SegTab S, const T *__restrict__ 
         scalar_step(B.partials, PA.nwt, PA.nproj, B.sc, PA.k, PA.resnorm, PA.publish);
         return;
     }
-    const TileId id = find_tile(S);
+    const int vt = xcd_tile(PA.k >= 0 ? (int)gridDim.x - 1 : (int)gridDim.x);
+    const TileId id = find_tile(S, vt);
     const int l = id.seg, n = id.n, lt = id.lt;
     const int T0 = n < NT ? n : NT;
     const int a = threadIdx.x >> 4, b = threadIdx.x & 15;
@@ -869,7 +884,7 @@ __global__ __launch_bounds__((FwdLanes<KF, TQ>::block)) void k_fwd(SegTab S, con
     if constexpr (EPI == kEpiRhs) {
         if (blockIdx.x == 0 && tid == 0) reset_scalars(B.sc + 1);  // the state "before pass 0"
     }
-    const TileId id = find_tile(S);
+    const TileId id = find_tile(S, xcd_tile(gridDim.x));
     const int l = id.seg, n = id.n, lt = id.lt, nm = n - 1;
     const int qy = (id.loc >> lt) * TQ, qx = (id.loc & ((1 << lt) - 1)) * TQ;
     const long coff = id.off;
@@ -899,6 +914,13 @@ __global__ __launch_bounds__((FwdLanes<KF, TQ>::block)) void k_fwd(SegTab S, con
         for (int o = 0; o < 4; ++o)
             if (o > 0 || KF == J) epi_load<T, EPI>(B, E, band_index(coff, n, s_own, o, by, bx), op[o]);
     }
+    // prior weight and Jacobi factors of the lane's level, in the same round of loads
+    T ad = 0, ji[4] = {0, 0, 0, 0};
+    if (EPI != kEpiPlain) ad = B.ad[l * (J + 1) + s_own];
+    if (EPI == kEpiPcg || EPI == kEpiRhs) {
+#pragma unroll
+        for (int o = 0; o < 4; ++o) ji[o] = B.jinv[(l * (J + 1) + s_own) * 4 + o];
+    }
     StepOut so{0.0, 0.0, 0};
     if constexpr (EPI == kEpiPcg) so = read_step(B.sc);
     lds_fence();
@@ -910,12 +932,6 @@ __global__ __launch_bounds__((FwdLanes<KF, TQ>::block)) void k_fwd(SegTab S, con
         const int sp = s == 1 ? L0 : L1;
         const bool mine = s == 1 ? own1 : own2;
         if (mine) {
-            T ad = 0, ji[4] = {0, 0, 0, 0};
-            if (EPI != kEpiPlain) ad = B.ad[l * (J + 1) + s];
-            if (EPI == kEpiPcg || EPI == kEpiRhs) {
-#pragma unroll
-                for (int o = 0; o < 4; ++o) ji[o] = B.jinv[(l * (J + 1) + s) * 4 + o];
-            }
             T w[4];
             analyse(src, sp, rq, cq, tp, w[0], w[1], w[2], w[3]);
 #pragma unroll
@@ -1010,6 +1026,10 @@ __global__ __launch_bounds__(kCB) void k_coarse(LayTab LT, Bufs<T> B, FwdArgs E,
             }
         }
     }
+    // prior weights and Jacobi factors of the layer's levels: [s] = alpha D, [kMaxJ + 1 + 4 s + o] = J^-1
+    __shared__ T sW[5 * (kMaxJ + 1)];
+    if (EPI != kEpiPlain && tid <= J) sW[tid] = B.ad[l * (J + 1) + tid];
+    if ((EPI == kEpiPcg || EPI == kEpiRhs) && tid < 4 * (J + 1)) sW[kMaxJ + 1 + tid] = B.jinv[l * (J + 1) * 4 + tid];
     StepOut so{0.0, 0.0, 0};
     if constexpr (EPI == kEpiPcg) so = read_step(B.sc);
     lds_fence();
@@ -1017,10 +1037,10 @@ __global__ __launch_bounds__(kCB) void k_coarse(LayTab LT, Bufs<T> B, FwdArgs E,
     for (int s = KF + 1; s <= J; ++s) {
         const int mi = n >> (s - 1), h = mi >> 1, msk = mi - 1, nq = h * h;
         T ad = 0, ji[4] = {0, 0, 0, 0};
-        if (EPI != kEpiPlain) ad = B.ad[l * (J + 1) + s];
+        if (EPI != kEpiPlain) ad = sW[s];
         if (EPI == kEpiPcg || EPI == kEpiRhs) {
 #pragma unroll
-            for (int o = 0; o < 4; ++o) ji[o] = B.jinv[(l * (J + 1) + s) * 4 + o];
+            for (int o = 0; o < 4; ++o) ji[o] = sW[kMaxJ + 1 + 4 * s + o];
         }
         for (int q0 = 0; q0 < nq; q0 += kCB) {
             const int qi = q0 + tid;
@@ -1203,7 +1223,7 @@ __global__ __launch_bounds__(kMaxWfs) void k_build_rects(SegTab S, const Range *
                                                          const Range *__restrict__ yrng, int4 *rects, int nw, int sum_n) {
     const int g = threadIdx.x;
     if (g >= nw) return;
-    const TileId id = find_tile(S);
+    const TileId id = find_tile(S, (int)blockIdx.x);
     const int n = id.n, lt = id.lt;
     const int T0 = n < kPtTile ? n : kPtTile;
     const int k0 = (id.loc >> lt) * T0, q0 = (id.loc & ((1 << lt) - 1)) * T0;
