@@ -55,7 +55,7 @@ struct PupilArgs {            // subaperture (i, j) of guide star g is active if
 // The tile of this workgroup and its segment's entries.  Every lane of the wave reads one
 // segment's entries in a single round of loads (entries past the last segment start at INT_MAX);
 // a ballot then picks the last segment starting at or before this workgroup and its entries are
-// broadcast from that lane.
+// broadcast from that lane.  All 64 lanes of the wave must be active.
 struct TileId {
     int seg, loc;
     int off, n, lt, aux, capr, capw, pitch;
@@ -975,21 +975,25 @@ __global__ __launch_bounds__((FwdLanes<KF, TQ>::block)) void k_fwd(SegTab S, con
 // m0 x m0 block (m0 = n >> KF).  With `pre`, that block of every epilogue operand is staged in
 // LDS together with the approximation, in one round of loads; otherwise each level requests its
 // operands before its analysis.  Dynamic LDS: m0^2 + (m0/2)^2 (+ NOP m0^2 with `pre`) values.
+// With `gin` (a block too large for LDS) level KF+1 reads the approximation from global memory
+// and the LDS holds only the smaller levels: (m0/4)^2 + (m0/2)^2 values.
 template <typename T, int EPI>
 __global__ __launch_bounds__(kCB) void k_coarse(LayTab LT, Bufs<T> B, FwdArgs E, Taps<T> tp, int J, int KF, int nfine,
-                                                int pre) {
+                                                int pre, int gin) {
     extern __shared__ char smem_raw[];
     constexpr int NOP = EpiOps<EPI>::n, NL = 16;
     const int tid = threadIdx.x, l = blockIdx.x, n = LT.n[l], m0 = n >> KF, mm = m0 * m0;
     const long coff = LT.off[l];
-    T *cs = reinterpret_cast<T *>(smem_raw), *cd = cs + mm, *opl = cd + mm / 4;
+    T *cs = reinterpret_cast<T *>(smem_raw), *cd = cs + (gin ? mm / 16 : mm), *opl = cd + mm / 4;
     const T *__restrict__ llin = B.ll + (coff >> (2 * KF));
+    if (!gin) {
 #pragma unroll
-    for (int c = 0; c < NL; ++c) {
-        const int k = tid + c * kCB;
-        if (c * kCB < mm && k < mm) {
-            if constexpr (sizeof(T) == 4) g2lds(llin + k, cs + c * kCB + (tid & ~63));
-            else cs[k] = llin[k];
+        for (int c = 0; c < NL; ++c) {
+            const int k = tid + c * kCB;
+            if (c * kCB < mm && k < mm) {
+                if constexpr (sizeof(T) == 4) g2lds(llin + k, cs + c * kCB + (tid & ~63));
+                else cs[k] = llin[k];
+            }
         }
     }
     if (NOP > 0 && pre) {
@@ -1065,21 +1069,25 @@ __global__ __launch_bounds__(kCB) void k_coarse(LayTab LT, Bufs<T> B, FwdArgs E,
             }
             if (act) {
                 T w[4] = {0, 0, 0, 0};
+                auto analyse_wrap = [&](const T *src) {
 #pragma unroll
-                for (int a = 0; a < 6; ++a) {
-                    const T *row = cs + ((2 * r + a) & msk) * mi;
-                    T ax = 0, dx = 0;
+                    for (int a = 0; a < 6; ++a) {
+                        const T *row = src + ((2 * r + a) & msk) * mi;
+                        T ax = 0, dx = 0;
 #pragma unroll
-                    for (int b = 0; b < 6; ++b) {
-                        const T xv = row[(2 * q + b) & msk];
-                        ax += tp.h[b] * xv;
-                        dx += tp.g[b] * xv;
+                        for (int b = 0; b < 6; ++b) {
+                            const T xv = row[(2 * q + b) & msk];
+                            ax += tp.h[b] * xv;
+                            dx += tp.g[b] * xv;
+                        }
+                        w[0] += tp.h[a] * ax;
+                        w[2] += tp.g[a] * ax;
+                        w[1] += tp.h[a] * dx;
+                        w[3] += tp.g[a] * dx;
                     }
-                    w[0] += tp.h[a] * ax;
-                    w[2] += tp.g[a] * ax;
-                    w[1] += tp.h[a] * dx;
-                    w[3] += tp.g[a] * dx;
-                }
+                };
+                if (gin && s == KF + 1) analyse_wrap(llin);
+                else analyse_wrap(cs);
 #pragma unroll
                 for (int o = 1; o < 4; ++o) epi_store<T, EPI>(B, E, band_index(coff, n, s, o, r, q), w[o], op[o], ji[o], ad, so, rho, dz);
                 if (s == J) epi_store<T, EPI>(B, E, band_index(coff, n, s, 0, r, q), w[0], op[0], ji[0], ad, so, rho, dz);
@@ -1222,8 +1230,8 @@ __global__ __launch_bounds__(kB) void k_build_ranges(Range *xrng, Range *yrng, R
 __global__ __launch_bounds__(kMaxWfs) void k_build_rects(SegTab S, const Range *__restrict__ xrng,
                                                          const Range *__restrict__ yrng, int4 *rects, int nw, int sum_n) {
     const int g = threadIdx.x;
+    const TileId id = find_tile(S, (int)blockIdx.x);  // the whole wave: lane s reads segment s
     if (g >= nw) return;
-    const TileId id = find_tile(S, (int)blockIdx.x);
     const int n = id.n, lt = id.lt;
     const int T0 = n < kPtTile ? n : kPtTile;
     const int k0 = (id.loc >> lt) * T0, q0 = (id.loc & ((1 << lt) - 1)) * T0;
@@ -1375,9 +1383,13 @@ static int fwd_launch(const Plan &P, const Bufs<T> &B, hipStream_t st, const T *
     if (P.kf < P.J) {
         size_t m = 0;
         for (auto &L : P.lay) m = (size_t)(L.n >> P.kf) > m ? (size_t)(L.n >> P.kf) : m;
-        const size_t base = (m * m + m * m / 4) * sizeof(T), opb = (size_t)EpiOps<EPI>::n * m * m * sizeof(T);
-        const int pre = EpiOps<EPI>::n > 0 && base + opb <= kCoarseLdsMax ? 1 : 0;
-        k_coarse<T, EPI><<<P.nl, kCB, base + (pre ? opb : 0), st>>>(P.laytab, B, E, tp, P.J, P.kf, nf, pre);
+        size_t base = (m * m + m * m / 4) * sizeof(T);
+        const size_t opb = (size_t)EpiOps<EPI>::n * m * m * sizeof(T);
+        const int gin = base > kCoarseLdsMax ? 1 : 0;
+        if (gin) base = (m * m / 16 + m * m / 4) * sizeof(T);
+        if (base > kCoarseLdsMax) return FEWHA_ERR_UNSUPPORTED;
+        const int pre = !gin && EpiOps<EPI>::n > 0 && base + opb <= kCoarseLdsMax ? 1 : 0;
+        k_coarse<T, EPI><<<P.nl, kCB, base + (pre ? opb : 0), st>>>(P.laytab, B, E, tp, P.J, P.kf, nf, pre, gin);
         if (int e = check()) return e;
     }
     return FEWHA_OK;

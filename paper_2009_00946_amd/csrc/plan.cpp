@@ -223,8 +223,11 @@ int plan_create(const fewha_config *cfg, Plan **out) {
     P->tq = kFwdQuads;
     while (P->tq > (min_n >> P->kf)) P->tq >>= 1;
     {
+        // the level-kf block and its first coarse level in LDS; a block too large for that is
+        // read from global memory by the first coarse level, leaving two smaller levels in LDS
         size_t m = size_t(max_n >> P->kf);
         P->coarse_lds = P->kf < P->J ? (m * m + (m / 2) * (m / 2)) * P->elem : 0;
+        if (P->coarse_lds > 150 * 1024) P->coarse_lds = ((m / 4) * (m / 4) + (m / 2) * (m / 2)) * P->elem;
     }
     if (P->coarse_lds > 150 * 1024 || (size_t(max_n >> P->kf) * (max_n >> P->kf) > size_t(16) * 1024) ||
         P->n_coef >= (size_t(1) << 31) || P->n_nodes >= (size_t(1) << 31) || P->n_slopes >= (size_t(1) << 31)) {

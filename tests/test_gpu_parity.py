@@ -88,6 +88,24 @@ def test_operator_parity(name, prec, tol):
     check(host(P.apply_M(dev(P, c))), O.M(c), tol, "M")
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_stress_config_operator_parity(prec, tol):
+    """35 layers up to 512^2 and J = 7 (the coarse forward levels of the largest layers read their
+    input from global memory): W, W^T, A, A^T and M against the oracle."""
+    from oracle import Oracle
+    P = plan("c4_stress", prec)
+    if "c4_stress/noprecond" not in _oracles:
+        _oracles["c4_stress/noprecond"] = Oracle(synth.load_config("c4_stress"), precond=False)
+    O = _oracles["c4_stress/noprecond"]
+    x = synth.normal_vector(O.n_coef, 31)
+    check(host(P.dwt_forward(dev(P, x))), O.W(x), tol, "W")
+    check(host(P.dwt_inverse(dev(P, x))), O.Wt(x), tol, "W^T")
+    s = synth.normal_vector(O.n_slopes, 32)
+    check(host(P.apply_A(dev(P, x))), O.A(x), tol, "A")
+    check(host(P.apply_At(dev(P, s))), O.At(s), tol, "A^T")
+    check(host(P.apply_M(dev(P, x))), O.M(x), tol, "M")
+
+
 @pytest.mark.parametrize("name,prec,tol", [("t1_mixed", "fp64", 1e-12), ("c0_tiny", "fp64", 1e-12),
                                            ("c1_elt_mcao", "fp32", 2e-5)])
 def test_precond_table_parity(name, prec, tol):
