@@ -104,7 +104,7 @@ typedef struct {
  * copied.  Geometry rules (Sec. 2.1): WFS node x_j = -D/2 + j d; a ray from node (x, y) towards
  * guide star g meets layer l at (sigma x + theta_x h, sigma y + theta_y h) with sigma = 1 - h/H
  * (LGS) or 1 (NGS); every such point and every fitting actuator must lie inside its layer grid.
- * Limits: n_layers <= 64, n_wfs <= 64, n_dms <= 16, J <= 12, layer n <= 4096, n_sub <= 4096.
+ * Limits: n_layers <= 64, n_wfs <= 64, n_dms <= 16, J <= 12, layer n <= 512, n_sub <= 4096.
  * Returns FEWHA_ERR_INVALID_ARG, FEWHA_ERR_GEOMETRY or FEWHA_ERR_UNSUPPORTED on rejection. */
 int fewha_plan_create(const fewha_config *cfg, fewha_plan **out);
 
@@ -156,6 +156,25 @@ int fewha_pcg_solve(fewha_plan *p, const void *d_s, void *d_c, int n_iter, int f
 int fewha_fit_dm(const fewha_plan *p, const void *d_c, const void *d_a_prev, double gain, void *d_a,
                  void *stream);
 
+/* Differentiation support (the adjoint state of Eq. (fewha)).  Solve M c = b for a right-hand
+ * side b given in the wavelet domain (n_coef values), from c = 0, with n_iter passes of Alg. 2
+ * and the Jacobi preconditioner of Sec. 3.4; d_resnorm as in fewha_pcg_solve.  The residual
+ * starts at W (W^T b), equal to b up to rounding.  Uses the workspace's residual and PCG vectors,
+ * so it overwrites the warm-restart state (b_prev = b, r_prev = the final residual): save it
+ * with fewha_state_get first when a frame chain continues.  d_b must not alias d_c. */
+int fewha_solve_M(fewha_plan *p, const void *d_b, void *d_c, int n_iter, double *d_resnorm, void *stream);
+
+/* s = C_eta^-1 mask Gamma P W^T c: fewha_apply_A weighted by the inverse noise variance
+ * sigma_g^-2 of each guide star (Eq. (MAP)), the map from coefficients to the weighted data
+ * residual of the MAP functional. */
+int fewha_apply_CA(const fewha_plan *p, const void *d_c, void *d_s, void *stream);
+
+/* Per layer l: d_out[l] = sum over the layer's coefficients k of x_k (alpha D)_k y_k, in FP64 and
+ * fixed order (d_out: n_layers doubles on the device).  alpha D is the prior of Eq. (fewha) per
+ * (layer, level); since D_l is proportional to 1/gamma_l (the Cn^2 weight), dM/dgamma_l is
+ * -(alpha D)_l / gamma_l on layer l and zero elsewhere. */
+int fewha_prior_dot(const fewha_plan *p, const void *d_x, const void *d_y, double *d_out, void *stream);
+
 /* Copy the warm-restart state (b_prev, r_prev; n_coef each) out of / into the workspace. */
 int fewha_state_get(const fewha_plan *p, void *d_b_prev, void *d_r_prev, void *stream);
 int fewha_state_set(fewha_plan *p, const void *d_b_prev, const void *d_r_prev, void *stream);
@@ -167,19 +186,22 @@ int fewha_precond_table(const fewha_plan *p, double *h_jdiag);
 
 /* Stages of one PCG pass, for timing a single launch (fewha_stage_launch). */
 typedef enum {
-    FEWHA_STAGE_WT = 0,   /* u = W^T J^-1 r: inverse DWT of the preconditioned residual, with the
-                             (r, z) and (z, alpha D z) partial sums (Alg. 2; Kernel 1, Sec. 3.3) */
-    FEWHA_STAGE_PROJ = 1, /* v = Gamma^T C_eta^-1 Gamma P u on every guide star (Kernel 2, Sec. 3.3) */
-    FEWHA_STAGE_PT = 2,   /* x = P^T v on every layer (Kernel 3, Sec. 3.3) */
-    FEWHA_STAGE_FWD = 3   /* y = W x + alpha D z, all levels, with the PCG update of Alg. 2, applied to
-                             workspace scratch copies of r, p, q, c (Kernel 3, Sec. 3.3) */
+    FEWHA_STAGE_WT = 0,   /* u = W^T J^-1 r: inverse DWT of the preconditioned residual (Alg. 2;
+                             Kernel 1, Sec. 3.3) */
+    FEWHA_STAGE_PROJ = 1, /* v = Gamma^T C_eta^-1 Gamma P u on every guide star, with the partial
+                             sums of C (Gamma P u)^2 (Kernel 2, Sec. 3.3) */
+    FEWHA_STAGE_PT = 2,   /* x = P^T v on every layer (Kernel 3, Sec. 3.3), with the Alg. 2 scalar
+                             step in one extra workgroup */
+    FEWHA_STAGE_FWD = 3   /* y = W x + alpha D z, all levels, with the PCG update of Alg. 2 and the
+                             next pass's partial sums, applied to workspace scratch copies of r, p,
+                             q, c (Kernel 3, Sec. 3.3) */
 } fewha_stage;
 
 /* Enqueue one launch of one stage of the PCG pass on the plan's current workspace contents
  * (the vectors the previous stage left there), for timing and profiling a single kernel.  The
  * stages read and write only workspace intermediates (u, v, x, partial sums, scratch vectors):
- * the caller's vectors, the warm-restart state and the PCG scalars are untouched, so a later
- * fewha_pcg_solve is unaffected.  Returns FEWHA_ERR_INVALID_ARG for an unknown stage. */
+ * the caller's vectors, the warm-restart state and the published PCG scalar state are untouched,
+ * so a later fewha_pcg_solve is unaffected.  Returns FEWHA_ERR_INVALID_ARG for an unknown stage. */
 int fewha_stage_launch(const fewha_plan *p, int stage, void *stream);
 
 /* Read the device status word of the last solve (synchronises the device): FEWHA_OK,

@@ -100,16 +100,9 @@ int apply_M(const Plan &P, const void *c, void *y, void *stream) {
     return o.fwd(o.B.x, E, kEpiPrior);
 }
 
+// n_iter passes of Alg. 2 from the residual and scalar state a right-hand-side epilogue left.
 template <typename T>
-int pcg_solve(const Plan &P, const void *s, void *c, int n_iter, int flags, double *resnorm, void *stream) {
-    auto o = ops<T>(P, stream);
-    // right-hand side b = W P^T Gamma^T C s, then the warm-restart residual update
-    TRY(o.gt(static_cast<const T *>(s), o.B.v, kGtRhs));
-    TRY(o.pt(o.B.v, o.B.x, PassArgs{-1, 0, 0, 0, nullptr}));
-    FwdArgs R{};
-    R.c = c;
-    R.cold = flags == FEWHA_COLD ? 1 : 0;
-    TRY(o.fwd(o.B.x, R, kEpiRhs));
+int pcg_passes(const Plan &P, const Ops<T> &o, void *c, int n_iter, double *resnorm) {
     // partial sums of (r, z) and (z, alpha D z) come from the forward transforms that write r
     const int nres = P.n_fwd + (P.kf < P.J ? P.nl : 0);
     for (int k = 0; k < n_iter; ++k) {
@@ -125,6 +118,46 @@ int pcg_solve(const Plan &P, const void *s, void *c, int n_iter, int flags, doub
     }
     const_cast<Plan &>(P).last_slot = n_iter > 0 ? ((n_iter - 1) & 1) : 1;
     return FEWHA_OK;
+}
+
+template <typename T>
+int pcg_solve(const Plan &P, const void *s, void *c, int n_iter, int flags, double *resnorm, void *stream) {
+    auto o = ops<T>(P, stream);
+    // right-hand side b = W P^T Gamma^T C s, then the warm-restart residual update
+    TRY(o.gt(static_cast<const T *>(s), o.B.v, kGtRhs));
+    TRY(o.pt(o.B.v, o.B.x, PassArgs{-1, 0, 0, 0, nullptr}));
+    FwdArgs R{};
+    R.c = c;
+    R.cold = flags == FEWHA_COLD ? 1 : 0;
+    TRY(o.fwd(o.B.x, R, kEpiRhs));
+    return pcg_passes<T>(P, o, c, n_iter, resnorm);
+}
+
+// M c = b for a right-hand side given in the coefficient domain, from c = 0: x = W^T b first,
+// so that the right-hand-side epilogue's W x reproduces b (W W^T = I, to rounding) and starts the
+// residual there.
+template <typename T>
+int solve_M(const Plan &P, const void *b, void *c, int n_iter, double *resnorm, void *stream) {
+    auto o = ops<T>(P, stream);
+    TRY(o.wt(static_cast<const T *>(b), o.B.x));
+    FwdArgs R{};
+    R.c = c;
+    R.cold = 1;
+    TRY(o.fwd(o.B.x, R, kEpiRhs));
+    return pcg_passes<T>(P, o, c, n_iter, resnorm);
+}
+
+template <typename T>
+int apply_CA(const Plan &P, const void *c, void *s, void *stream) {
+    auto o = ops<T>(P, stream);
+    TRY(o.wt(static_cast<const T *>(c), o.B.u));
+    return o.proj(o.B.u, static_cast<T *>(s), kProjCA);
+}
+
+template <typename T>
+int prior_dot(const Plan &P, const void *x, const void *y, double *out, void *stream) {
+    auto o = ops<T>(P, stream);
+    return o.prior_dot(static_cast<const T *>(x), static_cast<const T *>(y), out);
 }
 
 template <typename T>
@@ -345,6 +378,26 @@ int fewha_pcg_solve(fewha_plan *p, const void *d_s, void *d_c, int n_iter, int f
     if (!d_s || !d_c || n_iter < 0 || (flags != FEWHA_COLD && flags != FEWHA_WARM)) return FEWHA_ERR_INVALID_ARG;
     return p->p.prec == FEWHA_FP64 ? pcg_solve<double>(p->p, d_s, d_c, n_iter, flags, d_resnorm, stream)
                                    : pcg_solve<float>(p->p, d_s, d_c, n_iter, flags, d_resnorm, stream);
+}
+
+int fewha_solve_M(fewha_plan *p, const void *d_b, void *d_c, int n_iter, double *d_resnorm, void *stream) {
+    TRY(ready(p));
+    if (!d_b || !d_c || d_b == d_c || n_iter < 0) return FEWHA_ERR_INVALID_ARG;
+    return p->p.prec == FEWHA_FP64 ? solve_M<double>(p->p, d_b, d_c, n_iter, d_resnorm, stream)
+                                   : solve_M<float>(p->p, d_b, d_c, n_iter, d_resnorm, stream);
+}
+
+int fewha_apply_CA(const fewha_plan *p, const void *d_c, void *d_s, void *stream) {
+    TRY(ready(p));
+    if (!d_c || !d_s) return FEWHA_ERR_INVALID_ARG;
+    return p->p.prec == FEWHA_FP64 ? apply_CA<double>(p->p, d_c, d_s, stream) : apply_CA<float>(p->p, d_c, d_s, stream);
+}
+
+int fewha_prior_dot(const fewha_plan *p, const void *d_x, const void *d_y, double *d_out, void *stream) {
+    TRY(ready(p));
+    if (!d_x || !d_y || !d_out) return FEWHA_ERR_INVALID_ARG;
+    return p->p.prec == FEWHA_FP64 ? prior_dot<double>(p->p, d_x, d_y, d_out, stream)
+                                   : prior_dot<float>(p->p, d_x, d_y, d_out, stream);
 }
 
 int fewha_fit_dm(const fewha_plan *p, const void *d_c, const void *d_a_prev, double gain, void *d_a, void *stream) {

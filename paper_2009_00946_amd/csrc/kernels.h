@@ -36,8 +36,9 @@ struct Taps {
 template <typename T>
 Taps<T> make_taps();
 
-// Node-tile modes: Gamma^T C Gamma P u (with the data-term partial) | mask Gamma P u.
-enum { kProjM = 0, kProjA = 1 };
+// Node-tile modes: Gamma^T C Gamma P u (with the data-term partial) | mask Gamma P u |
+// C mask Gamma P u.
+enum { kProjM = 0, kProjA = 1, kProjCA = 2 };
 // Gamma^T modes: Gamma^T C s (right-hand side) | Gamma^T mask s (adjoint of A).
 enum { kGtRhs = 0, kGtAdj = 1 };
 
@@ -59,12 +60,13 @@ struct Ops {
     int prepare() const;                                  // per-device kernel attributes (bind)
     int wt(const T *c, T *out) const;                     // out = W^T c
     int wt_pcg(const T *r, T *out) const;                 // out = W^T J^-1 r; (r, z), (z, alpha D z) partials
-    int proj(const T *u, T *out, int mode) const;         // kProjM: v = Gamma^T C Gamma P u; kProjA: s = mask Gamma P u
+    int proj(const T *u, T *out, int mode) const;         // kProjM: v = Gamma^T C Gamma P u; kProjA/CA: s = (C) mask Gamma P u
     int gt(const T *s, T *v, int mode) const;             // v = Gamma^T C s | Gamma^T mask s
     int pt(const T *v, T *x, const PassArgs &PA) const;   // x = P^T v (+ the scalar step of pass PA.k)
     int fwd(const T *x, const FwdArgs &E, int epi) const; // W x with an epilogue (all levels)
     int wnorm(const T *s) const;                          // sc[2].rho = sum C s^2
     int fit(const T *u, const T *a_prev, T *a, double gain) const;
+    int prior_dot(const T *x, const T *y, double *out) const;  // out[l] = sum_layer x alpha D y
     int build_tables(int *over) const;                    // projection cell, transpose and rectangle tables
     int fill(T *x, long n, T val) const;
     int copy(T *dst, const T *src, long n) const;

@@ -433,7 +433,7 @@ constexpr int kProjLch = 12;         // layers whose bilinear loads are in fligh
 constexpr int kProjEntSlots = (2 * kMaxLayers * kPR + kB - 1) / kB;
 
 // kProjM: v = Gamma^T C Gamma P u with the partial sum C (Gamma P u)^2 (Kernel 2 of the paper);
-// kProjA: s = mask Gamma P u.  phi = P u comes from the bilinear cell tables of the region's 16
+// kProjA: s = mask Gamma P u; kProjCA: s = C mask Gamma P u.  phi = P u comes from the bilinear cell tables of the region's 16
 // rows and columns on every layer, staged in LDS; each lane then gathers its node's four
 // neighbours on kProjLch layers at a time and sums the layers in order.
 template <typename T, int MODE>
@@ -519,10 +519,11 @@ __global__ __launch_bounds__(kB) void k_proj(SegTab S, LayTab LT, InvVar IV, Pup
             sy = (T)0.5 * ((p10 - p00) + (p11 - p01));
         }
         const bool own = aa >= 1 && bb >= 1 && ii < ns && jj < ns;
-        if (MODE == kProjA) {
+        if (MODE != kProjM) {
+            const T wgt = MODE == kProjCA ? (T)IV.v[g] : (T)1;
             if (own) {
-                out[id.aux + (long)ii * ns + jj] = sx;
-                out[id.aux + (long)ns * ns + (long)ii * ns + jj] = sy;
+                out[id.aux + (long)ii * ns + jj] = wgt * sx;
+                out[id.aux + (long)ns * ns + (long)ii * ns + jj] = wgt * sy;
             }
         } else {
             const double iv = IV.v[g];
@@ -531,7 +532,7 @@ __global__ __launch_bounds__(kB) void k_proj(SegTab S, LayTab LT, InvVar IV, Pup
             sSy[tid] = (T)iv * sy;
         }
     }
-    if (MODE == kProjA) return;
+    if (MODE != kProjM) return;
     __syncthreads();
     if (tid < kProjTile * kProjTile) {
         const int aa = tid / kProjTile, bb = tid - aa * kProjTile, ii = i0 + aa, jj = j0 + bb;
@@ -1166,6 +1167,25 @@ __global__ __launch_bounds__(kB) void k_fit(const T *__restrict__ u, const T *__
 }
 
 // Cell tables: entry (g, l, j) of each axis from the ray geometry (setup, once per bind).
+// Per layer l (one workgroup each): out[l] = sum over the layer's coefficients of x alpha D y in
+// FP64, fixed order.  The level of coefficient (r, q) of an n x n Mallat pyramid is J inside the
+// top-left (n >> J)^2 block, else log2 n - floor(log2 max(r, q)).
+template <typename T>
+__global__ __launch_bounds__(kB) void k_prior_dot(LayTab LT, const T *__restrict__ x, const T *__restrict__ y,
+                                                  const T *__restrict__ ad, int J, double *out) {
+    __shared__ double sh[kB / 64];
+    const int l = blockIdx.x, n = LT.n[l], ln = 31 - __clz(n);
+    const long off = LT.off[l];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n * n; i += kB) {
+        const int r = i >> ln, q = i & (n - 1), t = r > q ? r : q;
+        const int s = t < (n >> J) ? J : ln - (31 - __clz(t));
+        acc += (double)x[off + i] * (double)ad[l * (J + 1) + s] * (double)y[off + i];
+    }
+    const double v = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[l] = v;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kB) void k_build_tabs(Ent<T> *xtab, Ent<T> *ytab, const DevWfs *__restrict__ wfs,
                                                    const DevProj *__restrict__ proj,
@@ -1338,6 +1358,8 @@ template <typename T>
 int Ops<T>::proj(const T *u, T *out, int mode) const {
     if (mode == kProjM)
         k_proj<T, kProjM><<<P.n_proj, kB, 0, st>>>(P.seg_proj, P.laytab, inv_var_tab(P), pupil(P), u, out, B, P.nl);
+    else if (mode == kProjCA)
+        k_proj<T, kProjCA><<<P.n_proj, kB, 0, st>>>(P.seg_proj, P.laytab, inv_var_tab(P), pupil(P), u, out, B, P.nl);
     else
         k_proj<T, kProjA><<<P.n_proj, kB, 0, st>>>(P.seg_proj, P.laytab, inv_var_tab(P), pupil(P), u, out, B, P.nl);
     return check();
@@ -1450,6 +1472,12 @@ int Ops<T>::build_tables(int *over) const {
         const_cast<RtabEnt<T> *>(B.yrtab), B.xtab, B.ytab, B.wfs, B.lay, P.nw, P.nl, P.maxnv, P.sum_n, over);
     if (int e = check()) return e;
     k_build_rects<<<P.n_pt, kMaxWfs, 0, st>>>(P.seg_pt, B.xrng, B.yrng, const_cast<int4 *>(B.rects), P.nw, P.sum_n);
+    return check();
+}
+
+template <typename T>
+int Ops<T>::prior_dot(const T *x, const T *y, double *out) const {
+    k_prior_dot<T><<<P.nl, kB, 0, st>>>(P.laytab, x, y, B.ad, P.J, out);
     return check();
 }
 

@@ -19,7 +19,8 @@ STATUS = {0: "FEWHA_OK", -1: "FEWHA_ERR_INVALID_ARG", -2: "FEWHA_ERR_GEOMETRY", 
 EXPORTS = ["fewha_plan_create", "fewha_workspace_bytes", "fewha_plan_bind", "fewha_plan_destroy", "fewha_sizes",
            "fewha_apply_A", "fewha_apply_At", "fewha_apply_M", "fewha_dwt_forward", "fewha_dwt_inverse",
            "fewha_pcg_solve", "fewha_fit_dm", "fewha_state_get", "fewha_state_set", "fewha_precond_table",
-           "fewha_last_status", "fewha_stage_launch", "fewha_strerror"]
+           "fewha_last_status", "fewha_stage_launch", "fewha_strerror", "fewha_solve_M", "fewha_apply_CA",
+           "fewha_prior_dot"]
 
 
 class FewhaError(RuntimeError):
@@ -68,8 +69,10 @@ def load_library():
     L.fewha_plan_destroy.argtypes = [vp]
     L.fewha_sizes.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz), ctypes.POINTER(sz)]
     for name in ("fewha_apply_A", "fewha_apply_At", "fewha_apply_M", "fewha_dwt_forward", "fewha_dwt_inverse",
-                 "fewha_state_get", "fewha_state_set"):
+                 "fewha_state_get", "fewha_state_set", "fewha_apply_CA"):
         getattr(L, name).argtypes = [vp, vp, vp, vp]
+    L.fewha_solve_M.argtypes = [vp, vp, vp, ctypes.c_int, vp, vp]
+    L.fewha_prior_dot.argtypes = [vp, vp, vp, vp, vp]
     L.fewha_pcg_solve.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, vp]
     L.fewha_fit_dm.argtypes = [vp, vp, vp, ctypes.c_double, vp, vp]
     L.fewha_precond_table.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
@@ -208,6 +211,33 @@ class Plan:
                                     int(n_iter), FEWHA_WARM if warm else FEWHA_COLD, rp, self._stream()),
                "fewha_pcg_solve")
         return c
+
+    def solve_M(self, b, c=None, n_iter=None, resnorm=None):
+        """c = M^-1 b (n_iter cold PCG passes) for a wavelet-domain right-hand side; overwrites the
+        warm-restart state."""
+        n_iter = int(self.cfg["n_iter"] if n_iter is None else n_iter)
+        c = self._out(c, self.n_coef)
+        rp = None
+        if resnorm is not None:
+            if not resnorm.is_cuda or resnorm.dtype != self._torch.float64 or resnorm.numel() < n_iter:
+                raise ValueError("resnorm: float64 CUDA tensor of n_iter elements expected")
+            rp = resnorm.data_ptr()
+        _check(_lib.fewha_solve_M(self._h, self._arg(b, self.n_coef, "b"), self._arg(c, self.n_coef, "c"), n_iter,
+                                  rp, self._stream()), "fewha_solve_M")
+        return c
+
+    def apply_CA(self, c, out=None):
+        s = self._out(out, self.n_slopes)
+        _check(_lib.fewha_apply_CA(self._h, self._arg(c, self.n_coef, "c"), self._arg(s, self.n_slopes, "s"),
+                                   self._stream()), "fewha_apply_CA")
+        return s
+
+    def prior_dot(self, x, y):
+        """Per layer: sum of x alpha D y over the layer's coefficients (float64 CUDA tensor)."""
+        out = self._torch.empty(len(self.cfg["layers"]), dtype=self._torch.float64, device=self.device)
+        _check(_lib.fewha_prior_dot(self._h, self._arg(x, self.n_coef, "x"), self._arg(y, self.n_coef, "y"),
+                                    out.data_ptr(), self._stream()), "fewha_prior_dot")
+        return out
 
     def fit_dm(self, c, a_prev=None, gain=1.0, out=None):
         a = self._out(out, self.n_act)
