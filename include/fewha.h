@@ -184,6 +184,26 @@ int fewha_state_set(fewha_plan *p, const void *d_b_prev, const void *d_r_prev, v
  * unused entries are 0.  h_jdiag holds n_layers * (J + 1) * 4 doubles.  Requires a bound plan. */
 int fewha_precond_table(const fewha_plan *p, double *h_jdiag);
 
+/* Batches of frames of one geometry.  Each stage of the path runs as one launch over every frame
+ * of the batch (the frames are independent reconstructions: each has its own right-hand side,
+ * warm-restart state and Alg. 2 scalars; only the geometry tables and the preconditioner are
+ * shared).  fewha_plan_set_batch(p, max_batch) sizes the workspace for max_batch frames
+ * (1 <= max_batch <= 1024); call it before fewha_workspace_bytes and fewha_plan_bind (it unbinds
+ * a bound plan).  The single-frame calls act on frame 0.  In the _batch calls every vector
+ * argument holds nbatch frames back to back, frame-major ([nbatch][n_coef], [nbatch][n_slopes],
+ * [nbatch][n_act]; d_resnorm [nbatch][n_iter]), 1 <= nbatch <= max_batch, and frame f uses the
+ * workspace state of frame f; otherwise each behaves as its single-frame counterpart. */
+int fewha_plan_set_batch(fewha_plan *p, int max_batch);
+int fewha_apply_A_batch(const fewha_plan *p, int nbatch, const void *d_c, void *d_s, void *stream);
+int fewha_apply_At_batch(const fewha_plan *p, int nbatch, const void *d_s, void *d_c, void *stream);
+int fewha_apply_M_batch(const fewha_plan *p, int nbatch, const void *d_c, void *d_y, void *stream);
+int fewha_pcg_solve_batch(fewha_plan *p, int nbatch, const void *d_s, void *d_c, int n_iter, int flags,
+                          double *d_resnorm, void *stream);
+int fewha_fit_dm_batch(const fewha_plan *p, int nbatch, const void *d_c, const void *d_a_prev, double gain,
+                       void *d_a, void *stream);
+/* Status words of frames 0..nbatch-1 after the last enqueued solve (synchronises the device). */
+int fewha_last_status_batch(const fewha_plan *p, int nbatch, int *h_status);
+
 /* Stages of one PCG pass, for timing a single launch (fewha_stage_launch). */
 typedef enum {
     FEWHA_STAGE_WT = 0,   /* u = W^T J^-1 r: inverse DWT of the preconditioned residual (Alg. 2;

@@ -46,12 +46,19 @@ Bufs<T> bufs(const Plan &P) {
     b.over = reinterpret_cast<int *>(w + P.o_over);
     b.partials = reinterpret_cast<double *>(w + P.o_partials);
     b.sc = reinterpret_cast<Scalars *>(w + P.o_scalars);
+    b.fs_c = (long)P.n_coef;
+    b.fs_v = (long)P.n_nodes;
+    b.fs_s = (long)P.n_slopes;
+    b.fs_a = (long)P.n_act;
+    b.fs_ll = (long)(P.n_coef / 4 + 1);
     return b;
 }
 
 template <typename T>
-Ops<T> ops(const Plan &P, void *stream) {
-    return Ops<T>{P, bufs<T>(P), static_cast<hipStream_t>(stream)};
+Ops<T> ops(const Plan &P, void *stream, int nb = 1) {
+    Ops<T> o{P, bufs<T>(P), static_cast<hipStream_t>(stream)};
+    o.nb = nb;
+    return o;
 }
 
 #define TRY(x)                          \
@@ -72,28 +79,28 @@ int ready(const fewha_plan *p) {
 }
 
 template <typename T>
-int apply_A(const Plan &P, const void *c, void *s, void *stream) {
-    auto o = ops<T>(P, stream);
+int apply_A(const Plan &P, const void *c, void *s, void *stream, int nb = 1) {
+    auto o = ops<T>(P, stream, nb);
     TRY(o.wt(static_cast<const T *>(c), o.B.u));
     return o.proj(o.B.u, static_cast<T *>(s), kProjA);
 }
 
 template <typename T>
-int apply_At(const Plan &P, const void *s, void *c, void *stream) {
-    auto o = ops<T>(P, stream);
+int apply_At(const Plan &P, const void *s, void *c, void *stream, int nb = 1) {
+    auto o = ops<T>(P, stream, nb);
     TRY(o.gt(static_cast<const T *>(s), o.B.v, kGtAdj));
-    TRY(o.pt(o.B.v, o.B.x, PassArgs{-1, 0, 0, 0, nullptr}));
+    TRY(o.pt(o.B.v, o.B.x, PassArgs{-1, 0, 0, 0, nullptr, 0}));
     FwdArgs E{};
     E.out = c;
     return o.fwd(o.B.x, E, kEpiPlain);
 }
 
 template <typename T>
-int apply_M(const Plan &P, const void *c, void *y, void *stream) {
-    auto o = ops<T>(P, stream);
+int apply_M(const Plan &P, const void *c, void *y, void *stream, int nb = 1) {
+    auto o = ops<T>(P, stream, nb);
     TRY(o.wt(static_cast<const T *>(c), o.B.u));
     TRY(o.proj(o.B.u, o.B.v, kProjM));
-    TRY(o.pt(o.B.v, o.B.x, PassArgs{-1, 0, 0, 0, nullptr}));
+    TRY(o.pt(o.B.v, o.B.x, PassArgs{-1, 0, 0, 0, nullptr, 0}));
     FwdArgs E{};
     E.out = y;
     E.cin = c;
@@ -108,11 +115,10 @@ int pcg_passes(const Plan &P, const Ops<T> &o, void *c, int n_iter, double *resn
     for (int k = 0; k < n_iter; ++k) {
         TRY(o.wt_pcg(o.B.r, o.B.u));             // u = W^T J^-1 r
         TRY(o.proj(o.B.u, o.B.v, kProjM));       // v = Gamma^T C Gamma P u; (C Gamma P u, Gamma P u) partials
-        TRY(o.pt(o.B.v, o.B.x, PassArgs{k, nres, P.n_proj, 1, resnorm}));  // x = P^T v; Alg. 2 scalars
+        TRY(o.pt(o.B.v, o.B.x, PassArgs{k, nres, P.n_proj, 1, resnorm, n_iter}));  // x = P^T v; Alg. 2 scalars
         FwdArgs E{};                             // y = W x + alpha D z; the pass update
         E.c = c;
         E.k = k;
-        E.resnorm = resnorm;
         E.publish = 1;
         TRY(o.fwd(o.B.x, E, kEpiPcg));
     }
@@ -121,11 +127,12 @@ int pcg_passes(const Plan &P, const Ops<T> &o, void *c, int n_iter, double *resn
 }
 
 template <typename T>
-int pcg_solve(const Plan &P, const void *s, void *c, int n_iter, int flags, double *resnorm, void *stream) {
-    auto o = ops<T>(P, stream);
+int pcg_solve(const Plan &P, const void *s, void *c, int n_iter, int flags, double *resnorm, void *stream,
+              int nb = 1) {
+    auto o = ops<T>(P, stream, nb);
     // right-hand side b = W P^T Gamma^T C s, then the warm-restart residual update
     TRY(o.gt(static_cast<const T *>(s), o.B.v, kGtRhs));
-    TRY(o.pt(o.B.v, o.B.x, PassArgs{-1, 0, 0, 0, nullptr}));
+    TRY(o.pt(o.B.v, o.B.x, PassArgs{-1, 0, 0, 0, nullptr, 0}));
     FwdArgs R{};
     R.c = c;
     R.cold = flags == FEWHA_COLD ? 1 : 0;
@@ -161,8 +168,8 @@ int prior_dot(const Plan &P, const void *x, const void *y, double *out, void *st
 }
 
 template <typename T>
-int fit_dm(const Plan &P, const void *c, const void *a_prev, double gain, void *a, void *stream) {
-    auto o = ops<T>(P, stream);
+int fit_dm(const Plan &P, const void *c, const void *a_prev, double gain, void *a, void *stream, int nb = 1) {
+    auto o = ops<T>(P, stream, nb);
     TRY(o.wt(static_cast<const T *>(c), o.B.u));
     return o.fit(o.B.u, static_cast<const T *>(a_prev), static_cast<T *>(a), gain);
 }
@@ -174,7 +181,7 @@ int stage_launch(const Plan &P, int stage, void *stream) {
         case FEWHA_STAGE_WT: return o.wt_pcg(o.B.r, o.B.u);
         case FEWHA_STAGE_PROJ: return o.proj(o.B.u, o.B.v, kProjM);
         case FEWHA_STAGE_PT:
-            return o.pt(o.B.v, o.B.x, PassArgs{1, P.n_fwd + (P.kf < P.J ? P.nl : 0), P.n_proj, 0, nullptr});
+            return o.pt(o.B.v, o.B.x, PassArgs{1, P.n_fwd + (P.kf < P.J ? P.nl : 0), P.n_proj, 0, nullptr, 0});
         default: {
             // the frame's y = W x + alpha D z with the pass update, applied to scratch copies of
             // r, p, q and c, without publishing scalars
@@ -208,9 +215,10 @@ int bind_tables(Plan &P, hipStream_t st) {
     TRY(o.prepare());
     HIPTRY(hipMemset(o.B.over, 0, sizeof(int) * P.nw));
     TRY(o.build_tables(o.B.over));
-    TRY(o.init_scalars());
-    TRY(o.fill(o.B.b_prev, N, 0));
-    TRY(o.fill(o.B.r, N, 0));
+    const long NB = N * P.max_batch;
+    TRY(ops<T>(P, st, P.max_batch).init_scalars());
+    TRY(o.fill(o.B.b_prev, NB, 0));
+    TRY(o.fill(o.B.r, NB, 0));
     TRY(o.fill(o.B.probe_c, N, 0));
     TRY(o.fill(reinterpret_cast<T *>(w + P.o_stage), 4 * N, 0));
     HIPTRY(hipStreamSynchronize(st));
@@ -270,7 +278,7 @@ int bind_tables(Plan &P, hipStream_t st) {
     for (size_t k = 0; k < jinv.size(); ++k)
         if (P.jtab[k] > 0) jinv[k] = (T)(1.0 / P.jtab[k]);
     HIPTRY(hipMemcpy(w + P.o_jinv, jinv.data(), sizeof(T) * jinv.size(), hipMemcpyHostToDevice));
-    TRY(o.init_scalars());
+    TRY(ops<T>(P, st, P.max_batch).init_scalars());
     HIPTRY(hipStreamSynchronize(st));
     return FEWHA_OK;
 }
@@ -405,6 +413,68 @@ int fewha_fit_dm(const fewha_plan *p, const void *d_c, const void *d_a_prev, dou
     if (!d_c || !d_a || d_a == d_c || !std::isfinite(gain)) return FEWHA_ERR_INVALID_ARG;
     return p->p.prec == FEWHA_FP64 ? fit_dm<double>(p->p, d_c, d_a_prev, gain, d_a, stream)
                                    : fit_dm<float>(p->p, d_c, d_a_prev, gain, d_a, stream);
+}
+
+int fewha_plan_set_batch(fewha_plan *p, int max_batch) {
+    if (!p || max_batch < 1 || max_batch > kMaxBatch) return FEWHA_ERR_INVALID_ARG;
+    p->p.max_batch = max_batch;
+    p->p.bound = false;  // the workspace map changed: bind again
+    p->p.ws = nullptr;
+    layout_workspace(&p->p);
+    return FEWHA_OK;
+}
+
+static int batch_ok(const fewha_plan *p, int nbatch) {
+    TRY(ready(p));
+    return nbatch >= 1 && nbatch <= p->p.max_batch ? FEWHA_OK : FEWHA_ERR_INVALID_ARG;
+}
+
+int fewha_apply_A_batch(const fewha_plan *p, int nbatch, const void *d_c, void *d_s, void *stream) {
+    TRY(batch_ok(p, nbatch));
+    if (!d_c || !d_s) return FEWHA_ERR_INVALID_ARG;
+    return p->p.prec == FEWHA_FP64 ? apply_A<double>(p->p, d_c, d_s, stream, nbatch)
+                                   : apply_A<float>(p->p, d_c, d_s, stream, nbatch);
+}
+
+int fewha_apply_At_batch(const fewha_plan *p, int nbatch, const void *d_s, void *d_c, void *stream) {
+    TRY(batch_ok(p, nbatch));
+    if (!d_c || !d_s) return FEWHA_ERR_INVALID_ARG;
+    return p->p.prec == FEWHA_FP64 ? apply_At<double>(p->p, d_s, d_c, stream, nbatch)
+                                   : apply_At<float>(p->p, d_s, d_c, stream, nbatch);
+}
+
+int fewha_apply_M_batch(const fewha_plan *p, int nbatch, const void *d_c, void *d_y, void *stream) {
+    TRY(batch_ok(p, nbatch));
+    if (!d_c || !d_y || d_c == d_y) return FEWHA_ERR_INVALID_ARG;
+    return p->p.prec == FEWHA_FP64 ? apply_M<double>(p->p, d_c, d_y, stream, nbatch)
+                                   : apply_M<float>(p->p, d_c, d_y, stream, nbatch);
+}
+
+int fewha_pcg_solve_batch(fewha_plan *p, int nbatch, const void *d_s, void *d_c, int n_iter, int flags,
+                          double *d_resnorm, void *stream) {
+    TRY(batch_ok(p, nbatch));
+    if (!d_s || !d_c || n_iter < 0 || (flags != FEWHA_COLD && flags != FEWHA_WARM)) return FEWHA_ERR_INVALID_ARG;
+    return p->p.prec == FEWHA_FP64 ? pcg_solve<double>(p->p, d_s, d_c, n_iter, flags, d_resnorm, stream, nbatch)
+                                   : pcg_solve<float>(p->p, d_s, d_c, n_iter, flags, d_resnorm, stream, nbatch);
+}
+
+int fewha_fit_dm_batch(const fewha_plan *p, int nbatch, const void *d_c, const void *d_a_prev, double gain,
+                       void *d_a, void *stream) {
+    TRY(batch_ok(p, nbatch));
+    if (!d_c || !d_a || d_a == d_c || !std::isfinite(gain)) return FEWHA_ERR_INVALID_ARG;
+    return p->p.prec == FEWHA_FP64 ? fit_dm<double>(p->p, d_c, d_a_prev, gain, d_a, stream, nbatch)
+                                   : fit_dm<float>(p->p, d_c, d_a_prev, gain, d_a, stream, nbatch);
+}
+
+int fewha_last_status_batch(const fewha_plan *p, int nbatch, int *h_status) {
+    TRY(batch_ok(p, nbatch));
+    if (!h_status) return FEWHA_ERR_INVALID_ARG;
+    if (hipDeviceSynchronize() != hipSuccess) return FEWHA_ERR_HIP;
+    std::vector<Scalars> sc(size_t(nbatch) * kScalarSlots);
+    if (hipMemcpy(sc.data(), p->p.ws + p->p.o_scalars, sizeof(Scalars) * sc.size(), hipMemcpyDeviceToHost) != hipSuccess)
+        return FEWHA_ERR_HIP;
+    for (int f = 0; f < nbatch; ++f) h_status[f] = sc[size_t(f) * kScalarSlots + p->p.last_slot].status;
+    return FEWHA_OK;
 }
 
 int fewha_stage_launch(const fewha_plan *p, int stage, void *stream) {

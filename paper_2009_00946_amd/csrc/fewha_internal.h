@@ -33,6 +33,10 @@ constexpr int kPtStage = 6144;
 constexpr int kPtMaxWfs = 16;
 // Slots per row of the FP64 partial-sum buffer (one per workgroup of a reduction).
 constexpr int kPartialPitch = 4096;
+// Scalar records per frame: two pass-parity slots, the right-hand-side record, the current pass.
+constexpr int kScalarSlots = 4;
+// Frames of one batched launch (grid y).
+constexpr int kMaxBatch = 1024;
 // Segments (layers or guide stars) of one launch's tile table.
 constexpr int kMaxSeg = 64;
 
@@ -152,9 +156,13 @@ struct Bufs {
     const T *ad;                      // [nl][J+1] alpha D per level
     T *b_prev, *r, *p, *q, *u, *x, *v, *ll, *probe_c, *probe_s;
     int *over;                        // per-sensor flags: a transpose row exceeded kRtabWidth (setup)
-    double *partials;                 // [3][kPartialPitch]: (r, z) and (z, alpha D z) per inverse-DWT
-                                      // tile, sum C (Gamma P u)^2 per projection tile
-    Scalars *sc;
+    double *partials;                 // [3][kPartialPitch]: (r, z) and (z, alpha D z) per forward-DWT
+                                      // tile and coarse layer, sum C (Gamma P u)^2 per projection tile
+    Scalars *sc;                      // [kScalarSlots]
+    // a batch of frames of the same geometry: frame f's vectors, partial sums and scalar slots sit
+    // f strides after frame 0's (in elements): coefficients, node grids, slopes, actuators,
+    // level-kf approximations
+    long fs_c, fs_v, fs_s, fs_a, fs_ll;
 };
 
 struct Plan {
@@ -179,6 +187,7 @@ struct Plan {
     int tq = 8;           // level-kf quads per tile edge of the fine forward DWT
     bool rtab_ok = true;  // the staged transpose gather applies (else the scanning P^T)
     int last_slot = 1;    // scalar slot holding the state after the last enqueued solve
+    int max_batch = 1;    // frames the workspace holds state for (same geometry, one launch per stage)
     size_t coarse_lds = 0;
     size_t pt_lds = 0;    // dynamic LDS of the staged P^T (node rectangles of every guide star)
     std::vector<double> ad;     // alpha D per (layer, level)
@@ -198,6 +207,7 @@ struct Plan {
 
 // plan.cpp (host only)
 int plan_create(const fewha_config *cfg, Plan **out);
+void layout_workspace(Plan *P);
 int level_band(int n, int J, int row, int col, int *s, int *o);
 // Inverse-DWT cone of a tile: level-s region origins / sizes (level-s index space), s = 0..J.
 void wt_cone(int y0, int x0, int T0, int J, int *loY, int *loX, int *LY, int *LX);

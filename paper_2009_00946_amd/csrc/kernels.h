@@ -12,7 +12,6 @@ struct FwdArgs {
     void *out;          // plain / prior: destination coefficients
     const void *cin;    // prior: c of y = W x + alpha D c
     void *c;            // pcg: iterate c (updated); rhs: caller's c (zeroed on a cold start)
-    double *resnorm;    // pcg: optional sqrt(rho) per pass
     int cold;           // rhs: cold start
     int k;              // pcg: pass index (0 = first pass: beta = 0, p = z, q = y)
     int publish;        // pcg: workgroup 0 stores the pass's scalar state (0 for stage timing)
@@ -21,9 +20,10 @@ struct FwdArgs {
 // The PCG pass whose scalar step an x = P^T v launch also performs (k < 0: none).
 struct PassArgs {
     int k;              // pass index
-    int nwt, nproj;     // partial sums of the inverse DWT and of the projection
+    int nwt, nproj;     // partial sums of the residual-writing transforms and of the projection
     int publish;        // store the new scalar state in the slot of pass k and sqrt(rho) in resnorm
-    double *resnorm;
+    double *resnorm;    // frame f's values start at resnorm + f * rstride
+    int rstride;
 };
 
 // Daubechies-3 analysis taps h and high-pass partner g_n = (-1)^n h_{5-n}.
@@ -56,6 +56,7 @@ struct Ops {
     const Plan &P;
     Bufs<T> B;
     hipStream_t st;
+    int nb = 1;  // frames per launch (grid y); caller vectors are [nb][length], frame-major
 
     int prepare() const;                                  // per-device kernel attributes (bind)
     int wt(const T *c, T *out) const;                     // out = W^T c

@@ -93,6 +93,33 @@ __device__ __forceinline__ TileId find_tile(const SegTab &S, int b) {
     return t;
 }
 
+// Frame blockIdx.y of a batch: its per-frame vectors, partial sums and scalar slots.
+template <typename T>
+__device__ __forceinline__ Bufs<T> at_frame(Bufs<T> B) {
+    const long f = blockIdx.y, c = f * B.fs_c;
+    B.b_prev += c;
+    B.r += c;
+    B.p += c;
+    B.q += c;
+    B.u += c;
+    B.x += c;
+    B.v += f * B.fs_v;
+    B.ll += f * B.fs_ll;
+    B.partials += f * 3 * kPartialPitch;
+    B.sc += f * kScalarSlots;
+    return B;
+}
+
+// The caller's coefficient vectors of frame blockIdx.y (frame-major, fs_c apart).
+template <typename T>
+__device__ __forceinline__ FwdArgs frame_args(FwdArgs E, long fs_c) {
+    const long c = blockIdx.y * fs_c;
+    if (E.out) E.out = static_cast<T *>(E.out) + c;
+    if (E.cin) E.cin = static_cast<const T *>(E.cin) + c;
+    if (E.c) E.c = static_cast<T *>(E.c) + c;
+    return E;
+}
+
 __device__ __forceinline__ bool subap_active(const PupilArgs &pa, int ns, int i, int j) {
     const double d = pa.D / ns, x0 = -0.5 * pa.D;
     const double xc = ((double)j + 0.5) * d + x0, yc = ((double)i + 0.5) * d + x0;
@@ -267,6 +294,8 @@ __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src,
     __shared__ T sXl[kWtX], sXh[kWtX];
     __shared__ T sJi[(kMaxJ + 1) * 4];
 
+    src += blockIdx.y * B.fs_c;
+    out += blockIdx.y * B.fs_c;
     const int tid = threadIdx.x;
     const TileId id = find_tile(S, xcd_tile(gridDim.x));
     const int l = id.seg, n = id.n, lt = id.lt;
@@ -445,6 +474,9 @@ __global__ __launch_bounds__(kB) void k_proj(SegTab S, LayTab LT, InvVar IV, Pup
     __shared__ T sSx[kPS * kPS], sSy[kPS * kPS];
     __shared__ double sRed[kB / 64];
 
+    B = at_frame(B);
+    u += blockIdx.y * B.fs_c;
+    out += blockIdx.y * (MODE == kProjM ? B.fs_v : B.fs_s);
     const int tid = threadIdx.x;
     const TileId id = find_tile(S, xcd_tile(gridDim.x));
     const int g = id.seg, ns = id.n, tpr = id.lt;
@@ -551,8 +583,10 @@ __global__ __launch_bounds__(kB) void k_proj(SegTab S, LayTab LT, InvVar IV, Pup
 // Gamma^T C s (kGtRhs) or Gamma^T mask s (kGtAdj) on the node tiles of k_proj.
 template <typename T, int MODE>
 __global__ __launch_bounds__(kB) void k_gt(SegTab S, InvVar IV, PupilArgs pa, const T *__restrict__ in,
-                                           T *__restrict__ v) {
+                                           T *__restrict__ v, long fs_s, long fs_v) {
     __shared__ T sSx[kPS * kPS], sSy[kPS * kPS];
+    in += blockIdx.y * fs_s;
+    v += blockIdx.y * fs_v;
     const int tid = threadIdx.x;
     const TileId id = find_tile(S, xcd_tile(gridDim.x));
     const int g = id.seg, ns = id.n, tpr = id.lt;
@@ -610,8 +644,12 @@ __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restr
     RtabEnt<T>(*sP)[2][RW][NT] = reinterpret_cast<RtabEnt<T>(*)[2][RW][NT]>(smem_raw);
     T *sV = reinterpret_cast<T *>(smem_raw + sizeof(RtabEnt<T>) * 2 * RW * NT * nw);
 
+    B = at_frame(B);
+    v += blockIdx.y * B.fs_v;
+    x += blockIdx.y * B.fs_c;
     if (PA.k >= 0 && blockIdx.x == gridDim.x - 1) {  // the pass's scalar step (extra workgroup)
-        scalar_step(B.partials, PA.nwt, PA.nproj, B.sc, PA.k, PA.resnorm, PA.publish);
+        scalar_step(B.partials, PA.nwt, PA.nproj, B.sc, PA.k, PA.resnorm ? PA.resnorm + blockIdx.y * PA.rstride : nullptr,
+                    PA.publish);
         return;
     }
     const int tid = threadIdx.x, lane = tid & 63;
@@ -721,8 +759,12 @@ template <typename T>
 __global__ __launch_bounds__(kB) void k_pt_scan(SegTab S, const T *__restrict__ v, T *__restrict__ x, Bufs<T> B,
                                                 int nl, int nw, PassArgs PA) {
     constexpr int NT = kPtTile;
+    B = at_frame(B);
+    v += blockIdx.y * B.fs_v;
+    x += blockIdx.y * B.fs_c;
     if (PA.k >= 0 && blockIdx.x == gridDim.x - 1) {  // the pass's scalar step (extra workgroup)
-        scalar_step(B.partials, PA.nwt, PA.nproj, B.sc, PA.k, PA.resnorm, PA.publish);
+        scalar_step(B.partials, PA.nwt, PA.nproj, B.sc, PA.k, PA.resnorm ? PA.resnorm + blockIdx.y * PA.rstride : nullptr,
+                    PA.publish);
         return;
     }
     const int vt = xcd_tile(PA.k >= 0 ? (int)gridDim.x - 1 : (int)gridDim.x);
@@ -881,6 +923,9 @@ __global__ __launch_bounds__((FwdLanes<KF, TQ>::block)) void k_fwd(SegTab S, con
     __shared__ T sA[L0 * L0];
     __shared__ T sB[KF >= 2 ? L1 * L1 : 1];
 
+    B = at_frame(B);
+    E = frame_args<T>(E, B.fs_c);
+    x += blockIdx.y * B.fs_c;
     const int tid = threadIdx.x;
     if constexpr (EPI == kEpiRhs) {
         if (blockIdx.x == 0 && tid == 0) reset_scalars(B.sc + 1);  // the state "before pass 0"
@@ -983,6 +1028,8 @@ __global__ __launch_bounds__(kCB) void k_coarse(LayTab LT, Bufs<T> B, FwdArgs E,
                                                 int pre, int gin) {
     extern __shared__ char smem_raw[];
     constexpr int NOP = EpiOps<EPI>::n, NL = 16;
+    B = at_frame(B);
+    E = frame_args<T>(E, B.fs_c);
     const int tid = threadIdx.x, l = blockIdx.x, n = LT.n[l], m0 = n >> KF, mm = m0 * m0;
     const long coff = LT.off[l];
     T *cs = reinterpret_cast<T *>(smem_raw), *cd = cs + (gin ? mm / 16 : mm), *opl = cd + mm / 4;
@@ -1145,6 +1192,9 @@ __global__ __launch_bounds__(kB) void k_sum_partials(const double *__restrict__ 
 template <typename T>
 __global__ __launch_bounds__(kB) void k_fit(const T *__restrict__ u, const T *__restrict__ a_prev, T *__restrict__ a,
                                             Bufs<T> B, int nl, int nd, long n_act, double gain) {
+    u += blockIdx.y * B.fs_c;
+    if (a_prev) a_prev += blockIdx.y * B.fs_a;
+    a += blockIdx.y * B.fs_a;
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_act) return;
     int m = 0;
@@ -1289,7 +1339,8 @@ __global__ __launch_bounds__(kB) void k_copy(T *__restrict__ dst, const T *__res
 }
 
 __global__ void k_init_scalars(Scalars *sc) {
-    if (threadIdx.x < 4 && blockIdx.x == 0) {
+    sc += blockIdx.y * kScalarSlots;
+    if (threadIdx.x < kScalarSlots && blockIdx.x == 0) {
         reset_scalars(sc + threadIdx.x);
         sc[threadIdx.x].counter = 0u;
     }
@@ -1344,47 +1395,48 @@ Taps<T> make_taps() {
 
 template <typename T>
 int Ops<T>::wt(const T *c, T *out) const {
-    k_wt<T, kWtPlain><<<P.n_wt, kWB, 0, st>>>(P.seg_wt, c, out, B, make_taps<T>(), P.J);
+    k_wt<T, kWtPlain><<<dim3(P.n_wt, nb), kWB, 0, st>>>(P.seg_wt, c, out, B, make_taps<T>(), P.J);
     return check();
 }
 
 template <typename T>
 int Ops<T>::wt_pcg(const T *r, T *out) const {
-    k_wt<T, kWtPcg><<<P.n_wt, kWB, 0, st>>>(P.seg_wt, r, out, B, make_taps<T>(), P.J);
+    k_wt<T, kWtPcg><<<dim3(P.n_wt, nb), kWB, 0, st>>>(P.seg_wt, r, out, B, make_taps<T>(), P.J);
     return check();
 }
 
 template <typename T>
 int Ops<T>::proj(const T *u, T *out, int mode) const {
     if (mode == kProjM)
-        k_proj<T, kProjM><<<P.n_proj, kB, 0, st>>>(P.seg_proj, P.laytab, inv_var_tab(P), pupil(P), u, out, B, P.nl);
+        k_proj<T, kProjM><<<dim3(P.n_proj, nb), kB, 0, st>>>(P.seg_proj, P.laytab, inv_var_tab(P), pupil(P), u, out, B, P.nl);
     else if (mode == kProjCA)
-        k_proj<T, kProjCA><<<P.n_proj, kB, 0, st>>>(P.seg_proj, P.laytab, inv_var_tab(P), pupil(P), u, out, B, P.nl);
+        k_proj<T, kProjCA><<<dim3(P.n_proj, nb), kB, 0, st>>>(P.seg_proj, P.laytab, inv_var_tab(P), pupil(P), u, out, B, P.nl);
     else
-        k_proj<T, kProjA><<<P.n_proj, kB, 0, st>>>(P.seg_proj, P.laytab, inv_var_tab(P), pupil(P), u, out, B, P.nl);
+        k_proj<T, kProjA><<<dim3(P.n_proj, nb), kB, 0, st>>>(P.seg_proj, P.laytab, inv_var_tab(P), pupil(P), u, out, B, P.nl);
     return check();
 }
 
 template <typename T>
 int Ops<T>::gt(const T *s, T *v, int mode) const {
-    if (mode == kGtRhs) k_gt<T, kGtRhs><<<P.n_proj, kB, 0, st>>>(P.seg_proj, inv_var_tab(P), pupil(P), s, v);
-    else k_gt<T, kGtAdj><<<P.n_proj, kB, 0, st>>>(P.seg_proj, inv_var_tab(P), pupil(P), s, v);
+    const dim3 grid(P.n_proj, nb);
+    if (mode == kGtRhs) k_gt<T, kGtRhs><<<grid, kB, 0, st>>>(P.seg_proj, inv_var_tab(P), pupil(P), s, v, B.fs_s, B.fs_v);
+    else k_gt<T, kGtAdj><<<grid, kB, 0, st>>>(P.seg_proj, inv_var_tab(P), pupil(P), s, v, B.fs_s, B.fs_v);
     return check();
 }
 
 template <typename T>
 int Ops<T>::pt(const T *v, T *x, const PassArgs &PA) const {
-    const int grid = P.n_pt + (PA.k >= 0 ? 1 : 0);
+    const dim3 grid(P.n_pt + (PA.k >= 0 ? 1 : 0), nb);
     if (P.rtab_ok) k_pt<T><<<grid, kB, P.pt_lds, st>>>(P.seg_pt, wfs_off_tab(P), v, x, B, P.nw, PA);
     else k_pt_scan<T><<<grid, kB, 0, st>>>(P.seg_pt, v, x, B, P.nl, P.nw, PA);
     return check();
 }
 
 template <typename T, int EPI>
-static int fwd_launch(const Plan &P, const Bufs<T> &B, hipStream_t st, const T *x, const FwdArgs &E) {
+static int fwd_launch(const Plan &P, const Bufs<T> &B, hipStream_t st, int nb, const T *x, const FwdArgs &E) {
     const Taps<T> tp = make_taps<T>();
     const int nf = P.n_fwd;
-#define FEWHA_FWD(KF, TQ) k_fwd<T, KF, TQ, EPI><<<nf, (FwdLanes<KF, TQ>::block), 0, st>>>(P.seg_fwd, x, B, E, tp, P.J)
+#define FEWHA_FWD(KF, TQ) k_fwd<T, KF, TQ, EPI><<<dim3(nf, nb), (FwdLanes<KF, TQ>::block), 0, st>>>(P.seg_fwd, x, B, E, tp, P.J)
     if (P.kf == 1) {
         switch (P.tq) {
             case 1: FEWHA_FWD(1, 1); break;
@@ -1411,7 +1463,7 @@ static int fwd_launch(const Plan &P, const Bufs<T> &B, hipStream_t st, const T *
         if (gin) base = (m * m / 16 + m * m / 4) * sizeof(T);
         if (base > kCoarseLdsMax) return FEWHA_ERR_UNSUPPORTED;
         const int pre = !gin && EpiOps<EPI>::n > 0 && base + opb <= kCoarseLdsMax ? 1 : 0;
-        k_coarse<T, EPI><<<P.nl, kCB, base + (pre ? opb : 0), st>>>(P.laytab, B, E, tp, P.J, P.kf, nf, pre, gin);
+        k_coarse<T, EPI><<<dim3(P.nl, nb), kCB, base + (pre ? opb : 0), st>>>(P.laytab, B, E, tp, P.J, P.kf, nf, pre, gin);
         if (int e = check()) return e;
     }
     return FEWHA_OK;
@@ -1420,10 +1472,10 @@ static int fwd_launch(const Plan &P, const Bufs<T> &B, hipStream_t st, const T *
 template <typename T>
 int Ops<T>::fwd(const T *x, const FwdArgs &E, int epi) const {
     switch (epi) {
-        case kEpiPlain: return fwd_launch<T, kEpiPlain>(P, B, st, x, E);
-        case kEpiPrior: return fwd_launch<T, kEpiPrior>(P, B, st, x, E);
-        case kEpiPcg: return fwd_launch<T, kEpiPcg>(P, B, st, x, E);
-        default: return fwd_launch<T, kEpiRhs>(P, B, st, x, E);
+        case kEpiPlain: return fwd_launch<T, kEpiPlain>(P, B, st, nb, x, E);
+        case kEpiPrior: return fwd_launch<T, kEpiPrior>(P, B, st, nb, x, E);
+        case kEpiPcg: return fwd_launch<T, kEpiPcg>(P, B, st, nb, x, E);
+        default: return fwd_launch<T, kEpiRhs>(P, B, st, nb, x, E);
     }
 }
 
@@ -1456,7 +1508,7 @@ int Ops<T>::wnorm(const T *s) const {
 
 template <typename T>
 int Ops<T>::fit(const T *u, const T *a_prev, T *a, double gain) const {
-    k_fit<T><<<grid_for((long)P.n_act), kB, 0, st>>>(u, a_prev, a, B, P.nl, P.nd, (long)P.n_act, gain);
+    k_fit<T><<<dim3(grid_for((long)P.n_act), nb), kB, 0, st>>>(u, a_prev, a, B, P.nl, P.nd, (long)P.n_act, gain);
     return check();
 }
 
@@ -1495,7 +1547,7 @@ int Ops<T>::copy(T *dst, const T *src, long n) const {
 
 template <typename T>
 int Ops<T>::init_scalars() const {
-    k_init_scalars<<<1, 64, 0, st>>>(B.sc);
+    k_init_scalars<<<dim3(1, nb), 64, 0, st>>>(B.sc);
     return check();
 }
 

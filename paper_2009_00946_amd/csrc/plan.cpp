@@ -62,6 +62,47 @@ void wt_cone(int y0, int x0, int T0, int J, int *loY, int *loX, int *LY, int *LX
     }
 }
 
+// Byte offsets of every workspace region (tables once; per-frame state max_batch times).
+void layout_workspace(Plan *P) {
+    size_t o = 0;
+    const size_t MB = size_t(P->max_batch);  // frames with their own vectors, partials and scalars
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    const size_t E = P->elem, N = P->n_coef;
+    P->o_wfs = take(sizeof(DevWfs) * P->nw);
+    P->o_lay = take(sizeof(DevLayer) * P->nl);
+    P->o_proj = take(sizeof(DevProj) * P->nw * P->nl);
+    P->o_dm = take(sizeof(DevDm) * P->nd);
+    const size_t ent = P->prec == FEWHA_FP64 ? 24 : 16;
+    P->o_xtab = take(ent * P->nw * P->nl * P->maxnv);
+    P->o_ytab = take(ent * P->nw * P->nl * P->maxnv);
+    P->o_xrng = take(sizeof(Range) * P->nw * P->sum_n);
+    P->o_yrng = take(sizeof(Range) * P->nw * P->sum_n);
+    P->o_xrtab = take((P->prec == FEWHA_FP64 ? 16 : 8) * size_t(kRtabWidth) * P->nw * P->sum_n);
+    P->o_yrtab = take((P->prec == FEWHA_FP64 ? 16 : 8) * size_t(kRtabWidth) * P->nw * P->sum_n);
+    P->o_rects = take(16 * size_t(P->n_pt) * P->nw);
+    P->o_jinv = take(E * P->nl * (P->J + 1) * 4);
+    P->o_ad = take(E * P->nl * (P->J + 1));
+    P->o_bprev = take(E * N * MB);
+    P->o_r = take(E * N * MB);
+    P->o_p = take(E * N * MB);
+    P->o_q = take(E * N * MB);
+    P->o_u = take(E * N * MB);
+    P->o_x = take(E * N * MB);
+    P->o_v = take(E * P->n_nodes * MB);
+    P->o_ll = take(E * (N / 4 + 1) * MB);
+    P->o_probe_c = take(E * N);
+    P->o_stage = take(4 * E * N);  // stage timing: scratch r, p, q, c
+    P->o_probe_s = take(E * P->n_slopes);
+    P->o_over = take(sizeof(int) * P->nw);
+    P->o_partials = take(sizeof(double) * 3 * kPartialPitch * MB);
+    P->o_scalars = take(kScalarSlots * sizeof(Scalars) * MB);
+    P->ws_bytes = o;
+}
+
 int plan_create(const fewha_config *cfg, Plan **out) {
     if (!cfg || !out) return FEWHA_ERR_INVALID_ARG;
     *out = nullptr;
@@ -306,43 +347,7 @@ int plan_create(const fewha_config *cfg, Plan **out) {
         return FEWHA_ERR_UNSUPPORTED;
     }
 
-    // workspace map
-    size_t o = 0;
-    auto take = [&](size_t bytes) {
-        size_t at = o;
-        o = align256(o + bytes);
-        return at;
-    };
-    const size_t E = P->elem, N = P->n_coef;
-    P->o_wfs = take(sizeof(DevWfs) * P->nw);
-    P->o_lay = take(sizeof(DevLayer) * P->nl);
-    P->o_proj = take(sizeof(DevProj) * P->nw * P->nl);
-    P->o_dm = take(sizeof(DevDm) * P->nd);
-    const size_t ent = P->prec == FEWHA_FP64 ? 24 : 16;
-    P->o_xtab = take(ent * P->nw * P->nl * P->maxnv);
-    P->o_ytab = take(ent * P->nw * P->nl * P->maxnv);
-    P->o_xrng = take(sizeof(Range) * P->nw * P->sum_n);
-    P->o_yrng = take(sizeof(Range) * P->nw * P->sum_n);
-    P->o_xrtab = take((P->prec == FEWHA_FP64 ? 16 : 8) * size_t(kRtabWidth) * P->nw * P->sum_n);
-    P->o_yrtab = take((P->prec == FEWHA_FP64 ? 16 : 8) * size_t(kRtabWidth) * P->nw * P->sum_n);
-    P->o_rects = take(16 * size_t(P->n_pt) * P->nw);
-    P->o_jinv = take(E * P->nl * (P->J + 1) * 4);
-    P->o_ad = take(E * P->nl * (P->J + 1));
-    P->o_bprev = take(E * N);
-    P->o_r = take(E * N);
-    P->o_p = take(E * N);
-    P->o_q = take(E * N);
-    P->o_u = take(E * N);
-    P->o_x = take(E * N);
-    P->o_v = take(E * P->n_nodes);
-    P->o_ll = take(E * (N / 4 + 1));
-    P->o_probe_c = take(E * N);
-    P->o_stage = take(4 * E * N);  // stage timing: scratch r, p, q, c
-    P->o_probe_s = take(E * P->n_slopes);
-    P->o_over = take(sizeof(int) * P->nw);
-    P->o_partials = take(sizeof(double) * 3 * kPartialPitch);
-    P->o_scalars = take(4 * sizeof(Scalars));
-    P->ws_bytes = o;
+    layout_workspace(P);
     *out = P;
     return FEWHA_OK;
 }

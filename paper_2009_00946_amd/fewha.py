@@ -20,7 +20,8 @@ EXPORTS = ["fewha_plan_create", "fewha_workspace_bytes", "fewha_plan_bind", "few
            "fewha_apply_A", "fewha_apply_At", "fewha_apply_M", "fewha_dwt_forward", "fewha_dwt_inverse",
            "fewha_pcg_solve", "fewha_fit_dm", "fewha_state_get", "fewha_state_set", "fewha_precond_table",
            "fewha_last_status", "fewha_stage_launch", "fewha_strerror", "fewha_solve_M", "fewha_apply_CA",
-           "fewha_prior_dot"]
+           "fewha_prior_dot", "fewha_plan_set_batch", "fewha_apply_A_batch", "fewha_apply_At_batch",
+           "fewha_apply_M_batch", "fewha_pcg_solve_batch", "fewha_fit_dm_batch", "fewha_last_status_batch"]
 
 
 class FewhaError(RuntimeError):
@@ -72,6 +73,12 @@ def load_library():
                  "fewha_state_get", "fewha_state_set", "fewha_apply_CA"):
         getattr(L, name).argtypes = [vp, vp, vp, vp]
     L.fewha_solve_M.argtypes = [vp, vp, vp, ctypes.c_int, vp, vp]
+    L.fewha_plan_set_batch.argtypes = [vp, ctypes.c_int]
+    for name in ("fewha_apply_A_batch", "fewha_apply_At_batch", "fewha_apply_M_batch"):
+        getattr(L, name).argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    L.fewha_pcg_solve_batch.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, ctypes.c_int, vp, vp]
+    L.fewha_fit_dm_batch.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_double, vp, vp]
+    L.fewha_last_status_batch.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     L.fewha_prior_dot.argtypes = [vp, vp, vp, vp, vp]
     L.fewha_pcg_solve.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, vp]
     L.fewha_fit_dm.argtypes = [vp, vp, vp, ctypes.c_double, vp, vp]
@@ -119,7 +126,7 @@ class Plan:
     contiguous CUDA tensors of ``self.dtype`` with the lengths of ``fewha_sizes``.
     """
 
-    def __init__(self, cfg, precision=None, device=None):
+    def __init__(self, cfg, precision=None, device=None, max_batch=1):
         import torch
         self._torch = torch
         L = load_library()
@@ -134,6 +141,9 @@ class Plan:
         nc, ns, na = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
         L.fewha_sizes(h, ctypes.byref(nc), ctypes.byref(ns), ctypes.byref(na))
         self.n_coef, self.n_slopes, self.n_act = nc.value, ns.value, na.value
+        self.max_batch = int(max_batch)
+        if self.max_batch != 1:
+            _check(L.fewha_plan_set_batch(h, self.max_batch), "fewha_plan_set_batch")
         nbytes = L.fewha_workspace_bytes(h)
         with torch.cuda.device(self.device):
             self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
@@ -238,6 +248,67 @@ class Plan:
         _check(_lib.fewha_prior_dot(self._h, self._arg(x, self.n_coef, "x"), self._arg(y, self.n_coef, "y"),
                                     out.data_ptr(), self._stream()), "fewha_prior_dot")
         return out
+
+    # -- batches of frames (one launch per stage over every frame; tensors [nbatch][length]) ---------
+    def _batch(self, t, n, name):
+        if t.dim() != 2 or t.shape[1] != n or not (1 <= t.shape[0] <= self.max_batch):
+            raise ValueError("%s: expected [nbatch <= %d][%d], got %s" % (name, self.max_batch, n, tuple(t.shape)))
+        self._arg(t, t.numel(), name)
+        return t.shape[0]
+
+    def apply_A_batch(self, c, out=None):
+        nb = self._batch(c, self.n_coef, "c")
+        s = out if out is not None else self._torch.empty((nb, self.n_slopes), dtype=self.dtype, device=self.device)
+        self._batch(s, self.n_slopes, "s")
+        _check(_lib.fewha_apply_A_batch(self._h, nb, c.data_ptr(), s.data_ptr(), self._stream()), "fewha_apply_A_batch")
+        return s
+
+    def apply_At_batch(self, s, out=None):
+        nb = self._batch(s, self.n_slopes, "s")
+        c = out if out is not None else self._torch.empty((nb, self.n_coef), dtype=self.dtype, device=self.device)
+        self._batch(c, self.n_coef, "c")
+        _check(_lib.fewha_apply_At_batch(self._h, nb, s.data_ptr(), c.data_ptr(), self._stream()), "fewha_apply_At_batch")
+        return c
+
+    def apply_M_batch(self, c, out=None):
+        nb = self._batch(c, self.n_coef, "c")
+        y = out if out is not None else self._torch.empty((nb, self.n_coef), dtype=self.dtype, device=self.device)
+        self._batch(y, self.n_coef, "y")
+        _check(_lib.fewha_apply_M_batch(self._h, nb, c.data_ptr(), y.data_ptr(), self._stream()), "fewha_apply_M_batch")
+        return y
+
+    def pcg_solve_batch(self, s, c, n_iter, warm=True, resnorm=None):
+        """Frames f = 0..nbatch-1 (s [nbatch][n_slopes], c [nbatch][n_coef] updated in place), one
+        launch per stage; frame f continues its own warm-restart chain."""
+        nb = self._batch(s, self.n_slopes, "s")
+        if self._batch(c, self.n_coef, "c") != nb:
+            raise ValueError("s and c: different batch sizes")
+        rp = None
+        if resnorm is not None:
+            if not resnorm.is_cuda or resnorm.dtype != self._torch.float64 or resnorm.numel() < nb * n_iter:
+                raise ValueError("resnorm: float64 CUDA tensor of nbatch * n_iter elements expected")
+            rp = resnorm.data_ptr()
+        _check(_lib.fewha_pcg_solve_batch(self._h, nb, s.data_ptr(), c.data_ptr(), int(n_iter),
+                                          FEWHA_WARM if warm else FEWHA_COLD, rp, self._stream()),
+               "fewha_pcg_solve_batch")
+        return c
+
+    def fit_dm_batch(self, c, a_prev=None, gain=1.0, out=None):
+        nb = self._batch(c, self.n_coef, "c")
+        a = out if out is not None else self._torch.empty((nb, self.n_act), dtype=self.dtype, device=self.device)
+        self._batch(a, self.n_act, "a")
+        ap = None
+        if a_prev is not None:
+            self._batch(a_prev, self.n_act, "a_prev")
+            ap = a_prev.data_ptr()
+        _check(_lib.fewha_fit_dm_batch(self._h, nb, c.data_ptr(), ap, float(gain), a.data_ptr(), self._stream()),
+               "fewha_fit_dm_batch")
+        return a
+
+    def last_status_batch(self, nbatch):
+        out = (ctypes.c_int * nbatch)()
+        _check(_lib.fewha_last_status_batch(self._h, int(nbatch), out), "fewha_last_status_batch")
+        return list(out)
 
     def fit_dm(self, c, a_prev=None, gain=1.0, out=None):
         a = self._out(out, self.n_act)
