@@ -171,6 +171,115 @@ def cpu_baseline(cfg, frames_s, n_iter, budget_s):
                       "median per frame" % (len(times), n_iter)}
 
 
+# The batched uneven workload: 64 independent FP32 frames of three geometries, 4 PCG passes each,
+# warm chains.  Each geometry is one batched plan (one launch per stage over all its frames).
+C3_GROUPS = (("c0_tiny", 32, "all guide stars"), ("c3_mid_lgs", 24, "all guide stars"),
+             ("c1_elt_mcao", 8, "LGS only"))
+
+
+def c3_configs():
+    import copy
+    from paper_2009_00946_amd import synth
+    out = []
+    for name, count, which in C3_GROUPS:
+        cfg = copy.deepcopy(synth.load_config(name))
+        cfg["precision"], cfg["n_iter"], cfg["warm"] = "fp32", 4, True
+        if which == "LGS only":
+            cfg["wfs"] = [w for w in cfg["wfs"] if w["gs_height"] > 0]
+            cfg["name"] = name + "_lgs"
+        out.append((cfg, count))
+    return out
+
+
+def c3_batch(args):
+    """ms per batch of 64 uneven frames: each geometry's frames in one batched plan, the three
+    plans one after the other in one HIP graph; beside it the same frames one at a time."""
+    import torch
+    from paper_2009_00946_amd import fewha, synth
+    torch.cuda.set_device(0)
+    groups = []
+    for cfg, count in c3_configs():
+        PB = fewha.Plan(cfg, max_batch=count)
+        P1 = fewha.Plan(cfg)
+        # synthetic slopes through the plan's own forward operator (seeded), resident in HBM
+        S = []
+        for f in range(count):
+            phi = torch.as_tensor(synth.layer_screens_flat(cfg, f), dtype=PB.dtype, device=PB.device)
+            s = P1.apply_A(P1.dwt_forward(phi))
+            s += torch.as_tensor(synth.slope_noise(cfg, f), dtype=PB.dtype, device=PB.device)
+            S.append(s)
+        sb = torch.stack(S).contiguous()
+        cb = torch.zeros((count, PB.n_coef), dtype=PB.dtype, device=PB.device)
+        ab = torch.zeros((count, PB.n_act), dtype=PB.dtype, device=PB.device)
+        c1 = P1.zeros(P1.n_coef)
+        a1 = P1.zeros(P1.n_act)
+        groups.append(dict(cfg=cfg, count=count, PB=PB, P1=P1, S=S, sb=sb, cb=cb, ab=ab, c1=c1, a1=a1))
+    n_iter = 4
+
+    def batched(warm=True):
+        for g in groups:
+            g["PB"].pcg_solve_batch(g["sb"], g["cb"], n_iter, warm=warm)
+            g["PB"].fit_dm_batch(g["cb"], gain=1.0, out=g["ab"])
+
+    def single(warm=True):
+        for g in groups:
+            for f in range(g["count"]):
+                g["P1"].pcg_solve(g["S"][f], g["c1"], n_iter, warm=warm)
+                g["P1"].fit_dm(g["c1"], gain=1.0, out=g["a1"])
+
+    def capture(fn):
+        fn(warm=False)
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        cap = torch.cuda.Stream()
+        cap.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.graph(g, stream=cap):
+            fn()
+        torch.cuda.current_stream().wait_stream(cap)
+        torch.cuda.synchronize()
+        return g
+
+    def time_graph(g, steps):
+        for _ in range(args.warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    gb = capture(batched)
+    ms_b = time_graph(gb, args.steps)
+    for g in groups:
+        assert g["PB"].last_status_batch(g["count"]) == [0] * g["count"]
+    gs = capture(single)
+    ms_s = time_graph(gs, max(args.steps // 10, 5))
+    total_bytes = sum(byte_model(g["cfg"], 4, n_iter)["frame"] * g["count"] for g in groups)
+    frames = sum(g["count"] for g in groups)
+    gbps = total_bytes / (ms_b * 1e-3) / 1e9
+    out = {
+        "metric": "ms per batch of 64 uneven frames (fixed PCG iters) + effective HBM GB/s vs peak",
+        "value": round(ms_b, 5), "unit": "ms/batch", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_b, 5), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "c3_batched_uneven: " + ", ".join(
+            "%d x %s (%s)" % (g["count"], g["cfg"]["name"], n) for g, (_, _, n) in zip(groups, C3_GROUPS)),
+            "n_iter": n_iter, "warm": True, "frames": frames, "launch": "hip_graph_per_batch"},
+        "ms_per_frame": round(ms_b / frames, 5),
+        "bytes_per_batch": total_bytes,
+        "effective_GBps": round(gbps, 1),
+        "frac_hbm_peak": round(gbps / HBM_PEAK_GBPS, 4),
+        "unbatched_ms_per_batch": round(ms_s, 5),
+        "batching_speedup": round(ms_s / ms_b, 2),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,6 +291,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eager", action="store_true", help="launch kernels one by one instead of replaying HIP graphs")
     ap.add_argument("--stage-reps", type=int, default=50, help="launches per PCG-pass stage in its timing graph")
+    ap.add_argument("--workload", default="frame", choices=("frame", "c3_batch"),
+                    help="frame: the ELT frame (default); c3_batch: 64 uneven frames in batched launches")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run plain 256 MiB device copies (reference dispatches for HBM counters)")
     args = ap.parse_args()
@@ -189,6 +300,10 @@ def main():
         print("bench.py: this build runs the single-GPU hot path only; multi-GPU runs are not provided "
               "(frames would shard across GPUs with no exchange)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "c3_batch":
+        c3_batch(args)
+        return
 
     import torch
     from paper_2009_00946_amd import fewha, synth
