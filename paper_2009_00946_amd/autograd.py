@@ -15,18 +15,21 @@ only wires them into autograd:
   on layer l.  These are exact for the converged solution; with few passes they are the gradients
   of the limit the passes approach.
 
-Inputs are 1-D tensors of the plan's lengths, or 2-D batches (one row per frame), applied row by
-row.  The reconstruction runs cold and overwrites the plan's warm-restart state.
+Inputs are 1-D tensors of the plan's lengths, or 2-D batches (one row per vector): one batched
+launch per stage when the plan holds that many frames (``max_batch``), else row by row.  The
+reconstruction runs cold and overwrites the plan's warm-restart state.
 """
 import torch
 
 __all__ = ["apply_A", "apply_At", "apply_M", "reconstruct"]
 
 
-def _rows(fn, x, n_out, plan):
+def _rows(fn, fn_batch, x, n_out, plan):
     x = x.contiguous()
     if x.dim() == 1:
         return fn(x)
+    if x.shape[0] <= plan.max_batch:  # one launch per stage over the whole batch
+        return fn_batch(x)
     out = torch.empty((x.shape[0], n_out), dtype=plan.dtype, device=plan.device)
     for i in range(x.shape[0]):
         fn(x[i], out=out[i])
@@ -37,7 +40,7 @@ class _A(torch.autograd.Function):
     @staticmethod
     def forward(ctx, c, plan):
         ctx.plan = plan
-        return _rows(plan.apply_A, c, plan.n_slopes, plan)
+        return _rows(plan.apply_A, plan.apply_A_batch, c, plan.n_slopes, plan)
 
     @staticmethod
     def backward(ctx, g):
@@ -48,7 +51,7 @@ class _At(torch.autograd.Function):
     @staticmethod
     def forward(ctx, s, plan):
         ctx.plan = plan
-        return _rows(plan.apply_At, s, plan.n_coef, plan)
+        return _rows(plan.apply_At, plan.apply_At_batch, s, plan.n_coef, plan)
 
     @staticmethod
     def backward(ctx, g):
@@ -59,7 +62,7 @@ class _M(torch.autograd.Function):
     @staticmethod
     def forward(ctx, c, plan):
         ctx.plan = plan
-        return _rows(plan.apply_M, c, plan.n_coef, plan)
+        return _rows(plan.apply_M, plan.apply_M_batch, c, plan.n_coef, plan)
 
     @staticmethod
     def backward(ctx, g):

@@ -142,21 +142,31 @@ def test_reconstruction_gradients(name, prec, tol):
     check(host(s.grad), O.slope_weights() * O.A(lam), tol, "dL/ds")
 
 
-def test_autograd_timing():
-    """Reported, not bounded: forward + backward of A on a batch of 8 ELT coefficient vectors."""
-    from paper_2009_00946_amd import autograd as ag
-    P = plan("c1_elt_mcao", "fp32")
-    c = torch.randn(8, P.n_coef, device=P.device).requires_grad_(True)
-    w = torch.randn(8, P.n_slopes, device=P.device)
-    for _ in range(3):
-        (ag.apply_A(P, c) * w).sum().backward()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    reps = 20
-    for _ in range(reps):
+def test_batched_plan_autograd_and_timing():
+    """A batched plan (one launch per stage over the 8 rows) gives the row-by-row results
+    bitwise; forward + backward of A on 8 ELT vectors is timed both ways (reported)."""
+    from paper_2009_00946_amd import autograd as ag, fewha
+    P1 = plan("c1_elt_mcao", "fp32")
+    PB = fewha.Plan(synth.load_config("c1_elt_mcao"), max_batch=8)
+    c = torch.randn(8, P1.n_coef, device=P1.device).requires_grad_(True)
+    w = torch.randn(8, P1.n_slopes, device=P1.device)
+    grads = []
+    for P in (P1, PB):
         c.grad = None
         (ag.apply_A(P, c) * w).sum().backward()
-    e1.record()
-    torch.cuda.synchronize()
-    print("[timing] A forward+backward, batch 8, ELT FP32: %.3f ms" % (e0.elapsed_time(e1) / reps), flush=True)
+        grads.append(c.grad.clone())
+    assert torch.equal(grads[0], grads[1])
+    for P, what in ((P1, "row by row"), (PB, "batched")):
+        for _ in range(3):
+            (ag.apply_A(P, c) * w).sum().backward()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        reps = 20
+        for _ in range(reps):
+            c.grad = None
+            (ag.apply_A(P, c) * w).sum().backward()
+        e1.record()
+        torch.cuda.synchronize()
+        print("[timing] A forward+backward, 8 ELT vectors FP32, %s: %.3f ms" % (what, e0.elapsed_time(e1) / reps),
+              flush=True)
