@@ -351,9 +351,6 @@ __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src,
     if (MODE == kWtPcg && tid < (J + 1) * 4) sJi[tid] = jl;
     lds_fence();
 
-    // PCG: (r, z) and (z, alpha D z) over the coefficients this tile owns.  At level s the owned
-    // indices form a contiguous run inside the staged region of every band (rows oy0 - loY_s ..,
-    // columns ox0 - loX_s ..), so the lanes sweep (band, row, column) of the owned blocks.
     // ---- synthesis, coarsest level first, all in LDS.  Levels are unrolled so that every
     // region pitch is the compile-time power of two of its level (LL_s below J and the y-pass
     // outputs use the level's pitch too).  In PCG mode the cone holds r: the band scales J^-1
@@ -1023,9 +1020,14 @@ __global__ __launch_bounds__((FwdLanes<KF, TQ>::block)) void k_fwd(SegTab S, con
 // operands before its analysis.  Dynamic LDS: m0^2 + (m0/2)^2 (+ NOP m0^2 with `pre`) values.
 // With `gin` (a block too large for LDS) level KF+1 reads the approximation from global memory
 // and the LDS holds only the smaller levels: (m0/4)^2 + (m0/2)^2 values.
-template <typename T, int EPI>
-__global__ __launch_bounds__(kCB) void k_coarse(LayTab LT, Bufs<T> B, FwdArgs E, Taps<T> tp, int J, int KF, int nfine,
-                                                int pre, int gin) {
+// Operand modes of the coarse levels (compile time, so that the staged mode's level loop holds no
+// global-memory waits): operands staged in LDS | loaded per level | loaded per level, with level
+// KF+1 reading the approximation from global memory.
+enum { kCoarseStaged = 0, kCoarseDirect = 1, kCoarseGlobalIn = 2 };
+
+template <typename T, int EPI, int CM>
+__global__ __launch_bounds__(kCB) void k_coarse(LayTab LT, Bufs<T> B, FwdArgs E, Taps<T> tp, int J, int KF, int nfine) {
+    constexpr bool pre = CM == kCoarseStaged && EpiOps<EPI>::n > 0, gin = CM == kCoarseGlobalIn;
     extern __shared__ char smem_raw[];
     constexpr int NOP = EpiOps<EPI>::n, NL = 16;
     B = at_frame(B);
@@ -1034,7 +1036,11 @@ __global__ __launch_bounds__(kCB) void k_coarse(LayTab LT, Bufs<T> B, FwdArgs E,
     const long coff = LT.off[l];
     T *cs = reinterpret_cast<T *>(smem_raw), *cd = cs + (gin ? mm / 16 : mm), *opl = cd + mm / 4;
     const T *__restrict__ llin = B.ll + (coff >> (2 * KF));
-    if (!gin) {
+    // prior weight and Jacobi factor values for the LDS table below, requested first (every lane,
+    // clamped) so that waiting for them does not wait for the block copies issued after them
+    const T adv = EPI != kEpiPlain ? B.ad[l * (J + 1) + min(tid, J)] : (T)0;
+    const T jiv = (EPI == kEpiPcg || EPI == kEpiRhs) ? B.jinv[l * (J + 1) * 4 + min(tid, 4 * (J + 1) - 1)] : (T)0;
+    if constexpr (!gin) {
 #pragma unroll
         for (int c = 0; c < NL; ++c) {
             const int k = tid + c * kCB;
@@ -1044,7 +1050,7 @@ __global__ __launch_bounds__(kCB) void k_coarse(LayTab LT, Bufs<T> B, FwdArgs E,
             }
         }
     }
-    if (NOP > 0 && pre) {
+    if constexpr (pre) {
         // operand j of block element (r, c) -> opl[j * mm + r * m0 + c]
         const T *srcs[4] = {nullptr, nullptr, nullptr, nullptr};
         int nsrc = 0;
@@ -1080,8 +1086,8 @@ __global__ __launch_bounds__(kCB) void k_coarse(LayTab LT, Bufs<T> B, FwdArgs E,
     }
     // prior weights and Jacobi factors of the layer's levels: [s] = alpha D, [kMaxJ + 1 + 4 s + o] = J^-1
     __shared__ T sW[5 * (kMaxJ + 1)];
-    if (EPI != kEpiPlain && tid <= J) sW[tid] = B.ad[l * (J + 1) + tid];
-    if ((EPI == kEpiPcg || EPI == kEpiRhs) && tid < 4 * (J + 1)) sW[kMaxJ + 1 + tid] = B.jinv[l * (J + 1) * 4 + tid];
+    if (EPI != kEpiPlain && tid <= J) sW[tid] = adv;
+    if ((EPI == kEpiPcg || EPI == kEpiRhs) && tid < 4 * (J + 1)) sW[kMaxJ + 1 + tid] = jiv;
     StepOut so{0.0, 0.0, 0};
     if constexpr (EPI == kEpiPcg) so = read_step(B.sc);
     lds_fence();
@@ -1104,7 +1110,7 @@ __global__ __launch_bounds__(kCB) void k_coarse(LayTab LT, Bufs<T> B, FwdArgs E,
                 for (int o = 0; o < 4; ++o) {
                     if (o > 0 || s == J) {
                         const int br = r + (o >= 2 ? h : 0), bc = q + ((o & 1) ? h : 0);
-                        if (pre) {
+                        if constexpr (pre) {
 #pragma unroll
                             for (int j = 0; j < (NOP > 0 ? NOP : 1); ++j) op[o][j] = opl[j * mm + br * m0 + bc];
                             if (EPI == kEpiPcg && E.k == 0) op[o][2] = op[o][3] = (T)0;
@@ -1134,8 +1140,12 @@ __global__ __launch_bounds__(kCB) void k_coarse(LayTab LT, Bufs<T> B, FwdArgs E,
                         w[3] += tp.g[a] * dx;
                     }
                 };
-                if (gin && s == KF + 1) analyse_wrap(llin);
-                else analyse_wrap(cs);
+                if constexpr (gin) {
+                    if (s == KF + 1) analyse_wrap(llin);
+                    else analyse_wrap(cs);
+                } else {
+                    analyse_wrap(cs);
+                }
 #pragma unroll
                 for (int o = 1; o < 4; ++o) epi_store<T, EPI>(B, E, band_index(coff, n, s, o, r, q), w[o], op[o], ji[o], ad, so, rho, dz);
                 if (s == J) epi_store<T, EPI>(B, E, band_index(coff, n, s, 0, r, q), w[0], op[0], ji[0], ad, so, rho, dz);
@@ -1463,7 +1473,11 @@ static int fwd_launch(const Plan &P, const Bufs<T> &B, hipStream_t st, int nb, c
         if (gin) base = (m * m / 16 + m * m / 4) * sizeof(T);
         if (base > kCoarseLdsMax) return FEWHA_ERR_UNSUPPORTED;
         const int pre = !gin && EpiOps<EPI>::n > 0 && base + opb <= kCoarseLdsMax ? 1 : 0;
-        k_coarse<T, EPI><<<dim3(P.nl, nb), kCB, base + (pre ? opb : 0), st>>>(P.laytab, B, E, tp, P.J, P.kf, nf, pre, gin);
+        const dim3 grid(P.nl, nb);
+        const size_t lds = base + (pre ? opb : 0);
+        if (pre) k_coarse<T, EPI, kCoarseStaged><<<grid, kCB, lds, st>>>(P.laytab, B, E, tp, P.J, P.kf, nf);
+        else if (gin) k_coarse<T, EPI, kCoarseGlobalIn><<<grid, kCB, lds, st>>>(P.laytab, B, E, tp, P.J, P.kf, nf);
+        else k_coarse<T, EPI, kCoarseDirect><<<grid, kCB, lds, st>>>(P.laytab, B, E, tp, P.J, P.kf, nf);
         if (int e = check()) return e;
     }
     return FEWHA_OK;
@@ -1482,9 +1496,12 @@ int Ops<T>::fwd(const T *x, const FwdArgs &E, int epi) const {
 template <typename T>
 int Ops<T>::prepare() const {
     // the per-layer coarse transform may need more than the default 64 KiB of dynamic LDS
-    const void *fns[4] = {(const void *)k_coarse<T, kEpiPlain>, (const void *)k_coarse<T, kEpiPrior>,
-                          (const void *)k_coarse<T, kEpiPcg>, (const void *)k_coarse<T, kEpiRhs>};
-    for (int i = 0; i < 4; ++i)
+#define FEWHA_COARSE3(EPI) (const void *)k_coarse<T, EPI, kCoarseStaged>, (const void *)k_coarse<T, EPI, kCoarseDirect>, \
+                           (const void *)k_coarse<T, EPI, kCoarseGlobalIn>
+    const void *fns[12] = {FEWHA_COARSE3(kEpiPlain), FEWHA_COARSE3(kEpiPrior), FEWHA_COARSE3(kEpiPcg),
+                           FEWHA_COARSE3(kEpiRhs)};
+#undef FEWHA_COARSE3
+    for (int i = 0; i < 12; ++i)
         if (hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCoarseLdsMax) != hipSuccess)
             return FEWHA_ERR_UNSUPPORTED;
     // staged P^T: the tile's transpose pairs and node rectangles
