@@ -603,6 +603,120 @@ void orc_fit(const orc_plan *P, const double *c, const double *a_prev, double ga
 }
 
 /* ------------------------------------------------------------------------------------ */
+/* Closed loop (Alg. 1): pseudo-open-loop slopes and the closed-loop control law.          */
+/* ------------------------------------------------------------------------------------ */
+/* DM m as the piecewise bilinear surface over its actuator grid (Sec. 4.1):
+ *   S_m(X, Y) = sum_ij a_m,ij hat((X - x_j) / p) hat((Y - y_i) / p),  hat(t) = max(0, 1 - |t|),
+ * actuator (i, j) at ((j - (n_a-1)/2) p, (i - (n_a-1)/2) p); zero beyond the outermost hats.
+ * Evaluated here by visiting every actuator whose hat support contains the point. */
+static double dm_surface(const orc_plan *P, int m, const double *a, double X, double Y)
+{
+    int na = P->dm[m].n_act;
+    double p = P->dm[m].pitch, c = (na - 1) / 2.0, acc = 0.0;
+    for (int i = 0; i < na; i++) {
+        double wy = 1.0 - fabs(Y / p - (i - c));
+        if (wy <= 0.0) continue;
+        for (int j = 0; j < na; j++) {
+            double wx = 1.0 - fabs(X / p - (j - c));
+            if (wx <= 0.0) continue;
+            acc += wx * wy * a[P->a_off[m] + (long)i * na + j];
+        }
+    }
+    return acc;
+}
+
+/* Where WFS node (i, j) of guide star g meets the altitude h (metres), as for a layer. */
+static void node_at_height(const orc_plan *P, int g, double h, int i, int j, double *X, double *Y)
+{
+    double d = subap(P, g), s = P->wfs[g].gs_height > 0 ? 1.0 - h / P->wfs[g].gs_height : 1.0;
+    *X = s * (-P->D / 2 + j * d) + P->wfs[g].theta_x * h;
+    *Y = s * (-P->D / 2 + i * d) + P->wfs[g].theta_y * h;
+}
+
+/* The DMs' correction as the sensors see it: s = mask Gamma_g sum_m P^DM_gm a_m (every ray passes
+ * through every DM).  Reading: Alg. 1 prints the pseudo-open-loop update as s + Gamma a^(-1),
+ * which leaves out the projection of the DM surfaces onto the sensor grids; it is read as this
+ * operator applied to a^(-1). */
+void orc_apply_Hdm(const orc_plan *P, const double *a, double *s)
+{
+    for (int g = 0; g < P->nw; g++) {
+        int ns = P->wfs[g].n_sub, nv = ns + 1;
+        double *phi = malloc(sizeof(double) * (size_t)nv * nv);
+        for (int i = 0; i < nv; i++)
+            for (int j = 0; j < nv; j++) {
+                double acc = 0.0;
+                for (int m = 0; m < P->nd; m++) {
+                    double X, Y;
+                    node_at_height(P, g, P->dm[m].height, i, j, &X, &Y);
+                    acc += dm_surface(P, m, a, X, Y);
+                }
+                phi[(long)i * nv + j] = acc;
+            }
+        double *sg = s + P->s_off[g];
+        orc_gamma(P, g, phi, sg);
+        for (int i = 0; i < ns; i++)
+            for (int j = 0; j < ns; j++)
+                if (!orc_active(P, g, i, j)) sg[(long)i * ns + j] = sg[(long)ns * ns + (long)i * ns + j] = 0.0;
+        free(phi);
+    }
+}
+
+/* Transpose of orc_apply_Hdm (for adjoint checks). */
+void orc_apply_Hdm_t(const orc_plan *P, const double *s, double *a)
+{
+    memset(a, 0, sizeof(double) * P->n_act);
+    for (int g = 0; g < P->nw; g++) {
+        int ns = P->wfs[g].n_sub, nv = ns + 1;
+        double *sm = malloc(sizeof(double) * 2 * (size_t)ns * ns), *phi = malloc(sizeof(double) * (size_t)nv * nv);
+        for (int i = 0; i < ns; i++)
+            for (int j = 0; j < ns; j++) {
+                int act = orc_active(P, g, i, j);
+                sm[(long)i * ns + j] = act ? s[P->s_off[g] + (long)i * ns + j] : 0.0;
+                sm[(long)ns * ns + (long)i * ns + j] = act ? s[P->s_off[g] + (long)ns * ns + (long)i * ns + j] : 0.0;
+            }
+        orc_gamma_t(P, g, sm, phi);
+        for (int i = 0; i < nv; i++)
+            for (int j = 0; j < nv; j++)
+                for (int m = 0; m < P->nd; m++) {
+                    int na = P->dm[m].n_act;
+                    double X, Y, p = P->dm[m].pitch, c = (na - 1) / 2.0;
+                    node_at_height(P, g, P->dm[m].height, i, j, &X, &Y);
+                    for (int ai = 0; ai < na; ai++) {
+                        double wy = 1.0 - fabs(Y / p - (ai - c));
+                        if (wy <= 0.0) continue;
+                        for (int aj = 0; aj < na; aj++) {
+                            double wx = 1.0 - fabs(X / p - (aj - c));
+                            if (wx > 0.0) a[P->a_off[m] + (long)ai * na + aj] += wx * wy * phi[(long)i * nv + j];
+                        }
+                    }
+                }
+        free(sm);
+        free(phi);
+    }
+}
+
+/* Pseudo-open-loop slopes of Alg. 1: s_pol = mask (s + H_dm a^(-1)). */
+void orc_pol(const orc_plan *P, const double *s, const double *a_m1, double *s_pol)
+{
+    orc_apply_Hdm(P, a_m1, s_pol);
+    double *m = malloc(sizeof(double) * P->n_slopes);
+    orc_slope_mask(P, m);
+    for (long k = 0; k < P->n_slopes; k++) s_pol[k] = m[k] * (s[k] + s_pol[k]);
+    free(m);
+}
+
+/* Closed-loop control of Alg. 1: a^(1) = a^(0) + gain (F W^T c - a^(-1)). */
+void orc_fit_closed(const orc_plan *P, const double *c, const double *a0, const double *a_m1, double gain, double *a)
+{
+    double *lay = malloc(sizeof(double) * P->n_coef), *at = malloc(sizeof(double) * P->n_act);
+    orc_Wt(P, c, lay);
+    orc_fit_interp(P, lay, at);
+    for (long k = 0; k < P->n_act; k++) a[k] = a0[k] + gain * (at[k] - a_m1[k]);
+    free(lay);
+    free(at);
+}
+
+/* ------------------------------------------------------------------------------------ */
 /* Plan: copy the configuration, check the geometry, lay out the vectors.                 */
 /* ------------------------------------------------------------------------------------ */
 void orc_destroy(orc_plan *P)

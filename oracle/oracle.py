@@ -56,7 +56,8 @@ def _load():
         L.orc_destroy.argtypes = [ctypes.c_void_p]
         L.orc_sizes.argtypes = [ctypes.c_void_p, _lp]
         for name in ("orc_W", "orc_Wt", "orc_P", "orc_Pt", "orc_apply_Ahat", "orc_apply_Ahat_t", "orc_apply_A",
-                     "orc_apply_At", "orc_rhs", "orc_apply_M", "orc_fit_interp", "orc_fit_interp_t"):
+                     "orc_apply_At", "orc_rhs", "orc_apply_M", "orc_fit_interp", "orc_fit_interp_t", "orc_apply_Hdm",
+                     "orc_apply_Hdm_t"):
             getattr(L, name).argtypes = [ctypes.c_void_p, _dp, _dp]
         for name in ("orc_slope_mask", "orc_slope_weights", "orc_prior", "orc_precond"):
             getattr(L, name).argtypes = [ctypes.c_void_p, _dp]
@@ -67,6 +68,8 @@ def _load():
         L.orc_pcg.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_int, _dp, _ip]
         L.orc_frame.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int, _dp]
         L.orc_fit.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double, _dp]
+        L.orc_pol.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
+        L.orc_fit_closed.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, ctypes.c_double, _dp]
         L.orc_db3.argtypes = [_dp]
         L.orc_dwt1_fwd.argtypes = [_dp, _dp, ctypes.c_int]
         L.orc_dwt1_inv.argtypes = [_dp, _dp, ctypes.c_int]
@@ -170,6 +173,21 @@ class Oracle:
     def M(self, c): return self._call("orc_apply_M", c, self.n_coef, self.n_coef)
     def fit_interp(self, layers): return self._call("orc_fit_interp", layers, self.n_coef, self.n_act)
     def fit_interp_t(self, a): return self._call("orc_fit_interp_t", a, self.n_act, self.n_coef)
+    def Hdm(self, a): return self._call("orc_apply_Hdm", a, self.n_act, self.n_slopes)
+    def Hdm_t(self, s): return self._call("orc_apply_Hdm_t", s, self.n_slopes, self.n_act)
+
+    def pol(self, s, a_m1):
+        """Pseudo-open-loop slopes of Alg. 1 (closed loop): mask (s + H_dm a^(-1))."""
+        out = np.zeros(self.n_slopes)
+        _lib.orc_pol(self._h, _p(_f64(s, self.n_slopes)), _p(_f64(a_m1, self.n_act)), _p(out))
+        return out
+
+    def fit_closed(self, c, a0, a_m1, gain):
+        """Closed-loop control of Alg. 1: a^(1) = a^(0) + gain (F W^T c - a^(-1))."""
+        a = np.zeros(self.n_act)
+        _lib.orc_fit_closed(self._h, _p(_f64(c, self.n_coef)), _p(_f64(a0, self.n_act)), _p(_f64(a_m1, self.n_act)),
+                            gain, _p(a))
+        return a
 
     def gamma(self, g, phi):
         ns = self.cfg["wfs"][g]["n_sub"]
