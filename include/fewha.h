@@ -175,6 +175,22 @@ int fewha_apply_CA(const fewha_plan *p, const void *d_c, void *d_s, void *stream
  * -(alpha D)_l / gamma_l on layer l and zero elsewhere. */
 int fewha_prior_dot(const fewha_plan *p, const void *d_x, const void *d_y, double *d_out, void *stream);
 
+/* Closed loop (Alg. 1).  Pseudo-open-loop slopes s_pol = mask (s + Gamma P_DM a_m1): the DMs'
+ * correction as the sensors see it added to the measured residual slopes, with a_m1 = a^(-1),
+ * the DM shape two frames back (two-step delay).  Alg. 1 prints the update as s + Gamma a^(-1);
+ * it is read with the projection P_DM of the DM surfaces onto the sensor grids: DM m is the
+ * piecewise bilinear surface over its actuators (Sec. 4.1; actuator (i, j) at ((j - (n_a-1)/2)
+ * pitch, (i - (n_a-1)/2) pitch), zero beyond the outermost actuators), met by each guide star's
+ * rays at the DM's altitude as a layer is (cone factor, shift).  Inactive slopes are written 0.
+ * d_s_pol may alias d_s. */
+int fewha_pol_slopes(const fewha_plan *p, const void *d_s, const void *d_a_m1, void *d_s_pol, void *stream);
+
+/* Closed-loop control of Alg. 1: a = a0 + gain (F W^T c - a_m1), with F the fitting of
+ * fewha_fit_dm, a0 = a^(0) and a_m1 = a^(-1).  d_a must alias neither d_c nor d_a_m1; it may
+ * alias d_a0. */
+int fewha_fit_dm_closed(const fewha_plan *p, const void *d_c, const void *d_a0, const void *d_a_m1, double gain,
+                        void *d_a, void *stream);
+
 /* Copy the warm-restart state (b_prev, r_prev; n_coef each) out of / into the workspace. */
 int fewha_state_get(const fewha_plan *p, void *d_b_prev, void *d_r_prev, void *stream);
 int fewha_state_set(fewha_plan *p, const void *d_b_prev, const void *d_r_prev, void *stream);
@@ -201,6 +217,10 @@ int fewha_pcg_solve_batch(fewha_plan *p, int nbatch, const void *d_s, void *d_c,
                           double *d_resnorm, void *stream);
 int fewha_fit_dm_batch(const fewha_plan *p, int nbatch, const void *d_c, const void *d_a_prev, double gain,
                        void *d_a, void *stream);
+int fewha_pol_slopes_batch(const fewha_plan *p, int nbatch, const void *d_s, const void *d_a_m1, void *d_s_pol,
+                           void *stream);
+int fewha_fit_dm_closed_batch(const fewha_plan *p, int nbatch, const void *d_c, const void *d_a0, const void *d_a_m1,
+                              double gain, void *d_a, void *stream);
 /* Status words of frames 0..nbatch-1 after the last enqueued solve (synchronises the device). */
 int fewha_last_status_batch(const fewha_plan *p, int nbatch, int *h_status);
 

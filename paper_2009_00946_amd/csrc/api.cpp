@@ -29,6 +29,8 @@ Bufs<T> bufs(const Plan &P) {
     b.xrtab = reinterpret_cast<const RtabEnt<T> *>(w + P.o_xrtab);
     b.yrtab = reinterpret_cast<const RtabEnt<T> *>(w + P.o_yrtab);
     b.rects = reinterpret_cast<const int4 *>(w + P.o_rects);
+    b.xdm = reinterpret_cast<const Ent<T> *>(w + P.o_xdm);
+    b.ydm = reinterpret_cast<const Ent<T> *>(w + P.o_ydm);
     b.maxnv = P.maxnv;
     b.sum_n = P.sum_n;
     b.jinv = reinterpret_cast<const T *>(w + P.o_jinv);
@@ -174,6 +176,22 @@ int fit_dm(const Plan &P, const void *c, const void *a_prev, double gain, void *
     return o.fit(o.B.u, static_cast<const T *>(a_prev), static_cast<T *>(a), gain);
 }
 
+// Pseudo-open-loop slopes: s_pol = mask (s + Gamma P_DM a^(-1)), the projection kernel run over the
+// DMs (their actuator grids as the "layers", their cell tables) with the input slopes added.
+template <typename T>
+int pol_slopes(const Plan &P, const void *s, const void *a_m1, void *s_pol, void *stream, int nb = 1) {
+    auto o = ops<T>(P, stream, nb);
+    return o.pol(static_cast<const T *>(a_m1), static_cast<const T *>(s), static_cast<T *>(s_pol));
+}
+
+template <typename T>
+int fit_closed(const Plan &P, const void *c, const void *a0, const void *a_m1, double gain, void *a, void *stream,
+               int nb = 1) {
+    auto o = ops<T>(P, stream, nb);
+    TRY(o.wt(static_cast<const T *>(c), o.B.u));
+    return o.fit(o.B.u, static_cast<const T *>(a0), static_cast<T *>(a), gain, static_cast<const T *>(a_m1));
+}
+
 template <typename T>
 int stage_launch(const Plan &P, int stage, void *stream) {
     auto o = ops<T>(P, stream);
@@ -211,6 +229,36 @@ int bind_tables(Plan &P, hipStream_t st) {
     std::vector<T> ad(nb);
     for (int k = 0; k < nb; ++k) ad[k] = (T)P.ad[k];
     HIPTRY(hipMemcpy(w + P.o_ad, ad.data(), sizeof(T) * nb, hipMemcpyHostToDevice));
+    // DM cells of every sensor node (closed loop): node j of guide star g meets DM m at
+    // X = sigma (x0 + j d) + theta h_m; the DM is the piecewise bilinear surface over its actuators,
+    // zero beyond the outermost ones, so actuator k carries the weight max(0, 1 - |u - k|) at
+    // u = X / pitch + (n_a - 1) / 2 (cells straddling the edge keep their inside actuator only)
+    {
+        const size_t ne = size_t(P.nw) * P.nd * P.maxnv;
+        std::vector<Ent<T>> xd(ne, Ent<T>{0, 0, (T)0, (T)0}), yd(ne, Ent<T>{0, 0, (T)0, (T)0});
+        for (int g = 0; g < P.nw; ++g)
+            for (int m = 0; m < P.nd; ++m) {
+                const DevWfs &W = P.dwfs[g];
+                const DevDm &Dm = P.ddm[m];
+                const double h = P.dm[m].height, H = P.wfs[g].gs_height;
+                const double sig = H > 0 ? 1.0 - h / H : 1.0;
+                for (int axis = 0; axis < 2; ++axis) {
+                    const double th = axis ? P.wfs[g].theta_y : P.wfs[g].theta_x;
+                    for (int j = 0; j < W.nv; ++j) {
+                        const double u = (sig * (W.x0 + j * W.d) + th * h) / Dm.pitch + Dm.centre;
+                        const int k0 = (int)std::floor(u), na = Dm.n_act;
+                        const double t = u - k0;
+                        Ent<T> e{0, 0, (T)0, (T)0};
+                        if (k0 >= 0 && k0 <= na - 2) e = Ent<T>{k0, 0, (T)(1.0 - t), (T)t};
+                        else if (k0 == -1) e = Ent<T>{0, 0, (T)t, (T)0};
+                        else if (k0 == na - 1) e = Ent<T>{na - 2, 0, (T)0, (T)(1.0 - t)};
+                        (axis ? yd : xd)[(size_t(g) * P.nd + m) * P.maxnv + j] = e;
+                    }
+                }
+            }
+        HIPTRY(hipMemcpy(w + P.o_xdm, xd.data(), sizeof(Ent<T>) * ne, hipMemcpyHostToDevice));
+        HIPTRY(hipMemcpy(w + P.o_ydm, yd.data(), sizeof(Ent<T>) * ne, hipMemcpyHostToDevice));
+    }
     const long N = (long)P.n_coef;
     TRY(o.prepare());
     HIPTRY(hipMemset(o.B.over, 0, sizeof(int) * P.nw));
@@ -415,6 +463,22 @@ int fewha_fit_dm(const fewha_plan *p, const void *d_c, const void *d_a_prev, dou
                                    : fit_dm<float>(p->p, d_c, d_a_prev, gain, d_a, stream);
 }
 
+int fewha_pol_slopes(const fewha_plan *p, const void *d_s, const void *d_a_m1, void *d_s_pol, void *stream) {
+    TRY(ready(p));
+    if (!d_s || !d_a_m1 || !d_s_pol || d_s_pol == d_a_m1) return FEWHA_ERR_INVALID_ARG;
+    return p->p.prec == FEWHA_FP64 ? pol_slopes<double>(p->p, d_s, d_a_m1, d_s_pol, stream)
+                                   : pol_slopes<float>(p->p, d_s, d_a_m1, d_s_pol, stream);
+}
+
+int fewha_fit_dm_closed(const fewha_plan *p, const void *d_c, const void *d_a0, const void *d_a_m1, double gain,
+                        void *d_a, void *stream) {
+    TRY(ready(p));
+    if (!d_c || !d_a0 || !d_a_m1 || !d_a || d_a == d_c || d_a == d_a_m1 || !std::isfinite(gain))
+        return FEWHA_ERR_INVALID_ARG;
+    return p->p.prec == FEWHA_FP64 ? fit_closed<double>(p->p, d_c, d_a0, d_a_m1, gain, d_a, stream)
+                                   : fit_closed<float>(p->p, d_c, d_a0, d_a_m1, gain, d_a, stream);
+}
+
 int fewha_plan_set_batch(fewha_plan *p, int max_batch) {
     if (!p || max_batch < 1 || max_batch > kMaxBatch) return FEWHA_ERR_INVALID_ARG;
     p->p.max_batch = max_batch;
@@ -464,6 +528,23 @@ int fewha_fit_dm_batch(const fewha_plan *p, int nbatch, const void *d_c, const v
     if (!d_c || !d_a || d_a == d_c || !std::isfinite(gain)) return FEWHA_ERR_INVALID_ARG;
     return p->p.prec == FEWHA_FP64 ? fit_dm<double>(p->p, d_c, d_a_prev, gain, d_a, stream, nbatch)
                                    : fit_dm<float>(p->p, d_c, d_a_prev, gain, d_a, stream, nbatch);
+}
+
+int fewha_pol_slopes_batch(const fewha_plan *p, int nbatch, const void *d_s, const void *d_a_m1, void *d_s_pol,
+                           void *stream) {
+    TRY(batch_ok(p, nbatch));
+    if (!d_s || !d_a_m1 || !d_s_pol || d_s_pol == d_a_m1) return FEWHA_ERR_INVALID_ARG;
+    return p->p.prec == FEWHA_FP64 ? pol_slopes<double>(p->p, d_s, d_a_m1, d_s_pol, stream, nbatch)
+                                   : pol_slopes<float>(p->p, d_s, d_a_m1, d_s_pol, stream, nbatch);
+}
+
+int fewha_fit_dm_closed_batch(const fewha_plan *p, int nbatch, const void *d_c, const void *d_a0, const void *d_a_m1,
+                              double gain, void *d_a, void *stream) {
+    TRY(batch_ok(p, nbatch));
+    if (!d_c || !d_a0 || !d_a_m1 || !d_a || d_a == d_c || d_a == d_a_m1 || !std::isfinite(gain))
+        return FEWHA_ERR_INVALID_ARG;
+    return p->p.prec == FEWHA_FP64 ? fit_closed<double>(p->p, d_c, d_a0, d_a_m1, gain, d_a, stream, nbatch)
+                                   : fit_closed<float>(p->p, d_c, d_a0, d_a_m1, gain, d_a, stream, nbatch);
 }
 
 int fewha_last_status_batch(const fewha_plan *p, int nbatch, int *h_status) {

@@ -151,6 +151,7 @@ struct Bufs {
     const Range *xrng, *yrng;         // [nw][sum_n]: sensor nodes touching each layer grid line
     const RtabEnt<T> *xrtab, *yrtab;  // [nw][sum_n][kRtabWidth]: the same as (node, weight) lists
     const int4 *rects;                // [P^T tile][nw]: node rows / columns a tile's lines touch
+    const Ent<T> *xdm, *ydm;          // [nw][nd][maxnv]: DM actuator cells of every sensor node (closed loop)
     int maxnv, sum_n;                 // table pitch, total grid lines
     const T *jinv;                    // [nl][J+1][4] inverse preconditioner per band
     const T *ad;                      // [nl][J+1] alpha D per level
@@ -181,6 +182,7 @@ struct Plan {
     // tile tables of the launches (kernel arguments)
     SegTab seg_wt{}, seg_pt{}, seg_fwd{}, seg_proj{};
     LayTab laytab{};
+    LayTab dmtab{};       // per DM: actuator offset and actuators per side
     int n_wt = 0, n_pt = 0, n_fwd = 0, n_proj = 0;  // workgroups of each launch
     int maxnv = 0, sum_n = 0;
     int kf = 1;           // forward-DWT levels done on tiles; the rest per layer in one workgroup
@@ -196,6 +198,7 @@ struct Plan {
     // workspace layout (byte offsets)
     size_t o_wfs = 0, o_lay = 0, o_proj = 0, o_dm = 0;
     size_t o_xtab = 0, o_ytab = 0, o_xrng = 0, o_yrng = 0, o_xrtab = 0, o_yrtab = 0, o_rects = 0;
+    size_t o_xdm = 0, o_ydm = 0;
     size_t o_jinv = 0, o_ad = 0, o_bprev = 0, o_r = 0, o_p = 0, o_q = 0, o_u = 0, o_x = 0, o_v = 0;
     size_t o_ll = 0, o_stage = 0, o_probe_c = 0, o_probe_s = 0, o_partials = 0, o_scalars = 0, o_over = 0;
     size_t ws_bytes = 0;

@@ -37,8 +37,8 @@ template <typename T>
 Taps<T> make_taps();
 
 // Node-tile modes: Gamma^T C Gamma P u (with the data-term partial) | mask Gamma P u |
-// C mask Gamma P u.
-enum { kProjM = 0, kProjA = 1, kProjCA = 2 };
+// C mask Gamma P u | mask (s + Gamma P_DM a) (pseudo-open-loop slopes; the DMs as the "layers").
+enum { kProjM = 0, kProjA = 1, kProjCA = 2, kProjPol = 3 };
 // Gamma^T modes: Gamma^T C s (right-hand side) | Gamma^T mask s (adjoint of A).
 enum { kGtRhs = 0, kGtAdj = 1 };
 
@@ -66,7 +66,8 @@ struct Ops {
     int pt(const T *v, T *x, const PassArgs &PA) const;   // x = P^T v (+ the scalar step of pass PA.k)
     int fwd(const T *x, const FwdArgs &E, int epi) const; // W x with an epilogue (all levels)
     int wnorm(const T *s) const;                          // sc[2].rho = sum C s^2
-    int fit(const T *u, const T *a_prev, T *a, double gain) const;
+    int fit(const T *u, const T *a_prev, T *a, double gain, const T *a_m1 = nullptr) const;  // a_m1: closed loop
+    int pol(const T *a_m1, const T *s, T *s_pol) const;   // s_pol = mask (s + Gamma P_DM a_m1)
     int prior_dot(const T *x, const T *y, double *out) const;  // out[l] = sum_layer x alpha D y
     int build_tables(int *over) const;                    // projection cell, transpose and rectangle tables
     int fill(T *x, long n, T val) const;

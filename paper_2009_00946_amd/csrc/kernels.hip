@@ -459,12 +459,13 @@ constexpr int kProjLch = 12;         // layers whose bilinear loads are in fligh
 constexpr int kProjEntSlots = (2 * kMaxLayers * kPR + kB - 1) / kB;
 
 // kProjM: v = Gamma^T C Gamma P u with the partial sum C (Gamma P u)^2 (Kernel 2 of the paper);
-// kProjA: s = mask Gamma P u; kProjCA: s = C mask Gamma P u.  phi = P u comes from the bilinear cell tables of the region's 16
+// kProjA: s = mask Gamma P u; kProjCA: s = C mask Gamma P u; kProjPol: s = mask (add + Gamma P u)
+// with the DMs' actuator grids and cell tables in place of the layers'.  phi = P u comes from the bilinear cell tables of the region's 16
 // rows and columns on every layer, staged in LDS; each lane then gathers its node's four
 // neighbours on kProjLch layers at a time and sums the layers in order.
 template <typename T, int MODE>
 __global__ __launch_bounds__(kB) void k_proj(SegTab S, LayTab LT, InvVar IV, PupilArgs pa, const T *__restrict__ u,
-                                             T *__restrict__ out, Bufs<T> B, int nl) {
+                                             T *__restrict__ out, const T *__restrict__ add, Bufs<T> B, int nl) {
     __shared__ int sK[2][kMaxLayers][kPR];
     __shared__ T sW0[2][kMaxLayers][kPR], sW1[2][kMaxLayers][kPR];
     __shared__ T sPhi[kPR * kPR];
@@ -472,15 +473,16 @@ __global__ __launch_bounds__(kB) void k_proj(SegTab S, LayTab LT, InvVar IV, Pup
     __shared__ double sRed[kB / 64];
 
     B = at_frame(B);
-    u += blockIdx.y * B.fs_c;
+    u += blockIdx.y * (MODE == kProjPol ? B.fs_a : B.fs_c);
     out += blockIdx.y * (MODE == kProjM ? B.fs_v : B.fs_s);
+    if (MODE == kProjPol) add += blockIdx.y * B.fs_s;
     const int tid = threadIdx.x;
     const TileId id = find_tile(S, xcd_tile(gridDim.x));
     const int g = id.seg, ns = id.n, tpr = id.lt;
     const int ti = id.loc / tpr, tj = id.loc - ti * tpr;
     const int i0 = ti * kProjTile, j0 = tj * kProjTile;
-    const Ent<T> *__restrict__ xt = B.xtab + (long)g * nl * B.maxnv;
-    const Ent<T> *__restrict__ yt = B.ytab + (long)g * nl * B.maxnv;
+    const Ent<T> *__restrict__ xt = (MODE == kProjPol ? B.xdm : B.xtab) + (long)g * nl * B.maxnv;
+    const Ent<T> *__restrict__ yt = (MODE == kProjPol ? B.ydm : B.ytab) + (long)g * nl * B.maxnv;
 
     // cell entries of the region's rows and columns on every layer: e = (l * 2 + axis) * 16 + idx
     {
@@ -548,7 +550,13 @@ __global__ __launch_bounds__(kB) void k_proj(SegTab S, LayTab LT, InvVar IV, Pup
             sy = (T)0.5 * ((p10 - p00) + (p11 - p01));
         }
         const bool own = aa >= 1 && bb >= 1 && ii < ns && jj < ns;
-        if (MODE != kProjM) {
+        if (MODE == kProjPol) {
+            if (own) {
+                const long ix = id.aux + (long)ii * ns + jj, iy = ix + (long)ns * ns;
+                out[ix] = act ? add[ix] + sx : (T)0;
+                out[iy] = act ? add[iy] + sy : (T)0;
+            }
+        } else if (MODE != kProjM) {
             const T wgt = MODE == kProjCA ? (T)IV.v[g] : (T)1;
             if (own) {
                 out[id.aux + (long)ii * ns + jj] = wgt * sx;
@@ -1201,9 +1209,11 @@ __global__ __launch_bounds__(kB) void k_sum_partials(const double *__restrict__ 
 // Fitting (bilinear on-axis sampling of the layers at the actuators of their DM) + gain.
 template <typename T>
 __global__ __launch_bounds__(kB) void k_fit(const T *__restrict__ u, const T *__restrict__ a_prev, T *__restrict__ a,
-                                            Bufs<T> B, int nl, int nd, long n_act, double gain) {
+                                            const T *__restrict__ a_m1, Bufs<T> B, int nl, int nd, long n_act,
+                                            double gain) {
     u += blockIdx.y * B.fs_c;
     if (a_prev) a_prev += blockIdx.y * B.fs_a;
+    if (a_m1) a_m1 += blockIdx.y * B.fs_a;
     a += blockIdx.y * B.fs_a;
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_act) return;
@@ -1223,7 +1233,8 @@ __global__ __launch_bounds__(kB) void k_fit(const T *__restrict__ u, const T *__
         acc += (wy0 * wx0) * U[0] + (wy0 * wx1) * U[1] + (wy1 * wx0) * U[L.n] + (wy1 * wx1) * U[L.n + 1];
     }
     const T prev = a_prev ? a_prev[i] : (T)0;
-    a[i] = (T)(1.0 - gain) * prev + (T)gain * acc;
+    if (a_m1) a[i] = prev + (T)gain * (acc - a_m1[i]);  // closed loop: a0 + gain (F W^T c - a^(-1))
+    else a[i] = (T)(1.0 - gain) * prev + (T)gain * acc;
 }
 
 // Cell tables: entry (g, l, j) of each axis from the ray geometry (setup, once per bind).
@@ -1418,11 +1429,18 @@ int Ops<T>::wt_pcg(const T *r, T *out) const {
 template <typename T>
 int Ops<T>::proj(const T *u, T *out, int mode) const {
     if (mode == kProjM)
-        k_proj<T, kProjM><<<dim3(P.n_proj, nb), kB, 0, st>>>(P.seg_proj, P.laytab, inv_var_tab(P), pupil(P), u, out, B, P.nl);
+        k_proj<T, kProjM><<<dim3(P.n_proj, nb), kB, 0, st>>>(P.seg_proj, P.laytab, inv_var_tab(P), pupil(P), u, out, nullptr, B, P.nl);
     else if (mode == kProjCA)
-        k_proj<T, kProjCA><<<dim3(P.n_proj, nb), kB, 0, st>>>(P.seg_proj, P.laytab, inv_var_tab(P), pupil(P), u, out, B, P.nl);
+        k_proj<T, kProjCA><<<dim3(P.n_proj, nb), kB, 0, st>>>(P.seg_proj, P.laytab, inv_var_tab(P), pupil(P), u, out, nullptr, B, P.nl);
     else
-        k_proj<T, kProjA><<<dim3(P.n_proj, nb), kB, 0, st>>>(P.seg_proj, P.laytab, inv_var_tab(P), pupil(P), u, out, B, P.nl);
+        k_proj<T, kProjA><<<dim3(P.n_proj, nb), kB, 0, st>>>(P.seg_proj, P.laytab, inv_var_tab(P), pupil(P), u, out, nullptr, B, P.nl);
+    return check();
+}
+
+template <typename T>
+int Ops<T>::pol(const T *a_m1, const T *s, T *s_pol) const {
+    k_proj<T, kProjPol><<<dim3(P.n_proj, nb), kB, 0, st>>>(P.seg_proj, P.dmtab, inv_var_tab(P), pupil(P), a_m1, s_pol, s,
+                                                           B, P.nd);
     return check();
 }
 
@@ -1524,8 +1542,8 @@ int Ops<T>::wnorm(const T *s) const {
 }
 
 template <typename T>
-int Ops<T>::fit(const T *u, const T *a_prev, T *a, double gain) const {
-    k_fit<T><<<dim3(grid_for((long)P.n_act), nb), kB, 0, st>>>(u, a_prev, a, B, P.nl, P.nd, (long)P.n_act, gain);
+int Ops<T>::fit(const T *u, const T *a_prev, T *a, double gain, const T *a_m1) const {
+    k_fit<T><<<dim3(grid_for((long)P.n_act), nb), kB, 0, st>>>(u, a_prev, a, a_m1, B, P.nl, P.nd, (long)P.n_act, gain);
     return check();
 }
 

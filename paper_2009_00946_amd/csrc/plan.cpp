@@ -84,6 +84,8 @@ void layout_workspace(Plan *P) {
     P->o_xrtab = take((P->prec == FEWHA_FP64 ? 16 : 8) * size_t(kRtabWidth) * P->nw * P->sum_n);
     P->o_yrtab = take((P->prec == FEWHA_FP64 ? 16 : 8) * size_t(kRtabWidth) * P->nw * P->sum_n);
     P->o_rects = take(16 * size_t(P->n_pt) * P->nw);
+    P->o_xdm = take(ent * P->nw * P->nd * P->maxnv);
+    P->o_ydm = take(ent * P->nw * P->nd * P->maxnv);
     P->o_jinv = take(E * P->nl * (P->J + 1) * 4);
     P->o_ad = take(E * P->nl * (P->J + 1));
     P->o_bprev = take(E * N * MB);
@@ -341,6 +343,10 @@ int plan_create(const fewha_config *cfg, Plan **out) {
     for (int l = 0; l < P->nl; ++l) {
         P->laytab.off[l] = int(P->dlay[l].c_off);
         P->laytab.n[l] = P->lay[l].n;
+    }
+    for (int m = 0; m < P->nd; ++m) {
+        P->dmtab.off[m] = int(P->ddm[m].a_off);
+        P->dmtab.n[m] = P->ddm[m].n_act;
     }
     if (P->n_fwd + P->nl > kPartialPitch || P->n_proj > kPartialPitch) {
         delete P;

@@ -21,7 +21,8 @@ EXPORTS = ["fewha_plan_create", "fewha_workspace_bytes", "fewha_plan_bind", "few
            "fewha_pcg_solve", "fewha_fit_dm", "fewha_state_get", "fewha_state_set", "fewha_precond_table",
            "fewha_last_status", "fewha_stage_launch", "fewha_strerror", "fewha_solve_M", "fewha_apply_CA",
            "fewha_prior_dot", "fewha_plan_set_batch", "fewha_apply_A_batch", "fewha_apply_At_batch",
-           "fewha_apply_M_batch", "fewha_pcg_solve_batch", "fewha_fit_dm_batch", "fewha_last_status_batch"]
+           "fewha_apply_M_batch", "fewha_pcg_solve_batch", "fewha_fit_dm_batch", "fewha_last_status_batch",
+           "fewha_pol_slopes", "fewha_fit_dm_closed", "fewha_pol_slopes_batch", "fewha_fit_dm_closed_batch"]
 
 
 class FewhaError(RuntimeError):
@@ -79,6 +80,10 @@ def load_library():
     L.fewha_pcg_solve_batch.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, ctypes.c_int, vp, vp]
     L.fewha_fit_dm_batch.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_double, vp, vp]
     L.fewha_last_status_batch.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    L.fewha_pol_slopes.argtypes = [vp, vp, vp, vp, vp]
+    L.fewha_fit_dm_closed.argtypes = [vp, vp, vp, vp, ctypes.c_double, vp, vp]
+    L.fewha_pol_slopes_batch.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
+    L.fewha_fit_dm_closed_batch.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_double, vp, vp]
     L.fewha_prior_dot.argtypes = [vp, vp, vp, vp, vp]
     L.fewha_pcg_solve.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, vp]
     L.fewha_fit_dm.argtypes = [vp, vp, vp, ctypes.c_double, vp, vp]
@@ -309,6 +314,43 @@ class Plan:
         out = (ctypes.c_int * nbatch)()
         _check(_lib.fewha_last_status_batch(self._h, int(nbatch), out), "fewha_last_status_batch")
         return list(out)
+
+    # -- closed loop (Alg. 1) ----------------------------------------------------------------------
+    def pol_slopes(self, s, a_m1, out=None):
+        """Pseudo-open-loop slopes mask (s + Gamma P_DM a_m1) (a_m1: the DM shape two frames back)."""
+        sp = self._out(out, self.n_slopes)
+        _check(_lib.fewha_pol_slopes(self._h, self._arg(s, self.n_slopes, "s"), self._arg(a_m1, self.n_act, "a_m1"),
+                                     self._arg(sp, self.n_slopes, "s_pol"), self._stream()), "fewha_pol_slopes")
+        return sp
+
+    def fit_dm_closed(self, c, a0, a_m1, gain, out=None):
+        """Closed-loop control: a0 + gain (F W^T c - a_m1)."""
+        a = self._out(out, self.n_act)
+        _check(_lib.fewha_fit_dm_closed(self._h, self._arg(c, self.n_coef, "c"), self._arg(a0, self.n_act, "a0"),
+                                        self._arg(a_m1, self.n_act, "a_m1"), float(gain),
+                                        self._arg(a, self.n_act, "a"), self._stream()), "fewha_fit_dm_closed")
+        return a
+
+    def pol_slopes_batch(self, s, a_m1, out=None):
+        nb = self._batch(s, self.n_slopes, "s")
+        if self._batch(a_m1, self.n_act, "a_m1") != nb:
+            raise ValueError("s and a_m1: different batch sizes")
+        sp = out if out is not None else self._torch.empty((nb, self.n_slopes), dtype=self.dtype, device=self.device)
+        self._batch(sp, self.n_slopes, "s_pol")
+        _check(_lib.fewha_pol_slopes_batch(self._h, nb, s.data_ptr(), a_m1.data_ptr(), sp.data_ptr(), self._stream()),
+               "fewha_pol_slopes_batch")
+        return sp
+
+    def fit_dm_closed_batch(self, c, a0, a_m1, gain, out=None):
+        nb = self._batch(c, self.n_coef, "c")
+        for t, nm in ((a0, "a0"), (a_m1, "a_m1")):
+            if self._batch(t, self.n_act, nm) != nb:
+                raise ValueError("%s: different batch size" % nm)
+        a = out if out is not None else self._torch.empty((nb, self.n_act), dtype=self.dtype, device=self.device)
+        self._batch(a, self.n_act, "a")
+        _check(_lib.fewha_fit_dm_closed_batch(self._h, nb, c.data_ptr(), a0.data_ptr(), a_m1.data_ptr(), float(gain),
+                                              a.data_ptr(), self._stream()), "fewha_fit_dm_closed_batch")
+        return a
 
     def fit_dm(self, c, a_prev=None, gain=1.0, out=None):
         a = self._out(out, self.n_act)
