@@ -98,6 +98,29 @@ def test_unbound_plan_refuses_work(cfg_c0):
     L.fewha_plan_destroy(h)
 
 
+def test_batch_limits_and_unbound_batch_calls(cfg_c0):
+    """Batch sizing: 1..1024 frames; a resize unbinds the plan and grows the workspace with the
+    per-frame state only; batched and closed-loop calls on an unbound plan are refused."""
+    L = fewha.load_library()
+    h, st = fewha.create_host_plan(cfg_c0)
+    assert st == 0
+    ws1 = L.fewha_workspace_bytes(h)
+    assert L.fewha_plan_set_batch(h, 0) == -1
+    assert L.fewha_plan_set_batch(h, 1025) == -1
+    assert L.fewha_plan_set_batch(h, 4) == 0
+    ws4 = L.fewha_workspace_bytes(h)
+    assert L.fewha_plan_set_batch(h, 7) == 0
+    ws7 = L.fewha_workspace_bytes(h)
+    per_frame = (ws7 - ws4) / 3
+    assert ws4 > ws1 and abs((ws4 - ws1) - 3 * per_frame) <= 3 * 256  # linear in the frame count (256-byte aligned)
+    assert L.fewha_pcg_solve_batch(h, 2, 1, 1, 4, 1, None, None) == -5
+    assert L.fewha_apply_A_batch(h, 2, 1, 1, None) == -5
+    assert L.fewha_pol_slopes(h, 1, 1, 2, None) == -5
+    assert L.fewha_fit_dm_closed(h, 1, 2, 3, 0.5, 4, None) == -5
+    assert L.fewha_solve_M(h, 1, 2, 4, None, None) == -5
+    L.fewha_plan_destroy(h)
+
+
 def test_no_cpu_fallback_in_binding():
     """The binding has no compute path of its own: every operator is a library call."""
     src = open(os.path.join(ROOT, "paper_2009_00946_amd", "fewha.py")).read()

@@ -247,6 +247,27 @@ def test_zero_slopes_and_nonfinite_status():
     assert torch.count_nonzero(c).item() == 0
 
 
+def test_zero_passes_updates_residual_only():
+    """n_iter = 0: the right-hand side and the warm-restart residual update run, c is unchanged
+    (Alg. 1 with an empty PCG), against the oracle's frame with zero passes."""
+    P, O = plan("c0_tiny", "fp64"), oracle("c0_tiny")
+    cfg = synth.load_config("c0_tiny")
+    N = O.n_coef
+    s0, s1 = _slopes(O, cfg, 0), _slopes(O, cfg, 1)
+    c_ref, bp, rp, _, st = O.frame(s0, np.zeros(N), np.zeros(N), np.zeros(N), cfg["n_iter"], True)
+    c = P.zeros(N)
+    P.pcg_solve(dev(P, s0), c, cfg["n_iter"], warm=False)
+    c_before = host(c).copy()
+    c_ref1, bp1, rp1, _, st1 = O.frame(s1, c_ref, bp, rp, 0, False)
+    P.pcg_solve(dev(P, s1), c, 0, warm=True)
+    assert st == 0 and st1 == 0 and P.last_status() == 0
+    assert np.array_equal(host(c), c_before)
+    check(host(c), c_ref1, 1e-9, "c")
+    b_g, r_g = P.state_get()
+    check(host(b_g), bp1, 1e-12, "b_prev")
+    check(host(r_g), rp1, 1e-9, "r_prev")
+
+
 def test_graph_replay_matches_eager():
     """A frame captured in a HIP graph and replayed gives bitwise the eager chain's result,
     replay after replay (host synchronisation between replays)."""
