@@ -120,12 +120,17 @@ def time_stages(P, stream, reps, replays=4):
 
 
 def source_digest():
-    """SHA-256 over the kernel sources; recorded traffic is valid only for this digest."""
+    """SHA-256 over the kernel sources with comments and whitespace removed; recorded traffic is
+    valid only for this digest (edits to comments keep it, edits to code do not)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in ("kernels.hip", "kernels.h", "fewha_internal.h"):
-        with open(os.path.join(ROOT, "paper_2009_00946_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2009_00946_amd", "csrc", name)) as f:
+            src = f.read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", "", src)
+        h.update(re.sub(r"\s+", "", src).encode())
     return h.hexdigest()
 
 

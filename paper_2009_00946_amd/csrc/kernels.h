@@ -60,7 +60,7 @@ struct Ops {
 
     int prepare() const;                                  // per-device kernel attributes (bind)
     int wt(const T *c, T *out) const;                     // out = W^T c
-    int wt_pcg(const T *r, T *out) const;                 // out = W^T J^-1 r; (r, z), (z, alpha D z) partials
+    int wt_pcg(const T *r, T *out) const;                 // out = W^T J^-1 r
     int proj(const T *u, T *out, int mode) const;         // kProjM: v = Gamma^T C Gamma P u; kProjA/CA: s = (C) mask Gamma P u
     int gt(const T *s, T *v, int mode) const;             // v = Gamma^T C s | Gamma^T mask s
     int pt(const T *v, T *x, const PassArgs &PA) const;   // x = P^T v (+ the scalar step of pass PA.k)

@@ -8,15 +8,16 @@
 // no atomics: reductions leave one FP64 partial per workgroup, summed in fixed order by the
 // kernels that need the result.
 //
-// One PCG pass of Alg. 2 (Jacobi-preconditioned, one reduction point) is four launches:
+// One PCG pass of Alg. 2 (Jacobi-preconditioned, one reduction point) is five launches:
 //   k_wt<pcg>    z = J^-1 r and u = W^T z on 32 x 32 output tiles (all J levels per tile from a
-//                cone of coefficients); partials of rho = (r, z) and (z, alpha D z)
+//                cone of coefficients)
 //   k_proj<M>    per 16 x 16 node tile of each guide star: phi = P u (bilinear rays, cone effect),
 //                Gamma, C_eta^-1, Gamma^T -> v; partial of sum C (Gamma P u)^2
 //   k_pt         x = P^T v on 16 x 16 layer tiles, from staged node rectangles and the transpose
-//                tables (the same matrix entries as P)
+//                tables (the same matrix entries as P); one extra workgroup steps the scalars
 //   k_fwd/k_coarse<pcg>  y = W x + alpha D z on the fine levels (tiles) and the coarse levels
-//                (one workgroup per layer), then the pass's update in place.
+//                (one workgroup per layer), then the pass's update in place, with the partials of
+//                rho = (r, z) and (z, alpha D z) of the new residual for the next pass.
 // The denominator mu = (M z, z) is formed from the partials as (C Gamma P W^T z, Gamma P W^T z)
 // + (z, alpha D z): W is orthonormal and every adjoint here is the exact transpose of its
 // forward operator, so this equals (y, z) without waiting for y, and the update of a pass can
@@ -209,11 +210,12 @@ struct StepOut {
     int stopped;
 };
 
-// The scalar step of pass k, done once by one extra workgroup of the P^T launch (whose inputs,
-// the partials of the inverse DWT and of the projection, are complete by then): reduce the
-// partials in fixed order, step the recurrence from sc[(k-1)&1], store (alpha, beta, stopped) in
-// sc[3] for the forward transform that applies the update and, if `publish`, the new state in
-// sc[k&1] and sqrt(rho) in resnorm[k].
+// The scalar step of pass k, done once by one extra workgroup of the P^T launch (whose inputs
+// are complete by then: the partials of (r, z) and (z, alpha D z) left by the forward transforms
+// that wrote r, and those of C (Gamma P u)^2 left by the projection): reduce the partials in
+// fixed order, step the recurrence from sc[(k-1)&1], store (alpha, beta, stopped) in sc[3] for the
+// forward transform that applies the update and, if `publish`, the new state in sc[k&1] and
+// sqrt(rho) in resnorm[k].
 __device__ void scalar_step(const double *__restrict__ part, int nwt, int nproj, Scalars *sc, int k,
                             double *resnorm, int publish) {
     __shared__ double sh[kB / 64];
