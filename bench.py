@@ -304,6 +304,67 @@ def c3_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def batch_scan(args):
+    """Throughput of the ELT frame against the number of frames per launch (one batched plan per
+    size; RHS + 4 warm PCG passes + fit per frame, one HIP graph per batch)."""
+    import torch
+    from paper_2009_00946_amd import fewha, synth
+    torch.cuda.set_device(0)
+    cfg = synth.load_config(args.config)
+    n_iter, gain = cfg["n_iter"], cfg["gain"]
+    model = byte_model(cfg, 4, n_iter)
+    rows = []
+    for nb in (1, 2, 4, 8, 16, 32):
+        PB = fewha.Plan(cfg, max_batch=nb)
+        P1 = PB if nb == 1 else fewha.Plan(cfg)
+        S = []
+        for f in range(nb):
+            phi = torch.as_tensor(synth.layer_screens_flat(cfg, f), dtype=PB.dtype, device=PB.device)
+            s = P1.apply_A(P1.dwt_forward(phi))
+            s += torch.as_tensor(synth.slope_noise(cfg, f), dtype=PB.dtype, device=PB.device)
+            S.append(s)
+        sb = torch.stack(S).contiguous()
+        cb = torch.zeros((nb, PB.n_coef), dtype=PB.dtype, device=PB.device)
+        ab = torch.zeros((nb, PB.n_act), dtype=PB.dtype, device=PB.device)
+
+        def step(warm=True):
+            PB.pcg_solve_batch(sb, cb, n_iter, warm=warm)
+            PB.fit_dm_batch(cb, gain=gain, out=ab)
+
+        step(warm=False)
+        for _ in range(3):
+            step()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        cap = torch.cuda.Stream()
+        cap.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.graph(g, stream=cap):
+            step()
+        torch.cuda.current_stream().wait_stream(cap)
+        for _ in range(args.warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        steps = max(args.steps // nb, 20)
+        e0.record()
+        for _ in range(steps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        assert PB.last_status_batch(nb) == [0] * nb
+        ms = e0.elapsed_time(e1) / steps
+        rows.append({"frames": nb, "ms_per_launch_set": round(ms, 4), "us_per_frame": round(1e3 * ms / nb, 2),
+                     "frames_per_s": round(1e3 * nb / ms, 1),
+                     "effective_GBps": round(model["frame"] * nb / (ms * 1e-3) / 1e9, 1)})
+        print("[batch_scan] %s" % json.dumps(rows[-1]), flush=True)
+        del PB, P1, S, sb, cb, ab, g
+        torch.cuda.empty_cache()
+    out = {"metric": "ELT frame throughput against frames per launch (batched plans)", "value": rows[-1]["us_per_frame"],
+           "unit": "us/frame", "n_gpus": 1, "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "%s batched" % cfg["name"], "n_iter": n_iter, "warm": True}, "scan": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -315,8 +376,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eager", action="store_true", help="launch kernels one by one instead of replaying HIP graphs")
     ap.add_argument("--stage-reps", type=int, default=50, help="launches per PCG-pass stage in its timing graph")
-    ap.add_argument("--workload", default="frame", choices=("frame", "c3_batch"),
-                    help="frame: the ELT frame (default); c3_batch: 64 uneven frames in batched launches")
+    ap.add_argument("--workload", default="frame", choices=("frame", "c3_batch", "batch_scan"),
+                    help="frame: the ELT frame (default); c3_batch: 64 uneven frames in batched launches; "
+                         "batch_scan: ELT frames per second against frames per launch")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run plain 256 MiB device copies (reference dispatches for HBM counters)")
     args = ap.parse_args()
@@ -327,6 +389,9 @@ def main():
 
     if args.workload == "c3_batch":
         c3_batch(args)
+        return
+    if args.workload == "batch_scan":
+        batch_scan(args)
         return
 
     import torch
