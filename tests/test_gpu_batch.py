@@ -98,3 +98,28 @@ def test_batched_frame_matches_oracle():
         c_ref = O.frame(S[f], z, z, z, n_iter, True)[0]
         got = cb[f].cpu().numpy()
         assert np.abs(got - c_ref).max() <= 1e-9 * np.abs(c_ref).max(), f
+
+
+def test_large_batch_cold_frames_equal_single():
+    """A batch of 17 cold frames: every frame equals, bitwise, the same cold frame on a
+    single-frame plan, with its residual norms."""
+    _need_gpu()
+    from oracle import Oracle
+    from paper_2009_00946_amd import fewha
+    cfg = synth.load_config("c0_tiny")
+    O = Oracle(cfg, precond=False)
+    nb, n_iter = 17, cfg["n_iter"]
+    PB = fewha.Plan(cfg, precision="fp64", max_batch=nb)
+    P1 = fewha.Plan(cfg, precision="fp64")
+    S = torch.as_tensor(np.stack([_slopes(O, cfg, f) for f in range(nb)]), dtype=PB.dtype, device=PB.device)
+    rb = torch.zeros(nb * n_iter, dtype=torch.float64, device=PB.device)
+    cb = torch.zeros((nb, PB.n_coef), dtype=PB.dtype, device=PB.device)
+    PB.pcg_solve_batch(S.contiguous(), cb, n_iter, warm=False, resnorm=rb)
+    assert PB.last_status_batch(nb) == [0] * nb
+    r1 = torch.zeros(n_iter, dtype=torch.float64, device=PB.device)
+    for f in range(nb):
+        c1 = P1.zeros(P1.n_coef)
+        P1.pcg_solve(S[f].contiguous(), c1, n_iter, warm=False, resnorm=r1)
+        torch.cuda.synchronize()
+        assert torch.equal(cb[f], c1), "frame %d" % f
+        assert torch.equal(rb[f * n_iter:(f + 1) * n_iter], r1), "resnorm frame %d" % f
