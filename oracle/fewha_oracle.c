@@ -717,6 +717,152 @@ void orc_fit_closed(const orc_plan *P, const double *c, const double *a0, const 
 }
 
 /* ------------------------------------------------------------------------------------ */
+/* Least-squares DM fitting for more layers than DMs (Sec. 4.1 asks for "an additional     */
+/* minimization problem" without stating it).  Reading: over the 25 probe directions of    */
+/* the quality evaluation grid (theta_x, theta_y in {-60, -30, 0, 30, 60} arcsec) and the   */
+/* nodes of the first sensor's grid inside the pupil annulus, natural-star rays, minimise   */
+/*   sum_theta sum_x (sum_l U_l(x + theta h_l) - sum_m S_m(x + theta h_m))^2 + eps |a|^2    */
+/* with U_l and S_m the piecewise bilinear (hat) surfaces over the layer nodes and the      */
+/* actuators (zero beyond their grids), by n_cg steps of plain CG on the normal equations   */
+/* from a = 0.                                                                             */
+/* ------------------------------------------------------------------------------------ */
+#define ORC_NPROBE 25
+
+static void probe_dir(int t, double *tx, double *ty)
+{
+    const double as = 3.14159265358979323846 / (180.0 * 3600.0);
+    *tx = (-60.0 + 30.0 * (t % 5)) * as;
+    *ty = (-60.0 + 30.0 * (t / 5)) * as;
+}
+
+/* Evaluation node j (per axis) of the fitting grid and whether node (i, j) is in the pupil. */
+static double fit_node(const orc_plan *P, int j) { return -P->D / 2 + j * (P->D / P->wfs[0].n_sub); }
+static int fit_in_pupil(const orc_plan *P, int i, int j)
+{
+    double x = fit_node(P, j), y = fit_node(P, i), r = sqrt(x * x + y * y);
+    return r <= P->D / 2 && r >= P->obstruction * P->D / 2;
+}
+
+/* Hat surface of layer l at (X, Y): its node k at ((k - n/2) delta), zero beyond the grid. */
+static double layer_surface(const orc_plan *P, int l, const double *layers, double X, double Y)
+{
+    int n = P->lay[l].n;
+    double dl = P->lay[l].spacing, acc = 0.0;
+    for (int i = 0; i < n; i++) {
+        double wy = 1.0 - fabs(Y / dl - (i - n / 2));
+        if (wy <= 0.0) continue;
+        for (int j = 0; j < n; j++) {
+            double wx = 1.0 - fabs(X / dl - (j - n / 2));
+            if (wx > 0.0) acc += wx * wy * layers[P->c_off[l] + (long)i * n + j];
+        }
+    }
+    return acc;
+}
+
+long orc_fit_points(const orc_plan *P) { long nv = P->wfs[0].n_sub + 1; return ORC_NPROBE * nv * nv; }
+
+/* The target: y[t][i][j] = sum_l U_l(x_ij + theta_t h_l) on pupil nodes (0 elsewhere). */
+void orc_ls_target(const orc_plan *P, const double *layers, double *y)
+{
+    int nv = P->wfs[0].n_sub + 1;
+    for (int t = 0; t < ORC_NPROBE; t++) {
+        double tx, ty;
+        probe_dir(t, &tx, &ty);
+        for (int i = 0; i < nv; i++)
+            for (int j = 0; j < nv; j++) {
+                double acc = 0.0;
+                if (fit_in_pupil(P, i, j))
+                    for (int l = 0; l < P->nl; l++)
+                        acc += layer_surface(P, l, layers, fit_node(P, j) + tx * P->lay[l].height,
+                                             fit_node(P, i) + ty * P->lay[l].height);
+                y[((long)t * nv + i) * nv + j] = acc;
+            }
+    }
+}
+
+/* H a: y[t][i][j] = sum_m S_m(x_ij + theta_t h_m) on pupil nodes (0 elsewhere). */
+void orc_ls_H(const orc_plan *P, const double *a, double *y)
+{
+    int nv = P->wfs[0].n_sub + 1;
+    for (int t = 0; t < ORC_NPROBE; t++) {
+        double tx, ty;
+        probe_dir(t, &tx, &ty);
+        for (int i = 0; i < nv; i++)
+            for (int j = 0; j < nv; j++) {
+                double acc = 0.0;
+                if (fit_in_pupil(P, i, j))
+                    for (int m = 0; m < P->nd; m++)
+                        acc += dm_surface(P, m, a, fit_node(P, j) + tx * P->dm[m].height,
+                                          fit_node(P, i) + ty * P->dm[m].height);
+                y[((long)t * nv + i) * nv + j] = acc;
+            }
+    }
+}
+
+/* H^T y: every pupil node of every direction spreads its value onto the actuators whose hats
+ * cover it. */
+void orc_ls_Ht(const orc_plan *P, const double *y, double *a)
+{
+    int nv = P->wfs[0].n_sub + 1;
+    memset(a, 0, sizeof(double) * P->n_act);
+    for (int t = 0; t < ORC_NPROBE; t++) {
+        double tx, ty;
+        probe_dir(t, &tx, &ty);
+        for (int i = 0; i < nv; i++)
+            for (int j = 0; j < nv; j++) {
+                if (!fit_in_pupil(P, i, j)) continue;
+                double f = y[((long)t * nv + i) * nv + j];
+                for (int m = 0; m < P->nd; m++) {
+                    int na = P->dm[m].n_act;
+                    double p = P->dm[m].pitch, c = (na - 1) / 2.0;
+                    double X = fit_node(P, j) + tx * P->dm[m].height, Y = fit_node(P, i) + ty * P->dm[m].height;
+                    for (int ai = 0; ai < na; ai++) {
+                        double wy = 1.0 - fabs(Y / p - (ai - c));
+                        if (wy <= 0.0) continue;
+                        for (int aj = 0; aj < na; aj++) {
+                            double wx = 1.0 - fabs(X / p - (aj - c));
+                            if (wx > 0.0) a[P->a_off[m] + (long)ai * na + aj] += wx * wy * f;
+                        }
+                    }
+                }
+            }
+    }
+}
+
+/* Least-squares fit of the layers W^T c onto the DMs: n_cg plain CG steps on
+ * (H^T H + eps I) a = H^T y0 from a = 0 (y0 the target). */
+void orc_fit_ls(const orc_plan *P, const double *c, int n_cg, double eps, double *a)
+{
+    long na = P->n_act, np = orc_fit_points(P);
+    double *lay = malloc(sizeof(double) * P->n_coef), *y = malloc(sizeof(double) * np);
+    double *r = malloc(sizeof(double) * na), *p = malloc(sizeof(double) * na), *q = malloc(sizeof(double) * na);
+    orc_Wt(P, c, lay);
+    orc_ls_target(P, lay, y);
+    orc_ls_Ht(P, y, r);
+    memset(a, 0, sizeof(double) * na);
+    memcpy(p, r, sizeof(double) * na);
+    double rr = dot(r, r, na);
+    for (int k = 0; k < n_cg && rr > 0.0; k++) {
+        orc_ls_H(P, p, y);
+        orc_ls_Ht(P, y, q);
+        for (long i = 0; i < na; i++) q[i] += eps * p[i];
+        double al = rr / dot(p, q, na);
+        for (long i = 0; i < na; i++) {
+            a[i] += al * p[i];
+            r[i] -= al * q[i];
+        }
+        double rn = dot(r, r, na), be = rn / rr;
+        for (long i = 0; i < na; i++) p[i] = r[i] + be * p[i];
+        rr = rn;
+    }
+    free(lay);
+    free(y);
+    free(r);
+    free(p);
+    free(q);
+}
+
+/* ------------------------------------------------------------------------------------ */
 /* Plan: copy the configuration, check the geometry, lay out the vectors.                 */
 /* ------------------------------------------------------------------------------------ */
 void orc_destroy(orc_plan *P)

@@ -69,6 +69,12 @@ def _load():
         L.orc_frame.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int, _dp]
         L.orc_fit.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double, _dp]
         L.orc_pol.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
+        L.orc_fit_points.argtypes = [ctypes.c_void_p]
+        L.orc_fit_points.restype = ctypes.c_long
+        L.orc_ls_target.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.orc_ls_H.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.orc_ls_Ht.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.orc_fit_ls.argtypes = [ctypes.c_void_p, _dp, ctypes.c_int, ctypes.c_double, _dp]
         L.orc_fit_closed.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, ctypes.c_double, _dp]
         L.orc_db3.argtypes = [_dp]
         L.orc_dwt1_fwd.argtypes = [_dp, _dp, ctypes.c_int]
@@ -175,6 +181,18 @@ class Oracle:
     def fit_interp_t(self, a): return self._call("orc_fit_interp_t", a, self.n_act, self.n_coef)
     def Hdm(self, a): return self._call("orc_apply_Hdm", a, self.n_act, self.n_slopes)
     def Hdm_t(self, s): return self._call("orc_apply_Hdm_t", s, self.n_slopes, self.n_act)
+
+    # least-squares DM fitting over the probe directions (L > M)
+    def fit_points(self): return int(_lib.orc_fit_points(self._h))
+    def ls_target(self, layers): return self._call("orc_ls_target", layers, self.n_coef, self.fit_points())
+    def ls_H(self, a): return self._call("orc_ls_H", a, self.n_act, self.fit_points())
+    def ls_Ht(self, y): return self._call("orc_ls_Ht", y, self.fit_points(), self.n_act)
+
+    def fit_ls(self, c, n_cg, eps):
+        """n_cg CG steps on (H^T H + eps I) a = H^T (target of W^T c) from a = 0."""
+        a = np.zeros(self.n_act)
+        _lib.orc_fit_ls(self._h, _p(_f64(c, self.n_coef)), int(n_cg), float(eps), _p(a))
+        return a
 
     def pol(self, s, a_m1):
         """Pseudo-open-loop slopes of Alg. 1 (closed loop): mask (s + H_dm a^(-1))."""
