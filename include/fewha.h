@@ -191,6 +191,23 @@ int fewha_pol_slopes(const fewha_plan *p, const void *d_s, const void *d_a_m1, v
 int fewha_fit_dm_closed(const fewha_plan *p, const void *d_c, const void *d_a0, const void *d_a_m1, double gain,
                         void *d_a, void *stream);
 
+/* Least-squares DM fitting for more layers than DMs, then the open-loop gain:
+ * a = (1 - gain) a_prev + gain a_ls.  Sec. 4.1 says that with more layers than DMs the fit becomes
+ * a minimisation of its own, which it leaves unstated.  Reading: a_ls minimises, over the 25 probe
+ * directions of the quality evaluation grid (theta_x, theta_y in {-60, -30, 0, 30, 60} arcsec)
+ * and the nodes (-D/2 + j d, -D/2 + i d), d = D / n_sub of the first guide star, inside the closed
+ * pupil annulus obstruction D/2 <= r <= D/2, along natural-star rays,
+ *   sum_theta sum_x (sum_l U_l(x + theta h_l) - sum_m S_m(x + theta h_m))^2 + eps |a|^2,
+ * U_l = the layers W^T c and S_m = the DMs, each the piecewise bilinear (hat) surface over its grid,
+ * zero beyond it; a_ls is n_cg plain CG steps on the normal equations from 0 (a step whose
+ * residual norm is 0 leaves a_ls unchanged).  d_c: n_coef coefficients; d_a_prev: n_act or NULL
+ * (taken as 0); d_a: n_act, must not alias d_c, may alias d_a_prev.  Device pointers of the plan's
+ * precision.  Uses workspace vectors of the plan (calls on one plan do not overlap).  Returns
+ * FEWHA_ERR_INVALID_ARG for a null d_c or d_a, d_a == d_c, n_cg < 0, a non-finite gain, or eps
+ * negative or non-finite. */
+int fewha_fit_dm_ls(const fewha_plan *p, const void *d_c, const void *d_a_prev, double gain, int n_cg, double eps,
+                    void *d_a, void *stream);
+
 /* Copy the warm-restart state (b_prev, r_prev; n_coef each) out of / into the workspace. */
 int fewha_state_get(const fewha_plan *p, void *d_b_prev, void *d_r_prev, void *stream);
 int fewha_state_set(fewha_plan *p, const void *d_b_prev, const void *d_r_prev, void *stream);

@@ -717,8 +717,8 @@ void orc_fit_closed(const orc_plan *P, const double *c, const double *a0, const 
 }
 
 /* ------------------------------------------------------------------------------------ */
-/* Least-squares DM fitting for more layers than DMs (Sec. 4.1 asks for "an additional     */
-/* minimization problem" without stating it).  Reading: over the 25 probe directions of    */
+/* Least-squares DM fitting for more layers than DMs (Sec. 4.1 makes the fit a            */
+/* minimisation of its own there, left unstated).  Reading: over the 25 probe directions of */
 /* the quality evaluation grid (theta_x, theta_y in {-60, -30, 0, 30, 60} arcsec) and the   */
 /* nodes of the first sensor's grid inside the pupil annulus, natural-star rays, minimise   */
 /*   sum_theta sum_x (sum_l U_l(x + theta h_l) - sum_m S_m(x + theta h_m))^2 + eps |a|^2    */

@@ -259,6 +259,20 @@ int bind_tables(Plan &P, hipStream_t st) {
         HIPTRY(hipMemcpy(w + P.o_xdm, xd.data(), sizeof(Ent<T>) * ne, hipMemcpyHostToDevice));
         HIPTRY(hipMemcpy(w + P.o_ydm, yd.data(), sizeof(Ent<T>) * ne, hipMemcpyHostToDevice));
     }
+    // Least-squares fitting nodes (x_j, y_i) = (-D/2 + j d, -D/2 + i d) of the first sensor's grid
+    // inside the closed pupil annulus obstruction D/2 <= r <= D/2; decided here in FP64 once, so
+    // that nodes on the rim are kept or dropped by the definition rather than by device rounding
+    {
+        const int nv = P.wfs[0].n_sub + 1;
+        const double d = P.D / P.wfs[0].n_sub;
+        std::vector<unsigned char> fm(size_t(nv) * nv);
+        for (int i = 0; i < nv; ++i)
+            for (int j = 0; j < nv; ++j) {
+                const double x = -P.D / 2 + j * d, y = -P.D / 2 + i * d, r = std::sqrt(x * x + y * y);
+                fm[size_t(i) * nv + j] = r <= P.D / 2 && r >= P.obstruction * P.D / 2;
+            }
+        HIPTRY(hipMemcpy(w + P.o_fmask, fm.data(), fm.size(), hipMemcpyHostToDevice));
+    }
     const long N = (long)P.n_coef;
     TRY(o.prepare());
     HIPTRY(hipMemset(o.B.over, 0, sizeof(int) * P.nw));
@@ -477,6 +491,22 @@ int fewha_fit_dm_closed(const fewha_plan *p, const void *d_c, const void *d_a0, 
         return FEWHA_ERR_INVALID_ARG;
     return p->p.prec == FEWHA_FP64 ? fit_closed<double>(p->p, d_c, d_a0, d_a_m1, gain, d_a, stream)
                                    : fit_closed<float>(p->p, d_c, d_a0, d_a_m1, gain, d_a, stream);
+}
+
+int fewha_fit_dm_ls(const fewha_plan *p, const void *d_c, const void *d_a_prev, double gain, int n_cg, double eps,
+                    void *d_a, void *stream) {
+    TRY(ready(p));
+    if (!d_c || !d_a || d_a == d_c || n_cg < 0 || !std::isfinite(gain) || !(eps >= 0) || !std::isfinite(eps))
+        return FEWHA_ERR_INVALID_ARG;
+    const Plan &P = p->p;
+    if (P.prec == FEWHA_FP64) {
+        auto o = ops<double>(P, stream);
+        TRY(o.wt(static_cast<const double *>(d_c), o.B.u));
+        return o.fit_ls(o.B.u, static_cast<const double *>(d_a_prev), static_cast<double *>(d_a), gain, n_cg, eps);
+    }
+    auto o = ops<float>(P, stream);
+    TRY(o.wt(static_cast<const float *>(d_c), o.B.u));
+    return o.fit_ls(o.B.u, static_cast<const float *>(d_a_prev), static_cast<float *>(d_a), gain, n_cg, eps);
 }
 
 int fewha_plan_set_batch(fewha_plan *p, int max_batch) {

@@ -33,6 +33,8 @@ constexpr int kPtStage = 6144;
 constexpr int kPtMaxWfs = 16;
 // Slots per row of the FP64 partial-sum buffer (one per workgroup of a reduction).
 constexpr int kPartialPitch = 4096;
+// Least-squares DM fitting: the 5 x 5 quality evaluation grid of probe directions.
+constexpr int kProbes = 25;
 // Scalar records per frame: two pass-parity slots, the right-hand-side record, the current pass.
 constexpr int kScalarSlots = 4;
 // Frames of one batched launch (grid y).
@@ -183,6 +185,7 @@ struct Plan {
     SegTab seg_wt{}, seg_pt{}, seg_fwd{}, seg_proj{};
     LayTab laytab{};
     LayTab dmtab{};       // per DM: actuator offset and actuators per side
+    size_t n_fit = 0;     // least-squares fitting points: probe directions x first sensor's nodes
     int n_wt = 0, n_pt = 0, n_fwd = 0, n_proj = 0;  // workgroups of each launch
     int maxnv = 0, sum_n = 0;
     int kf = 1;           // forward-DWT levels done on tiles; the rest per layer in one workgroup
@@ -199,6 +202,8 @@ struct Plan {
     size_t o_wfs = 0, o_lay = 0, o_proj = 0, o_dm = 0;
     size_t o_xtab = 0, o_ytab = 0, o_xrng = 0, o_yrng = 0, o_xrtab = 0, o_yrtab = 0, o_rects = 0;
     size_t o_xdm = 0, o_ydm = 0;
+    size_t o_fy = 0, o_fx = 0, o_fr = 0, o_fp = 0, o_fq = 0, o_frr = 0;  // least-squares DM fitting
+    size_t o_fmask = 0;   // least-squares fitting: 1 for the first sensor's nodes inside the pupil
     size_t o_jinv = 0, o_ad = 0, o_bprev = 0, o_r = 0, o_p = 0, o_q = 0, o_u = 0, o_x = 0, o_v = 0;
     size_t o_ll = 0, o_stage = 0, o_probe_c = 0, o_probe_s = 0, o_partials = 0, o_scalars = 0, o_over = 0;
     size_t ws_bytes = 0;

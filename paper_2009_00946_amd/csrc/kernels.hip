@@ -1259,6 +1259,176 @@ __global__ __launch_bounds__(kB) void k_prior_dot(LayTab LT, const T *__restrict
     if (threadIdx.x == 0) out[l] = v;
 }
 
+// ---------------------------------------------------------------------------------------------
+// Least-squares DM fitting over the probe directions (more layers than DMs).  Points: probe
+// direction t of the 5 x 5 grid (theta in {-60, -30, 0, 30, 60} arcsec per axis) and node (i, j)
+// of the first sensor's grid inside the pupil annulus; natural-star rays meet altitude h at
+// (x_j + theta_x h, y_i + theta_y h).  Layers and DMs are the hat (piecewise bilinear) surfaces
+// over their grids, zero beyond them.  With H the DM surfaces at the points and y0 the layers
+// there, the fit takes n_cg CG steps on (H^T H + eps I) a = H^T y0 from a = 0.
+// ---------------------------------------------------------------------------------------------
+struct FitGeom {
+    double D, d;                 // pupil diameter, node spacing
+    const unsigned char *in;     // nv x nv: 1 for nodes inside the pupil annulus
+    int nv;                      // nodes per side
+    double hl[kMaxLayers];       // layer altitudes
+    double hm[kMaxDms];          // DM altitudes
+};
+
+__device__ __forceinline__ void probe_dir(int t, double &tx, double &ty) {
+    const double as = 3.14159265358979323846 / (180.0 * 3600.0);
+    tx = (-60.0 + 30.0 * (t % 5)) * as;
+    ty = (-60.0 + 30.0 * (t / 5)) * as;
+}
+
+// The cell k0 in [0, n-2] and the hat weights of its lines k0, k0+1 at coordinate u of a grid
+// with lines 0..n-1: lines beyond the grid carry weight 0 (a cell straddling an edge keeps its
+// inside line only).
+__device__ __forceinline__ void hat_cell(double u, int n, int &k0, double &w0, double &w1) {
+    const int k = (int)floor(u);
+    const double t = u - k;
+    if (k >= 0 && k <= n - 2) {
+        k0 = k;
+        w0 = 1.0 - t;
+        w1 = t;
+    } else if (k == -1) {
+        k0 = 0;
+        w0 = t;
+        w1 = 0.0;
+    } else if (k == n - 1) {
+        k0 = n - 2;
+        w0 = 0.0;
+        w1 = 1.0 - t;
+    } else {
+        k0 = 0;
+        w0 = w1 = 0.0;
+    }
+}
+
+// y[t][i][j] = the layers (LAYERS) or the DMs (!LAYERS) summed along the ray of point (t, i, j).
+template <typename T, bool LAYERS>
+__global__ __launch_bounds__(kB) void k_fit_points(const T *__restrict__ src, T *__restrict__ y, Bufs<T> B, FitGeom G,
+                                                   int ngrid, int npts) {
+    const int id = blockIdx.x * kB + threadIdx.x;
+    if (id >= npts) return;
+    const int t = id / (G.nv * G.nv), rem = id - t * G.nv * G.nv, i = rem / G.nv, j = rem - i * G.nv;
+    const double x = -0.5 * G.D + j * G.d, yy = -0.5 * G.D + i * G.d;
+    T acc = 0;
+    if (G.in[rem]) {
+        double tx, ty;
+        probe_dir(t, tx, ty);
+        for (int q = 0; q < ngrid; ++q) {
+            double u, v;
+            int n;
+            long off;
+            if (LAYERS) {
+                const DevLayer L = B.lay[q];
+                u = (x + tx * G.hl[q]) / L.spacing + L.half;
+                v = (yy + ty * G.hl[q]) / L.spacing + L.half;
+                n = L.n;
+                off = L.c_off;
+            } else {
+                const DevDm Dm = B.dm[q];
+                u = (x + tx * G.hm[q]) / Dm.pitch + Dm.centre;
+                v = (yy + ty * G.hm[q]) / Dm.pitch + Dm.centre;
+                n = Dm.n_act;
+                off = Dm.a_off;
+            }
+            int kx, ky;
+            double wx0, wx1, wy0, wy1;
+            hat_cell(u, n, kx, wx0, wx1);
+            hat_cell(v, n, ky, wy0, wy1);
+            const T *U = src + off + (long)ky * n + kx;
+            acc += (T)(wy0 * wx0) * U[0] + (T)(wy0 * wx1) * U[1] + (T)(wy1 * wx0) * U[n] + (T)(wy1 * wx1) * U[n + 1];
+        }
+    }
+    y[id] = acc;
+}
+
+// out = H^T y (+ eps p): actuator (m, ai, aj) collects, for every direction, the points whose
+// node lies within one pitch of it.
+template <typename T>
+__global__ __launch_bounds__(kB) void k_fit_adjoint(const T *__restrict__ y, const T *__restrict__ p, T *__restrict__ out,
+                                                    Bufs<T> B, FitGeom G, int nd, long n_act, double eps) {
+    const long id = (long)blockIdx.x * kB + threadIdx.x;
+    if (id >= n_act) return;
+    int m = 0;
+    while (m + 1 < nd && B.dm[m + 1].a_off <= id) ++m;
+    const DevDm Dm = B.dm[m];
+    const long loc = id - Dm.a_off;
+    const int ai = (int)(loc / Dm.n_act), aj = (int)(loc - (long)ai * Dm.n_act);
+    const double h = G.hm[m], ca = (aj - Dm.centre) * Dm.pitch, ra = (ai - Dm.centre) * Dm.pitch;
+    double acc = 0.0;
+    for (int t = 0; t < kProbes; ++t) {
+        double tx, ty;
+        probe_dir(t, tx, ty);
+        // nodes with |x_j + tx h - ca| < pitch (x_j = -D/2 + j d)
+        const int j0 = max(0, (int)ceil((ca - Dm.pitch - tx * h + 0.5 * G.D) / G.d));
+        const int j1 = min(G.nv - 1, (int)floor((ca + Dm.pitch - tx * h + 0.5 * G.D) / G.d));
+        const int i0 = max(0, (int)ceil((ra - Dm.pitch - ty * h + 0.5 * G.D) / G.d));
+        const int i1 = min(G.nv - 1, (int)floor((ra + Dm.pitch - ty * h + 0.5 * G.D) / G.d));
+        for (int i = i0; i <= i1; ++i) {
+            const double wy = 1.0 - fabs((-0.5 * G.D + i * G.d + ty * h - ra) / Dm.pitch);
+            if (wy <= 0.0) continue;
+            for (int j = j0; j <= j1; ++j) {
+                const double wx = 1.0 - fabs((-0.5 * G.D + j * G.d + tx * h - ca) / Dm.pitch);
+                if (wx > 0.0) acc += wx * wy * (double)y[((long)t * G.nv + i) * G.nv + j];
+            }
+        }
+    }
+    out[id] = (T)(acc + (p ? eps * (double)p[id] : 0.0));
+}
+
+// One workgroup runs the vector part of CG on the actuators.  init: x = 0, r = p = b (in r),
+// rr = (r, r).  step: alpha = rr / (p, q), x += alpha p, r -= alpha q, rr' = (r, r),
+// p = r + (rr' / rr) p.  Sums in FP64 in a fixed order; rr = 0 leaves everything unchanged.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_fit_cg(T *__restrict__ x, T *__restrict__ r, T *__restrict__ p,
+                                                 const T *__restrict__ q, double *rr, long n, int init) {
+    __shared__ double sh[16];
+    const int tid = threadIdx.x;
+    if (init) {
+        double s = 0.0;
+        for (long i = tid; i < n; i += 1024) {
+            const T ri = r[i];
+            x[i] = 0;
+            p[i] = ri;
+            s += (double)ri * (double)ri;
+        }
+        const double t = block_sum(s, sh);
+        if (tid == 0) rr[0] = t;
+        return;
+    }
+    const double rr0 = rr[0];
+    if (!(rr0 > 0.0)) return;
+    double s = 0.0;
+    for (long i = tid; i < n; i += 1024) s += (double)p[i] * (double)q[i];
+    const double pq = block_sum(s, sh);
+    if (!(pq > 0.0)) return;
+    const double al = rr0 / pq;
+    s = 0.0;
+    for (long i = tid; i < n; i += 1024) {
+        x[i] += (T)al * p[i];
+        const T ri = r[i] - (T)al * q[i];
+        r[i] = ri;
+        s += (double)ri * (double)ri;
+    }
+    const double rn = block_sum(s, sh);
+    const T be = (T)(rn / rr0);
+    for (long i = tid; i < n; i += 1024) p[i] = r[i] + be * p[i];
+    if (tid == 0) rr[0] = rn;
+}
+
+// a = (1 - gain) a_prev + gain x (a_prev may be null).
+template <typename T>
+__global__ __launch_bounds__(kB) void k_fit_gain(const T *__restrict__ x, const T *__restrict__ a_prev, T *__restrict__ a,
+                                                 long n, double gain) {
+    const long i = (long)blockIdx.x * kB + threadIdx.x;
+    if (i >= n) return;
+    const T prev = a_prev ? a_prev[i] : (T)0;
+    a[i] = (T)(1.0 - gain) * prev + (T)gain * x[i];
+}
+
 template <typename T>
 __global__ __launch_bounds__(kB) void k_build_tabs(Ent<T> *xtab, Ent<T> *ytab, const DevWfs *__restrict__ wfs,
                                                    const DevProj *__restrict__ proj,
@@ -1567,6 +1737,40 @@ int Ops<T>::build_tables(int *over) const {
 template <typename T>
 int Ops<T>::prior_dot(const T *x, const T *y, double *out) const {
     k_prior_dot<T><<<P.nl, kB, 0, st>>>(P.laytab, x, y, B.ad, P.J, out);
+    return check();
+}
+
+FitGeom fit_geom(const Plan &P) {
+    FitGeom G{};
+    G.D = P.D;
+    G.d = P.D / P.wfs[0].n_sub;
+    G.in = reinterpret_cast<const unsigned char *>(P.ws + P.o_fmask);
+    G.nv = P.wfs[0].n_sub + 1;
+    for (int l = 0; l < P.nl; ++l) G.hl[l] = P.lay[l].height;
+    for (int m = 0; m < P.nd; ++m) G.hm[m] = P.dm[m].height;
+    return G;
+}
+
+template <typename T>
+int Ops<T>::fit_ls(const T *u, const T *a_prev, T *a, double gain, int n_cg, double eps) const {
+    const FitGeom G = fit_geom(P);
+    const int np = (int)P.n_fit;
+    const long na = (long)P.n_act;
+    char *w = P.ws;
+    T *y = reinterpret_cast<T *>(w + P.o_fy), *x = reinterpret_cast<T *>(w + P.o_fx);
+    T *r = reinterpret_cast<T *>(w + P.o_fr), *p = reinterpret_cast<T *>(w + P.o_fp);
+    T *q = reinterpret_cast<T *>(w + P.o_fq);
+    double *rr = reinterpret_cast<double *>(w + P.o_frr);
+    const int gp = (np + kB - 1) / kB, ga = (int)((na + kB - 1) / kB);
+    k_fit_points<T, true><<<gp, kB, 0, st>>>(u, y, B, G, P.nl, np);
+    k_fit_adjoint<T><<<ga, kB, 0, st>>>(y, nullptr, r, B, G, P.nd, na, 0.0);
+    k_fit_cg<T><<<1, 1024, 0, st>>>(x, r, p, q, rr, na, 1);
+    for (int it = 0; it < n_cg; ++it) {
+        k_fit_points<T, false><<<gp, kB, 0, st>>>(p, y, B, G, P.nd, np);
+        k_fit_adjoint<T><<<ga, kB, 0, st>>>(y, p, q, B, G, P.nd, na, eps);
+        k_fit_cg<T><<<1, 1024, 0, st>>>(x, r, p, q, rr, na, 0);
+    }
+    k_fit_gain<T><<<ga, kB, 0, st>>>(x, a_prev, a, na, gain);
     return check();
 }
 

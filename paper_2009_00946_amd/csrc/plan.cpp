@@ -86,6 +86,14 @@ void layout_workspace(Plan *P) {
     P->o_rects = take(16 * size_t(P->n_pt) * P->nw);
     P->o_xdm = take(ent * P->nw * P->nd * P->maxnv);
     P->o_ydm = take(ent * P->nw * P->nd * P->maxnv);
+    P->n_fit = size_t(kProbes) * (P->wfs[0].n_sub + 1) * (P->wfs[0].n_sub + 1);
+    P->o_fy = take(E * P->n_fit);
+    P->o_fx = take(E * P->n_act);
+    P->o_fr = take(E * P->n_act);
+    P->o_fp = take(E * P->n_act);
+    P->o_fq = take(E * P->n_act);
+    P->o_frr = take(sizeof(double) * 2);
+    P->o_fmask = take(size_t(P->wfs[0].n_sub + 1) * (P->wfs[0].n_sub + 1));
     P->o_jinv = take(E * P->nl * (P->J + 1) * 4);
     P->o_ad = take(E * P->nl * (P->J + 1));
     P->o_bprev = take(E * N * MB);

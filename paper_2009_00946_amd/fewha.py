@@ -22,7 +22,8 @@ EXPORTS = ["fewha_plan_create", "fewha_workspace_bytes", "fewha_plan_bind", "few
            "fewha_last_status", "fewha_stage_launch", "fewha_strerror", "fewha_solve_M", "fewha_apply_CA",
            "fewha_prior_dot", "fewha_plan_set_batch", "fewha_apply_A_batch", "fewha_apply_At_batch",
            "fewha_apply_M_batch", "fewha_pcg_solve_batch", "fewha_fit_dm_batch", "fewha_last_status_batch",
-           "fewha_pol_slopes", "fewha_fit_dm_closed", "fewha_pol_slopes_batch", "fewha_fit_dm_closed_batch"]
+           "fewha_pol_slopes", "fewha_fit_dm_closed", "fewha_pol_slopes_batch", "fewha_fit_dm_closed_batch",
+           "fewha_fit_dm_ls"]
 
 
 class FewhaError(RuntimeError):
@@ -81,6 +82,7 @@ def load_library():
     L.fewha_fit_dm_batch.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_double, vp, vp]
     L.fewha_last_status_batch.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     L.fewha_pol_slopes.argtypes = [vp, vp, vp, vp, vp]
+    L.fewha_fit_dm_ls.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int, ctypes.c_double, vp, vp]
     L.fewha_fit_dm_closed.argtypes = [vp, vp, vp, vp, ctypes.c_double, vp, vp]
     L.fewha_pol_slopes_batch.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
     L.fewha_fit_dm_closed_batch.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_double, vp, vp]
@@ -350,6 +352,14 @@ class Plan:
         self._batch(a, self.n_act, "a")
         _check(_lib.fewha_fit_dm_closed_batch(self._h, nb, c.data_ptr(), a0.data_ptr(), a_m1.data_ptr(), float(gain),
                                               a.data_ptr(), self._stream()), "fewha_fit_dm_closed_batch")
+        return a
+
+    def fit_dm_ls(self, c, a_prev=None, gain=1.0, n_cg=30, eps=1e-2, out=None):
+        """Least-squares fitting over the 25 probe directions (n_cg CG steps), then the gain."""
+        a = self._out(out, self.n_act)
+        ap = None if a_prev is None else self._arg(a_prev, self.n_act, "a_prev")
+        _check(_lib.fewha_fit_dm_ls(self._h, self._arg(c, self.n_coef, "c"), ap, float(gain), int(n_cg), float(eps),
+                                    self._arg(a, self.n_act, "a"), self._stream()), "fewha_fit_dm_ls")
         return a
 
     def fit_dm(self, c, a_prev=None, gain=1.0, out=None):
