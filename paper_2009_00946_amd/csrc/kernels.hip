@@ -162,6 +162,30 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
     return t;
 }
 
+// Two sums over the block at once, each in the fixed order of block_sum (so bitwise equal to two
+// block_sum calls): the shuffles of both interleave and one barrier pair serves both.  sh holds
+// 2 * (blockDim.x / 64) values.
+__device__ __forceinline__ void block_sum2(double &a, double &b, double *sh) {
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_down(a, off, 64);
+        b += __shfl_down(b, off, 64);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);
+    if (lane == 0) {
+        sh[wid] = a;
+        sh[nw + wid] = b;
+    }
+    __syncthreads();
+    double s = 0.0, t = 0.0;
+    for (int w = 0; w < nw; ++w) {
+        s += sh[w];
+        t += sh[nw + w];
+    }
+    __syncthreads();
+    a = s;
+    b = t;
+}
+
 __device__ __forceinline__ void reset_scalars(Scalars *sc) {
     sc->rho = sc->mu = sc->rho_old = sc->alpha = sc->alpha_old = sc->beta = 0.0;
     sc->stopped = 0;
@@ -218,15 +242,14 @@ struct StepOut {
 // sqrt(rho) in resnorm[k].
 __device__ void scalar_step(const double *__restrict__ part, int nwt, int nproj, Scalars *sc, int k,
                             double *resnorm, int publish) {
-    __shared__ double sh[kB / 64];
-    double r = 0.0, m = 0.0;
+    __shared__ double sh[2 * (kB / 64)];
+    double R = 0.0, Mu = 0.0;
     for (int i = threadIdx.x; i < nwt; i += blockDim.x) {
-        r += part[i];
-        m += part[kPartialPitch + i];
+        R += part[i];
+        Mu += part[kPartialPitch + i];
     }
-    for (int i = threadIdx.x; i < nproj; i += blockDim.x) m += part[2 * kPartialPitch + i];
-    const double R = block_sum(r, sh);
-    const double Mu = block_sum(m, sh);
+    for (int i = threadIdx.x; i < nproj; i += blockDim.x) Mu += part[2 * kPartialPitch + i];
+    block_sum2(R, Mu, sh);
     if (threadIdx.x == 0) {
         const Scalars prev = sc[(k - 1) & 1];
         const Scalars nx = alg2_step(prev, R, Mu, k);
@@ -1014,11 +1037,11 @@ __global__ __launch_bounds__((FwdLanes<KF, TQ>::block)) void k_fwd(SegTab S, con
         if (s < KF) __syncthreads();
     }
     if constexpr (EPI == kEpiPcg || EPI == kEpiRhs) {
-        __shared__ double sRed[16];
-        const double a = block_sum(rho, sRed), b = block_sum(dz, sRed);
+        __shared__ double sRed[2 * (FB / 64)];
+        block_sum2(rho, dz, sRed);
         if (tid == 0) {
-            B.partials[blockIdx.x] = a;
-            B.partials[kPartialPitch + blockIdx.x] = b;
+            B.partials[blockIdx.x] = rho;
+            B.partials[kPartialPitch + blockIdx.x] = dz;
         }
     }
 }
@@ -1111,6 +1134,7 @@ __global__ __launch_bounds__(kCB) void k_coarse(LayTab LT, Bufs<T> B, FwdArgs E,
             for (int o = 0; o < 4; ++o) ji[o] = sW[kMaxJ + 1 + 4 * s + o];
         }
         for (int q0 = 0; q0 < nq; q0 += kCB) {
+            if (q0 + (tid & ~63) >= nq) break;  // no quad of this level left for the wave
             const int qi = q0 + tid;
             const bool act = qi < nq;
             const int r = act ? qi / h : 0, q = act ? qi - r * h : 0;
@@ -1168,11 +1192,11 @@ __global__ __launch_bounds__(kCB) void k_coarse(LayTab LT, Bufs<T> B, FwdArgs E,
         cd = t;
     }
     if constexpr (EPI == kEpiPcg || EPI == kEpiRhs) {
-        __shared__ double sRed[kCB / 64];
-        const double a = block_sum(rho, sRed), b = block_sum(dz, sRed);
+        __shared__ double sRed[2 * (kCB / 64)];
+        block_sum2(rho, dz, sRed);
         if (tid == 0) {  // slots after the fine tiles' partials
-            B.partials[nfine + l] = a;
-            B.partials[kPartialPitch + nfine + l] = b;
+            B.partials[nfine + l] = rho;
+            B.partials[kPartialPitch + nfine + l] = dz;
         }
     }
 }
