@@ -383,7 +383,7 @@ def main():
                     help="also run plain 256 MiB device copies (reference dispatches for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs the single-GPU hot path only; multi-GPU runs are not provided "
+        print("bench.py: the library runs the hot path on one GPU; multi-GPU runs are not provided "
               "(frames would shard across GPUs with no exchange)", file=sys.stderr)
         sys.exit(2)
 
