@@ -154,6 +154,48 @@ def recorded_traffic(kernel_stage, config):
         return None
 
 
+def h2d_upload(stream, s_dev, reps=200):
+    """One frame's slopes uploaded from pinned host memory (timed on the launch stream).  The
+    library takes device pointers, so this is reported beside the frame time, never in it."""
+    import torch
+    host = torch.empty(s_dev.numel(), dtype=s_dev.dtype, pin_memory=True)
+    host.copy_(s_dev.cpu())
+    dst = torch.empty_like(s_dev)
+    for _ in range(5):
+        dst.copy_(host, non_blocking=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        dst.copy_(host, non_blocking=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    us = 1e3 * e0.elapsed_time(e1) / reps
+    nbytes = s_dev.numel() * s_dev.element_size()
+    return {"bytes": nbytes, "us_per_frame": round(us, 2), "GBps": round(nbytes / (us * 1e-6) / 1e9, 1)}
+
+
+def copy_bandwidth(stream, nbytes=256 << 20, reps=20):
+    """Device-to-device copy bandwidth of this GPU (bytes read + written per second), the
+    achievable reference beside the 8 TB/s peak."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    gbps = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return round(gbps, 1)
+
+
 def cpu_baseline(cfg, frames_s, n_iter, budget_s):
     """The FP64 oracle (single-threaded C) on host cores: ms per frame on a bounded sample."""
     from oracle import Oracle
@@ -475,6 +517,8 @@ def main():
     dom = max(SINGLE_KERNEL, key=lambda st: per_frame[st] * us[st])
     achieved = sel[dom] * elem / (us[dom] * 1e-6) / 1e9
     traffic = recorded_traffic(dom, cfg["name"])
+    h2d = h2d_upload(stream, S[0])
+    copy_gbps = copy_bandwidth(stream)
     if args.copy_calibration:
         import torch
         src = torch.empty(64 << 20, dtype=torch.float32, device=P.device).fill_(1.0)
@@ -505,6 +549,10 @@ def main():
         "effective_GBps": round(eff_gbps, 1),
         "frac_hbm_peak": round(eff_gbps / HBM_PEAK_GBPS, 4),
         "bytes_per_frame": model["frame"],
+        "copy_GBps": copy_gbps,
+        "frac_of_copy_bw": round(eff_gbps / copy_gbps, 4),
+        "h2d": h2d,
+        "ms_per_frame_with_h2d": round(ms_mean + h2d["us_per_frame"] * 1e-3, 5),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                      "kernel": STAGE_KERNELS[dom], "us_per_launch": round(us[dom], 3),
