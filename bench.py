@@ -356,7 +356,7 @@ def batch_scan(args):
     n_iter, gain = cfg["n_iter"], cfg["gain"]
     model = byte_model(cfg, 4, n_iter)
     rows = []
-    for nb in (1, 2, 4, 8, 16, 32):
+    for nb in (1, 2, 4, 8, 16, 32, 64, 128):
         PB = fewha.Plan(cfg, max_batch=nb)
         P1 = PB if nb == 1 else fewha.Plan(cfg)
         S = []
