@@ -35,6 +35,12 @@
  * Errors: every call returns FEWHA_OK (0) or a negative fewha_status; nothing is thrown across
  * the ABI.  Numerical failures inside a solve (PCG breakdown, non-finite reductions) are
  * recorded in a device status word that fewha_last_status reads after the caller synchronises.
+ * With the environment variable FEWHA_DEBUG set, a FEWHA_ERR_HIP return also prints the failing
+ * HIP call or launch, its source location and HIP's error string on stderr.
+ *
+ * HIP runtime: the library must run on the HIP runtime of the process that owns the device.
+ * Loaded into a process that already has one (e.g. PyTorch's), it binds to it through the
+ * shared soname; the Python binding imports torch before loading the library for that reason.
  */
 #ifndef FEWHA_H
 #define FEWHA_H

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstdint>
 #include <cstring>
 #include <new>
@@ -69,10 +71,21 @@ Ops<T> ops(const Plan &P, void *stream, int nb = 1) {
         if (_e != FEWHA_OK) return _e;  \
     } while (0)
 
-#define HIPTRY(x)                                          \
-    do {                                                   \
-        if ((x) != hipSuccess) return FEWHA_ERR_HIP;       \
+#define HIPTRY(x)                                                       \
+    do {                                                                \
+        const hipError_t _h = (x);                                      \
+        if (_h != hipSuccess) return hip_failure(_h, #x, __FILE__, __LINE__); \
     } while (0)
+
+}  // namespace
+
+int fewha::hip_failure(hipError_t e, const char *what, const char *file, int line) {
+    if (std::getenv("FEWHA_DEBUG"))
+        std::fprintf(stderr, "fewha: %s failed at %s:%d: %s\n", what, file, line, hipGetErrorString(e));
+    return FEWHA_ERR_HIP;
+}
+
+namespace {
 
 int ready(const fewha_plan *p) {
     if (!p) return FEWHA_ERR_INVALID_ARG;

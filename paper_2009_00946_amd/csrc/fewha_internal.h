@@ -215,6 +215,10 @@ struct Plan {
 
 // plan.cpp (host only)
 int plan_create(const fewha_config *cfg, Plan **out);
+// A failed HIP call or launch: with FEWHA_DEBUG set in the environment, names it on stderr
+// (call, source location, HIP's error string); returns FEWHA_ERR_HIP.
+int hip_failure(hipError_t e, const char *what, const char *file, int line);
+
 void layout_workspace(Plan *P);
 int level_band(int n, int J, int row, int col, int *s, int *o);
 // Inverse-DWT cone of a tile: level-s region origins / sizes (level-s index space), s = 0..J.

@@ -1570,7 +1570,11 @@ int grid_for(long n) {
     return (int)g;
 }
 
-int check() { return hipGetLastError() == hipSuccess ? FEWHA_OK : FEWHA_ERR_HIP; }
+int launch_status(const char *file, int line) {
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FEWHA_OK : hip_failure(e, "kernel launch", file, line);
+}
+#define check() launch_status(__FILE__, __LINE__)
 
 InvVar inv_var_tab(const Plan &P) {
     InvVar t{};

@@ -63,6 +63,10 @@ def load_library():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("libfewha.so is not built (run python -m paper_2009_00946_amd.build)")
+    # torch first: the library then binds to the HIP runtime torch has loaded (same soname), so
+    # the process has one runtime.  Loaded first, the library would bring a second runtime that
+    # does not see the device torch has opened.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp, sz = ctypes.c_void_p, ctypes.c_size_t
     L.fewha_plan_create.argtypes = [ctypes.POINTER(_Config), ctypes.POINTER(vp)]

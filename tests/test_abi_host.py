@@ -126,3 +126,16 @@ def test_no_cpu_fallback_in_binding():
     src = open(os.path.join(ROOT, "paper_2009_00946_amd", "fewha.py")).read()
     assert "oracle" not in src
     assert "numpy" not in src.split("def precond_table")[0]
+
+
+def test_library_shares_torchs_hip_runtime():
+    """Loading the library through the binding, even before torch is imported, maps a single HIP
+    runtime into the process (the one torch loads)."""
+    import subprocess
+    import sys
+    code = ("import paper_2009_00946_amd.fewha as F; F.load_library(); "
+            "print(len({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip().splitlines()[-1] == "1"
