@@ -38,6 +38,7 @@ ALPHA_REG = {
     "c3_mid_lgs": 0.110,
     "c4_stress": 0.173,
     "t1_mixed": 0.0692,
+    "maory_paper": 0.162,
 }
 
 
@@ -175,7 +176,33 @@ def t1_mixed():
                 seed=1005, r0=0.15, L0=25.0, wfs=wfs, layers=layers, dms=dms)
 
 
-ALL = [c0_tiny, c1_elt_mcao, c3_mid_lgs, c4_stress, t1_mixed]
+def maory_paper():
+    """The paper's own test configuration at the size of its first timed runs (Sec. 5 parameter
+    table; Sec. 6: L = M = 6, 4 PCG iterations): D = 39 m, about 28 % obstructed, six LGS
+    sensors of 80 x 80, one NGS of 2 x 2 and two of 1 x 1, LGS and NGS on 2' and 8/3' diameters,
+    128^2 layer grids, DM 1 with 81^2 actuators, DMs 2-5 with 48^2 and DM 6 with 54^2.
+    Readings for what the table leaves open: LGS at 90 km on a hexagon, NGS on a triangle at
+    30/150/270 deg; layers at 0, 2.5, 5, 7.5, 10 and 15 km, 0.5 m spacing; DM 1 at 0 km with the
+    subaperture pitch, DMs 2-6 at the layer heights 2.5-15 km covering the 1' field."""
+    D = 39.0
+    wfs = [dict(n_sub=80, theta_x=tx, theta_y=ty, gs_height=90000.0, sigma=0.05)
+           for tx, ty in _ring(ARCMIN, [0, 60, 120, 180, 240, 300])]
+    wfs += [dict(n_sub=ns, theta_x=tx, theta_y=ty, gs_height=0.0, sigma=0.05)
+            for ns, (tx, ty) in zip((2, 1, 1), _ring(80 * ARCSEC, [30, 150, 270]))]
+    heights = [0.0, 2500.0, 5000.0, 7500.0, 10000.0, 15000.0]
+    layers = [dict(height=h, cn2_weight=g, n=128, spacing=0.5, flow=[1, 0]) for h, g in zip(heights, _cn2(heights))]
+    dms = [dict(height=0.0, n_act=81, pitch=D / 80)]
+    dms += [dict(height=h, n_act=48, pitch=_dm_pitch(D, h, 48)) for h in heights[1:5]]
+    dms += [dict(height=heights[5], n_act=54, pitch=_dm_pitch(D, heights[5], 54))]
+    return dict(name="maory_paper",
+                description="the paper's MAORY-like test configuration, FP32: D=39 m (28% obstructed), 6 LGS 80x80 "
+                            "+ NGS 2x2 + 2 NGS 1x1, L = M = 6 (128^2 grids, J=6), DMs 81^2/4x48^2/54^2, "
+                            "4 warm PCG iterations",
+                D=D, obstruction=0.28, J=6, precision="fp32", n_iter=4, warm=True, gain=1.0,
+                seed=1006, r0=0.15, L0=25.0, wfs=wfs, layers=layers, dms=dms)
+
+
+ALL = [c0_tiny, c1_elt_mcao, c3_mid_lgs, c4_stress, t1_mixed, maory_paper]
 
 
 def main():

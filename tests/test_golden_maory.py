@@ -3,10 +3,8 @@ tests/golden/maory_parameters.txt) at the size of its first runs (Sec. 6: L = M 
 iterations): the plan's and the oracle's vector sizes against the matrix dimensions the paper
 prints (Sec. 2.3), and (GPU) a cold frame with fitting against the oracle.
 
-Readings beyond the printed values: LGS at 90 km on a hexagon of the printed diameter, NGS on a
-triangle of theirs; layers at 0, 2.5, 5, 7.5, 10 and 15 km on 128^2 grids at 0.5 m; DM 1 at 0 km
-with the subaperture pitch, DMs 2-5 at the layer heights 2.5-10 km and DM 6 at 15 km, pitched to
-cover the 25 probe directions (+-1 arcmin); slope noise 0.05 rad.  With 28 % obstruction the 1x1
+The configuration is `maory_paper` (written by configs/make_configs.py, which states its readings
+of what the table leaves open); the first test pins it to the printed values.  With 28 % obstruction the 1x1
 sensors' only subaperture is centred on the obstruction, so those two sensors have no active
 slope: a degenerate case the frame must carry."""
 import math
@@ -30,35 +28,27 @@ def golden():
 
 
 def maory_config():
-    G = golden()
-    D, L = G["telescope_diameter_m"], int(G["first_runs_layers"])
-    r_lgs = G["lgs_separation_diameter_arcmin"] * 60 / 2 * AS
-    r_ngs = G["ngs_separation_diameter_arcmin"] * 60 / 2 * AS
-    wfs = []
-    for k in range(int(G["n_lgs"])):
-        a = 2 * math.pi * k / G["n_lgs"]
-        wfs.append({"n_sub": int(G["n_sub_wfs_1_6"]), "theta_x": r_lgs * math.cos(a), "theta_y": r_lgs * math.sin(a),
-                    "gs_height": 90000.0, "sigma": 0.05})
-    for k, ns in enumerate((G["n_sub_wfs_7"], G["n_sub_wfs_8_9"], G["n_sub_wfs_8_9"])):
-        a = 2 * math.pi * k / 3 + math.pi / 6
-        wfs.append({"n_sub": int(ns), "theta_x": r_ngs * math.cos(a), "theta_y": r_ngs * math.sin(a),
-                    "gs_height": 0.0, "sigma": 0.05})
-    heights = [0.0, 2500.0, 5000.0, 7500.0, 10000.0, 15000.0][:L]
-    w = np.exp(-np.array(heights) / 4000.0)
-    w /= w.sum()
-    layers = [{"height": h, "cn2_weight": float(g), "n": int(G["n_lay"]), "spacing": 0.5, "flow": [1, 0]}
-              for h, g in zip(heights, w)]
-    probe = 60 * AS
-    dms = [{"height": 0.0, "n_act": int(G["n_act_dm_1"]), "pitch": D / G["n_sub_wfs_1_6"]}]
-    for h in heights[1:5]:
-        n = int(G["n_act_dm_2_5"])
-        dms.append({"height": h, "n_act": n, "pitch": (D + 2 * h * probe) / (n - 1)})
-    n = int(G["n_act_dm_6_9"])
-    dms.append({"height": heights[5], "n_act": n, "pitch": (D + 2 * heights[5] * probe) / (n - 1)})
-    return {"name": "maory_paper", "description": "the paper's MAORY-like configuration, L = M = 6",
-            "D": D, "obstruction": G["obstruction_fraction"], "J": 6, "precision": "fp64",
-            "n_iter": int(G["first_runs_n_iter"]), "warm": False, "gain": 1.0, "seed": 1200, "r0": 0.15,
-            "L0": 25.0, "layers": layers, "wfs": wfs, "dms": dms, "alpha_reg": 0.1}
+    from paper_2009_00946_amd import synth
+    return synth.load_config("maory_paper")
+
+
+def test_configuration_holds_the_printed_values():
+    G, cfg = golden(), maory_config()
+    ns = [w["n_sub"] for w in cfg["wfs"]]
+    assert cfg["D"] == G["telescope_diameter_m"] and cfg["obstruction"] == G["obstruction_fraction"]
+    assert len(ns) == G["n_wfs"] and cfg["n_iter"] == G["first_runs_n_iter"]
+    assert ns == [G["n_sub_wfs_1_6"]] * 6 + [G["n_sub_wfs_7"]] + [G["n_sub_wfs_8_9"]] * 2
+    lgs = [w for w in cfg["wfs"] if w["gs_height"] > 0]
+    ngs = [w for w in cfg["wfs"] if w["gs_height"] == 0]
+    assert (len(lgs), len(ngs)) == (G["n_lgs"], G["n_ngs"])
+    for group, diam in ((lgs, G["lgs_separation_diameter_arcmin"]), (ngs, G["ngs_separation_diameter_arcmin"])):
+        for w in group:
+            assert abs(2 * math.hypot(w["theta_x"], w["theta_y"]) / (60 * AS) - diam) < 1e-12
+    assert len(cfg["layers"]) == len(cfg["dms"]) == G["first_runs_layers"]
+    lo, hi = G["n_layers_range"]
+    assert lo <= len(cfg["layers"]) <= hi
+    assert all(l["n"] == G["n_lay"] for l in cfg["layers"])
+    assert [d["n_act"] for d in cfg["dms"]] == [G["n_act_dm_1"]] + [G["n_act_dm_2_5"]] * 4 + [G["n_act_dm_6_9"]]
 
 
 def test_sizes_follow_the_printed_dimensions():
@@ -100,7 +90,7 @@ def test_paper_configuration_frame():
     from paper_2009_00946_amd import fewha, synth
     cfg = maory_config()
     O = Oracle(cfg)
-    P = fewha.Plan(cfg, precision="fp64")
+    P = fewha.Plan(cfg, precision="fp64")  # the configuration's bench precision is FP32
     s = O.Ahat(synth.layer_screens_flat(cfg, 0)) + O.slope_mask() * synth.slope_noise(cfg, 0)
     z = np.zeros(P.n_coef)
     c_ref = O.frame(s, z, z, z, cfg["n_iter"], True)[0]

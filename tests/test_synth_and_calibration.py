@@ -86,7 +86,7 @@ def calibrate_alpha(cfg, n_screens=16):
     return 1.0 / np.median([np.mean(v) for v in acc.values()])
 
 
-@pytest.mark.parametrize("name", ["c0_tiny", "t1_mixed", "c3_mid_lgs", "c1_elt_mcao"])
+@pytest.mark.parametrize("name", ["c0_tiny", "t1_mixed", "c3_mid_lgs", "c1_elt_mcao", "maory_paper"])
 def test_alpha_reg_is_the_documented_calibration(name):
     cfg = synth.load_config(name)
     assert abs(calibrate_alpha(cfg) / cfg["alpha_reg"] - 1) < 0.01
