@@ -749,35 +749,34 @@ __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restr
     }
     lds_fence();
 
+    // All RW x RW pairs of a guide star are summed without per-pair conditions, so that its
+    // LDS reads issue together: the pairs past a line's count are padding (index -1, weight 0)
+    // and the clamps send them to the rectangle's first row / column, adding exact zeros.  Only a
+    // guide star with no rectangle on this tile is skipped.
     const int a = tid >> 4, b = tid & 15;
     if (a < T0 && b < T0) {
         T acc = 0;
         for (int g = 0; g < nw; ++g) {
             const int pg = __builtin_amdgcn_readlane(pitch, g);
-            const int cy = __builtin_amdgcn_readlane(rec.z, g), cx = __builtin_amdgcn_readlane(rec.w, g);
+            if (pg == 0) continue;
             const int ra = __builtin_amdgcn_readlane(iA, g), cg = __builtin_amdgcn_readlane(c0, g);
             const T *Vg = sV + __builtin_amdgcn_readlane(sbase, g) - ra * pg - cg;
             int jx[RW];
             T wx[RW];
 #pragma unroll
             for (int e = 0; e < RW; ++e) {
-                if (e < cx) {
-                    const RtabEnt<T> p = sP[g][0][e][b];
-                    jx[e] = max(p.idx, cg);  // padding (index -1) has weight 0
-                    wx[e] = p.w;
-                }
+                const RtabEnt<T> p = sP[g][0][e][b];
+                jx[e] = max(p.idx, cg);
+                wx[e] = p.w;
             }
 #pragma unroll
             for (int ea = 0; ea < RW; ++ea) {
-                if (ea < cy) {
-                    const RtabEnt<T> p = sP[g][1][ea][a];
-                    const T *Vr = Vg + max(p.idx, ra) * pg;
-                    T t = 0;
+                const RtabEnt<T> p = sP[g][1][ea][a];
+                const T *Vr = Vg + max(p.idx, ra) * pg;
+                T t = 0;
 #pragma unroll
-                    for (int eb = 0; eb < RW; ++eb)
-                        if (eb < cx) t += wx[eb] * Vr[jx[eb]];
-                    acc += p.w * t;
-                }
+                for (int eb = 0; eb < RW; ++eb) t += wx[eb] * Vr[jx[eb]];
+                acc += p.w * t;
             }
         }
         x[id.off + (long)(k0 + a) * n + q0 + b] = acc;
