@@ -550,14 +550,16 @@ __global__ __launch_bounds__(kB) void k_proj(SegTab S, LayTab LT, InvVar IV, Pup
             uv[c][2] = U[n];
             uv[c][3] = U[n + 1];
         }
+        // every slot reads its weights (at the clamped layer, like its values) and slots past the
+        // last layer are zeroed by a uniform factor instead of a branch, so that the weight reads
+        // of all slots issue together
 #pragma unroll
         for (int c = 0; c < kProjLch; ++c) {
-            const int l = l0 + c;
-            if (l < nl) {
-                const T wy0 = sW0[1][l][a], wy1 = sW1[1][l][a], wx0 = sW0[0][l][b], wx1 = sW1[0][l][b];
-                phi += (wy0 * wx0) * uv[c][0] + (wy0 * wx1) * uv[c][1] + (wy1 * wx0) * uv[c][2] +
-                       (wy1 * wx1) * uv[c][3];  // (garbage on rows outside the grid: sPhi drops it)
-            }
+            const int l = min(l0 + c, nl - 1);
+            const T keep = l0 + c < nl ? (T)1 : (T)0;
+            const T wy0 = sW0[1][l][a] * keep, wy1 = sW1[1][l][a] * keep, wx0 = sW0[0][l][b], wx1 = sW1[0][l][b];
+            phi += (wy0 * wx0) * uv[c][0] + (wy0 * wx1) * uv[c][1] + (wy1 * wx0) * uv[c][2] +
+                   (wy1 * wx1) * uv[c][3];  // (garbage on rows outside the grid: sPhi drops it)
         }
     }
     sPhi[tid] = node ? phi : (T)0;
