@@ -1134,6 +1134,56 @@ __global__ __launch_bounds__(kCB) void k_coarse(LayTab LT, Bufs<T> B, FwdArgs E,
 #pragma unroll
             for (int o = 0; o < 4; ++o) ji[o] = sW[kMaxJ + 1 + 4 * s + o];
         }
+        if (4 * nq <= kCB) {
+            // a small level: four lanes per quad, lane o = tid & 3 computes band o alone with the
+            // same two filter passes (so the same coefficient value) and delivers it; one lane's
+            // work per level is then a quarter of a quad's
+            const int qi = tid >> 2, o = tid & 3;
+            if (4 * nq > (tid & ~63)) {  // the wave holds quads
+                const bool act = qi < nq, deliver = o > 0 || s == J;
+                const int r = act ? qi / h : 0, q = act ? qi - r * h : 0;
+                const int br = r + (o >= 2 ? h : 0), bc = q + ((o & 1) ? h : 0);
+                T op1[NOP > 0 ? NOP : 1];
+                if (NOP > 0) {
+                    if constexpr (pre) {
+#pragma unroll
+                        for (int j = 0; j < (NOP > 0 ? NOP : 1); ++j) op1[j] = opl[j * mm + br * m0 + bc];
+                        if (EPI == kEpiPcg && E.k == 0) op1[2] = op1[3] = (T)0;
+                        if (EPI == kEpiRhs && E.cold) op1[0] = op1[1] = (T)0;
+                    } else {
+                        epi_load<T, EPI>(B, E, coff + (long)br * n + bc, op1);
+                    }
+                }
+                if (act) {
+                    T fy[6], fx[6];  // the band's filters along y (rows) and x (columns)
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) {
+                        fy[k] = o >= 2 ? tp.g[k] : tp.h[k];
+                        fx[k] = (o & 1) ? tp.g[k] : tp.h[k];
+                    }
+                    T w = 0;
+                    auto band = [&](const T *src) {
+#pragma unroll
+                        for (int a = 0; a < 6; ++a) {
+                            const T *row = src + ((2 * r + a) & msk) * mi;
+                            T acc = 0;
+#pragma unroll
+                            for (int b = 0; b < 6; ++b) acc += fx[b] * row[(2 * q + b) & msk];
+                            w += fy[a] * acc;
+                        }
+                    };
+                    if constexpr (gin) {
+                        if (s == KF + 1) band(llin);
+                        else band(cs);
+                    } else {
+                        band(cs);
+                    }
+                    const T jio = o == 0 ? ji[0] : (o == 1 ? ji[1] : (o == 2 ? ji[2] : ji[3]));
+                    if (deliver) epi_store<T, EPI>(B, E, band_index(coff, n, s, o, r, q), w, op1, jio, ad, so, rho, dz);
+                    else cd[r * h + q] = w;
+                }
+            }
+        } else
         for (int q0 = 0; q0 < nq; q0 += kCB) {
             if (q0 + (tid & ~63) >= nq) break;  // no quad of this level left for the wave
             const int qi = q0 + tid;
