@@ -1134,10 +1134,11 @@ __global__ __launch_bounds__(kCB) void k_coarse(LayTab LT, Bufs<T> B, FwdArgs E,
 #pragma unroll
             for (int o = 0; o < 4; ++o) ji[o] = sW[kMaxJ + 1 + 4 * s + o];
         }
-        if (4 * nq <= kCB) {
+        if (sizeof(T) == 4 && 4 * nq <= kCB) {
             // a small level: four lanes per quad, lane o = tid & 3 computes band o alone with the
             // same two filter passes (so the same coefficient value) and delivers it; one lane's
-            // work per level is then a quarter of a quad's
+            // work per level is then a quarter of a quad's (FP32 only: in FP64 the band's filters
+            // push this kernel into register spills)
             const int qi = tid >> 2, o = tid & 3;
             if (4 * nq > (tid & ~63)) {  // the wave holds quads
                 const bool act = qi < nq, deliver = o > 0 || s == J;
