@@ -93,3 +93,15 @@ def test_ls_fit_zero_steps_and_zero_input():
     # zero layers: r = 0 at the start and every step leaves x = 0
     got0 = P.fit_dm_ls(P.zeros(P.n_coef), None, 1.0, 10, EPS).double().cpu().numpy()
     assert np.array_equal(got0, np.zeros(P.n_act))
+
+
+def test_ls_fit_rejects_invalid_arguments():
+    O, P, c = _setup("c0_tiny", "fp64")
+    from paper_2009_00946_amd import fewha
+    cd = _dev(P, c)
+    for kw in ({"n_cg": -1}, {"eps": -1e-3}, {"eps": float("inf")}, {"gain": float("nan")}):
+        args = {"n_cg": 5, "eps": EPS, "gain": 1.0}
+        args.update(kw)
+        with pytest.raises(fewha.FewhaError) as e:
+            P.fit_dm_ls(cd, None, args["gain"], args["n_cg"], args["eps"])
+        assert e.value.status == -1, kw
