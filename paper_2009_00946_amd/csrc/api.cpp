@@ -54,7 +54,7 @@ Bufs<T> bufs(const Plan &P) {
     b.fs_v = (long)P.n_nodes;
     b.fs_s = (long)P.n_slopes;
     b.fs_a = (long)P.n_act;
-    b.fs_ll = (long)(P.n_coef / 4 + 1);
+    b.fs_ll = (long)ll_stride(P.n_coef);
     return b;
 }
 

@@ -219,6 +219,10 @@ int plan_create(const fewha_config *cfg, Plan **out);
 // (call, source location, HIP's error string); returns FEWHA_ERR_HIP.
 int hip_failure(hipError_t e, const char *what, const char *file, int line);
 
+// Values per frame of the level-kf approximation region (at most n_coef / 4 plus one), rounded up
+// to a multiple of 4 so that every frame's blocks start 16-byte aligned.
+inline size_t ll_stride(size_t n_coef) { return (n_coef / 4 + 1 + 3) & ~size_t(3); }
+
 void layout_workspace(Plan *P);
 int level_band(int n, int J, int row, int col, int *s, int *o);
 // Inverse-DWT cone of a tile: level-s region origins / sizes (level-s index space), s = 0..J.

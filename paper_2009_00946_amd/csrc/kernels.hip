@@ -1075,12 +1075,19 @@ __global__ __launch_bounds__(kCB) void k_coarse(LayTab LT, Bufs<T> B, FwdArgs E,
     const T adv = EPI != kEpiPlain ? B.ad[l * (J + 1) + min(tid, J)] : (T)0;
     const T jiv = (EPI == kEpiPcg || EPI == kEpiRhs) ? B.jinv[l * (J + 1) * 4 + min(tid, 4 * (J + 1) - 1)] : (T)0;
     if constexpr (!gin) {
+        if constexpr (sizeof(T) == 4) {
+            // 16-byte copies: lane chunk k4 holds values 4 k4 .. 4 k4 + 3 (the block is contiguous
+            // in the workspace, 16-byte aligned)
 #pragma unroll
-        for (int c = 0; c < NL; ++c) {
-            const int k = tid + c * kCB;
-            if (c * kCB < mm && k < mm) {
-                if constexpr (sizeof(T) == 4) g2lds(llin + k, cs + c * kCB + (tid & ~63));
-                else cs[k] = llin[k];
+            for (int c = 0; c < NL / 4; ++c) {
+                const int k4 = tid + c * kCB;
+                if (4 * c * kCB < mm && 4 * k4 < mm) g2lds16(llin + 4 * k4, cs + 4 * (c * kCB + (tid & ~63)));
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < NL; ++c) {
+                const int k = tid + c * kCB;
+                if (c * kCB < mm && k < mm) cs[k] = llin[k];
             }
         }
     }
@@ -1106,13 +1113,26 @@ __global__ __launch_bounds__(kCB) void k_coarse(LayTab LT, Bufs<T> B, FwdArgs E,
 #pragma unroll
         for (int j = 0; j < (NOP > 0 ? NOP : 1); ++j) {
             if (j < nsrc) {
+                if (sizeof(T) == 4 && m0 >= 4 && ((EPI == kEpiPcg && j != 1) || EPI == kEpiRhs)) {
+                    // workspace operands (pcg r, p, q; rhs b_prev, r; never the caller's vectors):
+                    // 16-byte copies of four values of one row (rows of m0 >= 4 values at 16-byte
+                    // aligned offsets)
 #pragma unroll
-                for (int c = 0; c < NL; ++c) {
-                    const int k = tid + c * kCB;
-                    if (c * kCB < mm && k < mm) {
-                        const T *gp = srcs[j] + coff + (long)(k >> lm) * n + (k & (m0 - 1));
-                        if constexpr (sizeof(T) == 4) g2lds(gp, opl + j * mm + c * kCB + (tid & ~63));
-                        else opl[j * mm + k] = *gp;
+                    for (int c = 0; c < NL / 4; ++c) {
+                        const int k = 4 * (tid + c * kCB);
+                        if (4 * c * kCB < mm && k < mm)
+                            g2lds16(reinterpret_cast<const float *>(srcs[j] + coff + (long)(k >> lm) * n + (k & (m0 - 1))),
+                                    reinterpret_cast<float *>(opl + j * mm + 4 * (c * kCB + (tid & ~63))));
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < NL; ++c) {
+                        const int k = tid + c * kCB;
+                        if (c * kCB < mm && k < mm) {
+                            const T *gp = srcs[j] + coff + (long)(k >> lm) * n + (k & (m0 - 1));
+                            if constexpr (sizeof(T) == 4) g2lds(gp, opl + j * mm + c * kCB + (tid & ~63));
+                            else opl[j * mm + k] = *gp;
+                        }
                     }
                 }
             }

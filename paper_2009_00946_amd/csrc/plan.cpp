@@ -103,7 +103,7 @@ void layout_workspace(Plan *P) {
     P->o_u = take(E * N * MB);
     P->o_x = take(E * N * MB);
     P->o_v = take(E * P->n_nodes * MB);
-    P->o_ll = take(E * (N / 4 + 1) * MB);
+    P->o_ll = take(E * ll_stride(N) * MB);
     P->o_probe_c = take(E * N);
     P->o_stage = take(4 * E * N);  // stage timing: scratch r, p, q, c
     P->o_probe_s = take(E * P->n_slopes);
