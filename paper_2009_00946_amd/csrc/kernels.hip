@@ -304,6 +304,11 @@ __device__ __forceinline__ void g2lds(const float *gp, float *wave_base) {
     __builtin_amdgcn_global_load_lds(gp, (__attribute__((address_space(3))) void *)wave_base, 4, 0, 0);
 }
 
+// The same with 16 bytes (four floats) per lane, to wave_base + 16 lane bytes.
+__device__ __forceinline__ void g2lds16(const float *gp, float *wave_base) {
+    __builtin_amdgcn_global_load_lds(gp, (__attribute__((address_space(3))) void *)wave_base, 16, 0, 0);
+}
+
 __device__ __forceinline__ void lds_fence() {
     __builtin_amdgcn_s_waitcnt(0);  // every outstanding load, including those into LDS
     __syncthreads();
@@ -314,7 +319,7 @@ enum { kWtPlain = 0, kWtPcg = 1 };
 template <typename T, int MODE>
 __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src, T *__restrict__ out, Bufs<T> B,
                                            Taps<T> tp, int J) {
-    __shared__ T sCone[kWtSlots * kWB];
+    __shared__ __attribute__((aligned(16))) T sCone[kWtSlots * kWB];
     __shared__ T sLL[2][kWtLL];
     __shared__ T sXl[kWtX], sXh[kWtX];
     __shared__ T sJi[(kMaxJ + 1) * 4];
@@ -340,7 +345,7 @@ __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src,
         for (int s = 1; s <= kMaxJ; ++s) {
             ly = ((ly >> 1) - 2) & ~1;
             hy >>= 1;
-            lx = ((lx >> 1) - 2) & ~1;
+            lx = ((lx >> 1) - 2) & (s == 1 ? ~3 : ~1);  // level 1 starts on a multiple of 4 (16-byte copies)
             hx >>= 1;
             loY[s] = ly;
             loX[s] = lx;
@@ -353,10 +358,31 @@ __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src,
     if (MODE == kWtPcg) jl = B.jinv[l * (J + 1) * 4 + min(tid, (J + 1) * 4 - 1)];
 
     // ---- one batch of independent loads: the whole cone, straight into LDS ----
+    // Levels 1 and 2 (most of the cone) arrive in 16-byte copies when the source is 16-byte
+    // aligned and the level's column start is a multiple of 4: lane i of a 4-slot pass copies the
+    // four values 4i..4i+3 of the same row-major slot block (pitch 2^lp), so the layout is that of
+    // the 4-byte copies.  Rows past the cone's bands are not copied, so a pass never writes into
+    // the next level's slots.
+    const bool src16 = sizeof(T) == 4 && (reinterpret_cast<uintptr_t>(src) & 15) == 0;
 #pragma unroll
     for (int s = 1; s <= kMaxJ; ++s) {
         if (s <= J) {
             const int lp = wt_lanes_log2(s), ly = LY[s], lx = LX[s], m = n >> s, mk = m - 1;
+            if (s <= 2 && src16 && m >= 4 && (loX[s] & 3) == 0) {
+                const int lq = lp - 2;  // 4-value chunks per row, log2
+#pragma unroll
+                for (int p4 = 0; p4 < (wt_passes(s) + 3) / 4; ++p4) {
+                    const int rowi = (tid >> lq) + p4 * (kWB >> lq), q = 4 * (tid & ((1 << lq) - 1));
+                    const int bi = (rowi >= ly) + (rowi >= 2 * ly) + (rowi >= 3 * ly);
+                    const int r = rowi - bi * ly, o = bi == 3 ? 0 : bi + 1;
+                    const int gr = ((loY[s] + r) & mk) + (o >= 2 ? m : 0);
+                    const int gc = ((loX[s] + q) & mk) + ((o & 1) ? m : 0);
+                    if (q < lx && rowi < (s == J ? 4 : 3) * ly)
+                        g2lds16(reinterpret_cast<const float *>(src + coff + (long)gr * n + gc),
+                                reinterpret_cast<float *>(sCone + (wt_slot0(s) + 4 * p4) * kWB + 4 * (tid & ~63)));
+                }
+                continue;
+            }
 #pragma unroll
             for (int p = 0; p < wt_passes(s); ++p) {
                 const int rowi = (tid >> lp) + p * (kWB >> lp), q = tid & ((1 << lp) - 1);
@@ -661,9 +687,6 @@ __global__ __launch_bounds__(kB) void k_gt(SegTab S, InvVar IV, PupilArgs pa, co
 //   x(k, q) = sum_g sum_{(i, wy) in row k} wy sum_{(j, wx) in column q} wx v_g(i, j)
 // from LDS, with loop bounds uniform over the tile (missing pairs carry weight 0).  The pairs are
 // the very matrix entries P uses, so P^T is P's exact transpose.
-__device__ __forceinline__ void g2lds16(const float *gp, float *wave_base) {
-    __builtin_amdgcn_global_load_lds(gp, (__attribute__((address_space(3))) void *)wave_base, 16, 0, 0);
-}
 
 template <typename T>
 __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restrict__ v, T *__restrict__ x, Bufs<T> B,
