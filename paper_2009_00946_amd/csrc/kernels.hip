@@ -1136,10 +1136,10 @@ __global__ __launch_bounds__(kCB) void k_coarse(LayTab LT, Bufs<T> B, FwdArgs E,
 #pragma unroll
         for (int j = 0; j < (NOP > 0 ? NOP : 1); ++j) {
             if (j < nsrc) {
-                if (sizeof(T) == 4 && m0 >= 4 && ((EPI == kEpiPcg && j != 1) || EPI == kEpiRhs)) {
-                    // workspace operands (pcg r, p, q; rhs b_prev, r; never the caller's vectors):
-                    // 16-byte copies of four values of one row (rows of m0 >= 4 values at 16-byte
-                    // aligned offsets)
+                if (sizeof(T) == 4 && m0 >= 4 && (reinterpret_cast<uintptr_t>(srcs[j]) & 15) == 0) {
+                    // a 16-byte aligned operand (the workspace's always; the caller's when its
+                    // vector is): 16-byte copies of four values of one row (rows of m0 >= 4 values
+                    // at offsets that are multiples of 4)
 #pragma unroll
                     for (int c = 0; c < NL / 4; ++c) {
                         const int k = 4 * (tid + c * kCB);
