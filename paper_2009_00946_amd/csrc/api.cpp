@@ -126,7 +126,7 @@ int apply_M(const Plan &P, const void *c, void *y, void *stream, int nb = 1) {
 template <typename T>
 int pcg_passes(const Plan &P, const Ops<T> &o, void *c, int n_iter, double *resnorm) {
     // partial sums of (r, z) and (z, alpha D z) come from the forward transforms that write r
-    const int nres = P.n_fwd + (P.kf < P.J ? P.nl : 0);
+    const int nres = residual_partials(P);
     for (int k = 0; k < n_iter; ++k) {
         TRY(o.wt_pcg(o.B.r, o.B.u));             // u = W^T J^-1 r
         TRY(o.proj(o.B.u, o.B.v, kProjM));       // v = Gamma^T C Gamma P u; (C Gamma P u, Gamma P u) partials
@@ -212,7 +212,7 @@ int stage_launch(const Plan &P, int stage, void *stream) {
         case FEWHA_STAGE_WT: return o.wt_pcg(o.B.r, o.B.u);
         case FEWHA_STAGE_PROJ: return o.proj(o.B.u, o.B.v, kProjM);
         case FEWHA_STAGE_PT:
-            return o.pt(o.B.v, o.B.x, PassArgs{1, P.n_fwd + (P.kf < P.J ? P.nl : 0), P.n_proj, 0, nullptr, 0});
+            return o.pt(o.B.v, o.B.x, PassArgs{1, residual_partials(P), P.n_proj, 0, nullptr, 0});
         default: {
             // the frame's y = W x + alpha D z with the pass update, applied to scratch copies of
             // r, p, q and c, without publishing scalars

@@ -219,6 +219,13 @@ int plan_create(const fewha_config *cfg, Plan **out);
 // (call, source location, HIP's error string); returns FEWHA_ERR_HIP.
 int hip_failure(hipError_t e, const char *what, const char *file, int line);
 
+// Waves of a coarse forward-DWT workgroup: each leaves its own pair of residual partials.
+constexpr int kCoarseWaves = 16;
+
+// Residual partial pairs a pass leaves for the next scalar step: one per fine forward-DWT tile and
+// one per wave of every layer's coarse workgroup.
+inline int residual_partials(const Plan &P) { return P.n_fwd + (P.kf < P.J ? P.nl * kCoarseWaves : 0); }
+
 // Values per frame of the level-kf approximation region (at most n_coef / 4 plus one), rounded up
 // to a multiple of 4 so that every frame's blocks start 16-byte aligned.
 inline size_t ll_stride(size_t n_coef) { return (n_coef / 4 + 1 + 3) & ~size_t(3); }

@@ -1287,11 +1287,15 @@ __global__ __launch_bounds__(kCB) void k_coarse(LayTab LT, Bufs<T> B, FwdArgs E,
         cd = t;
     }
     if constexpr (EPI == kEpiPcg || EPI == kEpiRhs) {
-        __shared__ double sRed[2 * (kCB / 64)];
-        block_sum2(rho, dz, sRed);
-        if (tid == 0) {  // slots after the fine tiles' partials
-            B.partials[nfine + l] = rho;
-            B.partials[kPartialPitch + nfine + l] = dz;
+        // one partial pair per wave, no block reduction: slots after the fine tiles' partials,
+        // kCoarseWaves per layer (every wave writes its own, also when it delivered nothing)
+        static_assert(kCB / 64 == kCoarseWaves, "one partial slot per wave of the coarse workgroup");
+        rho = wave_sum(rho);
+        dz = wave_sum(dz);
+        if ((tid & 63) == 0) {
+            const int slot = nfine + l * kCoarseWaves + (tid >> 6);
+            B.partials[slot] = rho;
+            B.partials[kPartialPitch + slot] = dz;
         }
     }
 }
