@@ -32,7 +32,7 @@ constexpr int kPtStage = 6144;
 // Guide stars whose transpose tables the P^T tile stages at once (more: the scanning P^T).
 constexpr int kPtMaxWfs = 16;
 // Slots per row of the FP64 partial-sum buffer (one per workgroup of a reduction).
-constexpr int kPartialPitch = 4096;
+constexpr int kPartialPitch = 65536;
 // Least-squares DM fitting: the 5 x 5 quality evaluation grid of probe directions.
 constexpr int kProbes = 25;
 // Scalar records per frame: two pass-parity slots, the right-hand-side record, the current pass.
@@ -222,9 +222,13 @@ int hip_failure(hipError_t e, const char *what, const char *file, int line);
 // Waves of a coarse forward-DWT workgroup: each leaves its own pair of residual partials.
 constexpr int kCoarseWaves = 16;
 
-// Residual partial pairs a pass leaves for the next scalar step: one per fine forward-DWT tile and
-// one per wave of every layer's coarse workgroup.
-inline int residual_partials(const Plan &P) { return P.n_fwd + (P.kf < P.J ? P.nl * kCoarseWaves : 0); }
+// Residual partial pairs a pass leaves for the next scalar step: one per wave of every fine
+// forward-DWT tile and of every layer's coarse workgroup.
+// Waves of a fine forward-DWT workgroup for the plan's (kf, tq) (each leaves its own pair).
+int fwd_waves(int kf, int tq);
+inline int residual_partials(const Plan &P) {
+    return P.n_fwd * fwd_waves(P.kf, P.tq) + (P.kf < P.J ? P.nl * kCoarseWaves : 0);
+}
 
 // Values per frame of the level-kf approximation region (at most n_coef / 4 plus one), rounded up
 // to a multiple of 4 so that every frame's blocks start 16-byte aligned.

@@ -1061,11 +1061,13 @@ __global__ __launch_bounds__((FwdLanes<KF, TQ>::block)) void k_fwd(SegTab S, con
         if (s < KF) __syncthreads();
     }
     if constexpr (EPI == kEpiPcg || EPI == kEpiRhs) {
-        __shared__ double sRed[2 * (FB / 64)];
-        block_sum2(rho, dz, sRed);
-        if (tid == 0) {
-            B.partials[blockIdx.x] = rho;
-            B.partials[kPartialPitch + blockIdx.x] = dz;
+        // one partial pair per wave, no block reduction: slots blockIdx.x * (FB / 64) + wave
+        rho = wave_sum(rho);
+        dz = wave_sum(dz);
+        if ((tid & 63) == 0) {
+            const int slot = (int)blockIdx.x * (FB / 64) + (tid >> 6);
+            B.partials[slot] = rho;
+            B.partials[kPartialPitch + slot] = dz;
         }
     }
 }
@@ -1759,10 +1761,30 @@ int Ops<T>::pt(const T *v, T *x, const PassArgs &PA) const {
     return check();
 }
 
+int fwd_waves(int kf, int tq) {
+#define FEWHA_FWD_WAVES(KF, TQ) return FwdLanes<KF, TQ>::block / 64
+    if (kf == 1) {
+        switch (tq) {
+            case 1: FEWHA_FWD_WAVES(1, 1);
+            case 2: FEWHA_FWD_WAVES(1, 2);
+            case 4: FEWHA_FWD_WAVES(1, 4);
+            default: FEWHA_FWD_WAVES(1, 8);
+        }
+    }
+    switch (tq) {
+        case 1: FEWHA_FWD_WAVES(2, 1);
+        case 2: FEWHA_FWD_WAVES(2, 2);
+        case 4: FEWHA_FWD_WAVES(2, 4);
+        default: FEWHA_FWD_WAVES(2, 8);
+    }
+#undef FEWHA_FWD_WAVES
+}
+
 template <typename T, int EPI>
 static int fwd_launch(const Plan &P, const Bufs<T> &B, hipStream_t st, int nb, const T *x, const FwdArgs &E) {
     const Taps<T> tp = make_taps<T>();
     const int nf = P.n_fwd;
+    const int nfs = nf * fwd_waves(P.kf, P.tq);  // the fine tiles' partial slots (one per wave)
 #define FEWHA_FWD(KF, TQ) k_fwd<T, KF, TQ, EPI><<<dim3(nf, nb), (FwdLanes<KF, TQ>::block), 0, st>>>(P.seg_fwd, x, B, E, tp, P.J)
     if (P.kf == 1) {
         switch (P.tq) {
@@ -1792,9 +1814,9 @@ static int fwd_launch(const Plan &P, const Bufs<T> &B, hipStream_t st, int nb, c
         const int pre = !gin && EpiOps<EPI>::n > 0 && base + opb <= kCoarseLdsMax ? 1 : 0;
         const dim3 grid(P.nl, nb);
         const size_t lds = base + (pre ? opb : 0);
-        if (pre) k_coarse<T, EPI, kCoarseStaged><<<grid, kCB, lds, st>>>(P.laytab, B, E, tp, P.J, P.kf, nf);
-        else if (gin) k_coarse<T, EPI, kCoarseGlobalIn><<<grid, kCB, lds, st>>>(P.laytab, B, E, tp, P.J, P.kf, nf);
-        else k_coarse<T, EPI, kCoarseDirect><<<grid, kCB, lds, st>>>(P.laytab, B, E, tp, P.J, P.kf, nf);
+        if (pre) k_coarse<T, EPI, kCoarseStaged><<<grid, kCB, lds, st>>>(P.laytab, B, E, tp, P.J, P.kf, nfs);
+        else if (gin) k_coarse<T, EPI, kCoarseGlobalIn><<<grid, kCB, lds, st>>>(P.laytab, B, E, tp, P.J, P.kf, nfs);
+        else k_coarse<T, EPI, kCoarseDirect><<<grid, kCB, lds, st>>>(P.laytab, B, E, tp, P.J, P.kf, nfs);
         if (int e = check()) return e;
     }
     return FEWHA_OK;
