@@ -159,8 +159,8 @@ struct Bufs {
     const T *ad;                      // [nl][J+1] alpha D per level
     T *b_prev, *r, *p, *q, *u, *x, *v, *ll, *probe_c, *probe_s;
     int *over;                        // per-sensor flags: a transpose row exceeded kRtabWidth (setup)
-    double *partials;                 // [3][kPartialPitch]: (r, z) and (z, alpha D z) per forward-DWT
-                                      // tile and coarse layer, sum C (Gamma P u)^2 per projection tile
+    double *partials;                 // [3][kPartialPitch]: (r, z) and (z, alpha D z) per wave of the
+                                      // forward-DWT workgroups, sum C (Gamma P u)^2 per projection tile
     Scalars *sc;                      // [kScalarSlots]
     // a batch of frames of the same geometry: frame f's vectors, partial sums and scalar slots sit
     // f strides after frame 0's (in elements): coefficients, node grids, slopes, actuators,
