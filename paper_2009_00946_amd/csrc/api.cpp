@@ -130,7 +130,7 @@ int pcg_passes(const Plan &P, const Ops<T> &o, void *c, int n_iter, double *resn
     for (int k = 0; k < n_iter; ++k) {
         TRY(o.wt_pcg(o.B.r, o.B.u));             // u = W^T J^-1 r
         TRY(o.proj(o.B.u, o.B.v, kProjM));       // v = Gamma^T C Gamma P u; (C Gamma P u, Gamma P u) partials
-        TRY(o.pt(o.B.v, o.B.x, PassArgs{k, nres, P.n_proj, 1, resnorm, n_iter}));  // x = P^T v; Alg. 2 scalars
+        TRY(o.pt(o.B.v, o.B.x, PassArgs{k, nres, P.n_proj * kProjWaves, 1, resnorm, n_iter}));  // x = P^T v; Alg. 2 scalars
         FwdArgs E{};                             // y = W x + alpha D z; the pass update
         E.c = c;
         E.k = k;
@@ -212,7 +212,7 @@ int stage_launch(const Plan &P, int stage, void *stream) {
         case FEWHA_STAGE_WT: return o.wt_pcg(o.B.r, o.B.u);
         case FEWHA_STAGE_PROJ: return o.proj(o.B.u, o.B.v, kProjM);
         case FEWHA_STAGE_PT:
-            return o.pt(o.B.v, o.B.x, PassArgs{1, residual_partials(P), P.n_proj, 0, nullptr, 0});
+            return o.pt(o.B.v, o.B.x, PassArgs{1, residual_partials(P), P.n_proj * kProjWaves, 0, nullptr, 0});
         default: {
             // the frame's y = W x + alpha D z with the pass update, applied to scratch copies of
             // r, p, q and c, without publishing scalars

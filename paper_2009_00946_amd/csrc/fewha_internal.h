@@ -219,6 +219,9 @@ int plan_create(const fewha_config *cfg, Plan **out);
 // (call, source location, HIP's error string); returns FEWHA_ERR_HIP.
 int hip_failure(hipError_t e, const char *what, const char *file, int line);
 
+// Waves of a projection workgroup: each leaves its own partial of sum C (Gamma P u)^2.
+constexpr int kProjWaves = 4;
+
 // Waves of a coarse forward-DWT workgroup: each leaves its own pair of residual partials.
 constexpr int kCoarseWaves = 16;
 

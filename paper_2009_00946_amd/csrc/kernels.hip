@@ -521,7 +521,6 @@ __global__ __launch_bounds__(kB) void k_proj(SegTab S, LayTab LT, InvVar IV, Pup
     __shared__ T sW0[2][kMaxLayers][kPR], sW1[2][kMaxLayers][kPR];
     __shared__ T sPhi[kPR * kPR];
     __shared__ T sSx[kPS * kPS], sSy[kPS * kPS];
-    __shared__ double sRed[kB / 64];
 
     B = at_frame(B);
     u += blockIdx.y * (MODE == kProjPol ? B.fs_a : B.fs_c);
@@ -634,8 +633,10 @@ __global__ __launch_bounds__(kB) void k_proj(SegTab S, LayTab LT, InvVar IV, Pup
                 (T)0.5 * ((-sSx[s11] - sSy[s11]) + (sSx[s10] - sSy[s10]) + (-sSx[s01] + sSy[s01]) + (sSx[s00] + sSy[s00]));
         }
     }
-    const double t = block_sum(e2, sRed);
-    if (tid == 0) B.partials[2 * kPartialPitch + blockIdx.x] = t;
+    // one partial per wave, no block reduction: slots blockIdx.x * (kB / 64) + wave
+    static_assert(kB / 64 == kProjWaves, "one projection partial slot per wave");
+    e2 = wave_sum(e2);
+    if ((tid & 63) == 0) B.partials[2 * kPartialPitch + (int)blockIdx.x * kProjWaves + (tid >> 6)] = e2;
 }
 
 // Gamma^T C s (kGtRhs) or Gamma^T mask s (kGtAdj) on the node tiles of k_proj.

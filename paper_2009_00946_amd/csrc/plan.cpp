@@ -356,7 +356,7 @@ int plan_create(const fewha_config *cfg, Plan **out) {
         P->dmtab.off[m] = int(P->ddm[m].a_off);
         P->dmtab.n[m] = P->ddm[m].n_act;
     }
-    if (residual_partials(*P) > kPartialPitch || P->n_proj > kPartialPitch) {
+    if (residual_partials(*P) > kPartialPitch || P->n_proj * kProjWaves > kPartialPitch) {
         delete P;
         return FEWHA_ERR_UNSUPPORTED;
     }
