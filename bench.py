@@ -80,7 +80,7 @@ def byte_model(cfg, elem_bytes, n_iter):
 # footprints, the node grids through the slope stencil and back) | P^T (read v, write x) |
 # W + alpha D z + dots + fused update.
 # Per-reconstruction times the paper prints for its own test configuration (L = M = 6, 4 PCG
-# iterations; Sec. 6), with their hardware: context for the same workload on this GPU.
+# iterations; Sec. 4.3), with their hardware: context for the same workload on this GPU.
 PAPER_MS = {"maory_paper": {"cpu_ms": 3.0, "cpu": "2x Intel Xeon E5-2630v3 (8-core Haswell), OpenMP",
                             "gpu_ms": 8.6, "gpu": "NVIDIA Tesla V100-PCIE-32GB, CUDA 10.1"}}
 
@@ -234,11 +234,8 @@ def c3_configs():
     from paper_2009_00946_amd import synth
     out = []
     for name, count, which in C3_GROUPS:
-        cfg = copy.deepcopy(synth.load_config(name))
+        cfg = copy.deepcopy(synth.load_config(name + ("_lgs" if which == "LGS only" else "")))
         cfg["precision"], cfg["n_iter"], cfg["warm"] = "fp32", 4, True
-        if which == "LGS only":
-            cfg["wfs"] = [w for w in cfg["wfs"] if w["gs_height"] > 0]
-            cfg["name"] = name + "_lgs"
         out.append((cfg, count))
     return out
 

@@ -34,7 +34,7 @@
  *
  * Errors: every call returns FEWHA_OK (0) or a negative fewha_status; nothing is thrown across
  * the ABI.  Numerical failures inside a solve (PCG breakdown, non-finite reductions) are
- * recorded in a device status word that fewha_last_status reads after the caller synchronises.
+ * recorded in a device status word that fewha_last_status reads (it synchronises the device).
  * With the environment variable FEWHA_DEBUG set, a FEWHA_ERR_HIP return also prints the failing
  * HIP call or launch, its source location and HIP's error string on stderr.
  *
@@ -69,6 +69,10 @@ typedef enum { FEWHA_FP32 = 0, FEWHA_FP64 = 1 } fewha_precision;
 /* PCG start flags for fewha_pcg_solve */
 #define FEWHA_COLD 0 /* c = b_prev = r_prev = 0 before the frame */
 #define FEWHA_WARM 1 /* warm restart from the caller's c and the plan's b_prev, r_prev */
+#define FEWHA_REFRESH 2 /* warm restart from the caller's c with the residual recomputed as
+                           b - M c (one application of M more) instead of carried by
+                           (b - b_prev) + r_prev: clears the rounding a long FP32 chain of
+                           carried residuals accumulates (about 1e-7 of |b| per frame) */
 
 /* One Shack-Hartmann wavefront sensor / guide star (Sec. 2.1). */
 typedef struct {
@@ -127,13 +131,19 @@ int fewha_plan_bind(fewha_plan *p, void *d_workspace, size_t bytes, void *stream
 /* Free the host side of the plan (the workspace stays the caller's). */
 int fewha_plan_destroy(fewha_plan *p);
 
-/* Vector lengths: wavelet coefficients (= layer nodes), dense slopes, actuators. Any output may be NULL. */
+/* Vector lengths, the dimensions of Table 1 (Sec. 2.2): n_coef = sum over layers of n_l^2 wavelet
+ * coefficients (= layer nodes; the paper's 2^(2 J_l) per layer), n_slopes = sum over sensors of
+ * 2 n_sub^2 dense slopes (Gamma's rows), n_act = sum over DMs of n_act^2 actuators.  Any output
+ * may be NULL.  Host only; FEWHA_ERR_INVALID_ARG for a null plan. */
 int fewha_sizes(const fewha_plan *p, size_t *n_coef, size_t *n_slopes, size_t *n_act);
 
 /* s = mask Gamma P W^T c: wavelet coefficients to slopes (Eq. (atmo) in the wavelet domain). */
 int fewha_apply_A(const fewha_plan *p, const void *d_c, void *d_s, void *stream);
 
-/* c = W P^T Gamma^T mask s: the exact adjoint of fewha_apply_A. */
+/* c = W P^T Gamma^T mask s: the exact adjoint A^T of the wavelet-domain tomography operator of
+ * Eq. (atmo) (A = mask Gamma P W^T), the product that forms the right-hand side of Eq. (fewha)
+ * (there weighted by C_eta^-1).  d_s: n_slopes (inactive entries are ignored), d_c: n_coef, not
+ * aliasing d_s.  Uses the plan's workspace intermediates (node grids, layer grid). */
 int fewha_apply_At(const fewha_plan *p, const void *d_s, void *d_c, void *stream);
 
 /* y = M c = W P^T Gamma^T C_eta^-1 Gamma P W^T c + alpha D c (left-hand side of Eq. (fewha)). */
@@ -148,7 +158,8 @@ int fewha_dwt_inverse(const fewha_plan *p, const void *d_c, void *d_layers, void
 /* One reconstruction frame of Alg. 1 up to the PCG: b = W Ahat^T C_eta^-1 s; residual update
  * r = (b - b_prev) + r_prev; n_iter passes of Alg. 2 with the Jacobi preconditioner; then
  * b_prev = b, r_prev = r (kept in the workspace).  d_c holds c^(0) on entry (ignored for
- * FEWHA_COLD, which starts from c = b_prev = r_prev = 0) and c^(1) on return.  d_resnorm
+ * FEWHA_COLD, which starts from c = b_prev = r_prev = 0) and c^(1) on return.  FEWHA_REFRESH
+ * forms the same residual as b - M c^(0), the left-hand form of Alg. 1's residual line.  d_resnorm
  * (optional, n_iter doubles on the device) receives sqrt((r, J^-1 r)) at the start of every pass
  * that ran.  A zero residual ends the passes early (not an error); breakdown or non-finite
  * reductions stop the passes and set the device status word (fewha_last_status). */
@@ -180,6 +191,14 @@ int fewha_apply_CA(const fewha_plan *p, const void *d_c, void *d_s, void *stream
  * (layer, level); since D_l is proportional to 1/gamma_l (the Cn^2 weight), dM/dgamma_l is
  * -(alpha D)_l / gamma_l on layer l and zero elsewhere. */
 int fewha_prior_dot(const fewha_plan *p, const void *d_x, const void *d_y, double *d_out, void *stream);
+
+/* The gradient of a loss L(c) of the MAP-FEWHA solution c = M^-1 b of Eq. (fewha) with respect to
+ * the layers' Cn^2 weights gamma_l, by the implicit-function rule: with lambda = M^-1 dL/dc (e.g.
+ * from fewha_solve_M), d_out[l] = dL/dgamma_l = lambda_l^T (alpha D)_l c_l / gamma_l, since the
+ * prior of Eq. (fewha) scales as D_l ~ 1/gamma_l (so dM/dgamma_l = -(alpha D)_l / gamma_l on layer
+ * l) and b does not depend on gamma.  d_lambda, d_c: n_coef values of the plan's precision;
+ * d_out: n_layers doubles on the device, each summed in FP64 in a fixed order over its layer. */
+int fewha_cn2_gradient(const fewha_plan *p, const void *d_lambda, const void *d_c, double *d_out, void *stream);
 
 /* Closed loop (Alg. 1).  Pseudo-open-loop slopes s_pol = mask (s + Gamma P_DM a_m1): the DMs'
  * correction as the sensors see it added to the measured residual slopes, with a_m1 = a^(-1),
@@ -214,7 +233,11 @@ int fewha_fit_dm_closed(const fewha_plan *p, const void *d_c, const void *d_a0, 
 int fewha_fit_dm_ls(const fewha_plan *p, const void *d_c, const void *d_a_prev, double gain, int n_cg, double eps,
                     void *d_a, void *stream);
 
-/* Copy the warm-restart state (b_prev, r_prev; n_coef each) out of / into the workspace. */
+/* The warm-restart state of Alg. 1: the previous frame's right-hand side b^(0) and residual
+ * r^(0), which the residual line combines with the new right-hand side as (b^(1) - b^(0)) + r^(0)
+ * (n_coef each, coefficient layout).  state_get copies them out of the workspace, state_set
+ * into it (e.g. to resume a chain, to run several chains on one plan, or to refresh r^(0) =
+ * b^(0) - M c^(0)).  Enqueued on the stream like every other call. */
 int fewha_state_get(const fewha_plan *p, void *d_b_prev, void *d_r_prev, void *stream);
 int fewha_state_set(fewha_plan *p, const void *d_b_prev, const void *d_r_prev, void *stream);
 
@@ -267,8 +290,12 @@ typedef enum {
  * so a later fewha_pcg_solve is unaffected.  Returns FEWHA_ERR_INVALID_ARG for an unknown stage. */
 int fewha_stage_launch(const fewha_plan *p, int stage, void *stream);
 
-/* Read the device status word of the last solve (synchronises the device): FEWHA_OK,
- * FEWHA_ERR_BREAKDOWN or FEWHA_ERR_NONFINITE; FEWHA_ERR_WORKSPACE if unbound. */
+/* The device status word of the last enqueued solve: FEWHA_ERR_BREAKDOWN when a pass of Alg. 2
+ * met a non-positive denominator mu - rho beta / alpha_old (the step-size line; M is SPD, so only
+ * rounding or corrupted input can cause it), FEWHA_ERR_NONFINITE when its reductions (rho, mu)
+ * were NaN or Inf, else FEWHA_OK.  Synchronises the whole device first (hipDeviceSynchronize),
+ * so the word is final whichever stream the solve was enqueued on.  FEWHA_ERR_WORKSPACE if
+ * unbound, FEWHA_ERR_HIP if the synchronisation or the read fails. */
 int fewha_last_status(const fewha_plan *p);
 
 /* Static description of a status code. */

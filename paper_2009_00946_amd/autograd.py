@@ -96,7 +96,7 @@ class _Reconstruct(torch.autograd.Function):
         c, gamma = ctx.saved_tensors
         lam = plan.solve_M(g.contiguous(), n_iter=ctx.n_adj)
         grad_s = plan.apply_CA(lam)
-        grad_gamma = plan.prior_dot(lam, c) / gamma.detach().to(torch.float64)
+        grad_gamma = plan.cn2_gradient(lam, c)
         return grad_s, grad_gamma.to(gamma.dtype), None, None, None
 
 

@@ -31,7 +31,7 @@ ARCMIN = math.pi / (180.0 * 60.0)
 ARCSEC = ARCMIN / 60.0
 HERE = os.path.dirname(os.path.abspath(__file__))
 
-# alpha_reg per configuration; see module docstring (checked by tests/test_alpha_calibration.py)
+# alpha_reg per configuration; see module docstring (checked by tests/test_synth_and_calibration.py)
 ALPHA_REG = {
     "c0_tiny": 0.103,
     "c1_elt_mcao": 0.168,
@@ -177,8 +177,8 @@ def t1_mixed():
 
 
 def maory_paper():
-    """The paper's own test configuration at the size of its first timed runs (Sec. 5 parameter
-    table; Sec. 6: L = M = 6, 4 PCG iterations): D = 39 m, about 28 % obstructed, six LGS
+    """The paper's own test configuration at the size of its first timed runs (Sec. 4.1,
+    Table 2; Sec. 4.3: L = M = 6, 4 PCG iterations): D = 39 m, about 28 % obstructed, six LGS
     sensors of 80 x 80, one NGS of 2 x 2 and two of 1 x 1, LGS and NGS on 2' and 8/3' diameters,
     128^2 layer grids, DM 1 with 81^2 actuators, DMs 2-5 with 48^2 and DM 6 with 54^2.
     Readings for what the table leaves open: LGS at 90 km on a hexagon, NGS on a triangle at

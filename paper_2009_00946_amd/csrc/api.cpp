@@ -145,6 +145,18 @@ template <typename T>
 int pcg_solve(const Plan &P, const void *s, void *c, int n_iter, int flags, double *resnorm, void *stream,
               int nb = 1) {
     auto o = ops<T>(P, stream, nb);
+    if (flags == FEWHA_REFRESH) {
+        // b_prev = M c and r_prev = 0, so that the residual update below gives r = b - M c (Alg. 1's
+        // residual line in its left-hand form) instead of carrying the previous frame's residual
+        FwdArgs E{};
+        E.out = o.B.b_prev;
+        E.cin = c;
+        TRY(o.wt(static_cast<const T *>(c), o.B.u));
+        TRY(o.proj(o.B.u, o.B.v, kProjM));
+        TRY(o.pt(o.B.v, o.B.x, PassArgs{-1, 0, 0, 0, nullptr, 0}));
+        TRY(o.fwd(o.B.x, E, kEpiPrior));
+        TRY(o.fill(o.B.r, (long)P.n_coef * nb, 0));
+    }
     // right-hand side b = W P^T Gamma^T C s, then the warm-restart residual update
     TRY(o.gt(static_cast<const T *>(s), o.B.v, kGtRhs));
     TRY(o.pt(o.B.v, o.B.x, PassArgs{-1, 0, 0, 0, nullptr, 0}));
@@ -177,9 +189,9 @@ int apply_CA(const Plan &P, const void *c, void *s, void *stream) {
 }
 
 template <typename T>
-int prior_dot(const Plan &P, const void *x, const void *y, double *out, void *stream) {
+int prior_dot(const Plan &P, const void *x, const void *y, double *out, void *stream, bool per_gamma = false) {
     auto o = ops<T>(P, stream);
-    return o.prior_dot(static_cast<const T *>(x), static_cast<const T *>(y), out);
+    return o.prior_dot(static_cast<const T *>(x), static_cast<const T *>(y), out, per_gamma);
 }
 
 template <typename T>
@@ -458,7 +470,7 @@ int fewha_dwt_inverse(const fewha_plan *p, const void *d_c, void *d_layers, void
 int fewha_pcg_solve(fewha_plan *p, const void *d_s, void *d_c, int n_iter, int flags, double *d_resnorm,
                     void *stream) {
     TRY(ready(p));
-    if (!d_s || !d_c || n_iter < 0 || (flags != FEWHA_COLD && flags != FEWHA_WARM)) return FEWHA_ERR_INVALID_ARG;
+    if (!d_s || !d_c || n_iter < 0 || (flags != FEWHA_COLD && flags != FEWHA_WARM && flags != FEWHA_REFRESH)) return FEWHA_ERR_INVALID_ARG;
     return p->p.prec == FEWHA_FP64 ? pcg_solve<double>(p->p, d_s, d_c, n_iter, flags, d_resnorm, stream)
                                    : pcg_solve<float>(p->p, d_s, d_c, n_iter, flags, d_resnorm, stream);
 }
@@ -481,6 +493,13 @@ int fewha_prior_dot(const fewha_plan *p, const void *d_x, const void *d_y, doubl
     if (!d_x || !d_y || !d_out) return FEWHA_ERR_INVALID_ARG;
     return p->p.prec == FEWHA_FP64 ? prior_dot<double>(p->p, d_x, d_y, d_out, stream)
                                    : prior_dot<float>(p->p, d_x, d_y, d_out, stream);
+}
+
+int fewha_cn2_gradient(const fewha_plan *p, const void *d_lambda, const void *d_c, double *d_out, void *stream) {
+    TRY(ready(p));
+    if (!d_lambda || !d_c || !d_out) return FEWHA_ERR_INVALID_ARG;
+    return p->p.prec == FEWHA_FP64 ? prior_dot<double>(p->p, d_lambda, d_c, d_out, stream, true)
+                                   : prior_dot<float>(p->p, d_lambda, d_c, d_out, stream, true);
 }
 
 int fewha_fit_dm(const fewha_plan *p, const void *d_c, const void *d_a_prev, double gain, void *d_a, void *stream) {
@@ -560,7 +579,7 @@ int fewha_apply_M_batch(const fewha_plan *p, int nbatch, const void *d_c, void *
 int fewha_pcg_solve_batch(fewha_plan *p, int nbatch, const void *d_s, void *d_c, int n_iter, int flags,
                           double *d_resnorm, void *stream) {
     TRY(batch_ok(p, nbatch));
-    if (!d_s || !d_c || n_iter < 0 || (flags != FEWHA_COLD && flags != FEWHA_WARM)) return FEWHA_ERR_INVALID_ARG;
+    if (!d_s || !d_c || n_iter < 0 || (flags != FEWHA_COLD && flags != FEWHA_WARM && flags != FEWHA_REFRESH)) return FEWHA_ERR_INVALID_ARG;
     return p->p.prec == FEWHA_FP64 ? pcg_solve<double>(p->p, d_s, d_c, n_iter, flags, d_resnorm, stream, nbatch)
                                    : pcg_solve<float>(p->p, d_s, d_c, n_iter, flags, d_resnorm, stream, nbatch);
 }
@@ -646,6 +665,7 @@ int fewha_precond_table(const fewha_plan *p, double *h_jdiag) {
 
 int fewha_last_status(const fewha_plan *p) {
     TRY(ready(p));
+    if (hipDeviceSynchronize() != hipSuccess) return FEWHA_ERR_HIP;  // final, on every stream
     int st = 0;
     const Scalars *sc = reinterpret_cast<const Scalars *>(p->p.ws + p->p.o_scalars) + p->p.last_slot;
     if (hipMemcpy(&st, &sc->status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return FEWHA_ERR_HIP;

@@ -138,8 +138,6 @@ struct Scalars {
     double rho, mu, rho_old, alpha, alpha_old, beta;
     int stopped;     // zero residual, breakdown or non-finite: later passes are no-ops
     int status;      // FEWHA_OK, FEWHA_ERR_BREAKDOWN or FEWHA_ERR_NONFINITE
-    unsigned counter;  // last-block-done counter of the reduction (returns to 0 after each use)
-    int pad;
 };
 
 // Device pointers into the bound workspace, typed per precision.

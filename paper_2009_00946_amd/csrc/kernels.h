@@ -70,7 +70,8 @@ struct Ops {
     int pol(const T *a_m1, const T *s, T *s_pol) const;   // s_pol = mask (s + Gamma P_DM a_m1)
     // least-squares fit of the layers u onto the DMs (n_cg CG steps), then the open-loop gain
     int fit_ls(const T *u, const T *a_prev, T *a, double gain, int n_cg, double eps) const;
-    int prior_dot(const T *x, const T *y, double *out) const;  // out[l] = sum_layer x alpha D y
+    // out[l] = sum_layer x alpha D y, times 1 / gamma_l with `per_gamma` (the Cn^2 gradient)
+    int prior_dot(const T *x, const T *y, double *out, bool per_gamma = false) const;
     int build_tables(int *over) const;                    // projection cell, transpose and rectangle tables
     int fill(T *x, long n, T val) const;
     int copy(T *dst, const T *src, long n) const;

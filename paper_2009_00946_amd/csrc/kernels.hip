@@ -1369,8 +1369,12 @@ __global__ __launch_bounds__(kB) void k_fit(const T *__restrict__ u, const T *__
 // Per layer l (one workgroup each): out[l] = sum over the layer's coefficients of x alpha D y in
 // FP64, fixed order.  The level of coefficient (r, q) of an n x n Mallat pyramid is J inside the
 // top-left (n >> J)^2 block, else log2 n - floor(log2 max(r, q)).
+struct LayScale {             // a factor per layer
+    double s[kMaxLayers];
+};
+
 template <typename T>
-__global__ __launch_bounds__(kB) void k_prior_dot(LayTab LT, const T *__restrict__ x, const T *__restrict__ y,
+__global__ __launch_bounds__(kB) void k_prior_dot(LayTab LT, LayScale sc, const T *__restrict__ x, const T *__restrict__ y,
                                                   const T *__restrict__ ad, int J, double *out) {
     __shared__ double sh[kB / 64];
     const int l = blockIdx.x, n = LT.n[l], ln = 31 - __clz(n);
@@ -1382,7 +1386,7 @@ __global__ __launch_bounds__(kB) void k_prior_dot(LayTab LT, const T *__restrict
         acc += (double)x[off + i] * (double)ad[l * (J + 1) + s] * (double)y[off + i];
     }
     const double v = block_sum(acc, sh);
-    if (threadIdx.x == 0) out[l] = v;
+    if (threadIdx.x == 0) out[l] = v * sc.s[l];
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1659,10 +1663,7 @@ __global__ __launch_bounds__(kB) void k_copy(T *__restrict__ dst, const T *__res
 
 __global__ void k_init_scalars(Scalars *sc) {
     sc += blockIdx.y * kScalarSlots;
-    if (threadIdx.x < kScalarSlots && blockIdx.x == 0) {
-        reset_scalars(sc + threadIdx.x);
-        sc[threadIdx.x].counter = 0u;
-    }
+    if (threadIdx.x < kScalarSlots && blockIdx.x == 0) reset_scalars(sc + threadIdx.x);
 }
 
 int grid_for(long n) {
@@ -1885,8 +1886,10 @@ int Ops<T>::build_tables(int *over) const {
 }
 
 template <typename T>
-int Ops<T>::prior_dot(const T *x, const T *y, double *out) const {
-    k_prior_dot<T><<<P.nl, kB, 0, st>>>(P.laytab, x, y, B.ad, P.J, out);
+int Ops<T>::prior_dot(const T *x, const T *y, double *out, bool per_gamma) const {
+    LayScale sc{};
+    for (int l = 0; l < P.nl; ++l) sc.s[l] = per_gamma ? 1.0 / P.lay[l].cn2_weight : 1.0;
+    k_prior_dot<T><<<P.nl, kB, 0, st>>>(P.laytab, sc, x, y, B.ad, P.J, out);
     return check();
 }
 

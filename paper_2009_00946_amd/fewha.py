@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfewha.so")
 
 FEWHA_FP32, FEWHA_FP64 = 0, 1
-FEWHA_COLD, FEWHA_WARM = 0, 1
+FEWHA_COLD, FEWHA_WARM, FEWHA_REFRESH = 0, 1, 2
 STATUS = {0: "FEWHA_OK", -1: "FEWHA_ERR_INVALID_ARG", -2: "FEWHA_ERR_GEOMETRY", -3: "FEWHA_ERR_UNSUPPORTED",
           -4: "FEWHA_ERR_HIP", -5: "FEWHA_ERR_WORKSPACE", -6: "FEWHA_ERR_BREAKDOWN", -7: "FEWHA_ERR_NONFINITE"}
 
@@ -23,7 +23,7 @@ EXPORTS = ["fewha_plan_create", "fewha_workspace_bytes", "fewha_plan_bind", "few
            "fewha_prior_dot", "fewha_plan_set_batch", "fewha_apply_A_batch", "fewha_apply_At_batch",
            "fewha_apply_M_batch", "fewha_pcg_solve_batch", "fewha_fit_dm_batch", "fewha_last_status_batch",
            "fewha_pol_slopes", "fewha_fit_dm_closed", "fewha_pol_slopes_batch", "fewha_fit_dm_closed_batch",
-           "fewha_fit_dm_ls"]
+           "fewha_fit_dm_ls", "fewha_cn2_gradient"]
 
 
 class FewhaError(RuntimeError):
@@ -91,6 +91,7 @@ def load_library():
     L.fewha_pol_slopes_batch.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
     L.fewha_fit_dm_closed_batch.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_double, vp, vp]
     L.fewha_prior_dot.argtypes = [vp, vp, vp, vp, vp]
+    L.fewha_cn2_gradient.argtypes = [vp, vp, vp, vp, vp]
     L.fewha_pcg_solve.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, vp]
     L.fewha_fit_dm.argtypes = [vp, vp, vp, ctypes.c_double, vp, vp]
     L.fewha_precond_table.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
@@ -221,15 +222,22 @@ class Plan:
         return x
 
     # -- solver --------------------------------------------------------------------------------
-    def pcg_solve(self, s, c, n_iter, warm=True, resnorm=None):
-        """One frame (RHS, residual update, n_iter PCG passes); c is updated in place and returned."""
+    @staticmethod
+    def _flags(warm, refresh):
+        if refresh and not warm:
+            raise ValueError("refresh applies to warm starts")
+        return FEWHA_REFRESH if refresh else (FEWHA_WARM if warm else FEWHA_COLD)
+
+    def pcg_solve(self, s, c, n_iter, warm=True, resnorm=None, refresh=False):
+        """One frame (RHS, residual update, n_iter PCG passes); c is updated in place and returned.
+        ``refresh`` (warm starts): the residual is recomputed as b - M c instead of carried."""
         rp = None
         if resnorm is not None:
             if not resnorm.is_cuda or resnorm.dtype != self._torch.float64 or resnorm.numel() < n_iter:
                 raise ValueError("resnorm: float64 CUDA tensor of n_iter elements expected")
             rp = resnorm.data_ptr()
         _check(_lib.fewha_pcg_solve(self._h, self._arg(s, self.n_slopes, "s"), self._arg(c, self.n_coef, "c"),
-                                    int(n_iter), FEWHA_WARM if warm else FEWHA_COLD, rp, self._stream()),
+                                    int(n_iter), self._flags(warm, refresh), rp, self._stream()),
                "fewha_pcg_solve")
         return c
 
@@ -260,6 +268,14 @@ class Plan:
                                     out.data_ptr(), self._stream()), "fewha_prior_dot")
         return out
 
+    def cn2_gradient(self, lam, c):
+        """Per layer: lambda_l^T (alpha D)_l c_l / gamma_l (float64 CUDA tensor), the implicit
+        gradient of a loss of c = M^-1 b with respect to the Cn^2 weights, lambda = M^-1 dL/dc."""
+        out = self._torch.empty(len(self.cfg["layers"]), dtype=self._torch.float64, device=self.device)
+        _check(_lib.fewha_cn2_gradient(self._h, self._arg(lam, self.n_coef, "lambda"), self._arg(c, self.n_coef, "c"),
+                                       out.data_ptr(), self._stream()), "fewha_cn2_gradient")
+        return out
+
     # -- batches of frames (one launch per stage over every frame; tensors [nbatch][length]) ---------
     def _batch(self, t, n, name):
         if t.dim() != 2 or t.shape[1] != n or not (1 <= t.shape[0] <= self.max_batch):
@@ -288,7 +304,7 @@ class Plan:
         _check(_lib.fewha_apply_M_batch(self._h, nb, c.data_ptr(), y.data_ptr(), self._stream()), "fewha_apply_M_batch")
         return y
 
-    def pcg_solve_batch(self, s, c, n_iter, warm=True, resnorm=None):
+    def pcg_solve_batch(self, s, c, n_iter, warm=True, resnorm=None, refresh=False):
         """Frames f = 0..nbatch-1 (s [nbatch][n_slopes], c [nbatch][n_coef] updated in place), one
         launch per stage; frame f continues its own warm-restart chain."""
         nb = self._batch(s, self.n_slopes, "s")
@@ -300,7 +316,7 @@ class Plan:
                 raise ValueError("resnorm: float64 CUDA tensor of nbatch * n_iter elements expected")
             rp = resnorm.data_ptr()
         _check(_lib.fewha_pcg_solve_batch(self._h, nb, s.data_ptr(), c.data_ptr(), int(n_iter),
-                                          FEWHA_WARM if warm else FEWHA_COLD, rp, self._stream()),
+                                          self._flags(warm, refresh), rp, self._stream()),
                "fewha_pcg_solve_batch")
         return c
 

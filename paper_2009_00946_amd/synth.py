@@ -24,12 +24,30 @@ CONFIG_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "configs")
 
 
 def load_config(name_or_path):
-    """Load an AO configuration (JSON) by name (e.g. ``"c1_elt_mcao"``) or path."""
+    """Load an AO configuration (JSON) by name (e.g. ``"c1_elt_mcao"``) or path.
+
+    A name ``<base>_lgs`` with no file of its own is configuration ``<base>`` with its laser guide
+    stars only (the natural guide stars dropped; layers, DMs, seeds and alpha_reg unchanged), the
+    geometry the batched mix runs for its ELT member."""
     path = name_or_path
     if not os.path.exists(path):
         path = os.path.join(CONFIG_DIR, name_or_path + ".json")
+    if not os.path.exists(path) and name_or_path.endswith("_lgs"):
+        return lgs_only(load_config(name_or_path[:-4]))
     with open(path) as f:
         return json.load(f)
+
+
+def lgs_only(cfg):
+    """A copy of ``cfg`` keeping only its laser guide stars, named ``<name>_lgs``."""
+    import copy
+    out = copy.deepcopy(cfg)
+    out["wfs"] = [w for w in out["wfs"] if w["gs_height"] > 0]
+    if not out["wfs"]:
+        raise ValueError("%s has no laser guide star" % cfg.get("name"))
+    out["name"] = cfg["name"] + "_lgs"
+    out["description"] = cfg.get("description", "") + " (laser guide stars only)"
+    return out
 
 
 def sizes(cfg):

@@ -85,7 +85,9 @@ def stress(precisions=("fp64", "fp32"), name="c4_stress", plans=None, O=None):
     return out
 
 
-def drift(frames=16, precisions=("fp64", "fp32"), name="c1_elt_mcao", plans=None, O=None):
+def drift(frames=16, precisions=("fp64", "fp32"), name="c1_elt_mcao", plans=None, O=None, refresh_every=0):
+    """Carried against recomputed residual after every frame; with ``refresh_every`` = k > 0 every
+    k-th warm frame recomputes its residual as b - M c (FEWHA_REFRESH) instead."""
     import torch
     from oracle import Oracle
     from paper_2009_00946_amd import fewha
@@ -93,14 +95,16 @@ def drift(frames=16, precisions=("fp64", "fp32"), name="c1_elt_mcao", plans=None
     O = O or Oracle(cfg)
     n_iter, N = cfg["n_iter"], O.n_coef
     S = [_slopes(O, cfg, f) for f in range(frames)]
-    out = {"config": name, "frames": frames, "n_iter": n_iter}
+    out = {"config": name, "frames": frames, "n_iter": n_iter, "refresh_every": refresh_every}
     for prec in precisions:
         print("[drift] %s %s" % (name, prec), flush=True)
         P = (plans or {}).get(prec) or fewha.Plan(cfg, precision=prec)
         c = P.zeros(N)
         rows = []
         for f in range(frames):
-            P.pcg_solve(torch.as_tensor(S[f], dtype=P.dtype, device=P.device), c, n_iter, warm=f > 0)
+            refresh = refresh_every > 0 and f > 0 and f % refresh_every == 0
+            P.pcg_solve(torch.as_tensor(S[f], dtype=P.dtype, device=P.device), c, n_iter, warm=f > 0,
+                        refresh=refresh)
             torch.cuda.synchronize()
             assert P.last_status() == 0
             _, r_g = P.state_get()

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     src = open(os.path.join(ROOT, "include", "fewha.h")).read()
-    return sorted(set(re.findall(r"\b(fewha_[A-Za-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(fewha_[A-Za-z0-9_]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_function():

@@ -1,7 +1,7 @@
-"""The paper's own test configuration (Sec. 5 and its parameter table, fixture
-tests/golden/maory_parameters.txt) at the size of its first runs (Sec. 6: L = M = 6, 4 PCG
+"""The paper's own test configuration (Sec. 4.1 and its parameter table, Table 2; fixture
+tests/golden/maory_parameters.txt) at the size of its first runs (Sec. 4.3: L = M = 6, 4 PCG
 iterations): the plan's and the oracle's vector sizes against the matrix dimensions the paper
-prints (Sec. 2.3), and (GPU) a cold frame with fitting against the oracle.
+prints (Table 1 in Sec. 2.2), and (GPU) a cold frame with fitting against the oracle.
 
 The configuration is `maory_paper` (written by configs/make_configs.py, which states its readings
 of what the table leaves open); the first test pins it to the printed values.  With 28 % obstruction the 1x1

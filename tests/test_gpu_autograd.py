@@ -1,12 +1,13 @@
 """Differentiation on the GPU (autograd wrapper over the C ABI), against central differences and
 the FP64 oracle.
 
-* gradcheck of A, A^T and M in FP64 (central differences, step 1e-6; second derivatives of A);
+* gradcheck of A, A^T and M in FP64 (central differences, step 1e-6; second derivatives of A), on
+  the tiny geometry (full Jacobian of A) and on the ELT geometry (random directions);
 * a batch of 8 coefficient vectors on the ELT geometry in FP32: the backward of A equals the
   oracle's A^T row by row (1e-5, the operator bound);
 * the entry points the implicit gradients use: M c = b from c = 0 (fewha_solve_M) against the
   oracle's Alg. 2 with the same passes, C A (fewha_apply_CA), the per-layer prior products
-  (fewha_prior_dot);
+  (fewha_prior_dot) and the Cn^2 gradient (fewha_cn2_gradient);
 * the reconstruction's backward (dL/ds = C A lambda, dL/dgamma_l = lambda_l^T (alpha D)_l c_l /
   gamma_l, lambda = M^-1 dL/dc) against the same expressions evaluated by the oracle with the same
   number of PCG passes.  The expressions themselves are pinned against exact dense derivatives in
@@ -61,6 +62,7 @@ def check(got, ref, tol, what=""):
     err = np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300)
     nrm = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300)
     assert err <= tol and nrm <= tol, "%s: max-rel %.3e norm-rel %.3e > %.1e" % (what, err, nrm, tol)
+    return max(err, nrm)
 
 
 def test_gradcheck_operators_fp64():
@@ -73,6 +75,20 @@ def test_gradcheck_operators_fp64():
     assert torch.autograd.gradcheck(lambda x: ag.apply_At(P, x), (s,), fast_mode=True, **kw)
     assert torch.autograd.gradcheck(lambda x: ag.apply_M(P, x), (c,), fast_mode=True, **kw)
     assert torch.autograd.gradgradcheck(lambda x: ag.apply_A(P, x), (c,), fast_mode=True, **kw)
+
+
+def test_gradcheck_operators_elt_geometry_fp64():
+    """The differentiation configuration's geometry (9 guide stars of 84 x 84, 9 layers up to
+    256^2): gradcheck in fast mode (a random direction through the Jacobian, central differences
+    step 1e-6, against the backward's vector-Jacobian product) of A, A^T and M in FP64."""
+    from paper_2009_00946_amd import autograd as ag
+    P = plan("c1_elt_mcao", "fp64")
+    c = dev(P, synth.normal_vector(P.n_coef, 53)).requires_grad_(True)
+    s = dev(P, synth.normal_vector(P.n_slopes, 54)).requires_grad_(True)
+    kw = dict(eps=1e-6, atol=1e-8, rtol=1e-6, fast_mode=True)
+    assert torch.autograd.gradcheck(lambda x: ag.apply_A(P, x), (c,), **kw)
+    assert torch.autograd.gradcheck(lambda x: ag.apply_At(P, x), (s,), **kw)
+    assert torch.autograd.gradcheck(lambda x: ag.apply_M(P, x), (c,), **kw)
 
 
 @pytest.mark.parametrize("name,prec,tol", [("c0_tiny", "fp64", 1e-12), ("c1_elt_mcao", "fp32", 1e-5)])
@@ -114,6 +130,8 @@ def test_adjoint_entry_points(name, prec, tol_c, tol_op):
     ref = np.array([xr[offs[l]:offs[l + 1]] @ (aD[offs[l]:offs[l + 1]] * yr[offs[l]:offs[l + 1]])
                     for l in range(len(cfg["layers"]))])
     check(host(P.prior_dot(dev(P, x), dev(P, y))), ref, tol_op, "prior_dot")
+    gam = np.array([lay["cn2_weight"] for lay in cfg["layers"]])
+    check(host(P.cn2_gradient(dev(P, x), dev(P, y))), ref / gam, tol_op, "cn2_gradient")
 
 
 @pytest.mark.parametrize("name,prec,tol", [("c0_tiny", "fp64", 1e-9), ("c1_elt_mcao", "fp32", 2e-3)])
@@ -138,8 +156,9 @@ def test_reconstruction_gradients(name, prec, tol):
     offs = np.cumsum([0] + [l["n"] ** 2 for l in cfg["layers"]])
     g_ref = np.array([lam[offs[l]:offs[l + 1]] @ (aD[offs[l]:offs[l + 1]] * c_ref[offs[l]:offs[l + 1]])
                       / lay["cn2_weight"] for l, lay in enumerate(cfg["layers"])])
-    check(host(gamma.grad), g_ref, tol, "dL/dgamma")
-    check(host(s.grad), O.slope_weights() * O.A(lam), tol, "dL/ds")
+    e_g = check(host(gamma.grad), g_ref, tol, "dL/dgamma")
+    e_s = check(host(s.grad), O.slope_weights() * O.A(lam), tol, "dL/ds")
+    print("[grad] %s %s: dL/dgamma %.2e dL/ds %.2e" % (name, prec, e_g, e_s), flush=True)
 
 
 def test_batched_plan_autograd_and_timing():

@@ -25,7 +25,7 @@ def _slopes(O, cfg, frame):
 
 
 @pytest.mark.parametrize("name,prec,nb,frames", [("c0_tiny", "fp64", 5, 3), ("t1_mixed", "fp32", 3, 3),
-                                                  ("c1_elt_mcao", "fp32", 4, 3)])
+                                                  ("c1_elt_mcao", "fp32", 4, 3), ("c1_elt_mcao_lgs", "fp32", 4, 3)])
 def test_batched_chains_equal_single_frame_chains(name, prec, nb, frames):
     _need_gpu()
     from oracle import Oracle
