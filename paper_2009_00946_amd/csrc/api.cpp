@@ -323,6 +323,7 @@ int bind_tables(Plan &P, hipStream_t st) {
         size_t stage = 1;
         const int ch = P.prec == FEWHA_FP64 ? 2 : 4;  // values per 16-byte chunk
         for (int l = 0; l < P.nl; ++l) {
+            int rw = 1;  // the layer's pair width: the largest pair count of any of its lines
             for (int t = P.seg_pt.start[l]; t < P.seg_pt.start[l + 1]; ++t) {
                 size_t need = 0;
                 for (int g = 0; g < P.nw; ++g) {
@@ -330,9 +331,12 @@ int bind_tables(Plan &P, hipStream_t st) {
                     const int iA = R.x & 0xffff, iB = R.x >> 16, jA = R.y & 0xffff, jB = R.y >> 16;
                     if (iA <= iB) need += size_t(iB - iA + 1) * (((jB - (jA & ~(ch - 1))) / ch + 1) * ch);
                     if (R.z > kRtabWidth || R.w > kRtabWidth) P.rtab_ok = false;
+                    rw = R.z > rw ? R.z : rw;
+                    rw = R.w > rw ? R.w : rw;
                 }
                 stage = need > stage ? need : stage;
             }
+            P.seg_pt.rw[l] = rw < kRtabWidth ? rw : kRtabWidth;
         }
         if (stage > size_t(kPtStage)) P.rtab_ok = false;
         // the tile's transpose pairs (index, weight) of every guide star, then the stage

@@ -52,8 +52,7 @@ struct SegTab {
     int aux[kMaxSeg];     // layers: first grid line in the per-axis line tables; sensors: s_off
     int n[kMaxSeg];       // layer n, or sensor n_sub
     int lt[kMaxSeg];      // layers: log2 of tiles per row; sensors: tiles per row
-    int capr[kMaxSeg];    // P^T (layer segments): staged node rows / columns per guide star
-    int capw[kMaxSeg];
+    int rw[kMaxSeg];      // P^T (layer segments): transpose pairs per grid line, 1..kRtabWidth
     int pitch[kMaxSeg];   // sensors: row pitch of the node grid (n_sub + 1 rounded up to 4)
 };
 

@@ -59,7 +59,7 @@ struct PupilArgs {            // subaperture (i, j) of guide star g is active if
 // broadcast from that lane.  All 64 lanes of the wave must be active.
 struct TileId {
     int seg, loc;
-    int off, n, lt, aux, capr, capw, pitch;
+    int off, n, lt, aux, rw, pitch;
 };
 
 // Workgroups are dealt to the chip's 8 XCDs round-robin (workgroup b runs on XCD b mod 8), and
@@ -78,7 +78,7 @@ __device__ __forceinline__ int xcd_tile(int ntiles) {
 __device__ __forceinline__ TileId find_tile(const SegTab &S, int b) {
     const int lane = threadIdx.x & 63;
     const int st = S.start[lane], of = S.off[lane], nn = S.n[lane], l2 = S.lt[lane], ax = S.aux[lane];
-    const int cr = S.capr[lane], cw = S.capw[lane], pi = S.pitch[lane];
+    const int rw = S.rw[lane], pi = S.pitch[lane];
     const unsigned long long m = __ballot(b >= st);
     const int s = 63 - __clzll(m);
     TileId t;
@@ -88,8 +88,7 @@ __device__ __forceinline__ TileId find_tile(const SegTab &S, int b) {
     t.n = __builtin_amdgcn_readlane(nn, s);
     t.lt = __builtin_amdgcn_readlane(l2, s);
     t.aux = __builtin_amdgcn_readlane(ax, s);
-    t.capr = __builtin_amdgcn_readlane(cr, s);
-    t.capw = __builtin_amdgcn_readlane(cw, s);
+    t.rw = __builtin_amdgcn_readlane(rw, s);
     t.pitch = __builtin_amdgcn_readlane(pi, s);
     return t;
 }
@@ -680,14 +679,50 @@ __global__ __launch_bounds__(kB) void k_gt(SegTab S, InvVar IV, PupilArgs pa, co
 // P^T
 // ---------------------------------------------------------------------------------------------
 // Staged gather on a 16 x 16 layer tile.  The transpose-table lines of the tile's rows and
-// columns (up to kRtabWidth (node, weight) pairs each, per guide star) and each guide star's
-// record (the node rows / columns those pairs name and the largest pair count over the tile's
-// rows / columns, precomputed at bind time) come first.  Each guide star's node rectangle is then
-// staged in LDS, widened to 16-byte column chunks (node grid rows are 16-byte aligned), one
-// guide star after the other with one 16-byte copy per lane and chunk, and each lane sums
+// columns (rw (node, weight) pairs each, per guide star, rw the layer's largest pair count, at
+// most kRtabWidth) and each guide star's record (the node rows / columns those pairs name and the
+// largest pair count over the tile's rows / columns, precomputed at bind time) come first.  Each
+// guide star's node rectangle is then staged in LDS, widened to 16-byte column chunks (node grid
+// rows are 16-byte aligned), one guide star after the other with one 16-byte copy per lane and
+// chunk, and each lane sums
 //   x(k, q) = sum_g sum_{(i, wy) in row k} wy sum_{(j, wx) in column q} wx v_g(i, j)
 // from LDS, with loop bounds uniform over the tile (missing pairs carry weight 0).  The pairs are
 // the very matrix entries P uses, so P^T is P's exact transpose.
+
+// The sum of one lane over the guide stars with R pairs per line (R the layer's pair width, so
+// that the loops unroll): every R x R pair product of a guide star is summed without per-pair
+// conditions, so that its LDS reads issue together; pairs past a line's count are padding (index
+// -1, weight 0) and the clamps send them to the rectangle's first row / column, adding exact
+// zeros.  Only a guide star with no rectangle on this tile is skipped.
+template <typename T, int R>
+__device__ __forceinline__ T pt_sum(const RtabEnt<T> (*sP)[2][kRtabWidth][kPtTile], const T *sV, int nw, int a, int b,
+                                    int pitch, int iA, int c0, int sbase) {
+    T acc = 0;
+    for (int g = 0; g < nw; ++g) {
+        const int pg = __builtin_amdgcn_readlane(pitch, g);
+        if (pg == 0) continue;
+        const int ra = __builtin_amdgcn_readlane(iA, g), cg = __builtin_amdgcn_readlane(c0, g);
+        const T *Vg = sV + __builtin_amdgcn_readlane(sbase, g) - ra * pg - cg;
+        int jx[R];
+        T wx[R];
+#pragma unroll
+        for (int e = 0; e < R; ++e) {
+            const RtabEnt<T> p = sP[g][0][e][b];
+            jx[e] = max(p.idx, cg);
+            wx[e] = p.w;
+        }
+#pragma unroll
+        for (int ea = 0; ea < R; ++ea) {
+            const RtabEnt<T> p = sP[g][1][ea][a];
+            const T *Vr = Vg + max(p.idx, ra) * pg;
+            T t = 0;
+#pragma unroll
+            for (int eb = 0; eb < R; ++eb) t += wx[eb] * Vr[jx[eb]];
+            acc += p.w * t;
+        }
+    }
+    return acc;
+}
 
 template <typename T>
 __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restrict__ v, T *__restrict__ x, Bufs<T> B,
@@ -714,17 +749,18 @@ __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restr
     const int n = id.n, lt = id.lt;
     const int T0 = n < NT ? n : NT;
     const int k0 = (id.loc >> lt) * T0, q0 = (id.loc & ((1 << lt) - 1)) * T0;
-    const int roff = id.aux;
+    const int roff = id.aux, rw = id.rw;  // pairs per line on this layer (uniform)
 
-    // transpose-table lines e = (g * 2 + axis) * 16 + idx, and the records (every lane loads;
-    // clamped indices stand in for lines the tile does not have)
+    // the first rw pairs of the transpose-table lines e = (g * 2 + axis) * 16 + idx, and the
+    // records (every lane loads; clamped indices stand in for lines the tile does not have)
     RtabEnt<T> pe[2][RW];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const int e = tid + c * kB, g = min(e >> 5, nw - 1), axis = (e >> 4) & 1, idx = min(e & 15, T0 - 1);
         const RtabEnt<T> *rt = (axis ? B.yrtab : B.xrtab) + ((long)g * B.sum_n + roff + (axis ? k0 : q0) + idx) * RW;
 #pragma unroll
-        for (int a = 0; a < RW; ++a) pe[c][a] = rt[a];
+        for (int a = 0; a < RW; ++a)
+            if (a < rw) pe[c][a] = rt[a];
     }
     // lane g of every wave holds guide star g's record: node rows iA..iB, first staged column c0
     // (16-byte aligned), last column jB, pair counts, node grid offset / pitch, and the LDS
@@ -746,7 +782,8 @@ __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restr
         const int e = tid + c * kB, g = e >> 5, axis = (e >> 4) & 1, idx = e & 15;
         if (g < nw && idx < T0) {
 #pragma unroll
-            for (int a = 0; a < RW; ++a) sP[g][axis][a][idx] = pe[c][a];
+            for (int a = 0; a < RW; ++a)
+                if (a < rw) sP[g][axis][a][idx] = pe[c][a];
         }
     }
 
@@ -775,35 +812,14 @@ __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restr
     }
     lds_fence();
 
-    // All RW x RW pairs of a guide star are summed without per-pair conditions, so that its
-    // LDS reads issue together: the pairs past a line's count are padding (index -1, weight 0)
-    // and the clamps send them to the rectangle's first row / column, adding exact zeros.  Only a
-    // guide star with no rectangle on this tile is skipped.
     const int a = tid >> 4, b = tid & 15;
     if (a < T0 && b < T0) {
-        T acc = 0;
-        for (int g = 0; g < nw; ++g) {
-            const int pg = __builtin_amdgcn_readlane(pitch, g);
-            if (pg == 0) continue;
-            const int ra = __builtin_amdgcn_readlane(iA, g), cg = __builtin_amdgcn_readlane(c0, g);
-            const T *Vg = sV + __builtin_amdgcn_readlane(sbase, g) - ra * pg - cg;
-            int jx[RW];
-            T wx[RW];
-#pragma unroll
-            for (int e = 0; e < RW; ++e) {
-                const RtabEnt<T> p = sP[g][0][e][b];
-                jx[e] = max(p.idx, cg);
-                wx[e] = p.w;
-            }
-#pragma unroll
-            for (int ea = 0; ea < RW; ++ea) {
-                const RtabEnt<T> p = sP[g][1][ea][a];
-                const T *Vr = Vg + max(p.idx, ra) * pg;
-                T t = 0;
-#pragma unroll
-                for (int eb = 0; eb < RW; ++eb) t += wx[eb] * Vr[jx[eb]];
-                acc += p.w * t;
-            }
+        T acc;
+        switch (rw) {  // uniform over the workgroup
+            case 1: acc = pt_sum<T, 1>(sP, sV, nw, a, b, pitch, iA, c0, sbase); break;
+            case 2: acc = pt_sum<T, 2>(sP, sV, nw, a, b, pitch, iA, c0, sbase); break;
+            case 3: acc = pt_sum<T, 3>(sP, sV, nw, a, b, pitch, iA, c0, sbase); break;
+            default: acc = pt_sum<T, RW>(sP, sV, nw, a, b, pitch, iA, c0, sbase); break;
         }
         x[id.off + (long)(k0 + a) * n + q0 + b] = acc;
     }
