@@ -418,6 +418,8 @@ def main():
     ap.add_argument("--frames", type=int, default=16, help="distinct synthetic slope frames (cycled)")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle CPU time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--refresh", type=int, default=8,
+                    help="FP32: recompute the residual as b - M c every this many frames (0: always carried)")
     ap.add_argument("--eager", action="store_true", help="launch kernels one by one instead of replaying HIP graphs")
     ap.add_argument("--stage-reps", type=int, default=50, help="launches per PCG-pass stage in its timing graph")
     ap.add_argument("--workload", default="frame", choices=("frame", "c3_batch", "batch_scan"),
@@ -461,8 +463,16 @@ def main():
     c = P.zeros(P.n_coef)
     a = P.zeros(P.n_act)
 
+    # every args.refresh-th warm frame recomputes its residual as b - M c (FP32 drift control; the
+    # frame graphs cycle through len(S) frames, a multiple of the period)
+    if P.precision != "fp32":
+        args.refresh = 0
+    if args.refresh and len(S) % args.refresh:
+        sys.exit("bench.py: --frames must be a multiple of --refresh")
+
     def frame(k, warm=True):
-        P.pcg_solve(S[k % len(S)], c, n_iter, warm=warm)
+        fresh = warm and args.refresh > 0 and k % args.refresh == 0
+        P.pcg_solve(S[k % len(S)], c, n_iter, warm=warm, refresh=fresh)
         P.fit_dm(c, a, gain, out=a)
 
     frame(0, warm=False)
@@ -544,7 +554,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%s: %s" % (cfg["name"], cfg["description"]), "n_iter": n_iter, "warm": True,
                    "gain": gain, "n_coef": model["n_coef"], "n_slopes": P.n_slopes, "n_act": P.n_act,
-                   "launch": "eager" if args.eager else "hip_graph_per_frame"},
+                   "launch": "eager" if args.eager else "hip_graph_per_frame",
+                   "residual_refresh_every": args.refresh or None},
         "ms_median": round(float(np.median(per)), 5),
         "ms_p99": round(float(np.percentile(per, 99)), 5),
         "frames_per_s": round(1e3 / ms_mean, 1),

@@ -147,18 +147,29 @@ def _slopes(O, cfg, frame):
     return O.Ahat(synth.layer_screens_flat(cfg, frame)) + O.slope_mask() * synth.slope_noise(cfg, frame)
 
 
-@pytest.mark.parametrize("name,prec,frames,tol_c,tol_layers", [
-    ("c0_tiny", "fp64", 2, 1e-9, 1e-9),
-    ("t1_mixed", "fp64", 4, 1e-9, 1e-9),
-    ("t1_mixed", "fp32", 4, 1e-3, 1e-4),
-    ("c3_mid_lgs", "fp32", 4, 1e-3, 1e-4),
-    # the ELT configuration's first 64 frames, and the laser-guide-star-only member of the batched mix
-    pytest.param("c1_elt_mcao", "fp32", 64, 1e-3, 1e-4, marks=pytest.mark.timeout(600)),
-    ("c1_elt_mcao_lgs", "fp32", 8, 1e-3, 1e-4),
+# FP32 refresh period of the long chains: every REFRESH-th warm frame recomputes its residual as
+# b - M c.  Carried alone, the FP32 residual drifts from b - M c by about 1e-7 of |b| per frame
+# (the rounding of each c update is invisible to the recurrence), and on the ELT geometry the
+# layers then leave the 1e-4 bound after about 19 frames; refreshed every 8 frames they stay
+# below 7e-5 over 64 frames (and below 7e-6 when refreshed every frame).
+REFRESH = 8
+
+
+@pytest.mark.parametrize("name,prec,frames,tol_c,tol_layers,refresh", [
+    ("c0_tiny", "fp64", 2, 1e-9, 1e-9, 0),
+    ("t1_mixed", "fp64", 4, 1e-9, 1e-9, 0),
+    ("t1_mixed", "fp32", 4, 1e-3, 1e-4, 0),
+    ("c3_mid_lgs", "fp32", 4, 1e-3, 1e-4, 0),
+    # the ELT configuration carried alone over 8 frames, then its first 64 frames with the residual
+    # refreshed every REFRESH frames, and the laser-guide-star-only member of the batched mix
+    ("c1_elt_mcao", "fp32", 8, 1e-3, 1e-4, 0),
+    pytest.param("c1_elt_mcao", "fp32", 64, 1e-3, 1e-4, REFRESH, marks=pytest.mark.timeout(600)),
+    ("c1_elt_mcao_lgs", "fp32", 8, 1e-3, 1e-4, 0),
 ])
-def test_frame_chain_parity(name, prec, frames, tol_c, tol_layers):
-    """Alg. 1 frames chained by warm restart (cold first frame), GPU vs oracle after every frame
-    (the carried FP32 residual drifts by about 1e-7 of |b| per frame, far inside the bounds here)."""
+def test_frame_chain_parity(name, prec, frames, tol_c, tol_layers, refresh):
+    """Alg. 1 frames chained by warm restart (cold first frame), GPU vs oracle after every frame.
+    With ``refresh`` every refresh-th warm frame recomputes its residual as b - M c (equal to the
+    carried residual in exact arithmetic, so the oracle's chain stays the carried one)."""
     P, O = plan(name, prec), oracle(name)
     cfg = synth.load_config(name)
     n_iter, warm = cfg["n_iter"], cfg["warm"]
@@ -172,7 +183,8 @@ def test_frame_chain_parity(name, prec, frames, tol_c, tol_layers):
         cold = (f == 0) or not warm
         c_ref, bp, rp, res_ref, st = O.frame(s, c_ref, bp, rp, n_iter, cold)
         assert st == 0
-        P.pcg_solve(dev(P, s), c_gpu, n_iter, warm=not cold, resnorm=res)
+        fresh = bool(refresh) and not cold and f % refresh == 0
+        P.pcg_solve(dev(P, s), c_gpu, n_iter, warm=not cold, resnorm=res, refresh=fresh)
         assert P.last_status() == 0
         e_c = check(host(c_gpu), c_ref, tol_c, "c frame %d" % f)
         e_l = check(host(P.dwt_inverse(c_gpu)), O.Wt(c_ref), tol_layers, "layers frame %d" % f)
