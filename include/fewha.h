@@ -152,6 +152,18 @@ int fewha_apply_M(const fewha_plan *p, const void *d_c, void *d_y, void *stream)
 /* c = W x: layer nodal values to wavelet coefficients (periodic Daubechies-3, J levels). */
 int fewha_dwt_forward(const fewha_plan *p, const void *d_layers, void *d_c, void *stream);
 
+/* c = W x as fewha_dwt_forward, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, hosts that forbid hipMalloc): this call allocates nothing
+ * and needs no bound workspace, only a created plan.  Its scratch (the level-kf approximation
+ * of every layer, (n_coef / 4 + 4) values rounded up to a multiple of 4) sits in a device array of
+ * the library, 8 MiB on every GPU the library runs on, held until the process ends; a plan needing
+ * more returns FEWHA_ERR_UNSUPPORTED before touching the device.  The first call on a device looks
+ * the array up there (and sets the kernels' LDS limits), so it must run with that device current.
+ * All calls on one GPU share the array: two calls that overlap in time on one GPU (on different
+ * streams, or from different threads) race on it and must be ordered by the caller.  Results are
+ * bitwise those of fewha_dwt_forward.  d_layers, d_c: n_coef values each, not aliasing. */
+int fewha_dwt_forward_noalloc(const fewha_plan *p, const void *d_layers, void *d_c, void *stream);
+
 /* x = W^T c = W^-1 c: wavelet coefficients to layer nodal values (the reconstructed layers). */
 int fewha_dwt_inverse(const fewha_plan *p, const void *d_c, void *d_layers, void *stream);
 

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfewha.so")
-SOURCES = ["plan.cpp", "api.cpp", "kernels.hip"]
+SOURCES = ["plan.cpp", "api.cpp", "kernels.hip", "noalloc.hip"]
 ARCH = os.environ.get("FEWHA_OFFLOAD_ARCH", "gfx950")
 
 

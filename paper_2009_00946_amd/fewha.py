@@ -23,7 +23,7 @@ EXPORTS = ["fewha_plan_create", "fewha_workspace_bytes", "fewha_plan_bind", "few
            "fewha_prior_dot", "fewha_plan_set_batch", "fewha_apply_A_batch", "fewha_apply_At_batch",
            "fewha_apply_M_batch", "fewha_pcg_solve_batch", "fewha_fit_dm_batch", "fewha_last_status_batch",
            "fewha_pol_slopes", "fewha_fit_dm_closed", "fewha_pol_slopes_batch", "fewha_fit_dm_closed_batch",
-           "fewha_fit_dm_ls", "fewha_cn2_gradient"]
+           "fewha_fit_dm_ls", "fewha_cn2_gradient", "fewha_dwt_forward_noalloc"]
 
 
 class FewhaError(RuntimeError):
@@ -76,7 +76,7 @@ def load_library():
     L.fewha_plan_destroy.argtypes = [vp]
     L.fewha_sizes.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz), ctypes.POINTER(sz)]
     for name in ("fewha_apply_A", "fewha_apply_At", "fewha_apply_M", "fewha_dwt_forward", "fewha_dwt_inverse",
-                 "fewha_state_get", "fewha_state_set", "fewha_apply_CA"):
+                 "fewha_state_get", "fewha_state_set", "fewha_apply_CA", "fewha_dwt_forward_noalloc"):
         getattr(L, name).argtypes = [vp, vp, vp, vp]
     L.fewha_solve_M.argtypes = [vp, vp, vp, ctypes.c_int, vp, vp]
     L.fewha_plan_set_batch.argtypes = [vp, ctypes.c_int]
@@ -213,6 +213,14 @@ class Plan:
         c = self._out(out, self.n_coef)
         _check(_lib.fewha_dwt_forward(self._h, self._arg(layers, self.n_coef, "layers"),
                                       self._arg(c, self.n_coef, "c"), self._stream()), "fewha_dwt_forward")
+        return c
+
+    def dwt_forward_noalloc(self, layers, out=None):
+        """W x through the entry point that allocates nothing (library-owned scratch array)."""
+        c = self._out(out, self.n_coef)
+        _check(_lib.fewha_dwt_forward_noalloc(self._h, self._arg(layers, self.n_coef, "layers"),
+                                              self._arg(c, self.n_coef, "c"), self._stream()),
+               "fewha_dwt_forward_noalloc")
         return c
 
     def dwt_inverse(self, c, out=None):

@@ -139,3 +139,26 @@ def test_library_shares_torchs_hip_runtime():
     r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr
     assert r.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_noalloc_forward_argument_checks(cfg_c0):
+    """The allocation-free forward transform refuses null or aliased vectors, and a plan whose
+    scratch would exceed the library's 8 MiB array, before any device call."""
+    L = fewha.load_library()
+    h, st = fewha.create_host_plan(cfg_c0)
+    assert st == 0
+    assert L.fewha_dwt_forward_noalloc(None, 1, 2, None) == -1
+    assert L.fewha_dwt_forward_noalloc(h, None, 2, None) == -1
+    assert L.fewha_dwt_forward_noalloc(h, 1, None, None) == -1
+    assert L.fewha_dwt_forward_noalloc(h, 1, 1, None) == -1
+    L.fewha_plan_destroy(h)
+    # 16 ground layers of 512^2 in FP64: the approximations need 1,048,580 values, 8,388,640 bytes
+    big = dict(cfg_c0)
+    big["layers"] = [dict(cfg_c0["layers"][0], n=512, cn2_weight=1.0 / 16) for _ in range(16)]
+    h, st = fewha.create_host_plan(big, precision="fp64")
+    assert st == 0
+    assert L.fewha_dwt_forward_noalloc(h, 1, 2, None) == -3
+    L.fewha_plan_destroy(h)
+    h, st = fewha.create_host_plan(big, precision="fp32")   # half the bytes: accepted (not called)
+    assert st == 0
+    L.fewha_plan_destroy(h)
