@@ -6,4 +6,4 @@ implementation in ``fewha_oracle.c`` through ctypes; the configuration dictionar
 JSON under ``paper_2009_00946_amd/configs``) is parsed here, independently of the
 library's own binding.
 """
-from .oracle import Oracle, build, lib_path, db3  # noqa: F401
+from .oracle import Oracle, build, db3, get_threads, lib_path, set_threads  # noqa: F401

@@ -7,8 +7,11 @@
  * may link, load or call this file; only the test suite, the smoke check and the CPU-baseline
  * leg of the benchmark do.  It shares no code, header, table or helper with the GPU library.
  *
- * Everything is double precision, single threaded, written as straightforward loops in the
- * order the paper states the method:
+ * Everything is double precision, written as straightforward loops in the order the paper
+ * states the method.  The outer loops over layers and over guide stars may run on OpenMP
+ * threads (the paper's own CPU scheme parallelises the same loops, Sec. 3.3): each iteration
+ * writes its own layer or sensor block, and every sum keeps its order, so results are bitwise
+ * those of one thread (orc_set_threads; the default is OpenMP's):
  *   Sec. 2.1      Shack-Hartmann operator Gamma (Fried geometry) and the NGS / LGS
  *                 geometric propagation P (bilinear interpolation, cone effect);
  *   Eq. (fewha)   M = W Ahat^T C^-1 Ahat W^T + alpha D,  b = W Ahat^T C^-1 s, with an
@@ -28,6 +31,7 @@
  *   actuator vectors: DMs concatenated, each n_a x n_a row-major.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -154,6 +158,7 @@ void orc_dwt2_inv(const double *c, double *x, int n, int J)
 /* W on every layer: FE nodal values -> wavelet coefficients. */
 void orc_W(const orc_plan *P, const double *layers, double *c)
 {
+#pragma omp parallel for schedule(dynamic, 1)
     for (int l = 0; l < P->nl; l++)
         orc_dwt2_fwd(layers + P->c_off[l], c + P->c_off[l], P->lay[l].n, P->J);
 }
@@ -161,6 +166,7 @@ void orc_W(const orc_plan *P, const double *layers, double *c)
 /* W^T on every layer: wavelet coefficients -> FE nodal values. */
 void orc_Wt(const orc_plan *P, const double *c, double *layers)
 {
+#pragma omp parallel for schedule(dynamic, 1)
     for (int l = 0; l < P->nl; l++)
         orc_dwt2_inv(c + P->c_off[l], layers + P->c_off[l], P->lay[l].n, P->J);
 }
@@ -224,6 +230,7 @@ static void project(const orc_plan *P, int g, int l, int i, int j, double *u, do
 /* phi_g = sum_l P_gl U_l on every WFS node grid (bilinear interpolation). */
 void orc_P(const orc_plan *P, const double *layers, double *phi)
 {
+#pragma omp parallel for schedule(dynamic, 1)
     for (int g = 0; g < P->nw; g++) {
         int nv = P->wfs[g].n_sub + 1;
         for (int i = 0; i < nv; i++)
@@ -244,28 +251,30 @@ void orc_P(const orc_plan *P, const double *layers, double *phi)
     }
 }
 
-/* P^T: each node value is spread back onto the four layer nodes with the same weights. */
+/* P^T: each node value is spread back onto the four layer nodes with the same weights.  Layer
+ * by layer (each layer receives its sums in guide-star, row, column order). */
 void orc_Pt(const orc_plan *P, const double *phi, double *layers)
 {
     memset(layers, 0, sizeof(double) * P->n_coef);
-    for (int g = 0; g < P->nw; g++) {
-        int nv = P->wfs[g].n_sub + 1;
-        for (int i = 0; i < nv; i++)
-            for (int j = 0; j < nv; j++) {
-                double f = phi[P->v_off[g] + (long)i * nv + j];
-                for (int l = 0; l < P->nl; l++) {
-                    int n = P->lay[l].n, k0, l0;
-                    double u, v, t, tau;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int l = 0; l < P->nl; l++) {
+        int n = P->lay[l].n;
+        double *U = layers + P->c_off[l];
+        for (int g = 0; g < P->nw; g++) {
+            int nv = P->wfs[g].n_sub + 1;
+            for (int i = 0; i < nv; i++)
+                for (int j = 0; j < nv; j++) {
+                    double f = phi[P->v_off[g] + (long)i * nv + j], u, v, t, tau;
+                    int k0, l0;
                     project(P, g, l, i, j, &u, &v);
                     cell(u, n, &l0, &t);
                     cell(v, n, &k0, &tau);
-                    double *U = layers + P->c_off[l];
                     U[(long)k0 * n + l0] += (1 - tau) * (1 - t) * f;
                     U[(long)k0 * n + l0 + 1] += (1 - tau) * t * f;
                     U[(long)(k0 + 1) * n + l0] += tau * (1 - t) * f;
                     U[(long)(k0 + 1) * n + l0 + 1] += tau * t * f;
                 }
-            }
+        }
     }
 }
 
@@ -331,6 +340,7 @@ void orc_apply_Ahat(const orc_plan *P, const double *layers, double *s)
 {
     double *phi = malloc(sizeof(double) * P->n_nodes), *m = malloc(sizeof(double) * P->n_slopes);
     orc_P(P, layers, phi);
+#pragma omp parallel for schedule(dynamic, 1)
     for (int g = 0; g < P->nw; g++) orc_gamma(P, g, phi + P->v_off[g], s + P->s_off[g]);
     orc_slope_mask(P, m);
     for (long k = 0; k < P->n_slopes; k++) s[k] *= m[k];
@@ -345,6 +355,7 @@ void orc_apply_Ahat_t(const orc_plan *P, const double *s, double *layers)
     double *sm = malloc(sizeof(double) * P->n_slopes);
     orc_slope_mask(P, m);
     for (long k = 0; k < P->n_slopes; k++) sm[k] = s[k] * m[k];
+#pragma omp parallel for schedule(dynamic, 1)
     for (int g = 0; g < P->nw; g++) orc_gamma_t(P, g, sm + P->s_off[g], phi + P->v_off[g]);
     orc_Pt(P, phi, layers);
     free(phi);
@@ -428,10 +439,11 @@ static void band_origin(int n, int s, int o, int *r0, int *c0)
  * orientation): block-local position (m_s/2, m_s/2).  Every coefficient of that band gets it. */
 int orc_build_precond(orc_plan *P)
 {
-    double *e = calloc(P->n_coef, sizeof(double)), *s = malloc(sizeof(double) * P->n_slopes);
     double *w = malloc(sizeof(double) * P->n_slopes);
     orc_slope_weights(P, w);
+#pragma omp parallel for schedule(dynamic, 1)
     for (int l = 0; l < P->nl; l++) {
+        double *e = calloc(P->n_coef, sizeof(double)), *s = malloc(sizeof(double) * P->n_slopes);
         int n = P->lay[l].n;
         for (int sl = 1; sl <= P->J; sl++)
             for (int o = 0; o < 4; o++) {
@@ -454,12 +466,16 @@ int orc_build_precond(orc_plan *P)
                         }
                     }
             }
+        free(e);
+        free(s);
     }
-    free(e);
-    free(s);
     free(w);
     return ORC_OK;
 }
+
+/* Threads of the outer layer / guide-star loops (results do not depend on it). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_get_threads(void) { return omp_get_max_threads(); }
 
 void orc_precond(const orc_plan *P, double *j) { memcpy(j, P->jdiag, sizeof(double) * P->n_coef); }
 

@@ -33,10 +33,11 @@ def lib_path():
 
 
 def build(force=False):
-    """Compile the oracle with gcc (plain -O2, no vectorisation flags, single thread)."""
+    """Compile the oracle with gcc (plain -O2, no vectorisation flags; OpenMP for the outer
+    layer / guide-star loops only)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall", "-o", tmp, SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB)
     return LIB
 
@@ -83,6 +84,8 @@ def _load():
         L.orc_dwt2_inv.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_int]
         L.orc_level_of.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _ip]
         L.orc_dm_of_layer.argtypes = [ctypes.c_void_p, _ip]
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_get_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -276,3 +279,12 @@ class Oracle:
 
     def active(self, g, i, j):
         return bool(_lib.orc_active(self._h, g, i, j))
+
+
+def set_threads(n):
+    """Threads of the oracle's outer layer / guide-star loops (results do not depend on it)."""
+    _load().orc_set_threads(int(n))
+
+
+def get_threads():
+    return int(_load().orc_get_threads())

@@ -7,6 +7,10 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# parallel test workers (pytest -n) each get one oracle thread rather than all of the host's
+if "PYTEST_XDIST_WORKER" in os.environ:
+    os.environ["OMP_NUM_THREADS"] = "1"
+
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
