@@ -275,93 +275,236 @@ def c3_configs():
     return out
 
 
+def batch_slopes(P1, cfg, count):
+    """[count][n_slopes] seeded synthetic slopes (frozen-flow frames through the plan's own forward
+    operator, plus white noise), resident in HBM."""
+    import torch
+    from paper_2009_00946_amd import synth
+    S = []
+    for f in range(count):
+        phi = torch.as_tensor(synth.layer_screens_flat(cfg, f), dtype=P1.dtype, device=P1.device)
+        s = P1.apply_A(P1.dwt_forward(phi))
+        s += torch.as_tensor(synth.slope_noise(cfg, f), dtype=P1.dtype, device=P1.device)
+        S.append(s)
+    return torch.stack(S).contiguous()
+
+
+def capture(fn, warm_steps=3):
+    """fn(warm) once cold and warm_steps times warm, then one warm call captured in a HIP graph."""
+    import torch
+    fn(warm=False)
+    for _ in range(warm_steps):
+        fn()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(g, stream=cap):
+        fn()
+    torch.cuda.current_stream().wait_stream(cap)
+    torch.cuda.synchronize()
+    return g
+
+
+def time_graphs(graphs, steps, warmup):
+    """ms per replay of the graph sequence graphs[k % len(graphs)], k = 0..steps-1."""
+    import torch
+    for k in range(warmup):
+        graphs[k % len(graphs)].replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(steps):
+        graphs[k % len(graphs)].replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def time_stages_batch(P, nb, stream, reps=20, replays=4):
+    """Average device duration (us) of each stage launch over nb frames (see time_stages)."""
+    import torch
+    out = {}
+    cap = torch.cuda.Stream()
+    for st in STAGES:
+        for _ in range(3):
+            P.stage_launch_batch(st, nb)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        cap.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.graph(g, stream=cap):
+            for _ in range(reps):
+                P.stage_launch_batch(st, nb)
+        torch.cuda.current_stream().wait_stream(cap)
+        g.replay()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(replays + 1)]
+        ev[0].record(stream)
+        for i in range(replays):
+            g.replay()
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        out[st] = 1e3 * ev[0].elapsed_time(ev[-1]) / (replays * reps)
+        del g
+    return out
+
+
+def roofline_of(cfg, us, frames, n_iter, elem=4):
+    """Roofline object of the dominant single kernel of a PCG pass (launches per frame x duration)
+    of a launch over `frames` frames of one geometry."""
+    sel = stage_elements(byte_model(cfg, elem, n_iter))
+    per_frame = {"wt": n_iter, "proj": n_iter, "pt": n_iter + 1, "fwd": n_iter}
+    dom = max(SINGLE_KERNEL, key=lambda st: per_frame[st] * us[st])
+    nbytes = sel[dom] * elem * frames
+    ach = nbytes / (us[dom] * 1e-6) / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": None, "kernel": STAGE_KERNELS[dom],
+            "us_per_launch": round(us[dom], 3), "bytes_per_launch": nbytes, "frames_per_launch": frames}
+
+
+def batched_same_geometry(cfg, nb, steps, warmup, refresh=8):
+    """nb frames of one geometry per launch (RHS + n_iter warm PCG passes + fit each, residual
+    refreshed every `refresh`-th step): us per frame, effective GB/s and the roofline object of the
+    batched launch's dominant kernel."""
+    import torch
+    from paper_2009_00946_amd import fewha
+    n_iter, gain = cfg["n_iter"], cfg["gain"]
+    PB = fewha.Plan(cfg, max_batch=nb)
+    P1 = fewha.Plan(cfg)
+    sb = batch_slopes(P1, cfg, nb)
+    del P1
+    cb = torch.zeros((nb, PB.n_coef), dtype=PB.dtype, device=PB.device)
+    ab = torch.zeros((nb, PB.n_act), dtype=PB.dtype, device=PB.device)
+
+    def step(warm=True, fresh=False):
+        PB.pcg_solve_batch(sb, cb, n_iter, warm=warm, refresh=fresh and warm)
+        PB.fit_dm_batch(cb, gain=gain, out=ab)
+
+    g_warm = capture(step)
+    g_fresh = capture(lambda warm=True: step(warm, fresh=True), warm_steps=0) if refresh else None
+    seq = [g_fresh] + [g_warm] * (refresh - 1) if refresh else [g_warm]
+    ms = time_graphs(seq, max(steps // 8, 2 * len(seq)), warmup)
+    assert PB.last_status_batch(nb) == [0] * nb
+    elem = 4 if PB.precision == "fp32" else 8
+    model = byte_model(cfg, elem, n_iter)
+    us = time_stages_batch(PB, nb, torch.cuda.current_stream())
+    gbps = model["frame"] * nb / (ms * 1e-3) / 1e9
+    out = {"workload": "%s, %d frames per launch" % (cfg["name"], nb), "frames_per_launch": nb,
+           "ms_per_launch_set": round(ms, 4), "us_per_frame": round(1e3 * ms / nb, 2),
+           "frames_per_s": round(1e3 * nb / ms, 1), "effective_GBps": round(gbps, 1),
+           "frac_hbm_peak": round(gbps / HBM_PEAK_GBPS, 4), "residual_refresh_every": refresh or None,
+           "roofline": roofline_of(cfg, us, nb, n_iter, elem),
+           "stages_us_per_launch": {k: round(v, 3) for k, v in us.items()}}
+    del PB, sb, cb, ab, g_warm, g_fresh, seq
+    torch.cuda.empty_cache()
+    return out
+
+
+class UnevenMix:
+    """The batched uneven workload: 64 FP32 frames of three geometries, 4 warm PCG passes and the
+    fit each; each geometry's frames in one batched plan (one launch per stage over all of them),
+    the three plans on streams of their own, forked and joined inside one HIP graph."""
+
+    def __init__(self, with_single=False):
+        import torch
+        from paper_2009_00946_amd import fewha
+        self.groups = []
+        for cfg, count in c3_configs():
+            PB = fewha.Plan(cfg, max_batch=count)
+            P1 = fewha.Plan(cfg)
+            sb = batch_slopes(P1, cfg, count)
+            g = dict(cfg=cfg, count=count, PB=PB, sb=sb,
+                     cb=torch.zeros((count, PB.n_coef), dtype=PB.dtype, device=PB.device),
+                     ab=torch.zeros((count, PB.n_act), dtype=PB.dtype, device=PB.device))
+            if with_single:
+                g.update(P1=P1, c1=P1.zeros(P1.n_coef), a1=P1.zeros(P1.n_act))
+            self.groups.append(g)
+        self.streams = [torch.cuda.Stream() for _ in self.groups]  # default priority
+        self.n_iter = 4
+
+    def batched(self, warm=True, fresh=False):
+        for g in self.groups:
+            g["PB"].pcg_solve_batch(g["sb"], g["cb"], self.n_iter, warm=warm, refresh=fresh and warm)
+            g["PB"].fit_dm_batch(g["cb"], gain=1.0, out=g["ab"])
+
+    def concurrent(self, warm=True, fresh=False):
+        # the three batched plans on streams of their own (fork and join by events): no data is
+        # shared, so the small geometries fill what the large one leaves idle
+        import torch
+        main = torch.cuda.current_stream()
+        for g, s in zip(self.groups, self.streams):
+            s.wait_stream(main)
+            with torch.cuda.stream(s):
+                g["PB"].pcg_solve_batch(g["sb"], g["cb"], self.n_iter, warm=warm, refresh=fresh and warm)
+                g["PB"].fit_dm_batch(g["cb"], gain=1.0, out=g["ab"])
+        for s in self.streams:
+            main.wait_stream(s)
+
+    def single(self, warm=True):
+        for g in self.groups:
+            for f in range(g["count"]):
+                g["P1"].pcg_solve(g["sb"][f], g["c1"], self.n_iter, warm=warm)
+                g["P1"].fit_dm(g["c1"], gain=1.0, out=g["a1"])
+
+    @property
+    def frames(self):
+        return sum(g["count"] for g in self.groups)
+
+    def batch_bytes(self):
+        return sum(byte_model(g["cfg"], 4, self.n_iter)["frame"] * g["count"] for g in self.groups)
+
+    def check(self):
+        for g in self.groups:
+            assert g["PB"].last_status_batch(g["count"]) == [0] * g["count"]
+
+    def roofline(self):
+        """The dominant single kernel of the mix: the largest launches-per-batch x duration over the
+        three plans' batched stage launches."""
+        import torch
+        best = None
+        for g in self.groups:
+            us = time_stages_batch(g["PB"], g["count"], torch.cuda.current_stream())
+            r = roofline_of(g["cfg"], us, g["count"], self.n_iter)
+            per_frame = {"k_wt<pcg>": self.n_iter, "k_proj<M>": self.n_iter, "k_pt": self.n_iter + 1}
+            cost = per_frame[r["kernel"]] * r["us_per_launch"]
+            if best is None or cost > best[0]:
+                best = (cost, dict(r, geometry=g["cfg"]["name"]))
+        return best[1]
+
+
+def uneven_mix_summary(steps, warmup, refresh=8):
+    mix = UnevenMix()
+    g_warm = capture(mix.concurrent)
+    g_fresh = capture(lambda warm=True: mix.concurrent(warm, fresh=True), warm_steps=0)
+    ms = time_graphs([g_fresh] + [g_warm] * (refresh - 1), max(steps // 8, 2 * refresh), warmup)
+    mix.check()
+    gbps = mix.batch_bytes() / (ms * 1e-3) / 1e9
+    out = {"workload": "c3_batched_uneven: " + ", ".join(
+        "%d x %s (%s)" % (g["count"], g["cfg"]["name"], n) for g, (_, _, n) in zip(mix.groups, C3_GROUPS)),
+        "frames": mix.frames, "ms_per_batch": round(ms, 4), "us_per_frame": round(1e3 * ms / mix.frames, 2),
+        "effective_GBps": round(gbps, 1), "frac_hbm_peak": round(gbps / HBM_PEAK_GBPS, 4),
+        "residual_refresh_every": refresh, "launch": "hip_graph_per_batch, one stream per geometry",
+        "roofline": mix.roofline()}
+    del mix, g_warm, g_fresh
+    return out
+
+
 def c3_batch(args):
     """ms per batch of 64 uneven frames: each geometry's frames in one batched plan, the three
     plans on streams of their own in one HIP graph; beside it the same batched plans on one
     stream, and the same frames one at a time."""
     import torch
-    from paper_2009_00946_amd import fewha, synth
     torch.cuda.set_device(0)
-    groups = []
-    for cfg, count in c3_configs():
-        PB = fewha.Plan(cfg, max_batch=count)
-        P1 = fewha.Plan(cfg)
-        # synthetic slopes through the plan's own forward operator (seeded), resident in HBM
-        S = []
-        for f in range(count):
-            phi = torch.as_tensor(synth.layer_screens_flat(cfg, f), dtype=PB.dtype, device=PB.device)
-            s = P1.apply_A(P1.dwt_forward(phi))
-            s += torch.as_tensor(synth.slope_noise(cfg, f), dtype=PB.dtype, device=PB.device)
-            S.append(s)
-        sb = torch.stack(S).contiguous()
-        cb = torch.zeros((count, PB.n_coef), dtype=PB.dtype, device=PB.device)
-        ab = torch.zeros((count, PB.n_act), dtype=PB.dtype, device=PB.device)
-        c1 = P1.zeros(P1.n_coef)
-        a1 = P1.zeros(P1.n_act)
-        groups.append(dict(cfg=cfg, count=count, PB=PB, P1=P1, S=S, sb=sb, cb=cb, ab=ab, c1=c1, a1=a1))
-    n_iter = 4
-
-    def batched(warm=True):
-        for g in groups:
-            g["PB"].pcg_solve_batch(g["sb"], g["cb"], n_iter, warm=warm)
-            g["PB"].fit_dm_batch(g["cb"], gain=1.0, out=g["ab"])
-
-    streams = [torch.cuda.Stream() for _ in groups]  # default priority
-
-    def concurrent(warm=True):
-        # the three batched plans on streams of their own (fork and join by events): no data is
-        # shared, so the small geometries fill what the large one leaves idle
-        main = torch.cuda.current_stream()
-        for g, s in zip(groups, streams):
-            s.wait_stream(main)
-            with torch.cuda.stream(s):
-                g["PB"].pcg_solve_batch(g["sb"], g["cb"], n_iter, warm=warm)
-                g["PB"].fit_dm_batch(g["cb"], gain=1.0, out=g["ab"])
-        for s in streams:
-            main.wait_stream(s)
-
-    def single(warm=True):
-        for g in groups:
-            for f in range(g["count"]):
-                g["P1"].pcg_solve(g["S"][f], g["c1"], n_iter, warm=warm)
-                g["P1"].fit_dm(g["c1"], gain=1.0, out=g["a1"])
-
-    def capture(fn):
-        fn(warm=False)
-        for _ in range(3):
-            fn()
-        torch.cuda.synchronize()
-        g = torch.cuda.CUDAGraph()
-        cap = torch.cuda.Stream()
-        cap.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.graph(g, stream=cap):
-            fn()
-        torch.cuda.current_stream().wait_stream(cap)
-        torch.cuda.synchronize()
-        return g
-
-    def time_graph(g, steps):
-        for _ in range(args.warmup):
-            g.replay()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(steps):
-            g.replay()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / steps
-
-    gb = capture(batched)
-    ms_seq = time_graph(gb, args.steps)
-    gc = capture(concurrent)
-    ms_b = time_graph(gc, args.steps)
-    for g in groups:
-        assert g["PB"].last_status_batch(g["count"]) == [0] * g["count"]
-    gs = capture(single)
-    ms_s = time_graph(gs, max(args.steps // 10, 5))
-    total_bytes = sum(byte_model(g["cfg"], 4, n_iter)["frame"] * g["count"] for g in groups)
-    frames = sum(g["count"] for g in groups)
+    mix = UnevenMix(with_single=True)
+    gb = capture(mix.batched)
+    ms_seq = time_graphs([gb], args.steps, args.warmup)
+    gc = capture(mix.concurrent)
+    ms_b = time_graphs([gc], args.steps, args.warmup)
+    mix.check()
+    gs = capture(mix.single)
+    ms_s = time_graphs([gs], max(args.steps // 10, 5), args.warmup)
+    total_bytes = mix.batch_bytes()
+    frames = mix.frames
     gbps = total_bytes / (ms_b * 1e-3) / 1e9
     out = {
         "metric": "ms per batch of 64 uneven frames (fixed PCG iters) + effective HBM GB/s vs peak",
@@ -369,8 +512,8 @@ def c3_batch(args):
         "ms_per_step": round(ms_b, 5), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "c3_batched_uneven: " + ", ".join(
-            "%d x %s (%s)" % (g["count"], g["cfg"]["name"], n) for g, (_, _, n) in zip(groups, C3_GROUPS)),
-            "n_iter": n_iter, "warm": True, "frames": frames,
+            "%d x %s (%s)" % (g["count"], g["cfg"]["name"], n) for g, (_, _, n) in zip(mix.groups, C3_GROUPS)),
+            "n_iter": mix.n_iter, "warm": True, "frames": frames,
             "launch": "hip_graph_per_batch, one stream per geometry"},
         "ms_per_frame": round(ms_b / frames, 5),
         "bytes_per_batch": total_bytes,
@@ -379,68 +522,26 @@ def c3_batch(args):
         "batched_one_stream_ms_per_batch": round(ms_seq, 5),
         "unbatched_ms_per_batch": round(ms_s, 5),
         "batching_speedup": round(ms_s / ms_b, 2),
+        "roofline": mix.roofline(),
     }
     print(json.dumps(out), flush=True)
 
 
 def batch_scan(args):
     """Throughput of the ELT frame against the number of frames per launch (one batched plan per
-    size; RHS + 4 warm PCG passes + fit per frame, one HIP graph per batch)."""
+    size; RHS + 4 warm PCG passes + fit per frame, residual refreshed every 8th step, HIP graphs)."""
     import torch
-    from paper_2009_00946_amd import fewha, synth
+    from paper_2009_00946_amd import synth
     torch.cuda.set_device(0)
     cfg = synth.load_config(args.config)
-    n_iter, gain = cfg["n_iter"], cfg["gain"]
-    model = byte_model(cfg, 4, n_iter)
     rows = []
     for nb in (1, 2, 4, 8, 16, 32, 64, 128):
-        PB = fewha.Plan(cfg, max_batch=nb)
-        P1 = PB if nb == 1 else fewha.Plan(cfg)
-        S = []
-        for f in range(nb):
-            phi = torch.as_tensor(synth.layer_screens_flat(cfg, f), dtype=PB.dtype, device=PB.device)
-            s = P1.apply_A(P1.dwt_forward(phi))
-            s += torch.as_tensor(synth.slope_noise(cfg, f), dtype=PB.dtype, device=PB.device)
-            S.append(s)
-        sb = torch.stack(S).contiguous()
-        cb = torch.zeros((nb, PB.n_coef), dtype=PB.dtype, device=PB.device)
-        ab = torch.zeros((nb, PB.n_act), dtype=PB.dtype, device=PB.device)
-
-        def step(warm=True):
-            PB.pcg_solve_batch(sb, cb, n_iter, warm=warm)
-            PB.fit_dm_batch(cb, gain=gain, out=ab)
-
-        step(warm=False)
-        for _ in range(3):
-            step()
-        torch.cuda.synchronize()
-        g = torch.cuda.CUDAGraph()
-        cap = torch.cuda.Stream()
-        cap.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.graph(g, stream=cap):
-            step()
-        torch.cuda.current_stream().wait_stream(cap)
-        for _ in range(args.warmup):
-            g.replay()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        steps = max(args.steps // nb, 20)
-        e0.record()
-        for _ in range(steps):
-            g.replay()
-        e1.record()
-        torch.cuda.synchronize()
-        assert PB.last_status_batch(nb) == [0] * nb
-        ms = e0.elapsed_time(e1) / steps
-        rows.append({"frames": nb, "ms_per_launch_set": round(ms, 4), "us_per_frame": round(1e3 * ms / nb, 2),
-                     "frames_per_s": round(1e3 * nb / ms, 1),
-                     "effective_GBps": round(model["frame"] * nb / (ms * 1e-3) / 1e9, 1)})
-        print("[batch_scan] %s" % json.dumps(rows[-1]), flush=True)
-        del PB, P1, S, sb, cb, ab, g
-        torch.cuda.empty_cache()
+        r = batched_same_geometry(cfg, nb, max(args.steps // nb, 64), args.warmup)
+        rows.append(r)
+        print("[batch_scan] %s" % json.dumps(r), flush=True)
     out = {"metric": "ELT frame throughput against frames per launch (batched plans)", "value": rows[-1]["us_per_frame"],
            "unit": "us/frame", "n_gpus": 1, "higher_is_better": False, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "%s batched" % cfg["name"], "n_iter": n_iter, "warm": True}, "scan": rows}
+           "config": {"workload": "%s batched" % cfg["name"], "n_iter": cfg["n_iter"], "warm": True}, "scan": rows}
     print(json.dumps(out), flush=True)
 
 
@@ -453,6 +554,8 @@ def main():
     ap.add_argument("--frames", type=int, default=16, help="distinct synthetic slope frames (cycled)")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle CPU time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched forms beside the single frame")
+    ap.add_argument("--batch", type=int, default=32, help="frames per launch of the same-geometry batched form")
     ap.add_argument("--refresh", type=int, default=8,
                     help="FP32: recompute the residual as b - M c every this many frames (0: always carried)")
     ap.add_argument("--eager", action="store_true", help="launch kernels one by one instead of replaying HIP graphs")
@@ -516,10 +619,10 @@ def main():
     torch.cuda.synchronize()
     assert P.last_status() == 0, fewha.STATUS.get(P.last_status())
     run = frame
+    graphs = []
     if not args.eager:
         # one HIP graph per synthetic frame (same launches, its own slope buffer): a replay is
         # one whole frame, RHS + PCG + fitting, with no host work between kernels
-        graphs = []
         cap = torch.cuda.Stream()
         cap.wait_stream(torch.cuda.current_stream())
         for f in range(len(S)):
@@ -612,6 +715,13 @@ def main():
         ref = PAPER_MS[cfg["name"]]
         out["vs_baseline"] = round(ms_mean / ref["cpu_ms"], 5)
         out["paper_context"] = ref
+    if not args.no_batched and P.precision == "fp32":
+        # the bandwidth regime beside the single frame: frames of this geometry batched into every
+        # launch, and the uneven 64-frame mix
+        del graphs
+        torch.cuda.synchronize()
+        out["batched"] = {"same_geometry": batched_same_geometry(cfg, args.batch, args.steps, args.warmup, args.refresh),
+                          "uneven_64": uneven_mix_summary(args.steps, args.warmup)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, S_host, n_iter, args.cpu_budget)
     print(json.dumps(out), flush=True)

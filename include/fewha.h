@@ -302,6 +302,11 @@ typedef enum {
  * so a later fewha_pcg_solve is unaffected.  Returns FEWHA_ERR_INVALID_ARG for an unknown stage. */
 int fewha_stage_launch(const fewha_plan *p, int stage, void *stream);
 
+/* fewha_stage_launch over frames 0..nbatch-1 of a batched plan (one launch, grid y = frame), for
+ * timing the stage kernels in the batched regime of fewha_pcg_solve_batch.  Same contract per
+ * frame; FEWHA_ERR_INVALID_ARG if nbatch is outside 1..max_batch or the stage is unknown. */
+int fewha_stage_launch_batch(const fewha_plan *p, int nbatch, int stage, void *stream);
+
 /* The device status word of the last enqueued solve: FEWHA_ERR_BREAKDOWN when a pass of Alg. 2
  * met a non-positive denominator mu - rho beta / alpha_old (the step-size line; M is SPD, so only
  * rounding or corrupted input can cause it), FEWHA_ERR_NONFINITE when its reductions (rho, mu)

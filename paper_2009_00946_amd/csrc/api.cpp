@@ -218,8 +218,8 @@ int fit_closed(const Plan &P, const void *c, const void *a0, const void *a_m1, d
 }
 
 template <typename T>
-int stage_launch(const Plan &P, int stage, void *stream) {
-    auto o = ops<T>(P, stream);
+int stage_launch(const Plan &P, int stage, void *stream, int nb = 1) {
+    auto o = ops<T>(P, stream, nb);
     switch (stage) {
         case FEWHA_STAGE_WT: return o.wt_pcg(o.B.r, o.B.u);
         case FEWHA_STAGE_PROJ: return o.proj(o.B.u, o.B.v, kProjM);
@@ -227,8 +227,8 @@ int stage_launch(const Plan &P, int stage, void *stream) {
             return o.pt(o.B.v, o.B.x, PassArgs{1, residual_partials(P), P.n_proj * kProjWaves, 0, nullptr, 0});
         default: {
             // the frame's y = W x + alpha D z with the pass update, applied to scratch copies of
-            // r, p, q and c, without publishing scalars
-            const size_t N = P.n_coef;
+            // r, p, q and c (blocks of max_batch frames each), without publishing scalars
+            const size_t N = P.n_coef * size_t(P.max_batch);
             T *scr = reinterpret_cast<T *>(P.ws + P.o_stage);
             o.B.r = scr;
             o.B.p = scr + N;
@@ -307,7 +307,7 @@ int bind_tables(Plan &P, hipStream_t st) {
     TRY(o.fill(o.B.b_prev, NB, 0));
     TRY(o.fill(o.B.r, NB, 0));
     TRY(o.fill(o.B.probe_c, N, 0));
-    TRY(o.fill(reinterpret_cast<T *>(w + P.o_stage), 4 * N, 0));
+    TRY(o.fill(reinterpret_cast<T *>(w + P.o_stage), 4 * N * P.max_batch, 0));
     HIPTRY(hipStreamSynchronize(st));
 
     // staged P^T: every guide star's node rectangle per tile must fit the LDS stage, every
@@ -630,6 +630,14 @@ int fewha_stage_launch(const fewha_plan *p, int stage, void *stream) {
     const Plan &P = p->p;
     if (P.prec == FEWHA_FP64) return stage_launch<double>(P, stage, stream);
     return stage_launch<float>(P, stage, stream);
+}
+
+int fewha_stage_launch_batch(const fewha_plan *p, int nbatch, int stage, void *stream) {
+    TRY(batch_ok(p, nbatch));
+    if (stage < FEWHA_STAGE_WT || stage > FEWHA_STAGE_FWD) return FEWHA_ERR_INVALID_ARG;
+    const Plan &P = p->p;
+    if (P.prec == FEWHA_FP64) return stage_launch<double>(P, stage, stream, nbatch);
+    return stage_launch<float>(P, stage, stream, nbatch);
 }
 
 int fewha_state_get(const fewha_plan *p, void *d_b_prev, void *d_r_prev, void *stream) {

@@ -47,6 +47,7 @@ constexpr int kMaxSeg = 64;
 // guide star) owns workgroups [start[i], start[i+1]).
 struct SegTab {
     int nseg;
+    int chunk;            // tiles per XCD chunk of the workgroup order (0: one contiguous run per XCD)
     int start[kMaxSeg + 1];
     int off[kMaxSeg];     // element offset of the segment's array (layer c_off / sensor v_off)
     int aux[kMaxSeg];     // layers: first grid line in the per-axis line tables; sensors: s_off
@@ -54,6 +55,7 @@ struct SegTab {
     int lt[kMaxSeg];      // layers: log2 of tiles per row; sensors: tiles per row
     int rw[kMaxSeg];      // P^T (layer segments): transpose pairs per grid line, 1..kRtabWidth
     int pitch[kMaxSeg];   // sensors: row pitch of the node grid (n_sub + 1 rounded up to 4)
+    int id[kMaxSeg];      // the segment's layer or guide-star index (segments may be reordered)
 };
 
 // Per-layer offsets and sizes, as a kernel argument (the projection reads every layer).

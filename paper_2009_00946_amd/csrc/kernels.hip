@@ -59,26 +59,32 @@ struct PupilArgs {            // subaperture (i, j) of guide star g is active if
 // broadcast from that lane.  All 64 lanes of the wave must be active.
 struct TileId {
     int seg, loc;
-    int off, n, lt, aux, rw, pitch;
+    int off, n, lt, aux, rw, pitch, id;
 };
 
 // Workgroups are dealt to the chip's 8 XCDs round-robin (workgroup b runs on XCD b mod 8), and
-// every XCD has its own L2.  Tile kernels renumber their ntiles workgroups so that each XCD
-// receives one contiguous run of tiles: neighbouring tiles share halos and table lines, which then
-// meet in one L2 instead of being fetched into all eight.
-constexpr bool kXcdRuns = true;
-
-__device__ __forceinline__ int xcd_tile(int ntiles) {
+// every XCD has its own L2.  Tile kernels renumber their ntiles workgroups: with chunk K = 0 each
+// XCD receives one contiguous run of tiles (neighbouring tiles share halos and table lines, which
+// then meet in one L2); with K > 0 the tile list is cut into chunks of K consecutive tiles dealt to
+// the XCDs in turn, so that every XCD gets a share of every layer (tiles of different layers
+// differ in cost) and the segments listed first are dispatched first, while a chunk's tiles still
+// share an L2.  Tiles past the last whole round of 8 chunks keep their own number.
+__device__ __forceinline__ int xcd_tile(int K, int ntiles) {
     const int b = (int)blockIdx.x;
-    if (!kXcdRuns) return b;
-    const int q = ntiles >> 3, rem = ntiles & 7, x = b & 7;
-    return x * q + min(x, rem) + (b >> 3);
+    if (K == 0) {
+        const int q = ntiles >> 3, rem = ntiles & 7, x = b & 7;
+        return x * q + min(x, rem) + (b >> 3);
+    }
+    const int full = ntiles / (8 * K) * (8 * K);
+    if (b >= full) return b;
+    const int i = b >> 3;
+    return ((i / K) * 8 + (b & 7)) * K + (i % K);
 }
 
 __device__ __forceinline__ TileId find_tile(const SegTab &S, int b) {
     const int lane = threadIdx.x & 63;
     const int st = S.start[lane], of = S.off[lane], nn = S.n[lane], l2 = S.lt[lane], ax = S.aux[lane];
-    const int rw = S.rw[lane], pi = S.pitch[lane];
+    const int rw = S.rw[lane], pi = S.pitch[lane], ix = S.id[lane];
     const unsigned long long m = __ballot(b >= st);
     const int s = 63 - __clzll(m);
     TileId t;
@@ -90,6 +96,7 @@ __device__ __forceinline__ TileId find_tile(const SegTab &S, int b) {
     t.aux = __builtin_amdgcn_readlane(ax, s);
     t.rw = __builtin_amdgcn_readlane(rw, s);
     t.pitch = __builtin_amdgcn_readlane(pi, s);
+    t.id = __builtin_amdgcn_readlane(ix, s);
     return t;
 }
 
@@ -326,8 +333,8 @@ __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src,
     src += blockIdx.y * B.fs_c;
     out += blockIdx.y * B.fs_c;
     const int tid = threadIdx.x;
-    const TileId id = find_tile(S, xcd_tile(gridDim.x));
-    const int l = id.seg, n = id.n, lt = id.lt;
+    const TileId id = find_tile(S, xcd_tile(S.chunk, gridDim.x));
+    const int l = id.id, n = id.n, lt = id.lt;
     const int T0 = n < kWtTile ? n : kWtTile;
     const int y0 = (id.loc >> lt) * T0, x0 = (id.loc & ((1 << lt) - 1)) * T0;
     const long coff = id.off;
@@ -526,8 +533,8 @@ __global__ __launch_bounds__(kB) void k_proj(SegTab S, LayTab LT, InvVar IV, Pup
     out += blockIdx.y * (MODE == kProjM ? B.fs_v : B.fs_s);
     if (MODE == kProjPol) add += blockIdx.y * B.fs_s;
     const int tid = threadIdx.x;
-    const TileId id = find_tile(S, xcd_tile(gridDim.x));
-    const int g = id.seg, ns = id.n, tpr = id.lt;
+    const TileId id = find_tile(S, xcd_tile(S.chunk, gridDim.x));
+    const int g = id.id, ns = id.n, tpr = id.lt;
     const int ti = id.loc / tpr, tj = id.loc - ti * tpr;
     const int i0 = ti * kProjTile, j0 = tj * kProjTile;
     const Ent<T> *__restrict__ xt = (MODE == kProjPol ? B.xdm : B.xtab) + (long)g * nl * B.maxnv;
@@ -646,8 +653,8 @@ __global__ __launch_bounds__(kB) void k_gt(SegTab S, InvVar IV, PupilArgs pa, co
     in += blockIdx.y * fs_s;
     v += blockIdx.y * fs_v;
     const int tid = threadIdx.x;
-    const TileId id = find_tile(S, xcd_tile(gridDim.x));
-    const int g = id.seg, ns = id.n, tpr = id.lt;
+    const TileId id = find_tile(S, xcd_tile(S.chunk, gridDim.x));
+    const int g = id.id, ns = id.n, tpr = id.lt;
     const int ti = id.loc / tpr, tj = id.loc - ti * tpr;
     const int i0 = ti * kProjTile, j0 = tj * kProjTile;
     {
@@ -744,7 +751,7 @@ __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restr
         return;
     }
     const int tid = threadIdx.x, lane = tid & 63;
-    const int vt = xcd_tile(PA.k >= 0 ? (int)gridDim.x - 1 : (int)gridDim.x);
+    const int vt = xcd_tile(S.chunk, PA.k >= 0 ? (int)gridDim.x - 1 : (int)gridDim.x);
     const TileId id = find_tile(S, vt);
     const int n = id.n, lt = id.lt;
     const int T0 = n < NT ? n : NT;
@@ -838,9 +845,9 @@ __global__ __launch_bounds__(kB) void k_pt_scan(SegTab S, const T *__restrict__ 
                     PA.publish);
         return;
     }
-    const int vt = xcd_tile(PA.k >= 0 ? (int)gridDim.x - 1 : (int)gridDim.x);
+    const int vt = xcd_tile(S.chunk, PA.k >= 0 ? (int)gridDim.x - 1 : (int)gridDim.x);
     const TileId id = find_tile(S, vt);
-    const int l = id.seg, n = id.n, lt = id.lt;
+    const int l = id.id, n = id.n, lt = id.lt;
     const int T0 = n < NT ? n : NT;
     const int a = threadIdx.x >> 4, b = threadIdx.x & 15;
     if (a >= T0 || b >= T0) return;
@@ -1001,8 +1008,8 @@ __global__ __launch_bounds__((FwdLanes<KF, TQ>::block)) void k_fwd(SegTab S, con
     if constexpr (EPI == kEpiRhs) {
         if (blockIdx.x == 0 && tid == 0) reset_scalars(B.sc + 1);  // the state "before pass 0"
     }
-    const TileId id = find_tile(S, xcd_tile(gridDim.x));
-    const int l = id.seg, n = id.n, lt = id.lt, nm = n - 1;
+    const TileId id = find_tile(S, xcd_tile(S.chunk, gridDim.x));
+    const int l = id.id, n = id.n, lt = id.lt, nm = n - 1;
     const int qy = (id.loc >> lt) * TQ, qx = (id.loc & ((1 << lt) - 1)) * TQ;
     const long coff = id.off;
     const int oy = qy << KF, ox = qx << KF;

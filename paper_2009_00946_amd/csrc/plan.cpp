@@ -1,5 +1,6 @@
 // Host side of the FEWHA plan: configuration checks, ray geometry, vector layouts, tile tables
 // and the workspace map.  Touches no GPU, so configuration validation is testable anywhere.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -105,7 +106,7 @@ void layout_workspace(Plan *P) {
     P->o_v = take(E * P->n_nodes * MB);
     P->o_ll = take(E * ll_stride(N) * MB);
     P->o_probe_c = take(E * N);
-    P->o_stage = take(4 * E * N);  // stage timing: scratch r, p, q, c
+    P->o_stage = take(4 * E * N * MB);  // stage timing: scratch r, p, q, c of every frame
     P->o_probe_s = take(E * P->n_slopes);
     P->o_over = take(sizeof(int) * P->nw);
     P->o_partials = take(sizeof(double) * 3 * kPartialPitch * MB);
@@ -294,21 +295,42 @@ int plan_create(const fewha_config *cfg, Plan **out) {
         return k;
     };
     P->seg_wt.nseg = P->seg_pt.nseg = P->seg_fwd.nseg = P->nl;
+    // P^T: chunks of 16 tiles per XCD turn (every XCD gets a share of the heavy, first-listed layers)
+    P->seg_pt.chunk = 16;
     for (int i = 0; i <= kMaxSeg; ++i)  // entries past the last segment never match a workgroup
         P->seg_wt.start[i] = P->seg_pt.start[i] = P->seg_fwd.start[i] = P->seg_proj.start[i] = 0x7fffffff;
+    // P^T segments (layers) heaviest first: a tile's gather work grows with the sensor nodes per
+    // layer cell, so the coarsest grids come first and their tiles are dispatched first
+    std::vector<int> pt_order(P->nl);
+    for (int l = 0; l < P->nl; ++l) pt_order[l] = l;
+    std::stable_sort(pt_order.begin(), pt_order.end(),
+                     [&](int a, int b) { return P->lay[a].spacing > P->lay[b].spacing; });
+    for (int i = 0; i < P->nl; ++i) {
+        const int l = pt_order[i];
+        const int n = P->lay[l].n, tp = n < kPtTile ? n : kPtTile;
+        SegTab &S = P->seg_pt;
+        S.start[i] = P->n_pt;
+        S.off[i] = int(P->dlay[l].c_off);
+        S.aux[i] = P->dlay[l].r_off;
+        S.n[i] = n;
+        S.lt[i] = lg2(n / tp);
+        S.id[i] = l;
+        P->n_pt += (n / tp) * (n / tp);
+    }
     for (int l = 0; l < P->nl; ++l) {
         const int n = P->lay[l].n, off = int(P->dlay[l].c_off);
-        const int tw = n < kWtTile ? n : kWtTile, tp = n < kPtTile ? n : kPtTile;
+        const int tw = n < kWtTile ? n : kWtTile;
         const int nq = (n >> P->kf) / P->tq;
-        SegTab *S[3] = {&P->seg_wt, &P->seg_pt, &P->seg_fwd};
-        const int per_row[3] = {n / tw, n / tp, nq};
-        int *cnt[3] = {&P->n_wt, &P->n_pt, &P->n_fwd};
-        for (int k = 0; k < 3; ++k) {
+        SegTab *S[2] = {&P->seg_wt, &P->seg_fwd};
+        const int per_row[2] = {n / tw, nq};
+        int *cnt[2] = {&P->n_wt, &P->n_fwd};
+        for (int k = 0; k < 2; ++k) {
             S[k]->start[l] = *cnt[k];
             S[k]->off[l] = off;
             S[k]->aux[l] = P->dlay[l].r_off;
             S[k]->n[l] = n;
             S[k]->lt[l] = lg2(per_row[k]);
+            S[k]->id[l] = l;
             *cnt[k] += per_row[k] * per_row[k];
         }
         // every inverse-DWT cone of this layer must fit the kernel's load slots and LDS
@@ -345,6 +367,7 @@ int plan_create(const fewha_config *cfg, Plan **out) {
         P->seg_proj.aux[g] = int(P->dwfs[g].s_off);
         P->seg_proj.n[g] = P->wfs[g].n_sub;
         P->seg_proj.lt[g] = tpr;
+        P->seg_proj.id[g] = g;
         P->n_proj += tpr * tpr;
     }
     P->seg_proj.start[P->nw] = P->n_proj;

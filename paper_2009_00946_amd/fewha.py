@@ -23,7 +23,7 @@ EXPORTS = ["fewha_plan_create", "fewha_workspace_bytes", "fewha_plan_bind", "few
            "fewha_prior_dot", "fewha_plan_set_batch", "fewha_apply_A_batch", "fewha_apply_At_batch",
            "fewha_apply_M_batch", "fewha_pcg_solve_batch", "fewha_fit_dm_batch", "fewha_last_status_batch",
            "fewha_pol_slopes", "fewha_fit_dm_closed", "fewha_pol_slopes_batch", "fewha_fit_dm_closed_batch",
-           "fewha_fit_dm_ls", "fewha_cn2_gradient", "fewha_dwt_forward_noalloc"]
+           "fewha_fit_dm_ls", "fewha_cn2_gradient", "fewha_dwt_forward_noalloc", "fewha_stage_launch_batch"]
 
 
 class FewhaError(RuntimeError):
@@ -97,6 +97,7 @@ def load_library():
     L.fewha_precond_table.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     L.fewha_last_status.argtypes = [vp]
     L.fewha_stage_launch.argtypes = [vp, ctypes.c_int, vp]
+    L.fewha_stage_launch_batch.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp]
     L.fewha_strerror.argtypes = [ctypes.c_int]
     L.fewha_strerror.restype = ctypes.c_char_p
     _lib = L
@@ -419,6 +420,11 @@ class Plan:
     def stage_launch(self, stage):
         """Enqueue one launch of one PCG-pass stage ("wt", "proj", "pt", "fwd") for timing."""
         _check(_lib.fewha_stage_launch(self._h, self.STAGES[stage], self._stream()), "fewha_stage_launch")
+
+    def stage_launch_batch(self, stage, nbatch):
+        """Enqueue one launch of one PCG-pass stage over frames 0..nbatch-1 of a batched plan."""
+        _check(_lib.fewha_stage_launch_batch(self._h, int(nbatch), self.STAGES[stage], self._stream()),
+               "fewha_stage_launch_batch")
 
     def last_status(self):
         return _lib.fewha_last_status(self._h)

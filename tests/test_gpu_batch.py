@@ -123,3 +123,34 @@ def test_large_batch_cold_frames_equal_single():
         torch.cuda.synchronize()
         assert torch.equal(cb[f], c1), "frame %d" % f
         assert torch.equal(rb[f * n_iter:(f + 1) * n_iter], r1), "resnorm frame %d" % f
+
+
+@pytest.mark.parametrize("nb", [1, 3])
+def test_stage_launches_leave_the_solver_state_alone(nb):
+    """Stage launches for timing (single-frame and batched forms) between the frames of a warm
+    chain change neither its iterates nor its carried state: the chain equals, bitwise, the same
+    chain run without them."""
+    _need_gpu()
+    from oracle import Oracle
+    from paper_2009_00946_amd import fewha
+    cfg = synth.load_config("t1_mixed")
+    O = Oracle(cfg, precond=False)
+    n_iter = cfg["n_iter"]
+    runs = []
+    for with_stages in (False, True):
+        PB = fewha.Plan(cfg, precision="fp32", max_batch=nb)
+        cb = torch.zeros((nb, PB.n_coef), dtype=PB.dtype, device=PB.device)
+        for t in range(3):
+            sb = torch.stack([torch.as_tensor(_slopes(O, cfg, f + nb * t), dtype=PB.dtype, device=PB.device)
+                              for f in range(nb)]).contiguous()
+            PB.pcg_solve_batch(sb, cb, n_iter, warm=t > 0)
+            if with_stages:
+                for st in ("wt", "proj", "pt", "fwd"):
+                    PB.stage_launch_batch(st, nb)
+                    PB.stage_launch(st)
+        torch.cuda.synchronize()
+        assert PB.last_status_batch(nb) == [0] * nb
+        b, r = PB.state_get()
+        runs.append((cb.clone(), b.clone(), r.clone()))
+    for a, b in zip(*runs):
+        assert torch.equal(a, b)
