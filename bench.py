@@ -362,14 +362,15 @@ def roofline_of(cfg, us, frames, n_iter, elem=4):
             "us_per_launch": round(us[dom], 3), "bytes_per_launch": nbytes, "frames_per_launch": frames}
 
 
-def batched_same_geometry(cfg, nb, steps, warmup, refresh=8):
+def batched_same_geometry(cfg, nb, steps, warmup, refresh=8, tuned=True):
     """nb frames of one geometry per launch (RHS + n_iter warm PCG passes + fit each, residual
     refreshed every `refresh`-th step): us per frame, effective GB/s and the roofline object of the
     batched launch's dominant kernel."""
     import torch
-    from paper_2009_00946_amd import fewha
+    from paper_2009_00946_amd import fewha, tune
     n_iter, gain = cfg["n_iter"], cfg["gain"]
     PB = fewha.Plan(cfg, max_batch=nb)
+    shapes = tune.tuned(PB) if tuned else None
     P1 = fewha.Plan(cfg)
     sb = batch_slopes(P1, cfg, nb)
     del P1
@@ -394,7 +395,8 @@ def batched_same_geometry(cfg, nb, steps, warmup, refresh=8):
            "frames_per_s": round(1e3 * nb / ms, 1), "effective_GBps": round(gbps, 1),
            "frac_hbm_peak": round(gbps / HBM_PEAK_GBPS, 4), "residual_refresh_every": refresh or None,
            "roofline": roofline_of(cfg, us, nb, n_iter, elem),
-           "stages_us_per_launch": {k: round(v, 3) for k, v in us.items()}}
+           "stages_us_per_launch": {k: round(v, 3) for k, v in us.items()},
+           "launch_shapes": shapes and shapes["tuning"]}
     del PB, sb, cb, ab, g_warm, g_fresh, seq
     torch.cuda.empty_cache()
     return out
@@ -405,12 +407,14 @@ class UnevenMix:
     fit each; each geometry's frames in one batched plan (one launch per stage over all of them),
     the three plans on streams of their own, forked and joined inside one HIP graph."""
 
-    def __init__(self, with_single=False):
+    def __init__(self, with_single=False, tuned=True):
         import torch
-        from paper_2009_00946_amd import fewha
+        from paper_2009_00946_amd import fewha, tune
         self.groups = []
         for cfg, count in c3_configs():
             PB = fewha.Plan(cfg, max_batch=count)
+            if tuned:
+                tune.tuned(PB)
             P1 = fewha.Plan(cfg)
             sb = batch_slopes(P1, cfg, count)
             g = dict(cfg=cfg, count=count, PB=PB, sb=sb,
@@ -472,8 +476,8 @@ class UnevenMix:
         return best[1]
 
 
-def uneven_mix_summary(steps, warmup, refresh=8):
-    mix = UnevenMix()
+def uneven_mix_summary(steps, warmup, refresh=8, tuned=True):
+    mix = UnevenMix(tuned=tuned)
     g_warm = capture(mix.concurrent)
     g_fresh = capture(lambda warm=True: mix.concurrent(warm, fresh=True), warm_steps=0)
     ms = time_graphs([g_fresh] + [g_warm] * (refresh - 1), max(steps // 8, 2 * refresh), warmup)
@@ -555,6 +559,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle CPU time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched forms beside the single frame")
+    ap.add_argument("--no-tune", action="store_true", help="default launch shapes instead of the autotuner's")
     ap.add_argument("--batch", type=int, default=32, help="frames per launch of the same-geometry batched form")
     ap.add_argument("--refresh", type=int, default=8,
                     help="FP32: recompute the residual as b - M c every this many frames (0: always carried)")
@@ -579,12 +584,13 @@ def main():
         return
 
     import torch
-    from paper_2009_00946_amd import fewha, synth
+    from paper_2009_00946_amd import fewha, synth, tune
 
     torch.cuda.set_device(0)
     cfg = synth.load_config(args.config)
     n_iter, gain = cfg["n_iter"], cfg["gain"]
     P = fewha.Plan(cfg)
+    tuning = None if args.no_tune else tune.tuned(P)
     stream = torch.cuda.current_stream()
 
     # synthetic frames, resident on the device before timing
@@ -693,7 +699,8 @@ def main():
         "config": {"workload": "%s: %s" % (cfg["name"], cfg["description"]), "n_iter": n_iter, "warm": True,
                    "gain": gain, "n_coef": model["n_coef"], "n_slopes": P.n_slopes, "n_act": P.n_act,
                    "launch": "eager" if args.eager else "hip_graph_per_frame",
-                   "residual_refresh_every": args.refresh or None},
+                   "residual_refresh_every": args.refresh or None,
+                   "launch_shapes": tuning and dict(tuning["tuning"], autotuned=not tuning["cached"])},
         "ms_median": round(float(np.median(per)), 5),
         "ms_p99": round(float(np.percentile(per, 99)), 5),
         "frames_per_s": round(1e3 / ms_mean, 1),
@@ -720,8 +727,9 @@ def main():
         # launch, and the uneven 64-frame mix
         del graphs
         torch.cuda.synchronize()
-        out["batched"] = {"same_geometry": batched_same_geometry(cfg, args.batch, args.steps, args.warmup, args.refresh),
-                          "uneven_64": uneven_mix_summary(args.steps, args.warmup)}
+        out["batched"] = {"same_geometry": batched_same_geometry(cfg, args.batch, args.steps, args.warmup, args.refresh,
+                                                                 tuned=not args.no_tune),
+                          "uneven_64": uneven_mix_summary(args.steps, args.warmup, tuned=not args.no_tune)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, S_host, n_iter, args.cpu_budget)
     print(json.dumps(out), flush=True)

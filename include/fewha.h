@@ -307,6 +307,40 @@ int fewha_stage_launch(const fewha_plan *p, int stage, void *stream);
  * frame; FEWHA_ERR_INVALID_ARG if nbatch is outside 1..max_batch or the stage is unknown. */
 int fewha_stage_launch_batch(const fewha_plan *p, int nbatch, int stage, void *stream);
 
+/* Launch shapes of a plan that change no result beyond the order of the PCG reductions' partial
+ * sums (Sec. 3.4 asks for as few, and as well-shaped, kernel calls as the hardware allows; these
+ * shapes are chosen per geometry, see fewha_autotune). */
+typedef struct {
+    int kf;         /* forward-DWT levels done on tiles over the whole GPU (1 or 2, at most J); the
+                       levels beyond run per layer in one workgroup */
+    int tq;         /* level-kf quads per edge of a fine forward-DWT tile: 1, 2, 4 or 8 (a tile
+                       covers (tq 2^kf)^2 layer nodes) */
+    int chunk_wt;   /* per tile kernel (W^T, projection, P^T, fine W): tiles per XCD chunk of the
+                       workgroup order, 0..256; 0 = one contiguous run of tiles per XCD */
+    int chunk_proj;
+    int chunk_pt;
+    int chunk_fwd;
+} fewha_tuning;
+
+/* The plan's current launch shapes (defaults after fewha_plan_create: kf = min(2, J), tq the
+ * largest of 8, 4, 2, 1 that fits the smallest layer, chunk_pt 16, other chunks 0). */
+int fewha_get_tuning(const fewha_plan *p, fewha_tuning *h_tuning);
+
+/* Set the launch shapes (host only; the plan stays bound, its workspace layout is unchanged).
+ * FEWHA_ERR_INVALID_ARG for values outside the ranges above, FEWHA_ERR_UNSUPPORTED when the
+ * split does not fit the coarse workgroup's LDS or the partial-sum buffer; the plan is then
+ * unchanged.  Must not be called while work of the plan is in flight. */
+int fewha_set_tuning(fewha_plan *p, const fewha_tuning *h_tuning);
+
+/* Autotuner: times the PCG-pass stage kernels (fewha_stage_launch over nbatch frames, each
+ * timing a HIP graph of back-to-back launches on a private stream) for every valid (kf, tq) and
+ * then every chunk in {0, 4, 8, 16, 32} of each tile kernel, and keeps the fastest of each; the
+ * result is set on the plan and returned in *h_best.  h_us (nullable, 4 values) receives the
+ * tuned per-launch microseconds of the stages wt, proj, pt, fwd.  Synchronous; needs a bound
+ * plan; resets the warm-restart state and the PCG scalars (as fewha_plan_bind leaves them), so it
+ * belongs before the first frame.  nbatch in 1..max_batch. */
+int fewha_autotune(fewha_plan *p, int nbatch, fewha_tuning *h_best, double *h_us);
+
 /* The device status word of the last enqueued solve: FEWHA_ERR_BREAKDOWN when a pass of Alg. 2
  * met a non-positive denominator mu - rho beta / alpha_old (the step-size line; M is SPD, so only
  * rounding or corrupted input can cause it), FEWHA_ERR_NONFINITE when its reductions (rho, mu)

@@ -632,6 +632,149 @@ int fewha_stage_launch(const fewha_plan *p, int stage, void *stream) {
     return stage_launch<float>(P, stage, stream);
 }
 
+int fewha_get_tuning(const fewha_plan *p, fewha_tuning *t) {
+    if (!p || !t) return FEWHA_ERR_INVALID_ARG;
+    const Plan &P = p->p;
+    *t = fewha_tuning{P.kf, P.tq, P.seg_wt.chunk, P.seg_proj.chunk, P.seg_pt.chunk, P.seg_fwd.chunk};
+    return FEWHA_OK;
+}
+
+int fewha_set_tuning(fewha_plan *p, const fewha_tuning *t) {
+    if (!p || !t) return FEWHA_ERR_INVALID_ARG;
+    const int ch[4] = {t->chunk_wt, t->chunk_proj, t->chunk_pt, t->chunk_fwd};
+    for (int c : ch)
+        if (c < 0 || c > 256) return FEWHA_ERR_INVALID_ARG;
+    Plan &P = p->p;
+    Plan keep = P;
+    P.seg_fwd.chunk = t->chunk_fwd;
+    const int st = set_fwd_split(&P, t->kf, t->tq);
+    if (st != FEWHA_OK) {
+        P = keep;
+        return st;
+    }
+    P.seg_wt.chunk = t->chunk_wt;
+    P.seg_proj.chunk = t->chunk_proj;
+    P.seg_pt.chunk = t->chunk_pt;
+    return FEWHA_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Device microseconds per launch of one stage over nb frames: `reps` launches captured in a HIP
+// graph on stream st, replayed `replays` times between two events.
+template <typename T>
+int time_stage(const Plan &P, int stage, int nb, hipStream_t st, hipEvent_t e0, hipEvent_t e1, double *us) {
+    constexpr int reps = 10, replays = 3;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    HIPTRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    int rc = FEWHA_OK;
+    for (int i = 0; i < reps && rc == FEWHA_OK; ++i) rc = stage_launch<T>(P, stage, st, nb);
+    const hipError_t ec = hipStreamEndCapture(st, &g);
+    if (rc != FEWHA_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    HIPTRY(ec);
+    hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(ge, st);  // warm-up replay
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    for (int i = 0; i < replays && e == hipSuccess; ++i) e = hipGraphLaunch(ge, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (ge) (void)hipGraphExecDestroy(ge);
+    (void)hipGraphDestroy(g);
+    HIPTRY(e);
+    *us = 1e3 * double(ms) / (reps * replays);
+    return FEWHA_OK;
+}
+
+template <typename T>
+int autotune_on(fewha_plan *h, int nb, hipStream_t st, hipEvent_t e0, hipEvent_t e1, fewha_tuning *best, double *us) {
+    Plan &P = h->p;
+    const long NB = (long)P.n_coef * nb;
+    auto o = ops<T>(P, st, nb);
+    // a non-degenerate pass state on every frame: r = 1, then one pass of the stages fills u, v,
+    // x, the partial sums and the current step (so that no stage runs a stopped-solve shortcut)
+    TRY(o.init_scalars());
+    TRY(o.fill(o.B.r, NB, (T)1));
+    for (int s = FEWHA_STAGE_WT; s <= FEWHA_STAGE_FWD; ++s) TRY(stage_launch<T>(P, s, st, nb));
+    fewha_tuning t{};
+    TRY(fewha_get_tuning(h, &t));
+    // 1. the forward-DWT split (kf, tq), timed on the forward-DWT stage
+    double bt = 1e30;
+    fewha_tuning bs = t;
+    for (int kf = 1; kf <= 2; ++kf)
+        for (int tq : {1, 2, 4, 8}) {
+            fewha_tuning c = t;
+            c.kf = kf;
+            c.tq = tq;
+            if (fewha_set_tuning(h, &c) != FEWHA_OK) continue;
+            double u = 0;
+            TRY(time_stage<T>(P, FEWHA_STAGE_FWD, nb, st, e0, e1, &u));
+            if (u < bt) {
+                bt = u;
+                bs = c;
+            }
+        }
+    t = bs;
+    TRY(fewha_set_tuning(h, &t));
+    // 2. each tile kernel's XCD chunk, on its own stage
+    int *chunk[4] = {&t.chunk_wt, &t.chunk_proj, &t.chunk_pt, &t.chunk_fwd};
+    for (int s = FEWHA_STAGE_WT; s <= FEWHA_STAGE_FWD; ++s) {
+        double bu = 1e30;
+        int bk = *chunk[s];
+        for (int k : {0, 4, 8, 16, 32}) {
+            *chunk[s] = k;
+            TRY(fewha_set_tuning(h, &t));
+            double u = 0;
+            TRY(time_stage<T>(P, s, nb, st, e0, e1, &u));
+            if (u < bu) {
+                bu = u;
+                bk = k;
+            }
+        }
+        *chunk[s] = bk;
+        TRY(fewha_set_tuning(h, &t));
+        if (us) us[s] = bu;
+    }
+    // the state fewha_plan_bind leaves: no warm-restart history, fresh scalars
+    TRY(o.fill(o.B.b_prev, NB, (T)0));
+    TRY(o.fill(o.B.r, NB, (T)0));
+    TRY(o.init_scalars());
+    HIPTRY(hipStreamSynchronize(st));
+    *best = t;
+    return FEWHA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fewha_autotune(fewha_plan *p, int nbatch, fewha_tuning *h_best, double *h_us) {
+    TRY(batch_ok(p, nbatch));
+    if (!h_best) return FEWHA_ERR_INVALID_ARG;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPTRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));  // default priority
+    int rc = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess ? FEWHA_OK : FEWHA_ERR_HIP;
+    fewha_tuning keep{};
+    fewha_get_tuning(p, &keep);
+    if (rc == FEWHA_OK)
+        rc = p->p.prec == FEWHA_FP64 ? autotune_on<double>(p, nbatch, st, e0, e1, h_best, h_us)
+                                     : autotune_on<float>(p, nbatch, st, e0, e1, h_best, h_us);
+    if (rc != FEWHA_OK) fewha_set_tuning(p, &keep);
+    (void)hipStreamSynchronize(st);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(st);
+    return rc;
+}
+
 int fewha_stage_launch_batch(const fewha_plan *p, int nbatch, int stage, void *stream) {
     TRY(batch_ok(p, nbatch));
     if (stage < FEWHA_STAGE_WT || stage > FEWHA_STAGE_FWD) return FEWHA_ERR_INVALID_ARG;

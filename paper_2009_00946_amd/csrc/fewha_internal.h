@@ -237,6 +237,8 @@ inline int residual_partials(const Plan &P) {
 inline size_t ll_stride(size_t n_coef) { return (n_coef / 4 + 1 + 3) & ~size_t(3); }
 
 void layout_workspace(Plan *P);
+// Forward-DWT split and fine-tile table (validated; FEWHA_OK, _INVALID_ARG or _UNSUPPORTED).
+int set_fwd_split(Plan *P, int kf, int tq);
 int level_band(int n, int J, int row, int col, int *s, int *o);
 // Inverse-DWT cone of a tile: level-s region origins / sizes (level-s index space), s = 0..J.
 void wt_cone(int y0, int x0, int T0, int J, int *loY, int *loX, int *LY, int *LX);

@@ -533,7 +533,8 @@ __global__ __launch_bounds__(kB) void k_proj(SegTab S, LayTab LT, InvVar IV, Pup
     out += blockIdx.y * (MODE == kProjM ? B.fs_v : B.fs_s);
     if (MODE == kProjPol) add += blockIdx.y * B.fs_s;
     const int tid = threadIdx.x;
-    const TileId id = find_tile(S, xcd_tile(S.chunk, gridDim.x));
+    const int tile = xcd_tile(S.chunk, gridDim.x);
+    const TileId id = find_tile(S, tile);
     const int g = id.id, ns = id.n, tpr = id.lt;
     const int ti = id.loc / tpr, tj = id.loc - ti * tpr;
     const int i0 = ti * kProjTile, j0 = tj * kProjTile;
@@ -639,10 +640,11 @@ __global__ __launch_bounds__(kB) void k_proj(SegTab S, LayTab LT, InvVar IV, Pup
                 (T)0.5 * ((-sSx[s11] - sSy[s11]) + (sSx[s10] - sSy[s10]) + (-sSx[s01] + sSy[s01]) + (sSx[s00] + sSy[s00]));
         }
     }
-    // one partial per wave, no block reduction: slots blockIdx.x * (kB / 64) + wave
+    // one partial per wave, no block reduction: slots tile * (kB / 64) + wave (by tile, so that the
+    // sums' order does not depend on the workgroup order)
     static_assert(kB / 64 == kProjWaves, "one projection partial slot per wave");
     e2 = wave_sum(e2);
-    if ((tid & 63) == 0) B.partials[2 * kPartialPitch + (int)blockIdx.x * kProjWaves + (tid >> 6)] = e2;
+    if ((tid & 63) == 0) B.partials[2 * kPartialPitch + tile * kProjWaves + (tid >> 6)] = e2;
 }
 
 // Gamma^T C s (kGtRhs) or Gamma^T mask s (kGtAdj) on the node tiles of k_proj.
@@ -1008,7 +1010,8 @@ __global__ __launch_bounds__((FwdLanes<KF, TQ>::block)) void k_fwd(SegTab S, con
     if constexpr (EPI == kEpiRhs) {
         if (blockIdx.x == 0 && tid == 0) reset_scalars(B.sc + 1);  // the state "before pass 0"
     }
-    const TileId id = find_tile(S, xcd_tile(S.chunk, gridDim.x));
+    const int tile = xcd_tile(S.chunk, gridDim.x);
+    const TileId id = find_tile(S, tile);
     const int l = id.id, n = id.n, lt = id.lt, nm = n - 1;
     const int qy = (id.loc >> lt) * TQ, qx = (id.loc & ((1 << lt) - 1)) * TQ;
     const long coff = id.off;
@@ -1085,11 +1088,11 @@ __global__ __launch_bounds__((FwdLanes<KF, TQ>::block)) void k_fwd(SegTab S, con
         if (s < KF) __syncthreads();
     }
     if constexpr (EPI == kEpiPcg || EPI == kEpiRhs) {
-        // one partial pair per wave, no block reduction: slots blockIdx.x * (FB / 64) + wave
+        // one partial pair per wave, no block reduction: slots tile * (FB / 64) + wave (by tile)
         rho = wave_sum(rho);
         dz = wave_sum(dz);
         if ((tid & 63) == 0) {
-            const int slot = (int)blockIdx.x * (FB / 64) + (tid >> 6);
+            const int slot = tile * (FB / 64) + (tid >> 6);
             B.partials[slot] = rho;
             B.partials[kPartialPitch + slot] = dz;
         }

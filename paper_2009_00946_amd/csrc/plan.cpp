@@ -114,6 +114,51 @@ void layout_workspace(Plan *P) {
     P->ws_bytes = o;
 }
 
+// Forward-DWT split (Eq. (fewha)'s W): levels 1..kf on tiles of tq x tq level-kf quads over the
+// whole GPU, levels kf+1..J per layer in one workgroup whose LDS holds the level-kf approximation.
+// Rebuilds the fine tiles' segment table; the workspace layout does not depend on the split.
+int set_fwd_split(Plan *P, int kf, int tq) {
+    int max_n = 0, min_n = 1 << 30;
+    for (auto &L : P->lay) {
+        max_n = L.n > max_n ? L.n : max_n;
+        min_n = L.n < min_n ? L.n : min_n;
+    }
+    if (kf < 1 || kf > 2 || kf > P->J || (tq != 1 && tq != 2 && tq != 4 && tq != 8) || tq > (min_n >> kf))
+        return FEWHA_ERR_INVALID_ARG;
+    // the level-kf block and its first coarse level in LDS; a block too large for that is read from
+    // global memory by the first coarse level, leaving two smaller levels in LDS
+    const size_t m = size_t(max_n >> kf);
+    size_t lds = kf < P->J ? (m * m + (m / 2) * (m / 2)) * P->elem : 0;
+    if (lds > 150 * 1024) lds = ((m / 4) * (m / 4) + (m / 2) * (m / 2)) * P->elem;
+    if (lds > 150 * 1024 || m * m > size_t(16) * 1024) return FEWHA_ERR_UNSUPPORTED;
+    SegTab S{};
+    S.nseg = P->nl;
+    S.chunk = P->seg_fwd.chunk;
+    for (int i = 0; i <= kMaxSeg; ++i) S.start[i] = 0x7fffffff;  // past the last segment: no match
+    int n_fwd = 0;
+    for (int l = 0; l < P->nl; ++l) {
+        const int n = P->lay[l].n, nq = (n >> kf) / tq;
+        int lt = 0;
+        while ((1 << lt) < nq) ++lt;
+        S.start[l] = n_fwd;
+        S.off[l] = int(P->dlay[l].c_off);
+        S.aux[l] = P->dlay[l].r_off;
+        S.n[l] = n;
+        S.lt[l] = lt;
+        S.id[l] = l;
+        n_fwd += nq * nq;
+    }
+    S.start[P->nl] = n_fwd;
+    const int nres = n_fwd * fwd_waves(kf, tq) + (kf < P->J ? P->nl * kCoarseWaves : 0);
+    if (nres > kPartialPitch) return FEWHA_ERR_UNSUPPORTED;
+    P->kf = kf;
+    P->tq = tq;
+    P->coarse_lds = lds;
+    P->seg_fwd = S;
+    P->n_fwd = n_fwd;
+    return FEWHA_OK;
+}
+
 int plan_create(const fewha_config *cfg, Plan **out) {
     if (!cfg || !out) return FEWHA_ERR_INVALID_ARG;
     *out = nullptr;
@@ -264,25 +309,7 @@ int plan_create(const fewha_config *cfg, Plan **out) {
                                                 std::pow(P->lay[l].spacing / P->dwfs[0].d, -5.0 / 3.0) *
                                                 std::pow(2.0, -(11.0 / 3.0) * (s - 1));
 
-    // forward DWT split: levels 1..kf on tiles of tq x tq level-kf quads over the whole GPU, the
-    // remaining ones per layer in one workgroup whose LDS holds the level-kf approximation
-    int max_n = 0, min_n = 1 << 30;
-    for (auto &L : P->lay) {
-        max_n = L.n > max_n ? L.n : max_n;
-        min_n = L.n < min_n ? L.n : min_n;
-    }
-    P->kf = P->J < 2 ? P->J : 2;
-    P->tq = kFwdQuads;
-    while (P->tq > (min_n >> P->kf)) P->tq >>= 1;
-    {
-        // the level-kf block and its first coarse level in LDS; a block too large for that is
-        // read from global memory by the first coarse level, leaving two smaller levels in LDS
-        size_t m = size_t(max_n >> P->kf);
-        P->coarse_lds = P->kf < P->J ? (m * m + (m / 2) * (m / 2)) * P->elem : 0;
-        if (P->coarse_lds > 150 * 1024) P->coarse_lds = ((m / 4) * (m / 4) + (m / 2) * (m / 2)) * P->elem;
-    }
-    if (P->coarse_lds > 150 * 1024 || (size_t(max_n >> P->kf) * (max_n >> P->kf) > size_t(16) * 1024) ||
-        P->n_coef >= (size_t(1) << 31) || P->n_nodes >= (size_t(1) << 31) || P->n_slopes >= (size_t(1) << 31)) {
+    if (P->n_coef >= (size_t(1) << 31) || P->n_nodes >= (size_t(1) << 31) || P->n_slopes >= (size_t(1) << 31)) {
         delete P;
         return FEWHA_ERR_UNSUPPORTED;
     }
@@ -294,7 +321,7 @@ int plan_create(const fewha_config *cfg, Plan **out) {
         while ((1 << k) < v) ++k;
         return k;
     };
-    P->seg_wt.nseg = P->seg_pt.nseg = P->seg_fwd.nseg = P->nl;
+    P->seg_wt.nseg = P->seg_pt.nseg = P->nl;
     // P^T: chunks of 16 tiles per XCD turn (every XCD gets a share of the heavy, first-listed layers)
     P->seg_pt.chunk = 16;
     for (int i = 0; i <= kMaxSeg; ++i)  // entries past the last segment never match a workgroup
@@ -318,21 +345,15 @@ int plan_create(const fewha_config *cfg, Plan **out) {
         P->n_pt += (n / tp) * (n / tp);
     }
     for (int l = 0; l < P->nl; ++l) {
-        const int n = P->lay[l].n, off = int(P->dlay[l].c_off);
-        const int tw = n < kWtTile ? n : kWtTile;
-        const int nq = (n >> P->kf) / P->tq;
-        SegTab *S[2] = {&P->seg_wt, &P->seg_fwd};
-        const int per_row[2] = {n / tw, nq};
-        int *cnt[2] = {&P->n_wt, &P->n_fwd};
-        for (int k = 0; k < 2; ++k) {
-            S[k]->start[l] = *cnt[k];
-            S[k]->off[l] = off;
-            S[k]->aux[l] = P->dlay[l].r_off;
-            S[k]->n[l] = n;
-            S[k]->lt[l] = lg2(per_row[k]);
-            S[k]->id[l] = l;
-            *cnt[k] += per_row[k] * per_row[k];
-        }
+        const int n = P->lay[l].n, tw = n < kWtTile ? n : kWtTile;
+        SegTab &S = P->seg_wt;
+        S.start[l] = P->n_wt;
+        S.off[l] = int(P->dlay[l].c_off);
+        S.aux[l] = P->dlay[l].r_off;
+        S.n[l] = n;
+        S.lt[l] = lg2(n / tw);
+        S.id[l] = l;
+        P->n_wt += (n / tw) * (n / tw);
         // every inverse-DWT cone of this layer must fit the kernel's load slots and LDS
         for (int y0 = 0; y0 < n; y0 += tw)
             for (int x0 = 0; x0 < n; x0 += tw) {
@@ -357,7 +378,18 @@ int plan_create(const fewha_config *cfg, Plan **out) {
     }
     P->seg_wt.start[P->nl] = P->n_wt;
     P->seg_pt.start[P->nl] = P->n_pt;
-    P->seg_fwd.start[P->nl] = P->n_fwd;
+    {
+        // forward DWT split: two levels on tiles of (at most) 8 x 8 level-2 quads
+        int min_n = 1 << 30;
+        for (auto &L : P->lay) min_n = L.n < min_n ? L.n : min_n;
+        const int kf = P->J < 2 ? P->J : 2;
+        int tq = kFwdQuads;
+        while (tq > (min_n >> kf)) tq >>= 1;
+        if (set_fwd_split(P, kf, tq) != FEWHA_OK) {
+            delete P;
+            return FEWHA_ERR_UNSUPPORTED;
+        }
+    }
     P->seg_proj.nseg = P->nw;
     for (int g = 0; g < P->nw; ++g) {
         const int nv = P->wfs[g].n_sub + 1, tpr = (nv + kProjTile - 1) / kProjTile;
@@ -379,7 +411,7 @@ int plan_create(const fewha_config *cfg, Plan **out) {
         P->dmtab.off[m] = int(P->ddm[m].a_off);
         P->dmtab.n[m] = P->ddm[m].n_act;
     }
-    if (residual_partials(*P) > kPartialPitch || P->n_proj * kProjWaves > kPartialPitch) {
+    if (P->n_proj * kProjWaves > kPartialPitch) {
         delete P;
         return FEWHA_ERR_UNSUPPORTED;
     }

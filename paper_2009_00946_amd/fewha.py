@@ -23,7 +23,8 @@ EXPORTS = ["fewha_plan_create", "fewha_workspace_bytes", "fewha_plan_bind", "few
            "fewha_prior_dot", "fewha_plan_set_batch", "fewha_apply_A_batch", "fewha_apply_At_batch",
            "fewha_apply_M_batch", "fewha_pcg_solve_batch", "fewha_fit_dm_batch", "fewha_last_status_batch",
            "fewha_pol_slopes", "fewha_fit_dm_closed", "fewha_pol_slopes_batch", "fewha_fit_dm_closed_batch",
-           "fewha_fit_dm_ls", "fewha_cn2_gradient", "fewha_dwt_forward_noalloc", "fewha_stage_launch_batch"]
+           "fewha_fit_dm_ls", "fewha_cn2_gradient", "fewha_dwt_forward_noalloc", "fewha_stage_launch_batch",
+           "fewha_get_tuning", "fewha_set_tuning", "fewha_autotune"]
 
 
 class FewhaError(RuntimeError):
@@ -44,6 +45,14 @@ class _Layer(ctypes.Structure):
 
 class _Dm(ctypes.Structure):
     _fields_ = [("height", ctypes.c_double), ("pitch", ctypes.c_double), ("n_act", ctypes.c_int)]
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("kf", ctypes.c_int), ("tq", ctypes.c_int), ("chunk_wt", ctypes.c_int), ("chunk_proj", ctypes.c_int),
+                ("chunk_pt", ctypes.c_int), ("chunk_fwd", ctypes.c_int)]
+
+
+TUNING_FIELDS = [f for f, _ in _Tuning._fields_]
 
 
 class _Config(ctypes.Structure):
@@ -98,6 +107,9 @@ def load_library():
     L.fewha_last_status.argtypes = [vp]
     L.fewha_stage_launch.argtypes = [vp, ctypes.c_int, vp]
     L.fewha_stage_launch_batch.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp]
+    L.fewha_get_tuning.argtypes = [vp, ctypes.POINTER(_Tuning)]
+    L.fewha_set_tuning.argtypes = [vp, ctypes.POINTER(_Tuning)]
+    L.fewha_autotune.argtypes = [vp, ctypes.c_int, ctypes.POINTER(_Tuning), ctypes.POINTER(ctypes.c_double)]
     L.fewha_strerror.argtypes = [ctypes.c_int]
     L.fewha_strerror.restype = ctypes.c_char_p
     _lib = L
@@ -425,6 +437,25 @@ class Plan:
         """Enqueue one launch of one PCG-pass stage over frames 0..nbatch-1 of a batched plan."""
         _check(_lib.fewha_stage_launch_batch(self._h, int(nbatch), self.STAGES[stage], self._stream()),
                "fewha_stage_launch_batch")
+
+    # -- launch shapes ----------------------------------------------------------------------------
+    def get_tuning(self):
+        t = _Tuning()
+        _check(_lib.fewha_get_tuning(self._h, ctypes.byref(t)), "fewha_get_tuning")
+        return {f: getattr(t, f) for f in TUNING_FIELDS}
+
+    def set_tuning(self, tuning):
+        t = _Tuning(*[int(tuning[f]) for f in TUNING_FIELDS])
+        _check(_lib.fewha_set_tuning(self._h, ctypes.byref(t)), "fewha_set_tuning")
+
+    def autotune(self, nbatch=None):
+        """Time the stage kernels for every launch shape and keep the fastest (resets the chain
+        state); returns (tuning, tuned microseconds per stage launch)."""
+        nb = self.max_batch if nbatch is None else int(nbatch)
+        t = _Tuning()
+        us = (ctypes.c_double * 4)()
+        _check(_lib.fewha_autotune(self._h, nb, ctypes.byref(t), us), "fewha_autotune")
+        return {f: getattr(t, f) for f in TUNING_FIELDS}, dict(zip(("wt", "proj", "pt", "fwd"), list(us)))
 
     def last_status(self):
         return _lib.fewha_last_status(self._h)

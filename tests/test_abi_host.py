@@ -162,3 +162,44 @@ def test_noalloc_forward_argument_checks(cfg_c0):
     h, st = fewha.create_host_plan(big, precision="fp32")   # half the bytes: accepted (not called)
     assert st == 0
     L.fewha_plan_destroy(h)
+
+
+def test_tuning_defaults_and_validation(cfg_c0):
+    """Launch shapes: the documented defaults, a valid change read back, and invalid or
+    unsupported ones refused with the plan unchanged (host only)."""
+    L = fewha.load_library()
+    cfg = synth.load_config("c1_elt_mcao")
+    h, st = fewha.create_host_plan(cfg)
+    assert st == 0
+    t = fewha._Tuning()
+    assert L.fewha_get_tuning(h, ctypes.byref(t)) == 0
+    assert (t.kf, t.tq, t.chunk_wt, t.chunk_proj, t.chunk_pt, t.chunk_fwd) == (2, 8, 0, 0, 16, 0)
+    t2 = fewha._Tuning(1, 4, 8, 4, 0, 16)
+    assert L.fewha_set_tuning(h, ctypes.byref(t2)) == 0
+    back = fewha._Tuning()
+    L.fewha_get_tuning(h, ctypes.byref(back))
+    assert [getattr(back, f) for f in fewha.TUNING_FIELDS] == [1, 4, 8, 4, 0, 16]
+    for bad in ((3, 4, 0, 0, 0, 0), (2, 3, 0, 0, 0, 0), (2, 16, 0, 0, 0, 0), (2, 8, -1, 0, 0, 0), (2, 8, 0, 0, 300, 0)):
+        assert L.fewha_set_tuning(h, ctypes.byref(fewha._Tuning(*bad))) == -1, bad
+    # one-level split with 1 x 1 tiles: more fine tiles' partial sums than the buffer holds
+    assert L.fewha_set_tuning(h, ctypes.byref(fewha._Tuning(1, 1, 0, 0, 0, 0))) == -3
+    L.fewha_get_tuning(h, ctypes.byref(back))
+    assert [getattr(back, f) for f in fewha.TUNING_FIELDS] == [1, 4, 8, 4, 0, 16]
+    assert L.fewha_autotune(h, 1, ctypes.byref(t), None) == -5   # unbound
+    L.fewha_plan_destroy(h)
+    # the tiny geometry: tiles of at most its 32 >> kf quads
+    h, st = fewha.create_host_plan(cfg_c0)
+    assert L.fewha_set_tuning(h, ctypes.byref(fewha._Tuning(2, 8, 0, 0, 0, 0))) == 0
+    assert L.fewha_set_tuning(h, ctypes.byref(fewha._Tuning(1, 8, 0, 0, 0, 0))) == 0
+    L.fewha_plan_destroy(h)
+
+
+def test_tuning_cache_key():
+    from paper_2009_00946_amd import tune
+    cfg = synth.load_config("c1_elt_mcao")
+    k = tune.geometry_key(cfg, "fp32", 1, "dev")
+    assert k == tune.geometry_key(dict(cfg, name="other", alpha_reg=2.0), "fp32", 1, "dev")  # not timing inputs
+    assert k != tune.geometry_key(cfg, "fp64", 1, "dev") and k != tune.geometry_key(cfg, "fp32", 32, "dev")
+    lay = [dict(l) for l in cfg["layers"]]
+    lay[0]["n"] = 512
+    assert k != tune.geometry_key(dict(cfg, layers=lay), "fp32", 1, "dev")
