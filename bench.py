@@ -86,12 +86,17 @@ PAPER_MS = {"maory_paper": {"cpu_ms": 3.0, "cpu": "2x Intel Xeon E5-2630v3 (8-co
 
 STAGES = ("wt", "proj", "pt", "fwd")
 STAGE_KERNELS = {"wt": "k_wt<pcg>", "proj": "k_proj<M>", "pt": "k_pt", "fwd": "k_fwd<pcg> + k_coarse<pcg>"}
+STAGE_KERNELS_FOLD = dict(STAGE_KERNELS, wt="k_wt<fold> (coarse update folded in)", fwd="k_fwd<pcg> (fine levels)")
 SINGLE_KERNEL = ("wt", "proj", "pt")
 
 
-def stage_elements(model):
+def stage_elements(model, fold=False):
+    """Algorithmic elements per stage launch.  With the fold the coarse levels' share of the forward
+    transform and update (their coefficients are 1/16 of the layer's with two fine levels) moves
+    from the forward-DWT stage into the inverse-DWT stage; the pass total is unchanged."""
     n_c, sv, su = model["n_coef"], model["sum_V"], model["sum_U"]
-    return {"wt": 2 * n_c, "proj": su + 3 * sv, "pt": sv + n_c, "fwd": 15 * n_c}
+    coarse = 15 * n_c / 16 if fold else 0
+    return {"wt": 2 * n_c + coarse, "proj": su + 3 * sv, "pt": sv + n_c, "fwd": 15 * n_c - coarse}
 
 
 def time_stages(P, stream, reps, replays=4):
@@ -349,16 +354,17 @@ def time_stages_batch(P, nb, stream, reps=20, replays=4):
     return out
 
 
-def roofline_of(cfg, us, frames, n_iter, elem=4):
+def roofline_of(cfg, us, frames, n_iter, elem=4, fold=False):
     """Roofline object of the dominant single kernel of a PCG pass (launches per frame x duration)
     of a launch over `frames` frames of one geometry."""
-    sel = stage_elements(byte_model(cfg, elem, n_iter))
+    sel = stage_elements(byte_model(cfg, elem, n_iter), fold)
     per_frame = {"wt": n_iter, "proj": n_iter, "pt": n_iter + 1, "fwd": n_iter}
-    dom = max(SINGLE_KERNEL, key=lambda st: per_frame[st] * us[st])
-    nbytes = sel[dom] * elem * frames
+    dom = max(SINGLE_KERNEL + (("fwd",) if fold else ()), key=lambda st: per_frame[st] * us[st])
+    nbytes = int(sel[dom] * elem * frames)
     ach = nbytes / (us[dom] * 1e-6) / 1e9
+    names = STAGE_KERNELS_FOLD if fold else STAGE_KERNELS
     return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": None, "kernel": STAGE_KERNELS[dom],
+            "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": None, "kernel": names[dom],
             "us_per_launch": round(us[dom], 3), "bytes_per_launch": nbytes, "frames_per_launch": frames}
 
 
@@ -394,7 +400,7 @@ def batched_same_geometry(cfg, nb, steps, warmup, refresh=8, tuned=True):
            "ms_per_launch_set": round(ms, 4), "us_per_frame": round(1e3 * ms / nb, 2),
            "frames_per_s": round(1e3 * nb / ms, 1), "effective_GBps": round(gbps, 1),
            "frac_hbm_peak": round(gbps / HBM_PEAK_GBPS, 4), "residual_refresh_every": refresh or None,
-           "roofline": roofline_of(cfg, us, nb, n_iter, elem),
+           "roofline": roofline_of(cfg, us, nb, n_iter, elem, PB.get_tuning()["fold"] == 1),
            "stages_us_per_launch": {k: round(v, 3) for k, v in us.items()},
            "launch_shapes": shapes and shapes["tuning"]}
     del PB, sb, cb, ab, g_warm, g_fresh, seq
@@ -468,8 +474,11 @@ class UnevenMix:
         best = None
         for g in self.groups:
             us = time_stages_batch(g["PB"], g["count"], torch.cuda.current_stream())
-            r = roofline_of(g["cfg"], us, g["count"], self.n_iter)
-            per_frame = {"k_wt<pcg>": self.n_iter, "k_proj<M>": self.n_iter, "k_pt": self.n_iter + 1}
+            fold = g["PB"].get_tuning()["fold"] == 1
+            r = roofline_of(g["cfg"], us, g["count"], self.n_iter, 4, fold)
+            names = STAGE_KERNELS_FOLD if fold else STAGE_KERNELS
+            per_frame = {names["wt"]: self.n_iter, names["proj"]: self.n_iter, names["pt"]: self.n_iter + 1,
+                         names["fwd"]: self.n_iter}
             cost = per_frame[r["kernel"]] * r["us_per_launch"]
             if best is None or cost > best[0]:
                 best = (cost, dict(r, geometry=g["cfg"]["name"]))
@@ -665,12 +674,14 @@ def main():
 
     # the dominant single kernel of a PCG pass, timed live (launches per frame x duration)
     us = time_stages(P, stream, args.stage_reps)
-    sel = stage_elements(model)
+    fold = P.get_tuning()["fold"] == 1
+    names = STAGE_KERNELS_FOLD if fold else STAGE_KERNELS
+    sel = stage_elements(model, fold)
     per_frame = {"wt": n_iter, "proj": n_iter, "pt": n_iter + 1, "fwd": n_iter}
-    stages = {st: {"kernel": STAGE_KERNELS[st], "us_per_launch": round(us[st], 3),
-                   "bytes_per_launch": sel[st] * elem, "launches_per_frame": per_frame[st],
+    stages = {st: {"kernel": names[st], "us_per_launch": round(us[st], 3),
+                   "bytes_per_launch": int(sel[st] * elem), "launches_per_frame": per_frame[st],
                    "GBps": round(sel[st] * elem / (us[st] * 1e-6) / 1e9, 1)} for st in STAGES}
-    dom = max(SINGLE_KERNEL, key=lambda st: per_frame[st] * us[st])
+    dom = max(SINGLE_KERNEL + (("fwd",) if fold else ()), key=lambda st: per_frame[st] * us[st])
     achieved = sel[dom] * elem / (us[dom] * 1e-6) / 1e9
     traffic = recorded_traffic(dom, cfg["name"])
     h2d = h2d_upload(stream, S[0])
@@ -713,8 +724,8 @@ def main():
         "ms_per_frame_with_h2d": round(ms_mean + h2d["us_per_frame"] * 1e-3, 5),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                     "kernel": STAGE_KERNELS[dom], "us_per_launch": round(us[dom], 3),
-                     "bytes_per_launch": sel[dom] * elem},
+                     "kernel": names[dom], "us_per_launch": round(us[dom], 3),
+                     "bytes_per_launch": int(sel[dom] * elem)},
         "stages": stages,
     }
     if cfg["name"] in PAPER_MS:

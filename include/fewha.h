@@ -320,10 +320,16 @@ typedef struct {
     int chunk_proj;
     int chunk_pt;
     int chunk_fwd;
+    int fold;       /* 1: the coarse forward-DWT levels (kf+1..J) of the right-hand side and of
+                       every PCG pass but the last run inside the next pass's inverse DWT (every
+                       tile recomputes them from the level-kf approximation and updates its own
+                       share), saving one launch per pass; FP32 plans with kf = 2, J > 2 and
+                       layers up to 256 x 256 */
 } fewha_tuning;
 
 /* The plan's current launch shapes (defaults after fewha_plan_create: kf = min(2, J), tq the
- * largest of 8, 4, 2, 1 that fits the smallest layer, chunk_pt 16, other chunks 0). */
+ * largest of 8, 4, 2, 1 that fits the smallest layer, chunk_pt 16, other chunks 0, fold where it
+ * applies). */
 int fewha_get_tuning(const fewha_plan *p, fewha_tuning *h_tuning);
 
 /* Set the launch shapes (host only; the plan stays bound, its workspace layout is unchanged).
@@ -333,8 +339,9 @@ int fewha_get_tuning(const fewha_plan *p, fewha_tuning *h_tuning);
 int fewha_set_tuning(fewha_plan *p, const fewha_tuning *h_tuning);
 
 /* Autotuner: times the PCG-pass stage kernels (fewha_stage_launch over nbatch frames, each
- * timing a HIP graph of back-to-back launches on a private stream) for every valid (kf, tq) and
- * then every chunk in {0, 4, 8, 16, 32} of each tile kernel, and keeps the fastest of each; the
+ * timing a HIP graph of back-to-back launches on a private stream) for every valid (kf, tq), then
+ * the fold against none (on the inverse and forward DWT stages together), then every chunk in
+ * {0, 4, 8, 16, 32} of each tile kernel, and keeps the fastest of each; the
  * result is set on the plan and returned in *h_best.  h_us (nullable, 4 values) receives the
  * tuned per-launch microseconds of the stages wt, proj, pt, fwd.  Synchronous; needs a bound
  * plan; resets the warm-restart state and the PCG scalars (as fewha_plan_bind leaves them), so it

@@ -45,6 +45,11 @@ Bufs<T> bufs(const Plan &P) {
     b.x = reinterpret_cast<T *>(w + P.o_x);
     b.v = reinterpret_cast<T *>(w + P.o_v);
     b.ll = reinterpret_cast<T *>(w + P.o_ll);
+    for (int i = 0; i < 2; ++i) {
+        b.rsh[i] = reinterpret_cast<T *>(w + P.o_rsh[i]);
+        b.qsh[i] = reinterpret_cast<T *>(w + P.o_qsh[i]);
+    }
+    b.bsh = reinterpret_cast<T *>(w + P.o_bsh);
     b.probe_c = reinterpret_cast<T *>(w + P.o_probe_c);
     b.probe_s = reinterpret_cast<T *>(w + P.o_probe_s);
     b.over = reinterpret_cast<int *>(w + P.o_over);
@@ -122,20 +127,58 @@ int apply_M(const Plan &P, const void *c, void *y, void *stream, int nb = 1) {
     return o.fwd(o.B.x, E, kEpiPrior);
 }
 
-// n_iter passes of Alg. 2 from the residual and scalar state a right-hand-side epilogue left.
+// The right-hand side's forward transform (Eq. (fewha)'s b = W x) with the residual update of
+// Alg. 1.  With the fold (and at least one pass to fold it into) only the fine levels run here;
+// the coarse ones run in the first pass's inverse DWT.
 template <typename T>
-int pcg_passes(const Plan &P, const Ops<T> &o, void *c, int n_iter, double *resnorm) {
-    // partial sums of (r, z) and (z, alpha D z) come from the forward transforms that write r
+int rhs_transform(const Plan &P, const Ops<T> &o, void *c, int cold, int n_iter) {
+    FwdArgs R{};
+    R.c = c;
+    R.cold = cold;
+    return o.fwd(o.B.x, R, kEpiRhs, !(P.fold && n_iter > 0));
+}
+
+// n_iter passes of Alg. 2 from the residual and scalar state a right-hand-side epilogue left.
+//
+// With the fold, the coarse levels of every forward transform but the last run in the next
+// pass's inverse DWT (pass k applies epilogue e = k - 1, the right-hand side's for k = 0).  While
+// the passes run, the coarse coefficients of r and q live in shadows by epilogue parity (epilogue
+// e writes r, q to shadow (e + 1) & 1 and reads shadow e & 1), because every tile of a layer reads
+// them at its cone while their owners write the new values; b's coarse coefficients wait in their
+// own shadow.  The last forward transform reads the shadows and leaves r, q, p, c and b_prev whole.
+template <typename T>
+int pcg_passes(const Plan &P, const Ops<T> &o, void *c, int n_iter, double *resnorm, int cold = 0) {
+    // partial sums of (r, z) and (z, alpha D z) come from the transforms that write r
     const int nres = residual_partials(P);
+    const bool fold = P.fold && n_iter > 0;
     for (int k = 0; k < n_iter; ++k) {
-        TRY(o.wt_pcg(o.B.r, o.B.u));             // u = W^T J^-1 r
+        if (fold) {
+            FoldArgs F{};                        // the previous epilogue's coarse levels, then u
+            F.e = k - 1;
+            F.cold = cold;
+            F.c = c;
+            F.rin = k == 0 ? o.B.r : o.B.rsh[(k - 1) & 1];
+            F.qin = k >= 2 ? o.B.qsh[(k - 1) & 1] : nullptr;
+            F.rout = o.B.rsh[k & 1];
+            F.qout = o.B.qsh[k & 1];
+            F.bsh = o.B.bsh;
+            TRY(o.wt_fold(o.B.r, o.B.u, F));
+        } else {
+            TRY(o.wt_pcg(o.B.r, o.B.u));         // u = W^T J^-1 r
+        }
         TRY(o.proj(o.B.u, o.B.v, kProjM));       // v = Gamma^T C Gamma P u; (C Gamma P u, Gamma P u) partials
         TRY(o.pt(o.B.v, o.B.x, PassArgs{k, nres, P.n_proj * kProjWaves, 1, resnorm, n_iter}));  // x = P^T v; Alg. 2 scalars
         FwdArgs E{};                             // y = W x + alpha D z; the pass update
         E.c = c;
         E.k = k;
         E.publish = 1;
-        TRY(o.fwd(o.B.x, E, kEpiPcg));
+        const bool last = k == n_iter - 1;
+        if (fold && last) {                      // coarse levels from the shadows of epilogue k - 1
+            E.r_in = o.B.rsh[k & 1];
+            E.q_in = k >= 1 ? o.B.qsh[k & 1] : nullptr;
+            E.b_in = o.B.bsh;
+        }
+        TRY(o.fwd(o.B.x, E, kEpiPcg, !fold || last));
     }
     const_cast<Plan &>(P).last_slot = n_iter > 0 ? ((n_iter - 1) & 1) : 1;
     return FEWHA_OK;
@@ -160,11 +203,9 @@ int pcg_solve(const Plan &P, const void *s, void *c, int n_iter, int flags, doub
     // right-hand side b = W P^T Gamma^T C s, then the warm-restart residual update
     TRY(o.gt(static_cast<const T *>(s), o.B.v, kGtRhs));
     TRY(o.pt(o.B.v, o.B.x, PassArgs{-1, 0, 0, 0, nullptr, 0}));
-    FwdArgs R{};
-    R.c = c;
-    R.cold = flags == FEWHA_COLD ? 1 : 0;
-    TRY(o.fwd(o.B.x, R, kEpiRhs));
-    return pcg_passes<T>(P, o, c, n_iter, resnorm);
+    const int cold = flags == FEWHA_COLD ? 1 : 0;
+    TRY(rhs_transform<T>(P, o, c, cold, n_iter));
+    return pcg_passes<T>(P, o, c, n_iter, resnorm, cold);
 }
 
 // M c = b for a right-hand side given in the coefficient domain, from c = 0: x = W^T b first,
@@ -174,11 +215,8 @@ template <typename T>
 int solve_M(const Plan &P, const void *b, void *c, int n_iter, double *resnorm, void *stream) {
     auto o = ops<T>(P, stream);
     TRY(o.wt(static_cast<const T *>(b), o.B.x));
-    FwdArgs R{};
-    R.c = c;
-    R.cold = 1;
-    TRY(o.fwd(o.B.x, R, kEpiRhs));
-    return pcg_passes<T>(P, o, c, n_iter, resnorm);
+    TRY(rhs_transform<T>(P, o, c, 1, n_iter));
+    return pcg_passes<T>(P, o, c, n_iter, resnorm, 1);
 }
 
 template <typename T>
@@ -220,24 +258,40 @@ int fit_closed(const Plan &P, const void *c, const void *a0, const void *a_m1, d
 template <typename T>
 int stage_launch(const Plan &P, int stage, void *stream, int nb = 1) {
     auto o = ops<T>(P, stream, nb);
+    const size_t NS = P.n_coef * size_t(P.max_batch);  // stage scratch: blocks of max_batch frames
+    T *scr = reinterpret_cast<T *>(P.ws + P.o_stage);
     switch (stage) {
-        case FEWHA_STAGE_WT: return o.wt_pcg(o.B.r, o.B.u);
+        case FEWHA_STAGE_WT:
+            if (P.fold) {
+                // a folded update of pass 1 (the shadows are scratch between solves; p and c are
+                // the stage scratch copies), then u = W^T J^-1 r
+                FoldArgs F{};
+                F.e = 1;
+                F.c = scr + 3 * NS;
+                F.rin = o.B.rsh[1];
+                F.qin = o.B.qsh[1];
+                F.rout = o.B.rsh[0];
+                F.qout = o.B.qsh[0];
+                auto os = o;
+                os.B.p = scr + NS;
+                return os.wt_fold(o.B.r, o.B.u, F);
+            }
+            return o.wt_pcg(o.B.r, o.B.u);
         case FEWHA_STAGE_PROJ: return o.proj(o.B.u, o.B.v, kProjM);
         case FEWHA_STAGE_PT:
             return o.pt(o.B.v, o.B.x, PassArgs{1, residual_partials(P), P.n_proj * kProjWaves, 0, nullptr, 0});
         default: {
             // the frame's y = W x + alpha D z with the pass update, applied to scratch copies of
-            // r, p, q and c (blocks of max_batch frames each), without publishing scalars
-            const size_t N = P.n_coef * size_t(P.max_batch);
-            T *scr = reinterpret_cast<T *>(P.ws + P.o_stage);
+            // r, p, q and c (blocks of max_batch frames each), without publishing scalars; with the
+            // fold, the fine levels only (as in every pass but the last)
             o.B.r = scr;
-            o.B.p = scr + N;
-            o.B.q = scr + 2 * N;
+            o.B.p = scr + NS;
+            o.B.q = scr + 2 * NS;
             FwdArgs E{};
-            E.c = scr + 3 * N;
+            E.c = scr + 3 * NS;
             E.k = 1;
             E.publish = 0;
-            return o.fwd(o.B.x, E, kEpiPcg);
+            return o.fwd(o.B.x, E, kEpiPcg, !P.fold);
         }
     }
 }
@@ -635,7 +689,7 @@ int fewha_stage_launch(const fewha_plan *p, int stage, void *stream) {
 int fewha_get_tuning(const fewha_plan *p, fewha_tuning *t) {
     if (!p || !t) return FEWHA_ERR_INVALID_ARG;
     const Plan &P = p->p;
-    *t = fewha_tuning{P.kf, P.tq, P.seg_wt.chunk, P.seg_proj.chunk, P.seg_pt.chunk, P.seg_fwd.chunk};
+    *t = fewha_tuning{P.kf, P.tq, P.seg_wt.chunk, P.seg_proj.chunk, P.seg_pt.chunk, P.seg_fwd.chunk, P.fold ? 1 : 0};
     return FEWHA_OK;
 }
 
@@ -644,10 +698,13 @@ int fewha_set_tuning(fewha_plan *p, const fewha_tuning *t) {
     const int ch[4] = {t->chunk_wt, t->chunk_proj, t->chunk_pt, t->chunk_fwd};
     for (int c : ch)
         if (c < 0 || c > 256) return FEWHA_ERR_INVALID_ARG;
+    if (t->fold != 0 && t->fold != 1) return FEWHA_ERR_INVALID_ARG;
     Plan &P = p->p;
     Plan keep = P;
     P.seg_fwd.chunk = t->chunk_fwd;
-    const int st = set_fwd_split(&P, t->kf, t->tq);
+    P.fold = t->fold == 1;
+    int st = set_fwd_split(&P, t->kf, t->tq);
+    if (st == FEWHA_OK && P.fold && !fold_possible(P)) st = FEWHA_ERR_UNSUPPORTED;
     if (st != FEWHA_OK) {
         P = keep;
         return st;
@@ -705,8 +762,10 @@ int autotune_on(fewha_plan *h, int nb, hipStream_t st, hipEvent_t e0, hipEvent_t
     for (int s = FEWHA_STAGE_WT; s <= FEWHA_STAGE_FWD; ++s) TRY(stage_launch<T>(P, s, st, nb));
     fewha_tuning t{};
     TRY(fewha_get_tuning(h, &t));
-    // 1. the forward-DWT split (kf, tq), timed on the forward-DWT stage
+    // 1. the forward-DWT split (kf, tq), timed on the forward-DWT stage with all its levels
     double bt = 1e30;
+    const int fold_default = t.fold;
+    t.fold = 0;
     fewha_tuning bs = t;
     for (int kf = 1; kf <= 2; ++kf)
         for (int tq : {1, 2, 4, 8}) {
@@ -723,7 +782,23 @@ int autotune_on(fewha_plan *h, int nb, hipStream_t st, hipEvent_t e0, hipEvent_t
         }
     t = bs;
     TRY(fewha_set_tuning(h, &t));
-    // 2. each tile kernel's XCD chunk, on its own stage
+    // 2. the fold against none, on the inverse and forward DWT stages together (where it applies)
+    {
+        fewha_tuning c = t;
+        c.fold = 1;
+        if (fewha_set_tuning(h, &c) == FEWHA_OK) {
+            double w1 = 0, f1 = 0, w0 = 0, f0 = 0;
+            TRY(time_stage<T>(P, FEWHA_STAGE_WT, nb, st, e0, e1, &w1));
+            TRY(time_stage<T>(P, FEWHA_STAGE_FWD, nb, st, e0, e1, &f1));
+            TRY(fewha_set_tuning(h, &t));
+            TRY(time_stage<T>(P, FEWHA_STAGE_WT, nb, st, e0, e1, &w0));
+            TRY(time_stage<T>(P, FEWHA_STAGE_FWD, nb, st, e0, e1, &f0));
+            if (w1 + f1 < w0 + f0) t = c;
+            TRY(fewha_set_tuning(h, &t));
+        }
+    }
+    (void)fold_default;
+    // 3. each tile kernel's XCD chunk, on its own stage
     int *chunk[4] = {&t.chunk_wt, &t.chunk_proj, &t.chunk_pt, &t.chunk_fwd};
     for (int s = FEWHA_STAGE_WT; s <= FEWHA_STAGE_FWD; ++s) {
         double bu = 1e30;

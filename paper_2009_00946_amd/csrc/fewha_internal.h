@@ -157,6 +157,7 @@ struct Bufs {
     const T *jinv;                    // [nl][J+1][4] inverse preconditioner per band
     const T *ad;                      // [nl][J+1] alpha D per level
     T *b_prev, *r, *p, *q, *u, *x, *v, *ll, *probe_c, *probe_s;
+    T *rsh[2], *qsh[2], *bsh;         // folded coarse updates: r, q by epilogue parity, b (N_c each)
     int *over;                        // per-sensor flags: a transpose row exceeded kRtabWidth (setup)
     double *partials;                 // [3][kPartialPitch]: (r, z) and (z, alpha D z) per wave of the
                                       // forward-DWT workgroups, sum C (Gamma P u)^2 per projection tile
@@ -189,6 +190,7 @@ struct Plan {
     int maxnv = 0, sum_n = 0;
     int kf = 1;           // forward-DWT levels done on tiles; the rest per layer in one workgroup
     int tq = 8;           // level-kf quads per tile edge of the fine forward DWT
+    bool fold = false;    // coarse forward levels of all but the last pass folded into the next W^T
     bool rtab_ok = true;  // the staged transpose gather applies (else the scanning P^T)
     int last_slot = 1;    // scalar slot holding the state after the last enqueued solve
     int max_batch = 1;    // frames the workspace holds state for (same geometry, one launch per stage)
@@ -204,6 +206,7 @@ struct Plan {
     size_t o_fy = 0, o_fx = 0, o_fr = 0, o_fp = 0, o_fq = 0, o_frr = 0;  // least-squares DM fitting
     size_t o_fmask = 0;   // least-squares fitting: 1 for the first sensor's nodes inside the pupil
     size_t o_jinv = 0, o_ad = 0, o_bprev = 0, o_r = 0, o_p = 0, o_q = 0, o_u = 0, o_x = 0, o_v = 0;
+    size_t o_rsh[2] = {0, 0}, o_qsh[2] = {0, 0}, o_bsh = 0;
     size_t o_ll = 0, o_stage = 0, o_probe_c = 0, o_probe_s = 0, o_partials = 0, o_scalars = 0, o_over = 0;
     size_t ws_bytes = 0;
 
@@ -223,14 +226,21 @@ constexpr int kProjWaves = 4;
 
 // Waves of a coarse forward-DWT workgroup: each leaves its own pair of residual partials.
 constexpr int kCoarseWaves = 16;
+// Coarse coefficients an inverse-DWT tile owns in a folded update, and the partial pairs it
+// leaves for them.
+constexpr int kFoldOwn = 64;
+constexpr int kFoldParts = 8;
 
 // Residual partial pairs a pass leaves for the next scalar step: one per wave of every fine
 // forward-DWT tile and of every layer's coarse workgroup.
 // Waves of a fine forward-DWT workgroup for the plan's (kf, tq) (each leaves its own pair).
 int fwd_waves(int kf, int tq);
+// With the fold, the coarse part comes from the inverse-DWT tiles instead: one pair per tile.
 inline int residual_partials(const Plan &P) {
-    return P.n_fwd * fwd_waves(P.kf, P.tq) + (P.kf < P.J ? P.nl * kCoarseWaves : 0);
+    return P.n_fwd * fwd_waves(P.kf, P.tq) + (P.kf < P.J ? (P.fold ? P.n_wt * kFoldParts : P.nl * kCoarseWaves) : 0);
 }
+// The fold applies (FP32; two fine levels; the level-2 block of every layer within 64 x 64).
+bool fold_possible(const Plan &P);
 
 // Values per frame of the level-kf approximation region (at most n_coef / 4 plus one), rounded up
 // to a multiple of 4 so that every frame's blocks start 16-byte aligned.

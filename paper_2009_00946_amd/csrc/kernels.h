@@ -15,6 +15,26 @@ struct FwdArgs {
     int cold;           // rhs: cold start
     int k;              // pcg: pass index (0 = first pass: beta = 0, p = z, q = y)
     int publish;        // pcg: workgroup 0 stores the pass's scalar state (0 for stage timing)
+    // pcg, coarse levels of a solve whose earlier coarse updates were folded into the inverse DWT:
+    // r and q before the update come from these shadows, and b_in (the right-hand side's coarse
+    // coefficients) is copied to b_prev (null: the plan's own r, q; no copy)
+    const void *r_in, *q_in, *b_in;
+};
+
+// The coarse levels (kf+1..J) of the forward transform that precedes an inverse DWT, folded into
+// that inverse DWT: every tile of a layer recomputes them from the level-kf approximation, applies
+// the update of epilogue e at the coefficients of its cone and at its own share of the layer's
+// coarse block, and leaves the partial sums of its share.
+struct FoldArgs {
+    int e;              // -1: the right-hand side's (r = (b - b_prev) + r_prev); k >= 0: pass k's update
+    int cold;           // e = -1: cold start (r = b, c = 0)
+    int kf;             // levels done on the fine tiles
+    int nfine;          // partial slots of the fine tiles (the fold's slots follow, one per tile)
+    void *c;            // caller's iterate (updated at the owned coefficients)
+    const void *rin;    // r before the update: the plan's r for e = -1, else the shadow of e - 1
+    const void *qin;    // q before the update (e >= 1)
+    void *rout, *qout;  // r, q after the update (shadows of e)
+    void *bsh;          // e = -1: b at the coarse coefficients (copied to b_prev at the solve's end)
 };
 
 // The PCG pass whose scalar step an x = P^T v launch also performs (k < 0: none).
@@ -61,10 +81,11 @@ struct Ops {
     int prepare() const;                                  // per-device kernel attributes (bind)
     int wt(const T *c, T *out) const;                     // out = W^T c
     int wt_pcg(const T *r, T *out) const;                 // out = W^T J^-1 r
+    int wt_fold(const T *r, T *out, const FoldArgs &F) const;  // the fold's update, then out = W^T J^-1 r'
     int proj(const T *u, T *out, int mode) const;         // kProjM: v = Gamma^T C Gamma P u; kProjA/CA: s = (C) mask Gamma P u
     int gt(const T *s, T *v, int mode) const;             // v = Gamma^T C s | Gamma^T mask s
     int pt(const T *v, T *x, const PassArgs &PA) const;   // x = P^T v (+ the scalar step of pass PA.k)
-    int fwd(const T *x, const FwdArgs &E, int epi) const; // W x with an epilogue (all levels)
+    int fwd(const T *x, const FwdArgs &E, int epi, bool coarse = true) const; // W x with an epilogue (coarse: levels past kf too)
     int wnorm(const T *s) const;                          // sc[2].rho = sum C s^2
     int fit(const T *u, const T *a_prev, T *a, double gain, const T *a_m1 = nullptr) const;  // a_m1: closed loop
     int pol(const T *a_m1, const T *s, T *s_pol) const;   // s_pol = mask (s + Gamma P_DM a_m1)

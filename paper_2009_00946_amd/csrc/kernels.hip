@@ -124,6 +124,9 @@ __device__ __forceinline__ FwdArgs frame_args(FwdArgs E, long fs_c) {
     if (E.out) E.out = static_cast<T *>(E.out) + c;
     if (E.cin) E.cin = static_cast<const T *>(E.cin) + c;
     if (E.c) E.c = static_cast<T *>(E.c) + c;
+    if (E.r_in) E.r_in = static_cast<const T *>(E.r_in) + c;
+    if (E.q_in) E.q_in = static_cast<const T *>(E.q_in) + c;
+    if (E.b_in) E.b_in = static_cast<const T *>(E.b_in) + c;
     return E;
 }
 
@@ -320,20 +323,75 @@ __device__ __forceinline__ void lds_fence() {
     __syncthreads();
 }
 
-enum { kWtPlain = 0, kWtPcg = 1 };
+// kWtFold: kWtPcg after the folded coarse update (see FoldArgs).
+enum { kWtPlain = 0, kWtPcg = 1, kWtFold = 2 };
+
+// Coarse block of a layer that the fold handles: levels 3..J of layers up to 256 x 256 (level-2
+// block at most 64 x 64); a tile owns at most kFoldOwn of its coefficients.
+constexpr int kFoldM0 = 64;
+
+// The updates of Alg. 1 (residual line) and Alg. 2 (vector lines) at one coarse coefficient, with
+// every product and sum rounded on its own: each tile of a layer recomputes them at the
+// coefficients of its cone, and must reproduce bit for bit what the coefficient's owner stores.
+struct FoldNew {
+    float p, q, c, r;
+};
+
+__device__ __forceinline__ float fold_rhs(float w, float b_prev, float r_prev, int cold) {
+#pragma clang fp contract(off)
+    return cold ? w : (w - b_prev) + r_prev;
+}
+
+__device__ __forceinline__ FoldNew fold_pcg(float w, float r, float c, float p, float q, float ji, float ad, float al,
+                                            float be, bool first) {
+#pragma clang fp contract(off)
+    const float z = r * ji, az = ad * z, y = w + az;
+    FoldNew o;
+    if (first) {
+        o.p = z;
+        o.q = y;
+    } else {
+        const float bp = be * p, bq = be * q;
+        o.p = z + bp;
+        o.q = y + bq;
+    }
+    const float ap = al * o.p, aq = al * o.q;
+    o.c = c + ap;
+    o.r = r - aq;
+    return o;
+}
+
+// Level s >= 1 and orientation (0 LL, 1 x-high, 2 y-high, 3 HH) of Mallat position (row, col) of
+// an n = 2^log2n layer with J levels.
+__device__ __forceinline__ void band_of(int log2n, int J, int row, int col, int &s, int &o) {
+    const int mx = row > col ? row : col;
+    s = mx == 0 ? J : log2n - (31 - __clz(mx));
+    if (s > J) s = J;
+    const int m = 1 << (log2n - s);
+    o = (col >= m ? 1 : 0) + (row >= m ? 2 : 0);
+}
 
 template <typename T, int MODE>
 __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src, T *__restrict__ out, Bufs<T> B,
-                                           Taps<T> tp, int J) {
+                                           Taps<T> tp, int J, FoldArgs F) {
+    constexpr bool FOLD = MODE == kWtFold && sizeof(T) == 4, PC = MODE != kWtPlain;
     __shared__ __attribute__((aligned(16))) T sCone[kWtSlots * kWB];
     __shared__ T sLL[2][kWtLL];
     __shared__ T sXl[kWtX], sXh[kWtX];
     __shared__ T sJi[(kMaxJ + 1) * 4];
+    // fold: the level-2 approximation, the coarse coefficients of W x, the second operand (q or
+    // b_prev) at the cone's coarse positions, and alpha D per level
+    __shared__ __attribute__((aligned(16))) T sLLb[FOLD ? kFoldM0 * kFoldM0 : 1];
+    __shared__ T sWb[FOLD ? kFoldM0 * kFoldM0 : 1];
+    __shared__ T sCone2[FOLD ? (kMaxJ - 2) * kWB : 1];
+    __shared__ T sAd[FOLD ? kMaxJ + 1 : 1];
+    __shared__ double sRed[2][FOLD ? kFoldOwn : 1];
 
     src += blockIdx.y * B.fs_c;
     out += blockIdx.y * B.fs_c;
     const int tid = threadIdx.x;
-    const TileId id = find_tile(S, xcd_tile(S.chunk, gridDim.x));
+    const int tile = xcd_tile(S.chunk, gridDim.x);
+    const TileId id = find_tile(S, tile);
     const int l = id.id, n = id.n, lt = id.lt;
     const int T0 = n < kWtTile ? n : kWtTile;
     const int y0 = (id.loc >> lt) * T0, x0 = (id.loc & ((1 << lt) - 1)) * T0;
@@ -361,7 +419,49 @@ __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src,
     }
     // preconditioner of the layer's bands (PCG), loaded with the cone
     T jl = 1;
-    if (MODE == kWtPcg) jl = B.jinv[l * (J + 1) * 4 + min(tid, (J + 1) * 4 - 1)];
+    if (PC) jl = B.jinv[l * (J + 1) * 4 + min(tid, (J + 1) * 4 - 1)];
+
+    // fold: frame f's workspace and caller vectors; the tile's share of the layer's coarse block
+    // (an sub x sub block of the m0 x m0 level-2 block, one coefficient per lane of wave 0); its
+    // operands, the level-2 approximation and alpha D, all in the same round of loads as the cone
+    const int kf = FOLD ? F.kf : 0, m0 = n >> kf, sub = T0 >> kf, nown = sub * sub;
+    const bool own = FOLD && tid < nown;
+    long gown = 0;
+    T o_r = 0, o_q = 0, o_c = 0, o_p = 0, o_b = 0, adv = 0;
+    const T *rin = nullptr, *qin = nullptr;
+    StepOut fso{0.0, 0.0, 0};  // the step (alpha, beta, stopped) of the update the fold applies
+    if constexpr (FOLD) {
+        B = at_frame(B);
+        const long fc = blockIdx.y * B.fs_c;
+        rin = static_cast<const T *>(F.rin) + fc;
+        qin = F.e >= 1 ? static_cast<const T *>(F.qin) + fc : nullptr;
+        F.c = static_cast<T *>(F.c) + fc;
+        F.rout = static_cast<T *>(F.rout) + fc;
+        if (F.e >= 0) F.qout = static_cast<T *>(F.qout) + fc;
+        else F.bsh = static_cast<T *>(F.bsh) + fc;
+        const int ty = id.loc >> lt, tx = id.loc & ((1 << lt) - 1);
+        const int t = own ? tid : 0, orow = ty * sub + t / sub, ocol = tx * sub + t % sub;
+        gown = coff + (long)orow * n + ocol;
+        o_r = rin[gown];
+        if (F.e < 0) {
+            o_b = B.b_prev[gown];
+        } else {
+            o_c = static_cast<const T *>(F.c)[gown];
+            if (F.e >= 1) {
+                o_q = qin[gown];
+                o_p = B.p[gown];
+            }
+        }
+        adv = B.ad[l * (J + 1) + min(tid, J)];
+        if (F.e >= 0) fso = read_step(B.sc);
+        const float *llin = reinterpret_cast<const float *>(B.ll + (coff >> (2 * kf)));
+        const int mm = m0 * m0;
+#pragma unroll
+        for (int c = 0; c < kFoldM0 * kFoldM0 / (4 * kWB); ++c) {
+            const int k4 = tid + c * kWB;
+            if (4 * k4 < mm) g2lds16(llin + 4 * k4, reinterpret_cast<float *>(sLLb) + 4 * (c * kWB + (tid & ~63)));
+        }
+    }
 
     // ---- one batch of independent loads: the whole cone, straight into LDS ----
     // Levels 1 and 2 (most of the cone) arrive in 16-byte copies when the source is 16-byte
@@ -389,6 +489,9 @@ __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src,
                 }
                 continue;
             }
+            const bool coarse = FOLD && s > kf;  // fold: r before the update, and q or b_prev beside it
+            const T *base = coarse ? rin : src;
+            const T *base2 = coarse ? (F.e < 0 ? B.b_prev : qin) : nullptr;
 #pragma unroll
             for (int p = 0; p < wt_passes(s); ++p) {
                 const int rowi = (tid >> lp) + p * (kWB >> lp), q = tid & ((1 << lp) - 1);
@@ -397,16 +500,176 @@ __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src,
                 const int gr = ((loY[s] + r) & mk) + (o >= 2 ? m : 0);
                 const int gc = ((loX[s] + q) & mk) + ((o & 1) ? m : 0);
                 if (q < lx && rowi < (s == J ? 4 : 3) * ly) {
-                    const T *gp = src + coff + (long)gr * n + gc;
+                    const T *gp = base + coff + (long)gr * n + gc;
                     T *dst = sCone + (wt_slot0(s) + p) * kWB;
                     if constexpr (sizeof(T) == 4) g2lds(gp, dst + (tid & ~63));
                     else dst[tid] = *gp;
+                    if constexpr (FOLD) {
+                        if (coarse && base2)
+                            g2lds(base2 + coff + (long)gr * n + gc, sCone2 + (s - 3) * kWB + (tid & ~63));
+                    }
                 }
             }
         }
     }
-    if (MODE == kWtPcg && tid < (J + 1) * 4) sJi[tid] = jl;
+    if (PC && tid < (J + 1) * 4) sJi[tid] = jl;
+    if (FOLD && tid <= J) sAd[tid] = adv;
     lds_fence();
+    if constexpr (FOLD) {
+        // levels kf+1..J of W x from the level-kf approximation: bands into the m0 x m0 block sWb
+        // (Mallat positions), the LL chain through sXl / sXh
+        {
+            const T *srcL = sLLb;
+            int mi = m0;
+            for (int s = kf + 1; s <= J; ++s) {
+                const int h = mi >> 1, msk = mi - 1, lh = __ffs(h) - 1;
+                T *dstL = ((s - kf) & 1) ? sXl : sXh;
+                auto put = [&](int r, int q, const T *w) {
+                    sWb[r * m0 + q + h] = w[1];
+                    sWb[(r + h) * m0 + q] = w[2];
+                    sWb[(r + h) * m0 + q + h] = w[3];
+                    if (s == J) sWb[r * m0 + q] = w[0];
+                    else dstL[r * h + q] = w[0];
+                };
+                if (h * h > kWB) {
+                    // 2 x 2 quads per item from one 8 x 8 input patch (each input value read once
+                    // per item, not once per quad); per quad the same sums in the same order
+                    const int hb = h >> 1, lhb = lh - 1;
+                    for (int bi = tid; bi < hb * hb; bi += kWB) {
+                        const int R = bi >> lhb, Q = bi & (hb - 1);
+                        T w[2][2][4] = {};
+#pragma unroll
+                        for (int rr = 0; rr < 8; ++rr) {
+                            const T *row = srcL + ((4 * R + rr) & msk) * mi;
+                            T xv[8];
+#pragma unroll
+                            for (int b = 0; b < 8; ++b) xv[b] = row[(4 * Q + b) & msk];
+                            T ax[2], dx[2];
+#pragma unroll
+                            for (int dc = 0; dc < 2; ++dc) {
+                                ax[dc] = 0;
+                                dx[dc] = 0;
+#pragma unroll
+                                for (int b = 0; b < 6; ++b) {
+                                    ax[dc] += tp.h[b] * xv[2 * dc + b];
+                                    dx[dc] += tp.g[b] * xv[2 * dc + b];
+                                }
+                            }
+#pragma unroll
+                            for (int dr = 0; dr < 2; ++dr) {
+                                const int a = rr - 2 * dr;
+                                if (a >= 0 && a < 6) {
+#pragma unroll
+                                    for (int dc = 0; dc < 2; ++dc) {
+                                        w[dr][dc][0] += tp.h[a] * ax[dc];
+                                        w[dr][dc][2] += tp.g[a] * ax[dc];
+                                        w[dr][dc][1] += tp.h[a] * dx[dc];
+                                        w[dr][dc][3] += tp.g[a] * dx[dc];
+                                    }
+                                }
+                            }
+                        }
+#pragma unroll
+                        for (int dr = 0; dr < 2; ++dr)
+#pragma unroll
+                            for (int dc = 0; dc < 2; ++dc) put(2 * R + dr, 2 * Q + dc, w[dr][dc]);
+                    }
+                } else {
+                    for (int qi = tid; qi < h * h; qi += kWB) {
+                        const int r = qi >> lh, q = qi & (h - 1);
+                        T w[4] = {0, 0, 0, 0};
+#pragma unroll
+                        for (int a = 0; a < 6; ++a) {
+                            const T *row = srcL + ((2 * r + a) & msk) * mi;
+                            T ax = 0, dx = 0;
+#pragma unroll
+                            for (int b = 0; b < 6; ++b) {
+                                const T xv = row[(2 * q + b) & msk];
+                                ax += tp.h[b] * xv;
+                                dx += tp.g[b] * xv;
+                            }
+                            w[0] += tp.h[a] * ax;
+                            w[2] += tp.g[a] * ax;
+                            w[1] += tp.h[a] * dx;
+                            w[3] += tp.g[a] * dx;
+                        }
+                        put(r, q, w);
+                    }
+                }
+                __syncthreads();
+                srcL = dstL;
+                mi = h;
+            }
+        }
+        const StepOut so = fso;
+        const float al = (float)so.alpha, be = (float)so.beta;
+        const int log2n = __ffs(n) - 1;
+        // the tile's own coefficients: stored, with their partial sums of (r, z) and (z, alpha D z)
+        double rho = 0.0, dz = 0.0;
+        if (own) {
+            const int t = tid, orow = (id.loc >> lt) * sub + t / sub, ocol = (id.loc & ((1 << lt) - 1)) * sub + t % sub;
+            int sl, ol;
+            band_of(log2n, J, orow, ocol, sl, ol);
+            const float w = sWb[orow * m0 + ocol], ji = sJi[sl * 4 + ol], ad = sAd[sl];
+            float rn;
+            if (F.e < 0) {
+                rn = fold_rhs(w, o_b, o_r, F.cold);
+                static_cast<T *>(F.bsh)[gown] = w;
+                if (F.cold) static_cast<T *>(F.c)[gown] = 0;
+            } else if (!so.stopped) {
+                const FoldNew u = fold_pcg(w, o_r, o_c, o_p, o_q, ji, ad, al, be, F.e == 0);
+                B.p[gown] = u.p;
+                static_cast<T *>(F.c)[gown] = u.c;
+                static_cast<T *>(F.qout)[gown] = u.q;
+                rn = u.r;
+            } else {
+                static_cast<T *>(F.qout)[gown] = o_q;
+                rn = o_r;
+            }
+            static_cast<T *>(F.rout)[gown] = rn;
+            const T zn = rn * ji;
+            rho = (double)rn * (double)zn;
+            dz = (double)ad * (double)zn * (double)zn;
+        }
+        if (tid < kFoldOwn) {  // summed below, kFoldOwn / kFoldParts per partial pair
+            sRed[0][tid] = rho;
+            sRed[1][tid] = dz;
+        }
+        // the cone's coarse coefficients: r after the update, recomputed exactly as its owner does
+#pragma unroll
+        for (int s = 3; s <= kMaxJ; ++s) {  // compile-time level index: the cone bounds stay in registers
+            if (s <= J && s > kf) {
+                constexpr int lp = 3;
+                const int ly = LY[s], lx = LX[s], m = n >> s, mk = m - 1;
+                const int rowi = tid >> lp, q = tid & ((1 << lp) - 1);
+                const int bi = (rowi >= ly) + (rowi >= 2 * ly) + (rowi >= 3 * ly);
+                const int r = rowi - bi * ly, o = bi == 3 ? 0 : bi + 1;
+                if (q < lx && rowi < (s == J ? 4 : 3) * ly) {
+                    const int gr = ((loY[s] + r) & mk) + (o >= 2 ? m : 0);
+                    const int gc = ((loX[s] + q) & mk) + ((o & 1) ? m : 0);
+                    T *slot = sCone + wt_slot0(s) * kWB + tid;
+                    const float w = sWb[gr * m0 + gc], r0 = *slot, x2 = sCone2[(s - 3) * kWB + tid];
+                    float rn;
+                    if (F.e < 0) rn = fold_rhs(w, x2, r0, F.cold);
+                    else if (so.stopped) rn = r0;
+                    else rn = fold_pcg(w, r0, 0.0f, 0.0f, F.e >= 1 ? x2 : 0.0f, sJi[s * 4 + o], sAd[s], al, be, F.e == 0).r;
+                    *slot = rn;
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < kFoldParts) {  // fixed-order sums of the owned coefficients' contributions
+            constexpr int per = kFoldOwn / kFoldParts;
+            double a = 0.0, b = 0.0;
+#pragma unroll
+            for (int i = 0; i < per; ++i) {
+                a += sRed[0][tid * per + i];
+                b += sRed[1][tid * per + i];
+            }
+            B.partials[F.nfine + tile * kFoldParts + tid] = a;
+            B.partials[kPartialPitch + F.nfine + tile * kFoldParts + tid] = b;
+        }
+    }
 
     // ---- synthesis, coarsest level first, all in LDS.  Levels are unrolled so that every
     // region pitch is the compile-time power of two of its level (LL_s below J and the y-pass
@@ -422,9 +685,8 @@ __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src,
             const int dY = (loY[s - 1] >> 1) - loY[s], dX = (loX[s - 1] >> 1) - loX[s];
             const T *B1 = sCone + wt_slot0(s) * kWB, *B2 = B1 + LYs * PB, *B3 = B2 + LYs * PB;
             const T *LLs = s == J ? B3 + LYs * PB : sLL[cur];
-            const T jL = (MODE == kWtPcg && s == J) ? sJi[s * 4] : (T)1;
-            const T j1 = MODE == kWtPcg ? sJi[s * 4 + 1] : (T)1, j2 = MODE == kWtPcg ? sJi[s * 4 + 2] : (T)1,
-                    j3 = MODE == kWtPcg ? sJi[s * 4 + 3] : (T)1;
+            const T jL = (PC && s == J) ? sJi[s * 4] : (T)1;
+            const T j1 = PC ? sJi[s * 4 + 1] : (T)1, j2 = PC ? sJi[s * 4 + 2] : (T)1, j3 = PC ? sJi[s * 4 + 3] : (T)1;
             if (s >= 3) {
                 // small coarse regions: both directions at once, one output per item (no barrier
                 // between the y and x passes)
@@ -919,10 +1181,10 @@ __device__ __forceinline__ void epi_load(const Bufs<T> &B, const FwdArgs &E, lon
     if constexpr (EPI == kEpiPrior) {
         op[0] = static_cast<const T *>(E.cin)[i];
     } else if constexpr (EPI == kEpiPcg) {
-        op[0] = B.r[i];
+        op[0] = E.r_in ? static_cast<const T *>(E.r_in)[i] : B.r[i];
         op[1] = static_cast<const T *>(E.c)[i];
         op[2] = E.k > 0 ? B.p[i] : (T)0;
-        op[3] = E.k > 0 ? B.q[i] : (T)0;
+        op[3] = E.k > 0 ? (E.q_in ? static_cast<const T *>(E.q_in)[i] : B.q[i]) : (T)0;
     } else if constexpr (EPI == kEpiRhs) {
         op[0] = E.cold ? (T)0 : B.b_prev[i];
         op[1] = E.cold ? (T)0 : B.r[i];
@@ -951,6 +1213,7 @@ __device__ __forceinline__ void epi_store(const Bufs<T> &B, const FwdArgs &E, lo
             rn = r - al * q;
             B.r[i] = rn;
         }
+        if (E.b_in) B.b_prev[i] = static_cast<const T *>(E.b_in)[i];
         const T zn = rn * ji;
         rho += (double)rn * (double)zn;
         dz += (double)ad * (double)zn * (double)zn;
@@ -1151,10 +1414,10 @@ __global__ __launch_bounds__(kCB) void k_coarse(LayTab LT, Bufs<T> B, FwdArgs E,
             srcs[0] = static_cast<const T *>(E.cin);
             nsrc = 1;
         } else if constexpr (EPI == kEpiPcg) {
-            srcs[0] = B.r;
+            srcs[0] = E.r_in ? static_cast<const T *>(E.r_in) : B.r;
             srcs[1] = static_cast<const T *>(E.c);
             srcs[2] = B.p;
-            srcs[3] = B.q;
+            srcs[3] = E.q_in ? static_cast<const T *>(E.q_in) : B.q;
             nsrc = E.k > 0 ? 4 : 2;
         } else if constexpr (EPI == kEpiRhs) {
             srcs[0] = B.b_prev;
@@ -1745,13 +2008,23 @@ Taps<T> make_taps() {
 
 template <typename T>
 int Ops<T>::wt(const T *c, T *out) const {
-    k_wt<T, kWtPlain><<<dim3(P.n_wt, nb), kWB, 0, st>>>(P.seg_wt, c, out, B, make_taps<T>(), P.J);
+    k_wt<T, kWtPlain><<<dim3(P.n_wt, nb), kWB, 0, st>>>(P.seg_wt, c, out, B, make_taps<T>(), P.J, FoldArgs{});
     return check();
 }
 
 template <typename T>
 int Ops<T>::wt_pcg(const T *r, T *out) const {
-    k_wt<T, kWtPcg><<<dim3(P.n_wt, nb), kWB, 0, st>>>(P.seg_wt, r, out, B, make_taps<T>(), P.J);
+    k_wt<T, kWtPcg><<<dim3(P.n_wt, nb), kWB, 0, st>>>(P.seg_wt, r, out, B, make_taps<T>(), P.J, FoldArgs{});
+    return check();
+}
+
+template <typename T>
+int Ops<T>::wt_fold(const T *r, T *out, const FoldArgs &F) const {
+    if (sizeof(T) != 4 || !P.fold) return FEWHA_ERR_UNSUPPORTED;
+    FoldArgs G = F;
+    G.kf = P.kf;
+    G.nfine = P.n_fwd * fwd_waves(P.kf, P.tq);
+    k_wt<T, kWtFold><<<dim3(P.n_wt, nb), kWB, 0, st>>>(P.seg_wt, r, out, B, make_taps<T>(), P.J, G);
     return check();
 }
 
@@ -1809,11 +2082,14 @@ int fwd_waves(int kf, int tq) {
 }
 
 template <typename T, int EPI>
-static int fwd_launch(const Plan &P, const Bufs<T> &B, hipStream_t st, int nb, const T *x, const FwdArgs &E) {
+static int fwd_launch(const Plan &P, const Bufs<T> &B, hipStream_t st, int nb, const T *x, const FwdArgs &E,
+                      bool coarse) {
     const Taps<T> tp = make_taps<T>();
     const int nf = P.n_fwd;
     const int nfs = nf * fwd_waves(P.kf, P.tq);  // the fine tiles' partial slots (one per wave)
-#define FEWHA_FWD(KF, TQ) k_fwd<T, KF, TQ, EPI><<<dim3(nf, nb), (FwdLanes<KF, TQ>::block), 0, st>>>(P.seg_fwd, x, B, E, tp, P.J)
+    FwdArgs Ef = E;  // the shadows of a folded solve concern the coarse levels only
+    Ef.r_in = Ef.q_in = Ef.b_in = nullptr;
+#define FEWHA_FWD(KF, TQ) k_fwd<T, KF, TQ, EPI><<<dim3(nf, nb), (FwdLanes<KF, TQ>::block), 0, st>>>(P.seg_fwd, x, B, Ef, tp, P.J)
     if (P.kf == 1) {
         switch (P.tq) {
             case 1: FEWHA_FWD(1, 1); break;
@@ -1831,7 +2107,7 @@ static int fwd_launch(const Plan &P, const Bufs<T> &B, hipStream_t st, int nb, c
     }
 #undef FEWHA_FWD
     if (int e = check()) return e;
-    if (P.kf < P.J) {
+    if (P.kf < P.J && coarse) {
         size_t m = 0;
         for (auto &L : P.lay) m = (size_t)(L.n >> P.kf) > m ? (size_t)(L.n >> P.kf) : m;
         size_t base = (m * m + m * m / 4) * sizeof(T);
@@ -1851,12 +2127,12 @@ static int fwd_launch(const Plan &P, const Bufs<T> &B, hipStream_t st, int nb, c
 }
 
 template <typename T>
-int Ops<T>::fwd(const T *x, const FwdArgs &E, int epi) const {
+int Ops<T>::fwd(const T *x, const FwdArgs &E, int epi, bool coarse) const {
     switch (epi) {
-        case kEpiPlain: return fwd_launch<T, kEpiPlain>(P, B, st, nb, x, E);
-        case kEpiPrior: return fwd_launch<T, kEpiPrior>(P, B, st, nb, x, E);
-        case kEpiPcg: return fwd_launch<T, kEpiPcg>(P, B, st, nb, x, E);
-        default: return fwd_launch<T, kEpiRhs>(P, B, st, nb, x, E);
+        case kEpiPlain: return fwd_launch<T, kEpiPlain>(P, B, st, nb, x, E, coarse);
+        case kEpiPrior: return fwd_launch<T, kEpiPrior>(P, B, st, nb, x, E, coarse);
+        case kEpiPcg: return fwd_launch<T, kEpiPcg>(P, B, st, nb, x, E, coarse);
+        default: return fwd_launch<T, kEpiRhs>(P, B, st, nb, x, E, coarse);
     }
 }
 

@@ -105,6 +105,12 @@ void layout_workspace(Plan *P) {
     P->o_x = take(E * N * MB);
     P->o_v = take(E * P->n_nodes * MB);
     P->o_ll = take(E * ll_stride(N) * MB);
+    // folded coarse updates (used at the coarse coefficients only)
+    for (int i = 0; i < 2; ++i) {
+        P->o_rsh[i] = take(E * N * MB);
+        P->o_qsh[i] = take(E * N * MB);
+    }
+    P->o_bsh = take(E * N * MB);
     P->o_probe_c = take(E * N);
     P->o_stage = take(4 * E * N * MB);  // stage timing: scratch r, p, q, c of every frame
     P->o_probe_s = take(E * P->n_slopes);
@@ -117,6 +123,13 @@ void layout_workspace(Plan *P) {
 // Forward-DWT split (Eq. (fewha)'s W): levels 1..kf on tiles of tq x tq level-kf quads over the
 // whole GPU, levels kf+1..J per layer in one workgroup whose LDS holds the level-kf approximation.
 // Rebuilds the fine tiles' segment table; the workspace layout does not depend on the split.
+bool fold_possible(const Plan &P) {
+    int max_n = 0;
+    for (auto &L : P.lay) max_n = L.n > max_n ? L.n : max_n;
+    return P.prec == FEWHA_FP32 && P.kf == 2 && P.J > 2 && (max_n >> 2) <= 64 &&
+           P.n_fwd * fwd_waves(P.kf, P.tq) + P.n_wt * kFoldParts <= kPartialPitch;
+}
+
 int set_fwd_split(Plan *P, int kf, int tq) {
     int max_n = 0, min_n = 1 << 30;
     for (auto &L : P->lay) {
@@ -149,7 +162,9 @@ int set_fwd_split(Plan *P, int kf, int tq) {
         n_fwd += nq * nq;
     }
     S.start[P->nl] = n_fwd;
-    const int nres = n_fwd * fwd_waves(kf, tq) + (kf < P->J ? P->nl * kCoarseWaves : 0);
+    int nc = P->nl * kCoarseWaves;
+    if (P->fold) nc = nc > P->n_wt * kFoldParts ? nc : P->n_wt * kFoldParts;
+    const int nres = n_fwd * fwd_waves(kf, tq) + (kf < P->J ? nc : 0);
     if (nres > kPartialPitch) return FEWHA_ERR_UNSUPPORTED;
     P->kf = kf;
     P->tq = tq;
@@ -389,6 +404,7 @@ int plan_create(const fewha_config *cfg, Plan **out) {
             delete P;
             return FEWHA_ERR_UNSUPPORTED;
         }
+        P->fold = fold_possible(*P);
     }
     P->seg_proj.nseg = P->nw;
     for (int g = 0; g < P->nw; ++g) {

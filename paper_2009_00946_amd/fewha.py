@@ -49,7 +49,7 @@ class _Dm(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("kf", ctypes.c_int), ("tq", ctypes.c_int), ("chunk_wt", ctypes.c_int), ("chunk_proj", ctypes.c_int),
-                ("chunk_pt", ctypes.c_int), ("chunk_fwd", ctypes.c_int)]
+                ("chunk_pt", ctypes.c_int), ("chunk_fwd", ctypes.c_int), ("fold", ctypes.c_int)]
 
 
 TUNING_FIELDS = [f for f, _ in _Tuning._fields_]

@@ -173,24 +173,33 @@ def test_tuning_defaults_and_validation(cfg_c0):
     assert st == 0
     t = fewha._Tuning()
     assert L.fewha_get_tuning(h, ctypes.byref(t)) == 0
-    assert (t.kf, t.tq, t.chunk_wt, t.chunk_proj, t.chunk_pt, t.chunk_fwd) == (2, 8, 0, 0, 16, 0)
-    t2 = fewha._Tuning(1, 4, 8, 4, 0, 16)
+    assert (t.kf, t.tq, t.chunk_wt, t.chunk_proj, t.chunk_pt, t.chunk_fwd, t.fold) == (2, 8, 0, 0, 16, 0, 1)
+    t2 = fewha._Tuning(1, 4, 8, 4, 0, 16, 0)
     assert L.fewha_set_tuning(h, ctypes.byref(t2)) == 0
     back = fewha._Tuning()
     L.fewha_get_tuning(h, ctypes.byref(back))
-    assert [getattr(back, f) for f in fewha.TUNING_FIELDS] == [1, 4, 8, 4, 0, 16]
-    for bad in ((3, 4, 0, 0, 0, 0), (2, 3, 0, 0, 0, 0), (2, 16, 0, 0, 0, 0), (2, 8, -1, 0, 0, 0), (2, 8, 0, 0, 300, 0)):
+    assert [getattr(back, f) for f in fewha.TUNING_FIELDS] == [1, 4, 8, 4, 0, 16, 0]
+    for bad in ((3, 4, 0, 0, 0, 0, 0), (2, 3, 0, 0, 0, 0, 0), (2, 16, 0, 0, 0, 0, 0), (2, 8, -1, 0, 0, 0, 0),
+                (2, 8, 0, 0, 300, 0, 0), (2, 8, 0, 0, 0, 0, 2)):
         assert L.fewha_set_tuning(h, ctypes.byref(fewha._Tuning(*bad))) == -1, bad
-    # one-level split with 1 x 1 tiles: more fine tiles' partial sums than the buffer holds
-    assert L.fewha_set_tuning(h, ctypes.byref(fewha._Tuning(1, 1, 0, 0, 0, 0))) == -3
+    # one-level split with 1 x 1 tiles: more fine tiles' partial sums than the buffer holds; the
+    # fold with a one-level split
+    assert L.fewha_set_tuning(h, ctypes.byref(fewha._Tuning(1, 1, 0, 0, 0, 0, 0))) == -3
+    assert L.fewha_set_tuning(h, ctypes.byref(fewha._Tuning(1, 4, 0, 0, 0, 0, 1))) == -3
     L.fewha_get_tuning(h, ctypes.byref(back))
-    assert [getattr(back, f) for f in fewha.TUNING_FIELDS] == [1, 4, 8, 4, 0, 16]
+    assert [getattr(back, f) for f in fewha.TUNING_FIELDS] == [1, 4, 8, 4, 0, 16, 0]
     assert L.fewha_autotune(h, 1, ctypes.byref(t), None) == -5   # unbound
     L.fewha_plan_destroy(h)
     # the tiny geometry: tiles of at most its 32 >> kf quads
     h, st = fewha.create_host_plan(cfg_c0)
-    assert L.fewha_set_tuning(h, ctypes.byref(fewha._Tuning(2, 8, 0, 0, 0, 0))) == 0
-    assert L.fewha_set_tuning(h, ctypes.byref(fewha._Tuning(1, 8, 0, 0, 0, 0))) == 0
+    assert L.fewha_set_tuning(h, ctypes.byref(fewha._Tuning(2, 8, 0, 0, 0, 0, 0))) == 0
+    assert L.fewha_set_tuning(h, ctypes.byref(fewha._Tuning(1, 8, 0, 0, 0, 0, 0))) == 0
+    L.fewha_plan_destroy(h)
+    # no fold in FP64
+    h, st = fewha.create_host_plan(cfg, precision="fp64")
+    L.fewha_get_tuning(h, ctypes.byref(back))
+    assert back.fold == 0
+    assert L.fewha_set_tuning(h, ctypes.byref(fewha._Tuning(2, 8, 0, 0, 16, 0, 1))) == -3
     L.fewha_plan_destroy(h)
 
 

@@ -53,15 +53,17 @@ def test_launch_shapes_keep_parity(name, prec):
     tol_c, tol_l = BOUNDS[prec]
     J = cfg["J"]
     shapes = [dict(default, chunk_wt=8, chunk_proj=4, chunk_pt=0, chunk_fwd=16),   # renumbering only
-              dict(default, kf=1, tq=4), dict(default, kf=1, tq=8), dict(default, kf=min(2, J), tq=2),
-              dict(default, kf=min(2, J), tq=4, chunk_wt=4, chunk_fwd=8)]
+              dict(default, kf=1, tq=4, fold=0), dict(default, kf=1, tq=8, fold=0),
+              dict(default, kf=min(2, J), tq=2), dict(default, kf=min(2, J), tq=4, chunk_wt=4, chunk_fwd=8)]
+    if default["fold"]:  # the coarse levels folded into the next inverse DWT, and not
+        shapes += [dict(default, fold=0), dict(default, fold=0, tq=4)]
     for sh in shapes:
         print("[shape] %s %s %s" % (name, prec, sh), flush=True)
         P.set_tuning(sh)
         assert P.get_tuning() == sh
         got = _chain(P, O, cfg, 3)
         for f, ((c, lay, c_ref, lay_ref), (c0, lay0, _, _)) in enumerate(zip(got, base)):
-            if (sh["kf"], sh["tq"]) == (default["kf"], default["tq"]):
+            if (sh["kf"], sh["tq"], sh["fold"]) == (default["kf"], default["tq"], default["fold"]):
                 assert np.array_equal(c, c0), (sh, f)
             assert _rel(c, c_ref) <= tol_c and _rel(lay, lay_ref) <= tol_l, (sh, f, _rel(c, c_ref), _rel(lay, lay_ref))
     P.set_tuning(default)
