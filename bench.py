@@ -574,9 +574,10 @@ def main():
                     help="FP32: recompute the residual as b - M c every this many frames (0: always carried)")
     ap.add_argument("--eager", action="store_true", help="launch kernels one by one instead of replaying HIP graphs")
     ap.add_argument("--stage-reps", type=int, default=50, help="launches per PCG-pass stage in its timing graph")
-    ap.add_argument("--workload", default="frame", choices=("frame", "c3_batch", "batch_scan"),
+    ap.add_argument("--workload", default="frame", choices=("frame", "c3_batch", "batch_scan", "batched"),
                     help="frame: the ELT frame (default); c3_batch: 64 uneven frames in batched launches; "
-                         "batch_scan: ELT frames per second against frames per launch")
+                         "batch_scan: ELT frames per second against frames per launch; batched: only the "
+                         "batched forms of the default line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run plain 256 MiB device copies (reference dispatches for HBM counters)")
     args = ap.parse_args()
@@ -590,6 +591,16 @@ def main():
         return
     if args.workload == "batch_scan":
         batch_scan(args)
+        return
+    if args.workload == "batched":
+        import torch
+        from paper_2009_00946_amd import synth
+        torch.cuda.set_device(0)
+        cfg = synth.load_config(args.config)
+        out = {"same_geometry": batched_same_geometry(cfg, args.batch, args.steps, args.warmup, args.refresh,
+                                                      tuned=not args.no_tune),
+               "uneven_64": uneven_mix_summary(args.steps, args.warmup, tuned=not args.no_tune)}
+        print(json.dumps(out), flush=True)
         return
 
     import torch

@@ -762,20 +762,26 @@ int autotune_on(fewha_plan *h, int nb, hipStream_t st, hipEvent_t e0, hipEvent_t
     for (int s = FEWHA_STAGE_WT; s <= FEWHA_STAGE_FWD; ++s) TRY(stage_launch<T>(P, s, st, nb));
     fewha_tuning t{};
     TRY(fewha_get_tuning(h, &t));
-    // 1. the forward-DWT split (kf, tq), timed on the forward-DWT stage with all its levels
-    double bt = 1e30;
+    // A candidate replaces the current choice only when it is faster by more than kGain, so that
+    // timing noise does not flip the shapes from run to run.
+    constexpr double kGain = 0.97;
+    // 1. the forward-DWT split (kf, tq), timed on the forward-DWT stage with all its levels,
+    // starting from the plan's current split
     const int fold_default = t.fold;
     t.fold = 0;
+    TRY(fewha_set_tuning(h, &t));
+    double bt = 0;
+    TRY(time_stage<T>(P, FEWHA_STAGE_FWD, nb, st, e0, e1, &bt));
     fewha_tuning bs = t;
     for (int kf = 1; kf <= 2; ++kf)
         for (int tq : {1, 2, 4, 8}) {
             fewha_tuning c = t;
             c.kf = kf;
             c.tq = tq;
-            if (fewha_set_tuning(h, &c) != FEWHA_OK) continue;
+            if ((kf == t.kf && tq == t.tq) || fewha_set_tuning(h, &c) != FEWHA_OK) continue;
             double u = 0;
             TRY(time_stage<T>(P, FEWHA_STAGE_FWD, nb, st, e0, e1, &u));
-            if (u < bt) {
+            if (u < kGain * bt) {
                 bt = u;
                 bs = c;
             }
@@ -793,22 +799,26 @@ int autotune_on(fewha_plan *h, int nb, hipStream_t st, hipEvent_t e0, hipEvent_t
             TRY(fewha_set_tuning(h, &t));
             TRY(time_stage<T>(P, FEWHA_STAGE_WT, nb, st, e0, e1, &w0));
             TRY(time_stage<T>(P, FEWHA_STAGE_FWD, nb, st, e0, e1, &f0));
-            if (w1 + f1 < w0 + f0) t = c;
+            // the plan's default (fold where it applies) unless the other is clearly faster
+            const bool on = fold_default ? !(w0 + f0 < kGain * (w1 + f1)) : (w1 + f1 < kGain * (w0 + f0));
+            if (on) t = c;
             TRY(fewha_set_tuning(h, &t));
         }
     }
-    (void)fold_default;
     // 3. each tile kernel's XCD chunk, on its own stage
     int *chunk[4] = {&t.chunk_wt, &t.chunk_proj, &t.chunk_pt, &t.chunk_fwd};
     for (int s = FEWHA_STAGE_WT; s <= FEWHA_STAGE_FWD; ++s) {
-        double bu = 1e30;
-        int bk = *chunk[s];
+        const int k0 = *chunk[s];
+        double bu = 0;
+        TRY(time_stage<T>(P, s, nb, st, e0, e1, &bu));
+        int bk = k0;
         for (int k : {0, 4, 8, 16, 32}) {
+            if (k == k0) continue;
             *chunk[s] = k;
             TRY(fewha_set_tuning(h, &t));
             double u = 0;
             TRY(time_stage<T>(P, s, nb, st, e0, e1, &u));
-            if (u < bu) {
+            if (u < kGain * bu) {
                 bu = u;
                 bk = k;
             }
