@@ -3,7 +3,8 @@
 The tuner itself is native: it times the stage kernels of a bound plan for every valid launch
 shape (forward-DWT split, fine tile size, XCD chunks) and keeps the fastest.  This module keeps
 its results in a JSON file keyed by everything the timing depends on (geometry, precision, frames
-per launch, device name), so a plan of a known geometry gets its shapes without timing again.
+per launch, device architecture and compute-unit count), so a plan of a known geometry gets its
+shapes without timing again.
 
     from paper_2009_00946_amd import fewha, tune
     P = fewha.Plan(cfg, max_batch=32)
@@ -30,6 +31,14 @@ def geometry_key(cfg, precision, nbatch, device):
     return hashlib.sha256(json.dumps(geo, sort_keys=True).encode()).hexdigest()[:32]
 
 
+def device_id(device):
+    """Architecture and compute-unit count of a device (its marketing name can differ between
+    runtimes, e.g. under a profiler, while the tuned shapes still apply)."""
+    import torch
+    pr = torch.cuda.get_device_properties(device)
+    return "%s/%dcu" % (getattr(pr, "gcnArchName", pr.name).split(":")[0], pr.multi_processor_count)
+
+
 def _read(path):
     try:
         with open(path) as f:
@@ -44,7 +53,7 @@ def tuned(P, nbatch=None, cache=None, retune=False):
     import torch
     nb = P.max_batch if nbatch is None else int(nbatch)
     path = cache or default_cache()
-    key = geometry_key(P.cfg, P.precision, nb, torch.cuda.get_device_name(P.device))
+    key = geometry_key(P.cfg, P.precision, nb, device_id(P.device))
     db = _read(path)
     if key in db and not retune:
         rec = db[key]
