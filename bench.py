@@ -384,8 +384,7 @@ def batched_same_geometry(cfg, nb, steps, warmup, refresh=8, tuned=True):
     ab = torch.zeros((nb, PB.n_act), dtype=PB.dtype, device=PB.device)
 
     def step(warm=True, fresh=False):
-        PB.pcg_solve_batch(sb, cb, n_iter, warm=warm, refresh=fresh and warm)
-        PB.fit_dm_batch(cb, gain=gain, out=ab)
+        PB.reconstruct_batch(sb, cb, n_iter, gain=gain, out=ab, warm=warm, refresh=fresh and warm)
 
     g_warm = capture(step)
     g_fresh = capture(lambda warm=True: step(warm, fresh=True), warm_steps=0) if refresh else None
@@ -434,8 +433,8 @@ class UnevenMix:
 
     def batched(self, warm=True, fresh=False):
         for g in self.groups:
-            g["PB"].pcg_solve_batch(g["sb"], g["cb"], self.n_iter, warm=warm, refresh=fresh and warm)
-            g["PB"].fit_dm_batch(g["cb"], gain=1.0, out=g["ab"])
+            g["PB"].reconstruct_batch(g["sb"], g["cb"], self.n_iter, gain=1.0, out=g["ab"], warm=warm,
+                                      refresh=fresh and warm)
 
     def concurrent(self, warm=True, fresh=False):
         # the three batched plans on streams of their own (fork and join by events): no data is
@@ -445,16 +444,15 @@ class UnevenMix:
         for g, s in zip(self.groups, self.streams):
             s.wait_stream(main)
             with torch.cuda.stream(s):
-                g["PB"].pcg_solve_batch(g["sb"], g["cb"], self.n_iter, warm=warm, refresh=fresh and warm)
-                g["PB"].fit_dm_batch(g["cb"], gain=1.0, out=g["ab"])
+                g["PB"].reconstruct_batch(g["sb"], g["cb"], self.n_iter, gain=1.0, out=g["ab"], warm=warm,
+                                          refresh=fresh and warm)
         for s in self.streams:
             main.wait_stream(s)
 
     def single(self, warm=True):
         for g in self.groups:
             for f in range(g["count"]):
-                g["P1"].pcg_solve(g["sb"][f], g["c1"], self.n_iter, warm=warm)
-                g["P1"].fit_dm(g["c1"], gain=1.0, out=g["a1"])
+                g["P1"].reconstruct(g["sb"][f], g["c1"], self.n_iter, gain=1.0, out=g["a1"], warm=warm)
 
     @property
     def frames(self):
@@ -636,8 +634,7 @@ def main():
 
     def frame(k, warm=True):
         fresh = warm and args.refresh > 0 and k % args.refresh == 0
-        P.pcg_solve(S[k % len(S)], c, n_iter, warm=warm, refresh=fresh)
-        P.fit_dm(c, a, gain, out=a)
+        P.reconstruct(S[k % len(S)], c, n_iter, a_prev=a, gain=gain, out=a, warm=warm, refresh=fresh)
 
     frame(0, warm=False)
     for k in range(1, args.warmup):
@@ -720,7 +717,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%s: %s" % (cfg["name"], cfg["description"]), "n_iter": n_iter, "warm": True,
                    "gain": gain, "n_coef": model["n_coef"], "n_slopes": P.n_slopes, "n_act": P.n_act,
-                   "launch": "eager" if args.eager else "hip_graph_per_frame",
+                   "launch": ("eager" if args.eager else "hip_graph_per_frame") + " (fewha_reconstruct: solve and fit in one call)",
                    "residual_refresh_every": args.refresh or None,
                    "launch_shapes": tuning and dict(tuning["tuning"], autotuned=not tuning["cached"])},
         "ms_median": round(float(np.median(per)), 5),

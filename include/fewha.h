@@ -185,6 +185,11 @@ int fewha_pcg_solve(fewha_plan *p, const void *d_s, void *d_c, int n_iter, int f
 int fewha_fit_dm(const fewha_plan *p, const void *d_c, const void *d_a_prev, double gain, void *d_a,
                  void *stream);
 
+/* One whole frame of Alg. 1 in one call: fewha_pcg_solve, then fewha_fit_dm of its c (arguments
+ * and results as theirs, bit for bit).  d_a must not alias d_c or d_s. */
+int fewha_reconstruct(fewha_plan *p, const void *d_s, void *d_c, int n_iter, int flags, double *d_resnorm,
+                      const void *d_a_prev, double gain, void *d_a, void *stream);
+
 /* Differentiation support (the adjoint state of Eq. (fewha)).  Solve M c = b for a right-hand
  * side b given in the wavelet domain (n_coef values), from c = 0, with n_iter passes of Alg. 2
  * and the Jacobi preconditioner of Sec. 3.4; d_resnorm as in fewha_pcg_solve.  The residual
@@ -275,6 +280,8 @@ int fewha_pcg_solve_batch(fewha_plan *p, int nbatch, const void *d_s, void *d_c,
                           double *d_resnorm, void *stream);
 int fewha_fit_dm_batch(const fewha_plan *p, int nbatch, const void *d_c, const void *d_a_prev, double gain,
                        void *d_a, void *stream);
+int fewha_reconstruct_batch(fewha_plan *p, int nbatch, const void *d_s, void *d_c, int n_iter, int flags,
+                            double *d_resnorm, const void *d_a_prev, double gain, void *d_a, void *stream);
 int fewha_pol_slopes_batch(const fewha_plan *p, int nbatch, const void *d_s, const void *d_a_m1, void *d_s_pol,
                            void *stream);
 int fewha_fit_dm_closed_batch(const fewha_plan *p, int nbatch, const void *d_c, const void *d_a0, const void *d_a_m1,

@@ -146,8 +146,37 @@ int rhs_transform(const Plan &P, const Ops<T> &o, void *c, int cold, int n_iter)
 // e writes r, q to shadow (e + 1) & 1 and reads shadow e & 1), because every tile of a layer reads
 // them at its cone while their owners write the new values; b's coarse coefficients wait in their
 // own shadow.  The last forward transform reads the shadows and leaves r, q, p, c and b_prev whole.
+// The last pass's coarse levels when the caller launches them (see last_fwd).
+struct Deferred {
+    bool set = false;
+    FoldArgs F{};
+};
+
+// The last pass's forward transform.  c's share of the coarse levels needs no W x (c + alpha p),
+// so the fine launch steps it; the coarse levels then update r, q, p (and b_prev) there and leave
+// c alone: for a folded solve in the tail workgroups of an inverse-DWT launch (their arguments go
+// to `defer` when the caller launches them beside its own W^T c, else they run here alone),
+// otherwise in the coarse forward launch.
 template <typename T>
-int pcg_passes(const Plan &P, const Ops<T> &o, void *c, int n_iter, double *resnorm, int cold = 0) {
+int last_fwd(const Ops<T> &o, FwdArgs E, void *c, bool fold, int k, Deferred *defer) {
+    E.cc = c;
+    E.cc_r = fold ? o.B.rsh[k & 1] : nullptr;
+    TRY(o.fwd(o.B.x, E, kEpiPcg, false, true));
+    if (!fold) return o.fwd(o.B.x, E, kEpiPcg, true, false);
+    FoldArgs F{};
+    F.e = k;
+    F.rin = o.B.rsh[k & 1];
+    F.qin = k >= 1 ? o.B.qsh[k & 1] : nullptr;
+    F.bsh = o.B.bsh;
+    if (!defer) return o.wt_tail(nullptr, nullptr, F);
+    defer->set = true;
+    defer->F = F;
+    return FEWHA_OK;
+}
+
+template <typename T>
+int pcg_passes(const Plan &P, const Ops<T> &o, void *c, int n_iter, double *resnorm, int cold = 0,
+               Deferred *defer = nullptr) {
     // partial sums of (r, z) and (z, alpha D z) come from the transforms that write r
     const int nres = residual_partials(P);
     const bool fold = P.fold && n_iter > 0;
@@ -178,7 +207,8 @@ int pcg_passes(const Plan &P, const Ops<T> &o, void *c, int n_iter, double *resn
             E.q_in = k >= 1 ? o.B.qsh[k & 1] : nullptr;
             E.b_in = o.B.bsh;
         }
-        TRY(o.fwd(o.B.x, E, kEpiPcg, !fold || last));
+        if (last && P.kf < P.J) TRY(last_fwd<T>(o, E, c, fold, k, defer));
+        else TRY(o.fwd(o.B.x, E, kEpiPcg, !fold || last));
     }
     const_cast<Plan &>(P).last_slot = n_iter > 0 ? ((n_iter - 1) & 1) : 1;
     return FEWHA_OK;
@@ -186,7 +216,7 @@ int pcg_passes(const Plan &P, const Ops<T> &o, void *c, int n_iter, double *resn
 
 template <typename T>
 int pcg_solve(const Plan &P, const void *s, void *c, int n_iter, int flags, double *resnorm, void *stream,
-              int nb = 1) {
+              int nb = 1, Deferred *defer = nullptr) {
     auto o = ops<T>(P, stream, nb);
     if (flags == FEWHA_REFRESH) {
         // b_prev = M c and r_prev = 0, so that the residual update below gives r = b - M c (Alg. 1's
@@ -205,7 +235,7 @@ int pcg_solve(const Plan &P, const void *s, void *c, int n_iter, int flags, doub
     TRY(o.pt(o.B.v, o.B.x, PassArgs{-1, 0, 0, 0, nullptr, 0}));
     const int cold = flags == FEWHA_COLD ? 1 : 0;
     TRY(rhs_transform<T>(P, o, c, cold, n_iter));
-    return pcg_passes<T>(P, o, c, n_iter, resnorm, cold);
+    return pcg_passes<T>(P, o, c, n_iter, resnorm, cold, defer);
 }
 
 // M c = b for a right-hand side given in the coefficient domain, from c = 0: x = W^T b first,
@@ -236,6 +266,19 @@ template <typename T>
 int fit_dm(const Plan &P, const void *c, const void *a_prev, double gain, void *a, void *stream, int nb = 1) {
     auto o = ops<T>(P, stream, nb);
     TRY(o.wt(static_cast<const T *>(c), o.B.u));
+    return o.fit(o.B.u, static_cast<const T *>(a_prev), static_cast<T *>(a), gain);
+}
+
+// One reconstruction of Alg. 1: the solve, then the fit of its c.  In a folded solve the last
+// pass's coarse levels (which the fit does not read) run as extra workgroups of the fit's W^T c.
+template <typename T>
+int reconstruct(const fewha_plan *h, const void *s, void *c, int n_iter, int flags, double *resnorm,
+                const void *a_prev, double gain, void *a, void *stream, int nb = 1) {
+    Deferred d;
+    TRY(pcg_solve<T>(h->p, s, c, n_iter, flags, resnorm, stream, nb, &d));
+    if (!d.set) return fit_dm<T>(h->p, c, a_prev, gain, a, stream, nb);
+    auto o = ops<T>(h->p, stream, nb);
+    TRY(o.wt_tail(static_cast<const T *>(c), o.B.u, d.F));
     return o.fit(o.B.u, static_cast<const T *>(a_prev), static_cast<T *>(a), gain);
 }
 
@@ -560,6 +603,17 @@ int fewha_cn2_gradient(const fewha_plan *p, const void *d_lambda, const void *d_
                                    : prior_dot<float>(p->p, d_lambda, d_c, d_out, stream, true);
 }
 
+int fewha_reconstruct(fewha_plan *p, const void *d_s, void *d_c, int n_iter, int flags, double *d_resnorm,
+                      const void *d_a_prev, double gain, void *d_a, void *stream) {
+    TRY(ready(p));
+    if (!d_s || !d_c || !d_a || d_a == d_c || d_a == d_s || n_iter < 0 || !std::isfinite(gain) ||
+        (flags != FEWHA_COLD && flags != FEWHA_WARM && flags != FEWHA_REFRESH))
+        return FEWHA_ERR_INVALID_ARG;
+    return p->p.prec == FEWHA_FP64
+               ? reconstruct<double>(p, d_s, d_c, n_iter, flags, d_resnorm, d_a_prev, gain, d_a, stream)
+               : reconstruct<float>(p, d_s, d_c, n_iter, flags, d_resnorm, d_a_prev, gain, d_a, stream);
+}
+
 int fewha_fit_dm(const fewha_plan *p, const void *d_c, const void *d_a_prev, double gain, void *d_a, void *stream) {
     TRY(ready(p));
     if (!d_c || !d_a || d_a == d_c || !std::isfinite(gain)) return FEWHA_ERR_INVALID_ARG;
@@ -640,6 +694,17 @@ int fewha_pcg_solve_batch(fewha_plan *p, int nbatch, const void *d_s, void *d_c,
     if (!d_s || !d_c || n_iter < 0 || (flags != FEWHA_COLD && flags != FEWHA_WARM && flags != FEWHA_REFRESH)) return FEWHA_ERR_INVALID_ARG;
     return p->p.prec == FEWHA_FP64 ? pcg_solve<double>(p->p, d_s, d_c, n_iter, flags, d_resnorm, stream, nbatch)
                                    : pcg_solve<float>(p->p, d_s, d_c, n_iter, flags, d_resnorm, stream, nbatch);
+}
+
+int fewha_reconstruct_batch(fewha_plan *p, int nbatch, const void *d_s, void *d_c, int n_iter, int flags,
+                            double *d_resnorm, const void *d_a_prev, double gain, void *d_a, void *stream) {
+    TRY(batch_ok(p, nbatch));
+    if (!d_s || !d_c || !d_a || d_a == d_c || d_a == d_s || n_iter < 0 || !std::isfinite(gain) ||
+        (flags != FEWHA_COLD && flags != FEWHA_WARM && flags != FEWHA_REFRESH))
+        return FEWHA_ERR_INVALID_ARG;
+    return p->p.prec == FEWHA_FP64
+               ? reconstruct<double>(p, d_s, d_c, n_iter, flags, d_resnorm, d_a_prev, gain, d_a, stream, nbatch)
+               : reconstruct<float>(p, d_s, d_c, n_iter, flags, d_resnorm, d_a_prev, gain, d_a, stream, nbatch);
 }
 
 int fewha_fit_dm_batch(const fewha_plan *p, int nbatch, const void *d_c, const void *d_a_prev, double gain,

@@ -226,6 +226,9 @@ constexpr int kProjWaves = 4;
 
 // Waves of a coarse forward-DWT workgroup: each leaves its own pair of residual partials.
 constexpr int kCoarseWaves = 16;
+// Workgroups per layer that run the last pass's coarse levels of a folded solve (each recomputes W x
+// of the layer's coarse block and updates a quarter of it: at most 4 coefficients per lane).
+constexpr int kTailParts = 4;
 // Coarse coefficients an inverse-DWT tile owns in a folded update, and the partial pairs it
 // leaves for them.
 constexpr int kFoldOwn = 64;

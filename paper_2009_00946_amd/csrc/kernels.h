@@ -19,6 +19,12 @@ struct FwdArgs {
     // r and q before the update come from these shadows, and b_in (the right-hand side's coarse
     // coefficients) is copied to b_prev (null: the plan's own r, q; no copy)
     const void *r_in, *q_in, *b_in;
+    // pcg, last pass: the fine transform's workgroups also step the coarse coefficients of c (each
+    // its share of the layer's coarse block; c's update needs no W x), from cc_r, the residual
+    // before the update there (null: the plan's r); the coarse levels then run with c null and
+    // leave c alone, so that nothing that reads only c waits for them
+    void *cc;
+    const void *cc_r;
 };
 
 // The coarse levels (kf+1..J) of the forward transform that precedes an inverse DWT, folded into
@@ -35,6 +41,9 @@ struct FoldArgs {
     const void *qin;    // q before the update (e >= 1)
     void *rout, *qout;  // r, q after the update (shadows of e)
     void *bsh;          // e = -1: b at the coarse coefficients (copied to b_prev at the solve's end)
+    // the last pass's coarse levels (kWtTail): workgroups [0, ntail) of the launch, `parts` per
+    // layer, update p, q, r (from rin, qin) and copy bsh to b_prev; the tiles follow them
+    int ntail, parts;
 };
 
 // The PCG pass whose scalar step an x = P^T v launch also performs (k < 0: none).
@@ -82,10 +91,14 @@ struct Ops {
     int wt(const T *c, T *out) const;                     // out = W^T c
     int wt_pcg(const T *r, T *out) const;                 // out = W^T J^-1 r
     int wt_fold(const T *r, T *out, const FoldArgs &F) const;  // the fold's update, then out = W^T J^-1 r'
+    // the last pass's coarse levels (pass F.e, operands F.rin, F.qin, F.bsh) beside out = W^T c
+    // (c null: those levels alone)
+    int wt_tail(const T *c, T *out, const FoldArgs &F) const;
     int proj(const T *u, T *out, int mode) const;         // kProjM: v = Gamma^T C Gamma P u; kProjA/CA: s = (C) mask Gamma P u
     int gt(const T *s, T *v, int mode) const;             // v = Gamma^T C s | Gamma^T mask s
     int pt(const T *v, T *x, const PassArgs &PA) const;   // x = P^T v (+ the scalar step of pass PA.k)
-    int fwd(const T *x, const FwdArgs &E, int epi, bool coarse = true) const; // W x with an epilogue (coarse: levels past kf too)
+    // W x with an epilogue: the fine levels (fine) and the levels past kf (coarse)
+    int fwd(const T *x, const FwdArgs &E, int epi, bool coarse = true, bool fine = true) const;
     int wnorm(const T *s) const;                          // sc[2].rho = sum C s^2
     int fit(const T *u, const T *a_prev, T *a, double gain, const T *a_m1 = nullptr) const;  // a_m1: closed loop
     int pol(const T *a_m1, const T *s, T *s_pol) const;   // s_pol = mask (s + Gamma P_DM a_m1)

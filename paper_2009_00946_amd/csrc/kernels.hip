@@ -69,8 +69,7 @@ struct TileId {
 // the XCDs in turn, so that every XCD gets a share of every layer (tiles of different layers
 // differ in cost) and the segments listed first are dispatched first, while a chunk's tiles still
 // share an L2.  Tiles past the last whole round of 8 chunks keep their own number.
-__device__ __forceinline__ int xcd_tile(int K, int ntiles) {
-    const int b = (int)blockIdx.x;
+__device__ __forceinline__ int xcd_tile(int K, int ntiles, int b) {
     if (K == 0) {
         const int q = ntiles >> 3, rem = ntiles & 7, x = b & 7;
         return x * q + min(x, rem) + (b >> 3);
@@ -80,6 +79,8 @@ __device__ __forceinline__ int xcd_tile(int K, int ntiles) {
     const int i = b >> 3;
     return ((i / K) * 8 + (b & 7)) * K + (i % K);
 }
+
+__device__ __forceinline__ int xcd_tile(int K, int ntiles) { return xcd_tile(K, ntiles, (int)blockIdx.x); }
 
 __device__ __forceinline__ TileId find_tile(const SegTab &S, int b) {
     const int lane = threadIdx.x & 63;
@@ -127,6 +128,8 @@ __device__ __forceinline__ FwdArgs frame_args(FwdArgs E, long fs_c) {
     if (E.r_in) E.r_in = static_cast<const T *>(E.r_in) + c;
     if (E.q_in) E.q_in = static_cast<const T *>(E.q_in) + c;
     if (E.b_in) E.b_in = static_cast<const T *>(E.b_in) + c;
+    if (E.cc) E.cc = static_cast<T *>(E.cc) + c;
+    if (E.cc_r) E.cc_r = static_cast<const T *>(E.cc_r) + c;
     return E;
 }
 
@@ -323,8 +326,9 @@ __device__ __forceinline__ void lds_fence() {
     __syncthreads();
 }
 
-// kWtFold: kWtPcg after the folded coarse update (see FoldArgs).
-enum { kWtPlain = 0, kWtPcg = 1, kWtFold = 2 };
+// kWtFold: kWtPcg after the folded coarse update (see FoldArgs).  kWtTail: kWtPlain tiles after
+// F.ntail workgroups that run the last pass's coarse levels (coarse_tail).
+enum { kWtPlain = 0, kWtPcg = 1, kWtFold = 2, kWtTail = 3 };
 
 // Coarse block of a layer that the fold handles: levels 3..J of layers up to 256 x 256 (level-2
 // block at most 64 x 64); a tile owns at most kFoldOwn of its coefficients.
@@ -371,26 +375,190 @@ __device__ __forceinline__ void band_of(int log2n, int J, int row, int col, int 
     o = (col >= m ? 1 : 0) + (row >= m ? 2 : 0);
 }
 
+// Levels kf+1..J of W x from the level-kf approximation sL (m0 x m0): the bands into the m0 x m0
+// block sW (Mallat positions), the LL chain through xl / xh (every thread of the workgroup).
+template <typename T>
+__device__ __forceinline__ void coarse_analysis(const T *sL, T *sW, T *xl, T *xh, int m0, int kf, int J, const Taps<T> &tp) {
+    const int tid = threadIdx.x;
+    const T *srcL = sL;
+    int mi = m0;
+    for (int s = kf + 1; s <= J; ++s) {
+        const int h = mi >> 1, msk = mi - 1, lh = __ffs(h) - 1;
+        T *dstL = ((s - kf) & 1) ? xl : xh;
+        auto put = [&](int r, int q, const T *w) {
+            sW[r * m0 + q + h] = w[1];
+            sW[(r + h) * m0 + q] = w[2];
+            sW[(r + h) * m0 + q + h] = w[3];
+            if (s == J) sW[r * m0 + q] = w[0];
+            else dstL[r * h + q] = w[0];
+        };
+        if (h * h > kWB) {
+            // 2 x 2 quads per item from one 8 x 8 input patch (each input value read once
+            // per item, not once per quad); per quad the same sums in the same order
+            const int hb = h >> 1, lhb = lh - 1;
+            for (int bi = tid; bi < hb * hb; bi += kWB) {
+                const int R = bi >> lhb, Q = bi & (hb - 1);
+                T w[2][2][4] = {};
+#pragma unroll
+                for (int rr = 0; rr < 8; ++rr) {
+                    const T *row = srcL + ((4 * R + rr) & msk) * mi;
+                    T xv[8];
+#pragma unroll
+                    for (int b = 0; b < 8; ++b) xv[b] = row[(4 * Q + b) & msk];
+                    T ax[2], dx[2];
+#pragma unroll
+                    for (int dc = 0; dc < 2; ++dc) {
+                        ax[dc] = 0;
+                        dx[dc] = 0;
+#pragma unroll
+                        for (int b = 0; b < 6; ++b) {
+                            ax[dc] += tp.h[b] * xv[2 * dc + b];
+                            dx[dc] += tp.g[b] * xv[2 * dc + b];
+                        }
+                    }
+#pragma unroll
+                    for (int dr = 0; dr < 2; ++dr) {
+                        const int a = rr - 2 * dr;
+                        if (a >= 0 && a < 6) {
+#pragma unroll
+                            for (int dc = 0; dc < 2; ++dc) {
+                                w[dr][dc][0] += tp.h[a] * ax[dc];
+                                w[dr][dc][2] += tp.g[a] * ax[dc];
+                                w[dr][dc][1] += tp.h[a] * dx[dc];
+                                w[dr][dc][3] += tp.g[a] * dx[dc];
+                            }
+                        }
+                    }
+                }
+#pragma unroll
+                for (int dr = 0; dr < 2; ++dr)
+#pragma unroll
+                    for (int dc = 0; dc < 2; ++dc) put(2 * R + dr, 2 * Q + dc, w[dr][dc]);
+            }
+        } else {
+            for (int qi = tid; qi < h * h; qi += kWB) {
+                const int r = qi >> lh, q = qi & (h - 1);
+                T w[4] = {0, 0, 0, 0};
+#pragma unroll
+                for (int a = 0; a < 6; ++a) {
+                    const T *row = srcL + ((2 * r + a) & msk) * mi;
+                    T ax = 0, dx = 0;
+#pragma unroll
+                    for (int b = 0; b < 6; ++b) {
+                        const T xv = row[(2 * q + b) & msk];
+                        ax += tp.h[b] * xv;
+                        dx += tp.g[b] * xv;
+                    }
+                    w[0] += tp.h[a] * ax;
+                    w[2] += tp.g[a] * ax;
+                    w[1] += tp.h[a] * dx;
+                    w[3] += tp.g[a] * dx;
+                }
+                put(r, q, w);
+            }
+        }
+        __syncthreads();
+        srcL = dstL;
+        mi = h;
+    }
+}
+
+// The last pass's coarse levels kf+1..J of the forward transform, for a solve whose earlier coarse
+// levels were folded (the fine transform of that pass stepped c there already, c + alpha p needing
+// no W x): workgroup t of the layer's F.parts recomputes W x of the layer's coarse block from the
+// level-kf approximation and, at its own part of the block, applies Alg. 2's p, q and r lines (in
+// the fold's arithmetic) and copies the right-hand side's coarse coefficients to b_prev.
+template <typename T>
+__device__ void coarse_tail(const SegTab &S, Bufs<T> B, const FoldArgs &F, const Taps<T> &tp, int J, int t, T *sL,
+                            T *sW, T *xl, T *xh, T *sJi, T *sAd) {
+    static_assert(sizeof(T) == 4, "the fold's arithmetic is FP32");
+    if (t >= S.nseg * F.parts) return;                  // padding workgroups
+    const int l = t / F.parts, part = t - l * F.parts;  // segment l of the inverse DWT's table is layer l
+    const int tid = threadIdx.x, n = S.n[l], kf = F.kf, m0 = n >> kf, lm = __ffs(m0) - 1, mm = m0 * m0;
+    const int per = mm / F.parts;                       // at most 4 kWB (checked by the host)
+    const long coff = S.off[l];
+    B = at_frame(B);
+    const long fc = blockIdx.y * B.fs_c;
+    const float *rin = static_cast<const float *>(F.rin) + fc;
+    const float *qin = F.qin ? static_cast<const float *>(F.qin) + fc : nullptr;
+    const float *bin = F.bsh ? static_cast<const float *>(F.bsh) + fc : nullptr;
+    // one round of loads: the approximation block, the tables, the step and this part's operands
+    const float *llin = reinterpret_cast<const float *>(B.ll + (coff >> (2 * kf)));
+#pragma unroll
+    for (int c = 0; c < kFoldM0 * kFoldM0 / (4 * kWB); ++c) {
+        const int k4 = tid + c * kWB;
+        if (4 * k4 < mm) g2lds16(llin + 4 * k4, reinterpret_cast<float *>(sL) + 4 * (c * kWB + (tid & ~63)));
+    }
+    const T jl = B.jinv[l * (J + 1) * 4 + min(tid, (J + 1) * 4 - 1)];
+    const T adv = B.ad[l * (J + 1) + min(tid, J)];
+    float o_r[4] = {}, o_q[4] = {}, o_p[4] = {}, o_b[4] = {};
+    long gi[4] = {};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int e = tid + i * kWB;
+        if (e < per) {
+            const int idx = part * per + e, row = idx >> lm, col = idx & (m0 - 1);
+            gi[i] = coff + (long)row * n + col;
+            o_r[i] = rin[gi[i]];
+            if (qin) o_q[i] = qin[gi[i]];
+            if (F.e >= 1) o_p[i] = B.p[gi[i]];
+            if (bin) o_b[i] = bin[gi[i]];
+        }
+    }
+    const StepOut so = read_step(B.sc);
+    if (tid < (J + 1) * 4) sJi[tid] = jl;
+    if (tid <= J) sAd[tid] = adv;
+    lds_fence();
+    coarse_analysis(sL, sW, xl, xh, m0, kf, J, tp);
+    const float al = (float)so.alpha, be = (float)so.beta;
+    const int log2n = __ffs(n) - 1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int e = tid + i * kWB;
+        if (e < per) {
+            const int idx = part * per + e, row = idx >> lm, col = idx & (m0 - 1);
+            int sl, ol;
+            band_of(log2n, J, row, col, sl, ol);
+            if (!so.stopped) {
+                const FoldNew u = fold_pcg(sW[row * m0 + col], o_r[i], 0.0f, o_p[i], o_q[i], sJi[sl * 4 + ol], sAd[sl],
+                                           al, be, F.e == 0);
+                B.p[gi[i]] = u.p;
+                B.q[gi[i]] = u.q;
+                B.r[gi[i]] = u.r;
+            }
+            if (bin) B.b_prev[gi[i]] = o_b[i];
+        }
+    }
+}
+
 template <typename T, int MODE>
 __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src, T *__restrict__ out, Bufs<T> B,
                                            Taps<T> tp, int J, FoldArgs F) {
-    constexpr bool FOLD = MODE == kWtFold && sizeof(T) == 4, PC = MODE != kWtPlain;
+    constexpr bool FOLD = MODE == kWtFold && sizeof(T) == 4, TAIL = MODE == kWtTail && sizeof(T) == 4;
+    constexpr bool PC = MODE == kWtPcg || MODE == kWtFold;
     __shared__ __attribute__((aligned(16))) T sCone[kWtSlots * kWB];
     __shared__ T sLL[2][kWtLL];
     __shared__ T sXl[kWtX], sXh[kWtX];
     __shared__ T sJi[(kMaxJ + 1) * 4];
     // fold: the level-2 approximation, the coarse coefficients of W x, the second operand (q or
     // b_prev) at the cone's coarse positions, and alpha D per level
-    __shared__ __attribute__((aligned(16))) T sLLb[FOLD ? kFoldM0 * kFoldM0 : 1];
-    __shared__ T sWb[FOLD ? kFoldM0 * kFoldM0 : 1];
+    __shared__ __attribute__((aligned(16))) T sLLb[FOLD || TAIL ? kFoldM0 * kFoldM0 : 1];
+    __shared__ T sWb[FOLD || TAIL ? kFoldM0 * kFoldM0 : 1];
     __shared__ T sCone2[FOLD ? (kMaxJ - 2) * kWB : 1];
-    __shared__ T sAd[FOLD ? kMaxJ + 1 : 1];
+    __shared__ T sAd[FOLD || TAIL ? kMaxJ + 1 : 1];
     __shared__ double sRed[2][FOLD ? kFoldOwn : 1];
 
+    if constexpr (TAIL) {
+        if ((int)blockIdx.x < F.ntail) {
+            coarse_tail<T>(S, B, F, tp, J, (int)blockIdx.x, sLLb, sWb, sXl, sXh, sJi, sAd);
+            return;
+        }
+    }
+    const int ntail = TAIL ? F.ntail : 0;  // tiles follow the tail workgroups (a multiple of 8 of them)
     src += blockIdx.y * B.fs_c;
     out += blockIdx.y * B.fs_c;
     const int tid = threadIdx.x;
-    const int tile = xcd_tile(S.chunk, gridDim.x);
+    const int tile = xcd_tile(S.chunk, (int)gridDim.x - ntail, (int)blockIdx.x - ntail);
     const TileId id = find_tile(S, tile);
     const int l = id.id, n = id.n, lt = id.lt;
     const int T0 = n < kWtTile ? n : kWtTile;
@@ -516,91 +684,7 @@ __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src,
     if (FOLD && tid <= J) sAd[tid] = adv;
     lds_fence();
     if constexpr (FOLD) {
-        // levels kf+1..J of W x from the level-kf approximation: bands into the m0 x m0 block sWb
-        // (Mallat positions), the LL chain through sXl / sXh
-        {
-            const T *srcL = sLLb;
-            int mi = m0;
-            for (int s = kf + 1; s <= J; ++s) {
-                const int h = mi >> 1, msk = mi - 1, lh = __ffs(h) - 1;
-                T *dstL = ((s - kf) & 1) ? sXl : sXh;
-                auto put = [&](int r, int q, const T *w) {
-                    sWb[r * m0 + q + h] = w[1];
-                    sWb[(r + h) * m0 + q] = w[2];
-                    sWb[(r + h) * m0 + q + h] = w[3];
-                    if (s == J) sWb[r * m0 + q] = w[0];
-                    else dstL[r * h + q] = w[0];
-                };
-                if (h * h > kWB) {
-                    // 2 x 2 quads per item from one 8 x 8 input patch (each input value read once
-                    // per item, not once per quad); per quad the same sums in the same order
-                    const int hb = h >> 1, lhb = lh - 1;
-                    for (int bi = tid; bi < hb * hb; bi += kWB) {
-                        const int R = bi >> lhb, Q = bi & (hb - 1);
-                        T w[2][2][4] = {};
-#pragma unroll
-                        for (int rr = 0; rr < 8; ++rr) {
-                            const T *row = srcL + ((4 * R + rr) & msk) * mi;
-                            T xv[8];
-#pragma unroll
-                            for (int b = 0; b < 8; ++b) xv[b] = row[(4 * Q + b) & msk];
-                            T ax[2], dx[2];
-#pragma unroll
-                            for (int dc = 0; dc < 2; ++dc) {
-                                ax[dc] = 0;
-                                dx[dc] = 0;
-#pragma unroll
-                                for (int b = 0; b < 6; ++b) {
-                                    ax[dc] += tp.h[b] * xv[2 * dc + b];
-                                    dx[dc] += tp.g[b] * xv[2 * dc + b];
-                                }
-                            }
-#pragma unroll
-                            for (int dr = 0; dr < 2; ++dr) {
-                                const int a = rr - 2 * dr;
-                                if (a >= 0 && a < 6) {
-#pragma unroll
-                                    for (int dc = 0; dc < 2; ++dc) {
-                                        w[dr][dc][0] += tp.h[a] * ax[dc];
-                                        w[dr][dc][2] += tp.g[a] * ax[dc];
-                                        w[dr][dc][1] += tp.h[a] * dx[dc];
-                                        w[dr][dc][3] += tp.g[a] * dx[dc];
-                                    }
-                                }
-                            }
-                        }
-#pragma unroll
-                        for (int dr = 0; dr < 2; ++dr)
-#pragma unroll
-                            for (int dc = 0; dc < 2; ++dc) put(2 * R + dr, 2 * Q + dc, w[dr][dc]);
-                    }
-                } else {
-                    for (int qi = tid; qi < h * h; qi += kWB) {
-                        const int r = qi >> lh, q = qi & (h - 1);
-                        T w[4] = {0, 0, 0, 0};
-#pragma unroll
-                        for (int a = 0; a < 6; ++a) {
-                            const T *row = srcL + ((2 * r + a) & msk) * mi;
-                            T ax = 0, dx = 0;
-#pragma unroll
-                            for (int b = 0; b < 6; ++b) {
-                                const T xv = row[(2 * q + b) & msk];
-                                ax += tp.h[b] * xv;
-                                dx += tp.g[b] * xv;
-                            }
-                            w[0] += tp.h[a] * ax;
-                            w[2] += tp.g[a] * ax;
-                            w[1] += tp.h[a] * dx;
-                            w[3] += tp.g[a] * dx;
-                        }
-                        put(r, q, w);
-                    }
-                }
-                __syncthreads();
-                srcL = dstL;
-                mi = h;
-            }
-        }
+        coarse_analysis(sLLb, sWb, sXl, sXh, m0, kf, J, tp);
         const StepOut so = fso;
         const float al = (float)so.alpha, be = (float)so.beta;
         const int log2n = __ffs(n) - 1;
@@ -1182,7 +1266,7 @@ __device__ __forceinline__ void epi_load(const Bufs<T> &B, const FwdArgs &E, lon
         op[0] = static_cast<const T *>(E.cin)[i];
     } else if constexpr (EPI == kEpiPcg) {
         op[0] = E.r_in ? static_cast<const T *>(E.r_in)[i] : B.r[i];
-        op[1] = static_cast<const T *>(E.c)[i];
+        op[1] = E.c ? static_cast<const T *>(E.c)[i] : (T)0;
         op[2] = E.k > 0 ? B.p[i] : (T)0;
         op[3] = E.k > 0 ? (E.q_in ? static_cast<const T *>(E.q_in)[i] : B.q[i]) : (T)0;
     } else if constexpr (EPI == kEpiRhs) {
@@ -1209,7 +1293,7 @@ __device__ __forceinline__ void epi_store(const Bufs<T> &B, const FwdArgs &E, lo
             const T q = E.k > 0 ? y + be * op[3] : y;
             B.p[i] = p;
             B.q[i] = q;
-            static_cast<T *>(E.c)[i] = op[1] + al * p;
+            if (E.c) static_cast<T *>(E.c)[i] = op[1] + al * p;
             rn = r - al * q;
             B.r[i] = rn;
         }
@@ -1311,10 +1395,36 @@ __global__ __launch_bounds__((FwdLanes<KF, TQ>::block)) void k_fwd(SegTab S, con
 #pragma unroll
         for (int o = 0; o < 4; ++o) ji[o] = B.jinv[(l * (J + 1) + s_own) * 4 + o];
     }
+    // last pass (cc set): this tile's share of the layer's coarse block of c, the level-KF
+    // positions of its TQ x TQ quads, stepped here (c + alpha p, p = z + beta p_old, z = J^-1 r
+    // needs no W x), so that the coarse levels' launch leaves c alone
+    T cr = 0, cp = 0, cv = 0, cj = 0;
+    long ci = 0;
+    bool cown = false;
+    if constexpr (EPI == kEpiPcg) {
+        cown = KF < J && E.cc != nullptr && tid < TQ * TQ;
+        if (cown) {
+            const int ry = qy + tid / TQ, rx = qx + tid % TQ;
+            int sl, ol;
+            band_of(__ffs(n) - 1, J, ry, rx, sl, ol);
+            ci = coff + (long)ry * n + rx;
+            cr = E.cc_r ? static_cast<const T *>(E.cc_r)[ci] : B.r[ci];
+            cp = E.k > 0 ? B.p[ci] : (T)0;
+            cv = static_cast<const T *>(E.cc)[ci];
+            cj = B.jinv[(l * (J + 1) + sl) * 4 + ol];
+        }
+    }
     StepOut so{0.0, 0.0, 0};
     if constexpr (EPI == kEpiPcg) so = read_step(B.sc);
     lds_fence();
 
+    if constexpr (EPI == kEpiPcg) {
+        if (cown && !so.stopped) {
+            const T z = cr * cj, al = (T)so.alpha, be = (T)so.beta;
+            const T p = E.k > 0 ? z + be * cp : z;
+            static_cast<T *>(E.cc)[ci] = cv + al * p;
+        }
+    }
     double rho = 0.0, dz = 0.0;  // (r, z), (z, alpha D z) of the residual written (pcg, rhs)
 #pragma unroll
     for (int s = 1; s <= KF; ++s) {
@@ -1427,7 +1537,7 @@ __global__ __launch_bounds__(kCB) void k_coarse(LayTab LT, Bufs<T> B, FwdArgs E,
         const int lm = __ffs(m0) - 1;
 #pragma unroll
         for (int j = 0; j < (NOP > 0 ? NOP : 1); ++j) {
-            if (j < nsrc) {
+            if (j < nsrc && srcs[j]) {  // (c is null when the fine transform stepped it)
                 if (sizeof(T) == 4 && m0 >= 4 && (reinterpret_cast<uintptr_t>(srcs[j]) & 15) == 0) {
                     // a 16-byte aligned operand (the workspace's always; the caller's when its
                     // vector is): 16-byte copies of four values of one row (rows of m0 >= 4 values
@@ -2029,6 +2139,17 @@ int Ops<T>::wt_fold(const T *r, T *out, const FoldArgs &F) const {
 }
 
 template <typename T>
+int Ops<T>::wt_tail(const T *c, T *out, const FoldArgs &F) const {
+    if (sizeof(T) != 4 || !P.fold || (P.lay.empty())) return FEWHA_ERR_UNSUPPORTED;
+    FoldArgs G = F;
+    G.kf = P.kf;
+    G.parts = kTailParts;
+    G.ntail = (P.nl * kTailParts + 7) & ~7;  // whole rounds of the eight XCDs
+    k_wt<T, kWtTail><<<dim3(G.ntail + (c ? P.n_wt : 0), nb), kWB, 0, st>>>(P.seg_wt, c, out, B, make_taps<T>(), P.J, G);
+    return check();
+}
+
+template <typename T>
 int Ops<T>::proj(const T *u, T *out, int mode) const {
     if (mode == kProjM)
         k_proj<T, kProjM><<<dim3(P.n_proj, nb), kB, 0, st>>>(P.seg_proj, P.laytab, inv_var_tab(P), pupil(P), u, out, nullptr, B, P.nl);
@@ -2083,14 +2204,15 @@ int fwd_waves(int kf, int tq) {
 
 template <typename T, int EPI>
 static int fwd_launch(const Plan &P, const Bufs<T> &B, hipStream_t st, int nb, const T *x, const FwdArgs &E,
-                      bool coarse) {
+                      bool fine, bool coarse) {
     const Taps<T> tp = make_taps<T>();
     const int nf = P.n_fwd;
     const int nfs = nf * fwd_waves(P.kf, P.tq);  // the fine tiles' partial slots (one per wave)
     FwdArgs Ef = E;  // the shadows of a folded solve concern the coarse levels only
     Ef.r_in = Ef.q_in = Ef.b_in = nullptr;
 #define FEWHA_FWD(KF, TQ) k_fwd<T, KF, TQ, EPI><<<dim3(nf, nb), (FwdLanes<KF, TQ>::block), 0, st>>>(P.seg_fwd, x, B, Ef, tp, P.J)
-    if (P.kf == 1) {
+    if (!fine) {
+    } else if (P.kf == 1) {
         switch (P.tq) {
             case 1: FEWHA_FWD(1, 1); break;
             case 2: FEWHA_FWD(1, 2); break;
@@ -2108,6 +2230,10 @@ static int fwd_launch(const Plan &P, const Bufs<T> &B, hipStream_t st, int nb, c
 #undef FEWHA_FWD
     if (int e = check()) return e;
     if (P.kf < P.J && coarse) {
+        FwdArgs Ec = E;  // c's coarse share, if any, is the fine transform's
+        if (E.cc) Ec.c = nullptr;
+        Ec.cc = nullptr;
+        Ec.cc_r = nullptr;
         size_t m = 0;
         for (auto &L : P.lay) m = (size_t)(L.n >> P.kf) > m ? (size_t)(L.n >> P.kf) : m;
         size_t base = (m * m + m * m / 4) * sizeof(T);
@@ -2118,21 +2244,21 @@ static int fwd_launch(const Plan &P, const Bufs<T> &B, hipStream_t st, int nb, c
         const int pre = !gin && EpiOps<EPI>::n > 0 && base + opb <= kCoarseLdsMax ? 1 : 0;
         const dim3 grid(P.nl, nb);
         const size_t lds = base + (pre ? opb : 0);
-        if (pre) k_coarse<T, EPI, kCoarseStaged><<<grid, kCB, lds, st>>>(P.laytab, B, E, tp, P.J, P.kf, nfs);
-        else if (gin) k_coarse<T, EPI, kCoarseGlobalIn><<<grid, kCB, lds, st>>>(P.laytab, B, E, tp, P.J, P.kf, nfs);
-        else k_coarse<T, EPI, kCoarseDirect><<<grid, kCB, lds, st>>>(P.laytab, B, E, tp, P.J, P.kf, nfs);
+        if (pre) k_coarse<T, EPI, kCoarseStaged><<<grid, kCB, lds, st>>>(P.laytab, B, Ec, tp, P.J, P.kf, nfs);
+        else if (gin) k_coarse<T, EPI, kCoarseGlobalIn><<<grid, kCB, lds, st>>>(P.laytab, B, Ec, tp, P.J, P.kf, nfs);
+        else k_coarse<T, EPI, kCoarseDirect><<<grid, kCB, lds, st>>>(P.laytab, B, Ec, tp, P.J, P.kf, nfs);
         if (int e = check()) return e;
     }
     return FEWHA_OK;
 }
 
 template <typename T>
-int Ops<T>::fwd(const T *x, const FwdArgs &E, int epi, bool coarse) const {
+int Ops<T>::fwd(const T *x, const FwdArgs &E, int epi, bool coarse, bool fine) const {
     switch (epi) {
-        case kEpiPlain: return fwd_launch<T, kEpiPlain>(P, B, st, nb, x, E, coarse);
-        case kEpiPrior: return fwd_launch<T, kEpiPrior>(P, B, st, nb, x, E, coarse);
-        case kEpiPcg: return fwd_launch<T, kEpiPcg>(P, B, st, nb, x, E, coarse);
-        default: return fwd_launch<T, kEpiRhs>(P, B, st, nb, x, E, coarse);
+        case kEpiPlain: return fwd_launch<T, kEpiPlain>(P, B, st, nb, x, E, fine, coarse);
+        case kEpiPrior: return fwd_launch<T, kEpiPrior>(P, B, st, nb, x, E, fine, coarse);
+        case kEpiPcg: return fwd_launch<T, kEpiPcg>(P, B, st, nb, x, E, fine, coarse);
+        default: return fwd_launch<T, kEpiRhs>(P, B, st, nb, x, E, fine, coarse);
     }
 }
 

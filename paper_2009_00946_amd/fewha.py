@@ -24,7 +24,7 @@ EXPORTS = ["fewha_plan_create", "fewha_workspace_bytes", "fewha_plan_bind", "few
            "fewha_apply_M_batch", "fewha_pcg_solve_batch", "fewha_fit_dm_batch", "fewha_last_status_batch",
            "fewha_pol_slopes", "fewha_fit_dm_closed", "fewha_pol_slopes_batch", "fewha_fit_dm_closed_batch",
            "fewha_fit_dm_ls", "fewha_cn2_gradient", "fewha_dwt_forward_noalloc", "fewha_stage_launch_batch",
-           "fewha_get_tuning", "fewha_set_tuning", "fewha_autotune"]
+           "fewha_get_tuning", "fewha_set_tuning", "fewha_autotune", "fewha_reconstruct", "fewha_reconstruct_batch"]
 
 
 class FewhaError(RuntimeError):
@@ -103,6 +103,9 @@ def load_library():
     L.fewha_cn2_gradient.argtypes = [vp, vp, vp, vp, vp]
     L.fewha_pcg_solve.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, vp]
     L.fewha_fit_dm.argtypes = [vp, vp, vp, ctypes.c_double, vp, vp]
+    L.fewha_reconstruct.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_double, vp, vp]
+    L.fewha_reconstruct_batch.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, ctypes.c_int, vp, vp,
+                                          ctypes.c_double, vp, vp]
     L.fewha_precond_table.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     L.fewha_last_status.argtypes = [vp]
     L.fewha_stage_launch.argtypes = [vp, ctypes.c_int, vp]
@@ -262,6 +265,21 @@ class Plan:
                "fewha_pcg_solve")
         return c
 
+    def reconstruct(self, s, c, n_iter, a_prev=None, gain=1.0, out=None, warm=True, resnorm=None, refresh=False):
+        """pcg_solve then fit_dm in one call (the last pass's coarse levels run beside the fit);
+        returns the actuator commands."""
+        rp = None
+        if resnorm is not None:
+            if not resnorm.is_cuda or resnorm.dtype != self._torch.float64 or resnorm.numel() < n_iter:
+                raise ValueError("resnorm: float64 CUDA tensor of n_iter elements expected")
+            rp = resnorm.data_ptr()
+        a = self._out(out, self.n_act)
+        ap = None if a_prev is None else self._arg(a_prev, self.n_act, "a_prev")
+        _check(_lib.fewha_reconstruct(self._h, self._arg(s, self.n_slopes, "s"), self._arg(c, self.n_coef, "c"),
+                                      int(n_iter), self._flags(warm, refresh), rp, ap, float(gain),
+                                      self._arg(a, self.n_act, "a"), self._stream()), "fewha_reconstruct")
+        return a
+
     def solve_M(self, b, c=None, n_iter=None, resnorm=None):
         """c = M^-1 b (n_iter cold PCG passes) for a wavelet-domain right-hand side; overwrites the
         warm-restart state."""
@@ -340,6 +358,28 @@ class Plan:
                                           self._flags(warm, refresh), rp, self._stream()),
                "fewha_pcg_solve_batch")
         return c
+
+    def reconstruct_batch(self, s, c, n_iter, a_prev=None, gain=1.0, out=None, warm=True, resnorm=None,
+                          refresh=False):
+        """pcg_solve_batch then fit_dm_batch in one call; returns the [nbatch][n_act] commands."""
+        nb = self._batch(s, self.n_slopes, "s")
+        if self._batch(c, self.n_coef, "c") != nb:
+            raise ValueError("s and c: different batch sizes")
+        rp = None
+        if resnorm is not None:
+            if not resnorm.is_cuda or resnorm.dtype != self._torch.float64 or resnorm.numel() < nb * n_iter:
+                raise ValueError("resnorm: float64 CUDA tensor of nbatch * n_iter elements expected")
+            rp = resnorm.data_ptr()
+        a = out if out is not None else self._torch.empty((nb, self.n_act), dtype=self.dtype, device=self.device)
+        self._batch(a, self.n_act, "a")
+        ap = None
+        if a_prev is not None:
+            self._batch(a_prev, self.n_act, "a_prev")
+            ap = a_prev.data_ptr()
+        _check(_lib.fewha_reconstruct_batch(self._h, nb, s.data_ptr(), c.data_ptr(), int(n_iter),
+                                            self._flags(warm, refresh), rp, ap, float(gain), a.data_ptr(),
+                                            self._stream()), "fewha_reconstruct_batch")
+        return a
 
     def fit_dm_batch(self, c, a_prev=None, gain=1.0, out=None):
         nb = self._batch(c, self.n_coef, "c")

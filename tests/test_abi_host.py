@@ -93,6 +93,8 @@ def test_unbound_plan_refuses_work(cfg_c0):
     assert L.fewha_apply_A(h, 1, 1, None) == -5
     assert L.fewha_pcg_solve(h, 1, 1, 4, 1, None, None) == -5
     assert L.fewha_fit_dm(h, 1, None, 1.0, 2, None) == -5
+    assert L.fewha_reconstruct(h, 1, 2, 4, 1, None, None, 1.0, 3, None) == -5
+    assert L.fewha_reconstruct_batch(h, 1, 1, 2, 4, 1, None, None, 1.0, 3, None) == -5
     assert L.fewha_last_status(h) == -5
     assert L.fewha_strerror(-6) == b"PCG breakdown (non-positive curvature)"
     L.fewha_plan_destroy(h)
