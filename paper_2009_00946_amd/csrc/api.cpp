@@ -436,8 +436,11 @@ int bind_tables(Plan &P, hipStream_t st) {
             P.seg_pt.rw[l] = rw < kRtabWidth ? rw : kRtabWidth;
         }
         if (stage > size_t(kPtStage)) P.rtab_ok = false;
-        // the tile's transpose pairs (index, weight) of every guide star, then the stage
-        P.pt_lds = size_t(P.nw) * 2 * kRtabWidth * kPtTile * (P.prec == FEWHA_FP64 ? 16 : 8) + stage * P.elem;
+        // the tile's transpose pairs (index, weight) of every guide star, at the widest layer's
+        // pair count, then the stage
+        P.pt_rw = 1;
+        for (int l = 0; l < P.nl; ++l) P.pt_rw = P.seg_pt.rw[l] > P.pt_rw ? P.seg_pt.rw[l] : P.pt_rw;
+        P.pt_lds = size_t(P.nw) * 2 * P.pt_rw * kPtTile * (P.prec == FEWHA_FP64 ? 16 : 8) + stage * P.elem;
     }
 
     // Preconditioner of Sec. 3.4: J = alpha D + tau per (layer, level, orientation), with tau the

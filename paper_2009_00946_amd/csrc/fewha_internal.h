@@ -196,6 +196,7 @@ struct Plan {
     int max_batch = 1;    // frames the workspace holds state for (same geometry, one launch per stage)
     size_t coarse_lds = 0;
     size_t pt_lds = 0;    // dynamic LDS of the staged P^T (node rectangles of every guide star)
+    int pt_rw = kRtabWidth;  // the widest transpose pair count of any layer (the pairs' LDS stride)
     std::vector<double> ad;     // alpha D per (layer, level)
     std::vector<double> jtab;   // alpha D + tau per (layer, level, orientation), after bind
 

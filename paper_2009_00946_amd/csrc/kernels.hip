@@ -1050,8 +1050,10 @@ __global__ __launch_bounds__(kB) void k_gt(SegTab S, InvVar IV, PupilArgs pa, co
 // -1, weight 0) and the clamps send them to the rectangle's first row / column, adding exact
 // zeros.  Only a guide star with no rectangle on this tile is skipped.
 template <typename T, int R>
-__device__ __forceinline__ T pt_sum(const RtabEnt<T> (*sP)[2][kRtabWidth][kPtTile], const T *sV, int nw, int a, int b,
+__device__ __forceinline__ T pt_sum(const RtabEnt<T> *sPairs, const T *sV, int nw, int a, int b,
                                     int pitch, int iA, int c0, int sbase) {
+    // the pairs of line idx, entry e, axis, guide star g at [((g * 2 + axis) * R + e) * 16 + idx]
+    const RtabEnt<T>(*sP)[2][R][kPtTile] = reinterpret_cast<const RtabEnt<T>(*)[2][R][kPtTile]>(sPairs);
     T acc = 0;
     for (int g = 0; g < nw; ++g) {
         const int pg = __builtin_amdgcn_readlane(pitch, g);
@@ -1081,14 +1083,15 @@ __device__ __forceinline__ T pt_sum(const RtabEnt<T> (*sP)[2][kRtabWidth][kPtTil
 
 template <typename T>
 __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restrict__ v, T *__restrict__ x, Bufs<T> B,
-                                           int nw, PassArgs PA) {
+                                           int nw, int prw, PassArgs PA) {
     constexpr int NT = kPtTile, RW = kRtabWidth, CH = 16 / sizeof(T);  // values per 16-byte chunk
     static_assert(NT == 16 && 2 * kPtMaxWfs * NT == 2 * kB, "line decode below assumes these sizes");
-    // dynamic LDS: the tile's (node, weight) pairs [g][axis][entry][line], then the staged node
-    // rectangles
+    // dynamic LDS: the tile's (node, weight) pairs [g][axis][entry][line] (entries: the plan's
+    // widest pair count prw, so that the stage leaves room for more workgroups per CU), then the
+    // staged node rectangles
     extern __shared__ char smem_raw[];
-    RtabEnt<T>(*sP)[2][RW][NT] = reinterpret_cast<RtabEnt<T>(*)[2][RW][NT]>(smem_raw);
-    T *sV = reinterpret_cast<T *>(smem_raw + sizeof(RtabEnt<T>) * 2 * RW * NT * nw);
+    RtabEnt<T> *sP = reinterpret_cast<RtabEnt<T> *>(smem_raw);
+    T *sV = reinterpret_cast<T *>(smem_raw + sizeof(RtabEnt<T>) * 2 * prw * NT * nw);
 
     B = at_frame(B);
     v += blockIdx.y * B.fs_v;
@@ -1138,7 +1141,7 @@ __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restr
         if (g < nw && idx < T0) {
 #pragma unroll
             for (int a = 0; a < RW; ++a)
-                if (a < rw) sP[g][axis][a][idx] = pe[c][a];
+                if (a < rw) sP[((g * 2 + axis) * rw + a) * NT + idx] = pe[c][a];
         }
     }
 
@@ -2178,7 +2181,7 @@ int Ops<T>::gt(const T *s, T *v, int mode) const {
 template <typename T>
 int Ops<T>::pt(const T *v, T *x, const PassArgs &PA) const {
     const dim3 grid(P.n_pt + (PA.k >= 0 ? 1 : 0), nb);
-    if (P.rtab_ok) k_pt<T><<<grid, kB, P.pt_lds, st>>>(P.seg_pt, wfs_off_tab(P), v, x, B, P.nw, PA);
+    if (P.rtab_ok) k_pt<T><<<grid, kB, P.pt_lds, st>>>(P.seg_pt, wfs_off_tab(P), v, x, B, P.nw, P.pt_rw, PA);
     else k_pt_scan<T><<<grid, kB, 0, st>>>(P.seg_pt, v, x, B, P.nl, P.nw, PA);
     return check();
 }
