@@ -48,6 +48,8 @@ constexpr int kMaxSeg = 64;
 struct SegTab {
     int nseg;
     int chunk;            // tiles per XCD chunk of the workgroup order (0: one contiguous run per XCD)
+    int ilv;              // 1: segments of equal tile counts interleaved, tile b being tile b / nseg of
+                          // segment b % nseg (sensor tiles over one pupil region run side by side)
     int start[kMaxSeg + 1];
     int off[kMaxSeg];     // element offset of the segment's array (layer c_off / sensor v_off)
     int aux[kMaxSeg];     // layers: first grid line in the per-axis line tables; sensors: s_off

@@ -83,6 +83,10 @@ __device__ __forceinline__ int xcd_tile(int K, int ntiles, int b) {
 __device__ __forceinline__ int xcd_tile(int K, int ntiles) { return xcd_tile(K, ntiles, (int)blockIdx.x); }
 
 __device__ __forceinline__ TileId find_tile(const SegTab &S, int b) {
+    if (S.ilv) {  // interleaved equal segments: tile b / nseg of segment b % nseg
+        const int s0 = b % S.nseg;
+        b = S.start[s0] + b / S.nseg;
+    }
     const int lane = threadIdx.x & 63;
     const int st = S.start[lane], of = S.off[lane], nn = S.n[lane], l2 = S.lt[lane], ax = S.aux[lane];
     const int rw = S.rw[lane], pi = S.pitch[lane], ix = S.id[lane];

@@ -419,6 +419,12 @@ int plan_create(const fewha_config *cfg, Plan **out) {
         P->n_proj += tpr * tpr;
     }
     P->seg_proj.start[P->nw] = P->n_proj;
+    // sensors of one tile count: interleave their tiles, so that the tiles over one pupil region
+    // (which read the same layer nodes) run side by side on the same XCD
+    P->seg_proj.ilv = 1;
+    for (int g = 1; g < P->nw; ++g)
+        if (P->seg_proj.start[g + 1] - P->seg_proj.start[g] != P->seg_proj.start[1] - P->seg_proj.start[0])
+            P->seg_proj.ilv = 0;
     for (int l = 0; l < P->nl; ++l) {
         P->laytab.off[l] = int(P->dlay[l].c_off);
         P->laytab.n[l] = P->lay[l].n;
