@@ -109,3 +109,52 @@ def test_reconstruct_batch_equals_solve_then_fit(name, prec, nb):
         torch.cuda.synchronize()
         assert PA.last_status_batch(nb) == [0] * nb
         assert torch.equal(cA, cB) and torch.equal(aA, aB) and torch.equal(rA, rB), t
+
+
+def _rel(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    assert np.all(np.isfinite(a))
+    return max(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300),
+               np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+# n_iter = 1 makes the last pass the first (no q or p before it: the coarse levels' first-pass
+# lines); 2 and 3 the short chains of the fold's shadow parities
+@pytest.mark.parametrize("name,prec,n_iter", [("c1_elt_mcao", "fp32", 1), ("c1_elt_mcao", "fp32", 2),
+                                               ("c3_mid_lgs", "fp32", 3), ("t1_mixed", "fp64", 1),
+                                               ("t1_mixed", "fp64", 2)])
+def test_reconstruct_short_solves_match_oracle(name, prec, n_iter):
+    """Warm chains of 1- to 3-pass frames through fewha_reconstruct against the oracle's frame and
+    fit (Alg. 1), and bitwise against fewha_pcg_solve then fewha_fit_dm."""
+    _need_gpu()
+    from oracle import Oracle
+    from paper_2009_00946_amd import fewha
+    cfg = synth.load_config(name)
+    O = Oracle(cfg)
+    gain = 0.6
+    tol_c, tol_l, tol_a = (1e-3, 1e-4, 1e-4) if prec == "fp32" else (1e-9, 1e-9, 1e-9)
+    PA, PB = fewha.Plan(cfg, precision=prec), fewha.Plan(cfg, precision=prec)
+    print("\n[short] %s %s n_iter=%d fold=%d" % (name, prec, n_iter, PA.get_tuning()["fold"]), flush=True)
+    N = O.n_coef
+    c_ref, bp, rp, a_ref = np.zeros(N), np.zeros(N), np.zeros(N), np.zeros(O.n_act)
+    cA, cB = PA.zeros(N), PB.zeros(N)
+    aA, aB = PA.zeros(PA.n_act), PB.zeros(PB.n_act)
+    for f in range(3):
+        s = O.Ahat(synth.layer_screens_flat(cfg, f)) + O.slope_mask() * synth.slope_noise(cfg, f)
+        c_ref, bp, rp, _, st = O.frame(s, c_ref, bp, rp, n_iter, f == 0)
+        a_ref = O.fit(c_ref, a_ref, gain)
+        sd = torch.as_tensor(s, dtype=PA.dtype, device=PA.device)
+        PA.reconstruct(sd, cA, n_iter, a_prev=aA, gain=gain, out=aA, warm=f > 0)
+        PB.pcg_solve(sd, cB, n_iter, warm=f > 0)
+        PB.fit_dm(cB, aB, gain, out=aB)
+        torch.cuda.synchronize()
+        assert st == 0 and PA.last_status() == 0
+        assert torch.equal(cA, cB) and torch.equal(aA, aB), "frame %d: reconstruct vs solve + fit" % f
+        for x, y in zip(PA.state_get(), PB.state_get()):
+            assert torch.equal(x, y), "frame %d: state" % f
+        c = cA.double().cpu().numpy()
+        assert _rel(c, c_ref) <= tol_c, ("c", f, _rel(c, c_ref))
+        assert _rel(PA.dwt_inverse(cA).double().cpu().numpy(), O.Wt(c_ref)) <= tol_l, ("layers", f)
+        assert _rel(aA.double().cpu().numpy(), a_ref) <= tol_a, ("actuators", f)
+        b_g, r_g = PA.state_get()
+        assert _rel(b_g.double().cpu().numpy(), bp) <= (1e-5 if prec == "fp32" else 1e-12), ("b_prev", f)
