@@ -145,7 +145,7 @@ int rhs_transform(const Plan &P, const Ops<T> &o, void *c, int cold, int n_iter)
 // the passes run, the coarse coefficients of r and q live in shadows by epilogue parity (epilogue
 // e writes r, q to shadow (e + 1) & 1 and reads shadow e & 1), because every tile of a layer reads
 // them at its cone while their owners write the new values; b's coarse coefficients wait in their
-// own shadow.  The last forward transform reads the shadows and leaves r, q, p, c and b_prev whole.
+// own shadow.  The last pass reads the shadows and leaves r, q, p, c and b_prev whole (last_fwd).
 // The last pass's coarse levels when the caller launches them (see last_fwd).
 struct Deferred {
     bool set = false;

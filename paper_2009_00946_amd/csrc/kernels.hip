@@ -22,6 +22,11 @@
 // + (z, alpha D z): W is orthonormal and every adjoint here is the exact transpose of its
 // forward operator, so this equals (y, z) without waiting for y, and the update of a pass can
 // run in the same launch that produces y.
+//
+// With the fold (k_wt<fold>) a pass's coarse levels run at the start of the next pass's inverse
+// DWT, so a pass is four launches; the last pass's coarse levels run in the tail workgroups of an
+// inverse-DWT launch (k_wt<tail>: beside the fit's W^T c in a whole frame), its step of c in the
+// fine transform.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
