@@ -265,28 +265,39 @@ def cpu_baseline(cfg, frames_s, n_iter, budget_s):
 
 # The batched uneven workload: 64 independent FP32 frames of three geometries, 4 PCG passes each,
 # warm chains.  Each geometry is one batched plan (one launch per stage over all its frames).
-C3_GROUPS = (("c0_tiny", 32, "all guide stars"), ("c3_mid_lgs", 24, "all guide stars"),
-             ("c1_elt_mcao", 8, "LGS only"))
+# (geometry, frames, guide stars, batched plans the frames are dealt to: one stream each)
+C3_GROUPS = (("c0_tiny", 32, "all guide stars", 1), ("c3_mid_lgs", 24, "all guide stars", 1),
+             ("c1_elt_mcao", 8, "LGS only", 2))
 
 
 def c3_configs():
+    """(configuration, frames) of every batched plan of the uneven mix: a geometry whose frames are
+    dealt to k plans contributes k entries (the ELT-LGS frames run as two 4-frame batches on two
+    streams: 0.620 -> 0.579 ms per 64 frames; more than four streams in all was slower)."""
     import copy
     from paper_2009_00946_amd import synth
     out = []
-    for name, count, which in C3_GROUPS:
+    for name, count, which, plans in C3_GROUPS:
         cfg = copy.deepcopy(synth.load_config(name + ("_lgs" if which == "LGS only" else "")))
         cfg["precision"], cfg["n_iter"], cfg["warm"] = "fp32", 4, True
-        out.append((cfg, count))
+        out += [(cfg, count // plans)] * plans
     return out
 
 
-def batch_slopes(P1, cfg, count):
-    """[count][n_slopes] seeded synthetic slopes (frozen-flow frames through the plan's own forward
-    operator, plus white noise), resident in HBM."""
+def c3_description():
+    return "c3_batched_uneven: " + ", ".join(
+        "%d x %s (%s%s)" % (count, name + ("_lgs" if which == "LGS only" else ""), which,
+                            ", %d plans of %d frames" % (plans, count // plans) if plans > 1 else "")
+        for name, count, which, plans in C3_GROUPS)
+
+
+def batch_slopes(P1, cfg, count, first=0):
+    """[count][n_slopes] seeded synthetic slopes (frozen-flow frames first .. first + count - 1
+    through the plan's own forward operator, plus white noise), resident in HBM."""
     import torch
     from paper_2009_00946_amd import synth
     S = []
-    for f in range(count):
+    for f in range(first, first + count):
         phi = torch.as_tensor(synth.layer_screens_flat(cfg, f), dtype=P1.dtype, device=P1.device)
         s = P1.apply_A(P1.dwt_forward(phi))
         s += torch.as_tensor(synth.slope_noise(cfg, f), dtype=P1.dtype, device=P1.device)
@@ -409,19 +420,23 @@ def batched_same_geometry(cfg, nb, steps, warmup, refresh=8, tuned=True):
 
 class UnevenMix:
     """The batched uneven workload: 64 FP32 frames of three geometries, 4 warm PCG passes and the
-    fit each; each geometry's frames in one batched plan (one launch per stage over all of them),
-    the three plans on streams of their own, forked and joined inside one HIP graph."""
+    fit each; each geometry's frames in batched plans (one launch per stage over all of a plan's
+    frames; the ELT-LGS frames in two plans), the plans on streams of their own, forked and joined
+    inside one HIP graph."""
 
     def __init__(self, with_single=False, tuned=True):
         import torch
         from paper_2009_00946_amd import fewha, tune
         self.groups = []
+        first = {}  # a geometry's plans take consecutive synthetic frames
         for cfg, count in c3_configs():
             PB = fewha.Plan(cfg, max_batch=count)
             if tuned:
                 tune.tuned(PB)
             P1 = fewha.Plan(cfg)
-            sb = batch_slopes(P1, cfg, count)
+            f0 = first.get(cfg["name"], 0)
+            first[cfg["name"]] = f0 + count
+            sb = batch_slopes(P1, cfg, count, f0)
             g = dict(cfg=cfg, count=count, PB=PB, sb=sb,
                      cb=torch.zeros((count, PB.n_coef), dtype=PB.dtype, device=PB.device),
                      ab=torch.zeros((count, PB.n_act), dtype=PB.dtype, device=PB.device))
@@ -467,7 +482,7 @@ class UnevenMix:
 
     def roofline(self):
         """The dominant single kernel of the mix: the largest launches-per-batch x duration over the
-        three plans' batched stage launches."""
+        plans' batched stage launches."""
         import torch
         best = None
         for g in self.groups:
@@ -490,11 +505,9 @@ def uneven_mix_summary(steps, warmup, refresh=8, tuned=True):
     ms = time_graphs([g_fresh] + [g_warm] * (refresh - 1), max(steps // 8, 2 * refresh), warmup)
     mix.check()
     gbps = mix.batch_bytes() / (ms * 1e-3) / 1e9
-    out = {"workload": "c3_batched_uneven: " + ", ".join(
-        "%d x %s (%s)" % (g["count"], g["cfg"]["name"], n) for g, (_, _, n) in zip(mix.groups, C3_GROUPS)),
-        "frames": mix.frames, "ms_per_batch": round(ms, 4), "us_per_frame": round(1e3 * ms / mix.frames, 2),
+    out = {"workload": c3_description(), "frames": mix.frames, "ms_per_batch": round(ms, 4), "us_per_frame": round(1e3 * ms / mix.frames, 2),
         "effective_GBps": round(gbps, 1), "frac_hbm_peak": round(gbps / HBM_PEAK_GBPS, 4),
-        "residual_refresh_every": refresh, "launch": "hip_graph_per_batch, one stream per geometry",
+        "residual_refresh_every": refresh, "launch": "hip_graph_per_batch, one stream per batched plan",
         "roofline": mix.roofline()}
     del mix, g_warm, g_fresh
     return out
@@ -522,10 +535,9 @@ def c3_batch(args):
         "value": round(ms_b, 5), "unit": "ms/batch", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_b, 5), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "c3_batched_uneven: " + ", ".join(
-            "%d x %s (%s)" % (g["count"], g["cfg"]["name"], n) for g, (_, _, n) in zip(mix.groups, C3_GROUPS)),
+        "config": {"workload": c3_description(),
             "n_iter": mix.n_iter, "warm": True, "frames": frames,
-            "launch": "hip_graph_per_batch, one stream per geometry"},
+            "launch": "hip_graph_per_batch, one stream per batched plan"},
         "ms_per_frame": round(ms_b / frames, 5),
         "bytes_per_batch": total_bytes,
         "effective_GBps": round(gbps, 1),
