@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "kernels.h"
+#include "trace.h"
 
 using namespace fewha;
 
@@ -180,7 +181,10 @@ int pcg_passes(const Plan &P, const Ops<T> &o, void *c, int n_iter, double *resn
     // partial sums of (r, z) and (z, alpha D z) come from the transforms that write r
     const int nres = residual_partials(P);
     const bool fold = P.fold && n_iter > 0;
+    static const char *const kPassName[] = {"PCG pass 0", "PCG pass 1", "PCG pass 2", "PCG pass 3",
+                                            "PCG pass 4", "PCG pass 5", "PCG pass 6", "PCG pass 7"};
     for (int k = 0; k < n_iter; ++k) {
+        trace::Range tr(k < 8 ? kPassName[k] : "PCG pass");
         if (fold) {
             FoldArgs F{};                        // the previous epilogue's coarse levels, then u
             F.e = k - 1;
@@ -219,6 +223,7 @@ int pcg_solve(const Plan &P, const void *s, void *c, int n_iter, int flags, doub
               int nb = 1, Deferred *defer = nullptr) {
     auto o = ops<T>(P, stream, nb);
     if (flags == FEWHA_REFRESH) {
+        trace::Range tr("residual refresh");
         // b_prev = M c and r_prev = 0, so that the residual update below gives r = b - M c (Alg. 1's
         // residual line in its left-hand form) instead of carrying the previous frame's residual
         FwdArgs E{};
@@ -231,10 +236,13 @@ int pcg_solve(const Plan &P, const void *s, void *c, int n_iter, int flags, doub
         TRY(o.fill(o.B.r, (long)P.n_coef * nb, 0));
     }
     // right-hand side b = W P^T Gamma^T C s, then the warm-restart residual update
-    TRY(o.gt(static_cast<const T *>(s), o.B.v, kGtRhs));
-    TRY(o.pt(o.B.v, o.B.x, PassArgs{-1, 0, 0, 0, nullptr, 0}));
     const int cold = flags == FEWHA_COLD ? 1 : 0;
-    TRY(rhs_transform<T>(P, o, c, cold, n_iter));
+    {
+        trace::Range tr("right-hand side");
+        TRY(o.gt(static_cast<const T *>(s), o.B.v, kGtRhs));
+        TRY(o.pt(o.B.v, o.B.x, PassArgs{-1, 0, 0, 0, nullptr, 0}));
+        TRY(rhs_transform<T>(P, o, c, cold, n_iter));
+    }
     return pcg_passes<T>(P, o, c, n_iter, resnorm, cold, defer);
 }
 
@@ -276,6 +284,7 @@ int reconstruct(const fewha_plan *h, const void *s, void *c, int n_iter, int fla
                 const void *a_prev, double gain, void *a, void *stream, int nb = 1) {
     Deferred d;
     TRY(pcg_solve<T>(h->p, s, c, n_iter, flags, resnorm, stream, nb, &d));
+    trace::Range tr("fit");
     if (!d.set) return fit_dm<T>(h->p, c, a_prev, gain, a, stream, nb);
     auto o = ops<T>(h->p, stream, nb);
     TRY(o.wt_tail(static_cast<const T *>(c), o.B.u, d.F));
@@ -498,6 +507,7 @@ int fewha_plan_create(const fewha_config *cfg, fewha_plan **out) {
 size_t fewha_workspace_bytes(const fewha_plan *p) { return p ? p->p.ws_bytes : 0; }
 
 int fewha_plan_bind(fewha_plan *p, void *d_workspace, size_t bytes, void *stream) {
+    trace::Range trace_call("fewha_plan_bind");
     if (!p || !d_workspace) return FEWHA_ERR_INVALID_ARG;
     Plan &P = p->p;
     if (bytes < P.ws_bytes || (reinterpret_cast<uintptr_t>(d_workspace) & 255)) return FEWHA_ERR_WORKSPACE;
@@ -527,12 +537,14 @@ int fewha_sizes(const fewha_plan *p, size_t *n_coef, size_t *n_slopes, size_t *n
 }
 
 int fewha_apply_A(const fewha_plan *p, const void *d_c, void *d_s, void *stream) {
+    trace::Range trace_call("fewha_apply_A");
     TRY(ready(p));
     if (!d_c || !d_s) return FEWHA_ERR_INVALID_ARG;
     return p->p.prec == FEWHA_FP64 ? apply_A<double>(p->p, d_c, d_s, stream) : apply_A<float>(p->p, d_c, d_s, stream);
 }
 
 int fewha_apply_At(const fewha_plan *p, const void *d_s, void *d_c, void *stream) {
+    trace::Range trace_call("fewha_apply_At");
     TRY(ready(p));
     if (!d_c || !d_s) return FEWHA_ERR_INVALID_ARG;
     return p->p.prec == FEWHA_FP64 ? apply_At<double>(p->p, d_s, d_c, stream)
@@ -540,12 +552,14 @@ int fewha_apply_At(const fewha_plan *p, const void *d_s, void *d_c, void *stream
 }
 
 int fewha_apply_M(const fewha_plan *p, const void *d_c, void *d_y, void *stream) {
+    trace::Range trace_call("fewha_apply_M");
     TRY(ready(p));
     if (!d_c || !d_y || d_c == d_y) return FEWHA_ERR_INVALID_ARG;
     return p->p.prec == FEWHA_FP64 ? apply_M<double>(p->p, d_c, d_y, stream) : apply_M<float>(p->p, d_c, d_y, stream);
 }
 
 int fewha_dwt_forward(const fewha_plan *p, const void *d_layers, void *d_c, void *stream) {
+    trace::Range trace_call("fewha_dwt_forward");
     TRY(ready(p));
     if (!d_layers || !d_c || d_layers == d_c) return FEWHA_ERR_INVALID_ARG;
     if (p->p.prec == FEWHA_FP64) {
@@ -561,6 +575,7 @@ int fewha_dwt_forward(const fewha_plan *p, const void *d_layers, void *d_c, void
 }
 
 int fewha_dwt_inverse(const fewha_plan *p, const void *d_c, void *d_layers, void *stream) {
+    trace::Range trace_call("fewha_dwt_inverse");
     TRY(ready(p));
     if (!d_layers || !d_c || d_layers == d_c) return FEWHA_ERR_INVALID_ARG;
     if (p->p.prec == FEWHA_FP64) {
@@ -573,6 +588,7 @@ int fewha_dwt_inverse(const fewha_plan *p, const void *d_c, void *d_layers, void
 
 int fewha_pcg_solve(fewha_plan *p, const void *d_s, void *d_c, int n_iter, int flags, double *d_resnorm,
                     void *stream) {
+    trace::Range trace_call("fewha_pcg_solve");
     TRY(ready(p));
     if (!d_s || !d_c || n_iter < 0 || (flags != FEWHA_COLD && flags != FEWHA_WARM && flags != FEWHA_REFRESH)) return FEWHA_ERR_INVALID_ARG;
     return p->p.prec == FEWHA_FP64 ? pcg_solve<double>(p->p, d_s, d_c, n_iter, flags, d_resnorm, stream)
@@ -580,6 +596,7 @@ int fewha_pcg_solve(fewha_plan *p, const void *d_s, void *d_c, int n_iter, int f
 }
 
 int fewha_solve_M(fewha_plan *p, const void *d_b, void *d_c, int n_iter, double *d_resnorm, void *stream) {
+    trace::Range trace_call("fewha_solve_M");
     TRY(ready(p));
     if (!d_b || !d_c || d_b == d_c || n_iter < 0) return FEWHA_ERR_INVALID_ARG;
     return p->p.prec == FEWHA_FP64 ? solve_M<double>(p->p, d_b, d_c, n_iter, d_resnorm, stream)
@@ -587,12 +604,14 @@ int fewha_solve_M(fewha_plan *p, const void *d_b, void *d_c, int n_iter, double 
 }
 
 int fewha_apply_CA(const fewha_plan *p, const void *d_c, void *d_s, void *stream) {
+    trace::Range trace_call("fewha_apply_CA");
     TRY(ready(p));
     if (!d_c || !d_s) return FEWHA_ERR_INVALID_ARG;
     return p->p.prec == FEWHA_FP64 ? apply_CA<double>(p->p, d_c, d_s, stream) : apply_CA<float>(p->p, d_c, d_s, stream);
 }
 
 int fewha_prior_dot(const fewha_plan *p, const void *d_x, const void *d_y, double *d_out, void *stream) {
+    trace::Range trace_call("fewha_prior_dot");
     TRY(ready(p));
     if (!d_x || !d_y || !d_out) return FEWHA_ERR_INVALID_ARG;
     return p->p.prec == FEWHA_FP64 ? prior_dot<double>(p->p, d_x, d_y, d_out, stream)
@@ -600,6 +619,7 @@ int fewha_prior_dot(const fewha_plan *p, const void *d_x, const void *d_y, doubl
 }
 
 int fewha_cn2_gradient(const fewha_plan *p, const void *d_lambda, const void *d_c, double *d_out, void *stream) {
+    trace::Range trace_call("fewha_cn2_gradient");
     TRY(ready(p));
     if (!d_lambda || !d_c || !d_out) return FEWHA_ERR_INVALID_ARG;
     return p->p.prec == FEWHA_FP64 ? prior_dot<double>(p->p, d_lambda, d_c, d_out, stream, true)
@@ -608,6 +628,7 @@ int fewha_cn2_gradient(const fewha_plan *p, const void *d_lambda, const void *d_
 
 int fewha_reconstruct(fewha_plan *p, const void *d_s, void *d_c, int n_iter, int flags, double *d_resnorm,
                       const void *d_a_prev, double gain, void *d_a, void *stream) {
+    trace::Range trace_call("fewha_reconstruct");
     TRY(ready(p));
     if (!d_s || !d_c || !d_a || d_a == d_c || d_a == d_s || n_iter < 0 || !std::isfinite(gain) ||
         (flags != FEWHA_COLD && flags != FEWHA_WARM && flags != FEWHA_REFRESH))
@@ -618,6 +639,7 @@ int fewha_reconstruct(fewha_plan *p, const void *d_s, void *d_c, int n_iter, int
 }
 
 int fewha_fit_dm(const fewha_plan *p, const void *d_c, const void *d_a_prev, double gain, void *d_a, void *stream) {
+    trace::Range trace_call("fewha_fit_dm");
     TRY(ready(p));
     if (!d_c || !d_a || d_a == d_c || !std::isfinite(gain)) return FEWHA_ERR_INVALID_ARG;
     return p->p.prec == FEWHA_FP64 ? fit_dm<double>(p->p, d_c, d_a_prev, gain, d_a, stream)
@@ -625,6 +647,7 @@ int fewha_fit_dm(const fewha_plan *p, const void *d_c, const void *d_a_prev, dou
 }
 
 int fewha_pol_slopes(const fewha_plan *p, const void *d_s, const void *d_a_m1, void *d_s_pol, void *stream) {
+    trace::Range trace_call("fewha_pol_slopes");
     TRY(ready(p));
     if (!d_s || !d_a_m1 || !d_s_pol || d_s_pol == d_a_m1) return FEWHA_ERR_INVALID_ARG;
     return p->p.prec == FEWHA_FP64 ? pol_slopes<double>(p->p, d_s, d_a_m1, d_s_pol, stream)
@@ -633,6 +656,7 @@ int fewha_pol_slopes(const fewha_plan *p, const void *d_s, const void *d_a_m1, v
 
 int fewha_fit_dm_closed(const fewha_plan *p, const void *d_c, const void *d_a0, const void *d_a_m1, double gain,
                         void *d_a, void *stream) {
+    trace::Range trace_call("fewha_fit_dm_closed");
     TRY(ready(p));
     if (!d_c || !d_a0 || !d_a_m1 || !d_a || d_a == d_c || d_a == d_a_m1 || !std::isfinite(gain))
         return FEWHA_ERR_INVALID_ARG;
@@ -642,6 +666,7 @@ int fewha_fit_dm_closed(const fewha_plan *p, const void *d_c, const void *d_a0, 
 
 int fewha_fit_dm_ls(const fewha_plan *p, const void *d_c, const void *d_a_prev, double gain, int n_cg, double eps,
                     void *d_a, void *stream) {
+    trace::Range trace_call("fewha_fit_dm_ls");
     TRY(ready(p));
     if (!d_c || !d_a || d_a == d_c || n_cg < 0 || !std::isfinite(gain) || !(eps >= 0) || !std::isfinite(eps))
         return FEWHA_ERR_INVALID_ARG;
@@ -671,6 +696,7 @@ static int batch_ok(const fewha_plan *p, int nbatch) {
 }
 
 int fewha_apply_A_batch(const fewha_plan *p, int nbatch, const void *d_c, void *d_s, void *stream) {
+    trace::Range trace_call("fewha_apply_A_batch");
     TRY(batch_ok(p, nbatch));
     if (!d_c || !d_s) return FEWHA_ERR_INVALID_ARG;
     return p->p.prec == FEWHA_FP64 ? apply_A<double>(p->p, d_c, d_s, stream, nbatch)
@@ -678,6 +704,7 @@ int fewha_apply_A_batch(const fewha_plan *p, int nbatch, const void *d_c, void *
 }
 
 int fewha_apply_At_batch(const fewha_plan *p, int nbatch, const void *d_s, void *d_c, void *stream) {
+    trace::Range trace_call("fewha_apply_At_batch");
     TRY(batch_ok(p, nbatch));
     if (!d_c || !d_s) return FEWHA_ERR_INVALID_ARG;
     return p->p.prec == FEWHA_FP64 ? apply_At<double>(p->p, d_s, d_c, stream, nbatch)
@@ -685,6 +712,7 @@ int fewha_apply_At_batch(const fewha_plan *p, int nbatch, const void *d_s, void 
 }
 
 int fewha_apply_M_batch(const fewha_plan *p, int nbatch, const void *d_c, void *d_y, void *stream) {
+    trace::Range trace_call("fewha_apply_M_batch");
     TRY(batch_ok(p, nbatch));
     if (!d_c || !d_y || d_c == d_y) return FEWHA_ERR_INVALID_ARG;
     return p->p.prec == FEWHA_FP64 ? apply_M<double>(p->p, d_c, d_y, stream, nbatch)
@@ -693,6 +721,7 @@ int fewha_apply_M_batch(const fewha_plan *p, int nbatch, const void *d_c, void *
 
 int fewha_pcg_solve_batch(fewha_plan *p, int nbatch, const void *d_s, void *d_c, int n_iter, int flags,
                           double *d_resnorm, void *stream) {
+    trace::Range trace_call("fewha_pcg_solve_batch");
     TRY(batch_ok(p, nbatch));
     if (!d_s || !d_c || n_iter < 0 || (flags != FEWHA_COLD && flags != FEWHA_WARM && flags != FEWHA_REFRESH)) return FEWHA_ERR_INVALID_ARG;
     return p->p.prec == FEWHA_FP64 ? pcg_solve<double>(p->p, d_s, d_c, n_iter, flags, d_resnorm, stream, nbatch)
@@ -701,6 +730,7 @@ int fewha_pcg_solve_batch(fewha_plan *p, int nbatch, const void *d_s, void *d_c,
 
 int fewha_reconstruct_batch(fewha_plan *p, int nbatch, const void *d_s, void *d_c, int n_iter, int flags,
                             double *d_resnorm, const void *d_a_prev, double gain, void *d_a, void *stream) {
+    trace::Range trace_call("fewha_reconstruct_batch");
     TRY(batch_ok(p, nbatch));
     if (!d_s || !d_c || !d_a || d_a == d_c || d_a == d_s || n_iter < 0 || !std::isfinite(gain) ||
         (flags != FEWHA_COLD && flags != FEWHA_WARM && flags != FEWHA_REFRESH))
@@ -712,6 +742,7 @@ int fewha_reconstruct_batch(fewha_plan *p, int nbatch, const void *d_s, void *d_
 
 int fewha_fit_dm_batch(const fewha_plan *p, int nbatch, const void *d_c, const void *d_a_prev, double gain,
                        void *d_a, void *stream) {
+    trace::Range trace_call("fewha_fit_dm_batch");
     TRY(batch_ok(p, nbatch));
     if (!d_c || !d_a || d_a == d_c || !std::isfinite(gain)) return FEWHA_ERR_INVALID_ARG;
     return p->p.prec == FEWHA_FP64 ? fit_dm<double>(p->p, d_c, d_a_prev, gain, d_a, stream, nbatch)
@@ -720,6 +751,7 @@ int fewha_fit_dm_batch(const fewha_plan *p, int nbatch, const void *d_c, const v
 
 int fewha_pol_slopes_batch(const fewha_plan *p, int nbatch, const void *d_s, const void *d_a_m1, void *d_s_pol,
                            void *stream) {
+    trace::Range trace_call("fewha_pol_slopes_batch");
     TRY(batch_ok(p, nbatch));
     if (!d_s || !d_a_m1 || !d_s_pol || d_s_pol == d_a_m1) return FEWHA_ERR_INVALID_ARG;
     return p->p.prec == FEWHA_FP64 ? pol_slopes<double>(p->p, d_s, d_a_m1, d_s_pol, stream, nbatch)
@@ -728,6 +760,7 @@ int fewha_pol_slopes_batch(const fewha_plan *p, int nbatch, const void *d_s, con
 
 int fewha_fit_dm_closed_batch(const fewha_plan *p, int nbatch, const void *d_c, const void *d_a0, const void *d_a_m1,
                               double gain, void *d_a, void *stream) {
+    trace::Range trace_call("fewha_fit_dm_closed_batch");
     TRY(batch_ok(p, nbatch));
     if (!d_c || !d_a0 || !d_a_m1 || !d_a || d_a == d_c || d_a == d_a_m1 || !std::isfinite(gain))
         return FEWHA_ERR_INVALID_ARG;
@@ -909,6 +942,7 @@ int autotune_on(fewha_plan *h, int nb, hipStream_t st, hipEvent_t e0, hipEvent_t
 extern "C" {
 
 int fewha_autotune(fewha_plan *p, int nbatch, fewha_tuning *h_best, double *h_us) {
+    trace::Range trace_call("fewha_autotune");
     TRY(batch_ok(p, nbatch));
     if (!h_best) return FEWHA_ERR_INVALID_ARG;
     hipStream_t st = nullptr;
@@ -937,6 +971,7 @@ int fewha_stage_launch_batch(const fewha_plan *p, int nbatch, int stage, void *s
 }
 
 int fewha_state_get(const fewha_plan *p, void *d_b_prev, void *d_r_prev, void *stream) {
+    trace::Range trace_call("fewha_state_get");
     TRY(ready(p));
     if (!d_b_prev || !d_r_prev) return FEWHA_ERR_INVALID_ARG;
     const long N = (long)p->p.n_coef;
@@ -951,6 +986,7 @@ int fewha_state_get(const fewha_plan *p, void *d_b_prev, void *d_r_prev, void *s
 }
 
 int fewha_state_set(fewha_plan *p, const void *d_b_prev, const void *d_r_prev, void *stream) {
+    trace::Range trace_call("fewha_state_set");
     TRY(ready(p));
     if (!d_b_prev || !d_r_prev) return FEWHA_ERR_INVALID_ARG;
     const long N = (long)p->p.n_coef;

@@ -214,3 +214,25 @@ def test_tuning_cache_key():
     lay = [dict(l) for l in cfg["layers"]]
     lay[0]["n"] = 512
     assert k != tune.geometry_key(dict(cfg, layers=lay), "fp32", 1, "dev")
+
+
+def test_trace_ranges_load_and_stay_balanced(tmp_path):
+    """FEWHA_TRACE=1: the roctx library is opened on the first range, and calls that return early
+    (an unbound plan) still close their ranges; results of host-only calls are unchanged."""
+    import subprocess
+    import sys
+    code = (
+        "import ctypes, sys\n"
+        "sys.path.insert(0, %r)\n"
+        "from paper_2009_00946_amd import fewha, synth\n"
+        "L = fewha.load_library()\n"
+        "h, st = fewha.create_host_plan(synth.load_config('c0_tiny'))\n"
+        "assert st == 0\n"
+        "assert L.fewha_pcg_solve(h, 1, 1, 4, 1, None, None) == -5\n"
+        "assert L.fewha_reconstruct(h, 1, 2, 4, 1, None, None, 1.0, 3, None) == -5\n"
+        "assert L.fewha_fit_dm(h, 1, None, 1.0, 2, None) == -5\n"
+        "L.fewha_plan_destroy(h)\n"
+        "print('ok')\n" % ROOT)
+    env = dict(os.environ, FEWHA_TRACE="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stderr[-2000:]
