@@ -384,92 +384,159 @@ __device__ __forceinline__ void band_of(int log2n, int J, int row, int col, int 
     o = (col >= m ? 1 : 0) + (row >= m ? 2 : 0);
 }
 
-// Levels kf+1..J of W x from the level-kf approximation sL (m0 x m0): the bands into the m0 x m0
-// block sW (Mallat positions), the LL chain through xl / xh (every thread of the workgroup).
-template <typename T>
-__device__ __forceinline__ void coarse_analysis(const T *sL, T *sW, T *xl, T *xh, int m0, int kf, int J, const Taps<T> &tp) {
+// One level of the forward DWT, in place on the MI x MI approximation at the top-left of sB (row
+// pitch P): afterwards that corner holds the next approximation (top-left MI/2 x MI/2) and the
+// level's three bands in Mallat position (x-high top-right, y-high bottom-left, HH bottom-right).
+// Separable and periodic: the x pass takes every row to its low and high halves, output j the
+// sum over b of tap[b] x[(2j + b) mod MI]; the y pass does the same down every column.  Products
+// are accumulated in tap order, so the result is one fixed function of the block.  Each pass
+// computes into registers, then (after a barrier) writes in place.  x pass: lane j of a row
+// group reads its six inputs as three aligned pairs (a row group's lanes cover contiguous words);
+// y pass: a lane owns a column and K consecutive outputs, sharing 2K + 4 input rows.
+template <int MI, int P>
+__device__ __forceinline__ void dwt_level_inplace(float *sB, const Taps<float> &tp) {
+    constexpr int H = MI / 2, N = MI * H;  // output pairs of one pass
+    constexpr int K = N > kWB ? N / kWB : 1, NT = N / K;
+    static_assert(N % K == 0 && H % K == 0 && NT <= kWB, "pass layout");
     const int tid = threadIdx.x;
-    const T *srcL = sL;
-    int mi = m0;
-    for (int s = kf + 1; s <= J; ++s) {
-        const int h = mi >> 1, msk = mi - 1, lh = __ffs(h) - 1;
-        T *dstL = ((s - kf) & 1) ? xl : xh;
-        auto put = [&](int r, int q, const T *w) {
-            sW[r * m0 + q + h] = w[1];
-            sW[(r + h) * m0 + q] = w[2];
-            sW[(r + h) * m0 + q + h] = w[3];
-            if (s == J) sW[r * m0 + q] = w[0];
-            else dstL[r * h + q] = w[0];
-        };
-        if (h * h > kWB) {
-            // 2 x 2 quads per item from one 8 x 8 input patch (each input value read once
-            // per item, not once per quad); per quad the same sums in the same order
-            const int hb = h >> 1, lhb = lh - 1;
-            for (int bi = tid; bi < hb * hb; bi += kWB) {
-                const int R = bi >> lhb, Q = bi & (hb - 1);
-                T w[2][2][4] = {};
+    const bool act = tid < NT;
+    float lo[K], hi[K];
+    {
+        const int j = tid % H, r0 = tid / H;
+        if (act) {
 #pragma unroll
-                for (int rr = 0; rr < 8; ++rr) {
-                    const T *row = srcL + ((4 * R + rr) & msk) * mi;
-                    T xv[8];
+            for (int k = 0; k < K; ++k) {
+                const float *row = sB + (r0 + k * (NT / H)) * P;
+                float x[6];
 #pragma unroll
-                    for (int b = 0; b < 8; ++b) xv[b] = row[(4 * Q + b) & msk];
-                    T ax[2], dx[2];
-#pragma unroll
-                    for (int dc = 0; dc < 2; ++dc) {
-                        ax[dc] = 0;
-                        dx[dc] = 0;
-#pragma unroll
-                        for (int b = 0; b < 6; ++b) {
-                            ax[dc] += tp.h[b] * xv[2 * dc + b];
-                            dx[dc] += tp.g[b] * xv[2 * dc + b];
-                        }
-                    }
-#pragma unroll
-                    for (int dr = 0; dr < 2; ++dr) {
-                        const int a = rr - 2 * dr;
-                        if (a >= 0 && a < 6) {
-#pragma unroll
-                            for (int dc = 0; dc < 2; ++dc) {
-                                w[dr][dc][0] += tp.h[a] * ax[dc];
-                                w[dr][dc][2] += tp.g[a] * ax[dc];
-                                w[dr][dc][1] += tp.h[a] * dx[dc];
-                                w[dr][dc][3] += tp.g[a] * dx[dc];
-                            }
-                        }
-                    }
+                for (int u = 0; u < 3; ++u) {
+                    const float2 v = *reinterpret_cast<const float2 *>(row + ((2 * j + 2 * u) & (MI - 1)));
+                    x[2 * u] = v.x;
+                    x[2 * u + 1] = v.y;
                 }
+                float l = 0, g = 0;
 #pragma unroll
-                for (int dr = 0; dr < 2; ++dr)
-#pragma unroll
-                    for (int dc = 0; dc < 2; ++dc) put(2 * R + dr, 2 * Q + dc, w[dr][dc]);
-            }
-        } else {
-            for (int qi = tid; qi < h * h; qi += kWB) {
-                const int r = qi >> lh, q = qi & (h - 1);
-                T w[4] = {0, 0, 0, 0};
-#pragma unroll
-                for (int a = 0; a < 6; ++a) {
-                    const T *row = srcL + ((2 * r + a) & msk) * mi;
-                    T ax = 0, dx = 0;
-#pragma unroll
-                    for (int b = 0; b < 6; ++b) {
-                        const T xv = row[(2 * q + b) & msk];
-                        ax += tp.h[b] * xv;
-                        dx += tp.g[b] * xv;
-                    }
-                    w[0] += tp.h[a] * ax;
-                    w[2] += tp.g[a] * ax;
-                    w[1] += tp.h[a] * dx;
-                    w[3] += tp.g[a] * dx;
+                for (int b = 0; b < 6; ++b) {
+                    l += tp.h[b] * x[b];
+                    g += tp.g[b] * x[b];
                 }
-                put(r, q, w);
+                lo[k] = l;
+                hi[k] = g;
             }
         }
         __syncthreads();
-        srcL = dstL;
-        mi = h;
+        if (act) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                float *row = sB + (r0 + k * (NT / H)) * P;
+                row[j] = lo[k];
+                row[j + H] = hi[k];
+            }
+        }
+        __syncthreads();
     }
+    {
+        const int c = tid % MI, i0 = K * (tid / MI);
+        if (act) {
+            float x[2 * K + 4];
+#pragma unroll
+            for (int a = 0; a < 2 * K + 4; ++a) x[a] = sB[((2 * i0 + a) & (MI - 1)) * P + c];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                float l = 0, g = 0;
+#pragma unroll
+                for (int a = 0; a < 6; ++a) {
+                    l += tp.h[a] * x[2 * k + a];
+                    g += tp.g[a] * x[2 * k + a];
+                }
+                lo[k] = l;
+                hi[k] = g;
+            }
+        }
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                sB[(i0 + k) * P + c] = lo[k];
+                sB[(i0 + k + H) * P + c] = hi[k];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// The same for an input of at most 16 x 16 (2^lmi rows, row pitch P), one output pair per lane.
+__device__ __forceinline__ void dwt_level_small(float *sB, int lmi, int P, const Taps<float> &tp) {
+    const int MI = 1 << lmi, H = MI >> 1, tid = threadIdx.x;
+    const bool act = tid < MI * H;
+    float lo = 0, hi = 0;
+    {
+        const int j = tid & (H - 1), r = tid >> (lmi - 1);
+        if (act) {
+            const float *row = sB + r * P;
+            float x[6];
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                const float2 v = *reinterpret_cast<const float2 *>(row + ((2 * j + 2 * u) & (MI - 1)));
+                x[2 * u] = v.x;
+                x[2 * u + 1] = v.y;
+            }
+#pragma unroll
+            for (int b = 0; b < 6; ++b) {
+                lo += tp.h[b] * x[b];
+                hi += tp.g[b] * x[b];
+            }
+        }
+        __syncthreads();
+        if (act) {
+            sB[r * P + j] = lo;
+            sB[r * P + j + H] = hi;
+        }
+        __syncthreads();
+    }
+    {
+        const int c = tid & (MI - 1), i = tid >> lmi;
+        lo = 0;
+        hi = 0;
+        if (act) {
+#pragma unroll
+            for (int a = 0; a < 6; ++a) {
+                const float x = sB[((2 * i + a) & (MI - 1)) * P + c];
+                lo += tp.h[a] * x;
+                hi += tp.g[a] * x;
+            }
+        }
+        __syncthreads();
+        if (act) {
+            sB[i * P + c] = lo;
+            sB[(i + H) * P + c] = hi;
+        }
+        __syncthreads();
+    }
+}
+
+// Levels kf+1..kf+nlev of W x, in place on the level-kf approximation sB (m0 x m0, pitch m0, at
+// most kFoldM0): afterwards sB holds the Mallat layout of those levels, the coarsest LL at (0, 0).
+// The 64- and 32-row levels have compile-time shapes (several output pairs per lane); every
+// smaller level runs the one runtime-shaped routine.
+__device__ __forceinline__ void coarse_analysis(float *sB, int m0, int nlev, const Taps<float> &tp) {
+    static_assert(kFoldM0 == 64, "compile-time levels for 64 and 32 rows");
+    int lmi = 31 - __clz(m0);
+    if (m0 == 64 && nlev > 0) {
+        dwt_level_inplace<64, 64>(sB, tp);
+        --nlev;
+        --lmi;
+        if (nlev > 0) {
+            dwt_level_inplace<32, 64>(sB, tp);
+            --nlev;
+            --lmi;
+        }
+    } else if (m0 == 32 && nlev > 0) {
+        dwt_level_inplace<32, 32>(sB, tp);
+        --nlev;
+        --lmi;
+    }
+    for (; nlev > 0 && lmi >= 1; --nlev, --lmi) dwt_level_small(sB, lmi, m0, tp);  // uniform trip count
 }
 
 // The last pass's coarse levels kf+1..J of the forward transform, for a solve whose earlier coarse
@@ -479,7 +546,7 @@ __device__ __forceinline__ void coarse_analysis(const T *sL, T *sW, T *xl, T *xh
 // the fold's arithmetic) and copies the right-hand side's coarse coefficients to b_prev.
 template <typename T>
 __device__ void coarse_tail(const SegTab &S, Bufs<T> B, const FoldArgs &F, const Taps<T> &tp, int J, int t, T *sL,
-                            T *sW, T *xl, T *xh, T *sJi, T *sAd) {
+                            T *sJi, T *sAd) {
     static_assert(sizeof(T) == 4, "the fold's arithmetic is FP32");
     if (t >= S.nseg * F.parts) return;                  // padding workgroups
     const int l = t / F.parts, part = t - l * F.parts;  // segment l of the inverse DWT's table is layer l
@@ -518,7 +585,7 @@ __device__ void coarse_tail(const SegTab &S, Bufs<T> B, const FoldArgs &F, const
     if (tid < (J + 1) * 4) sJi[tid] = jl;
     if (tid <= J) sAd[tid] = adv;
     lds_fence();
-    coarse_analysis(sL, sW, xl, xh, m0, kf, J, tp);
+    coarse_analysis(sL, m0, J - kf, tp);
     const float al = (float)so.alpha, be = (float)so.beta;
     const int log2n = __ffs(n) - 1;
 #pragma unroll
@@ -529,7 +596,7 @@ __device__ void coarse_tail(const SegTab &S, Bufs<T> B, const FoldArgs &F, const
             int sl, ol;
             band_of(log2n, J, row, col, sl, ol);
             if (!so.stopped) {
-                const FoldNew u = fold_pcg(sW[row * m0 + col], o_r[i], 0.0f, o_p[i], o_q[i], sJi[sl * 4 + ol], sAd[sl],
+                const FoldNew u = fold_pcg(sL[row * m0 + col], o_r[i], 0.0f, o_p[i], o_q[i], sJi[sl * 4 + ol], sAd[sl],
                                            al, be, F.e == 0);
                 B.p[gi[i]] = u.p;
                 B.q[gi[i]] = u.q;
@@ -546,20 +613,23 @@ __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src,
     constexpr bool FOLD = MODE == kWtFold && sizeof(T) == 4, TAIL = MODE == kWtTail && sizeof(T) == 4;
     constexpr bool PC = MODE == kWtPcg || MODE == kWtFold;
     __shared__ __attribute__((aligned(16))) T sCone[kWtSlots * kWB];
-    __shared__ T sLL[2][kWtLL];
-    __shared__ T sXl[kWtX], sXh[kWtX];
+    // synthesis regions: two LL buffers and the y-synthesis outputs.  Before the synthesis the
+    // fold keeps there the second operand (q or b_prev) at the cone's coarse positions.
+    __shared__ __attribute__((aligned(16))) T sSyn[2 * kWtLL + 2 * kWtX];
+    static_assert((kMaxJ - 2) * kWB <= 2 * kWtLL + 2 * kWtX, "cone operands fit the synthesis regions");
+    T (*const sLL)[kWtLL] = reinterpret_cast<T (*)[kWtLL]>(sSyn);
+    T *const sXl = sSyn + 2 * kWtLL, *const sXh = sXl + kWtX;
+    T *const sCone2 = sSyn;
     __shared__ T sJi[(kMaxJ + 1) * 4];
-    // fold: the level-2 approximation, the coarse coefficients of W x, the second operand (q or
-    // b_prev) at the cone's coarse positions, and alpha D per level
+    // fold: the level-2 approximation (transformed in place into the coarse coefficients of W x)
+    // and alpha D per level
     __shared__ __attribute__((aligned(16))) T sLLb[FOLD || TAIL ? kFoldM0 * kFoldM0 : 1];
-    __shared__ T sWb[FOLD || TAIL ? kFoldM0 * kFoldM0 : 1];
-    __shared__ T sCone2[FOLD ? (kMaxJ - 2) * kWB : 1];
     __shared__ T sAd[FOLD || TAIL ? kMaxJ + 1 : 1];
     __shared__ double sRed[2][FOLD ? kFoldOwn : 1];
 
     if constexpr (TAIL) {
         if ((int)blockIdx.x < F.ntail) {
-            coarse_tail<T>(S, B, F, tp, J, (int)blockIdx.x, sLLb, sWb, sXl, sXh, sJi, sAd);
+            coarse_tail<T>(S, B, F, tp, J, (int)blockIdx.x, sLLb, sJi, sAd);
             return;
         }
     }
@@ -693,7 +763,7 @@ __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src,
     if (FOLD && tid <= J) sAd[tid] = adv;
     lds_fence();
     if constexpr (FOLD) {
-        coarse_analysis(sLLb, sWb, sXl, sXh, m0, kf, J, tp);
+        coarse_analysis(sLLb, m0, J - kf, tp);
         const StepOut so = fso;
         const float al = (float)so.alpha, be = (float)so.beta;
         const int log2n = __ffs(n) - 1;
@@ -703,7 +773,7 @@ __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src,
             const int t = tid, orow = (id.loc >> lt) * sub + t / sub, ocol = (id.loc & ((1 << lt) - 1)) * sub + t % sub;
             int sl, ol;
             band_of(log2n, J, orow, ocol, sl, ol);
-            const float w = sWb[orow * m0 + ocol], ji = sJi[sl * 4 + ol], ad = sAd[sl];
+            const float w = sLLb[orow * m0 + ocol], ji = sJi[sl * 4 + ol], ad = sAd[sl];
             float rn;
             if (F.e < 0) {
                 rn = fold_rhs(w, o_b, o_r, F.cold);
@@ -741,7 +811,7 @@ __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src,
                     const int gr = ((loY[s] + r) & mk) + (o >= 2 ? m : 0);
                     const int gc = ((loX[s] + q) & mk) + ((o & 1) ? m : 0);
                     T *slot = sCone + wt_slot0(s) * kWB + tid;
-                    const float w = sWb[gr * m0 + gc], r0 = *slot, x2 = sCone2[(s - 3) * kWB + tid];
+                    const float w = sLLb[gr * m0 + gc], r0 = *slot, x2 = sCone2[(s - 3) * kWB + tid];
                     float rn;
                     if (F.e < 0) rn = fold_rhs(w, x2, r0, F.cold);
                     else if (so.stopped) rn = r0;
