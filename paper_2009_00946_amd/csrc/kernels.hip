@@ -1182,26 +1182,12 @@ __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restr
     }
     const int tid = threadIdx.x, lane = tid & 63;
     const int vt = xcd_tile(S.chunk, PA.k >= 0 ? (int)gridDim.x - 1 : (int)gridDim.x);
-    const TileId id = find_tile(S, vt);
-    const int n = id.n, lt = id.lt;
-    const int T0 = n < NT ? n : NT;
-    const int k0 = (id.loc >> lt) * T0, q0 = (id.loc & ((1 << lt) - 1)) * T0;
-    const int roff = id.aux, rw = id.rw;  // pairs per line on this layer (uniform)
 
-    // the first rw pairs of the transpose-table lines e = (g * 2 + axis) * 16 + idx, and the
-    // records (every lane loads; clamped indices stand in for lines the tile does not have)
-    RtabEnt<T> pe[2][RW];
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const int e = tid + c * kB, g = min(e >> 5, nw - 1), axis = (e >> 4) & 1, idx = min(e & 15, T0 - 1);
-        const RtabEnt<T> *rt = (axis ? B.yrtab : B.xrtab) + ((long)g * B.sum_n + roff + (axis ? k0 : q0) + idx) * RW;
-#pragma unroll
-        for (int a = 0; a < RW; ++a)
-            if (a < rw) pe[c][a] = rt[a];
-    }
     // lane g of every wave holds guide star g's record: node rows iA..iB, first staged column c0
     // (16-byte aligned), last column jB, pair counts, node grid offset / pitch, and the LDS
-    // offset / pitch of its staged rectangle
+    // offset / pitch of its staged rectangle.  The records are indexed by the tile number alone,
+    // so they (and the copies they drive) go out before the segment lookup, whose round trip
+    // then overlaps theirs.
     const int tg = min(lane, nw - 1);
     const int4 rec = B.rects[(long)vt * nw + tg];
     const int gv = WO.v_off[tg], gp = WO.vp[tg];
@@ -1214,15 +1200,6 @@ __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restr
         if (lane >= o) incl += t;
     }
     const int sbase = incl - sz;
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const int e = tid + c * kB, g = e >> 5, axis = (e >> 4) & 1, idx = e & 15;
-        if (g < nw && idx < T0) {
-#pragma unroll
-            for (int a = 0; a < RW; ++a)
-                if (a < rw) sP[((g * 2 + axis) * rw + a) * NT + idx] = pe[c][a];
-        }
-    }
 
     // node rectangles, one guide star after the other (the copies of all of them in flight)
     for (int g = 0; g < nw; ++g) {
@@ -1245,6 +1222,33 @@ __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restr
                     for (int e = 0; e < CH; ++e) sV[bg + it * CH + e] = src[e];
                 }
             }
+        }
+    }
+
+    const TileId id = find_tile(S, vt);
+    const int n = id.n, lt = id.lt;
+    const int T0 = n < NT ? n : NT;
+    const int k0 = (id.loc >> lt) * T0, q0 = (id.loc & ((1 << lt) - 1)) * T0;
+    const int roff = id.aux, rw = id.rw;  // pairs per line on this layer (uniform)
+
+    // the first rw pairs of the transpose-table lines e = (g * 2 + axis) * 16 + idx (every lane
+    // loads; clamped indices stand in for lines the tile does not have)
+    RtabEnt<T> pe[2][RW];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int e = tid + c * kB, g = min(e >> 5, nw - 1), axis = (e >> 4) & 1, idx = min(e & 15, T0 - 1);
+        const RtabEnt<T> *rt = (axis ? B.yrtab : B.xrtab) + ((long)g * B.sum_n + roff + (axis ? k0 : q0) + idx) * RW;
+#pragma unroll
+        for (int a = 0; a < RW; ++a)
+            if (a < rw) pe[c][a] = rt[a];
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int e = tid + c * kB, g = e >> 5, axis = (e >> 4) & 1, idx = e & 15;
+        if (g < nw && idx < T0) {
+#pragma unroll
+            for (int a = 0; a < RW; ++a)
+                if (a < rw) sP[((g * 2 + axis) * rw + a) * NT + idx] = pe[c][a];
         }
     }
     lds_fence();
