@@ -852,24 +852,34 @@ __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src,
             const T j1 = PC ? sJi[s * 4 + 1] : (T)1, j2 = PC ? sJi[s * 4 + 2] : (T)1, j3 = PC ? sJi[s * 4 + 3] : (T)1;
             if (s >= 3) {
                 // small coarse regions: both directions at once, one output per item (no barrier
-                // between the y and x passes)
+                // between the y and x passes): the y synthesis of the three input columns the
+                // output needs, in registers, then the x synthesis
                 T *dst = sLL[cur ^ 1];
                 for (int it = tid; it < (LYo << lpo); it += kWB) {
                     const int y = it >> lpo, xq = it & (PO - 1);
                     if (xq < LXo) {
                         const int py = y & 1, px = xq & 1, ky = (y >> 1) + dY, kx = (xq >> 1) + dX;
-                        T acc = 0;
+                        T cL[3], c1[3], c2[3], c3[3];
 #pragma unroll
                         for (int jy = 0; jy < 3; ++jy) {
                             const T hy = py ? tp.h[2 * jy + 1] : tp.h[2 * jy], gy = py ? tp.g[2 * jy + 1] : tp.g[2 * jy];
-                            const T cL = hy * jL, c1 = hy * j1, c2 = gy * j2, c3 = gy * j3;
-                            const int row = (ky - jy) * PB;
+                            cL[jy] = hy * jL;
+                            c1[jy] = hy * j1;
+                            c2[jy] = gy * j2;
+                            c3[jy] = gy * j3;
+                        }
+                        T acc = 0;
 #pragma unroll
-                            for (int jx = 0; jx < 3; ++jx) {
-                                const T hx = px ? tp.h[2 * jx + 1] : tp.h[2 * jx], gx = px ? tp.g[2 * jx + 1] : tp.g[2 * jx];
-                                const int o = row + kx - jx;
-                                acc += (cL * hx) * LLs[o] + (c1 * gx) * B1[o] + (c2 * hx) * B2[o] + (c3 * gx) * B3[o];
+                        for (int jx = 0; jx < 3; ++jx) {
+                            T xl = 0, xh = 0;  // x-low and x-high rows of column kx - jx
+#pragma unroll
+                            for (int jy = 0; jy < 3; ++jy) {
+                                const int o = (ky - jy) * PB + kx - jx;
+                                xl += cL[jy] * LLs[o] + c2[jy] * B2[o];
+                                xh += c1[jy] * B1[o] + c3[jy] * B3[o];
                             }
+                            const T hx = px ? tp.h[2 * jx + 1] : tp.h[2 * jx], gx = px ? tp.g[2 * jx + 1] : tp.g[2 * jx];
+                            acc += hx * xl + gx * xh;
                         }
                         dst[y * PO + xq] = acc;
                     }
