@@ -224,16 +224,17 @@ int pcg_solve(const Plan &P, const void *s, void *c, int n_iter, int flags, doub
     auto o = ops<T>(P, stream, nb);
     if (flags == FEWHA_REFRESH) {
         trace::Range tr("residual refresh");
-        // b_prev = M c and r_prev = 0, so that the residual update below gives r = b - M c (Alg. 1's
-        // residual line in its left-hand form) instead of carrying the previous frame's residual
+        // b_prev = M c and r_prev = 0 (written beside b_prev by the same epilogue), so that the
+        // residual update below gives r = b - M c (Alg. 1's residual line in its left-hand form)
+        // instead of carrying the previous frame's residual
         FwdArgs E{};
         E.out = o.B.b_prev;
         E.cin = c;
+        E.rzero = 1;
         TRY(o.wt(static_cast<const T *>(c), o.B.u));
         TRY(o.proj(o.B.u, o.B.v, kProjM));
         TRY(o.pt(o.B.v, o.B.x, PassArgs{-1, 0, 0, 0, nullptr, 0}));
         TRY(o.fwd(o.B.x, E, kEpiPrior));
-        TRY(o.fill(o.B.r, (long)P.n_coef * nb, 0));
     }
     // right-hand side b = W P^T Gamma^T C s, then the warm-restart residual update
     const int cold = flags == FEWHA_COLD ? 1 : 0;

@@ -13,6 +13,7 @@ struct FwdArgs {
     const void *cin;    // prior: c of y = W x + alpha D c
     void *c;            // pcg: iterate c (updated); rhs: caller's c (zeroed on a cold start)
     int cold;           // rhs: cold start
+    int rzero;          // prior: also set the plan's r to 0 at every coefficient written
     int k;              // pcg: pass index (0 = first pass: beta = 0, p = z, q = y)
     int publish;        // pcg: workgroup 0 stores the pass's scalar state (0 for stage timing)
     // pcg, coarse levels of a solve whose earlier coarse updates were folded into the inverse DWT:

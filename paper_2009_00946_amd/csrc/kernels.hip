@@ -1380,6 +1380,7 @@ __device__ __forceinline__ void epi_store(const Bufs<T> &B, const FwdArgs &E, lo
         static_cast<T *>(E.out)[i] = w;
     } else if constexpr (EPI == kEpiPrior) {
         static_cast<T *>(E.out)[i] = w + ad * op[0];
+        if (E.rzero) B.r[i] = 0;
     } else if constexpr (EPI == kEpiPcg) {
         T rn = op[0];
         if (!so.stopped) {
