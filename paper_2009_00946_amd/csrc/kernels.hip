@@ -317,6 +317,10 @@ constexpr int kWtSlots = 9 + 3 + (kMaxJ - 2);
 __host__ __device__ constexpr int wt_passes(int s) { return s == 1 ? 9 : (s == 2 ? 3 : 1); }
 __host__ __device__ constexpr int wt_lanes_log2(int s) { return s == 1 ? 5 : (s == 2 ? 4 : 3); }
 __host__ __device__ constexpr int wt_slot0(int s) { return s == 1 ? 0 : (s == 2 ? 9 : 12 + (s - 3)); }
+// Slots of a J-level cone, the launch's dynamic LDS: through level J's (a level-2 pass of 16-byte
+// copies spans four slots, so J <= 2 keeps 13), at most kWtSlots.
+__host__ __device__ constexpr int wt_slots(int J) { return J <= 2 ? 13 : J + 10; }
+static_assert(wt_slots(kMaxJ) == kWtSlots, "the cone of the deepest transform");
 
 // Asynchronous copy of one 4-byte value per active lane from global memory into LDS at
 // wave_base[lane] (lane = threadIdx.x & 63) without registers; complete at s_waitcnt vmcnt(0).
@@ -612,7 +616,9 @@ __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src,
                                            Taps<T> tp, int J, FoldArgs F) {
     constexpr bool FOLD = MODE == kWtFold && sizeof(T) == 4, TAIL = MODE == kWtTail && sizeof(T) == 4;
     constexpr bool PC = MODE == kWtPcg || MODE == kWtFold;
-    __shared__ __attribute__((aligned(16))) T sCone[kWtSlots * kWB];
+    // the cone: wt_slots(J) slots of kWB values, the launch's dynamic LDS
+    extern __shared__ __attribute__((aligned(16))) char wt_cone[];
+    T *const sCone = reinterpret_cast<T *>(wt_cone);
     // synthesis regions: two LL buffers and the y-synthesis outputs.  Before the synthesis the
     // fold keeps there the second operand (q or b_prev) at the cone's coarse positions.
     __shared__ __attribute__((aligned(16))) T sSyn[2 * kWtLL + 2 * kWtX];
@@ -2200,6 +2206,9 @@ PupilArgs pupil(const Plan &P) {
 // ---------------------------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------------------------
+// Dynamic LDS of an inverse-DWT launch: the cone of the plan's J levels.
+inline size_t wt_lds(const Plan &P) { return (size_t)wt_slots(P.J) * kWB * P.elem; }
+
 template <typename T>
 Taps<T> make_taps() {
     const double q = std::sqrt(10.0), p = std::sqrt(5.0 + 2.0 * std::sqrt(10.0)), s = 16.0 * std::sqrt(2.0);
@@ -2215,13 +2224,13 @@ Taps<T> make_taps() {
 
 template <typename T>
 int Ops<T>::wt(const T *c, T *out) const {
-    k_wt<T, kWtPlain><<<dim3(P.n_wt, nb), kWB, 0, st>>>(P.seg_wt, c, out, B, make_taps<T>(), P.J, FoldArgs{});
+    k_wt<T, kWtPlain><<<dim3(P.n_wt, nb), kWB, wt_lds(P), st>>>(P.seg_wt, c, out, B, make_taps<T>(), P.J, FoldArgs{});
     return check();
 }
 
 template <typename T>
 int Ops<T>::wt_pcg(const T *r, T *out) const {
-    k_wt<T, kWtPcg><<<dim3(P.n_wt, nb), kWB, 0, st>>>(P.seg_wt, r, out, B, make_taps<T>(), P.J, FoldArgs{});
+    k_wt<T, kWtPcg><<<dim3(P.n_wt, nb), kWB, wt_lds(P), st>>>(P.seg_wt, r, out, B, make_taps<T>(), P.J, FoldArgs{});
     return check();
 }
 
@@ -2231,7 +2240,7 @@ int Ops<T>::wt_fold(const T *r, T *out, const FoldArgs &F) const {
     FoldArgs G = F;
     G.kf = P.kf;
     G.nfine = P.n_fwd * fwd_waves(P.kf, P.tq);
-    k_wt<T, kWtFold><<<dim3(P.n_wt, nb), kWB, 0, st>>>(P.seg_wt, r, out, B, make_taps<T>(), P.J, G);
+    k_wt<T, kWtFold><<<dim3(P.n_wt, nb), kWB, wt_lds(P), st>>>(P.seg_wt, r, out, B, make_taps<T>(), P.J, G);
     return check();
 }
 
@@ -2242,7 +2251,7 @@ int Ops<T>::wt_tail(const T *c, T *out, const FoldArgs &F) const {
     G.kf = P.kf;
     G.parts = kTailParts;
     G.ntail = (P.nl * kTailParts + 7) & ~7;  // whole rounds of the eight XCDs
-    k_wt<T, kWtTail><<<dim3(G.ntail + (c ? P.n_wt : 0), nb), kWB, 0, st>>>(P.seg_wt, c, out, B, make_taps<T>(), P.J, G);
+    k_wt<T, kWtTail><<<dim3(G.ntail + (c ? P.n_wt : 0), nb), kWB, wt_lds(P), st>>>(P.seg_wt, c, out, B, make_taps<T>(), P.J, G);
     return check();
 }
 
