@@ -1141,32 +1141,30 @@ __global__ __launch_bounds__(kB) void k_gt(SegTab S, InvVar IV, PupilArgs pa, co
 
 // The sum of one lane over the guide stars with R pairs per line (R the layer's pair width, so
 // that the loops unroll): every R x R pair product of a guide star is summed without per-pair
-// conditions, so that its LDS reads issue together; pairs past a line's count are padding (index
-// -1, weight 0) and the clamps send them to the rectangle's first row / column, adding exact
-// zeros.  Only a guide star with no rectangle on this tile is skipped.
+// conditions, so that its LDS reads issue together.  The entries carry staged offsets (a row
+// entry the offset of its node row in the stage, a column entry its column within the row), so
+// that a product reads sV at the sum of the two; pairs past a line's count are padding (weight 0,
+// offset of the rectangle's first row / column), adding exact zeros.  Only a guide star with no
+// rectangle on this tile is skipped.
 template <typename T, int R>
-__device__ __forceinline__ T pt_sum(const RtabEnt<T> *sPairs, const T *sV, int nw, int a, int b,
-                                    int pitch, int iA, int c0, int sbase) {
+__device__ __forceinline__ T pt_sum(const RtabEnt<T> *sPairs, const T *sV, int nw, int a, int b, int pitch) {
     // the pairs of line idx, entry e, axis, guide star g at [((g * 2 + axis) * R + e) * 16 + idx]
     const RtabEnt<T>(*sP)[2][R][kPtTile] = reinterpret_cast<const RtabEnt<T>(*)[2][R][kPtTile]>(sPairs);
     T acc = 0;
     for (int g = 0; g < nw; ++g) {
-        const int pg = __builtin_amdgcn_readlane(pitch, g);
-        if (pg == 0) continue;
-        const int ra = __builtin_amdgcn_readlane(iA, g), cg = __builtin_amdgcn_readlane(c0, g);
-        const T *Vg = sV + __builtin_amdgcn_readlane(sbase, g) - ra * pg - cg;
+        if (__builtin_amdgcn_readlane(pitch, g) == 0) continue;
         int jx[R];
         T wx[R];
 #pragma unroll
         for (int e = 0; e < R; ++e) {
             const RtabEnt<T> p = sP[g][0][e][b];
-            jx[e] = max(p.idx, cg);
+            jx[e] = p.idx;
             wx[e] = p.w;
         }
 #pragma unroll
         for (int ea = 0; ea < R; ++ea) {
             const RtabEnt<T> p = sP[g][1][ea][a];
-            const T *Vr = Vg + max(p.idx, ra) * pg;
+            const T *Vr = sV + p.idx;
             T t = 0;
 #pragma unroll
             for (int eb = 0; eb < R; ++eb) t += wx[eb] * Vr[jx[eb]];
@@ -1258,13 +1256,20 @@ __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restr
         for (int a = 0; a < RW; ++a)
             if (a < rw) pe[c][a] = rt[a];
     }
+    // written with their staged offsets: a row entry sbase + (max(i, iA) - iA) pitch, a column
+    // entry max(j, c0) - c0, from guide star g's record (lane g of this wave)
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const int e = tid + c * kB, g = e >> 5, axis = (e >> 4) & 1, idx = e & 15;
+        const int ga = __shfl(iA, g, 64), gc = __shfl(c0, g, 64), gpt = __shfl(pitch, g, 64), gsb = __shfl(sbase, g, 64);
         if (g < nw && idx < T0) {
 #pragma unroll
             for (int a = 0; a < RW; ++a)
-                if (a < rw) sP[((g * 2 + axis) * rw + a) * NT + idx] = pe[c][a];
+                if (a < rw) {
+                    RtabEnt<T> p = pe[c][a];
+                    p.idx = axis ? gsb + (max(p.idx, ga) - ga) * gpt : max(p.idx, gc) - gc;
+                    sP[((g * 2 + axis) * rw + a) * NT + idx] = p;
+                }
         }
     }
     lds_fence();
@@ -1273,10 +1278,10 @@ __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restr
     if (a < T0 && b < T0) {
         T acc;
         switch (rw) {  // uniform over the workgroup
-            case 1: acc = pt_sum<T, 1>(sP, sV, nw, a, b, pitch, iA, c0, sbase); break;
-            case 2: acc = pt_sum<T, 2>(sP, sV, nw, a, b, pitch, iA, c0, sbase); break;
-            case 3: acc = pt_sum<T, 3>(sP, sV, nw, a, b, pitch, iA, c0, sbase); break;
-            default: acc = pt_sum<T, RW>(sP, sV, nw, a, b, pitch, iA, c0, sbase); break;
+            case 1: acc = pt_sum<T, 1>(sP, sV, nw, a, b, pitch); break;
+            case 2: acc = pt_sum<T, 2>(sP, sV, nw, a, b, pitch); break;
+            case 3: acc = pt_sum<T, 3>(sP, sV, nw, a, b, pitch); break;
+            default: acc = pt_sum<T, RW>(sP, sV, nw, a, b, pitch); break;
         }
         x[id.off + (long)(k0 + a) * n + q0 + b] = acc;
     }
