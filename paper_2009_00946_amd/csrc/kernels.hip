@@ -1174,17 +1174,19 @@ __device__ __forceinline__ T pt_sum(const RtabEnt<T> *sPairs, const T *sV, int n
     return acc;
 }
 
-template <typename T>
+// R: the plan's widest pair count (the launch's template argument): every layer's lines are read
+// with R entries, the ones past a line's count being the tables' padding (index -1, weight 0).
+template <typename T, int R>
 __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restrict__ v, T *__restrict__ x, Bufs<T> B,
-                                           int nw, int prw, PassArgs PA) {
+                                           int nw, PassArgs PA) {
     constexpr int NT = kPtTile, RW = kRtabWidth, CH = 16 / sizeof(T);  // values per 16-byte chunk
     static_assert(NT == 16 && 2 * kPtMaxWfs * NT == 2 * kB, "line decode below assumes these sizes");
-    // dynamic LDS: the tile's (node, weight) pairs [g][axis][entry][line] (entries: the plan's
-    // widest pair count prw, so that the stage leaves room for more workgroups per CU), then the
-    // staged node rectangles
+    static_assert(R >= 1 && R <= RW, "pair width");
+    // dynamic LDS: the tile's (node, weight) pairs [g][axis][entry][line], then the staged node
+    // rectangles
     extern __shared__ char smem_raw[];
     RtabEnt<T> *sP = reinterpret_cast<RtabEnt<T> *>(smem_raw);
-    T *sV = reinterpret_cast<T *>(smem_raw + sizeof(RtabEnt<T>) * 2 * prw * NT * nw);
+    T *sV = reinterpret_cast<T *>(smem_raw + sizeof(RtabEnt<T>) * 2 * R * NT * nw);
 
     B = at_frame(B);
     v += blockIdx.y * B.fs_v;
@@ -1215,8 +1217,11 @@ __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restr
     }
     const int sbase = incl - sz;
 
-    // node rectangles, one guide star after the other (the copies of all of them in flight)
-    for (int g = 0; g < nw; ++g) {
+    // node rectangles: wave w copies those of guide stars w, w + kB / 64, ... (the copies of all
+    // of them in flight); item it of guide star g (row it / chunks, 16-byte chunk it % chunks of
+    // the row) lands at sV + sbase_g + it CH
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    for (int g = wave; g < nw; g += kB / 64) {
         const int pg = __builtin_amdgcn_readlane(pitch, g);
         if (pg == 0) continue;
         const int ra = __builtin_amdgcn_readlane(iA, g), rb = __builtin_amdgcn_readlane(iB, g);
@@ -1224,13 +1229,13 @@ __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restr
         const int vg = __builtin_amdgcn_readlane(gv, g), vpg = __builtin_amdgcn_readlane(gp, g);
         const int chunks = pg / CH, items = (rb - ra + 1) * chunks;
         const float rch = 1.0f / (float)chunks;
-        for (int i0 = 0; i0 < items; i0 += kB) {
-            const int it = i0 + tid;
+        for (int i0 = 0; i0 < items; i0 += 64) {
+            const int it = i0 + lane;
             if (it < items) {
                 const int r = small_div(it, rch), c4 = it - r * chunks;
                 const T *src = v + vg + (long)(ra + r) * vpg + cg + c4 * CH;
                 if constexpr (sizeof(T) == 4) {
-                    g2lds16(src, sV + bg + (i0 + (tid & ~63)) * CH);
+                    g2lds16(src, sV + bg + i0 * CH);
                 } else {
 #pragma unroll
                     for (int e = 0; e < CH; ++e) sV[bg + it * CH + e] = src[e];
@@ -1243,18 +1248,17 @@ __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restr
     const int n = id.n, lt = id.lt;
     const int T0 = n < NT ? n : NT;
     const int k0 = (id.loc >> lt) * T0, q0 = (id.loc & ((1 << lt) - 1)) * T0;
-    const int roff = id.aux, rw = id.rw;  // pairs per line on this layer (uniform)
+    const int roff = id.aux;
 
-    // the first rw pairs of the transpose-table lines e = (g * 2 + axis) * 16 + idx (every lane
+    // the first R pairs of the transpose-table lines e = (g * 2 + axis) * 16 + idx (every lane
     // loads; clamped indices stand in for lines the tile does not have)
-    RtabEnt<T> pe[2][RW];
+    RtabEnt<T> pe[2][R];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const int e = tid + c * kB, g = min(e >> 5, nw - 1), axis = (e >> 4) & 1, idx = min(e & 15, T0 - 1);
         const RtabEnt<T> *rt = (axis ? B.yrtab : B.xrtab) + ((long)g * B.sum_n + roff + (axis ? k0 : q0) + idx) * RW;
 #pragma unroll
-        for (int a = 0; a < RW; ++a)
-            if (a < rw) pe[c][a] = rt[a];
+        for (int a = 0; a < R; ++a) pe[c][a] = rt[a];
     }
     // written with their staged offsets: a row entry sbase + (max(i, iA) - iA) pitch, a column
     // entry max(j, c0) - c0, from guide star g's record (lane g of this wave)
@@ -1264,26 +1268,18 @@ __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restr
         const int ga = __shfl(iA, g, 64), gc = __shfl(c0, g, 64), gpt = __shfl(pitch, g, 64), gsb = __shfl(sbase, g, 64);
         if (g < nw && idx < T0) {
 #pragma unroll
-            for (int a = 0; a < RW; ++a)
-                if (a < rw) {
-                    RtabEnt<T> p = pe[c][a];
-                    p.idx = axis ? gsb + (max(p.idx, ga) - ga) * gpt : max(p.idx, gc) - gc;
-                    sP[((g * 2 + axis) * rw + a) * NT + idx] = p;
-                }
+            for (int a = 0; a < R; ++a) {
+                RtabEnt<T> p = pe[c][a];
+                p.idx = axis ? gsb + (max(p.idx, ga) - ga) * gpt : max(p.idx, gc) - gc;
+                sP[((g * 2 + axis) * R + a) * NT + idx] = p;
+            }
         }
     }
     lds_fence();
 
     const int a = tid >> 4, b = tid & 15;
     if (a < T0 && b < T0) {
-        T acc;
-        switch (rw) {  // uniform over the workgroup
-            case 1: acc = pt_sum<T, 1>(sP, sV, nw, a, b, pitch); break;
-            case 2: acc = pt_sum<T, 2>(sP, sV, nw, a, b, pitch); break;
-            case 3: acc = pt_sum<T, 3>(sP, sV, nw, a, b, pitch); break;
-            default: acc = pt_sum<T, RW>(sP, sV, nw, a, b, pitch); break;
-        }
-        x[id.off + (long)(k0 + a) * n + q0 + b] = acc;
+        x[id.off + (long)(k0 + a) * n + q0 + b] = pt_sum<T, R>(sP, sV, nw, a, b, pitch);
     }
 }
 
@@ -2289,8 +2285,16 @@ int Ops<T>::gt(const T *s, T *v, int mode) const {
 template <typename T>
 int Ops<T>::pt(const T *v, T *x, const PassArgs &PA) const {
     const dim3 grid(P.n_pt + (PA.k >= 0 ? 1 : 0), nb);
-    if (P.rtab_ok) k_pt<T><<<grid, kB, P.pt_lds, st>>>(P.seg_pt, wfs_off_tab(P), v, x, B, P.nw, P.pt_rw, PA);
-    else k_pt_scan<T><<<grid, kB, 0, st>>>(P.seg_pt, v, x, B, P.nl, P.nw, PA);
+    if (!P.rtab_ok) {
+        k_pt_scan<T><<<grid, kB, 0, st>>>(P.seg_pt, v, x, B, P.nl, P.nw, PA);
+        return check();
+    }
+    switch (P.pt_rw) {  // the plan's widest pair count
+        case 1: k_pt<T, 1><<<grid, kB, P.pt_lds, st>>>(P.seg_pt, wfs_off_tab(P), v, x, B, P.nw, PA); break;
+        case 2: k_pt<T, 2><<<grid, kB, P.pt_lds, st>>>(P.seg_pt, wfs_off_tab(P), v, x, B, P.nw, PA); break;
+        case 3: k_pt<T, 3><<<grid, kB, P.pt_lds, st>>>(P.seg_pt, wfs_off_tab(P), v, x, B, P.nw, PA); break;
+        default: k_pt<T, kRtabWidth><<<grid, kB, P.pt_lds, st>>>(P.seg_pt, wfs_off_tab(P), v, x, B, P.nw, PA); break;
+    }
     return check();
 }
 
@@ -2386,8 +2390,11 @@ int Ops<T>::prepare() const {
             return FEWHA_ERR_UNSUPPORTED;
     // staged P^T: the tile's transpose pairs and node rectangles
     const int pt_max = (int)(kPtMaxWfs * 2 * kRtabWidth * kPtTile * sizeof(RtabEnt<T>) + kPtStage * sizeof(T));
-    if (hipFuncSetAttribute((const void *)k_pt<T>, hipFuncAttributeMaxDynamicSharedMemorySize, pt_max) != hipSuccess)
-        return FEWHA_ERR_UNSUPPORTED;
+    const void *pts[4] = {(const void *)k_pt<T, 1>, (const void *)k_pt<T, 2>, (const void *)k_pt<T, 3>,
+                          (const void *)k_pt<T, kRtabWidth>};
+    for (const void *f : pts)
+        if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, pt_max) != hipSuccess)
+            return FEWHA_ERR_UNSUPPORTED;
     return FEWHA_OK;
 }
 
