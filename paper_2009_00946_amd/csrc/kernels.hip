@@ -1146,10 +1146,11 @@ __global__ __launch_bounds__(kB) void k_gt(SegTab S, InvVar IV, PupilArgs pa, co
 // that a product reads sV at the sum of the two; pairs past a line's count are padding (weight 0,
 // offset of the rectangle's first row / column), adding exact zeros.  Only a guide star with no
 // rectangle on this tile is skipped.
-template <typename T, int R>
+template <typename T, int R, int RS>
 __device__ __forceinline__ T pt_sum(const RtabEnt<T> *sPairs, const T *sV, int nw, int a, int b, int pitch) {
-    // the pairs of line idx, entry e, axis, guide star g at [((g * 2 + axis) * R + e) * 16 + idx]
-    const RtabEnt<T>(*sP)[2][R][kPtTile] = reinterpret_cast<const RtabEnt<T>(*)[2][R][kPtTile]>(sPairs);
+    // the pairs of line idx, entry e, axis, guide star g at [((g * 2 + axis) * RS + e) * 16 + idx]
+    // (RS >= R entries stored per line; the first R are summed)
+    const RtabEnt<T>(*sP)[2][RS][kPtTile] = reinterpret_cast<const RtabEnt<T>(*)[2][RS][kPtTile]>(sPairs);
     T acc = 0;
     for (int g = 0; g < nw; ++g) {
         if (__builtin_amdgcn_readlane(pitch, g) == 0) continue;
@@ -1248,7 +1249,7 @@ __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restr
     const int n = id.n, lt = id.lt;
     const int T0 = n < NT ? n : NT;
     const int k0 = (id.loc >> lt) * T0, q0 = (id.loc & ((1 << lt) - 1)) * T0;
-    const int roff = id.aux;
+    const int roff = id.aux, rw = id.rw;  // this layer's pair count per line (at most R)
 
     // the first R pairs of the transpose-table lines e = (g * 2 + axis) * 16 + idx (every lane
     // loads; clamped indices stand in for lines the tile does not have)
@@ -1279,7 +1280,12 @@ __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restr
 
     const int a = tid >> 4, b = tid & 15;
     if (a < T0 && b < T0) {
-        x[id.off + (long)(k0 + a) * n + q0 + b] = pt_sum<T, R>(sP, sV, nw, a, b, pitch);
+        T acc;
+        if (R >= 2 && rw == 1) acc = pt_sum<T, 1, R>(sP, sV, nw, a, b, pitch);  // uniform over the workgroup
+        else if (R >= 3 && rw == 2) acc = pt_sum<T, (R >= 3 ? 2 : R), R>(sP, sV, nw, a, b, pitch);
+        else if (R >= 4 && rw == 3) acc = pt_sum<T, (R >= 4 ? 3 : R), R>(sP, sV, nw, a, b, pitch);
+        else acc = pt_sum<T, R, R>(sP, sV, nw, a, b, pitch);
+        x[id.off + (long)(k0 + a) * n + q0 + b] = acc;
     }
 }
 
