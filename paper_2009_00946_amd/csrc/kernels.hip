@@ -954,7 +954,7 @@ __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src,
 constexpr int kPR = kProjTile + 2;   // computed region edge (16)
 constexpr int kPS = kProjTile + 1;   // subaperture block edge (15)
 constexpr int kProjLch = 12;         // layers whose bilinear loads are in flight together
-constexpr int kProjEntSlots = (2 * kMaxLayers * kPR + kB - 1) / kB;
+constexpr int kProjEntFast = 2;     // entry slots of a lane whose loads are in flight together (16 layers)
 
 // kProjM: v = Gamma^T C Gamma P u with the partial sum C (Gamma P u)^2 (Kernel 2 of the paper);
 // kProjA: s = mask Gamma P u; kProjCA: s = C mask Gamma P u; kProjPol: s = mask (add + Gamma P u)
@@ -964,8 +964,12 @@ constexpr int kProjEntSlots = (2 * kMaxLayers * kPR + kB - 1) / kB;
 template <typename T, int MODE>
 __global__ __launch_bounds__(kB) void k_proj(SegTab S, LayTab LT, InvVar IV, PupilArgs pa, const T *__restrict__ u,
                                              T *__restrict__ out, const T *__restrict__ add, Bufs<T> B, int nl) {
-    __shared__ int sK[2][kMaxLayers][kPR];
-    __shared__ T sW0[2][kMaxLayers][kPR], sW1[2][kMaxLayers][kPR];
+    // the cell entries [axis][layer][line] (cell, weights), the launch's dynamic LDS for its nl
+    // layers (proj_lds)
+    extern __shared__ __attribute__((aligned(16))) char proj_ent[];
+    int *const sK = reinterpret_cast<int *>(proj_ent);
+    T *const sW0 = reinterpret_cast<T *>(proj_ent + sizeof(T) * 2 * nl * kPR);  // after sK, T-aligned
+    T *const sW1 = sW0 + 2 * nl * kPR;
     __shared__ T sPhi[kPR * kPR];
     __shared__ T sSx[kPS * kPS], sSy[kPS * kPS];
 
@@ -982,28 +986,30 @@ __global__ __launch_bounds__(kB) void k_proj(SegTab S, LayTab LT, InvVar IV, Pup
     const Ent<T> *__restrict__ xt = (MODE == kProjPol ? B.xdm : B.xtab) + (long)g * nl * B.maxnv;
     const Ent<T> *__restrict__ yt = (MODE == kProjPol ? B.ydm : B.ytab) + (long)g * nl * B.maxnv;
 
-    // cell entries of the region's rows and columns on every layer: e = (l * 2 + axis) * 16 + idx
+    // cell entries of the region's rows and columns on every layer: e = (l * 2 + axis) * 16 + idx,
+    // stored at [(axis * nl + l) * kPR + idx]; the first kProjEntFast slots of a lane load together
+    // (clamped indices stand in past the last entry), the rest (over 16 layers) one after another
     {
         const int ne = 2 * nl * kPR;
-        Ent<T> en[kProjEntSlots];
-#pragma unroll
-        for (int c = 0; c < kProjEntSlots; ++c) {
-            const int e = min(tid + c * kB, ne - 1);
+        auto entry = [&](int e) {
             const int l = e >> 5, axis = (e >> 4) & 1, idx = e & 15;
             int nd = (axis ? i0 : j0) - 1 + idx;
             nd = nd < 0 ? 0 : (nd > ns ? ns : nd);
-            en[c] = (axis ? yt : xt)[(long)l * B.maxnv + nd];
-        }
+            return (axis ? yt : xt)[(long)l * B.maxnv + nd];
+        };
+        auto store = [&](int e, const Ent<T> &en) {
+            const int l = e >> 5, axis = (e >> 4) & 1, idx = e & 15, at = (axis * nl + l) * kPR + idx;
+            sK[at] = en.k0;
+            sW0[at] = en.w0;
+            sW1[at] = en.w1;
+        };
+        Ent<T> en[kProjEntFast];
 #pragma unroll
-        for (int c = 0; c < kProjEntSlots; ++c) {
-            const int e = tid + c * kB;
-            if (c * kB < ne && e < ne) {
-                const int l = e >> 5, axis = (e >> 4) & 1, idx = e & 15;
-                sK[axis][l][idx] = en[c].k0;
-                sW0[axis][l][idx] = en[c].w0;
-                sW1[axis][l][idx] = en[c].w1;
-            }
-        }
+        for (int c = 0; c < kProjEntFast; ++c) en[c] = entry(min(tid + c * kB, ne - 1));
+#pragma unroll
+        for (int c = 0; c < kProjEntFast; ++c)
+            if (tid + c * kB < ne) store(tid + c * kB, en[c]);
+        for (int e = tid + kProjEntFast * kB; e < ne; e += kB) store(e, entry(e));
     }
     __syncthreads();
 
@@ -1017,7 +1023,7 @@ __global__ __launch_bounds__(kB) void k_proj(SegTab S, LayTab LT, InvVar IV, Pup
         for (int c = 0; c < kProjLch; ++c) {
             const int l = min(l0 + c, nl - 1);  // layers past the last reload it (dropped below)
             const int n = __builtin_amdgcn_readlane(lay_n, l);
-            const T *U = u + __builtin_amdgcn_readlane(lay_off, l) + (long)sK[1][l][a] * n + sK[0][l][b];
+            const T *U = u + __builtin_amdgcn_readlane(lay_off, l) + (long)sK[(nl + l) * kPR + a] * n + sK[l * kPR + b];
             uv[c][0] = U[0];
             uv[c][1] = U[1];
             uv[c][2] = U[n];
@@ -1030,7 +1036,8 @@ __global__ __launch_bounds__(kB) void k_proj(SegTab S, LayTab LT, InvVar IV, Pup
         for (int c = 0; c < kProjLch; ++c) {
             const int l = min(l0 + c, nl - 1);
             const T keep = l0 + c < nl ? (T)1 : (T)0;
-            const T wy0 = sW0[1][l][a] * keep, wy1 = sW1[1][l][a] * keep, wx0 = sW0[0][l][b], wx1 = sW1[0][l][b];
+            const T wy0 = sW0[(nl + l) * kPR + a] * keep, wy1 = sW1[(nl + l) * kPR + a] * keep, wx0 = sW0[l * kPR + b],
+                    wx1 = sW1[l * kPR + b];
             phi += (wy0 * wx0) * uv[c][0] + (wy0 * wx1) * uv[c][1] + (wy1 * wx0) * uv[c][2] +
                    (wy1 * wx1) * uv[c][3];  // (garbage on rows outside the grid: sPhi drops it)
         }
@@ -2262,21 +2269,28 @@ int Ops<T>::wt_tail(const T *c, T *out, const FoldArgs &F) const {
     return check();
 }
 
+// Dynamic LDS of a projection launch over nl layers (or DMs): its cell entries.
+template <typename T>
+inline size_t proj_lds(int nl) { return (size_t)2 * nl * kPR * (sizeof(T) + 2 * sizeof(T)); }
+
 template <typename T>
 int Ops<T>::proj(const T *u, T *out, int mode) const {
     if (mode == kProjM)
-        k_proj<T, kProjM><<<dim3(P.n_proj, nb), kB, 0, st>>>(P.seg_proj, P.laytab, inv_var_tab(P), pupil(P), u, out, nullptr, B, P.nl);
+        k_proj<T, kProjM><<<dim3(P.n_proj, nb), kB, proj_lds<T>(P.nl), st>>>(P.seg_proj, P.laytab, inv_var_tab(P), pupil(P), u, out, nullptr, B,
+                                                                          P.nl);
     else if (mode == kProjCA)
-        k_proj<T, kProjCA><<<dim3(P.n_proj, nb), kB, 0, st>>>(P.seg_proj, P.laytab, inv_var_tab(P), pupil(P), u, out, nullptr, B, P.nl);
+        k_proj<T, kProjCA><<<dim3(P.n_proj, nb), kB, proj_lds<T>(P.nl), st>>>(P.seg_proj, P.laytab, inv_var_tab(P), pupil(P), u, out, nullptr, B,
+                                                                          P.nl);
     else
-        k_proj<T, kProjA><<<dim3(P.n_proj, nb), kB, 0, st>>>(P.seg_proj, P.laytab, inv_var_tab(P), pupil(P), u, out, nullptr, B, P.nl);
+        k_proj<T, kProjA><<<dim3(P.n_proj, nb), kB, proj_lds<T>(P.nl), st>>>(P.seg_proj, P.laytab, inv_var_tab(P), pupil(P), u, out, nullptr, B,
+                                                                          P.nl);
     return check();
 }
 
 template <typename T>
 int Ops<T>::pol(const T *a_m1, const T *s, T *s_pol) const {
-    k_proj<T, kProjPol><<<dim3(P.n_proj, nb), kB, 0, st>>>(P.seg_proj, P.dmtab, inv_var_tab(P), pupil(P), a_m1, s_pol, s,
-                                                           B, P.nd);
+    k_proj<T, kProjPol><<<dim3(P.n_proj, nb), kB, proj_lds<T>(P.nd), st>>>(P.seg_proj, P.dmtab, inv_var_tab(P), pupil(P),
+                                                                           a_m1, s_pol, s, B, P.nd);
     return check();
 }
 
