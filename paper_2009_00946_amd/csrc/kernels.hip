@@ -611,26 +611,27 @@ __device__ void coarse_tail(const SegTab &S, Bufs<T> B, const FoldArgs &F, const
     }
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, int JM>
 __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src, T *__restrict__ out, Bufs<T> B,
                                            Taps<T> tp, int J, FoldArgs F) {
     constexpr bool FOLD = MODE == kWtFold && sizeof(T) == 4, TAIL = MODE == kWtTail && sizeof(T) == 4;
     constexpr bool PC = MODE == kWtPcg || MODE == kWtFold;
+    static_assert(JM >= 3 && JM <= kMaxJ, "level bound of the unrolled loops and cone registers");
     // the cone: wt_slots(J) slots of kWB values, the launch's dynamic LDS
     extern __shared__ __attribute__((aligned(16))) char wt_cone[];
     T *const sCone = reinterpret_cast<T *>(wt_cone);
     // synthesis regions: two LL buffers and the y-synthesis outputs.  Before the synthesis the
     // fold keeps there the second operand (q or b_prev) at the cone's coarse positions.
     __shared__ __attribute__((aligned(16))) T sSyn[2 * kWtLL + 2 * kWtX];
-    static_assert((kMaxJ - 2) * kWB <= 2 * kWtLL + 2 * kWtX, "cone operands fit the synthesis regions");
+    static_assert((JM - 2) * kWB <= 2 * kWtLL + 2 * kWtX, "cone operands fit the synthesis regions");
     T (*const sLL)[kWtLL] = reinterpret_cast<T (*)[kWtLL]>(sSyn);
     T *const sXl = sSyn + 2 * kWtLL, *const sXh = sXl + kWtX;
     T *const sCone2 = sSyn;
-    __shared__ T sJi[(kMaxJ + 1) * 4];
+    __shared__ T sJi[(JM + 1) * 4];
     // fold: the level-2 approximation (transformed in place into the coarse coefficients of W x)
     // and alpha D per level
     __shared__ __attribute__((aligned(16))) T sLLb[FOLD || TAIL ? kFoldM0 * kFoldM0 : 1];
-    __shared__ T sAd[FOLD || TAIL ? kMaxJ + 1 : 1];
+    __shared__ T sAd[FOLD || TAIL ? JM + 1 : 1];
     __shared__ double sRed[2][FOLD ? kFoldOwn : 1];
 
     if constexpr (TAIL) {
@@ -651,7 +652,7 @@ __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src,
     const long coff = id.off;
 
     // cone bounds (uniform; compile-time indexed, so they stay in scalar registers)
-    int loY[kMaxJ + 1], loX[kMaxJ + 1], LY[kMaxJ + 1], LX[kMaxJ + 1];
+    int loY[JM + 1], loX[JM + 1], LY[JM + 1], LX[JM + 1];
     {
         int ly = y0, hy = y0 + T0 - 1, lx = x0, hx = x0 + T0 - 1;
         loY[0] = ly;
@@ -659,7 +660,7 @@ __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src,
         LY[0] = T0;
         LX[0] = T0;
 #pragma unroll
-        for (int s = 1; s <= kMaxJ; ++s) {
+        for (int s = 1; s <= JM; ++s) {
             ly = ((ly >> 1) - 2) & ~1;
             hy >>= 1;
             lx = ((lx >> 1) - 2) & (s == 1 ? ~3 : ~1);  // level 1 starts on a multiple of 4 (16-byte copies)
@@ -724,7 +725,7 @@ __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src,
     // the next level's slots.
     const bool src16 = sizeof(T) == 4 && (reinterpret_cast<uintptr_t>(src) & 15) == 0;
 #pragma unroll
-    for (int s = 1; s <= kMaxJ; ++s) {
+    for (int s = 1; s <= JM; ++s) {
         if (s <= J) {
             const int lp = wt_lanes_log2(s), ly = LY[s], lx = LX[s], m = n >> s, mk = m - 1;
             if (s <= 2 && src16 && m >= 4 && (loX[s] & 3) == 0) {
@@ -806,7 +807,7 @@ __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src,
         }
         // the cone's coarse coefficients: r after the update, recomputed exactly as its owner does
 #pragma unroll
-        for (int s = 3; s <= kMaxJ; ++s) {  // compile-time level index: the cone bounds stay in registers
+        for (int s = 3; s <= JM; ++s) {  // compile-time level index: the cone bounds stay in registers
             if (s <= J && s > kf) {
                 constexpr int lp = 3;
                 const int ly = LY[s], lx = LX[s], m = n >> s, mk = m - 1;
@@ -846,7 +847,7 @@ __global__ __launch_bounds__(kWB) void k_wt(SegTab S, const T *__restrict__ src,
     // are applied as the values are read (the synthesized LL below J is z-space already). ----
     int cur = 0;
 #pragma unroll
-    for (int s = kMaxJ; s >= 1; --s) {
+    for (int s = JM; s >= 1; --s) {
         if (s <= J) {
             const int lp = wt_lanes_log2(s), PB = 1 << lp;
             const int lpo = s > 1 ? wt_lanes_log2(s - 1) : 5, PO = 1 << lpo;  // level 0: tiles <= 32 wide
@@ -2220,6 +2221,10 @@ PupilArgs pupil(const Plan &P) {
 // ---------------------------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------------------------
+// Level bound of the inverse-DWT launches of plans with at most this many levels (their unrolled
+// level loops and cone registers stop there; deeper plans take kMaxJ).
+constexpr int kWtJSmall = 6;
+
 // Dynamic LDS of an inverse-DWT launch: the cone of the plan's J levels.
 inline size_t wt_lds(const Plan &P) { return (size_t)wt_slots(P.J) * kWB * P.elem; }
 
@@ -2238,13 +2243,15 @@ Taps<T> make_taps() {
 
 template <typename T>
 int Ops<T>::wt(const T *c, T *out) const {
-    k_wt<T, kWtPlain><<<dim3(P.n_wt, nb), kWB, wt_lds(P), st>>>(P.seg_wt, c, out, B, make_taps<T>(), P.J, FoldArgs{});
+    if (P.J <= kWtJSmall) k_wt<T, kWtPlain, kWtJSmall><<<dim3(P.n_wt, nb), kWB, wt_lds(P), st>>>(P.seg_wt, c, out, B, make_taps<T>(), P.J, FoldArgs{});
+    else k_wt<T, kWtPlain, kMaxJ><<<dim3(P.n_wt, nb), kWB, wt_lds(P), st>>>(P.seg_wt, c, out, B, make_taps<T>(), P.J, FoldArgs{});
     return check();
 }
 
 template <typename T>
 int Ops<T>::wt_pcg(const T *r, T *out) const {
-    k_wt<T, kWtPcg><<<dim3(P.n_wt, nb), kWB, wt_lds(P), st>>>(P.seg_wt, r, out, B, make_taps<T>(), P.J, FoldArgs{});
+    if (P.J <= kWtJSmall) k_wt<T, kWtPcg, kWtJSmall><<<dim3(P.n_wt, nb), kWB, wt_lds(P), st>>>(P.seg_wt, r, out, B, make_taps<T>(), P.J, FoldArgs{});
+    else k_wt<T, kWtPcg, kMaxJ><<<dim3(P.n_wt, nb), kWB, wt_lds(P), st>>>(P.seg_wt, r, out, B, make_taps<T>(), P.J, FoldArgs{});
     return check();
 }
 
@@ -2254,7 +2261,8 @@ int Ops<T>::wt_fold(const T *r, T *out, const FoldArgs &F) const {
     FoldArgs G = F;
     G.kf = P.kf;
     G.nfine = P.n_fwd * fwd_waves(P.kf, P.tq);
-    k_wt<T, kWtFold><<<dim3(P.n_wt, nb), kWB, wt_lds(P), st>>>(P.seg_wt, r, out, B, make_taps<T>(), P.J, G);
+    if (P.J <= kWtJSmall) k_wt<T, kWtFold, kWtJSmall><<<dim3(P.n_wt, nb), kWB, wt_lds(P), st>>>(P.seg_wt, r, out, B, make_taps<T>(), P.J, G);
+    else k_wt<T, kWtFold, kMaxJ><<<dim3(P.n_wt, nb), kWB, wt_lds(P), st>>>(P.seg_wt, r, out, B, make_taps<T>(), P.J, G);
     return check();
 }
 
@@ -2265,7 +2273,9 @@ int Ops<T>::wt_tail(const T *c, T *out, const FoldArgs &F) const {
     G.kf = P.kf;
     G.parts = kTailParts;
     G.ntail = (P.nl * kTailParts + 7) & ~7;  // whole rounds of the eight XCDs
-    k_wt<T, kWtTail><<<dim3(G.ntail + (c ? P.n_wt : 0), nb), kWB, wt_lds(P), st>>>(P.seg_wt, c, out, B, make_taps<T>(), P.J, G);
+    const dim3 grid(G.ntail + (c ? P.n_wt : 0), nb);
+    if (P.J <= kWtJSmall) k_wt<T, kWtTail, kWtJSmall><<<grid, kWB, wt_lds(P), st>>>(P.seg_wt, c, out, B, make_taps<T>(), P.J, G);
+    else k_wt<T, kWtTail, kMaxJ><<<grid, kWB, wt_lds(P), st>>>(P.seg_wt, c, out, B, make_taps<T>(), P.J, G);
     return check();
 }
 
