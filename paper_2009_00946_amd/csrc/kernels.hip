@@ -989,7 +989,8 @@ __global__ __launch_bounds__(kB) void k_proj(SegTab S, LayTab LT, InvVar IV, Pup
 
     // cell entries of the region's rows and columns on every layer: e = (l * 2 + axis) * 16 + idx,
     // stored at [(axis * nl + l) * kPR + idx]; the first kProjEntFast slots of a lane load together
-    // (clamped indices stand in past the last entry), the rest (over 16 layers) one after another
+    // (lanes past the last entry load nothing, so whole waves drop out), the rest (over 16 layers)
+    // one after another
     {
         const int ne = 2 * nl * kPR;
         auto entry = [&](int e) {
@@ -1006,7 +1007,7 @@ __global__ __launch_bounds__(kB) void k_proj(SegTab S, LayTab LT, InvVar IV, Pup
         };
         Ent<T> en[kProjEntFast];
 #pragma unroll
-        for (int c = 0; c < kProjEntFast; ++c) en[c] = entry(min(tid + c * kB, ne - 1));
+        for (int c = 0; c < kProjEntFast; ++c) en[c] = tid + c * kB < ne ? entry(tid + c * kB) : Ent<T>{};
 #pragma unroll
         for (int c = 0; c < kProjEntFast; ++c)
             if (tid + c * kB < ne) store(tid + c * kB, en[c]);
@@ -1022,22 +1023,25 @@ __global__ __launch_bounds__(kB) void k_proj(SegTab S, LayTab LT, InvVar IV, Pup
         T uv[kProjLch][4];
 #pragma unroll
         for (int c = 0; c < kProjLch; ++c) {
-            const int l = min(l0 + c, nl - 1);  // layers past the last reload it (dropped below)
-            const int n = __builtin_amdgcn_readlane(lay_n, l);
-            const T *U = u + __builtin_amdgcn_readlane(lay_off, l) + (long)sK[(nl + l) * kPR + a] * n + sK[l * kPR + b];
-            uv[c][0] = U[0];
-            uv[c][1] = U[1];
-            uv[c][2] = U[n];
-            uv[c][3] = U[n + 1];
+            const int l = min(l0 + c, nl - 1);
+            if (l0 + c < nl) {
+                const int n = __builtin_amdgcn_readlane(lay_n, l);
+                const T *U = u + __builtin_amdgcn_readlane(lay_off, l) + (long)sK[(nl + l) * kPR + a] * n + sK[l * kPR + b];
+                uv[c][0] = U[0];
+                uv[c][1] = U[1];
+                uv[c][2] = U[n];
+                uv[c][3] = U[n + 1];
+            } else {
+                uv[c][0] = uv[c][1] = uv[c][2] = uv[c][3] = (T)0;
+            }
         }
-        // every slot reads its weights (at the clamped layer, like its values) and slots past the
-        // last layer are zeroed by a uniform factor instead of a branch, so that the weight reads
-        // of all slots issue together
+        // slots past the last layer (a branch uniform over the workgroup) load nothing and hold
+        // zeros; every slot reads its weights at the clamped layer, so that the weight reads of
+        // all slots issue together
 #pragma unroll
         for (int c = 0; c < kProjLch; ++c) {
             const int l = min(l0 + c, nl - 1);
-            const T keep = l0 + c < nl ? (T)1 : (T)0;
-            const T wy0 = sW0[(nl + l) * kPR + a] * keep, wy1 = sW1[(nl + l) * kPR + a] * keep, wx0 = sW0[l * kPR + b],
+            const T wy0 = sW0[(nl + l) * kPR + a], wy1 = sW1[(nl + l) * kPR + a], wx0 = sW0[l * kPR + b],
                     wx1 = sW1[l * kPR + b];
             phi += (wy0 * wx0) * uv[c][0] + (wy0 * wx1) * uv[c][1] + (wy1 * wx0) * uv[c][2] +
                    (wy1 * wx1) * uv[c][3];  // (garbage on rows outside the grid: sPhi drops it)
@@ -1259,15 +1263,21 @@ __global__ __launch_bounds__(kB) void k_pt(SegTab S, WfsOff WO, const T *__restr
     const int k0 = (id.loc >> lt) * T0, q0 = (id.loc & ((1 << lt) - 1)) * T0;
     const int roff = id.aux, rw = id.rw;  // this layer's pair count per line (at most R)
 
-    // the first R pairs of the transpose-table lines e = (g * 2 + axis) * 16 + idx (every lane
-    // loads; clamped indices stand in for lines the tile does not have)
+    // the first R pairs of the transpose-table lines e = (g * 2 + axis) * 16 + idx; lanes of guide
+    // stars the plan does not have load nothing (32 lanes share g, so whole waves drop out), and
+    // a clamped index stands in for a line the tile does not have
     RtabEnt<T> pe[2][R];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-        const int e = tid + c * kB, g = min(e >> 5, nw - 1), axis = (e >> 4) & 1, idx = min(e & 15, T0 - 1);
-        const RtabEnt<T> *rt = (axis ? B.yrtab : B.xrtab) + ((long)g * B.sum_n + roff + (axis ? k0 : q0) + idx) * RW;
+        const int e = tid + c * kB, g = e >> 5, axis = (e >> 4) & 1, idx = min(e & 15, T0 - 1);
+        if (g < nw) {
+            const RtabEnt<T> *rt = (axis ? B.yrtab : B.xrtab) + ((long)g * B.sum_n + roff + (axis ? k0 : q0) + idx) * RW;
 #pragma unroll
-        for (int a = 0; a < R; ++a) pe[c][a] = rt[a];
+            for (int a = 0; a < R; ++a) pe[c][a] = rt[a];
+        } else {
+#pragma unroll
+            for (int a = 0; a < R; ++a) pe[c][a] = RtabEnt<T>{0, T(0)};
+        }
     }
     // written with their staged offsets: a row entry sbase + (max(i, iA) - iA) pitch, a column
     // entry max(j, c0) - c0, from guide star g's record (lane g of this wave)
